@@ -1,0 +1,314 @@
+/*
+ * ORACLE — test infrastructure, not product code.
+ *
+ * A plain, single-threaded CPU implementation of the random-walk method of
+ * ThunderRW (Sun et al., "ThunderRW: An In-Memory Graph Random Walk Engine",
+ * VLDB 2021), written from the paper for checking the HIP path.  Only the
+ * test-suite, the smoke check and the benchmark's CPU-baseline leg load it.
+ * It shares no code, header, table or constant with the HIP library.
+ *
+ * What is computed (paper section in brackets):
+ *   - the execution paradigm: every query repeats "pick a random neighbour of
+ *     the current vertex, append it" until it terminates [Introduction,
+ *     execution-paradigm algorithm; Step-centric Programming, framework
+ *     algorithm: Gather, Move, Update in a do-while loop];
+ *   - the sampling methods NAIVE, ITS, ALIAS and O-REJ [Sampling Methods];
+ *   - the preprocessing of static walks: one sampling table per vertex,
+ *     built once [preprocessing algorithm];
+ *   - the four applications PPR, DeepWalk, Node2Vec (the second-order
+ *     transition equation and the Node2Vec listing), MetaPath [Random Walk
+ *     based Algorithms].
+ *
+ * The paper uses real-valued uniforms; this build fixes one integer random
+ * contract so that a second implementation can be compared bit for bit:
+ *   block(k, t) = Philox4x32-10(counter = (k, t, qid_lo, qid_hi),
+ *                               key = (seed_lo, seed_hi))  -> words r0..r3
+ *   uniform index in [0, d)  = floor(r * d / 2^32)       (r a 32-bit word)
+ *   ALIAS coin               = r1 < thr                   (thr = floor(H * 2^32))
+ *   ITS draw in [0, W)       = floor((r1:r0) * W / 2^64)  (64-bit word)
+ *   PPR stop coin            = r2 < stop_q32              (after each move)
+ *   O-REJ dart height        = r1 >> 16 against Q16 thresholds
+ * Integer choices that the paper leaves open are listed with the readings in
+ * the design notes of the repository.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw: "Parallel random numbers: as   */
+/* easy as 1, 2, 3", SC 2011).  Ten rounds; each round multiplies counter    */
+/* words 0 and 2 by the two round multipliers, recombines the high and low   */
+/* halves with words 1 and 3 and the key, and the key is bumped by the two   */
+/* Weyl constants between rounds.                                            */
+/* ------------------------------------------------------------------------ */
+#define ORC_PHILOX_M0 0xD2511F53u
+#define ORC_PHILOX_M1 0xCD9E8D57u
+#define ORC_PHILOX_W0 0x9E3779B9u
+#define ORC_PHILOX_W1 0xBB67AE85u
+
+void trwo_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4]) {
+    uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    for (int round = 0; round < 10; round++) {
+        if (round > 0) { k0 += ORC_PHILOX_W0; k1 += ORC_PHILOX_W1; }
+        uint64_t p0 = (uint64_t)ORC_PHILOX_M0 * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)ORC_PHILOX_M1 * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+static void block(uint64_t seed, uint64_t qid, uint32_t k, uint32_t t, uint32_t r[4]) {
+    uint32_t ctr[4] = { k, t, (uint32_t)qid, (uint32_t)(qid >> 32) };
+    uint32_t key[2] = { (uint32_t)seed, (uint32_t)(seed >> 32) };
+    trwo_philox4x32_10(ctr, key, r);
+}
+
+/* floor(r * d / 2^32): a uniform index in [0, d) from one 32-bit word. */
+static uint32_t index_of(uint32_t r, uint32_t d) {
+    return (uint32_t)(((uint64_t)r * (uint64_t)d) >> 32);
+}
+
+/* ------------------------------------------------------------------------ */
+/* ALIAS initialization [Sampling Methods, alias sampling; Walker 1977],    */
+/* built with Vose's worklist method in exact integer arithmetic.            */
+/*                                                                          */
+/* For a vertex with degree d and weights w_i, let W = sum w_i and scale     */
+/* every weight to s_i = w_i * d, so that the average column holds exactly  */
+/* W.  Columns below W go to a "small" stack, the others to a "large" stack */
+/* (both last-in first-out, pushed in index order).  While both stacks are  */
+/* non-empty: pop a small column l, look at the large column g on top; l's  */
+/* bucket is (l with mass s_l, g with the rest); g gives up W - s_l and moves */
+/* to the small stack if it falls below W.  Whatever remains on the large   */
+/* stack is a full bucket (probability 1, alias = itself).                  */
+/*                                                                          */
+/* Output per edge slot j of the row: thr[j] = floor(s_j * 2^32 / W), or    */
+/* 0xFFFFFFFF for a full bucket, and alias[j] = local index of the second   */
+/* element.  A row whose weights sum to zero has no transition: all its     */
+/* slots get thr = 0xFFFFFFFF and alias = -1, which the walk reads as a dead */
+/* end.                                                                     */
+/* ------------------------------------------------------------------------ */
+int trwo_alias_build(int64_t n, const int32_t *row_ptr, const uint32_t *w,
+                     uint32_t *thr, int32_t *alias) {
+    int64_t dmax = 0;
+    for (int64_t v = 0; v < n; v++) {
+        int64_t d = (int64_t)row_ptr[v + 1] - row_ptr[v];
+        if (d > dmax) dmax = d;
+    }
+    uint64_t *s = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(dmax + 1));
+    int64_t *small = (int64_t *)malloc(sizeof(int64_t) * (size_t)(dmax + 1));
+    int64_t *large = (int64_t *)malloc(sizeof(int64_t) * (size_t)(dmax + 1));
+    if (!s || !small || !large) { free(s); free(small); free(large); return -1; }
+
+    for (int64_t v = 0; v < n; v++) {
+        int64_t off = row_ptr[v];
+        int64_t d = (int64_t)row_ptr[v + 1] - off;
+        if (d == 0) continue;
+        uint64_t W = 0;
+        for (int64_t i = 0; i < d; i++) W += w[off + i];
+        if (W == 0) {
+            for (int64_t i = 0; i < d; i++) { thr[off + i] = 0xFFFFFFFFu; alias[off + i] = -1; }
+            continue;
+        }
+        int64_t ns = 0, nl = 0;
+        for (int64_t i = 0; i < d; i++) {
+            s[i] = (uint64_t)w[off + i] * (uint64_t)d;
+            if (s[i] < W) small[ns++] = i; else large[nl++] = i;
+        }
+        while (ns > 0 && nl > 0) {
+            int64_t l = small[--ns];
+            int64_t g = large[nl - 1];
+            /* bucket l: first = l with mass s[l], second = g */
+            thr[off + l] = (uint32_t)(((unsigned __int128)s[l] << 32) / W);
+            alias[off + l] = (int32_t)g;
+            s[g] -= (W - s[l]);
+            if (s[g] < W) { nl--; small[ns++] = g; }
+        }
+        while (nl > 0) {
+            int64_t g = large[--nl];
+            thr[off + g] = 0xFFFFFFFFu;
+            alias[off + g] = (int32_t)g;
+        }
+        /* In exact arithmetic the small stack is empty here: the remaining
+           columns hold (#remaining) * W in total and each is below W. */
+        if (ns != 0) { free(s); free(small); free(large); return -2; }
+    }
+    free(s); free(small); free(large);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* ITS initialization [Sampling Methods, inverse transformation sampling]:  */
+/* per vertex, the inclusive running sum of the weights, in 64-bit integers. */
+/* ------------------------------------------------------------------------ */
+int trwo_its_build(int64_t n, const int32_t *row_ptr, const uint32_t *w, uint64_t *prefix) {
+    for (int64_t v = 0; v < n; v++) {
+        uint64_t acc = 0;
+        for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; e++) {
+            acc += w[e];
+            prefix[e] = acc;
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Walk                                                                      */
+/* ------------------------------------------------------------------------ */
+enum { ORC_DEEPWALK = 0, ORC_PPR = 1, ORC_NODE2VEC = 2, ORC_METAPATH = 3 };
+enum { ORC_NAIVE = 0, ORC_ALIAS = 1, ORC_ITS = 2, ORC_OREJ = 3 };
+enum { ORC_ST_LENGTH = 1, ORC_ST_STOPPED = 2, ORC_ST_DEAD_END = 3, ORC_ST_BAD_SOURCE = 4 };
+
+/* Upper bound on O-REJ darts per move.  With every threshold >= 1 a dart is
+   accepted with probability >= 2^-16, so 2^24 darts are exceeded with
+   probability below e^-256; the last dart is then taken. */
+#define ORC_OREJ_MAX_TRIALS (1u << 24)
+
+typedef struct {
+    uint32_t algo;
+    uint32_t sampler;
+    uint32_t max_len;          /* moves per query at most */
+    uint32_t stop_q32;         /* PPR: stop after a move iff r2 < stop_q32 */
+    uint32_t n2v_thr_q16[3];   /* Node2Vec: x == prev, x adjacent to prev, otherwise */
+    uint32_t schema_len;       /* MetaPath */
+    uint8_t  schema[16];
+    uint64_t seed;
+} trwo_params;
+
+typedef struct {
+    uint64_t moves;            /* successful moves */
+    uint64_t philox_blocks;    /* Philox blocks drawn */
+    uint64_t its_probes;       /* prefix entries read by ITS searches */
+    uint64_t orej_trials;      /* O-REJ darts */
+    uint64_t adjacency_probes; /* entries read by Node2Vec adjacency tests */
+    uint64_t label_reads;      /* labels read by MetaPath */
+} trwo_counters;
+
+/* Is x in the sorted row [lo, hi) of col?  Textbook binary search. */
+static int in_sorted_row(const int32_t *col, int64_t lo, int64_t hi, int32_t x, uint64_t *probes) {
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        (*probes)++;
+        if (col[mid] == x) return 1;
+        if (col[mid] < x) lo = mid + 1; else hi = mid;
+    }
+    return 0;
+}
+
+/* Smallest i in [0, d) with t < prefix[off + i]; prefix is non-decreasing. */
+static int64_t its_search(const uint64_t *prefix, int64_t off, int64_t d, uint64_t t, uint64_t *probes) {
+    int64_t lo = 0, hi = d - 1;        /* answer in [lo, hi]; prefix[off+d-1] = W > t */
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        (*probes)++;
+        if (t < prefix[off + mid]) hi = mid; else lo = mid + 1;
+    }
+    return lo;
+}
+
+/*
+ * Run nq queries.  Query i starts at sources[i] and has id qids ? qids[i] : qid_base + i.
+ * Its path goes to paths[i * path_stride + 0 .. lengths[i]]; status[i] says why it ended.
+ * Tables: thr/alias for ALIAS, prefix for ITS; label for MetaPath.
+ */
+int trwo_walk(int64_t n, const int32_t *row_ptr, const int32_t *col,
+              const uint32_t *thr, const int32_t *alias, const uint64_t *prefix,
+              const uint8_t *label, const trwo_params *p,
+              const int32_t *sources, int64_t nq, uint64_t qid_base, const uint64_t *qids,
+              int32_t *paths, int64_t path_stride, uint32_t *lengths, uint8_t *status,
+              trwo_counters *cnt) {
+    trwo_counters local;
+    memset(&local, 0, sizeof(local));
+    for (int64_t i = 0; i < nq; i++) {
+        const uint64_t qid = qids ? qids[i] : qid_base + (uint64_t)i;
+        int32_t *path = paths + i * path_stride;
+        const int32_t s = sources[i];
+        if (s < 0 || (int64_t)s >= n) { lengths[i] = 0; status[i] = ORC_ST_BAD_SOURCE; continue; }
+        int32_t cur = s, prev = -1;
+        uint32_t k = 0;
+        uint8_t st;
+        path[0] = s;
+        for (;;) {
+            if (k == p->max_len) { st = ORC_ST_LENGTH; break; }
+            const int64_t off = row_ptr[cur];
+            const uint32_t d = (uint32_t)(row_ptr[cur + 1] - row_ptr[cur]);
+            if (d == 0) { st = ORC_ST_DEAD_END; break; }
+            uint32_t r[4];
+            int32_t nxt = -1;
+            if (p->algo == ORC_DEEPWALK || p->algo == ORC_PPR) {
+                block(p->seed, qid, k, 0, r);
+                local.philox_blocks++;
+                if (p->sampler == ORC_NAIVE) {
+                    nxt = col[off + index_of(r[0], d)];
+                } else if (p->sampler == ORC_ALIAS) {
+                    const uint32_t j = index_of(r[0], d);
+                    const int32_t a = alias[off + j];
+                    if (a < 0) { st = ORC_ST_DEAD_END; break; }
+                    nxt = (r[1] < thr[off + j]) ? col[off + j] : col[off + a];
+                } else { /* ITS */
+                    const uint64_t W = prefix[off + d - 1];
+                    if (W == 0) { st = ORC_ST_DEAD_END; break; }
+                    const uint64_t r64 = ((uint64_t)r[1] << 32) | r[0];
+                    const uint64_t t = (uint64_t)(((unsigned __int128)r64 * W) >> 64);
+                    nxt = col[off + its_search(prefix, off, d, t, &local.its_probes)];
+                }
+            } else if (p->algo == ORC_NODE2VEC) {
+                /* O-REJ: darts (x, y) until y falls under p(x) / p*; the
+                   Q16 thresholds are p(e) / p* scaled by 2^16. */
+                for (uint32_t t = 0;; t++) {
+                    block(p->seed, qid, k, t, r);
+                    local.philox_blocks++;
+                    local.orej_trials++;
+                    const int32_t x = col[off + index_of(r[0], d)];
+                    if (k == 0 || t + 1 == ORC_OREJ_MAX_TRIALS) { nxt = x; break; }
+                    uint32_t th;
+                    if (x == prev) th = p->n2v_thr_q16[0];
+                    else if (in_sorted_row(col, row_ptr[prev], row_ptr[prev + 1], x, &local.adjacency_probes))
+                        th = p->n2v_thr_q16[1];
+                    else th = p->n2v_thr_q16[2];
+                    if ((r[1] >> 16) < th) { nxt = x; break; }
+                }
+            } else { /* METAPATH: only edges whose label is the schema's label for this move */
+                const uint8_t want = p->schema[k % p->schema_len];
+                uint32_t m = 0;
+                for (uint32_t i2 = 0; i2 < d; i2++) m += (label[off + i2] == want);
+                local.label_reads += d;
+                if (m == 0) { st = ORC_ST_DEAD_END; break; }
+                block(p->seed, qid, k, 0, r);
+                local.philox_blocks++;
+                const uint32_t j = index_of(r[0], m);
+                uint32_t seen = 0;
+                for (uint32_t i2 = 0; i2 < d; i2++) {
+                    if (label[off + i2] == want) {
+                        if (seen == j) { nxt = col[off + i2]; break; }
+                        seen++;
+                    }
+                }
+            }
+            path[k + 1] = nxt;
+            prev = cur;
+            cur = nxt;
+            k++;
+            local.moves++;
+            if (p->algo == ORC_PPR && r[2] < p->stop_q32) { st = ORC_ST_STOPPED; break; }
+        }
+        lengths[i] = k;
+        status[i] = st;
+    }
+    if (cnt) {
+        cnt->moves += local.moves;
+        cnt->philox_blocks += local.philox_blocks;
+        cnt->its_probes += local.its_probes;
+        cnt->orej_trials += local.orej_trials;
+        cnt->adjacency_probes += local.adjacency_probes;
+        cnt->label_reads += local.label_reads;
+    }
+    return 0;
+}
