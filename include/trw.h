@@ -1,0 +1,234 @@
+/*
+ * trw.h — C ABI of the MI355X random-walk engine (libtrw.so).
+ *
+ * The engine runs the step of ThunderRW's method (Sun et al., "ThunderRW: An
+ * In-Memory Graph Random Walk Engine", VLDB 2021) over many independent
+ * random-walk queries on one GPU: each step gathers the current vertex's
+ * neighbours and transition weights, samples the next vertex and updates the
+ * walker (Step-centric Programming: the Gather-Move-Update framework).  The
+ * calls follow the paper's problem statement: input a graph and a set of
+ * queries, output each query's walk sequence (Introduction, execution
+ * paradigm; Other Implementation Details: graph storage, walker management,
+ * input and output).
+ *
+ * Conventions
+ *  - Every call returns trw_status (TRW_OK = 0).  Nothing throws across the
+ *    ABI.  A failing call leaves its outputs untouched and records a message
+ *    that trw_last_error() returns (per thread).
+ *  - Device pointers ("d_" prefix) are HIP device memory owned by the caller.
+ *    The library allocates no device memory on these paths: it reports the
+ *    sizes it needs (trw_table_bytes, trw_walk_workspace_bytes) and the
+ *    caller passes buffers.  Handles borrow the caller's buffers; keep them
+ *    alive until the handle is destroyed.
+ *  - Device work is asynchronous on the caller's stream (a hipStream_t passed
+ *    as trw_stream_t; NULL = the null stream) unless a call says it
+ *    synchronises.  Host pointers are read before the call returns.
+ *  - Handles are not thread-safe.
+ *
+ * Random contract (the paper samples with real uniforms; this engine fixes an
+ * integer contract so that any run is reproducible bit for bit):
+ *   block(k, t) = Philox4x32-10(counter = (k, t, qid_lo, qid_hi),
+ *                               key = (seed_lo, seed_hi)) -> words r0..r3
+ * where k is the move number (0-based), t the dart number (O-REJ) and qid the
+ * query id.  A query's walk depends only on (graph, params, seed, qid,
+ * source), never on batch composition, launch shape or tuning.
+ */
+#ifndef TRW_H
+#define TRW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TRW_ABI_VERSION 1u
+
+typedef void *trw_stream_t;          /* hipStream_t */
+
+typedef enum {
+    TRW_OK = 0,
+    TRW_E_INVALID = 1,       /* bad argument, size or missing input */
+    TRW_E_UNSUPPORTED = 2,   /* (algorithm, sampler) pair not provided */
+    TRW_E_DEVICE = 3,        /* a HIP runtime call failed */
+    TRW_E_NOMEM_BUDGET = 4,  /* serving: request can never fit the memory budget */
+    TRW_E_BUSY = 5,          /* serving: no slot free right now (retry) */
+    TRW_E_TIMEOUT = 6,       /* serving: poll timed out with nothing complete */
+    TRW_E_CANCELLED = 7      /* serving: request was cancelled */
+} trw_status;
+
+/* Message of the last failing call on this thread ("" if none).  Owned by the library. */
+const char *trw_last_error(void);
+/* TRW_ABI_VERSION of the loaded library. */
+uint32_t trw_abi_version(void);
+
+/* ------------------------------------------------------------------------ */
+/* Graph (Preliminary: directed G = (V, E), an undirected edge as two        */
+/* directed edges; Other Implementation Details, graph storage: CSR with     */
+/* per-edge weight and label arrays).                                        */
+/* ------------------------------------------------------------------------ */
+typedef struct trw_graph_s *trw_graph;
+
+enum { TRW_G_SYMMETRIC = 1 };
+
+/*
+ * Wrap a device-resident CSR graph.
+ *   n          vertices, 1 <= n < 2^31
+ *   m          directed edges, 0 <= m < 2^31
+ *   d_row_ptr  int32[n+1]: row v is col[row_ptr[v] .. row_ptr[v+1])
+ *   d_col      int32[m]: destinations, each row sorted ascending without
+ *              duplicates (Node2Vec's adjacency test is a binary search)
+ *   d_weight   uint32[m] or NULL: static transition weights (ALIAS, ITS)
+ *   d_label    uint8[m] or NULL: edge labels (MetaPath)
+ *   flags      TRW_G_SYMMETRIC if every edge has its reverse (informational)
+ * Borrows the arrays; does not read them (see trw_graph_validate).
+ * Errors: TRW_E_INVALID for sizes out of range or NULL row_ptr/col.
+ */
+trw_status trw_graph_create(int64_t n, int64_t m, const int32_t *d_row_ptr, const int32_t *d_col,
+                            const uint32_t *d_weight, const uint8_t *d_label, uint32_t flags,
+                            trw_graph *out);
+
+/*
+ * O(n + m) check on the device: row_ptr[0] == 0, row_ptr non-decreasing,
+ * row_ptr[n] == m, every col in [0, n), rows strictly ascending.
+ * d_ws: device scratch of at least 64 bytes.  Synchronises the stream and
+ * writes the number of violations to *n_bad.  Returns TRW_E_INVALID if
+ * *n_bad > 0.
+ */
+trw_status trw_graph_validate(trw_graph g, void *d_ws, size_t ws_bytes, trw_stream_t stream,
+                              uint64_t *n_bad);
+
+trw_status trw_graph_destroy(trw_graph g);
+
+/* ------------------------------------------------------------------------ */
+/* Sampling tables (Sampling Methods; preprocessing algorithm for static      */
+/* walks: one table C_v per vertex, built once before the queries run).      */
+/* ------------------------------------------------------------------------ */
+typedef enum {
+    TRW_S_NAIVE = 0,   /* uniform index; no table */
+    TRW_S_ALIAS = 1,   /* Walker alias table, integer Vose construction */
+    TRW_S_ITS = 2,     /* inverse transform: inclusive uint64 prefix + binary search */
+    TRW_S_OREJ = 3     /* rejection with a user bound p*; no table (Node2Vec) */
+} trw_sampler;
+
+typedef struct trw_table_s *trw_table;
+
+/* Bytes of device memory the table for `sampler` needs: ALIAS 16*m, ITS 8*m. */
+trw_status trw_table_bytes(trw_graph g, uint32_t sampler, size_t *bytes);
+
+/*
+ * Build the per-vertex table for `sampler` from the graph's weights into
+ * d_buf (caller-owned, >= trw_table_bytes, 16-byte aligned), asynchronously.
+ * Layout (per directed edge slot e of row v, in CSR order):
+ *   ALIAS: uint32x4 {thr, dst_first, dst_second, 0}.  Column j of row v is the
+ *          bucket (first = col[off+j], second = col[off+alias_j]); it picks
+ *          the first iff r1 < thr.  thr = floor(s_j * 2^32 / W) from Vose's
+ *          worklist method in exact integers (W = sum of the row's weights,
+ *          s_j = w_j * d after the transfers), 0xFFFFFFFF for a full bucket.
+ *          A row whose weights sum to 0 holds {0xFFFFFFFF, -1, -1, 0}: a
+ *          walk that reaches it ends as a dead end.
+ *   ITS:   uint64 prefix[e] = sum of w over row v up to and including e.
+ * Errors: TRW_E_INVALID if the graph has no weights, bytes is too small or the
+ * buffer is misaligned; TRW_E_UNSUPPORTED for NAIVE / OREJ (no table).
+ */
+trw_status trw_table_build(trw_graph g, uint32_t sampler, void *d_buf, size_t bytes,
+                           trw_stream_t stream, trw_table *out);
+
+trw_status trw_table_destroy(trw_table t);
+
+/* ------------------------------------------------------------------------ */
+/* Walks                                                                     */
+/* ------------------------------------------------------------------------ */
+typedef enum {
+    TRW_A_DEEPWALK = 0,   /* fixed length (Random Walk based Algorithms: DeepWalk) */
+    TRW_A_PPR = 1,        /* stop with a fixed probability after each move (PPR) */
+    TRW_A_NODE2VEC = 2,   /* second-order: the Node2Vec transition equation */
+    TRW_A_METAPATH = 3    /* only edges whose label matches the schema (MetaPath) */
+} trw_algo;
+
+typedef enum {
+    TRW_ST_LENGTH = 1,        /* made max_len moves */
+    TRW_ST_STOPPED = 2,       /* PPR stop coin after a move */
+    TRW_ST_DEAD_END = 3,      /* no eligible edge at the current vertex */
+    TRW_ST_BAD_SOURCE = 4     /* source outside [0, n) */
+} trw_walk_status;
+
+typedef struct {
+    uint32_t algo;             /* trw_algo */
+    uint32_t sampler;          /* DEEPWALK/PPR: NAIVE, ALIAS or ITS; NODE2VEC: OREJ; METAPATH: ITS */
+    uint32_t max_len;          /* moves per query, 1..65535; a path holds max_len+1 vertices */
+    uint32_t stop_q32;         /* PPR: stop after a move iff r2 < stop_q32 (0.2 -> 858993459) */
+    uint32_t n2v_thr_q16[3];   /* NODE2VEC: accept a dart iff (r1 >> 16) < thr[c], c = 0 when
+                                  the candidate is the previous vertex, 1 when it is adjacent to
+                                  it, 2 otherwise; thr = round(2^16 p(e) / p*), in [1, 65536] */
+    uint32_t schema_len;       /* METAPATH: 1..16; move k uses label schema[k % schema_len] */
+    uint8_t schema[16];
+    uint64_t seed;             /* Philox key */
+} trw_walk_params;
+
+typedef enum {
+    TRW_M_PER_STEP = 0,        /* one launch per move over the live walkers (bulk-synchronous) */
+    TRW_M_PERSISTENT = 1       /* one launch; lanes refill from a device queue as walks end */
+} trw_mode;
+
+/* Launch and scheduling knobs.  Any field 0 = library default.  Results never depend on them. */
+typedef struct {
+    uint32_t walkers_per_lane;  /* persistent: 1, 2 or 4 walkers interleaved per lane */
+    uint32_t block_threads;     /* 64..1024, multiple of 64 */
+    uint32_t blocks_per_cu;     /* persistent grid = CUs * blocks_per_cu */
+    uint32_t queue_chunk;       /* persistent: queries claimed per wave per queue access */
+    uint32_t coop_degree;       /* MetaPath: rows at least this long are scanned by the whole wave */
+    uint32_t reserved[3];
+} trw_tuning;
+
+/* Workspace bytes trw_walk needs for nq queries in `mode`. */
+trw_status trw_walk_workspace_bytes(trw_graph g, const trw_walk_params *p, uint64_t nq,
+                                    uint32_t mode, size_t *bytes);
+
+/* The library's default tuning for this graph, params and mode. */
+trw_status trw_default_tuning(trw_graph g, const trw_walk_params *p, uint32_t mode, trw_tuning *out);
+
+/*
+ * Run nq queries, query i starting at d_sources[i] with id qid_base + i.
+ *   table       ALIAS/ITS table built for p->sampler (NULL for NAIVE, OREJ, METAPATH)
+ *   d_paths     int32, row i at d_paths + i*path_stride, path_stride >= max_len+1:
+ *               paths[i][0] = source, paths[i][1..lengths[i]] = the moves;
+ *               entries beyond lengths[i] are left unspecified
+ *   d_lengths   uint32[nq]: moves made
+ *   d_status    uint8[nq]: trw_walk_status
+ *   tuning      NULL = trw_default_tuning
+ *   d_ws        workspace of >= trw_walk_workspace_bytes, 256-byte aligned
+ * Asynchronous on `stream`.  Sources outside [0, n) get status BAD_SOURCE and
+ * length 0 (path row untouched); they are not an error of the call.
+ * Errors: TRW_E_UNSUPPORTED for an (algo, sampler) pair outside the list
+ * above; TRW_E_INVALID for max_len outside 1..65535, thresholds > 65536 or
+ * 0, schema_len outside 1..16, a missing or mismatched table, missing labels
+ * for METAPATH, path_stride < max_len+1, a short or misaligned workspace, or
+ * nq >= 2^32.
+ */
+trw_status trw_walk(trw_graph g, trw_table table, const trw_walk_params *p,
+                    const int32_t *d_sources, uint64_t nq, uint64_t qid_base,
+                    int32_t *d_paths, uint64_t path_stride, uint32_t *d_lengths, uint8_t *d_status,
+                    uint32_t mode, const trw_tuning *tuning, void *d_ws, size_t ws_bytes,
+                    trw_stream_t stream);
+
+/*
+ * Pick a tuning by pre-executing short walks (the paper tunes its ring sizes
+ * the same way: Ring Size Tuning).  Runs up to `budget` candidate launches of
+ * `nq` queries (length-capped at p->max_len) from d_sources in `mode`, timing
+ * each with HIP events, and writes the fastest to *out.  d_paths, d_lengths,
+ * d_status and d_ws are scratch of the sizes trw_walk needs for nq queries.
+ * Synchronises the stream.  Errors as trw_walk.
+ */
+trw_status trw_autotune(trw_graph g, trw_table table, const trw_walk_params *p,
+                        const int32_t *d_sources, uint64_t nq, int32_t *d_paths,
+                        uint64_t path_stride, uint32_t *d_lengths, uint8_t *d_status,
+                        uint32_t mode, uint32_t budget, void *d_ws, size_t ws_bytes,
+                        trw_stream_t stream, trw_tuning *out, float *best_ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TRW_H */

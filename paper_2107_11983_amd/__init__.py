@@ -1,0 +1,197 @@
+"""MI355X random-walk engine: Python binding of libtrw.so.
+
+PyTorch supplies device memory and streams; every step of the walk path runs
+in the library's HIP kernels, reached through the C ABI (include/trw.h).
+The binding marshals arguments and raises TrwError on any failing call.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _abi
+from ._abi import (TRW_A_DEEPWALK, TRW_A_METAPATH, TRW_A_NODE2VEC, TRW_A_PPR, TRW_G_SYMMETRIC,
+                   TRW_M_PER_STEP, TRW_M_PERSISTENT, TRW_S_ALIAS, TRW_S_ITS, TRW_S_NAIVE, TRW_S_OREJ,
+                   TRW_ST_BAD_SOURCE, TRW_ST_DEAD_END, TRW_ST_LENGTH, TRW_ST_STOPPED, TrwError, check,
+                   trw_tuning, trw_walk_params)
+
+__all__ = ["Graph", "Table", "walk", "make_params", "workspace_bytes", "default_tuning", "autotune",
+           "TrwError", "ALGOS", "SAMPLERS"]
+
+ALGOS = {"deepwalk": TRW_A_DEEPWALK, "ppr": TRW_A_PPR, "node2vec": TRW_A_NODE2VEC, "metapath": TRW_A_METAPATH}
+SAMPLERS = {"naive": TRW_S_NAIVE, "alias": TRW_S_ALIAS, "its": TRW_S_ITS, "orej": TRW_S_OREJ}
+MODES = {"per_step": TRW_M_PER_STEP, "persistent": TRW_M_PERSISTENT}
+
+
+def _stream_ptr(stream: Optional[torch.cuda.Stream]) -> ctypes.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dptr(t: Optional[torch.Tensor]) -> Optional[ctypes.c_void_p]:
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _as_device(a, dtype_np, device) -> torch.Tensor:
+    """numpy array -> device tensor with the same bits (uint32/uint8 kept bit-exact)."""
+    if isinstance(a, torch.Tensor):
+        return a.to(device)
+    a = np.ascontiguousarray(a, dtype=dtype_np)
+    if dtype_np == np.uint32:
+        a = a.view(np.int32)
+    return torch.from_numpy(a).to(device)
+
+
+def make_params(algo, sampler, max_len: int, seed: int, stop_q32: int = 0,
+                n2v_thr_q16: Sequence[int] = (65536, 65536, 65536), schema: Sequence[int] = ()) -> trw_walk_params:
+    """Fill trw_walk_params.  algo / sampler may be names ('ppr', 'alias') or enum values."""
+    p = trw_walk_params()
+    p.algo = ALGOS[algo] if isinstance(algo, str) else int(algo)
+    p.sampler = SAMPLERS[sampler] if isinstance(sampler, str) else int(sampler)
+    p.max_len = int(max_len)
+    p.stop_q32 = int(stop_q32)
+    for i in range(3):
+        p.n2v_thr_q16[i] = int(n2v_thr_q16[i])
+    p.schema_len = len(schema)
+    for i, s in enumerate(schema):
+        p.schema[i] = int(s)
+    p.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
+    return p
+
+
+class Graph:
+    """A device-resident CSR graph wrapped in a trw_graph handle.
+
+    row_ptr int32[n+1], col int32[m] (rows sorted, no duplicates), optional
+    weight uint32[m] and label uint8[m].  The tensors live as long as the Graph.
+    """
+
+    def __init__(self, row_ptr, col, weight=None, label=None, symmetric: bool = False,
+                 device: str = "cuda"):
+        self.device = torch.device(device)
+        self.row_ptr = _as_device(row_ptr, np.int32, self.device)
+        self.col = _as_device(col, np.int32, self.device)
+        self.weight = None if weight is None else _as_device(weight, np.uint32, self.device)
+        self.label = None if label is None else _as_device(label, np.uint8, self.device)
+        self.n = self.row_ptr.numel() - 1
+        self.m = self.col.numel()
+        h = ctypes.c_void_p()
+        check(_abi.trw_graph_create(self.n, self.m, _dptr(self.row_ptr), _dptr(self.col), _dptr(self.weight),
+                                    _dptr(self.label), TRW_G_SYMMETRIC if symmetric else 0, ctypes.byref(h)))
+        self.handle = h
+        self._tables = []
+
+    def validate(self, stream=None) -> int:
+        ws = torch.empty(64, dtype=torch.uint8, device=self.device)
+        bad = ctypes.c_uint64(0)
+        st = _abi.trw_graph_validate(self.handle, _dptr(ws), 64, _stream_ptr(stream), ctypes.byref(bad))
+        if st not in (0, _abi.TRW_E_INVALID):
+            check(st)
+        return int(bad.value)
+
+    def table(self, sampler, stream=None) -> "Table":
+        return Table(self, sampler, stream)
+
+    def close(self):
+        for t in self._tables:
+            t.close()
+        self._tables = []
+        if self.handle:
+            _abi.trw_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Table:
+    """Per-vertex ALIAS or ITS table (built on the device, asynchronously)."""
+
+    def __init__(self, graph: Graph, sampler, stream=None):
+        self.graph = graph
+        self.sampler = SAMPLERS[sampler] if isinstance(sampler, str) else int(sampler)
+        nbytes = ctypes.c_size_t(0)
+        check(_abi.trw_table_bytes(graph.handle, self.sampler, ctypes.byref(nbytes)))
+        self.buf = torch.empty(max(int(nbytes.value), 16), dtype=torch.uint8, device=graph.device)
+        h = ctypes.c_void_p()
+        check(_abi.trw_table_build(graph.handle, self.sampler, _dptr(self.buf), int(nbytes.value),
+                                   _stream_ptr(stream), ctypes.byref(h)))
+        self.handle = h
+        graph._tables.append(self)
+
+    def close(self):
+        if self.handle:
+            _abi.trw_table_destroy(self.handle)
+            self.handle = None
+
+
+def workspace_bytes(graph: Graph, p: trw_walk_params, nq: int, mode=TRW_M_PERSISTENT) -> int:
+    out = ctypes.c_size_t(0)
+    check(_abi.trw_walk_workspace_bytes(graph.handle, ctypes.byref(p), nq, MODES.get(mode, mode), ctypes.byref(out)))
+    return int(out.value)
+
+
+def default_tuning(graph: Graph, p: trw_walk_params, mode=TRW_M_PERSISTENT) -> trw_tuning:
+    t = trw_tuning()
+    check(_abi.trw_default_tuning(graph.handle, ctypes.byref(p), MODES.get(mode, mode), ctypes.byref(t)))
+    return t
+
+
+def make_tuning(**kw) -> trw_tuning:
+    t = trw_tuning()
+    for k, v in kw.items():
+        setattr(t, k, int(v))
+    return t
+
+
+class WalkBuffers:
+    """Output and scratch buffers for repeated walks of the same shape."""
+
+    def __init__(self, graph: Graph, p: trw_walk_params, nq: int, mode=TRW_M_PERSISTENT, stride: int = 0):
+        self.nq = nq
+        self.stride = stride or (p.max_len + 1)
+        dev = graph.device
+        self.paths = torch.empty((nq, self.stride), dtype=torch.int32, device=dev)
+        self.lengths = torch.empty(nq, dtype=torch.int32, device=dev)
+        self.status = torch.empty(nq, dtype=torch.uint8, device=dev)
+        self.ws = torch.empty(max(workspace_bytes(graph, p, nq, mode), 256), dtype=torch.uint8, device=dev)
+
+
+def walk(graph: Graph, table: Optional[Table], p: trw_walk_params, sources: torch.Tensor, qid_base: int = 0,
+         mode=TRW_M_PERSISTENT, tuning: Optional[trw_tuning] = None, bufs: Optional[WalkBuffers] = None,
+         stream=None):
+    """Run len(sources) queries; returns (paths int32[nq, stride], lengths, status).
+
+    lengths are uint32 values held in an int32 tensor (moves per query, <= 65535).
+    """
+    mode = MODES.get(mode, mode)
+    nq = int(sources.numel())
+    if bufs is None:
+        bufs = WalkBuffers(graph, p, nq, mode)
+    assert bufs.nq == nq
+    check(_abi.trw_walk(graph.handle, table.handle if table is not None else None, ctypes.byref(p),
+                        _dptr(sources), nq, qid_base, _dptr(bufs.paths), bufs.stride, _dptr(bufs.lengths),
+                        _dptr(bufs.status), mode, ctypes.byref(tuning) if tuning is not None else None,
+                        _dptr(bufs.ws), bufs.ws.numel(), _stream_ptr(stream)))
+    return bufs.paths, bufs.lengths, bufs.status
+
+
+def autotune(graph: Graph, table: Optional[Table], p: trw_walk_params, sources: torch.Tensor,
+             mode=TRW_M_PERSISTENT, budget: int = 0, stream=None):
+    """Pre-execute walks under candidate tunings; returns (best trw_tuning, best ms)."""
+    mode = MODES.get(mode, mode)
+    nq = int(sources.numel())
+    bufs = WalkBuffers(graph, p, nq, mode)
+    out = trw_tuning()
+    ms = ctypes.c_float(0)
+    check(_abi.trw_autotune(graph.handle, table.handle if table is not None else None, ctypes.byref(p),
+                            _dptr(sources), nq, _dptr(bufs.paths), bufs.stride, _dptr(bufs.lengths),
+                            _dptr(bufs.status), mode, budget, _dptr(bufs.ws), bufs.ws.numel(),
+                            _stream_ptr(stream), ctypes.byref(out), ctypes.byref(ms)))
+    return out, float(ms.value)

@@ -1,0 +1,106 @@
+"""ctypes declarations of libtrw.so's C ABI (include/trw.h), same names.
+
+Argument marshalling only: every step of a walk runs in the library's HIP
+kernels.  If the library is missing this module raises on import; there is
+no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtrw.so")
+
+TRW_OK, TRW_E_INVALID, TRW_E_UNSUPPORTED, TRW_E_DEVICE = 0, 1, 2, 3
+TRW_E_NOMEM_BUDGET, TRW_E_BUSY, TRW_E_TIMEOUT, TRW_E_CANCELLED = 4, 5, 6, 7
+STATUS_NAMES = {0: "TRW_OK", 1: "TRW_E_INVALID", 2: "TRW_E_UNSUPPORTED", 3: "TRW_E_DEVICE",
+                4: "TRW_E_NOMEM_BUDGET", 5: "TRW_E_BUSY", 6: "TRW_E_TIMEOUT", 7: "TRW_E_CANCELLED"}
+TRW_G_SYMMETRIC = 1
+TRW_S_NAIVE, TRW_S_ALIAS, TRW_S_ITS, TRW_S_OREJ = 0, 1, 2, 3
+TRW_A_DEEPWALK, TRW_A_PPR, TRW_A_NODE2VEC, TRW_A_METAPATH = 0, 1, 2, 3
+TRW_ST_LENGTH, TRW_ST_STOPPED, TRW_ST_DEAD_END, TRW_ST_BAD_SOURCE = 1, 2, 3, 4
+TRW_M_PER_STEP, TRW_M_PERSISTENT = 0, 1
+
+
+class trw_walk_params(ctypes.Structure):
+    _fields_ = [("algo", ctypes.c_uint32), ("sampler", ctypes.c_uint32),
+                ("max_len", ctypes.c_uint32), ("stop_q32", ctypes.c_uint32),
+                ("n2v_thr_q16", ctypes.c_uint32 * 3), ("schema_len", ctypes.c_uint32),
+                ("schema", ctypes.c_uint8 * 16), ("seed", ctypes.c_uint64)]
+
+
+class trw_tuning(ctypes.Structure):
+    _fields_ = [("walkers_per_lane", ctypes.c_uint32), ("block_threads", ctypes.c_uint32),
+                ("blocks_per_cu", ctypes.c_uint32), ("queue_chunk", ctypes.c_uint32),
+                ("coop_degree", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 3)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_ if k != "reserved"}
+
+
+class TrwError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                      "(hipcc --offload-arch=gfx950) first")
+
+lib = ctypes.CDLL(LIB_PATH)
+
+_P = ctypes.c_void_p
+_PP = ctypes.POINTER(ctypes.c_void_p)
+_u32, _u64, _i64, _sz = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int64, ctypes.c_size_t
+_st = ctypes.c_int
+
+_SIGS = {
+    "trw_last_error": (ctypes.c_char_p, []),
+    "trw_abi_version": (_u32, []),
+    "trw_graph_create": (_st, [_i64, _i64, _P, _P, _P, _P, _u32, _PP]),
+    "trw_graph_validate": (_st, [_P, _P, _sz, _P, ctypes.POINTER(_u64)]),
+    "trw_graph_destroy": (_st, [_P]),
+    "trw_table_bytes": (_st, [_P, _u32, ctypes.POINTER(_sz)]),
+    "trw_table_build": (_st, [_P, _u32, _P, _sz, _P, _PP]),
+    "trw_table_destroy": (_st, [_P]),
+    "trw_walk_workspace_bytes": (_st, [_P, ctypes.POINTER(trw_walk_params), _u64, _u32, ctypes.POINTER(_sz)]),
+    "trw_default_tuning": (_st, [_P, ctypes.POINTER(trw_walk_params), _u32, ctypes.POINTER(trw_tuning)]),
+    "trw_walk": (_st, [_P, _P, ctypes.POINTER(trw_walk_params), _P, _u64, _u64, _P, _u64, _P, _P, _u32,
+                       ctypes.POINTER(trw_tuning), _P, _sz, _P]),
+    "trw_autotune": (_st, [_P, _P, ctypes.POINTER(trw_walk_params), _P, _u64, _P, _u64, _P, _P, _u32, _u32,
+                           _P, _sz, _P, ctypes.POINTER(trw_tuning), ctypes.POINTER(ctypes.c_float)]),
+}
+
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+def check(status: int) -> None:
+    """Raise TrwError with the library's message unless status == TRW_OK."""
+    if status != TRW_OK:
+        raise TrwError(status, lib.trw_last_error().decode())
+
+
+def __getattr__(name):
+    if name.startswith("trw_"):
+        return getattr(lib, name)
+    raise AttributeError(name)
+
+
+# Module-level functions with the ABI's names (argument marshalling only).
+trw_last_error = lib.trw_last_error
+trw_abi_version = lib.trw_abi_version
+trw_graph_create = lib.trw_graph_create
+trw_graph_validate = lib.trw_graph_validate
+trw_graph_destroy = lib.trw_graph_destroy
+trw_table_bytes = lib.trw_table_bytes
+trw_table_build = lib.trw_table_build
+trw_table_destroy = lib.trw_table_destroy
+trw_walk_workspace_bytes = lib.trw_walk_workspace_bytes
+trw_default_tuning = lib.trw_default_tuning
+trw_walk = lib.trw_walk
+trw_autotune = lib.trw_autotune

@@ -1,0 +1,325 @@
+// C ABI of the walk engine: argument checks, handles and dispatch to the
+// kernel launchers.  Nothing here computes a walk.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "trw_internal.hpp"
+
+struct trw_graph_s {
+    trw::GraphDev dev;
+    uint32_t flags;
+    int device;
+};
+
+struct trw_table_s {
+    trw_graph graph;
+    uint32_t sampler;
+    void *buf;
+};
+
+namespace trw {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+const DeviceInfo &device_info() {
+    static std::mutex mu;
+    static std::vector<DeviceInfo> cache;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lk(mu);
+    for (const auto &d : cache)
+        if (d.device == dev) return d;
+    DeviceInfo di{dev, 256};
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+        di.num_cus = cus;
+    cache.push_back(di);
+    return cache.back();
+}
+
+namespace {
+
+trw_status fail(trw_status st, const std::string &msg) {
+    set_error(msg);
+    return st;
+}
+
+trw_status device_fail(hipError_t e, const char *what) {
+    return fail(TRW_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+bool pair_supported(uint32_t algo, uint32_t sampler) {
+    switch (algo) {
+        case TRW_A_DEEPWALK:
+        case TRW_A_PPR:
+            return sampler == TRW_S_NAIVE || sampler == TRW_S_ALIAS || sampler == TRW_S_ITS;
+        case TRW_A_NODE2VEC:
+            return sampler == TRW_S_OREJ;
+        case TRW_A_METAPATH:
+            return sampler == TRW_S_ITS;
+        default:
+            return false;
+    }
+}
+
+trw_status check_params(trw_graph g, const trw_walk_params *p) {
+    if (!g) return fail(TRW_E_INVALID, "graph is NULL");
+    if (!p) return fail(TRW_E_INVALID, "params is NULL");
+    if (p->algo > TRW_A_METAPATH) return fail(TRW_E_UNSUPPORTED, "unknown algorithm");
+    if (!pair_supported(p->algo, p->sampler))
+        return fail(TRW_E_UNSUPPORTED, "sampler not provided for this algorithm");
+    if (p->max_len == 0 || p->max_len > 65535) return fail(TRW_E_INVALID, "max_len must be in 1..65535");
+    if (p->algo == TRW_A_NODE2VEC) {
+        for (int i = 0; i < 3; ++i)
+            if (p->n2v_thr_q16[i] == 0 || p->n2v_thr_q16[i] > 65536)
+                return fail(TRW_E_INVALID, "Node2Vec thresholds must be in 1..65536");
+    }
+    if (p->algo == TRW_A_METAPATH) {
+        if (p->schema_len == 0 || p->schema_len > 16) return fail(TRW_E_INVALID, "schema_len must be in 1..16");
+        if (!g->dev.label) return fail(TRW_E_INVALID, "MetaPath needs edge labels");
+    }
+    return TRW_OK;
+}
+
+Tuning resolve_tuning(const trw_walk_params *p, uint32_t mode, const trw_tuning *t) {
+    Tuning tu{1, 256, mode == TRW_M_PERSISTENT ? 8u : 8u, 256, 256};
+    (void)p;
+    if (t) {
+        if (t->walkers_per_lane == 1 || t->walkers_per_lane == 2 || t->walkers_per_lane == 4)
+            tu.walkers_per_lane = t->walkers_per_lane;
+        if (t->block_threads >= 64 && t->block_threads <= 256 && t->block_threads % 64 == 0)
+            tu.block_threads = t->block_threads;
+        if (t->blocks_per_cu >= 1 && t->blocks_per_cu <= 64) tu.blocks_per_cu = t->blocks_per_cu;
+        if (t->queue_chunk >= 1) tu.queue_chunk = t->queue_chunk;
+        if (t->coop_degree >= 1) tu.coop_degree = t->coop_degree;
+    }
+    return tu;
+}
+
+}  // namespace
+}  // namespace trw
+
+using namespace trw;
+
+extern "C" {
+
+const char *trw_last_error(void) { return g_last_error.c_str(); }
+
+uint32_t trw_abi_version(void) { return TRW_ABI_VERSION; }
+
+trw_status trw_graph_create(int64_t n, int64_t m, const int32_t *d_row_ptr, const int32_t *d_col,
+                            const uint32_t *d_weight, const uint8_t *d_label, uint32_t flags,
+                            trw_graph *out) {
+    if (!out) return fail(TRW_E_INVALID, "out is NULL");
+    if (n < 1 || n >= (int64_t(1) << 31)) return fail(TRW_E_INVALID, "n must be in 1..2^31-1");
+    if (m < 0 || m >= (int64_t(1) << 31)) return fail(TRW_E_INVALID, "m must be in 0..2^31-1");
+    if (!d_row_ptr || (!d_col && m > 0)) return fail(TRW_E_INVALID, "row_ptr / col is NULL");
+    auto *g = new (std::nothrow) trw_graph_s;
+    if (!g) return fail(TRW_E_INVALID, "out of host memory");
+    g->dev = GraphDev{d_row_ptr, d_col, d_weight, d_label, (int32_t)n, (int32_t)m};
+    g->flags = flags;
+    g->device = device_info().device;
+    *out = g;
+    return TRW_OK;
+}
+
+trw_status trw_graph_validate(trw_graph g, void *d_ws, size_t ws_bytes, trw_stream_t stream, uint64_t *n_bad) {
+    if (!g || !n_bad) return fail(TRW_E_INVALID, "graph / n_bad is NULL");
+    if (!d_ws || ws_bytes < 64 || (reinterpret_cast<uintptr_t>(d_ws) & 7))
+        return fail(TRW_E_INVALID, "validate needs >= 64 bytes of 8-byte aligned device scratch");
+    auto s = static_cast<hipStream_t>(stream);
+    auto *bad = static_cast<unsigned long long *>(d_ws);
+    hipError_t e = launch_validate(g->dev, bad, s);
+    if (e != hipSuccess) return device_fail(e, "validate launch");
+    unsigned long long h = 0;
+    e = hipMemcpyAsync(&h, bad, sizeof(h), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return device_fail(e, "validate readback");
+    *n_bad = h;
+    if (h) return fail(TRW_E_INVALID, "graph failed validation: " + std::to_string(h) + " violations");
+    return TRW_OK;
+}
+
+trw_status trw_graph_destroy(trw_graph g) {
+    delete g;
+    return TRW_OK;
+}
+
+trw_status trw_table_bytes(trw_graph g, uint32_t sampler, size_t *bytes) {
+    if (!g || !bytes) return fail(TRW_E_INVALID, "graph / bytes is NULL");
+    switch (sampler) {
+        case TRW_S_ALIAS: *bytes = sizeof(uint4) * (size_t)g->dev.m; return TRW_OK;
+        case TRW_S_ITS: *bytes = sizeof(uint64_t) * (size_t)g->dev.m; return TRW_OK;
+        case TRW_S_NAIVE:
+        case TRW_S_OREJ: *bytes = 0; return fail(TRW_E_UNSUPPORTED, "sampler has no table");
+        default: return fail(TRW_E_UNSUPPORTED, "unknown sampler");
+    }
+}
+
+trw_status trw_table_build(trw_graph g, uint32_t sampler, void *d_buf, size_t bytes, trw_stream_t stream,
+                           trw_table *out) {
+    if (!g || !out) return fail(TRW_E_INVALID, "graph / out is NULL");
+    size_t need = 0;
+    trw_status st = trw_table_bytes(g, sampler, &need);
+    if (st != TRW_OK) return st;
+    if (!g->dev.weight) return fail(TRW_E_INVALID, "table needs edge weights");
+    if (bytes < need) return fail(TRW_E_INVALID, "table buffer too small");
+    if (g->dev.m > 0 && (!d_buf || (reinterpret_cast<uintptr_t>(d_buf) & 15)))
+        return fail(TRW_E_INVALID, "table buffer NULL or not 16-byte aligned");
+    auto s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipSuccess;
+    if (g->dev.m > 0) {
+        e = sampler == TRW_S_ALIAS ? launch_alias_build(g->dev, static_cast<uint4 *>(d_buf), s)
+                                   : launch_its_build(g->dev, static_cast<uint64_t *>(d_buf), s);
+    }
+    if (e != hipSuccess) return device_fail(e, "table build launch");
+    auto *t = new (std::nothrow) trw_table_s{g, sampler, d_buf};
+    if (!t) return fail(TRW_E_INVALID, "out of host memory");
+    *out = t;
+    return TRW_OK;
+}
+
+trw_status trw_table_destroy(trw_table t) {
+    delete t;
+    return TRW_OK;
+}
+
+trw_status trw_walk_workspace_bytes(trw_graph g, const trw_walk_params *p, uint64_t nq, uint32_t mode,
+                                    size_t *bytes) {
+    trw_status st = check_params(g, p);
+    if (st != TRW_OK) return st;
+    if (!bytes) return fail(TRW_E_INVALID, "bytes is NULL");
+    if (mode > TRW_M_PERSISTENT) return fail(TRW_E_INVALID, "unknown mode");
+    if (nq >= (uint64_t(1) << 32)) return fail(TRW_E_INVALID, "nq must be < 2^32");
+    *bytes = walk_workspace_bytes(mode, nq, p->max_len);
+    return TRW_OK;
+}
+
+trw_status trw_default_tuning(trw_graph g, const trw_walk_params *p, uint32_t mode, trw_tuning *out) {
+    trw_status st = check_params(g, p);
+    if (st != TRW_OK) return st;
+    if (!out) return fail(TRW_E_INVALID, "out is NULL");
+    const Tuning tu = resolve_tuning(p, mode, nullptr);
+    std::memset(out, 0, sizeof(*out));
+    out->walkers_per_lane = tu.walkers_per_lane;
+    out->block_threads = tu.block_threads;
+    out->blocks_per_cu = tu.blocks_per_cu;
+    out->queue_chunk = tu.queue_chunk;
+    out->coop_degree = tu.coop_degree;
+    return TRW_OK;
+}
+
+trw_status trw_walk(trw_graph g, trw_table table, const trw_walk_params *p, const int32_t *d_sources,
+                    uint64_t nq, uint64_t qid_base, int32_t *d_paths, uint64_t path_stride,
+                    uint32_t *d_lengths, uint8_t *d_status, uint32_t mode, const trw_tuning *tuning,
+                    void *d_ws, size_t ws_bytes, trw_stream_t stream) {
+    trw_status st = check_params(g, p);
+    if (st != TRW_OK) return st;
+    if (mode > TRW_M_PERSISTENT) return fail(TRW_E_INVALID, "unknown mode");
+    if (nq >= (uint64_t(1) << 32)) return fail(TRW_E_INVALID, "nq must be < 2^32");
+    const bool needs_table = (p->algo == TRW_A_DEEPWALK || p->algo == TRW_A_PPR) &&
+                             (p->sampler == TRW_S_ALIAS || p->sampler == TRW_S_ITS);
+    if (needs_table) {
+        if (!table) return fail(TRW_E_INVALID, "ALIAS / ITS walks need a table");
+        if (table->graph != g) return fail(TRW_E_INVALID, "table was built for another graph");
+        if (table->sampler != p->sampler) return fail(TRW_E_INVALID, "table was built for another sampler");
+    }
+    if (path_stride < (uint64_t)p->max_len + 1) return fail(TRW_E_INVALID, "path_stride < max_len + 1");
+    if (nq == 0) return TRW_OK;
+    if (!d_sources || !d_paths || !d_lengths || !d_status)
+        return fail(TRW_E_INVALID, "sources / paths / lengths / status is NULL");
+    const size_t need = walk_workspace_bytes(mode, nq, p->max_len);
+    if (!d_ws || ws_bytes < need || (reinterpret_cast<uintptr_t>(d_ws) & 255))
+        return fail(TRW_E_INVALID, "workspace NULL, too small or not 256-byte aligned");
+
+    WalkDev w{};
+    w.max_len = p->max_len;
+    w.stop_q32 = p->algo == TRW_A_PPR ? p->stop_q32 : 0;
+    for (int i = 0; i < 3; ++i) w.thr[i] = p->n2v_thr_q16[i];
+    w.schema_len = p->algo == TRW_A_METAPATH ? p->schema_len : 1;
+    for (int i = 0; i < 8; ++i) {
+        w.schema_lo |= (uint64_t)p->schema[i] << (8 * i);
+        w.schema_hi |= (uint64_t)p->schema[8 + i] << (8 * i);
+    }
+    w.seed = p->seed;
+    w.sources = d_sources;
+    w.nq = (uint32_t)nq;
+    w.qid_base = qid_base;
+    w.paths = d_paths;
+    w.stride = path_stride;
+    w.lengths = d_lengths;
+    w.status = d_status;
+    TableDev t{nullptr, nullptr};
+    if (needs_table) {
+        if (p->sampler == TRW_S_ALIAS) t.alias = static_cast<const uint4 *>(table->buf);
+        else t.prefix = static_cast<const uint64_t *>(table->buf);
+    }
+    const Tuning tu = resolve_tuning(p, mode, tuning);
+    hipError_t e = launch_walk(g->dev, t, p->algo, p->sampler, w, mode, tu, device_info(), d_ws, ws_bytes,
+                               static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return device_fail(e, "walk launch");
+    return TRW_OK;
+}
+
+trw_status trw_autotune(trw_graph g, trw_table table, const trw_walk_params *p, const int32_t *d_sources,
+                        uint64_t nq, int32_t *d_paths, uint64_t path_stride, uint32_t *d_lengths,
+                        uint8_t *d_status, uint32_t mode, uint32_t budget, void *d_ws, size_t ws_bytes,
+                        trw_stream_t stream, trw_tuning *out, float *best_ms) {
+    if (!out) return fail(TRW_E_INVALID, "out is NULL");
+    std::vector<trw_tuning> cands;
+    if (mode == TRW_M_PERSISTENT) {
+        for (uint32_t wpl : {1u, 2u, 4u})
+            for (uint32_t bpc : {4u, 8u, 16u})
+                for (uint32_t chunk : {64u, 256u, 1024u}) {
+                    trw_tuning t{};
+                    t.walkers_per_lane = wpl; t.block_threads = 256; t.blocks_per_cu = bpc;
+                    t.queue_chunk = chunk; t.coop_degree = 256;
+                    cands.push_back(t);
+                }
+    } else {
+        for (uint32_t bpc : {2u, 4u, 8u, 16u})
+            for (uint32_t threads : {128u, 256u}) {
+                trw_tuning t{};
+                t.walkers_per_lane = 1; t.block_threads = threads; t.blocks_per_cu = bpc;
+                t.queue_chunk = 256; t.coop_degree = 256;
+                cands.push_back(t);
+            }
+    }
+    if (budget > 0 && budget < cands.size()) cands.resize(budget);
+    auto s = static_cast<hipStream_t>(stream);
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(TRW_E_DEVICE, "hipEventCreate failed");
+    float best = -1.0f;
+    trw_tuning best_t{};
+    trw_status result = TRW_OK;
+    for (const auto &c : cands) {
+        // one untimed run (warm caches), one timed run
+        for (int rep = 0; rep < 2 && result == TRW_OK; ++rep) {
+            (void)hipEventRecord(e0, s);
+            result = trw_walk(g, table, p, d_sources, nq, 0, d_paths, path_stride, d_lengths, d_status, mode,
+                              &c, d_ws, ws_bytes, stream);
+            (void)hipEventRecord(e1, s);
+        }
+        if (result != TRW_OK) break;
+        if (hipEventSynchronize(e1) != hipSuccess) { result = fail(TRW_E_DEVICE, "event sync failed"); break; }
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (best < 0 || ms < best) { best = ms; best_t = c; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (result != TRW_OK) return result;
+    *out = best_t;
+    if (best_ms) *best_ms = best;
+    return TRW_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,155 @@
+// Per-vertex sampling tables (the preprocessing of static walks: the paper
+// builds each vertex's table once, before any query runs).
+//
+// ALIAS: Walker's alias method with Vose's worklist construction in exact
+// integers.  The construction pops "small" columns (scaled mass below the row
+// total W) and pairs each with the "large" column on top of the large stack,
+// both stacks last-in first-out and filled in index order.  Two facts make a
+// stack-free, single-pass form possible on the GPU:
+//   * a small column is popped exactly once, and the only column whose mass
+//     changes is the large column on top; when it falls below W it is pushed
+//     on the small stack and therefore popped immediately after;
+//   * so the small stack is "the original small columns from the highest
+//     index down, with at most one demoted large column in front", and the
+//     large stack is "the original large columns from the highest index
+//     down".
+// Each thread therefore walks its row with two cursors moving downwards and
+// keeps one demoted column in registers: O(d) time, O(1) state, no scratch.
+//
+// ITS: inclusive running sum of the weights per row in uint64.
+#include "trw_device.hpp"
+#include "trw_internal.hpp"
+
+namespace trw {
+namespace {
+
+// floor(s * 2^32 / W) for s < W < 2^63, by restoring shift-subtract division.
+__device__ __forceinline__ uint32_t frac32(uint64_t s, uint64_t W) {
+    uint64_t rem = s;
+    uint32_t q = 0;
+#pragma unroll 4
+    for (int i = 0; i < 32; ++i) {
+        rem <<= 1;
+        q <<= 1;
+        if (rem >= W) { rem -= W; q |= 1u; }
+    }
+    return q;
+}
+
+// Next index below `from` whose scaled mass w*d is below (want_small) or at least W.
+__device__ __forceinline__ int64_t next_below(const uint32_t *__restrict__ w, int64_t from, uint64_t d,
+                                              uint64_t W, bool want_small) {
+    for (int64_t i = from - 1; i >= 0; --i) {
+        const bool small = (uint64_t)w[i] * d < W;
+        if (small == want_small) return i;
+    }
+    return -1;
+}
+
+__global__ void k_alias_build(GraphDev g, uint4 *__restrict__ out) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= g.n) return;
+    const int64_t off = g.row_ptr[v];
+    const int64_t d = (int64_t)g.row_ptr[v + 1] - off;
+    if (d <= 0) return;
+    const uint32_t *__restrict__ w = g.weight + off;
+    const int32_t *__restrict__ col = g.col + off;
+    uint4 *__restrict__ row = out + off;
+
+    uint64_t W = 0;
+    for (int64_t i = 0; i < d; ++i) W += w[i];
+    if (W == 0) {
+        for (int64_t i = 0; i < d; ++i) row[i] = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0u);
+        return;
+    }
+    const uint64_t ud = (uint64_t)d;
+    int64_t small_next = next_below(w, d, ud, W, true);   // top of the original small stack
+    int64_t g_top = next_below(w, d, ud, W, false);       // top of the large stack
+    uint64_t g_mass = g_top >= 0 ? (uint64_t)w[g_top] * ud : 0;
+    int64_t demoted = -1;                                  // a large column pushed on "small"
+    uint64_t demoted_mass = 0;
+
+    while ((demoted >= 0 || small_next >= 0) && g_top >= 0) {
+        int64_t l;
+        uint64_t l_mass;
+        if (demoted >= 0) {
+            l = demoted; l_mass = demoted_mass; demoted = -1;
+        } else {
+            l = small_next; l_mass = (uint64_t)w[l] * ud;
+            small_next = next_below(w, l, ud, W, true);
+        }
+        row[l] = make_uint4(frac32(l_mass, W), (uint32_t)col[l], (uint32_t)col[g_top], 0u);
+        g_mass -= W - l_mass;
+        if (g_mass < W) {
+            demoted = g_top; demoted_mass = g_mass;
+            g_top = next_below(w, g_top, ud, W, false);
+            g_mass = g_top >= 0 ? (uint64_t)w[g_top] * ud : 0;
+        }
+    }
+    // Columns left on the large stack are full buckets.
+    while (g_top >= 0) {
+        row[g_top] = make_uint4(0xFFFFFFFFu, (uint32_t)col[g_top], (uint32_t)col[g_top], 0u);
+        g_top = next_below(w, g_top, ud, W, false);
+    }
+}
+
+__global__ void k_its_build(GraphDev g, uint64_t *__restrict__ out) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= g.n) return;
+    const int64_t lo = g.row_ptr[v], hi = g.row_ptr[v + 1];
+    uint64_t acc = 0;
+    for (int64_t e = lo; e < hi; ++e) {
+        acc += g.weight[e];
+        out[e] = acc;
+    }
+}
+
+__global__ void k_zero_u64(unsigned long long *p) { *p = 0; }
+
+__global__ void k_validate(GraphDev g, unsigned long long *__restrict__ bad) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v > g.n) return;
+    unsigned long long nbad = 0;
+    if (v == 0 && g.row_ptr[0] != 0) nbad++;
+    if (v == g.n) {
+        if (g.row_ptr[g.n] != g.m) nbad++;
+    } else {
+        const int64_t lo = g.row_ptr[v], hi = g.row_ptr[v + 1];
+        if (hi < lo || lo < 0 || hi > g.m) {
+            nbad++;
+        } else {
+            int64_t last = -1;
+            for (int64_t e = lo; e < hi; ++e) {
+                const int64_t c = g.col[e];
+                if (c < 0 || c >= g.n || c <= last) nbad++;
+                last = c;
+            }
+        }
+    }
+    if (nbad) atomicAdd(bad, nbad);
+}
+
+constexpr int kBuildThreads = 256;
+
+}  // namespace
+
+hipError_t launch_alias_build(const GraphDev &g, uint4 *out, hipStream_t s) {
+    const int blocks = (g.n + kBuildThreads - 1) / kBuildThreads;
+    hipLaunchKernelGGL(k_alias_build, dim3(blocks), dim3(kBuildThreads), 0, s, g, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_its_build(const GraphDev &g, uint64_t *out, hipStream_t s) {
+    const int blocks = (g.n + kBuildThreads - 1) / kBuildThreads;
+    hipLaunchKernelGGL(k_its_build, dim3(blocks), dim3(kBuildThreads), 0, s, g, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_validate(const GraphDev &g, unsigned long long *d_bad, hipStream_t s) {
+    const int blocks = (g.n + 1 + kBuildThreads - 1) / kBuildThreads;
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, d_bad);
+    hipLaunchKernelGGL(k_validate, dim3(blocks), dim3(kBuildThreads), 0, s, g, d_bad);
+    return hipGetLastError();
+}
+
+}  // namespace trw

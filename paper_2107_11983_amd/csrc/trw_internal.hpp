@@ -1,0 +1,83 @@
+// Internal types shared by the C ABI layer and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/trw.h"
+
+namespace trw {
+
+// Device view of a CSR graph (borrowed caller memory).
+struct GraphDev {
+    const int32_t *row_ptr;
+    const int32_t *col;
+    const uint32_t *weight;
+    const uint8_t *label;
+    int32_t n;
+    int32_t m;
+};
+
+// ALIAS entries are {thr, dst_first, dst_second, 0}: the destination ids are
+// stored beside the coin threshold so that a move needs one random 16-byte
+// read of the table and none of the adjacency array.
+struct TableDev {
+    const uint4 *alias;       // ALIAS: one entry per edge slot
+    const uint64_t *prefix;   // ITS: inclusive prefix per row
+};
+
+// Parameters of one batch of queries as the kernels see them.
+struct WalkDev {
+    uint32_t max_len;
+    uint32_t stop_q32;
+    uint32_t thr[3];
+    uint32_t schema_len;
+    uint64_t schema_lo;      // labels 0..7 of the MetaPath schema, one byte each
+    uint64_t schema_hi;      // labels 8..15
+    uint64_t seed;
+    const int32_t *sources;
+    uint32_t nq;
+    uint64_t qid_base;
+    int32_t *paths;
+    uint64_t stride;
+    uint32_t *lengths;
+    uint8_t *status;
+};
+
+enum : uint8_t { ST_LENGTH = 1, ST_STOPPED = 2, ST_DEAD_END = 3, ST_BAD_SOURCE = 4 };
+enum : uint32_t { ALG_DEEPWALK = 0, ALG_PPR = 1, ALG_NODE2VEC = 2, ALG_METAPATH = 3 };
+enum : uint32_t { SMP_NAIVE = 0, SMP_ALIAS = 1, SMP_ITS = 2, SMP_OREJ = 3 };
+
+// Darts per O-REJ move at most (then the last dart is taken); with every
+// threshold >= 1 the cap is reached with probability below e^-256.
+constexpr uint32_t kMaxDarts = 1u << 24;
+
+struct Tuning {
+    uint32_t walkers_per_lane;
+    uint32_t block_threads;
+    uint32_t blocks_per_cu;
+    uint32_t queue_chunk;
+    uint32_t coop_degree;
+};
+
+struct DeviceInfo {
+    int device;
+    int num_cus;
+};
+
+// Host launchers (tables.hip, walk.hip).  Return hipSuccess or the launch error.
+hipError_t launch_alias_build(const GraphDev &g, uint4 *out, hipStream_t s);
+hipError_t launch_its_build(const GraphDev &g, uint64_t *out, hipStream_t s);
+hipError_t launch_validate(const GraphDev &g, unsigned long long *d_bad, hipStream_t s);
+
+size_t walk_workspace_bytes(uint32_t mode, uint64_t nq, uint32_t max_len);
+hipError_t launch_walk(const GraphDev &g, const TableDev &t, uint32_t algo, uint32_t sampler,
+                       const WalkDev &w, uint32_t mode, const Tuning &tu, const DeviceInfo &di,
+                       void *d_ws, size_t ws_bytes, hipStream_t s);
+
+const DeviceInfo &device_info();
+void set_error(const std::string &msg);
+
+}  // namespace trw

@@ -1,0 +1,131 @@
+"""The C ABI library on a host without a GPU: it loads, exports every symbol
+that include/trw.h declares, and rejects bad arguments before any device work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "trw.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(trw_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def abi():
+    from paper_2107_11983_amd import _abi
+    return _abi
+
+
+def test_exports_every_declared_symbol(abi):
+    names = _declared_functions()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(abi.lib, n), f"{n} declared in trw.h but not exported"
+    assert set(names) <= set(abi._SIGS), "binding lacks a declared function"
+
+
+def test_abi_version(abi):
+    m = re.search(r"#define TRW_ABI_VERSION (\d+)u", open(HEADER).read())
+    assert abi.trw_abi_version() == int(m.group(1))
+
+
+def _fake_graph(abi, labels=False, weights=False):
+    h = ctypes.c_void_p()
+    fake = ctypes.c_void_p(0x1000)
+    st = abi.trw_graph_create(100, 1000, fake, fake, fake if weights else None, fake if labels else None,
+                              0, ctypes.byref(h))
+    assert st == abi.TRW_OK, abi.trw_last_error()
+    return h
+
+
+def test_graph_create_rejects_bad_sizes(abi):
+    h = ctypes.c_void_p()
+    fake = ctypes.c_void_p(0x1000)
+    assert abi.trw_graph_create(0, 10, fake, fake, None, None, 0, ctypes.byref(h)) == abi.TRW_E_INVALID
+    assert b"n must be" in abi.trw_last_error()
+    assert abi.trw_graph_create(10, -1, fake, fake, None, None, 0, ctypes.byref(h)) == abi.TRW_E_INVALID
+    assert abi.trw_graph_create(10, 2**31, fake, fake, None, None, 0, ctypes.byref(h)) == abi.TRW_E_INVALID
+    assert abi.trw_graph_create(10, 5, None, fake, None, None, 0, ctypes.byref(h)) == abi.TRW_E_INVALID
+    assert abi.trw_graph_create(10, 5, fake, fake, None, None, 0, None) == abi.TRW_E_INVALID
+
+
+def _params(abi, algo, sampler, max_len=10, thr=(65536, 65536, 65536), schema=()):
+    from paper_2107_11983_amd import make_params
+    return make_params(algo, sampler, max_len, 1, n2v_thr_q16=thr, schema=schema)
+
+
+def test_param_validation(abi):
+    g = _fake_graph(abi)
+    sz = ctypes.c_size_t()
+    def ws(p, nq=10, mode=1):
+        return abi.trw_walk_workspace_bytes(g, ctypes.byref(p), nq, mode, ctypes.byref(sz))
+    assert ws(_params(abi, "deepwalk", "naive")) == abi.TRW_OK
+    assert ws(_params(abi, "deepwalk", "orej")) == abi.TRW_E_UNSUPPORTED
+    assert ws(_params(abi, "node2vec", "naive")) == abi.TRW_E_UNSUPPORTED
+    assert ws(_params(abi, "metapath", "alias")) == abi.TRW_E_UNSUPPORTED
+    assert ws(_params(abi, "deepwalk", "naive", max_len=0)) == abi.TRW_E_INVALID
+    assert ws(_params(abi, "deepwalk", "naive", max_len=65536)) == abi.TRW_E_INVALID
+    assert ws(_params(abi, "node2vec", "orej", thr=(0, 1, 1))) == abi.TRW_E_INVALID
+    assert ws(_params(abi, "node2vec", "orej", thr=(65537, 1, 1))) == abi.TRW_E_INVALID
+    assert ws(_params(abi, "metapath", "its", schema=(1, 2))) == abi.TRW_E_INVALID   # no labels
+    assert ws(_params(abi, "deepwalk", "naive"), nq=2**32) == abi.TRW_E_INVALID
+    assert ws(_params(abi, "deepwalk", "naive"), mode=7) == abi.TRW_E_INVALID
+    gl = _fake_graph(abi, labels=True)
+    p = _params(abi, "metapath", "its", schema=())
+    assert abi.trw_walk_workspace_bytes(gl, ctypes.byref(p), 1, 1, ctypes.byref(sz)) == abi.TRW_E_INVALID
+    p = _params(abi, "metapath", "its", schema=(1, 2, 3))
+    assert abi.trw_walk_workspace_bytes(gl, ctypes.byref(p), 1, 1, ctypes.byref(sz)) == abi.TRW_OK
+    # per-step workspace grows with nq; persistent does not
+    p = _params(abi, "ppr", "naive", max_len=256)
+    abi.trw_walk_workspace_bytes(g, ctypes.byref(p), 1000, 0, ctypes.byref(sz))
+    small = sz.value
+    abi.trw_walk_workspace_bytes(g, ctypes.byref(p), 100000, 0, ctypes.byref(sz))
+    assert sz.value > small
+    abi.trw_walk_workspace_bytes(g, ctypes.byref(p), 100000, 1, ctypes.byref(sz))
+    assert sz.value <= 256
+    for h in (g, gl):
+        abi.trw_graph_destroy(h)
+
+
+def test_walk_argument_checks(abi):
+    g = _fake_graph(abi, weights=True)
+    fake = ctypes.c_void_p(0x1000)
+    ws = ctypes.c_void_p(0x10000)
+    def walk(p, table=None, stride=11, ws_ptr=ws, ws_bytes=1 << 20, nq=5):
+        return abi.trw_walk(g, table, ctypes.byref(p), fake, nq, 0, fake, stride, fake, fake, 1, None,
+                            ws_ptr, ws_bytes, None)
+    assert walk(_params(abi, "deepwalk", "alias")) == abi.TRW_E_INVALID          # no table
+    assert b"table" in abi.trw_last_error()
+    assert walk(_params(abi, "ppr", "its")) == abi.TRW_E_INVALID
+    assert walk(_params(abi, "deepwalk", "naive"), stride=10) == abi.TRW_E_INVALID
+    assert walk(_params(abi, "deepwalk", "naive"), ws_ptr=ctypes.c_void_p(0x10010)) == abi.TRW_E_INVALID
+    assert walk(_params(abi, "deepwalk", "naive"), ws_bytes=0) == abi.TRW_E_INVALID
+    assert walk(_params(abi, "deepwalk", "naive"), nq=0) == abi.TRW_OK           # nothing to do
+    sz = ctypes.c_size_t()
+    assert abi.trw_table_bytes(g, abi.TRW_S_ALIAS, ctypes.byref(sz)) == abi.TRW_OK and sz.value == 16 * 1000
+    assert abi.trw_table_bytes(g, abi.TRW_S_ITS, ctypes.byref(sz)) == abi.TRW_OK and sz.value == 8 * 1000
+    assert abi.trw_table_bytes(g, abi.TRW_S_NAIVE, ctypes.byref(sz)) == abi.TRW_E_UNSUPPORTED
+    t = ctypes.c_void_p()
+    assert abi.trw_table_build(g, abi.TRW_S_ALIAS, fake, 10, None, ctypes.byref(t)) == abi.TRW_E_INVALID
+    assert abi.trw_table_build(g, abi.TRW_S_ALIAS, ctypes.c_void_p(0x1004), 16000, None,
+                               ctypes.byref(t)) == abi.TRW_E_INVALID
+    gn = _fake_graph(abi)
+    assert abi.trw_table_build(gn, abi.TRW_S_ITS, fake, 8000, None, ctypes.byref(t)) == abi.TRW_E_INVALID
+    abi.trw_graph_destroy(g)
+    abi.trw_graph_destroy(gn)
+
+
+def test_default_tuning(abi):
+    from paper_2107_11983_amd import default_tuning
+    g = _fake_graph(abi)
+    t = abi.trw_tuning()
+    p = _params(abi, "deepwalk", "naive")
+    assert abi.trw_default_tuning(g, ctypes.byref(p), 1, ctypes.byref(t)) == abi.TRW_OK
+    assert t.walkers_per_lane in (1, 2, 4) and t.block_threads % 64 == 0 and t.queue_chunk >= 1
+    abi.trw_graph_destroy(g)

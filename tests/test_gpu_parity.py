@@ -1,0 +1,329 @@
+"""Bit-exact parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Tables: ALIAS entries and ITS prefixes equal the oracle's, slot by slot.
+Walks: lengths, status and every path entry equal the oracle's for every
+(algorithm, sampler) pair, both schedules and every walkers-per-lane setting,
+on inputs that span many waves and end in a ragged tail, plus edge cases.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from helpers import star, undirected, zoo
+
+pytestmark = pytest.mark.gpu
+
+trw = None
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    global trw
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2107_11983_amd as mod
+    trw = mod
+    torch.cuda.set_device(0)
+    yield
+    torch.cuda.synchronize()
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+ORC_ALGO = {"deepwalk": oracle.DEEPWALK, "ppr": oracle.PPR, "node2vec": oracle.NODE2VEC, "metapath": oracle.METAPATH}
+ORC_SMP = {"naive": oracle.NAIVE, "alias": oracle.ALIAS, "its": oracle.ITS, "orej": oracle.OREJ}
+
+
+class Case:
+    """A host graph, its device twin and the oracle's tables."""
+
+    def __init__(self, g, symmetric=False):
+        self.g = g
+        self.G = trw.Graph(g.row_ptr, g.col, g.weight, g.label, symmetric=symmetric)
+        assert self.G.validate() == 0
+        self._dev_tables = {}
+        self._orc_tables = {}
+
+    def dev_table(self, sampler):
+        if sampler not in ("alias", "its"):
+            return None
+        if sampler not in self._dev_tables:
+            self._dev_tables[sampler] = self.G.table(sampler)
+        return self._dev_tables[sampler]
+
+    def orc_tables(self, sampler):
+        if sampler not in self._orc_tables:
+            if sampler == "alias":
+                t, a = oracle.alias_build(self.g.row_ptr, self.g.weight)
+                self._orc_tables[sampler] = dict(thr=t, alias=a)
+            elif sampler == "its":
+                self._orc_tables[sampler] = dict(prefix=oracle.its_build(self.g.row_ptr, self.g.weight))
+            else:
+                self._orc_tables[sampler] = {}
+        return self._orc_tables[sampler]
+
+
+def run_both(case, algo, sampler, max_len, seed, src, mode, tuning=None, qid_base=0, stop=0,
+             thr=(65536, 65536, 65536), schema=(), stride=0):
+    g = case.g
+    src = np.ascontiguousarray(src, dtype=np.int32)
+    nq = len(src)
+    log(f"  walk {algo}/{sampler} mode={mode} nq={nq} max_len={max_len} tuning={tuning and tuning.as_dict()}")
+    p = trw.make_params(algo, sampler, max_len, seed, stop_q32=stop, n2v_thr_q16=thr, schema=schema)
+    bufs = trw.WalkBuffers(case.G, p, nq, mode, stride)
+    bufs.paths.fill_(-7)
+    d_src = torch.from_numpy(src).cuda()
+    table = case.dev_table(sampler) if algo in ("deepwalk", "ppr") else None
+    trw.walk(case.G, table, p, d_src, qid_base=qid_base, mode=mode, tuning=tuning, bufs=bufs)
+    torch.cuda.synchronize()
+    gp = bufs.paths.cpu().numpy()
+    gl = bufs.lengths.cpu().numpy().view(np.uint32)
+    gs = bufs.status.cpu().numpy()
+    kw = dict(case.orc_tables(sampler)) if algo in ("deepwalk", "ppr") else {}
+    if algo == "metapath":
+        kw["label"] = g.label
+    op = oracle.WalkParams(ORC_ALGO[algo], ORC_SMP[sampler], max_len, seed, stop_q32=stop,
+                           n2v_thr_q16=tuple(thr), schema=tuple(schema))
+    ref = oracle.walk(g.row_ptr, g.col, op, src, qid_base=qid_base, **kw)
+    return (gp, gl, gs), ref
+
+
+def assert_same(gpu, ref, max_len):
+    gp, gl, gs = gpu
+    assert np.array_equal(gs, ref.status), f"status differs at {np.nonzero(gs != ref.status)[0][:10]}"
+    assert np.array_equal(gl, ref.lengths), f"lengths differ at {np.nonzero(gl != ref.lengths)[0][:10]}"
+    ok = ref.status != oracle.ST_BAD_SOURCE
+    mask = (np.arange(max_len + 1)[None, :] <= ref.lengths[:, None]) & ok[:, None]
+    bad = np.nonzero((gp[:, :max_len + 1] != ref.paths) & mask)
+    assert bad[0].size == 0, f"paths differ at queries {np.unique(bad[0])[:10]}"
+    # rows of bad sources are left untouched
+    if (~ok).any():
+        assert (gp[~ok] == -7).all()
+
+
+# --------------------------------------------------------------------------- fixtures
+@pytest.fixture(scope="module")
+def rmat_sym():
+    g = synth.rmat(11, 12, True, 0xC0FFEE)
+    synth.attach_attrs(g, 0xC0FFEE ^ 3, weights=True, labels=5)
+    return Case(g, symmetric=True)
+
+
+@pytest.fixture(scope="module")
+def rmat_dir():
+    g = synth.rmat(11, 16, False, 0xD1CE)
+    synth.attach_attrs(g, 0xD1CE ^ 3, weights=True)
+    return Case(g)
+
+
+# --------------------------------------------------------------------------- tables
+def _alias_expected(g, thr, alias):
+    rp, col = g.row_ptr.astype(np.int64), g.col
+    m = g.m
+    exp = np.zeros((m, 4), dtype=np.uint32)
+    exp[:, 0] = thr
+    src_row = np.repeat(np.arange(g.n), np.diff(rp))
+    first = col.astype(np.int64)
+    second = np.where(alias >= 0, col[np.clip(rp[src_row] + alias, 0, max(m - 1, 0))], -1)
+    exp[:, 1] = first.astype(np.int32).view(np.uint32)
+    exp[:, 2] = second.astype(np.int32).view(np.uint32)
+    dead = alias < 0
+    exp[dead, 1] = 0xFFFFFFFF
+    return exp
+
+
+def _weighted_rows_graph(seed, wmax, zero_rows=True):
+    rng = np.random.default_rng(seed)
+    edges, ws = [], []
+    n = 300
+    for v in range(n):
+        d = int(rng.integers(0, 120)) if v % 7 else int(rng.integers(300, 2000))
+        d = min(d, n - 1)
+        nb = np.sort(rng.choice(np.setdiff1d(np.arange(n), [v]), size=d, replace=False))
+        w = rng.integers(1, wmax + 1, size=d, dtype=np.uint64).astype(np.uint32)
+        if zero_rows and v % 11 == 0:
+            w[:] = 0
+        elif zero_rows and v % 5 == 0 and d > 2:
+            w[::2] = 0
+        edges += [(v, int(x)) for x in nb]
+        ws += w.tolist()
+    return synth.from_edges(n, edges, ws)
+
+
+@pytest.mark.parametrize("wmax", [255, 2**32 - 1])
+def test_alias_table_matches_oracle(wmax):
+    g = _weighted_rows_graph(wmax % 1000, wmax)
+    case = Case(g)
+    log(f"  alias table m={g.m}")
+    t = case.dev_table("alias")
+    torch.cuda.synchronize()
+    got = t.buf[:16 * g.m].view(torch.int32).cpu().numpy().view(np.uint32).reshape(-1, 4)
+    thr, alias = oracle.alias_build(g.row_ptr, g.weight)
+    exp = _alias_expected(g, thr, alias)
+    bad = np.nonzero((got[:, :3] != exp[:, :3]).any(axis=1))[0]
+    assert bad.size == 0, f"alias entries differ at edge slots {bad[:10]}"
+
+
+def test_alias_table_rmat(rmat_dir):
+    g = rmat_dir.g
+    t = rmat_dir.dev_table("alias")
+    torch.cuda.synchronize()
+    got = t.buf[:16 * g.m].view(torch.int32).cpu().numpy().view(np.uint32).reshape(-1, 4)
+    thr, alias = oracle.alias_build(g.row_ptr, g.weight)
+    assert np.array_equal(got[:, :3], _alias_expected(g, thr, alias)[:, :3])
+
+
+def test_its_table_matches_oracle(rmat_dir):
+    for case in (rmat_dir, Case(_weighted_rows_graph(5, 2**32 - 1))):
+        g = case.g
+        t = case.dev_table("its")
+        torch.cuda.synchronize()
+        got = t.buf[:8 * g.m].view(torch.int64).cpu().numpy().view(np.uint64)
+        assert np.array_equal(got, oracle.its_build(g.row_ptr, g.weight))
+
+
+def test_validate_rejects_bad_graphs():
+    g = synth.from_edges(4, [(0, 1), (0, 2), (1, 0), (2, 3)])
+    G = trw.Graph(g.row_ptr, g.col)
+    assert G.validate() == 0
+    bad_col = g.col.copy()
+    bad_col[0], bad_col[1] = bad_col[1], bad_col[0]          # unsorted row
+    assert trw.Graph(g.row_ptr, bad_col).validate() == 1
+    bad_col2 = g.col.copy()
+    bad_col2[3] = 9                                          # out of range
+    assert trw.Graph(g.row_ptr, bad_col2).validate() >= 1
+    dup = synth.from_edges(3, [(0, 1), (0, 1), (1, 2)])      # duplicate edge
+    assert trw.Graph(dup.row_ptr, dup.col).validate() == 1
+
+
+# --------------------------------------------------------------------------- walks
+PAIRS = [("deepwalk", "naive"), ("deepwalk", "alias"), ("deepwalk", "its"),
+         ("ppr", "naive"), ("ppr", "alias"), ("ppr", "its"),
+         ("node2vec", "orej"), ("metapath", "its")]
+
+
+def _args(algo):
+    kw = {}
+    if algo == "ppr":
+        kw["stop"] = oracle.stop_q32(0.2)
+    if algo == "node2vec":
+        kw["thr"] = oracle.n2v_thresholds(2.0, 0.5)
+    if algo == "metapath":
+        kw["schema"] = (3, 1, 4, 1, 0)
+    return kw
+
+
+@pytest.mark.parametrize("algo,sampler", PAIRS)
+@pytest.mark.parametrize("mode", [1, 0])
+def test_walk_parity(rmat_sym, rmat_dir, algo, sampler, mode):
+    case = rmat_dir if algo == "ppr" else rmat_sym
+    n = case.g.n
+    src = np.concatenate([np.arange(n), synth.sources(37 + 64 * 3, n, 4)]).astype(np.int32)  # ragged tail
+    max_len = 256 if algo == "ppr" else (100 if algo == "metapath" else 40)
+    gpu, ref = run_both(case, algo, sampler, max_len, 0x5EED + mode, src, mode, **_args(algo))
+    assert_same(gpu, ref, max_len)
+    assert ref.counters["moves"] > 0
+
+
+@pytest.mark.parametrize("algo,sampler", [("ppr", "alias"), ("node2vec", "orej"), ("metapath", "its"),
+                                          ("deepwalk", "its")])
+@pytest.mark.parametrize("wpl,bpc,chunk,threads", [(2, 8, 256, 256), (4, 4, 64, 256), (1, 1, 1, 64),
+                                                   (2, 3, 1000, 128)])
+def test_tuning_does_not_change_results(rmat_sym, rmat_dir, algo, sampler, wpl, bpc, chunk, threads):
+    case = rmat_dir if algo == "ppr" else rmat_sym
+    src = synth.sources(3 * 1024 + 5, case.g.n, 99)
+    max_len = 64
+    tu = trw.make_tuning(walkers_per_lane=wpl, blocks_per_cu=bpc, queue_chunk=chunk, block_threads=threads)
+    gpu, ref = run_both(case, algo, sampler, max_len, 77, src, 1, tuning=tu, **_args(algo))
+    assert_same(gpu, ref, max_len)
+
+
+def test_edge_cases(rmat_sym, rmat_dir):
+    n = rmat_dir.g.n
+    deg = rmat_dir.g.degrees()
+    dangling = np.nonzero(deg == 0)[0][:5]
+    assert len(dangling) > 0
+    # bad sources, dangling sources, one query, qid offset, wide stride
+    src = np.array([0, -1, n, int(dangling[0]), 5, 2**31 - 1, int(dangling[-1]), 7], np.int32)
+    for mode in (1, 0):
+        for algo, sampler in PAIRS:
+            case = rmat_dir if algo == "ppr" else rmat_sym
+            gpu, ref = run_both(case, algo, sampler, 9, 3, src, mode, qid_base=(1 << 40) + 5, stride=13,
+                                **_args(algo))
+            assert_same(gpu, ref, 9)
+        gpu, ref = run_both(rmat_dir, "ppr", "alias", 1, 3, src[4:5], mode)
+        assert_same(gpu, ref, 1)
+        gpu, ref = run_both(rmat_sym, "deepwalk", "naive", 1, 3, np.arange(n, dtype=np.int32), mode)
+        assert_same(gpu, ref, 1)
+
+
+def test_zero_weight_rows_are_dead_ends():
+    g = _weighted_rows_graph(9, 255)
+    case = Case(g)
+    src = np.arange(g.n, dtype=np.int32)
+    for sampler in ("alias", "its"):
+        for mode in (1, 0):
+            gpu, ref = run_both(case, "deepwalk", sampler, 30, 11, src, mode)
+            assert_same(gpu, ref, 30)
+            assert (ref.status == oracle.ST_DEAD_END).any()
+
+
+def test_zoo_graphs():
+    for name, g in zoo().items():
+        case = Case(g, symmetric=True)
+        src = np.tile(np.arange(g.n, dtype=np.int32), 50)
+        for algo, sampler in PAIRS:
+            gpu, ref = run_both(case, algo, sampler, 12, 5, src, 1, **_args(algo))
+            assert_same(gpu, ref, 12)
+
+
+def test_longest_walk():
+    n = 5
+    g = synth.from_edges(n, [(i, (i + 1) % n) for i in range(n)], weights=[2] * n)
+    case = Case(g)
+    src = np.array([0, 3], np.int32)
+    for mode in (1, 0):
+        gpu, ref = run_both(case, "deepwalk", "alias", 65535, 1, src, mode)
+        assert_same(gpu, ref, 65535)
+        assert (ref.lengths == 65535).all()
+
+
+def test_empty_batch(rmat_sym):
+    p = trw.make_params("deepwalk", "naive", 5, 1)
+    bufs = trw.WalkBuffers(rmat_sym.G, p, 0, 1)
+    trw.walk(rmat_sym.G, None, p, torch.empty(0, dtype=torch.int32, device="cuda"), bufs=bufs)
+    torch.cuda.synchronize()
+
+
+# --------------------------------------------------------------------------- workloads
+def test_deepwalk_rmat12_full():
+    """DeepWalk on the 2^12-vertex symmetric R-MAT graph, one walk of 80 per vertex."""
+    wl = synth.WORKLOADS["deepwalk-rmat12"]
+    g = synth.make_graph(wl)
+    case = Case(g, symmetric=True)
+    src = synth.make_sources(wl, g)
+    for mode in (1, 0):
+        gpu, ref = run_both(case, "deepwalk", "naive", 80, wl.walk_seed, src, mode)
+        assert_same(gpu, ref, 80)
+
+
+@pytest.mark.parametrize("name", ["ppr-rmat22", "node2vec-rmat24", "metapath-rmat24"])
+def test_workloads_reduced_scale(name):
+    """The larger workloads' recipes at 2^16 vertices, compared in full."""
+    wl = synth.WORKLOADS[name]
+    g = synth.make_graph(wl, scale=16)
+    case = Case(g, symmetric=wl.symmetric)
+    src = synth.make_sources(wl, g, nq=200_000 if wl.nq else None)
+    kw = _args(wl.algo)
+    if wl.algo == "metapath":
+        kw["schema"] = tuple(int(x) for x in synth.make_schema(wl))
+    for sampler in wl.samplers:
+        for mode in (1, 0):
+            gpu, ref = run_both(case, wl.algo, sampler, wl.max_len, wl.walk_seed, src, mode, **kw)
+            assert_same(gpu, ref, wl.max_len)
