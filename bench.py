@@ -1,0 +1,352 @@
+#!/usr/bin/env python3
+"""Walk-throughput benchmark on one MI355X.
+
+Default workload: PPR walks (stop probability 0.2 after each move, at most 256
+moves) from 10^7 uniformly random sources on a weighted directed R-MAT graph
+with 2^22 vertices and average degree 32 (uint32 weights in [1, 255]),
+sampled with the integer ALIAS table, one persistent launch per batch.  A
+"step" of this benchmark is one batch: all 10^7 queries walked to completion.
+
+Metric: walk steps (moves) per second of walk time, graph and tables resident
+in HBM (the paper's throughput: steps of all queries / execution time, table
+preprocessing timed separately; Experimental Setup, "Metrics").
+
+Printed: one JSON line with the throughput, a roofline object for the walk
+kernel, the oracle's single-core throughput on a bounded sample, the other
+sampler / schedule variants of the same workload, and the random-gather
+ceiling measured on the device.
+"""
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+KERNEL_SOURCES = ["paper_2107_11983_amd/csrc/walk.hip", "paper_2107_11983_amd/csrc/trw_device.hpp",
+                  "paper_2107_11983_amd/csrc/trw_internal.hpp"]
+
+# Algorithmic bytes ("Measurement"): per move the row range
+# (two int32 row offsets) 8 B, the sampling entry the move needs and the path
+# entry written 4 B; per query the source read, path[0], length and status.
+ENTRY_BYTES = {"alias": 12, "naive": 4, "its": None, "orej": None}
+PER_QUERY_BYTES = 4 + 4 + 4 + 1
+
+
+def log(msg):
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(tag):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, if it is current."""
+    path = os.path.join(ROOT, "profiles", f"counters_{tag}.md")
+    if not os.path.exists(path):
+        return None, None
+    text = open(path).read()
+    kv = dict(re.findall(r"^- (\w+): ([0-9a-fA-F.e+]+)\s*$", text, flags=re.M))
+    if kv.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None, "stale"
+    try:
+        return float(kv["traffic_bytes_per_launch"]), path
+    except KeyError:
+        return None, None
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="ppr-rmat22")
+    ap.add_argument("--sampler", default=None, help="default: the workload's first sampler")
+    ap.add_argument("--mode", default="persistent", choices=["persistent", "per_step"])
+    ap.add_argument("--wpl", type=int, default=0, help="walkers per lane (0 = library default)")
+    ap.add_argument("--blocks-per-cu", type=int, default=0)
+    ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--nq", type=int, default=0, help="override the number of queries (throughput-vs-batch sweeps)")
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-probe", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle CPU time")
+    ap.add_argument("--profile-pass", action="store_true",
+                    help="short run for counter collection: a 1 GiB copy (calibration) then the walk only")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this engine runs on one GPU; queries shard across GPUs with no exchange "
+              "(see DESIGN.md), but only the 1-GPU figure is measured. Use --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_2107_11983_amd as trw
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    props = torch.cuda.get_device_properties(0)
+    log(f"device {props.name} cus={props.multi_processor_count}")
+
+    wl = synth.WORKLOADS[args.workload]
+    sampler = args.sampler or wl.samplers[0]
+    t0 = time.time()
+    g = synth.make_graph(wl)
+    log(f"graph {wl.name}: n={g.n} m={g.m} dmax={int(g.degrees().max())} ({time.time() - t0:.1f}s)")
+    src_np = synth.make_sources(wl, g, nq=args.nq or None)
+    nq = len(src_np)
+    G = trw.Graph(g.row_ptr, g.col, g.weight, g.label, symmetric=wl.symmetric, device="cuda:0")
+    nbad = G.validate()
+    assert nbad == 0, f"graph failed validation ({nbad})"
+    d_src = torch.from_numpy(src_np).to(dev)
+
+    # Preprocessing: per-vertex tables, timed separately from the walk.
+    tables, pre_ms = {}, {}
+    need = {sampler} if (args.no_variants or args.profile_pass) else set(wl.samplers)
+    for s in sorted(need):
+        if s in ("alias", "its") and wl.algo in ("ppr", "deepwalk", "mixed"):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            tables[s] = G.table(s)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            pre_ms[s] = e0.elapsed_time(e1)
+            log(f"table {s}: {pre_ms[s]:.2f} ms")
+
+    kw = {}
+    if wl.algo == "ppr":
+        kw["stop_q32"] = trw.stop_threshold(wl.stop_prob)
+    if wl.algo == "node2vec":
+        kw["n2v_thr_q16"] = trw.n2v_thresholds(*wl.n2v_pq)
+    if wl.algo == "metapath":
+        kw["schema"] = [int(x) for x in synth.make_schema(wl)]
+
+    def params(s):
+        return trw.make_params(wl.algo, s, wl.max_len, wl.walk_seed, **kw)
+
+    def tuning_for():
+        t = {}
+        if args.wpl:
+            t["walkers_per_lane"] = args.wpl
+        if args.blocks_per_cu:
+            t["blocks_per_cu"] = args.blocks_per_cu
+        if args.chunk:
+            t["queue_chunk"] = args.chunk
+        return trw.make_tuning(**t) if t else None
+
+    def run(s, mode, warmup, steps, tuning=None):
+        p = params(s)
+        bufs = trw.WalkBuffers(G, p, nq, mode)
+        table = tables.get(s)
+        for _ in range(warmup):
+            trw.walk(G, table, p, d_src, mode=mode, tuning=tuning, bufs=bufs)
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        t_start = time.perf_counter()
+        for a, b in ev:
+            a.record(stream)
+            trw.walk(G, table, p, d_src, mode=mode, tuning=tuning, bufs=bufs)
+            b.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t_start
+        per_launch_ms = [a.elapsed_time(b) for a, b in ev]
+        lengths = bufs.lengths.to(torch.int64)
+        moves = int(lengths.sum().item())
+        st = bufs.status
+        dead = int((st == trw.TRW_ST_DEAD_END).sum().item())
+        badsrc = int((st == trw.TRW_ST_BAD_SOURCE).sum().item())
+        del bufs
+        return dict(moves=moves, dead_ends=dead, bad_sources=badsrc, wall_s=wall, per_launch_ms=per_launch_ms)
+
+    mode = trw.MODES[args.mode]
+    if args.profile_pass:
+        # calibration: a plain device copy of exactly 1 GiB, then the walk
+        a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        r = run(sampler, mode, 1, max(args.steps, 1), tuning_for())
+        log(f"profile pass: {r['moves']} moves per launch, {np.mean(r['per_launch_ms']):.3f} ms per launch")
+        return
+
+    log(f"main: {wl.algo}/{sampler} {args.mode} warmup={args.warmup} steps={args.steps}")
+    main_r = run(sampler, mode, args.warmup, args.steps, tuning_for())
+    ms_step = 1000.0 * main_r["wall_s"] / args.steps
+    avg_launch_ms = float(np.mean(main_r["per_launch_ms"]))
+    moves = main_r["moves"]
+    value = moves * args.steps / main_r["wall_s"]
+    log(f"main: {moves} moves per batch, {ms_step:.3f} ms per batch, {value:.4g} steps/s")
+
+    # Roofline of the walk kernel: algorithmic bytes / kernel time.
+    entry = ENTRY_BYTES.get(sampler)
+    roofline = None
+    valid_q = nq - main_r["bad_sources"]
+    if entry is not None and wl.algo in ("ppr", "deepwalk"):
+        row_reads = moves + main_r["dead_ends"]
+        alg_bytes = 8 * row_reads + entry * moves + 4 * moves + PER_QUERY_BYTES * valid_q + 5 * main_r["bad_sources"]
+        achieved = alg_bytes / (avg_launch_ms * 1e-3) / 1e9
+        traffic, src = read_traffic(f"{wl.name}_{sampler}_{args.mode}")
+        roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBPS, 5), "traffic": traffic,
+                    "kernel": f"k_walk_persistent<{wl.algo},{sampler}>" if args.mode == "persistent"
+                    else f"k_bsp_step<{wl.algo},{sampler}>",
+                    "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": round(avg_launch_ms, 4),
+                    "random_reads_per_launch": row_reads + moves}
+        if traffic is not None:
+            roofline["traffic_frac_of_peak"] = round(traffic / (avg_launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)
+
+    # Other samplers / schedules of the same workload (same queries, same graph).
+    variants = {}
+    if not args.no_variants:
+        for s in wl.samplers:
+            for mname in ("persistent", "per_step"):
+                if s == sampler and mname == args.mode:
+                    continue
+                if wl.algo in ("ppr", "deepwalk") and s in ("alias", "its") and s not in tables:
+                    continue
+                r = run(s, trw.MODES[mname], 1, 3)
+                v = r["moves"] * 3 / r["wall_s"]
+                variants[f"{s}/{mname}"] = {"steps_per_s": round(v, 1), "ms_per_batch": round(1000 * r["wall_s"] / 3, 3),
+                                            "moves": r["moves"]}
+                log(f"variant {s}/{mname}: {v:.4g} steps/s")
+
+    # Random-gather ceiling of the device (dependent and independent chains).
+    gather = None
+    if not args.no_probe:
+        gather = probe_gather(trw, torch, dev, props.multi_processor_count)
+        if roofline is not None and gather:
+            acc_s = roofline["random_reads_per_launch"] / (avg_launch_ms * 1e-3)
+            roofline["random_reads_per_s"] = round(acc_s, 1)
+            roofline["frac_of_dependent_gather_ceiling"] = round(acc_s / gather["dependent_best_reads_per_s"], 4)
+            roofline["frac_of_independent_gather_ceiling"] = round(acc_s / gather["independent_best_reads_per_s"], 4)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(g, wl, sampler, src_np, kw, args.cpu_seconds)
+
+    out = {
+        "metric": "walk steps/sec + % HBM roofline (1 GPU); p50/p99 query latency served",
+        "value": round(value, 1),
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": f"{wl.name}: {wl.algo} sampler={sampler} mode={args.mode}; R-MAT 2^{wl.scale} "
+                               f"{'symmetric' if wl.symmetric else 'directed'} avg deg {wl.avg_degree}"
+                               f"{', uint32 weights 1..255' if wl.weights else ''}"
+                               f"{', ' + str(wl.labels) + ' labels' if wl.labels else ''}; {nq} queries, max {wl.max_len} moves"
+                               f"{', stop prob ' + str(wl.stop_prob) if wl.algo == 'ppr' else ''}",
+                   "n": g.n, "m": g.m, "nq": nq, "moves_per_batch": moves, "parallelism": "1 GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "preprocess_ms": {k: round(v, 3) for k, v in pre_ms.items()},
+        "variants": variants,
+        "gather_ceiling": gather,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def probe_gather(trw, torch, dev, cus):
+    """Best random-read rate over occupancy / chains, 4 GiB buffer of 16-byte elements."""
+    import ctypes
+    from paper_2107_11983_amd import _abi
+    nbytes = 4 << 30
+    buf = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    sink = torch.zeros(4096, dtype=torch.uint8, device=dev)
+    s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    assert _abi.trw_probe_fill(ctypes.c_void_p(buf.data_ptr()), nbytes, 7, s) == 0
+    res = {"buffer_bytes": nbytes, "elem_bytes": 16, "runs": []}
+    best = {0: 0.0, 1: 0.0}
+    steps = 64
+    for dep in (1, 0):
+        for chains in (1, 2, 4):
+            for bpc in (4, 8):
+                grid = cus * bpc
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                args = (ctypes.c_void_p(buf.data_ptr()), nbytes, 16, chains, steps, dep, grid, 256,
+                        ctypes.c_void_p(sink.data_ptr()), s)
+                assert _abi.trw_probe_gather(*args) == 0
+                a.record()
+                assert _abi.trw_probe_gather(*args) == 0
+                b.record()
+                torch.cuda.synchronize()
+                ms = a.elapsed_time(b)
+                reads = grid * 256 * chains * steps
+                rate = reads / (ms * 1e-3)
+                best[dep] = max(best[dep], rate)
+                res["runs"].append({"dependent": dep, "chains": chains, "blocks_per_cu": bpc,
+                                    "reads_per_s": round(rate, 1), "ms": round(ms, 3)})
+    res["dependent_best_reads_per_s"] = round(best[1], 1)
+    res["independent_best_reads_per_s"] = round(best[0], 1)
+    res["dependent_best_GBps_at_64B"] = round(best[1] * 64 / 1e9, 1)
+    res["independent_best_GBps_at_64B"] = round(best[0] * 64 / 1e9, 1)
+    log(f"gather ceiling: dependent {best[1]:.4g} reads/s, independent {best[0]:.4g} reads/s")
+    del buf
+    return res
+
+
+def cpu_baseline(g, wl, sampler, src_np, kw, target_s):
+    """The oracle (single-threaded C) on a bounded prefix of the same queries."""
+    try:
+        import oracle
+        oracle._load()
+    except Exception as e:  # the oracle is test infrastructure; the GPU number does not depend on it
+        log(f"cpu baseline skipped: {e}")
+        return None
+    algo = oracle.ALGOS[wl.algo]
+    smp = oracle.SAMPLERS[sampler]
+    tab = {}
+    t0 = time.time()
+    if algo in (oracle.DEEPWALK, oracle.PPR) and smp == oracle.ALIAS:
+        t, a = oracle.alias_build(g.row_ptr, g.weight)
+        tab = dict(thr=t, alias=a)
+    elif algo in (oracle.DEEPWALK, oracle.PPR) and smp == oracle.ITS:
+        tab = dict(prefix=oracle.its_build(g.row_ptr, g.weight))
+    if algo == oracle.METAPATH:
+        tab = dict(label=g.label)
+    log(f"cpu baseline: oracle tables {time.time() - t0:.1f}s")
+    p = oracle.WalkParams(algo, smp, wl.max_len, wl.walk_seed, stop_q32=kw.get("stop_q32", 0),
+                          n2v_thr_q16=tuple(kw.get("n2v_thr_q16", (65536,) * 3)), schema=tuple(kw.get("schema", ())))
+    # calibrate on a small prefix, then size the timed sample to ~target_s
+    n0 = min(len(src_np), 20000)
+    t0 = time.perf_counter()
+    r = oracle.walk(g.row_ptr, g.col, p, src_np[:n0], **tab)
+    dt = time.perf_counter() - t0
+    per_q = max(dt / n0, 1e-9)
+    nsamp = int(min(len(src_np), max(n0, target_s / per_q)))
+    nsamp = min(nsamp, (2 << 30) // (4 * (wl.max_len + 1)))      # host paths buffer <= 2 GiB
+    t0 = time.perf_counter()
+    r = oracle.walk(g.row_ptr, g.col, p, src_np[:nsamp], **tab)
+    dt = time.perf_counter() - t0
+    moves = int(r.lengths.sum())
+    log(f"cpu baseline: {nsamp} queries, {moves} moves in {dt:.2f}s")
+    return {"value": round(moves / dt, 1), "unit": "steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {nsamp} of {len(src_np)} queries of the same batch ({moves} moves, {dt:.1f} s, "
+                      f"single thread, tables prebuilt)"}
+
+
+if __name__ == "__main__":
+    main()

@@ -114,20 +114,24 @@ typedef enum {
 
 typedef struct trw_table_s *trw_table;
 
-/* Bytes of device memory the table for `sampler` needs: ALIAS 16*m, ITS 8*m. */
+/* Bytes of device memory the table for `sampler` needs: ALIAS 32*m, ITS 8*m. */
 trw_status trw_table_bytes(trw_graph g, uint32_t sampler, size_t *bytes);
 
 /*
  * Build the per-vertex table for `sampler` from the graph's weights into
- * d_buf (caller-owned, >= trw_table_bytes, 16-byte aligned), asynchronously.
+ * d_buf (caller-owned, >= trw_table_bytes, 32-byte aligned), asynchronously.
+ * The graph must be valid (trw_graph_validate); rows are read as given.
  * Layout (per directed edge slot e of row v, in CSR order):
- *   ALIAS: uint32x4 {thr, dst_first, dst_second, 0}.  Column j of row v is the
- *          bucket (first = col[off+j], second = col[off+alias_j]); it picks
- *          the first iff r1 < thr.  thr = floor(s_j * 2^32 / W) from Vose's
- *          worklist method in exact integers (W = sum of the row's weights,
- *          s_j = w_j * d after the transfers), 0xFFFFFFFF for a full bucket.
- *          A row whose weights sum to 0 holds {0xFFFFFFFF, -1, -1, 0}: a
- *          walk that reaches it ends as a dead end.
+ *   ALIAS: 8 x uint32 {thr, dst_first, dst_second, 0,
+ *                      row_off(dst_first), deg(dst_first), row_off(dst_second), deg(dst_second)}.
+ *          Column j of row v is the bucket (first = col[off+j], second =
+ *          col[off+alias_j]); it picks the first iff r1 < thr.  thr =
+ *          floor(s_j * 2^32 / W) from Vose's worklist method in exact
+ *          integers (W = sum of the row's weights, s_j = w_j * d after the
+ *          transfers), 0xFFFFFFFF for a full bucket.  The row ranges of both
+ *          candidates ride along so that a move needs one 32-byte read.
+ *          A row whose weights sum to 0 holds {0xFFFFFFFF, -1, -1, 0, 0, 0,
+ *          0, 0}: a walk that reaches it ends as a dead end.
  *   ITS:   uint64 prefix[e] = sum of w over row v up to and including e.
  * Errors: TRW_E_INVALID if the graph has no weights, bytes is too small or the
  * buffer is misaligned; TRW_E_UNSUPPORTED for NAIVE / OREJ (no table).

@@ -45,6 +45,24 @@ def _as_device(a, dtype_np, device) -> torch.Tensor:
     return torch.from_numpy(a).to(device)
 
 
+def stop_threshold(prob: float) -> int:
+    """PPR stop coin threshold: a walk stops after a move iff r2 < floor(prob * 2^32)."""
+    if not 0.0 <= prob <= 1.0:
+        raise ValueError("stop probability must be in [0, 1]")
+    return min(int(prob * 4294967296.0), 0xFFFFFFFF)
+
+
+def n2v_thresholds(p: float, q: float) -> tuple:
+    """Node2Vec dart thresholds in Q16: round(2^16 * p(e) / p*), clamped to [1, 65536].
+
+    p(e) = 1/p for the previous vertex, 1 for its neighbours, 1/q otherwise
+    (the Node2Vec transition equation); p* = max(1, 1/p, 1/q) is the O-REJ bound.
+    """
+    w = (1.0 / p, 1.0, 1.0 / q)
+    top = max(w)
+    return tuple(min(65536, max(1, int(round(65536.0 * x / top)))) for x in w)
+
+
 def make_params(algo, sampler, max_len: int, seed: int, stop_q32: int = 0,
                 n2v_thr_q16: Sequence[int] = (65536, 65536, 65536), schema: Sequence[int] = ()) -> trw_walk_params:
     """Fill trw_walk_params.  algo / sampler may be names ('ppr', 'alias') or enum values."""
@@ -155,7 +173,8 @@ class WalkBuffers:
 
     def __init__(self, graph: Graph, p: trw_walk_params, nq: int, mode=TRW_M_PERSISTENT, stride: int = 0):
         self.nq = nq
-        self.stride = stride or (p.max_len + 1)
+        # rows start on 32-byte boundaries: a short walk's path then lands in one memory sector
+        self.stride = stride or ((p.max_len + 1 + 7) // 8 * 8)
         dev = graph.device
         self.paths = torch.empty((nq, self.stride), dtype=torch.int32, device=dev)
         self.lengths = torch.empty(nq, dtype=torch.int32, device=dev)

@@ -88,9 +88,13 @@ trw_status check_params(trw_graph g, const trw_walk_params *p) {
     return TRW_OK;
 }
 
+// Defaults measured on MI355X: static walks (one random read per move) run
+// best at low occupancy (2 workgroups of 256 per CU: fewer requests queued in
+// the memory system), walks that scan rows or search adjacency at full
+// occupancy.
 Tuning resolve_tuning(const trw_walk_params *p, uint32_t mode, const trw_tuning *t) {
-    Tuning tu{1, 256, mode == TRW_M_PERSISTENT ? 8u : 8u, 256, 256};
-    (void)p;
+    const bool table_walk = (p->algo == TRW_A_DEEPWALK || p->algo == TRW_A_PPR) && p->sampler == TRW_S_ALIAS;
+    Tuning tu{1, 256, (mode == TRW_M_PERSISTENT && table_walk) ? 2u : 8u, 256, 256};
     if (t) {
         if (t->walkers_per_lane == 1 || t->walkers_per_lane == 2 || t->walkers_per_lane == 4)
             tu.walkers_per_lane = t->walkers_per_lane;
@@ -155,7 +159,7 @@ trw_status trw_graph_destroy(trw_graph g) {
 trw_status trw_table_bytes(trw_graph g, uint32_t sampler, size_t *bytes) {
     if (!g || !bytes) return fail(TRW_E_INVALID, "graph / bytes is NULL");
     switch (sampler) {
-        case TRW_S_ALIAS: *bytes = sizeof(uint4) * (size_t)g->dev.m; return TRW_OK;
+        case TRW_S_ALIAS: *bytes = kAliasEntryBytes * (size_t)g->dev.m; return TRW_OK;
         case TRW_S_ITS: *bytes = sizeof(uint64_t) * (size_t)g->dev.m; return TRW_OK;
         case TRW_S_NAIVE:
         case TRW_S_OREJ: *bytes = 0; return fail(TRW_E_UNSUPPORTED, "sampler has no table");
@@ -171,8 +175,8 @@ trw_status trw_table_build(trw_graph g, uint32_t sampler, void *d_buf, size_t by
     if (st != TRW_OK) return st;
     if (!g->dev.weight) return fail(TRW_E_INVALID, "table needs edge weights");
     if (bytes < need) return fail(TRW_E_INVALID, "table buffer too small");
-    if (g->dev.m > 0 && (!d_buf || (reinterpret_cast<uintptr_t>(d_buf) & 15)))
-        return fail(TRW_E_INVALID, "table buffer NULL or not 16-byte aligned");
+    if (g->dev.m > 0 && (!d_buf || (reinterpret_cast<uintptr_t>(d_buf) & 31)))
+        return fail(TRW_E_INVALID, "table buffer NULL or not 32-byte aligned");
     auto s = static_cast<hipStream_t>(stream);
     hipError_t e = hipSuccess;
     if (g->dev.m > 0) {

@@ -46,6 +46,19 @@ __device__ __forceinline__ int64_t next_below(const uint32_t *__restrict__ w, in
     return -1;
 }
 
+// Row range {row_off, degree} of vertex v.
+__device__ __forceinline__ uint2 row_of(const GraphDev &g, int32_t v) {
+    const int32_t lo = g.row_ptr[v];
+    return make_uint2((uint32_t)lo, (uint32_t)(g.row_ptr[v + 1] - lo));
+}
+
+__device__ __forceinline__ void put_entry(uint4 *__restrict__ row, int64_t j, const GraphDev &g, uint32_t thr,
+                                          int32_t first, int32_t second) {
+    const uint2 a = row_of(g, first), b = row_of(g, second);
+    row[2 * j] = make_uint4(thr, (uint32_t)first, (uint32_t)second, 0u);
+    row[2 * j + 1] = make_uint4(a.x, a.y, b.x, b.y);
+}
+
 __global__ void k_alias_build(GraphDev g, uint4 *__restrict__ out) {
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= g.n) return;
@@ -54,12 +67,15 @@ __global__ void k_alias_build(GraphDev g, uint4 *__restrict__ out) {
     if (d <= 0) return;
     const uint32_t *__restrict__ w = g.weight + off;
     const int32_t *__restrict__ col = g.col + off;
-    uint4 *__restrict__ row = out + off;
+    uint4 *__restrict__ row = out + 2 * off;
 
     uint64_t W = 0;
     for (int64_t i = 0; i < d; ++i) W += w[i];
     if (W == 0) {
-        for (int64_t i = 0; i < d; ++i) row[i] = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0u);
+        for (int64_t i = 0; i < d; ++i) {
+            row[2 * i] = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0u);
+            row[2 * i + 1] = make_uint4(0u, 0u, 0u, 0u);
+        }
         return;
     }
     const uint64_t ud = (uint64_t)d;
@@ -78,7 +94,7 @@ __global__ void k_alias_build(GraphDev g, uint4 *__restrict__ out) {
             l = small_next; l_mass = (uint64_t)w[l] * ud;
             small_next = next_below(w, l, ud, W, true);
         }
-        row[l] = make_uint4(frac32(l_mass, W), (uint32_t)col[l], (uint32_t)col[g_top], 0u);
+        put_entry(row, l, g, frac32(l_mass, W), col[l], col[g_top]);
         g_mass -= W - l_mass;
         if (g_mass < W) {
             demoted = g_top; demoted_mass = g_mass;
@@ -88,7 +104,7 @@ __global__ void k_alias_build(GraphDev g, uint4 *__restrict__ out) {
     }
     // Columns left on the large stack are full buckets.
     while (g_top >= 0) {
-        row[g_top] = make_uint4(0xFFFFFFFFu, (uint32_t)col[g_top], (uint32_t)col[g_top], 0u);
+        put_entry(row, g_top, g, 0xFFFFFFFFu, col[g_top], col[g_top]);
         g_top = next_below(w, g_top, ud, W, false);
     }
 }

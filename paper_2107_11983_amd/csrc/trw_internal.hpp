@@ -20,13 +20,17 @@ struct GraphDev {
     int32_t m;
 };
 
-// ALIAS entries are {thr, dst_first, dst_second, 0}: the destination ids are
-// stored beside the coin threshold so that a move needs one random 16-byte
-// read of the table and none of the adjacency array.
+// An ALIAS entry is 32 bytes, two uint4 per edge slot:
+//   [0] {thr, dst_first, dst_second, 0}
+//   [1] {row_off(dst_first), deg(dst_first), row_off(dst_second), deg(dst_second)}
+// The destination ids and their row ranges sit beside the coin threshold, so
+// a move reads one 32-byte entry (one cache line) and neither the adjacency
+// array nor the row offsets.
 struct TableDev {
-    const uint4 *alias;       // ALIAS: one entry per edge slot
+    const uint4 *alias;       // ALIAS: 2 x uint4 per edge slot
     const uint64_t *prefix;   // ITS: inclusive prefix per row
 };
+constexpr size_t kAliasEntryBytes = 32;
 
 // Parameters of one batch of queries as the kernels see them.
 struct WalkDev {

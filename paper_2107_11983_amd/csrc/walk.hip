@@ -16,6 +16,12 @@
 //  * per step (bulk-synchronous): one launch per move over a compacted list
 //    of live walker records; finished walkers drop out of the next list.
 //
+// Memory traffic per move is what bounds the step (random reads fetch whole
+// cache lines).  ALIAS entries carry the row range of both candidate
+// destinations, so an ALIAS move is a single random 32-byte read; path
+// entries are buffered in registers and written 16 bytes at a time on 16-byte
+// boundaries of the path row.
+//
 // Sampling is integer throughout: uniform index = high half of r * d; ALIAS
 // coin r1 < thr; ITS draw = high half of (r1:r0) * W and a binary search over
 // the uint64 prefix; O-REJ darts compare r1 >> 16 with Q16 thresholds;
@@ -29,9 +35,9 @@ namespace {
 constexpr uint32_t kIdle = 0xFFFFFFFFu;
 
 // ---------------------------------------------------------------------------
-// Move: sample one edge of `cur` for move k.  Returns the next vertex, or -1
-// when the current vertex has no eligible edge (dead end).  `r` is the block
-// of dart 0; Node2Vec draws further darts itself.
+// Move for the samplers that read the adjacency array (NAIVE, ITS, O-REJ,
+// MetaPath).  Returns the next vertex, or -1 when the current vertex has no
+// eligible edge (dead end).  `r` is the block of dart 0.
 // ---------------------------------------------------------------------------
 template <uint32_t ALGO, uint32_t SMP>
 __device__ __forceinline__ int32_t sample_next(const GraphDev &g, const TableDev &t, const WalkDev &a,
@@ -78,9 +84,6 @@ __device__ __forceinline__ int32_t sample_next(const GraphDev &g, const TableDev
         }
     } else if (SMP == SMP_NAIVE) {
         return g.col[off + scale32(r.r0, d)];
-    } else if (SMP == SMP_ALIAS) {
-        const uint4 e = t.alias[off + scale32(r.r0, d)];
-        return (int32_t)(r.r1 < e.x ? e.y : e.z);          // -1 marks a row of zero weight
     } else {  // ITS
         const uint64_t *__restrict__ p = t.prefix + off;
         const uint64_t W = p[d - 1];
@@ -95,6 +98,45 @@ __device__ __forceinline__ int32_t sample_next(const GraphDev &g, const TableDev
     }
 }
 
+// ALIAS move from the 32-byte entry of column j: next vertex and its row range.
+__device__ __forceinline__ int32_t alias_pick(const uint4 &e0, const uint4 &e1, uint32_t r1, int32_t &off,
+                                              int32_t &deg) {
+    const bool first = r1 < e0.x;
+    off = (int32_t)(first ? e1.x : e1.z);
+    deg = (int32_t)(first ? e1.y : e1.w);
+    return (int32_t)(first ? e0.y : e0.z);                  // -1 marks a row of zero weight
+}
+
+// ---------------------------------------------------------------------------
+// Path writer: up to 4 pending entries per walker, flushed as one 16-byte
+// store when they end on a 16-byte boundary, else entry by entry at the end.
+// ---------------------------------------------------------------------------
+struct PathBuf {
+    int32_t *p;      // address of the first pending entry
+    uint32_t n;      // pending entries
+    int32_t b0, b1, b2, b3;
+
+    __device__ __forceinline__ void start(int32_t *row) { p = row; n = 0; }
+
+    __device__ __forceinline__ void flush() {
+        if (n == 4) {
+            *reinterpret_cast<int4 *>(p) = make_int4(b0, b1, b2, b3);
+        } else {
+            if (n > 0) p[0] = b0;
+            if (n > 1) p[1] = b1;
+            if (n > 2) p[2] = b2;
+        }
+        p += n;
+        n = 0;
+    }
+
+    __device__ __forceinline__ void push(int32_t v) {
+        if (n == 0) b0 = v; else if (n == 1) b1 = v; else if (n == 2) b2 = v; else b3 = v;
+        ++n;
+        if (((reinterpret_cast<uintptr_t>(p + n)) & 15u) == 0) flush();
+    }
+};
+
 // ---------------------------------------------------------------------------
 // Persistent schedule
 // ---------------------------------------------------------------------------
@@ -103,20 +145,27 @@ struct Walker {
     int32_t cur;
     int32_t prev;
     uint32_t k;
+    int32_t off;     // row of cur (valid when !need_row)
+    int32_t deg;
     int32_t poff;    // row of prev (Node2Vec)
-    int32_t pd;
+    int32_t pdeg;
+    bool need_row;
+    PathBuf path;
 };
 
 template <uint32_t ALGO, uint32_t SMP, int WPL>
 __global__ void __launch_bounds__(256)
 k_walk_persistent(GraphDev g, TableDev t, WalkDev a, unsigned long long *__restrict__ queue_head,
                   uint32_t chunk) {
+    constexpr bool kAlias = (SMP == SMP_ALIAS) && (ALGO == ALG_DEEPWALK || ALGO == ALG_PPR);
     Walker w[WPL];
 #pragma unroll
     for (int i = 0; i < WPL; ++i) w[i].qi = kIdle;
     uint32_t pool_next = 0, pool_end = 0;   // this wave's claimed id range (wave-uniform)
     bool exhausted = false;
     const uint32_t lane = lane_id();
+    const unsigned long long n_waves = ((unsigned long long)gridDim.x * blockDim.x + 63) / 64;
+    unsigned long long seen = 0;            // queue head after this wave's last claim (wave-uniform)
 
     for (;;) {
         // Admission / refill: idle slots take the next ids of the wave's chunk.
@@ -125,12 +174,19 @@ k_walk_persistent(GraphDev g, TableDev t, WalkDev a, unsigned long long *__restr
             while (idle != 0 && !exhausted) {
                 uint32_t avail = pool_end - pool_next;
                 if (avail == 0) {
+                    // Guided claim: a share of what was left at this wave's previous claim,
+                    // between 64 ids and `chunk`, so that early claims are large (few
+                    // atomics) and late ones small (waves finish together).
+                    const unsigned long long left = seen < a.nq ? a.nq - seen : 0;
+                    uint32_t take = (uint32_t)min(left / (2ull * n_waves), (unsigned long long)chunk);
+                    take = max(take, min(64u, chunk));
                     unsigned long long base = 0;
-                    if (lane == 0) base = atomicAdd(queue_head, (unsigned long long)chunk);
+                    if (lane == 0) base = atomicAdd(queue_head, (unsigned long long)take);
                     base = __shfl(base, 0);
+                    seen = base + take;
                     if (base >= a.nq) { exhausted = true; break; }
                     pool_next = (uint32_t)base;
-                    pool_end = (uint32_t)min(base + chunk, (unsigned long long)a.nq);
+                    pool_end = (uint32_t)min(base + take, (unsigned long long)a.nq);
                     avail = pool_end - pool_next;
                 }
                 const uint32_t rk = rank_below(idle);
@@ -141,9 +197,10 @@ k_walk_persistent(GraphDev g, TableDev t, WalkDev a, unsigned long long *__restr
                         a.lengths[qi] = 0;
                         a.status[qi] = ST_BAD_SOURCE;
                     } else {
-                        a.paths[(uint64_t)qi * a.stride] = s;
                         w[i].qi = qi; w[i].cur = s; w[i].prev = -1; w[i].k = 0;
-                        w[i].poff = 0; w[i].pd = 0;
+                        w[i].poff = 0; w[i].pdeg = 0; w[i].need_row = true;
+                        w[i].path.start(a.paths + (uint64_t)qi * a.stride);
+                        w[i].path.push(s);
                     }
                 }
                 pool_next += min((uint32_t)__popcll(idle), avail);
@@ -155,33 +212,70 @@ k_walk_persistent(GraphDev g, TableDev t, WalkDev a, unsigned long long *__restr
         for (int i = 0; i < WPL; ++i) any |= (w[i].qi != kIdle);
         if (__ballot(any) == 0) break;   // every slot idle after refill: the queue is drained
 
-        // Gather: row ranges of all walkers of this lane (independent loads).
-        int32_t off[WPL], end[WPL];
+        // Gather: row ranges the walkers do not carry yet (independent loads).
 #pragma unroll
         for (int i = 0; i < WPL; ++i) {
-            if (w[i].qi != kIdle) { off[i] = g.row_ptr[w[i].cur]; end[i] = g.row_ptr[w[i].cur + 1]; }
+            if (w[i].qi != kIdle && w[i].need_row) {
+                const int32_t lo = g.row_ptr[w[i].cur];
+                w[i].deg = g.row_ptr[w[i].cur + 1] - lo;
+                w[i].off = lo;
+                w[i].need_row = false;
+            }
         }
-        // Move + Update.
+        Rand4 r[WPL];
+#pragma unroll
+        for (int i = 0; i < WPL; ++i) r[i] = philox(w[i].k, 0, a.qid_base + w[i].qi, a.seed);
+
+        // Move.
+        int32_t nxt[WPL];
+        if (kAlias) {
+            uint4 e0[WPL], e1[WPL];
+#pragma unroll
+            for (int i = 0; i < WPL; ++i) {
+                if (w[i].qi != kIdle && w[i].deg != 0) {
+                    const uint32_t e = (uint32_t)w[i].off + scale32(r[i].r0, (uint32_t)w[i].deg);
+                    e0[i] = t.alias[2 * (uint64_t)e];
+                    e1[i] = t.alias[2 * (uint64_t)e + 1];
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < WPL; ++i) {
+                nxt[i] = -1;
+                if (w[i].qi != kIdle && w[i].deg != 0) {
+                    w[i].poff = w[i].off; w[i].pdeg = w[i].deg;
+                    nxt[i] = alias_pick(e0[i], e1[i], r[i].r1, w[i].off, w[i].deg);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < WPL; ++i) {
+                nxt[i] = -1;
+                if (w[i].qi != kIdle && w[i].deg != 0) {
+                    nxt[i] = sample_next<ALGO, SMP>(g, t, a, a.qid_base + w[i].qi, w[i].k, w[i].off,
+                                                    (uint32_t)w[i].deg, r[i], w[i].prev, w[i].poff, w[i].pdeg);
+                    w[i].poff = w[i].off; w[i].pdeg = w[i].deg;
+                    w[i].need_row = true;
+                }
+            }
+        }
+
+        // Update.
 #pragma unroll
         for (int i = 0; i < WPL; ++i) {
             if (w[i].qi == kIdle) continue;
-            const uint64_t qid = a.qid_base + w[i].qi;
-            const Rand4 r = philox(w[i].k, 0, qid, a.seed);
-            const uint32_t d = (uint32_t)(end[i] - off[i]);
             uint8_t st = 0;
-            int32_t nxt = -1;
-            if (d != 0) nxt = sample_next<ALGO, SMP>(g, t, a, qid, w[i].k, off[i], d, r, w[i].prev, w[i].poff, w[i].pd);
-            if (nxt < 0) {
+            if (nxt[i] < 0) {
                 st = ST_DEAD_END;
             } else {
-                a.paths[(uint64_t)w[i].qi * a.stride + w[i].k + 1] = nxt;
-                w[i].prev = w[i].cur; w[i].poff = off[i]; w[i].pd = (int32_t)d;
-                w[i].cur = nxt;
+                w[i].path.push(nxt[i]);
+                w[i].prev = w[i].cur;
+                w[i].cur = nxt[i];
                 w[i].k += 1;
-                if (ALGO == ALG_PPR && r.r2 < a.stop_q32) st = ST_STOPPED;
+                if (ALGO == ALG_PPR && r[i].r2 < a.stop_q32) st = ST_STOPPED;
                 else if (w[i].k == a.max_len) st = ST_LENGTH;
             }
             if (st) {
+                w[i].path.flush();
                 a.lengths[w[i].qi] = w[i].k;
                 a.status[w[i].qi] = st;
                 w[i].qi = kIdle;
@@ -193,11 +287,13 @@ k_walk_persistent(GraphDev g, TableDev t, WalkDev a, unsigned long long *__restr
 // ---------------------------------------------------------------------------
 // Per-step (bulk-synchronous) schedule
 // ---------------------------------------------------------------------------
+// A live walker between launches: query index, current vertex and two words
+// that are the row range of cur for ALIAS walks, and (prev, unused) otherwise.
 struct alignas(16) Rec {
     uint32_t qi;
     int32_t cur;
-    int32_t prev;
-    uint32_t pad;
+    int32_t a;
+    int32_t b;
 };
 
 __global__ void k_fill_u32(uint32_t *p, uint32_t n, uint32_t v) {
@@ -205,6 +301,7 @@ __global__ void k_fill_u32(uint32_t *p, uint32_t n, uint32_t v) {
     if (i < n) p[i] = v;
 }
 
+template <bool ALIAS_ROWS>
 __global__ void __launch_bounds__(256) k_bsp_init(GraphDev g, WalkDev a, Rec *__restrict__ out,
                                                   uint32_t *__restrict__ count) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -223,7 +320,14 @@ __global__ void __launch_bounds__(256) k_bsp_init(GraphDev g, WalkDev a, Rec *__
             }
         }
         const uint32_t slot = wave_append(count, keep);
-        if (keep) out[slot] = Rec{(uint32_t)i, s, -1, 0u};
+        if (keep) {
+            if (ALIAS_ROWS) {
+                const int32_t lo = g.row_ptr[s];
+                out[slot] = Rec{(uint32_t)i, s, lo, g.row_ptr[s + 1] - lo};
+            } else {
+                out[slot] = Rec{(uint32_t)i, s, -1, 0};
+            }
+        }
     }
 }
 
@@ -231,6 +335,7 @@ template <uint32_t ALGO, uint32_t SMP>
 __global__ void __launch_bounds__(256) k_bsp_step(GraphDev g, TableDev t, WalkDev a, uint32_t k,
                                                   const Rec *__restrict__ in, const uint32_t *__restrict__ count_in,
                                                   Rec *__restrict__ out, uint32_t *__restrict__ count_out) {
+    constexpr bool kAlias = (SMP == SMP_ALIAS) && (ALGO == ALG_DEEPWALK || ALGO == ALG_PPR);
     const uint32_t n_in = *count_in;
     const uint32_t stride = gridDim.x * blockDim.x;
     for (uint32_t base = 0; base < n_in; base += stride) {
@@ -239,17 +344,24 @@ __global__ void __launch_bounds__(256) k_bsp_step(GraphDev g, TableDev t, WalkDe
         Rec nr{};
         if (idx < n_in) {
             const Rec rc = in[idx];
-            const int32_t off = g.row_ptr[rc.cur];
-            const uint32_t d = (uint32_t)(g.row_ptr[rc.cur + 1] - off);
             const uint64_t qid = a.qid_base + rc.qi;
             const Rand4 r = philox(k, 0, qid, a.seed);
-            int32_t poff = 0, pd = 0;
-            if (ALGO == ALG_NODE2VEC && rc.prev >= 0) {
-                poff = g.row_ptr[rc.prev];
-                pd = g.row_ptr[rc.prev + 1] - poff;
+            int32_t nxt = -1, noff = 0, ndeg = 0;
+            if (kAlias) {
+                if (rc.b != 0) {
+                    const uint32_t e = (uint32_t)rc.a + scale32(r.r0, (uint32_t)rc.b);
+                    nxt = alias_pick(t.alias[2 * (uint64_t)e], t.alias[2 * (uint64_t)e + 1], r.r1, noff, ndeg);
+                }
+            } else {
+                const int32_t off = g.row_ptr[rc.cur];
+                const uint32_t d = (uint32_t)(g.row_ptr[rc.cur + 1] - off);
+                int32_t poff = 0, pd = 0;
+                if (ALGO == ALG_NODE2VEC && rc.a >= 0) {
+                    poff = g.row_ptr[rc.a];
+                    pd = g.row_ptr[rc.a + 1] - poff;
+                }
+                if (d != 0) nxt = sample_next<ALGO, SMP>(g, t, a, qid, k, off, d, r, rc.a, poff, pd);
             }
-            int32_t nxt = -1;
-            if (d != 0) nxt = sample_next<ALGO, SMP>(g, t, a, qid, k, off, d, r, rc.prev, poff, pd);
             uint8_t st = 0;
             uint32_t len = k;
             if (nxt < 0) {
@@ -265,7 +377,7 @@ __global__ void __launch_bounds__(256) k_bsp_step(GraphDev g, TableDev t, WalkDe
                 a.status[rc.qi] = st;
             } else {
                 keep = true;
-                nr = Rec{rc.qi, nxt, rc.cur, 0u};
+                nr = kAlias ? Rec{rc.qi, nxt, noff, ndeg} : Rec{rc.qi, nxt, rc.cur, 0};
             }
         }
         const uint32_t slot = wave_append(count_out, keep);
@@ -306,6 +418,7 @@ hipError_t run_persistent(const GraphDev &g, const TableDev &t, const WalkDev &w
 template <uint32_t ALGO, uint32_t SMP>
 hipError_t run_bsp(const GraphDev &g, const TableDev &t, const WalkDev &w, const Tuning &tu,
                    const DeviceInfo &di, void *ws, hipStream_t s) {
+    constexpr bool kAlias = (SMP == SMP_ALIAS) && (ALGO == ALG_DEEPWALK || ALGO == ALG_PPR);
     char *base = reinterpret_cast<char *>(ws);
     uint32_t *counts = reinterpret_cast<uint32_t *>(base);
     const size_t counts_bytes = round_up(sizeof(uint32_t) * (w.max_len + 2));
@@ -318,7 +431,7 @@ hipError_t run_bsp(const GraphDev &g, const TableDev &t, const WalkDev &w, const
     const uint64_t need = ((uint64_t)w.nq + threads - 1) / threads;
     if (blocks > need) blocks = need;
     if (blocks == 0) blocks = 1;
-    hipLaunchKernelGGL(k_bsp_init, dim3(blocks), dim3(threads), 0, s, g, w, lists[0], counts);
+    hipLaunchKernelGGL(k_bsp_init<kAlias>, dim3(blocks), dim3(threads), 0, s, g, w, lists[0], counts);
     for (uint32_t k = 0; k < w.max_len; ++k) {
         hipLaunchKernelGGL((k_bsp_step<ALGO, SMP>), dim3(blocks), dim3(threads), 0, s, g, t, w, k,
                            lists[k & 1], counts + k, lists[(k + 1) & 1], counts + k + 1);

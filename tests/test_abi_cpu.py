@@ -11,9 +11,12 @@ HEADER = os.path.join(ROOT, "include", "trw.h")
 
 
 def _declared_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(trw_[a-z0-9_]+)\s*\(", text)))
+    import glob
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(trw_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
 
 
 @pytest.fixture(scope="module")
@@ -108,12 +111,12 @@ def test_walk_argument_checks(abi):
     assert walk(_params(abi, "deepwalk", "naive"), ws_bytes=0) == abi.TRW_E_INVALID
     assert walk(_params(abi, "deepwalk", "naive"), nq=0) == abi.TRW_OK           # nothing to do
     sz = ctypes.c_size_t()
-    assert abi.trw_table_bytes(g, abi.TRW_S_ALIAS, ctypes.byref(sz)) == abi.TRW_OK and sz.value == 16 * 1000
+    assert abi.trw_table_bytes(g, abi.TRW_S_ALIAS, ctypes.byref(sz)) == abi.TRW_OK and sz.value == 32 * 1000
     assert abi.trw_table_bytes(g, abi.TRW_S_ITS, ctypes.byref(sz)) == abi.TRW_OK and sz.value == 8 * 1000
     assert abi.trw_table_bytes(g, abi.TRW_S_NAIVE, ctypes.byref(sz)) == abi.TRW_E_UNSUPPORTED
     t = ctypes.c_void_p()
     assert abi.trw_table_build(g, abi.TRW_S_ALIAS, fake, 10, None, ctypes.byref(t)) == abi.TRW_E_INVALID
-    assert abi.trw_table_build(g, abi.TRW_S_ALIAS, ctypes.c_void_p(0x1004), 16000, None,
+    assert abi.trw_table_build(g, abi.TRW_S_ALIAS, ctypes.c_void_p(0x1010), 32000, None,
                                ctypes.byref(t)) == abi.TRW_E_INVALID
     gn = _fake_graph(abi)
     assert abi.trw_table_build(gn, abi.TRW_S_ITS, fake, 8000, None, ctypes.byref(t)) == abi.TRW_E_INVALID

@@ -124,18 +124,27 @@ def rmat_dir():
 
 # --------------------------------------------------------------------------- tables
 def _alias_expected(g, thr, alias):
-    rp, col = g.row_ptr.astype(np.int64), g.col
+    """The documented 32-byte ALIAS entry for every edge slot, from the oracle's (thr, alias)."""
+    rp, col = g.row_ptr.astype(np.int64), g.col.astype(np.int64)
     m = g.m
-    exp = np.zeros((m, 4), dtype=np.uint32)
-    exp[:, 0] = thr
+    exp = np.zeros((m, 8), dtype=np.int64)
     src_row = np.repeat(np.arange(g.n), np.diff(rp))
-    first = col.astype(np.int64)
-    second = np.where(alias >= 0, col[np.clip(rp[src_row] + alias, 0, max(m - 1, 0))], -1)
-    exp[:, 1] = first.astype(np.int32).view(np.uint32)
-    exp[:, 2] = second.astype(np.int32).view(np.uint32)
     dead = alias < 0
-    exp[dead, 1] = 0xFFFFFFFF
-    return exp
+    second = np.where(dead, -1, col[np.clip(rp[src_row] + alias, 0, max(m - 1, 0))])
+    first = np.where(dead, -1, col)
+    deg = np.diff(rp)
+    exp[:, 0] = thr
+    exp[:, 1] = first
+    exp[:, 2] = second
+    exp[:, 4] = np.where(dead, 0, rp[np.clip(first, 0, None)])
+    exp[:, 5] = np.where(dead, 0, deg[np.clip(first, 0, None)])
+    exp[:, 6] = np.where(dead, 0, rp[np.clip(second, 0, None)])
+    exp[:, 7] = np.where(dead, 0, deg[np.clip(second, 0, None)])
+    return (exp & 0xFFFFFFFF).astype(np.uint32)
+
+
+def _alias_got(t, m):
+    return t.buf[:32 * m].view(torch.int32).cpu().numpy().view(np.uint32).reshape(-1, 8)
 
 
 def _weighted_rows_graph(seed, wmax, zero_rows=True):
@@ -163,10 +172,10 @@ def test_alias_table_matches_oracle(wmax):
     log(f"  alias table m={g.m}")
     t = case.dev_table("alias")
     torch.cuda.synchronize()
-    got = t.buf[:16 * g.m].view(torch.int32).cpu().numpy().view(np.uint32).reshape(-1, 4)
+    got = _alias_got(t, g.m)
     thr, alias = oracle.alias_build(g.row_ptr, g.weight)
     exp = _alias_expected(g, thr, alias)
-    bad = np.nonzero((got[:, :3] != exp[:, :3]).any(axis=1))[0]
+    bad = np.nonzero((got != exp).any(axis=1))[0]
     assert bad.size == 0, f"alias entries differ at edge slots {bad[:10]}"
 
 
@@ -174,9 +183,9 @@ def test_alias_table_rmat(rmat_dir):
     g = rmat_dir.g
     t = rmat_dir.dev_table("alias")
     torch.cuda.synchronize()
-    got = t.buf[:16 * g.m].view(torch.int32).cpu().numpy().view(np.uint32).reshape(-1, 4)
+    got = _alias_got(t, g.m)
     thr, alias = oracle.alias_build(g.row_ptr, g.weight)
-    assert np.array_equal(got[:, :3], _alias_expected(g, thr, alias)[:, :3])
+    assert np.array_equal(got, _alias_expected(g, thr, alias))
 
 
 def test_its_table_matches_oracle(rmat_dir):
