@@ -105,7 +105,7 @@ def main():
     log(f"device {props.name} cus={props.multi_processor_count}")
 
     wl = synth.WORKLOADS[args.workload]
-    sampler = args.sampler or wl.samplers[0]
+    sampler = args.sampler or ("its+index" if wl.algo == "metapath" else wl.samplers[0])
     t0 = time.time()
     g = synth.make_graph(wl)
     log(f"graph {wl.name}: n={g.n} m={g.m} dmax={int(g.degrees().max())} ({time.time() - t0:.1f}s)")
@@ -119,11 +119,13 @@ def main():
     # Preprocessing: per-vertex tables, timed separately from the walk.
     tables, pre_ms = {}, {}
     need = {sampler} if (args.no_variants or args.profile_pass) else set(wl.samplers)
+    if wl.algo == "metapath":
+        need = {"its+index"} if (args.no_variants or args.profile_pass) and sampler == "its+index" else {"its+index", "its"}
     for s in sorted(need):
-        if s in ("alias", "its") and wl.algo in ("ppr", "deepwalk", "mixed"):
+        if (s in ("alias", "its") and wl.algo in ("ppr", "deepwalk", "mixed")) or s == "its+index":
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(stream)
-            tables[s] = G.table(s)
+            tables[s] = G.label_index(wl.labels) if s == "its+index" else G.table(s)
             e1.record(stream)
             torch.cuda.synchronize()
             pre_ms[s] = e0.elapsed_time(e1)
@@ -138,7 +140,7 @@ def main():
         kw["schema"] = [int(x) for x in synth.make_schema(wl)]
 
     def params(s):
-        return trw.make_params(wl.algo, s, wl.max_len, wl.walk_seed, **kw)
+        return trw.make_params(wl.algo, s.split("+")[0], wl.max_len, wl.walk_seed, **kw)
 
     def tuning_for():
         t = {}
@@ -215,7 +217,7 @@ def main():
     # Other samplers / schedules of the same workload (same queries, same graph).
     variants = {}
     if not args.no_variants:
-        for s in wl.samplers:
+        for s in (("its+index", "its") if wl.algo == "metapath" else wl.samplers):
             for mname in ("persistent", "per_step"):
                 if s == sampler and mname == args.mode:
                     continue

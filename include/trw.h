@@ -141,6 +141,25 @@ trw_status trw_table_build(trw_graph g, uint32_t sampler, void *d_buf, size_t by
 
 trw_status trw_table_destroy(trw_table t);
 
+/*
+ * MetaPath label index (optional).  A MetaPath move only considers the edges
+ * of the current vertex whose label equals the schema's label for that move
+ * (Random Walk based Algorithms, MetaPath); without an index every move
+ * counts the matching labels of the row (the dynamic Gather).  The index
+ * stores every row stably sorted by label and, per vertex, where each label's
+ * run starts, so a move reads two offsets and one destination.  It selects
+ * the same edge as the scan (the j-th match in CSR order is the j-th entry of
+ * the label's run), so results are identical with and without it.
+ *   n_labels  L in 1..64; edges with labels >= L are left out of the index
+ *             and schemas used with it must have every label < L
+ * Layout in d_buf (256-byte aligned): int32 loff[n][L+1] (absolute offsets
+ * into lcol; loff[v][L] = end of v's indexed edges), padded to 256 bytes,
+ * then int32 lcol[m].
+ */
+trw_status trw_label_index_bytes(trw_graph g, uint32_t n_labels, size_t *bytes);
+trw_status trw_label_index_build(trw_graph g, uint32_t n_labels, void *d_buf, size_t bytes,
+                                 trw_stream_t stream, trw_table *out);
+
 /* ------------------------------------------------------------------------ */
 /* Walks                                                                     */
 /* ------------------------------------------------------------------------ */
@@ -182,7 +201,8 @@ typedef struct {
     uint32_t block_threads;     /* 64..1024, multiple of 64 */
     uint32_t blocks_per_cu;     /* persistent grid = CUs * blocks_per_cu */
     uint32_t queue_chunk;       /* persistent: queries claimed per wave per queue access */
-    uint32_t coop_degree;       /* MetaPath: rows at least this long are scanned by the whole wave */
+    uint32_t coop_degree;       /* MetaPath without an index: rows at least this long are
+                                   scanned by the whole wave, shorter ones by their lane */
     uint32_t reserved[3];
 } trw_tuning;
 
@@ -195,7 +215,8 @@ trw_status trw_default_tuning(trw_graph g, const trw_walk_params *p, uint32_t mo
 
 /*
  * Run nq queries, query i starting at d_sources[i] with id qid_base + i.
- *   table       ALIAS/ITS table built for p->sampler (NULL for NAIVE, OREJ, METAPATH)
+ *   table       ALIAS/ITS table built for p->sampler; NULL for NAIVE and OREJ;
+ *               for METAPATH NULL (scan rows) or a label index
  *   d_paths     int32, row i at d_paths + i*path_stride, path_stride >= max_len+1:
  *               paths[i][0] = source, paths[i][1..lengths[i]] = the moves;
  *               entries beyond lengths[i] are left unspecified

@@ -113,6 +113,10 @@ class Graph:
     def table(self, sampler, stream=None) -> "Table":
         return Table(self, sampler, stream)
 
+    def label_index(self, n_labels: int, stream=None) -> "Table":
+        """MetaPath label index (rows sorted by label + per-vertex label offsets)."""
+        return Table(self, "label_index", stream, n_labels=n_labels)
+
     def close(self):
         for t in self._tables:
             t.close()
@@ -131,15 +135,23 @@ class Graph:
 class Table:
     """Per-vertex ALIAS or ITS table (built on the device, asynchronously)."""
 
-    def __init__(self, graph: Graph, sampler, stream=None):
+    def __init__(self, graph: Graph, sampler, stream=None, n_labels: int = 0):
         self.graph = graph
-        self.sampler = SAMPLERS[sampler] if isinstance(sampler, str) else int(sampler)
         nbytes = ctypes.c_size_t(0)
-        check(_abi.trw_table_bytes(graph.handle, self.sampler, ctypes.byref(nbytes)))
-        self.buf = torch.empty(max(int(nbytes.value), 16), dtype=torch.uint8, device=graph.device)
         h = ctypes.c_void_p()
-        check(_abi.trw_table_build(graph.handle, self.sampler, _dptr(self.buf), int(nbytes.value),
-                                   _stream_ptr(stream), ctypes.byref(h)))
+        if sampler == "label_index":
+            self.sampler = None
+            self.n_labels = n_labels
+            check(_abi.trw_label_index_bytes(graph.handle, n_labels, ctypes.byref(nbytes)))
+            self.buf = torch.empty(max(int(nbytes.value), 256), dtype=torch.uint8, device=graph.device)
+            check(_abi.trw_label_index_build(graph.handle, n_labels, _dptr(self.buf), int(nbytes.value),
+                                             _stream_ptr(stream), ctypes.byref(h)))
+        else:
+            self.sampler = SAMPLERS[sampler] if isinstance(sampler, str) else int(sampler)
+            check(_abi.trw_table_bytes(graph.handle, self.sampler, ctypes.byref(nbytes)))
+            self.buf = torch.empty(max(int(nbytes.value), 16), dtype=torch.uint8, device=graph.device)
+            check(_abi.trw_table_build(graph.handle, self.sampler, _dptr(self.buf), int(nbytes.value),
+                                       _stream_ptr(stream), ctypes.byref(h)))
         self.handle = h
         graph._tables.append(self)
 

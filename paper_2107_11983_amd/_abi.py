@@ -71,6 +71,8 @@ _SIGS = {
                        ctypes.POINTER(trw_tuning), _P, _sz, _P]),
     "trw_autotune": (_st, [_P, _P, ctypes.POINTER(trw_walk_params), _P, _u64, _P, _u64, _P, _P, _u32, _u32,
                            _P, _sz, _P, ctypes.POINTER(trw_tuning), ctypes.POINTER(ctypes.c_float)]),
+    "trw_label_index_bytes": (_st, [_P, _u32, ctypes.POINTER(_sz)]),
+    "trw_label_index_build": (_st, [_P, _u32, _P, _sz, _P, _PP]),
     # measurement probe (include/trw_probe.h)
     "trw_probe_fill": (ctypes.c_int, [_P, _u64, _u32, _P]),
     "trw_probe_gather": (ctypes.c_int, [_P, _u64, _u32, _u32, _u32, ctypes.c_int, _u32, _u32, _P, _P]),
@@ -107,5 +109,7 @@ trw_walk_workspace_bytes = lib.trw_walk_workspace_bytes
 trw_default_tuning = lib.trw_default_tuning
 trw_walk = lib.trw_walk
 trw_autotune = lib.trw_autotune
+trw_label_index_bytes = lib.trw_label_index_bytes
+trw_label_index_build = lib.trw_label_index_build
 trw_probe_fill = lib.trw_probe_fill
 trw_probe_gather = lib.trw_probe_gather

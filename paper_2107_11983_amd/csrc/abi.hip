@@ -18,9 +18,17 @@ struct trw_graph_s {
 
 struct trw_table_s {
     trw_graph graph;
-    uint32_t sampler;
+    uint32_t sampler;   // TRW_S_ALIAS / TRW_S_ITS, or kLabelIndexKind
     void *buf;
+    uint32_t nlab;      // label index: number of labels L
 };
+
+static constexpr uint32_t kLabelIndexKind = 0x100;
+
+static size_t label_index_loff_bytes(const trw::GraphDev &g, uint32_t nlab) {
+    const size_t b = sizeof(int32_t) * (size_t)g.n * (nlab + 1);
+    return (b + 255) / 256 * 256;
+}
 
 namespace trw {
 
@@ -184,7 +192,34 @@ trw_status trw_table_build(trw_graph g, uint32_t sampler, void *d_buf, size_t by
                                    : launch_its_build(g->dev, static_cast<uint64_t *>(d_buf), s);
     }
     if (e != hipSuccess) return device_fail(e, "table build launch");
-    auto *t = new (std::nothrow) trw_table_s{g, sampler, d_buf};
+    auto *t = new (std::nothrow) trw_table_s{g, sampler, d_buf, 0};
+    if (!t) return fail(TRW_E_INVALID, "out of host memory");
+    *out = t;
+    return TRW_OK;
+}
+
+trw_status trw_label_index_bytes(trw_graph g, uint32_t n_labels, size_t *bytes) {
+    if (!g || !bytes) return fail(TRW_E_INVALID, "graph / bytes is NULL");
+    if (n_labels == 0 || n_labels > kMaxIndexLabels) return fail(TRW_E_INVALID, "n_labels must be in 1..64");
+    *bytes = label_index_loff_bytes(g->dev, n_labels) + sizeof(int32_t) * (size_t)g->dev.m;
+    return TRW_OK;
+}
+
+trw_status trw_label_index_build(trw_graph g, uint32_t n_labels, void *d_buf, size_t bytes, trw_stream_t stream,
+                                 trw_table *out) {
+    if (!g || !out) return fail(TRW_E_INVALID, "graph / out is NULL");
+    size_t need = 0;
+    trw_status st = trw_label_index_bytes(g, n_labels, &need);
+    if (st != TRW_OK) return st;
+    if (!g->dev.label) return fail(TRW_E_INVALID, "label index needs edge labels");
+    if (bytes < need) return fail(TRW_E_INVALID, "label index buffer too small");
+    if (!d_buf || (reinterpret_cast<uintptr_t>(d_buf) & 255))
+        return fail(TRW_E_INVALID, "label index buffer NULL or not 256-byte aligned");
+    auto *loff = static_cast<int32_t *>(d_buf);
+    auto *lcol = reinterpret_cast<int32_t *>(static_cast<char *>(d_buf) + label_index_loff_bytes(g->dev, n_labels));
+    hipError_t e = launch_label_index_build(g->dev, n_labels, loff, lcol, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return device_fail(e, "label index build launch");
+    auto *t = new (std::nothrow) trw_table_s{g, kLabelIndexKind, d_buf, n_labels};
     if (!t) return fail(TRW_E_INVALID, "out of host memory");
     *out = t;
     return TRW_OK;
@@ -235,6 +270,13 @@ trw_status trw_walk(trw_graph g, trw_table table, const trw_walk_params *p, cons
         if (table->graph != g) return fail(TRW_E_INVALID, "table was built for another graph");
         if (table->sampler != p->sampler) return fail(TRW_E_INVALID, "table was built for another sampler");
     }
+    const bool label_index = p->algo == TRW_A_METAPATH && table != nullptr;
+    if (label_index) {
+        if (table->graph != g) return fail(TRW_E_INVALID, "label index was built for another graph");
+        if (table->sampler != kLabelIndexKind) return fail(TRW_E_INVALID, "MetaPath takes a label index or no table");
+        for (uint32_t i = 0; i < p->schema_len; ++i)
+            if (p->schema[i] >= table->nlab) return fail(TRW_E_INVALID, "schema label >= label index n_labels");
+    }
     if (path_stride < (uint64_t)p->max_len + 1) return fail(TRW_E_INVALID, "path_stride < max_len + 1");
     if (nq == 0) return TRW_OK;
     if (!d_sources || !d_paths || !d_lengths || !d_status)
@@ -260,10 +302,16 @@ trw_status trw_walk(trw_graph g, trw_table table, const trw_walk_params *p, cons
     w.stride = path_stride;
     w.lengths = d_lengths;
     w.status = d_status;
-    TableDev t{nullptr, nullptr};
+    TableDev t{nullptr, nullptr, nullptr, nullptr, 0};
     if (needs_table) {
         if (p->sampler == TRW_S_ALIAS) t.alias = static_cast<const uint4 *>(table->buf);
         else t.prefix = static_cast<const uint64_t *>(table->buf);
+    }
+    if (label_index) {
+        t.loff = static_cast<const int32_t *>(table->buf);
+        t.lcol = reinterpret_cast<const int32_t *>(static_cast<const char *>(table->buf) +
+                                                   label_index_loff_bytes(g->dev, table->nlab));
+        t.nlab = table->nlab;
     }
     const Tuning tu = resolve_tuning(p, mode, tuning);
     hipError_t e = launch_walk(g->dev, t, p->algo, p->sampler, w, mode, tu, device_info(), d_ws, ws_bytes,

@@ -145,6 +145,24 @@ __global__ void k_validate(GraphDev g, unsigned long long *__restrict__ bad) {
     if (nbad) atomicAdd(bad, nbad);
 }
 
+// MetaPath label index: stable counting sort of each row by label, one pass
+// per label value (O(L * d) per row, L <= kMaxIndexLabels).
+__global__ void k_label_index_build(GraphDev g, uint32_t nlab, int32_t *__restrict__ loff,
+                                    int32_t *__restrict__ lcol) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= g.n) return;
+    const int64_t off = g.row_ptr[v], end = g.row_ptr[v + 1];
+    int32_t *__restrict__ rec = loff + v * (int64_t)(nlab + 1);
+    int64_t pos = off;
+    for (uint32_t x = 0; x < nlab; ++x) {
+        rec[x] = (int32_t)pos;
+        for (int64_t e = off; e < end; ++e)
+            if (g.label[e] == x) lcol[pos++] = g.col[e];
+    }
+    rec[nlab] = (int32_t)pos;
+    for (; pos < end; ++pos) lcol[pos] = -1;      // edges whose label is >= L
+}
+
 constexpr int kBuildThreads = 256;
 
 }  // namespace
@@ -158,6 +176,12 @@ hipError_t launch_alias_build(const GraphDev &g, uint4 *out, hipStream_t s) {
 hipError_t launch_its_build(const GraphDev &g, uint64_t *out, hipStream_t s) {
     const int blocks = (g.n + kBuildThreads - 1) / kBuildThreads;
     hipLaunchKernelGGL(k_its_build, dim3(blocks), dim3(kBuildThreads), 0, s, g, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_label_index_build(const GraphDev &g, uint32_t nlab, int32_t *loff, int32_t *lcol, hipStream_t s) {
+    const int blocks = (g.n + kBuildThreads - 1) / kBuildThreads;
+    hipLaunchKernelGGL(k_label_index_build, dim3(blocks), dim3(kBuildThreads), 0, s, g, nlab, loff, lcol);
     return hipGetLastError();
 }
 

@@ -26,11 +26,20 @@ struct GraphDev {
 // The destination ids and their row ranges sit beside the coin threshold, so
 // a move reads one 32-byte entry (one cache line) and neither the adjacency
 // array nor the row offsets.
+// MetaPath label index: each row stably sorted by label (so within one label
+// the CSR order is kept) in lcol, and per vertex v the offsets
+// loff[v * (L + 1) + x] = start in lcol of v's edges with label x, for
+// x = 0..L (loff[v][L] = end of the row).  Edges with labels >= L are left
+// out: a schema label is always < L, so they never match.
 struct TableDev {
     const uint4 *alias;       // ALIAS: 2 x uint4 per edge slot
     const uint64_t *prefix;   // ITS: inclusive prefix per row
+    const int32_t *loff;      // label index: (L + 1) offsets per vertex
+    const int32_t *lcol;      // label index: label-sorted destinations
+    uint32_t nlab;            // label index: L
 };
 constexpr size_t kAliasEntryBytes = 32;
+constexpr uint32_t kMaxIndexLabels = 64;
 
 // Parameters of one batch of queries as the kernels see them.
 struct WalkDev {
@@ -52,7 +61,7 @@ struct WalkDev {
 
 enum : uint8_t { ST_LENGTH = 1, ST_STOPPED = 2, ST_DEAD_END = 3, ST_BAD_SOURCE = 4 };
 enum : uint32_t { ALG_DEEPWALK = 0, ALG_PPR = 1, ALG_NODE2VEC = 2, ALG_METAPATH = 3 };
-enum : uint32_t { SMP_NAIVE = 0, SMP_ALIAS = 1, SMP_ITS = 2, SMP_OREJ = 3 };
+enum : uint32_t { SMP_NAIVE = 0, SMP_ALIAS = 1, SMP_ITS = 2, SMP_OREJ = 3, SMP_LABEL_INDEX = 4 };
 
 // Darts per O-REJ move at most (then the last dart is taken); with every
 // threshold >= 1 the cap is reached with probability below e^-256.
@@ -63,7 +72,7 @@ struct Tuning {
     uint32_t block_threads;
     uint32_t blocks_per_cu;
     uint32_t queue_chunk;
-    uint32_t coop_degree;
+    uint32_t coop_degree;     // MetaPath scan: rows at least this long are scanned by the whole wave
 };
 
 struct DeviceInfo {
@@ -75,6 +84,7 @@ struct DeviceInfo {
 hipError_t launch_alias_build(const GraphDev &g, uint4 *out, hipStream_t s);
 hipError_t launch_its_build(const GraphDev &g, uint64_t *out, hipStream_t s);
 hipError_t launch_validate(const GraphDev &g, unsigned long long *d_bad, hipStream_t s);
+hipError_t launch_label_index_build(const GraphDev &g, uint32_t nlab, int32_t *loff, int32_t *lcol, hipStream_t s);
 
 size_t walk_workspace_bytes(uint32_t mode, uint64_t nq, uint32_t max_len);
 hipError_t launch_walk(const GraphDev &g, const TableDev &t, uint32_t algo, uint32_t sampler,

@@ -67,21 +67,6 @@ __device__ __forceinline__ int32_t sample_next(const GraphDev &g, const TableDev
             }
             if ((rr.r1 >> 16) < th) return x;
         }
-    } else if (ALGO == ALG_METAPATH) {
-        const uint32_t si = k % a.schema_len;
-        const uint64_t word = si < 8 ? a.schema_lo : a.schema_hi;
-        const uint8_t want = (uint8_t)(word >> ((si & 7u) * 8u));
-        const uint8_t *__restrict__ lab = g.label + off;
-        uint32_t m = 0;
-        for (uint32_t i = 0; i < d; ++i) m += (lab[i] == want);
-        if (m == 0) return -1;
-        uint32_t j = scale32(r.r0, m);
-        for (uint32_t i = 0;; ++i) {
-            if (lab[i] == want) {
-                if (j == 0) return g.col[off + i];
-                --j;
-            }
-        }
     } else if (SMP == SMP_NAIVE) {
         return g.col[off + scale32(r.r0, d)];
     } else {  // ITS
@@ -96,6 +81,152 @@ __device__ __forceinline__ int32_t sample_next(const GraphDev &g, const TableDev
         }
         return g.col[off + lo];
     }
+}
+
+// ---------------------------------------------------------------------------
+// MetaPath Gather (the dynamic walk: only edges whose label is the schema's
+// label for this move are eligible).  Degree-bucketed: a lane compares the
+// labels of a short row four at a time (SWAR on 32-bit words); rows of at
+// least `coop` labels are scanned by the whole wave, 256 bytes per coalesced
+// load, one such row after another.  With a label index (rows sorted by
+// label, per-vertex label offsets) the Gather is two reads instead.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t match_bits(uint32_t word, uint32_t want4) {
+    const uint32_t x = word ^ want4;
+    return ~(((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x | 0x7F7F7F7Fu);   // 0x80 where a byte equals want
+}
+
+// 0x80 flags of the bytes of the word at wa that lie in [lo, hi).
+__device__ __forceinline__ uint32_t byte_window(uintptr_t wa, uintptr_t lo, uintptr_t hi) {
+    uint32_t m = 0x80808080u;
+    if (lo > wa) m &= 0xFFFFFFFFu << (8u * (uint32_t)(lo - wa));
+    if (hi < wa + 4) m &= (1u << (8u * (uint32_t)(hi - wa))) - 1u;
+    return m;
+}
+
+// Aligned word at wa; bytes past the end of the label array read as 0 (masked anyway).
+__device__ __forceinline__ uint32_t load_word(uintptr_t wa, uintptr_t arr_end) {
+    if (wa + 4 <= arr_end) return *reinterpret_cast<const uint32_t *>(wa);
+    uint32_t w = 0;
+    for (uint32_t b = 0; b < 4 && wa + b < arr_end; ++b) w |= (uint32_t)(*reinterpret_cast<const uint8_t *>(wa + b)) << (8u * b);
+    return w;
+}
+
+__device__ __forceinline__ uint32_t lane_count(uintptr_t l, uint32_t d, uint32_t want4, uintptr_t arr_end) {
+    const uintptr_t h = l + d;
+    uint32_t m = 0;
+    for (uintptr_t wa = l & ~(uintptr_t)3; wa < h; wa += 4)
+        m += __popc(match_bits(load_word(wa, arr_end), want4) & byte_window(wa, l, h));
+    return m;
+}
+
+// Offset from l of the j-th (0-based) matching label; j < number of matches.
+__device__ __forceinline__ uint32_t lane_find(uintptr_t l, uint32_t d, uint32_t want4, uint32_t j, uintptr_t arr_end) {
+    const uintptr_t h = l + d;
+    for (uintptr_t wa = l & ~(uintptr_t)3;; wa += 4) {
+        uint32_t bits = match_bits(load_word(wa, arr_end), want4) & byte_window(wa, l, h);
+        const uint32_t c = __popc(bits);
+        if (j < c) {
+            for (; j > 0; --j) bits &= bits - 1u;
+            return (uint32_t)(wa + (__builtin_ctz(bits) >> 3) - l);
+        }
+        j -= c;
+    }
+}
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v) {
+    const uint32_t lane = lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t t = __shfl_up(v, o);
+        if (lane >= (uint32_t)o) v += t;
+    }
+    return v;
+}
+
+// Whole wave, uniform arguments: offset from l of the j-th matching label with
+// j = scale32(r0, m), m the number of matches; -1 when m == 0.
+__device__ int64_t wave_pick(uintptr_t l, uint32_t d, uint32_t want4, uint32_t r0, uintptr_t arr_end) {
+    const uint32_t lane = lane_id();
+    const uintptr_t h = l + d;
+    const uintptr_t w0 = l & ~(uintptr_t)3;
+    const uint32_t nwords = (uint32_t)((h - w0 + 3) >> 2);
+    uint32_t cnt = 0;
+    for (uint32_t i = lane; i < nwords; i += 64) {
+        const uintptr_t wa = w0 + 4 * (uintptr_t)i;
+        cnt += __popc(match_bits(load_word(wa, arr_end), want4) & byte_window(wa, l, h));
+    }
+    const uint32_t m = wave_sum(cnt);
+    if (m == 0) return -1;
+    uint32_t j = scale32(r0, m);
+    for (uint32_t base = 0; base < nwords; base += 64) {
+        const uint32_t i = base + lane;
+        const uintptr_t wa = w0 + 4 * (uintptr_t)i;
+        uint32_t bits = 0;
+        if (i < nwords) bits = match_bits(load_word(wa, arr_end), want4) & byte_window(wa, l, h);
+        const uint32_t c = __popc(bits);
+        const uint32_t incl = wave_inclusive_scan(c);
+        const uint32_t total = __shfl(incl, 63);
+        if (j < total) {
+            const bool mine = c != 0 && incl - c <= j && j < incl;
+            int64_t pos = -1;
+            if (mine) {
+                for (uint32_t jj = j - (incl - c); jj > 0; --jj) bits &= bits - 1u;
+                pos = (int64_t)(wa + (__builtin_ctz(bits) >> 3)) - (int64_t)l;
+            }
+            const uint64_t who = __ballot(mine);
+            return __shfl(pos, (int)__builtin_ctzll(who));
+        }
+        j -= total;
+    }
+    return -1;
+}
+
+// One MetaPath move for every lane of the wave (call with uniform control
+// flow; `active` says whether this lane has a walker).  Returns the next
+// vertex or -1 (no eligible edge).
+template <uint32_t SMP>
+__device__ __forceinline__ int32_t metapath_move(const GraphDev &g, const TableDev &t, const WalkDev &a, bool active,
+                                                 uint32_t k, int32_t cur, int32_t off, uint32_t d, uint32_t r0,
+                                                 uint32_t coop) {
+    const uint32_t si = k % a.schema_len;
+    const uint64_t word = si < 8 ? a.schema_lo : a.schema_hi;
+    const uint32_t want = (uint32_t)(uint8_t)(word >> ((si & 7u) * 8u));
+    if (SMP == SMP_LABEL_INDEX) {
+        if (!active) return -1;
+        const int32_t *rec = t.loff + (uint64_t)cur * (t.nlab + 1);
+        const int32_t lo = rec[want], hi = rec[want + 1];
+        if (hi == lo) return -1;
+        return t.lcol[lo + scale32(r0, (uint32_t)(hi - lo))];
+    }
+    const uint32_t want4 = want * 0x01010101u;
+    const uintptr_t base = reinterpret_cast<uintptr_t>(g.label);
+    const uintptr_t arr_end = base + (uintptr_t)g.m;
+    int32_t nxt = -1;
+    const bool big = active && d >= coop;
+    if (active && !big && d > 0) {
+        const uintptr_t l = base + (uintptr_t)off;
+        const uint32_t m = lane_count(l, d, want4, arr_end);
+        if (m) nxt = g.col[off + lane_find(l, d, want4, scale32(r0, m), arr_end)];
+    }
+    uint64_t todo = __ballot(big);
+    while (todo) {
+        const int src = (int)__builtin_ctzll(todo);
+        todo &= todo - 1;
+        const int32_t off_s = __shfl(off, src);
+        const uint32_t d_s = __shfl(d, src);
+        const uint32_t want4_s = __shfl(want4, src);
+        const uint32_t r0_s = __shfl(r0, src);
+        const int64_t pos = wave_pick(base + (uintptr_t)off_s, d_s, want4_s, r0_s, arr_end);
+        if (lane_id() == (uint32_t)src && pos >= 0) nxt = g.col[off_s + pos];
+    }
+    return nxt;
 }
 
 // ALIAS move from the 32-byte entry of column j: next vertex and its row range.
@@ -156,8 +287,9 @@ struct Walker {
 template <uint32_t ALGO, uint32_t SMP, int WPL>
 __global__ void __launch_bounds__(256)
 k_walk_persistent(GraphDev g, TableDev t, WalkDev a, unsigned long long *__restrict__ queue_head,
-                  uint32_t chunk) {
+                  uint32_t chunk, uint32_t coop) {
     constexpr bool kAlias = (SMP == SMP_ALIAS) && (ALGO == ALG_DEEPWALK || ALGO == ALG_PPR);
+    constexpr bool kNoRows = (SMP == SMP_LABEL_INDEX);   // the label index replaces the row lookup
     Walker w[WPL];
 #pragma unroll
     for (int i = 0; i < WPL; ++i) w[i].qi = kIdle;
@@ -198,7 +330,8 @@ k_walk_persistent(GraphDev g, TableDev t, WalkDev a, unsigned long long *__restr
                         a.status[qi] = ST_BAD_SOURCE;
                     } else {
                         w[i].qi = qi; w[i].cur = s; w[i].prev = -1; w[i].k = 0;
-                        w[i].poff = 0; w[i].pdeg = 0; w[i].need_row = true;
+                        w[i].poff = 0; w[i].pdeg = 0; w[i].need_row = !kNoRows;
+                        w[i].off = 0; w[i].deg = 1;
                         w[i].path.start(a.paths + (uint64_t)qi * a.stride);
                         w[i].path.push(s);
                     }
@@ -245,6 +378,14 @@ k_walk_persistent(GraphDev g, TableDev t, WalkDev a, unsigned long long *__restr
                     w[i].poff = w[i].off; w[i].pdeg = w[i].deg;
                     nxt[i] = alias_pick(e0[i], e1[i], r[i].r1, w[i].off, w[i].deg);
                 }
+            }
+        } else if (ALGO == ALG_METAPATH) {
+#pragma unroll
+            for (int i = 0; i < WPL; ++i) {
+                const bool act = w[i].qi != kIdle;
+                nxt[i] = metapath_move<SMP>(g, t, a, act, w[i].k, w[i].cur, w[i].off, (uint32_t)w[i].deg,
+                                            r[i].r0, coop);
+                if (act) w[i].need_row = !kNoRows;
             }
         } else {
 #pragma unroll
@@ -334,34 +475,47 @@ __global__ void __launch_bounds__(256) k_bsp_init(GraphDev g, WalkDev a, Rec *__
 template <uint32_t ALGO, uint32_t SMP>
 __global__ void __launch_bounds__(256) k_bsp_step(GraphDev g, TableDev t, WalkDev a, uint32_t k,
                                                   const Rec *__restrict__ in, const uint32_t *__restrict__ count_in,
-                                                  Rec *__restrict__ out, uint32_t *__restrict__ count_out) {
+                                                  Rec *__restrict__ out, uint32_t *__restrict__ count_out,
+                                                  uint32_t coop) {
     constexpr bool kAlias = (SMP == SMP_ALIAS) && (ALGO == ALG_DEEPWALK || ALGO == ALG_PPR);
     const uint32_t n_in = *count_in;
     const uint32_t stride = gridDim.x * blockDim.x;
     for (uint32_t base = 0; base < n_in; base += stride) {
         const uint32_t idx = base + blockIdx.x * blockDim.x + threadIdx.x;
-        bool keep = false;
-        Rec nr{};
-        if (idx < n_in) {
-            const Rec rc = in[idx];
-            const uint64_t qid = a.qid_base + rc.qi;
-            const Rand4 r = philox(k, 0, qid, a.seed);
-            int32_t nxt = -1, noff = 0, ndeg = 0;
+        const bool act = idx < n_in;
+        Rec rc{0u, 0, -1, 0};
+        Rand4 r{0u, 0u, 0u, 0u};
+        int32_t off = 0;
+        uint32_t d = 0;
+        if (act) {
+            rc = in[idx];
+            r = philox(k, 0, a.qid_base + rc.qi, a.seed);
+            if (!kAlias && SMP != SMP_LABEL_INDEX) {
+                off = g.row_ptr[rc.cur];
+                d = (uint32_t)(g.row_ptr[rc.cur + 1] - off);
+            }
+        }
+        int32_t nxt = -1, noff = 0, ndeg = 0;
+        if (ALGO == ALG_METAPATH) {
+            nxt = metapath_move<SMP>(g, t, a, act, k, rc.cur, off, d, r.r0, coop);
+        } else if (act) {
             if (kAlias) {
                 if (rc.b != 0) {
                     const uint32_t e = (uint32_t)rc.a + scale32(r.r0, (uint32_t)rc.b);
                     nxt = alias_pick(t.alias[2 * (uint64_t)e], t.alias[2 * (uint64_t)e + 1], r.r1, noff, ndeg);
                 }
             } else {
-                const int32_t off = g.row_ptr[rc.cur];
-                const uint32_t d = (uint32_t)(g.row_ptr[rc.cur + 1] - off);
                 int32_t poff = 0, pd = 0;
                 if (ALGO == ALG_NODE2VEC && rc.a >= 0) {
                     poff = g.row_ptr[rc.a];
                     pd = g.row_ptr[rc.a + 1] - poff;
                 }
-                if (d != 0) nxt = sample_next<ALGO, SMP>(g, t, a, qid, k, off, d, r, rc.a, poff, pd);
+                if (d != 0) nxt = sample_next<ALGO, SMP>(g, t, a, a.qid_base + rc.qi, k, off, d, r, rc.a, poff, pd);
             }
+        }
+        bool keep = false;
+        Rec nr{};
+        if (act) {
             uint8_t st = 0;
             uint32_t len = k;
             if (nxt < 0) {
@@ -404,13 +558,13 @@ hipError_t run_persistent(const GraphDev &g, const TableDev &t, const WalkDev &w
     if (blocks == 0) blocks = 1;
     switch (tu.walkers_per_lane) {
         case 2:
-            hipLaunchKernelGGL((k_walk_persistent<ALGO, SMP, 2>), dim3(blocks), dim3(threads), 0, s, g, t, w, head, tu.queue_chunk);
+            hipLaunchKernelGGL((k_walk_persistent<ALGO, SMP, 2>), dim3(blocks), dim3(threads), 0, s, g, t, w, head, tu.queue_chunk, tu.coop_degree);
             break;
         case 4:
-            hipLaunchKernelGGL((k_walk_persistent<ALGO, SMP, 4>), dim3(blocks), dim3(threads), 0, s, g, t, w, head, tu.queue_chunk);
+            hipLaunchKernelGGL((k_walk_persistent<ALGO, SMP, 4>), dim3(blocks), dim3(threads), 0, s, g, t, w, head, tu.queue_chunk, tu.coop_degree);
             break;
         default:
-            hipLaunchKernelGGL((k_walk_persistent<ALGO, SMP, 1>), dim3(blocks), dim3(threads), 0, s, g, t, w, head, tu.queue_chunk);
+            hipLaunchKernelGGL((k_walk_persistent<ALGO, SMP, 1>), dim3(blocks), dim3(threads), 0, s, g, t, w, head, tu.queue_chunk, tu.coop_degree);
     }
     return hipGetLastError();
 }
@@ -434,7 +588,7 @@ hipError_t run_bsp(const GraphDev &g, const TableDev &t, const WalkDev &w, const
     hipLaunchKernelGGL(k_bsp_init<kAlias>, dim3(blocks), dim3(threads), 0, s, g, w, lists[0], counts);
     for (uint32_t k = 0; k < w.max_len; ++k) {
         hipLaunchKernelGGL((k_bsp_step<ALGO, SMP>), dim3(blocks), dim3(threads), 0, s, g, t, w, k,
-                           lists[k & 1], counts + k, lists[(k + 1) & 1], counts + k + 1);
+                           lists[k & 1], counts + k, lists[(k + 1) & 1], counts + k + 1, tu.coop_degree);
     }
     return hipGetLastError();
 }
@@ -469,6 +623,7 @@ hipError_t launch_walk(const GraphDev &g, const TableDev &t, uint32_t algo, uint
         case ALG_NODE2VEC:
             return run<ALG_NODE2VEC, SMP_OREJ>(g, t, w, mode, tu, di, ws, s);
         default:
+            if (t.loff) return run<ALG_METAPATH, SMP_LABEL_INDEX>(g, t, w, mode, tu, di, ws, s);
             return run<ALG_METAPATH, SMP_ITS>(g, t, w, mode, tu, di, ws, s);
     }
 }

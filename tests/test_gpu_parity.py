@@ -57,6 +57,12 @@ class Case:
             self._dev_tables[sampler] = self.G.table(sampler)
         return self._dev_tables[sampler]
 
+    def label_index(self, n_labels):
+        key = ("label_index", n_labels)
+        if key not in self._dev_tables:
+            self._dev_tables[key] = self.G.label_index(n_labels)
+        return self._dev_tables[key]
+
     def orc_tables(self, sampler):
         if sampler not in self._orc_tables:
             if sampler == "alias":
@@ -70,7 +76,7 @@ class Case:
 
 
 def run_both(case, algo, sampler, max_len, seed, src, mode, tuning=None, qid_base=0, stop=0,
-             thr=(65536, 65536, 65536), schema=(), stride=0):
+             thr=(65536, 65536, 65536), schema=(), stride=0, label_index=0):
     g = case.g
     src = np.ascontiguousarray(src, dtype=np.int32)
     nq = len(src)
@@ -80,6 +86,8 @@ def run_both(case, algo, sampler, max_len, seed, src, mode, tuning=None, qid_bas
     bufs.paths.fill_(-7)
     d_src = torch.from_numpy(src).cuda()
     table = case.dev_table(sampler) if algo in ("deepwalk", "ppr") else None
+    if algo == "metapath" and label_index:
+        table = case.label_index(label_index)
     trw.walk(case.G, table, p, d_src, qid_base=qid_base, mode=mode, tuning=tuning, bufs=bufs)
     torch.cuda.synchronize()
     gp = bufs.paths.cpu().numpy()
@@ -336,3 +344,61 @@ def test_workloads_reduced_scale(name):
         for mode in (1, 0):
             gpu, ref = run_both(case, wl.algo, sampler, wl.max_len, wl.walk_seed, src, mode, **kw)
             assert_same(gpu, ref, wl.max_len)
+            if wl.algo == "metapath":
+                gpu, ref = run_both(case, wl.algo, sampler, wl.max_len, wl.walk_seed, src, mode,
+                                    label_index=wl.labels, **kw)
+                assert_same(gpu, ref, wl.max_len)
+
+
+# --------------------------------------------------------------------------- MetaPath gathers
+@pytest.mark.parametrize("mode", [1, 0])
+@pytest.mark.parametrize("n_labels", [5, 8])
+def test_metapath_label_index(rmat_sym, mode, n_labels):
+    n = rmat_sym.g.n
+    src = np.concatenate([np.arange(n), synth.sources(301, n, 8)]).astype(np.int32)
+    gpu, ref = run_both(rmat_sym, "metapath", "its", 100, 21, src, mode, schema=(3, 1, 4, 1, 0, 2, 2),
+                        label_index=n_labels)
+    assert_same(gpu, ref, 100)
+
+
+@pytest.mark.parametrize("coop", [1, 3, 64, 1 << 30])
+def test_metapath_cooperative_scan(rmat_sym, coop):
+    n = rmat_sym.g.n
+    src = np.arange(n, dtype=np.int32)
+    for mode in (1, 0):
+        tu = trw.make_tuning(coop_degree=coop)
+        gpu, ref = run_both(rmat_sym, "metapath", "its", 60, 5, src, mode, tuning=tu, schema=(0, 4, 2))
+        assert_same(gpu, ref, 60)
+
+
+def test_metapath_hub_rows_unaligned():
+    """Rows of 1..6000 labels at every byte alignment, labels to the end of the array."""
+    rng = np.random.default_rng(3)
+    edges, labs = [], []
+    n = 6500
+    for v in range(40):
+        d = int(rng.integers(1, 6000)) if v % 3 else int(rng.integers(1, 9))
+        nb = np.sort(rng.choice(np.arange(40, n), size=d, replace=False))
+        edges += [(v, int(x)) for x in nb]
+        labs += rng.integers(0, 4, size=d).tolist()
+    for x in range(40, n):            # every leaf points back to a few hubs
+        for h in (0, 1, 2):
+            edges.append((x, h))
+            labs.append(int(rng.integers(0, 4)))
+    g = synth.from_edges(n, edges, labels=labs)
+    case = Case(g)
+    src = np.tile(np.arange(40, dtype=np.int32), 64)
+    for coop in (1 << 30, 100, 1):
+        for mode in (1, 0):
+            tu = trw.make_tuning(coop_degree=coop)
+            gpu, ref = run_both(case, "metapath", "its", 30, 17, src, mode, tuning=tu, schema=(1, 0, 3, 2))
+            assert_same(gpu, ref, 30)
+    gpu, ref = run_both(case, "metapath", "its", 30, 17, src, 1, schema=(1, 0, 3, 2), label_index=4)
+    assert_same(gpu, ref, 30)
+
+
+def test_metapath_label_index_rejects_large_schema_labels(rmat_sym):
+    p = trw.make_params("metapath", "its", 10, 1, schema=(1, 6))
+    src = torch.arange(10, dtype=torch.int32, device="cuda")
+    with pytest.raises(trw.TrwError):
+        trw.walk(rmat_sym.G, rmat_sym.label_index(5), p, src)
