@@ -105,7 +105,8 @@ def main():
     log(f"device {props.name} cus={props.multi_processor_count}")
 
     wl = synth.WORKLOADS[args.workload]
-    sampler = args.sampler or ("its+index" if wl.algo == "metapath" else wl.samplers[0])
+    sampler = args.sampler or {"metapath": "its+index", "node2vec": "orej+adj",
+                               "deepwalk": "naive+adj"}.get(wl.algo, wl.samplers[0])
     t0 = time.time()
     g = synth.make_graph(wl)
     log(f"graph {wl.name}: n={g.n} m={g.m} dmax={int(g.degrees().max())} ({time.time() - t0:.1f}s)")
@@ -118,14 +119,19 @@ def main():
 
     # Preprocessing: per-vertex tables, timed separately from the walk.
     tables, pre_ms = {}, {}
-    need = {sampler} if (args.no_variants or args.profile_pass) else set(wl.samplers)
-    if wl.algo == "metapath":
-        need = {"its+index"} if (args.no_variants or args.profile_pass) and sampler == "its+index" else {"its+index", "its"}
+    variant_samplers = {"metapath": ("its+index", "its"), "node2vec": ("orej+adj", "orej"),
+                        "deepwalk": ("naive+adj", "naive")}.get(wl.algo, wl.samplers)
+    need = {sampler} if (args.no_variants or args.profile_pass) else set(variant_samplers) | {sampler}
     for s in sorted(need):
-        if (s in ("alias", "its") and wl.algo in ("ppr", "deepwalk", "mixed")) or s == "its+index":
+        if (s in ("alias", "its") and wl.algo in ("ppr", "deepwalk", "mixed")) or "+" in s:
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(stream)
-            tables[s] = G.label_index(wl.labels) if s == "its+index" else G.table(s)
+            if s == "its+index":
+                tables[s] = G.label_index(wl.labels)
+            elif s.endswith("+adj"):
+                tables[s] = G.adjacency_index()
+            else:
+                tables[s] = G.table(s)
             e1.record(stream)
             torch.cuda.synchronize()
             pre_ms[s] = e0.elapsed_time(e1)
@@ -217,11 +223,11 @@ def main():
     # Other samplers / schedules of the same workload (same queries, same graph).
     variants = {}
     if not args.no_variants:
-        for s in (("its+index", "its") if wl.algo == "metapath" else wl.samplers):
+        for s in variant_samplers:
             for mname in ("persistent", "per_step"):
                 if s == sampler and mname == args.mode:
                     continue
-                if wl.algo in ("ppr", "deepwalk") and s in ("alias", "its") and s not in tables:
+                if ((wl.algo in ("ppr", "deepwalk") and s in ("alias", "its")) or "+" in s) and s not in tables:
                     continue
                 r = run(s, trw.MODES[mname], 1, 3)
                 v = r["moves"] * 3 / r["wall_s"]

@@ -81,7 +81,9 @@ enum { TRW_G_SYMMETRIC = 1 };
  *              duplicates (Node2Vec's adjacency test is a binary search)
  *   d_weight   uint32[m] or NULL: static transition weights (ALIAS, ITS)
  *   d_label    uint8[m] or NULL: edge labels (MetaPath)
- *   flags      TRW_G_SYMMETRIC if every edge has its reverse (informational)
+ *   flags      TRW_G_SYMMETRIC if every edge has its reverse; Node2Vec then tests
+ *              adjacency in the shorter of the two rows.  Must be true when
+ *              set (trw_graph_validate checks it)
  * Borrows the arrays; does not read them (see trw_graph_validate).
  * Errors: TRW_E_INVALID for sizes out of range or NULL row_ptr/col.
  */
@@ -91,8 +93,10 @@ trw_status trw_graph_create(int64_t n, int64_t m, const int32_t *d_row_ptr, cons
 
 /*
  * O(n + m) check on the device: row_ptr[0] == 0, row_ptr non-decreasing,
- * row_ptr[n] == m, every col in [0, n), rows strictly ascending.
- * d_ws: device scratch of at least 64 bytes.  Synchronises the stream and
+ * row_ptr[n] == m, every col in [0, n), rows strictly ascending; and, for a
+ * graph created with TRW_G_SYMMETRIC, O(m log d) check that every edge has
+ * its reverse.
+ * d_ws: device scratch of at least 64 bytes, 8-byte aligned.  Synchronises the stream and
  * writes the number of violations to *n_bad.  Returns TRW_E_INVALID if
  * *n_bad > 0.
  */
@@ -140,6 +144,17 @@ trw_status trw_table_build(trw_graph g, uint32_t sampler, void *d_buf, size_t by
                            trw_stream_t stream, trw_table *out);
 
 trw_status trw_table_destroy(trw_table t);
+
+/*
+ * Adjacency index (optional, for NAIVE and OREJ walks).  Every edge slot e
+ * holds uint32x4 {col[e], row_off(col[e]), deg(col[e]), 0}, so a move that
+ * picks a slot learns the next vertex's row range with the same read, and
+ * Node2Vec darts learn the candidate's degree.  Results are identical with
+ * and without it.  16*m bytes, 16-byte aligned.
+ */
+trw_status trw_adjacency_index_bytes(trw_graph g, size_t *bytes);
+trw_status trw_adjacency_index_build(trw_graph g, void *d_buf, size_t bytes, trw_stream_t stream,
+                                     trw_table *out);
 
 /*
  * MetaPath label index (optional).  A MetaPath move only considers the edges
@@ -215,8 +230,8 @@ trw_status trw_default_tuning(trw_graph g, const trw_walk_params *p, uint32_t mo
 
 /*
  * Run nq queries, query i starting at d_sources[i] with id qid_base + i.
- *   table       ALIAS/ITS table built for p->sampler; NULL for NAIVE and OREJ;
- *               for METAPATH NULL (scan rows) or a label index
+ *   table       ALIAS/ITS table built for p->sampler; for NAIVE and OREJ NULL or
+ *               an adjacency index; for METAPATH NULL (scan rows) or a label index
  *   d_paths     int32, row i at d_paths + i*path_stride, path_stride >= max_len+1:
  *               paths[i][0] = source, paths[i][1..lengths[i]] = the moves;
  *               entries beyond lengths[i] are left unspecified

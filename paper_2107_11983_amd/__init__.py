@@ -113,6 +113,10 @@ class Graph:
     def table(self, sampler, stream=None) -> "Table":
         return Table(self, sampler, stream)
 
+    def adjacency_index(self, stream=None) -> "Table":
+        """Row-annotated adjacency for NAIVE / Node2Vec walks (identical results, fewer reads)."""
+        return Table(self, "adjacency_index", stream)
+
     def label_index(self, n_labels: int, stream=None) -> "Table":
         """MetaPath label index (rows sorted by label + per-vertex label offsets)."""
         return Table(self, "label_index", stream, n_labels=n_labels)
@@ -139,7 +143,13 @@ class Table:
         self.graph = graph
         nbytes = ctypes.c_size_t(0)
         h = ctypes.c_void_p()
-        if sampler == "label_index":
+        if sampler == "adjacency_index":
+            self.sampler = None
+            check(_abi.trw_adjacency_index_bytes(graph.handle, ctypes.byref(nbytes)))
+            self.buf = torch.empty(max(int(nbytes.value), 16), dtype=torch.uint8, device=graph.device)
+            check(_abi.trw_adjacency_index_build(graph.handle, _dptr(self.buf), int(nbytes.value),
+                                                 _stream_ptr(stream), ctypes.byref(h)))
+        elif sampler == "label_index":
             self.sampler = None
             self.n_labels = n_labels
             check(_abi.trw_label_index_bytes(graph.handle, n_labels, ctypes.byref(nbytes)))

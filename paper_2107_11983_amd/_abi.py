@@ -71,6 +71,8 @@ _SIGS = {
                        ctypes.POINTER(trw_tuning), _P, _sz, _P]),
     "trw_autotune": (_st, [_P, _P, ctypes.POINTER(trw_walk_params), _P, _u64, _P, _u64, _P, _P, _u32, _u32,
                            _P, _sz, _P, ctypes.POINTER(trw_tuning), ctypes.POINTER(ctypes.c_float)]),
+    "trw_adjacency_index_bytes": (_st, [_P, ctypes.POINTER(_sz)]),
+    "trw_adjacency_index_build": (_st, [_P, _P, _sz, _P, _PP]),
     "trw_label_index_bytes": (_st, [_P, _u32, ctypes.POINTER(_sz)]),
     "trw_label_index_build": (_st, [_P, _u32, _P, _sz, _P, _PP]),
     # measurement probe (include/trw_probe.h)
@@ -109,6 +111,8 @@ trw_walk_workspace_bytes = lib.trw_walk_workspace_bytes
 trw_default_tuning = lib.trw_default_tuning
 trw_walk = lib.trw_walk
 trw_autotune = lib.trw_autotune
+trw_adjacency_index_bytes = lib.trw_adjacency_index_bytes
+trw_adjacency_index_build = lib.trw_adjacency_index_build
 trw_label_index_bytes = lib.trw_label_index_bytes
 trw_label_index_build = lib.trw_label_index_build
 trw_probe_fill = lib.trw_probe_fill

@@ -24,6 +24,7 @@ struct trw_table_s {
 };
 
 static constexpr uint32_t kLabelIndexKind = 0x100;
+static constexpr uint32_t kAdjacencyKind = 0x101;
 
 static size_t label_index_loff_bytes(const trw::GraphDev &g, uint32_t nlab) {
     const size_t b = sizeof(int32_t) * (size_t)g.n * (nlab + 1);
@@ -31,6 +32,8 @@ static size_t label_index_loff_bytes(const trw::GraphDev &g, uint32_t nlab) {
 }
 
 namespace trw {
+
+__global__ void k_zero_first(unsigned long long *p) { *p = 0; }
 
 static thread_local std::string g_last_error;
 
@@ -135,7 +138,8 @@ trw_status trw_graph_create(int64_t n, int64_t m, const int32_t *d_row_ptr, cons
     if (!d_row_ptr || (!d_col && m > 0)) return fail(TRW_E_INVALID, "row_ptr / col is NULL");
     auto *g = new (std::nothrow) trw_graph_s;
     if (!g) return fail(TRW_E_INVALID, "out of host memory");
-    g->dev = GraphDev{d_row_ptr, d_col, d_weight, d_label, (int32_t)n, (int32_t)m};
+    g->dev = GraphDev{d_row_ptr, d_col, d_weight, d_label, (int32_t)n, (int32_t)m,
+                      (flags & TRW_G_SYMMETRIC) ? 1 : 0};
     g->flags = flags;
     g->device = device_info().device;
     *out = g;
@@ -156,6 +160,17 @@ trw_status trw_graph_validate(trw_graph g, void *d_ws, size_t ws_bytes, trw_stre
     if (e != hipSuccess) return device_fail(e, "validate readback");
     *n_bad = h;
     if (h) return fail(TRW_E_INVALID, "graph failed validation: " + std::to_string(h) + " violations");
+    if (g->dev.symmetric) {   // only on a well-formed graph: the check reads the rows it is pointed to
+        unsigned long long *bad2 = bad + 1;
+        hipLaunchKernelGGL(k_zero_first, dim3(1), dim3(1), 0, s, bad2);
+        e = launch_symmetry_check(g->dev, bad2, s);
+        if (e != hipSuccess) return device_fail(e, "symmetry check launch");
+        e = hipMemcpyAsync(&h, bad2, sizeof(h), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return device_fail(e, "symmetry check readback");
+        *n_bad = h;
+        if (h) return fail(TRW_E_INVALID, "graph flagged symmetric has " + std::to_string(h) + " edges without reverse");
+    }
     return TRW_OK;
 }
 
@@ -225,6 +240,27 @@ trw_status trw_label_index_build(trw_graph g, uint32_t n_labels, void *d_buf, si
     return TRW_OK;
 }
 
+trw_status trw_adjacency_index_bytes(trw_graph g, size_t *bytes) {
+    if (!g || !bytes) return fail(TRW_E_INVALID, "graph / bytes is NULL");
+    *bytes = sizeof(uint4) * (size_t)g->dev.m;
+    return TRW_OK;
+}
+
+trw_status trw_adjacency_index_build(trw_graph g, void *d_buf, size_t bytes, trw_stream_t stream, trw_table *out) {
+    if (!g || !out) return fail(TRW_E_INVALID, "graph / out is NULL");
+    if (bytes < sizeof(uint4) * (size_t)g->dev.m) return fail(TRW_E_INVALID, "adjacency index buffer too small");
+    if (g->dev.m > 0 && (!d_buf || (reinterpret_cast<uintptr_t>(d_buf) & 15)))
+        return fail(TRW_E_INVALID, "adjacency index buffer NULL or not 16-byte aligned");
+    if (g->dev.m > 0) {
+        hipError_t e = launch_adjacency_build(g->dev, static_cast<uint4 *>(d_buf), static_cast<hipStream_t>(stream));
+        if (e != hipSuccess) return device_fail(e, "adjacency index build launch");
+    }
+    auto *t = new (std::nothrow) trw_table_s{g, kAdjacencyKind, d_buf, 0};
+    if (!t) return fail(TRW_E_INVALID, "out of host memory");
+    *out = t;
+    return TRW_OK;
+}
+
 trw_status trw_table_destroy(trw_table t) {
     delete t;
     return TRW_OK;
@@ -270,6 +306,12 @@ trw_status trw_walk(trw_graph g, trw_table table, const trw_walk_params *p, cons
         if (table->graph != g) return fail(TRW_E_INVALID, "table was built for another graph");
         if (table->sampler != p->sampler) return fail(TRW_E_INVALID, "table was built for another sampler");
     }
+    const bool adjacency = !needs_table && p->algo != TRW_A_METAPATH && table != nullptr;
+    if (adjacency) {
+        if (table->graph != g) return fail(TRW_E_INVALID, "adjacency index was built for another graph");
+        if (table->sampler != kAdjacencyKind)
+            return fail(TRW_E_INVALID, "NAIVE / OREJ walks take an adjacency index or no table");
+    }
     const bool label_index = p->algo == TRW_A_METAPATH && table != nullptr;
     if (label_index) {
         if (table->graph != g) return fail(TRW_E_INVALID, "label index was built for another graph");
@@ -302,7 +344,8 @@ trw_status trw_walk(trw_graph g, trw_table table, const trw_walk_params *p, cons
     w.stride = path_stride;
     w.lengths = d_lengths;
     w.status = d_status;
-    TableDev t{nullptr, nullptr, nullptr, nullptr, 0};
+    TableDev t{nullptr, nullptr, nullptr, nullptr, 0, nullptr};
+    if (adjacency) t.adj = static_cast<const uint4 *>(table->buf);
     if (needs_table) {
         if (p->sampler == TRW_S_ALIAS) t.alias = static_cast<const uint4 *>(table->buf);
         else t.prefix = static_cast<const uint64_t *>(table->buf);

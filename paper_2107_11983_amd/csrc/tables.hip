@@ -163,6 +163,36 @@ __global__ void k_label_index_build(GraphDev g, uint32_t nlab, int32_t *__restri
     for (; pos < end; ++pos) lcol[pos] = -1;      // edges whose label is >= L
 }
 
+// Row-annotated adjacency: every edge slot carries its destination's row
+// range, so a walk that picks the slot knows the next row without a lookup.
+__global__ void k_adjacency_build(GraphDev g, uint4 *__restrict__ out) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= g.m) return;
+    const int32_t v = g.col[e];
+    const uint2 r = row_of(g, v);
+    out[e] = make_uint4((uint32_t)v, r.x, r.y, 0u);
+}
+
+// Edges (u, v) whose reverse (v, u) is missing; rows must be sorted.
+__global__ void k_symmetry_check(GraphDev g, unsigned long long *__restrict__ bad) {
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= g.n) return;
+    unsigned long long nbad = 0;
+    for (int64_t e = g.row_ptr[u]; e < g.row_ptr[u + 1]; ++e) {
+        const int32_t v = g.col[e];
+        int64_t lo = g.row_ptr[v], hi = g.row_ptr[v + 1];
+        bool found = false;
+        while (lo < hi) {
+            const int64_t mid = lo + ((hi - lo) >> 1);
+            const int32_t c = g.col[mid];
+            if (c == (int32_t)u) { found = true; break; }
+            if (c < (int32_t)u) lo = mid + 1; else hi = mid;
+        }
+        nbad += !found;
+    }
+    if (nbad) atomicAdd(bad, nbad);
+}
+
 constexpr int kBuildThreads = 256;
 
 }  // namespace
@@ -182,6 +212,18 @@ hipError_t launch_its_build(const GraphDev &g, uint64_t *out, hipStream_t s) {
 hipError_t launch_label_index_build(const GraphDev &g, uint32_t nlab, int32_t *loff, int32_t *lcol, hipStream_t s) {
     const int blocks = (g.n + kBuildThreads - 1) / kBuildThreads;
     hipLaunchKernelGGL(k_label_index_build, dim3(blocks), dim3(kBuildThreads), 0, s, g, nlab, loff, lcol);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjacency_build(const GraphDev &g, uint4 *out, hipStream_t s) {
+    const int64_t blocks = ((int64_t)g.m + kBuildThreads - 1) / kBuildThreads;
+    hipLaunchKernelGGL(k_adjacency_build, dim3((uint32_t)blocks), dim3(kBuildThreads), 0, s, g, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_symmetry_check(const GraphDev &g, unsigned long long *d_bad, hipStream_t s) {
+    const int blocks = (g.n + kBuildThreads - 1) / kBuildThreads;
+    hipLaunchKernelGGL(k_symmetry_check, dim3(blocks), dim3(kBuildThreads), 0, s, g, d_bad);
     return hipGetLastError();
 }
 

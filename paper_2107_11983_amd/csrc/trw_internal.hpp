@@ -18,6 +18,7 @@ struct GraphDev {
     const uint8_t *label;
     int32_t n;
     int32_t m;
+    int32_t symmetric;   // every edge has its reverse (checked by trw_graph_validate)
 };
 
 // An ALIAS entry is 32 bytes, two uint4 per edge slot:
@@ -37,6 +38,7 @@ struct TableDev {
     const int32_t *loff;      // label index: (L + 1) offsets per vertex
     const int32_t *lcol;      // label index: label-sorted destinations
     uint32_t nlab;            // label index: L
+    const uint4 *adj;         // adjacency index: {dst, row_off(dst), deg(dst), 0} per edge slot
 };
 constexpr size_t kAliasEntryBytes = 32;
 constexpr uint32_t kMaxIndexLabels = 64;
@@ -61,7 +63,14 @@ struct WalkDev {
 
 enum : uint8_t { ST_LENGTH = 1, ST_STOPPED = 2, ST_DEAD_END = 3, ST_BAD_SOURCE = 4 };
 enum : uint32_t { ALG_DEEPWALK = 0, ALG_PPR = 1, ALG_NODE2VEC = 2, ALG_METAPATH = 3 };
-enum : uint32_t { SMP_NAIVE = 0, SMP_ALIAS = 1, SMP_ITS = 2, SMP_OREJ = 3, SMP_LABEL_INDEX = 4 };
+// Internal sampler codes: the public four, plus the same samplers reading an
+// index (identical results, fewer dependent reads).
+enum : uint32_t {
+    SMP_NAIVE = 0, SMP_ALIAS = 1, SMP_ITS = 2, SMP_OREJ = 3,
+    SMP_LABEL_INDEX = 4,   // MetaPath with a label index
+    SMP_NAIVE_ADJ = 5,     // NAIVE with the adjacency index
+    SMP_OREJ_ADJ = 6       // Node2Vec O-REJ with the adjacency index
+};
 
 // Darts per O-REJ move at most (then the last dart is taken); with every
 // threshold >= 1 the cap is reached with probability below e^-256.
@@ -85,6 +94,8 @@ hipError_t launch_alias_build(const GraphDev &g, uint4 *out, hipStream_t s);
 hipError_t launch_its_build(const GraphDev &g, uint64_t *out, hipStream_t s);
 hipError_t launch_validate(const GraphDev &g, unsigned long long *d_bad, hipStream_t s);
 hipError_t launch_label_index_build(const GraphDev &g, uint32_t nlab, int32_t *loff, int32_t *lcol, hipStream_t s);
+hipError_t launch_adjacency_build(const GraphDev &g, uint4 *out, hipStream_t s);
+hipError_t launch_symmetry_check(const GraphDev &g, unsigned long long *d_bad, hipStream_t s);
 
 size_t walk_workspace_bytes(uint32_t mode, uint64_t nq, uint32_t max_len);
 hipError_t launch_walk(const GraphDev &g, const TableDev &t, uint32_t algo, uint32_t sampler,

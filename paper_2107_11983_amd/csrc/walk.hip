@@ -35,51 +35,81 @@ namespace {
 constexpr uint32_t kIdle = 0xFFFFFFFFu;
 
 // ---------------------------------------------------------------------------
-// Move for the samplers that read the adjacency array (NAIVE, ITS, O-REJ,
-// MetaPath).  Returns the next vertex, or -1 when the current vertex has no
-// eligible edge (dead end).  `r` is the block of dart 0.
+// Move of a static walk that reads the adjacency array (NAIVE, ITS).  Returns
+// the next vertex, or -1 when the row has no transition (weights sum to 0).
 // ---------------------------------------------------------------------------
-template <uint32_t ALGO, uint32_t SMP>
-__device__ __forceinline__ int32_t sample_next(const GraphDev &g, const TableDev &t, const WalkDev &a,
-                                               uint64_t qid, uint32_t k, int32_t off, uint32_t d,
-                                               const Rand4 &r, int32_t prev, int32_t poff, int32_t pd) {
-    if (ALGO == ALG_NODE2VEC) {
-        // O-REJ with p* = max weight: throw darts (x, y) until y < p(x) / p*.
-        Rand4 rr = r;
-        for (uint32_t dart = 0;; ++dart) {
-            if (dart > 0) rr = philox(k, dart, qid, a.seed);
-            const int32_t x = g.col[off + scale32(rr.r0, d)];
-            if (k == 0 || dart + 1 == kMaxDarts) return x;
-            uint32_t th;
+template <uint32_t SMP>
+__device__ __forceinline__ int32_t static_next(const GraphDev &g, const TableDev &t, int32_t off, uint32_t d,
+                                               const Rand4 &r) {
+    if (SMP == SMP_NAIVE) return g.col[off + scale32(r.r0, d)];
+    // ITS: x uniform in [0, W) from 64 bits, smallest i with x < prefix[i]
+    const uint64_t *__restrict__ p = t.prefix + off;
+    const uint64_t W = p[d - 1];
+    if (W == 0) return -1;
+    const uint64_t x = scale64(r.r0, r.r1, W);
+    uint32_t lo = 0, hi = d - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (x < p[mid]) hi = mid; else lo = mid + 1;
+    }
+    return g.col[off + lo];
+}
+
+// ---------------------------------------------------------------------------
+// Node2Vec move, O-REJ (Sampling Methods: rejection with a user bound p*):
+// throw darts (x, y) with x a uniform edge slot of cur and y = r1 >> 16 until
+// y falls under the Q16 threshold of x's class (x == prev, x adjacent to
+// prev, otherwise; the Node2Vec transition equation).  The adjacency test is
+// a binary search in a sorted row, made only when the dart's height lies
+// between the two thresholds it would choose between.  With the adjacency index a dart also
+// learns x's row, so on a symmetric graph the search can run in the shorter
+// of the two rows (x in N(prev) iff prev in N(x)), and an accepted move needs
+// no row lookup.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool in_row(const int32_t *__restrict__ col, int32_t lo, int32_t hi, int32_t key) {
+    while (lo < hi) {
+        const int32_t mid = lo + ((hi - lo) >> 1);
+        const int32_t c = col[mid];
+        if (c == key) return true;
+        if (c < key) lo = mid + 1; else hi = mid;
+    }
+    return false;
+}
+
+template <bool ADJ>
+__device__ __forceinline__ int32_t n2v_move(const GraphDev &g, const TableDev &t, const WalkDev &a, uint64_t qid,
+                                            uint32_t k, int32_t off, uint32_t d, const Rand4 &r, int32_t prev,
+                                            int32_t poff, int32_t pd, int32_t &noff, int32_t &ndeg) {
+    Rand4 rr = r;
+    for (uint32_t dart = 0;; ++dart) {
+        if (dart > 0) rr = philox(k, dart, qid, a.seed);
+        const uint32_t slot = (uint32_t)off + scale32(rr.r0, d);
+        int32_t x, xo = 0, xd = 0;
+        if (ADJ) {
+            const uint4 e = t.adj[slot];
+            x = (int32_t)e.x; xo = (int32_t)e.y; xd = (int32_t)e.z;
+        } else {
+            x = g.col[slot];
+        }
+        bool accept = (k == 0 || dart + 1 == kMaxDarts);
+        if (!accept) {
+            const uint32_t y = rr.r1 >> 16;
             if (x == prev) {
-                th = a.thr[0];
+                accept = y < a.thr[0];
+            } else if (y < min(a.thr[1], a.thr[2])) {
+                accept = true;          // under both thresholds: the adjacency test cannot change it
+            } else if (y >= max(a.thr[1], a.thr[2])) {
+                accept = false;         // over both
             } else {
-                // is x adjacent to prev?  binary search in prev's sorted row
-                int32_t lo = poff, hi = poff + pd;
-                bool found = false;
-                while (lo < hi) {
-                    const int32_t mid = lo + ((hi - lo) >> 1);
-                    const int32_t c = g.col[mid];
-                    if (c == x) { found = true; break; }
-                    if (c < x) lo = mid + 1; else hi = mid;
-                }
-                th = found ? a.thr[1] : a.thr[2];
+                const bool adjacent = (ADJ && g.symmetric && xd < pd) ? in_row(g.col, xo, xo + xd, prev)
+                                                                      : in_row(g.col, poff, poff + pd, x);
+                accept = y < (adjacent ? a.thr[1] : a.thr[2]);
             }
-            if ((rr.r1 >> 16) < th) return x;
         }
-    } else if (SMP == SMP_NAIVE) {
-        return g.col[off + scale32(r.r0, d)];
-    } else {  // ITS
-        const uint64_t *__restrict__ p = t.prefix + off;
-        const uint64_t W = p[d - 1];
-        if (W == 0) return -1;
-        const uint64_t x = scale64(r.r0, r.r1, W);
-        uint32_t lo = 0, hi = d - 1;                          // smallest i with x < p[i]
-        while (lo < hi) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (x < p[mid]) hi = mid; else lo = mid + 1;
+        if (accept) {
+            noff = xo; ndeg = xd;
+            return x;
         }
-        return g.col[off + lo];
     }
 }
 
@@ -288,7 +318,9 @@ template <uint32_t ALGO, uint32_t SMP, int WPL>
 __global__ void __launch_bounds__(256)
 k_walk_persistent(GraphDev g, TableDev t, WalkDev a, unsigned long long *__restrict__ queue_head,
                   uint32_t chunk, uint32_t coop) {
-    constexpr bool kAlias = (SMP == SMP_ALIAS) && (ALGO == ALG_DEEPWALK || ALGO == ALG_PPR);
+    constexpr bool kStatic = (ALGO == ALG_DEEPWALK || ALGO == ALG_PPR);
+    constexpr bool kAlias = kStatic && SMP == SMP_ALIAS;
+    constexpr bool kOneRead = kAlias || (kStatic && SMP == SMP_NAIVE_ADJ);   // entry carries the next row
     constexpr bool kNoRows = (SMP == SMP_LABEL_INDEX);   // the label index replaces the row lookup
     Walker w[WPL];
 #pragma unroll
@@ -361,14 +393,18 @@ k_walk_persistent(GraphDev g, TableDev t, WalkDev a, unsigned long long *__restr
 
         // Move.
         int32_t nxt[WPL];
-        if (kAlias) {
+        if (kOneRead) {
             uint4 e0[WPL], e1[WPL];
 #pragma unroll
             for (int i = 0; i < WPL; ++i) {
                 if (w[i].qi != kIdle && w[i].deg != 0) {
                     const uint32_t e = (uint32_t)w[i].off + scale32(r[i].r0, (uint32_t)w[i].deg);
-                    e0[i] = t.alias[2 * (uint64_t)e];
-                    e1[i] = t.alias[2 * (uint64_t)e + 1];
+                    if (kAlias) {
+                        e0[i] = t.alias[2 * (uint64_t)e];
+                        e1[i] = t.alias[2 * (uint64_t)e + 1];
+                    } else {
+                        e0[i] = t.adj[e];
+                    }
                 }
             }
 #pragma unroll
@@ -376,7 +412,11 @@ k_walk_persistent(GraphDev g, TableDev t, WalkDev a, unsigned long long *__restr
                 nxt[i] = -1;
                 if (w[i].qi != kIdle && w[i].deg != 0) {
                     w[i].poff = w[i].off; w[i].pdeg = w[i].deg;
-                    nxt[i] = alias_pick(e0[i], e1[i], r[i].r1, w[i].off, w[i].deg);
+                    if (kAlias) {
+                        nxt[i] = alias_pick(e0[i], e1[i], r[i].r1, w[i].off, w[i].deg);
+                    } else {
+                        nxt[i] = (int32_t)e0[i].x; w[i].off = (int32_t)e0[i].y; w[i].deg = (int32_t)e0[i].z;
+                    }
                 }
             }
         } else if (ALGO == ALG_METAPATH) {
@@ -387,13 +427,26 @@ k_walk_persistent(GraphDev g, TableDev t, WalkDev a, unsigned long long *__restr
                                             r[i].r0, coop);
                 if (act) w[i].need_row = !kNoRows;
             }
+        } else if (ALGO == ALG_NODE2VEC) {
+            constexpr bool kAdj = SMP == SMP_OREJ_ADJ;
+#pragma unroll
+            for (int i = 0; i < WPL; ++i) {
+                nxt[i] = -1;
+                if (w[i].qi != kIdle && w[i].deg != 0) {
+                    int32_t no = 0, nd = 0;
+                    nxt[i] = n2v_move<kAdj>(g, t, a, a.qid_base + w[i].qi, w[i].k, w[i].off, (uint32_t)w[i].deg,
+                                            r[i], w[i].prev, w[i].poff, w[i].pdeg, no, nd);
+                    w[i].poff = w[i].off; w[i].pdeg = w[i].deg;
+                    if (kAdj) { w[i].off = no; w[i].deg = nd; }
+                    w[i].need_row = !kAdj;
+                }
+            }
         } else {
 #pragma unroll
             for (int i = 0; i < WPL; ++i) {
                 nxt[i] = -1;
                 if (w[i].qi != kIdle && w[i].deg != 0) {
-                    nxt[i] = sample_next<ALGO, SMP>(g, t, a, a.qid_base + w[i].qi, w[i].k, w[i].off,
-                                                    (uint32_t)w[i].deg, r[i], w[i].prev, w[i].poff, w[i].pdeg);
+                    nxt[i] = static_next<SMP>(g, t, w[i].off, (uint32_t)w[i].deg, r[i]);
                     w[i].poff = w[i].off; w[i].pdeg = w[i].deg;
                     w[i].need_row = true;
                 }
@@ -477,7 +530,9 @@ __global__ void __launch_bounds__(256) k_bsp_step(GraphDev g, TableDev t, WalkDe
                                                   const Rec *__restrict__ in, const uint32_t *__restrict__ count_in,
                                                   Rec *__restrict__ out, uint32_t *__restrict__ count_out,
                                                   uint32_t coop) {
-    constexpr bool kAlias = (SMP == SMP_ALIAS) && (ALGO == ALG_DEEPWALK || ALGO == ALG_PPR);
+    constexpr bool kStatic = (ALGO == ALG_DEEPWALK || ALGO == ALG_PPR);
+    constexpr bool kAlias = kStatic && SMP == SMP_ALIAS;
+    constexpr bool kCarry = kAlias || (kStatic && SMP == SMP_NAIVE_ADJ);   // records carry cur's row
     const uint32_t n_in = *count_in;
     const uint32_t stride = gridDim.x * blockDim.x;
     for (uint32_t base = 0; base < n_in; base += stride) {
@@ -490,7 +545,7 @@ __global__ void __launch_bounds__(256) k_bsp_step(GraphDev g, TableDev t, WalkDe
         if (act) {
             rc = in[idx];
             r = philox(k, 0, a.qid_base + rc.qi, a.seed);
-            if (!kAlias && SMP != SMP_LABEL_INDEX) {
+            if (!kCarry && SMP != SMP_LABEL_INDEX) {
                 off = g.row_ptr[rc.cur];
                 d = (uint32_t)(g.row_ptr[rc.cur + 1] - off);
             }
@@ -499,18 +554,26 @@ __global__ void __launch_bounds__(256) k_bsp_step(GraphDev g, TableDev t, WalkDe
         if (ALGO == ALG_METAPATH) {
             nxt = metapath_move<SMP>(g, t, a, act, k, rc.cur, off, d, r.r0, coop);
         } else if (act) {
-            if (kAlias) {
+            if (kCarry) {
                 if (rc.b != 0) {
                     const uint32_t e = (uint32_t)rc.a + scale32(r.r0, (uint32_t)rc.b);
-                    nxt = alias_pick(t.alias[2 * (uint64_t)e], t.alias[2 * (uint64_t)e + 1], r.r1, noff, ndeg);
+                    if (kAlias) {
+                        nxt = alias_pick(t.alias[2 * (uint64_t)e], t.alias[2 * (uint64_t)e + 1], r.r1, noff, ndeg);
+                    } else {
+                        const uint4 rec = t.adj[e];
+                        nxt = (int32_t)rec.x; noff = (int32_t)rec.y; ndeg = (int32_t)rec.z;
+                    }
                 }
-            } else {
-                int32_t poff = 0, pd = 0;
-                if (ALGO == ALG_NODE2VEC && rc.a >= 0) {
+            } else if (ALGO == ALG_NODE2VEC) {
+                int32_t poff = 0, pd = 0, no = 0, nd = 0;
+                if (rc.a >= 0) {
                     poff = g.row_ptr[rc.a];
                     pd = g.row_ptr[rc.a + 1] - poff;
                 }
-                if (d != 0) nxt = sample_next<ALGO, SMP>(g, t, a, a.qid_base + rc.qi, k, off, d, r, rc.a, poff, pd);
+                if (d != 0)
+                    nxt = n2v_move<SMP == SMP_OREJ_ADJ>(g, t, a, a.qid_base + rc.qi, k, off, d, r, rc.a, poff, pd, no, nd);
+            } else {
+                if (d != 0) nxt = static_next<SMP>(g, t, off, d, r);
             }
         }
         bool keep = false;
@@ -531,7 +594,7 @@ __global__ void __launch_bounds__(256) k_bsp_step(GraphDev g, TableDev t, WalkDe
                 a.status[rc.qi] = st;
             } else {
                 keep = true;
-                nr = kAlias ? Rec{rc.qi, nxt, noff, ndeg} : Rec{rc.qi, nxt, rc.cur, 0};
+                nr = kCarry ? Rec{rc.qi, nxt, noff, ndeg} : Rec{rc.qi, nxt, rc.cur, 0};
             }
         }
         const uint32_t slot = wave_append(count_out, keep);
@@ -572,7 +635,7 @@ hipError_t run_persistent(const GraphDev &g, const TableDev &t, const WalkDev &w
 template <uint32_t ALGO, uint32_t SMP>
 hipError_t run_bsp(const GraphDev &g, const TableDev &t, const WalkDev &w, const Tuning &tu,
                    const DeviceInfo &di, void *ws, hipStream_t s) {
-    constexpr bool kAlias = (SMP == SMP_ALIAS) && (ALGO == ALG_DEEPWALK || ALGO == ALG_PPR);
+    constexpr bool kCarry = (ALGO == ALG_DEEPWALK || ALGO == ALG_PPR) && (SMP == SMP_ALIAS || SMP == SMP_NAIVE_ADJ);
     char *base = reinterpret_cast<char *>(ws);
     uint32_t *counts = reinterpret_cast<uint32_t *>(base);
     const size_t counts_bytes = round_up(sizeof(uint32_t) * (w.max_len + 2));
@@ -585,7 +648,7 @@ hipError_t run_bsp(const GraphDev &g, const TableDev &t, const WalkDev &w, const
     const uint64_t need = ((uint64_t)w.nq + threads - 1) / threads;
     if (blocks > need) blocks = need;
     if (blocks == 0) blocks = 1;
-    hipLaunchKernelGGL(k_bsp_init<kAlias>, dim3(blocks), dim3(threads), 0, s, g, w, lists[0], counts);
+    hipLaunchKernelGGL(k_bsp_init<kCarry>, dim3(blocks), dim3(threads), 0, s, g, w, lists[0], counts);
     for (uint32_t k = 0; k < w.max_len; ++k) {
         hipLaunchKernelGGL((k_bsp_step<ALGO, SMP>), dim3(blocks), dim3(threads), 0, s, g, t, w, k,
                            lists[k & 1], counts + k, lists[(k + 1) & 1], counts + k + 1, tu.coop_degree);
@@ -613,14 +676,17 @@ hipError_t launch_walk(const GraphDev &g, const TableDev &t, uint32_t algo, uint
     if (w.nq == 0) return hipSuccess;
     switch (algo) {
         case ALG_DEEPWALK:
+            if (sampler == SMP_NAIVE && t.adj) return run<ALG_DEEPWALK, SMP_NAIVE_ADJ>(g, t, w, mode, tu, di, ws, s);
             if (sampler == SMP_NAIVE) return run<ALG_DEEPWALK, SMP_NAIVE>(g, t, w, mode, tu, di, ws, s);
             if (sampler == SMP_ALIAS) return run<ALG_DEEPWALK, SMP_ALIAS>(g, t, w, mode, tu, di, ws, s);
             return run<ALG_DEEPWALK, SMP_ITS>(g, t, w, mode, tu, di, ws, s);
         case ALG_PPR:
+            if (sampler == SMP_NAIVE && t.adj) return run<ALG_PPR, SMP_NAIVE_ADJ>(g, t, w, mode, tu, di, ws, s);
             if (sampler == SMP_NAIVE) return run<ALG_PPR, SMP_NAIVE>(g, t, w, mode, tu, di, ws, s);
             if (sampler == SMP_ALIAS) return run<ALG_PPR, SMP_ALIAS>(g, t, w, mode, tu, di, ws, s);
             return run<ALG_PPR, SMP_ITS>(g, t, w, mode, tu, di, ws, s);
         case ALG_NODE2VEC:
+            if (t.adj) return run<ALG_NODE2VEC, SMP_OREJ_ADJ>(g, t, w, mode, tu, di, ws, s);
             return run<ALG_NODE2VEC, SMP_OREJ>(g, t, w, mode, tu, di, ws, s);
         default:
             if (t.loff) return run<ALG_METAPATH, SMP_LABEL_INDEX>(g, t, w, mode, tu, di, ws, s);

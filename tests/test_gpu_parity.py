@@ -57,6 +57,11 @@ class Case:
             self._dev_tables[sampler] = self.G.table(sampler)
         return self._dev_tables[sampler]
 
+    def adjacency_index(self):
+        if "adj" not in self._dev_tables:
+            self._dev_tables["adj"] = self.G.adjacency_index()
+        return self._dev_tables["adj"]
+
     def label_index(self, n_labels):
         key = ("label_index", n_labels)
         if key not in self._dev_tables:
@@ -76,7 +81,7 @@ class Case:
 
 
 def run_both(case, algo, sampler, max_len, seed, src, mode, tuning=None, qid_base=0, stop=0,
-             thr=(65536, 65536, 65536), schema=(), stride=0, label_index=0):
+             thr=(65536, 65536, 65536), schema=(), stride=0, label_index=0, adjacency=False):
     g = case.g
     src = np.ascontiguousarray(src, dtype=np.int32)
     nq = len(src)
@@ -88,6 +93,9 @@ def run_both(case, algo, sampler, max_len, seed, src, mode, tuning=None, qid_bas
     table = case.dev_table(sampler) if algo in ("deepwalk", "ppr") else None
     if algo == "metapath" and label_index:
         table = case.label_index(label_index)
+    if adjacency:
+        assert sampler in ("naive", "orej")
+        table = case.adjacency_index()
     trw.walk(case.G, table, p, d_src, qid_base=qid_base, mode=mode, tuning=tuning, bufs=bufs)
     torch.cuda.synchronize()
     gp = bufs.paths.cpu().numpy()
@@ -348,6 +356,10 @@ def test_workloads_reduced_scale(name):
                 gpu, ref = run_both(case, wl.algo, sampler, wl.max_len, wl.walk_seed, src, mode,
                                     label_index=wl.labels, **kw)
                 assert_same(gpu, ref, wl.max_len)
+            if wl.algo == "node2vec":
+                gpu, ref = run_both(case, wl.algo, sampler, wl.max_len, wl.walk_seed, src, mode,
+                                    adjacency=True, **kw)
+                assert_same(gpu, ref, wl.max_len)
 
 
 # --------------------------------------------------------------------------- MetaPath gathers
@@ -402,3 +414,37 @@ def test_metapath_label_index_rejects_large_schema_labels(rmat_sym):
     src = torch.arange(10, dtype=torch.int32, device="cuda")
     with pytest.raises(trw.TrwError):
         trw.walk(rmat_sym.G, rmat_sym.label_index(5), p, src)
+
+
+# --------------------------------------------------------------------------- adjacency index
+def test_adjacency_index_records(rmat_dir):
+    g = rmat_dir.g
+    t = rmat_dir.adjacency_index()
+    torch.cuda.synchronize()
+    got = t.buf[:16 * g.m].view(torch.int32).cpu().numpy().view(np.uint32).reshape(-1, 4)
+    rp = g.row_ptr.astype(np.int64)
+    assert np.array_equal(got[:, 0], g.col.view(np.uint32))
+    assert np.array_equal(got[:, 1], rp[g.col].astype(np.uint32))
+    assert np.array_equal(got[:, 2], np.diff(rp)[g.col].astype(np.uint32))
+
+
+@pytest.mark.parametrize("algo,sampler", [("deepwalk", "naive"), ("ppr", "naive"), ("node2vec", "orej")])
+@pytest.mark.parametrize("mode", [1, 0])
+def test_adjacency_index_parity(rmat_sym, rmat_dir, algo, sampler, mode):
+    for case in (rmat_sym, rmat_dir):          # Node2Vec on the directed graph searches prev's row only
+        n = case.g.n
+        src = np.concatenate([np.arange(n), synth.sources(77, n, 2)]).astype(np.int32)
+        for pq in ((2.0, 0.5), (0.25, 4.0)):
+            kw = _args(algo)
+            if algo == "node2vec":
+                kw["thr"] = oracle.n2v_thresholds(*pq)
+            gpu, ref = run_both(case, algo, sampler, 50, 1234, src, mode, adjacency=True, **kw)
+            assert_same(gpu, ref, 50)
+            if algo != "node2vec":
+                break
+
+
+def test_validate_checks_symmetry():
+    g = synth.from_edges(4, [(0, 1), (1, 0), (1, 2), (2, 1), (2, 3)])      # (2,3) has no reverse
+    assert trw.Graph(g.row_ptr, g.col, symmetric=False).validate() == 0
+    assert trw.Graph(g.row_ptr, g.col, symmetric=True).validate() == 1
