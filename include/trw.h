@@ -267,6 +267,95 @@ trw_status trw_autotune(trw_graph g, trw_table table, const trw_walk_params *p,
                         uint32_t mode, uint32_t budget, void *d_ws, size_t ws_bytes,
                         trw_stream_t stream, trw_tuning *out, float *best_ms);
 
+/* ------------------------------------------------------------------------ */
+/* Serving (all calls thread-safe).  A server keeps the graph, its tables and */
+/* a pool of walker slots resident on the GPU and runs a host thread that     */
+/* admits requests as memory and request slots free up (continuous batching: */
+/* requests that arrive while others run share the device from the next tick)*/
+/* The paper's engine runs one batch of queries at a time (Step-centric      */
+/* Programming: parallelization); serving is this engine's addition.         */
+/* ------------------------------------------------------------------------ */
+typedef struct trw_server_s *trw_server;
+
+typedef struct {
+    uint32_t max_slots;        /* walker slots, a multiple of 256; 0 = 512 per CU */
+    uint32_t max_requests;     /* requests admitted at once, <= 65536; 0 = 1024 */
+    uint32_t steps_per_tick;   /* moves per slot per tick; 0 = 32 */
+    uint32_t use_hipgraph;     /* 1: replay the tick as a captured HIP graph */
+    uint32_t reserved[4];
+} trw_server_cfg;
+
+enum { TRW_REQ_HOST = 1 };     /* sources / paths / lengths / status are host memory */
+
+typedef struct {
+    trw_walk_params params;    /* DeepWalk / PPR with NAIVE or ALIAS, Node2Vec with OREJ */
+    const int32_t *sources;    /* nq sources; read when the request is admitted */
+    uint32_t nq;               /* >= 1 */
+    uint32_t flags;            /* TRW_REQ_HOST or 0 (device buffers) */
+    uint64_t qid_base;         /* query i has id qid_base + i (same walks as trw_walk) */
+    int32_t *paths;            /* nq rows of path_stride entries, written at completion */
+    uint64_t path_stride;      /* >= max_len + 1 */
+    uint32_t *lengths;         /* nq */
+    uint8_t *status;           /* nq, trw_walk_status */
+    void *user;                /* returned in the completion */
+} trw_request;
+
+typedef struct {
+    uint64_t request_id;
+    int32_t status;            /* TRW_OK or TRW_E_CANCELLED */
+    uint32_t nq;
+    void *user;
+    uint64_t t_submit_ns;      /* host steady clock: submit, admission, outputs delivered */
+    uint64_t t_admit_ns;
+    uint64_t t_done_ns;
+} trw_completion;
+
+typedef struct {
+    uint64_t submitted, completed, cancelled, rejected, ticks, moves;
+    uint32_t active, waiting;
+    uint64_t pool_bytes, pool_bytes_used;
+} trw_server_stats;
+
+/* Device bytes of a server arena for `cfg` with a request pool of pool_bytes. */
+trw_status trw_server_arena_bytes(const trw_server_cfg *cfg, size_t pool_bytes, size_t *bytes);
+
+/*
+ * Create a server on the current device.  alias: the graph's ALIAS table (or
+ * NULL: then ALIAS requests are refused); adjacency: an adjacency index (or
+ * NULL).  d_arena: caller-owned device memory (256-byte aligned) holding the
+ * fixed server state and, after it, the request pool; keep it alive until
+ * trw_server_destroy.  Starts the server thread.
+ */
+trw_status trw_server_create(trw_graph g, trw_table alias, trw_table adjacency, const trw_server_cfg *cfg,
+                             void *d_arena, size_t arena_bytes, trw_server *out);
+
+/* Pool bytes a request occupies while admitted (its sources and outputs). */
+trw_status trw_server_request_bytes(trw_server s, const trw_request *r, size_t *bytes);
+
+/*
+ * Queue a request.  Returns at once with its id; the request is admitted when
+ * a request slot and pool space are free, in submission order.  Errors:
+ * TRW_E_NOMEM_BUDGET if it can never fit the pool, TRW_E_UNSUPPORTED /
+ * TRW_E_INVALID as trw_walk.  The caller keeps sources valid until admission
+ * and the output buffers until the completion is polled.
+ */
+trw_status trw_server_submit(trw_server s, const trw_request *r, uint64_t *request_id);
+
+/* Cancel a request: it completes with TRW_E_CANCELLED; others are unaffected. */
+trw_status trw_server_cancel(trw_server s, uint64_t request_id);
+
+/*
+ * Take up to `max` completions, waiting up to timeout_ms for the first one
+ * (0 = do not wait).  Returns TRW_E_TIMEOUT if it waited and none arrived.
+ */
+trw_status trw_server_poll(trw_server s, trw_completion *out, uint32_t max, uint32_t *n_out,
+                           uint32_t timeout_ms);
+
+trw_status trw_server_stats_get(trw_server s, trw_server_stats *out);
+
+/* Cancel what is queued or running, stop the thread and release host state. */
+trw_status trw_server_destroy(trw_server s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -13,6 +13,8 @@ import numpy as np
 import torch
 
 from . import _abi
+from ._abi import (TRW_E_CANCELLED, TRW_E_NOMEM_BUDGET, TRW_E_TIMEOUT, TRW_REQ_HOST, trw_completion,
+                   trw_request, trw_server_cfg, trw_server_stats)
 from ._abi import (TRW_A_DEEPWALK, TRW_A_METAPATH, TRW_A_NODE2VEC, TRW_A_PPR, TRW_G_SYMMETRIC,
                    TRW_M_PER_STEP, TRW_M_PERSISTENT, TRW_S_ALIAS, TRW_S_ITS, TRW_S_NAIVE, TRW_S_OREJ,
                    TRW_ST_BAD_SOURCE, TRW_ST_DEAD_END, TRW_ST_LENGTH, TRW_ST_STOPPED, TrwError, check,
@@ -236,3 +238,93 @@ def autotune(graph: Graph, table: Optional[Table], p: trw_walk_params, sources: 
                             _dptr(bufs.status), mode, budget, _dptr(bufs.ws), bufs.ws.numel(),
                             _stream_ptr(stream), ctypes.byref(out), ctypes.byref(ms)))
     return out, float(ms.value)
+
+
+class Server:
+    """Continuous-batching walk server (C ABI trw_server_*): the graph and tables stay
+    resident; requests of different sizes are admitted as memory frees up and share the
+    device tick by tick.  Outputs are device tensors allocated here (or host arrays with
+    host=True) and stay referenced until their completion is polled."""
+
+    def __init__(self, graph: Graph, alias: Optional[Table] = None, adjacency: Optional[Table] = None,
+                 pool_bytes: int = 1 << 30, max_slots: int = 0, max_requests: int = 0, steps_per_tick: int = 0,
+                 use_hipgraph: bool = True):
+        self.graph = graph
+        cfg = trw_server_cfg()
+        cfg.max_slots, cfg.max_requests, cfg.steps_per_tick = max_slots, max_requests, steps_per_tick
+        cfg.use_hipgraph = 1 if use_hipgraph else 0
+        nbytes = ctypes.c_size_t(0)
+        check(_abi.trw_server_arena_bytes(ctypes.byref(cfg), pool_bytes, ctypes.byref(nbytes)))
+        self.arena = torch.empty(int(nbytes.value), dtype=torch.uint8, device=graph.device)
+        torch.cuda.synchronize()
+        h = ctypes.c_void_p()
+        check(_abi.trw_server_create(graph.handle, alias.handle if alias else None,
+                                     adjacency.handle if adjacency else None, ctypes.byref(cfg),
+                                     _dptr(self.arena), int(nbytes.value), ctypes.byref(h)))
+        self.handle = h
+        self._live = {}
+
+    def submit(self, p: trw_walk_params, sources, qid_base: int = 0, host: bool = False, stride: int = 0) -> int:
+        """Queue len(sources) queries; returns the request id."""
+        nq = len(sources)
+        stride = stride or ((p.max_len + 1 + 7) // 8 * 8)
+        r = trw_request()
+        r.params = p
+        r.nq = nq
+        r.qid_base = qid_base
+        r.path_stride = stride
+        if host:
+            src = np.ascontiguousarray(sources, dtype=np.int32)
+            out = (np.empty((nq, stride), np.int32), np.empty(nq, np.uint32), np.empty(nq, np.uint8))
+            ptr = lambda a: ctypes.c_void_p(a.ctypes.data)
+            r.flags = TRW_REQ_HOST
+        else:
+            src = sources if isinstance(sources, torch.Tensor) else torch.from_numpy(
+                np.ascontiguousarray(sources, dtype=np.int32)).to(self.graph.device)
+            out = (torch.empty((nq, stride), dtype=torch.int32, device=self.graph.device),
+                   torch.empty(nq, dtype=torch.int32, device=self.graph.device),
+                   torch.empty(nq, dtype=torch.uint8, device=self.graph.device))
+            ptr = lambda a: ctypes.c_void_p(a.data_ptr())
+            torch.cuda.current_stream().synchronize()      # sources / outputs ready before the server's stream reads them
+        r.sources = ptr(src)
+        r.paths, r.lengths, r.status = ptr(out[0]), ptr(out[1]), ptr(out[2])
+        rid = ctypes.c_uint64(0)
+        check(_abi.trw_server_submit(self.handle, ctypes.byref(r), ctypes.byref(rid)))
+        self._live[int(rid.value)] = (src, out)
+        return int(rid.value)
+
+    def cancel(self, request_id: int) -> None:
+        check(_abi.trw_server_cancel(self.handle, request_id))
+
+    def poll(self, max_n: int = 256, timeout_ms: int = 0):
+        """Completed requests: list of dicts with request_id, status, times and the outputs."""
+        buf = (trw_completion * max_n)()
+        n = ctypes.c_uint32(0)
+        st = _abi.trw_server_poll(self.handle, buf, max_n, ctypes.byref(n), timeout_ms)
+        if st not in (0, TRW_E_TIMEOUT):
+            check(st)
+        res = []
+        for i in range(n.value):
+            c = buf[i]
+            src, out = self._live.pop(int(c.request_id))
+            res.append(dict(request_id=int(c.request_id), status=int(c.status), nq=int(c.nq),
+                            t_submit_ns=int(c.t_submit_ns), t_admit_ns=int(c.t_admit_ns), t_done_ns=int(c.t_done_ns),
+                            paths=out[0], lengths=out[1], status_codes=out[2]))
+        return res
+
+    def stats(self) -> dict:
+        st = trw_server_stats()
+        check(_abi.trw_server_stats_get(self.handle, ctypes.byref(st)))
+        return st.as_dict()
+
+    def close(self):
+        if self.handle:
+            _abi.trw_server_destroy(self.handle)
+            self.handle = None
+            self._live = {}
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

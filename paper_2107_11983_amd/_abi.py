@@ -39,6 +39,38 @@ class trw_tuning(ctypes.Structure):
         return {k: int(getattr(self, k)) for k, _ in self._fields_ if k != "reserved"}
 
 
+class trw_server_cfg(ctypes.Structure):
+    _fields_ = [("max_slots", ctypes.c_uint32), ("max_requests", ctypes.c_uint32),
+                ("steps_per_tick", ctypes.c_uint32), ("use_hipgraph", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 4)]
+
+
+TRW_REQ_HOST = 1
+
+
+class trw_request(ctypes.Structure):
+    _fields_ = [("params", trw_walk_params), ("sources", ctypes.c_void_p), ("nq", ctypes.c_uint32),
+                ("flags", ctypes.c_uint32), ("qid_base", ctypes.c_uint64), ("paths", ctypes.c_void_p),
+                ("path_stride", ctypes.c_uint64), ("lengths", ctypes.c_void_p), ("status", ctypes.c_void_p),
+                ("user", ctypes.c_void_p)]
+
+
+class trw_completion(ctypes.Structure):
+    _fields_ = [("request_id", ctypes.c_uint64), ("status", ctypes.c_int32), ("nq", ctypes.c_uint32),
+                ("user", ctypes.c_void_p), ("t_submit_ns", ctypes.c_uint64), ("t_admit_ns", ctypes.c_uint64),
+                ("t_done_ns", ctypes.c_uint64)]
+
+
+class trw_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("cancelled", ctypes.c_uint64),
+                ("rejected", ctypes.c_uint64), ("ticks", ctypes.c_uint64), ("moves", ctypes.c_uint64),
+                ("active", ctypes.c_uint32), ("waiting", ctypes.c_uint32), ("pool_bytes", ctypes.c_uint64),
+                ("pool_bytes_used", ctypes.c_uint64)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
 class TrwError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
@@ -75,6 +107,14 @@ _SIGS = {
     "trw_adjacency_index_build": (_st, [_P, _P, _sz, _P, _PP]),
     "trw_label_index_bytes": (_st, [_P, _u32, ctypes.POINTER(_sz)]),
     "trw_label_index_build": (_st, [_P, _u32, _P, _sz, _P, _PP]),
+    "trw_server_arena_bytes": (_st, [ctypes.POINTER(trw_server_cfg), _sz, ctypes.POINTER(_sz)]),
+    "trw_server_create": (_st, [_P, _P, _P, ctypes.POINTER(trw_server_cfg), _P, _sz, _PP]),
+    "trw_server_request_bytes": (_st, [_P, ctypes.POINTER(trw_request), ctypes.POINTER(_sz)]),
+    "trw_server_submit": (_st, [_P, ctypes.POINTER(trw_request), ctypes.POINTER(_u64)]),
+    "trw_server_cancel": (_st, [_P, _u64]),
+    "trw_server_poll": (_st, [_P, ctypes.POINTER(trw_completion), _u32, ctypes.POINTER(_u32), _u32]),
+    "trw_server_stats_get": (_st, [_P, ctypes.POINTER(trw_server_stats)]),
+    "trw_server_destroy": (_st, [_P]),
     # measurement probe (include/trw_probe.h)
     "trw_probe_fill": (ctypes.c_int, [_P, _u64, _u32, _P]),
     "trw_probe_gather": (ctypes.c_int, [_P, _u64, _u32, _u32, _u32, ctypes.c_int, _u32, _u32, _P, _P]),
@@ -115,5 +155,13 @@ trw_adjacency_index_bytes = lib.trw_adjacency_index_bytes
 trw_adjacency_index_build = lib.trw_adjacency_index_build
 trw_label_index_bytes = lib.trw_label_index_bytes
 trw_label_index_build = lib.trw_label_index_build
+trw_server_arena_bytes = lib.trw_server_arena_bytes
+trw_server_create = lib.trw_server_create
+trw_server_request_bytes = lib.trw_server_request_bytes
+trw_server_submit = lib.trw_server_submit
+trw_server_cancel = lib.trw_server_cancel
+trw_server_poll = lib.trw_server_poll
+trw_server_stats_get = lib.trw_server_stats_get
+trw_server_destroy = lib.trw_server_destroy
 trw_probe_fill = lib.trw_probe_fill
 trw_probe_gather = lib.trw_probe_gather

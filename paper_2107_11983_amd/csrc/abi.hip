@@ -23,8 +23,6 @@ struct trw_table_s {
     uint32_t nlab;      // label index: number of labels L
 };
 
-static constexpr uint32_t kLabelIndexKind = 0x100;
-static constexpr uint32_t kAdjacencyKind = 0x101;
 
 static size_t label_index_loff_bytes(const trw::GraphDev &g, uint32_t nlab) {
     const size_t b = sizeof(int32_t) * (size_t)g.n * (nlab + 1);
@@ -34,6 +32,15 @@ static size_t label_index_loff_bytes(const trw::GraphDev &g, uint32_t nlab) {
 namespace trw {
 
 __global__ void k_zero_first(unsigned long long *p) { *p = 0; }
+
+const GraphDev &graph_dev(trw_graph g) { return g->dev; }
+
+bool table_view(trw_table t, uint32_t kind, const void **buf, trw_graph *graph) {
+    if (!t || t->sampler != kind) return false;
+    *buf = t->buf;
+    *graph = t->graph;
+    return true;
+}
 
 static thread_local std::string g_last_error;
 

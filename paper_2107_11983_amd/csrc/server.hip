@@ -1,0 +1,627 @@
+// Serving: a resident graph and tables, a fixed pool of walker slots on the
+// device, and a host thread that admits requests by memory, publishes their
+// queries in chunks and replays the tick graph while anything is in flight.
+//
+// Memory: one caller-provided arena holds the fixed device state (request
+// descriptors, chunk ring, counters, walker slots) followed by a pool from
+// which every admitted request gets its input copy and output rows.  A
+// request waits (first come, first served) until a descriptor slot and pool
+// space are free; one that could never fit is refused at submit.
+//
+// Per tick the thread (1) admits what fits, copying sources, descriptors and
+// ring chunks to the device, (2) launches the tick (a captured graph), (3)
+// reads the per-request completion counters back, and (4) copies the outputs
+// of finished requests to their destinations and releases their memory.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "serve_internal.hpp"
+#include "trw_internal.hpp"
+
+namespace trw {
+
+__global__ void k_fill_bytes(uint32_t *p, size_t n_words, uint32_t v) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_words; i += stride) p[i] = v;
+}
+
+namespace {
+
+constexpr size_t kA = 256;
+inline size_t align_up(size_t x) { return (x + kA - 1) / kA * kA; }
+
+uint64_t now_ns() {
+    return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+// First-fit allocator over [0, size) with coalescing of free ranges.
+class RangeAllocator {
+  public:
+    explicit RangeAllocator(size_t size) : size_(size) { free_[0] = size; }
+    bool alloc(size_t bytes, size_t *off) {
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                *off = it->first;
+                const size_t rest = it->second - bytes;
+                const size_t start = it->first + bytes;
+                free_.erase(it);
+                if (rest) free_[start] = rest;
+                used_ += bytes;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes) {
+        used_ -= bytes;
+        auto it = free_.emplace(off, bytes).first;
+        auto next = std::next(it);
+        if (next != free_.end() && it->first + it->second == next->first) {
+            it->second += next->second;
+            free_.erase(next);
+        }
+        if (it != free_.begin()) {
+            auto prev = std::prev(it);
+            if (prev->first + prev->second == it->first) {
+                prev->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    size_t used() const { return used_; }
+    size_t size() const { return size_; }
+
+  private:
+    size_t size_;
+    size_t used_ = 0;
+    std::map<size_t, size_t> free_;
+};
+
+struct Layout {
+    size_t reqs, ring, counters, done, slots, waves, pool, fixed;
+};
+
+Layout layout(uint32_t slots, uint32_t max_reqs, uint32_t ring) {
+    Layout l{};
+    size_t o = 0;
+    l.reqs = o; o = align_up(o + sizeof(ReqDesc) * max_reqs);
+    l.ring = o; o = align_up(o + sizeof(Chunk) * ring);
+    l.counters = o; o = align_up(o + 3 * sizeof(unsigned long long));   // head, tail, moves
+    l.done = o; o = align_up(o + sizeof(uint32_t) * max_reqs);
+    l.slots = o; o = align_up(o + sizeof(SlotState) * slots);
+    l.waves = o; o = align_up(o + sizeof(WaveState) * (slots / 64));
+    l.pool = o;
+    l.fixed = o;
+    return l;
+}
+
+struct Pending {
+    uint64_t id;
+    trw_request req;
+    uint64_t t_submit;
+    size_t bytes;
+};
+
+struct Active {
+    uint64_t id;
+    trw_request req;
+    uint64_t t_submit, t_admit;
+    size_t pool_off, pool_bytes;
+    uint32_t slot;
+    uint64_t stride;
+    bool finishing = false;
+    bool cancel_sent = false;
+    bool cancelled = false;
+    hipEvent_t copied = nullptr;
+};
+
+}  // namespace
+}  // namespace trw
+
+using namespace trw;
+
+struct trw_server_s {
+    // configuration
+    GraphDev g;
+    TableDev t;
+    uint32_t slots, max_reqs, ring, steps;
+    bool use_graph;
+    int device;
+    // device memory
+    char *arena;
+    Layout lay;
+    ServeDev dev;
+    RangeAllocator pool;
+    // host staging (pinned)
+    ReqDesc *h_desc = nullptr;
+    Chunk *h_ring = nullptr;
+    unsigned long long *h_tail = nullptr;
+    uint32_t *h_done = nullptr;              // max_reqs counters followed by the moves counter
+    hipStream_t stream = nullptr;
+    hipEvent_t tick_done = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    // scheduling state (guarded by mu)
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Pending> waiting;
+    std::vector<uint64_t> cancel_requests;
+    std::deque<trw_completion> completed;
+    bool stopping = false;
+    uint64_t next_id = 1;
+    trw_server_stats stats{};
+    // owned by the worker thread
+    std::vector<Active> active;
+    std::vector<uint32_t> free_slots;
+    unsigned long long tail = 0;
+    std::thread worker;
+    std::string fatal;
+
+    trw_server_s(size_t pool_bytes) : pool(pool_bytes) {}
+};
+
+namespace trw {
+namespace {
+
+trw_status sfail(trw_status st, const std::string &m) {
+    set_error(m);
+    return st;
+}
+
+size_t request_pool_bytes(const trw_request &r) {
+    const uint64_t stride = ((uint64_t)r.params.max_len + 1 + 7) / 8 * 8;
+    return align_up(sizeof(int32_t) * (size_t)r.nq) + align_up(sizeof(int32_t) * stride * r.nq) +
+           align_up(sizeof(uint32_t) * (size_t)r.nq) + align_up((size_t)r.nq);
+}
+
+trw_status check_request(const trw_server_s *s, const trw_request *r) {
+    if (!r) return sfail(TRW_E_INVALID, "request is NULL");
+    const trw_walk_params &p = r->params;
+    const bool static_walk = p.algo == TRW_A_DEEPWALK || p.algo == TRW_A_PPR;
+    if (!((static_walk && (p.sampler == TRW_S_NAIVE || p.sampler == TRW_S_ALIAS)) ||
+          (p.algo == TRW_A_NODE2VEC && p.sampler == TRW_S_OREJ)))
+        return sfail(TRW_E_UNSUPPORTED, "served walks: DeepWalk/PPR with NAIVE or ALIAS, Node2Vec with OREJ");
+    if (p.sampler == TRW_S_ALIAS && !s->t.alias) return sfail(TRW_E_INVALID, "server was created without an ALIAS table");
+    if (p.max_len == 0 || p.max_len > 65535) return sfail(TRW_E_INVALID, "max_len must be in 1..65535");
+    if (p.algo == TRW_A_NODE2VEC)
+        for (int i = 0; i < 3; ++i)
+            if (p.n2v_thr_q16[i] == 0 || p.n2v_thr_q16[i] > 65536)
+                return sfail(TRW_E_INVALID, "Node2Vec thresholds must be in 1..65536");
+    if (r->nq == 0) return sfail(TRW_E_INVALID, "nq must be >= 1");
+    if (!r->sources || !r->paths || !r->lengths || !r->status)
+        return sfail(TRW_E_INVALID, "sources / paths / lengths / status is NULL");
+    if (r->path_stride < (uint64_t)p.max_len + 1) return sfail(TRW_E_INVALID, "path_stride < max_len + 1");
+    if ((uint64_t)r->nq / kChunkQueries + 1 > s->ring / 2) return sfail(TRW_E_INVALID, "request has too many queries");
+    return TRW_OK;
+}
+
+void server_loop(trw_server_s *s);
+
+}  // namespace
+}  // namespace trw
+
+extern "C" {
+
+trw_status trw_server_arena_bytes(const trw_server_cfg *cfg, size_t pool_bytes, size_t *bytes) {
+    if (!cfg || !bytes) return sfail(TRW_E_INVALID, "cfg / bytes is NULL");
+    const DeviceInfo &di = device_info();
+    const uint32_t slots = cfg->max_slots ? cfg->max_slots : (uint32_t)di.num_cus * 512;
+    const uint32_t reqs = cfg->max_requests ? cfg->max_requests : 1024;
+    if (slots % kServeBlock) return sfail(TRW_E_INVALID, "max_slots must be a multiple of 256");
+    *bytes = layout(slots, reqs, 1u << 20).fixed + align_up(pool_bytes);
+    return TRW_OK;
+}
+
+trw_status trw_server_create(trw_graph g, trw_table alias, trw_table adjacency, const trw_server_cfg *cfg,
+                             void *d_arena, size_t arena_bytes, trw_server *out);
+trw_status trw_server_destroy(trw_server s);
+
+}  // extern "C"
+
+extern "C" trw_status trw_server_create(trw_graph g, trw_table alias, trw_table adjacency, const trw_server_cfg *cfg,
+                                        void *d_arena, size_t arena_bytes, trw_server *out) {
+    if (!g || !cfg || !out) return sfail(TRW_E_INVALID, "graph / cfg / out is NULL");
+    const DeviceInfo &di = device_info();
+    const uint32_t slots = cfg->max_slots ? cfg->max_slots : (uint32_t)di.num_cus * 512;
+    const uint32_t reqs = cfg->max_requests ? cfg->max_requests : 1024;
+    const uint32_t steps = cfg->steps_per_tick ? cfg->steps_per_tick : 32;
+    if (slots % kServeBlock || slots > (1u << 24)) return sfail(TRW_E_INVALID, "max_slots must be a multiple of 256, <= 2^24");
+    if (reqs > 65536) return sfail(TRW_E_INVALID, "max_requests must be <= 65536");
+    const uint32_t ring = 1u << 20;
+    const Layout lay = layout(slots, reqs, ring);
+    if (!d_arena || (reinterpret_cast<uintptr_t>(d_arena) & 255)) return sfail(TRW_E_INVALID, "arena NULL or not 256-byte aligned");
+    if (arena_bytes < lay.fixed + kA) return sfail(TRW_E_INVALID, "arena smaller than the fixed server state");
+    TableDev t{nullptr, nullptr, nullptr, nullptr, 0, nullptr};
+    const void *buf = nullptr;
+    trw_graph tg = nullptr;
+    if (alias) {
+        if (!table_view(alias, TRW_S_ALIAS, &buf, &tg) || tg != g)
+            return sfail(TRW_E_INVALID, "alias is not an ALIAS table of this graph");
+        t.alias = static_cast<const uint4 *>(buf);
+    }
+    if (adjacency) {
+        if (!table_view(adjacency, kAdjacencyKind, &buf, &tg) || tg != g)
+            return sfail(TRW_E_INVALID, "adjacency is not an adjacency index of this graph");
+        t.adj = static_cast<const uint4 *>(buf);
+    }
+    auto *s = new (std::nothrow) trw_server_s(arena_bytes - lay.fixed);
+    if (!s) return sfail(TRW_E_INVALID, "out of host memory");
+    s->g = graph_dev(g);
+    s->t = t;
+    s->slots = slots; s->max_reqs = reqs; s->ring = ring; s->steps = steps;
+    s->use_graph = cfg->use_hipgraph != 0;
+    s->device = di.device;
+    s->arena = static_cast<char *>(d_arena);
+    s->lay = lay;
+    char *a = s->arena;
+    s->dev.reqs = reinterpret_cast<ReqDesc *>(a + lay.reqs);
+    s->dev.ring = reinterpret_cast<const Chunk *>(a + lay.ring);
+    s->dev.ring_size = ring;
+    auto *ctr = reinterpret_cast<unsigned long long *>(a + lay.counters);
+    s->dev.head = ctr;
+    s->dev.tail = ctr + 1;
+    s->dev.moves = ctr + 2;
+    s->dev.done = reinterpret_cast<uint32_t *>(a + lay.done);
+    s->dev.slots = reinterpret_cast<SlotState *>(a + lay.slots);
+    s->dev.waves = reinterpret_cast<WaveState *>(a + lay.waves);
+
+    hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->tick_done, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_desc, sizeof(ReqDesc) * reqs, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_ring, sizeof(Chunk) * ring, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_tail, sizeof(unsigned long long), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_done, sizeof(uint32_t) * reqs + 8, hipHostMallocDefault);
+    if (e == hipSuccess) {
+        // zero the counters, descriptors and waves; mark every slot free (0xFF bytes)
+        auto fill = [&](size_t off, size_t bytes, uint32_t v) {
+            hipLaunchKernelGGL(k_fill_bytes, dim3(1024), dim3(256), 0, s->stream,
+                               reinterpret_cast<uint32_t *>(a + off), bytes / 4, v);
+        };
+        fill(lay.reqs, lay.slots - lay.reqs, 0u);
+        fill(lay.slots, lay.waves - lay.slots, 0xFFFFFFFFu);
+        fill(lay.waves, lay.pool - lay.waves, 0u);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess && s->use_graph) {
+        e = hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            hipError_t le = launch_serve_tick(s->g, s->t, s->dev, s->steps, s->slots / kServeBlock, s->stream);
+            e = hipStreamEndCapture(s->stream, &s->graph);
+            if (e == hipSuccess) e = le;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&s->graph_exec, s->graph, nullptr, nullptr, 0);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) {
+        std::string msg = std::string("server setup: ") + hipGetErrorString(e);
+        trw_server_destroy(s);
+        return sfail(TRW_E_DEVICE, msg);
+    }
+    for (uint32_t i = 0; i < reqs; ++i) s->free_slots.push_back(reqs - 1 - i);
+    s->worker = std::thread([s] { server_loop(s); });
+    *out = s;
+    return TRW_OK;
+}
+
+extern "C" trw_status trw_server_request_bytes(trw_server s, const trw_request *r, size_t *bytes) {
+    if (!s || !bytes) return sfail(TRW_E_INVALID, "server / bytes is NULL");
+    trw_status st = check_request(s, r);
+    if (st != TRW_OK) return st;
+    *bytes = request_pool_bytes(*r);
+    return TRW_OK;
+}
+
+extern "C" trw_status trw_server_submit(trw_server s, const trw_request *r, uint64_t *request_id) {
+    if (!s || !request_id) return sfail(TRW_E_INVALID, "server / request_id is NULL");
+    trw_status st = check_request(s, r);
+    if (st != TRW_OK) return st;
+    const size_t bytes = request_pool_bytes(*r);
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (!s->fatal.empty()) return sfail(TRW_E_DEVICE, s->fatal);
+    if (s->stopping) return sfail(TRW_E_CANCELLED, "server is shutting down");
+    if (bytes > s->pool.size()) {
+        s->stats.rejected++;
+        return sfail(TRW_E_NOMEM_BUDGET, "request needs " + std::to_string(bytes) + " bytes, the pool has " +
+                                             std::to_string(s->pool.size()));
+    }
+    const uint64_t id = s->next_id++;
+    s->waiting.push_back(Pending{id, *r, now_ns(), bytes});
+    s->stats.submitted++;
+    *request_id = id;
+    s->cv_work.notify_one();
+    return TRW_OK;
+}
+
+extern "C" trw_status trw_server_cancel(trw_server s, uint64_t request_id) {
+    if (!s) return sfail(TRW_E_INVALID, "server is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->cancel_requests.push_back(request_id);
+    s->cv_work.notify_one();
+    return TRW_OK;
+}
+
+extern "C" trw_status trw_server_poll(trw_server s, trw_completion *out, uint32_t max, uint32_t *n_out,
+                                      uint32_t timeout_ms) {
+    if (!s || !n_out || (!out && max)) return sfail(TRW_E_INVALID, "server / out / n_out is NULL");
+    std::unique_lock<std::mutex> lk(s->mu);
+    if (s->completed.empty() && timeout_ms)
+        s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms),
+                            [s] { return !s->completed.empty() || !s->fatal.empty(); });
+    uint32_t n = 0;
+    while (n < max && !s->completed.empty()) {
+        out[n++] = s->completed.front();
+        s->completed.pop_front();
+    }
+    *n_out = n;
+    if (!s->fatal.empty() && n == 0) return sfail(TRW_E_DEVICE, s->fatal);
+    if (n == 0 && timeout_ms) return sfail(TRW_E_TIMEOUT, "no request completed in time");
+    return TRW_OK;
+}
+
+extern "C" trw_status trw_server_stats_get(trw_server s, trw_server_stats *out) {
+    if (!s || !out) return sfail(TRW_E_INVALID, "server / out is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    *out = s->stats;
+    out->waiting = (uint32_t)s->waiting.size();
+    out->pool_bytes = s->pool.size();
+    return TRW_OK;
+}
+
+extern "C" trw_status trw_server_destroy(trw_server s) {
+    if (!s) return TRW_OK;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stopping = true;
+        s->cv_work.notify_all();
+    }
+    if (s->worker.joinable()) s->worker.join();
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    if (s->graph_exec) (void)hipGraphExecDestroy(s->graph_exec);
+    if (s->graph) (void)hipGraphDestroy(s->graph);
+    if (s->tick_done) (void)hipEventDestroy(s->tick_done);
+    for (auto &a : s->active)
+        if (a.copied) (void)hipEventDestroy(a.copied);
+    if (s->h_desc) (void)hipHostFree(s->h_desc);
+    if (s->h_ring) (void)hipHostFree(s->h_ring);
+    if (s->h_tail) (void)hipHostFree(s->h_tail);
+    if (s->h_done) (void)hipHostFree(s->h_done);
+    if (s->stream) (void)hipStreamDestroy(s->stream);
+    delete s;
+    return TRW_OK;
+}
+
+namespace trw {
+namespace {
+
+hipMemcpyKind kind_in(const trw_request &r) { return (r.flags & TRW_REQ_HOST) ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice; }
+hipMemcpyKind kind_out(const trw_request &r) { return (r.flags & TRW_REQ_HOST) ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice; }
+
+void complete(trw_server_s *s, Active &a, int32_t status) {
+    trw_completion c{};
+    c.request_id = a.id;
+    c.status = status;
+    c.nq = a.req.nq;
+    c.user = a.req.user;
+    c.t_submit_ns = a.t_submit;
+    c.t_admit_ns = a.t_admit;
+    c.t_done_ns = now_ns();
+    s->pool.release(a.pool_off, a.pool_bytes);
+    s->free_slots.push_back(a.slot);
+    if (a.copied) (void)hipEventDestroy(a.copied);
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->completed.push_back(c);
+    if (status == TRW_OK) s->stats.completed++; else s->stats.cancelled++;
+    s->stats.active = (uint32_t)s->active.size() - 1;
+    s->cv_done.notify_all();
+}
+
+// Admit waiting requests while a slot and pool space are free (first come, first served).
+hipError_t admit(trw_server_s *s, std::deque<Pending> &incoming) {
+    hipError_t e = hipSuccess;
+    bool any = false;
+    const unsigned long long tail0 = s->tail;
+    while (!incoming.empty() && !s->free_slots.empty()) {
+        Pending &p = incoming.front();
+        size_t off = 0;
+        if (!s->pool.alloc(p.bytes, &off)) break;
+        const uint32_t slot = s->free_slots.back();
+        s->free_slots.pop_back();
+        const trw_request &r = p.req;
+        const uint64_t stride = ((uint64_t)r.params.max_len + 1 + 7) / 8 * 8;
+        char *base = s->arena + s->lay.pool + off;
+        int32_t *src = reinterpret_cast<int32_t *>(base);
+        int32_t *paths = reinterpret_cast<int32_t *>(base + align_up(sizeof(int32_t) * (size_t)r.nq));
+        uint32_t *lengths = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(paths) +
+                                                         align_up(sizeof(int32_t) * stride * r.nq));
+        uint8_t *status = reinterpret_cast<uint8_t *>(reinterpret_cast<char *>(lengths) +
+                                                      align_up(sizeof(uint32_t) * (size_t)r.nq));
+        e = hipMemcpyAsync(src, r.sources, sizeof(int32_t) * r.nq, kind_in(r), s->stream);
+        if (e != hipSuccess) return e;
+        ReqDesc &d = s->h_desc[slot];
+        std::memset(&d, 0, sizeof(d));
+        d.algo = r.params.algo;
+        d.sampler = r.params.sampler;
+        d.max_len = r.params.max_len;
+        d.stop_q32 = r.params.algo == TRW_A_PPR ? r.params.stop_q32 : 0;
+        for (int i = 0; i < 3; ++i) d.thr[i] = r.params.n2v_thr_q16[i];
+        d.seed = r.params.seed;
+        d.qid_base = r.qid_base;
+        d.sources = src;
+        d.paths = paths;
+        d.lengths = lengths;
+        d.status = status;
+        d.stride = stride;
+        d.nq = r.nq;
+        e = hipMemcpyAsync(s->dev.reqs + slot, &d, sizeof(d), hipMemcpyHostToDevice, s->stream);
+        if (e != hipSuccess) return e;
+        // zero this slot's completion counter (a one-word copy from the staging area)
+        s->h_done[slot] = 0;
+        e = hipMemcpyAsync(s->dev.done + slot, s->h_done + slot, sizeof(uint32_t), hipMemcpyHostToDevice, s->stream);
+        if (e != hipSuccess) return e;
+        for (uint32_t b = 0; b < r.nq; b += kChunkQueries) {
+            Chunk &c = s->h_ring[s->tail % s->ring];
+            c.req = slot; c.begin = b; c.end = std::min<uint32_t>(r.nq, b + kChunkQueries); c.pad = 0;
+            s->tail++;
+        }
+        Active a;
+        a.id = p.id; a.req = r; a.t_submit = p.t_submit; a.t_admit = now_ns();
+        a.pool_off = off; a.pool_bytes = p.bytes; a.slot = slot; a.stride = stride;
+        s->active.push_back(a);
+        incoming.pop_front();
+        any = true;
+    }
+    if (!any) return hipSuccess;
+    // copy the new ring entries (they may wrap around), then publish the tail
+    for (unsigned long long i = tail0; i < s->tail;) {
+        const unsigned long long pos = i % s->ring;
+        const unsigned long long n = std::min<unsigned long long>(s->tail - i, s->ring - pos);
+        e = hipMemcpyAsync(const_cast<Chunk *>(s->dev.ring) + pos, s->h_ring + pos, sizeof(Chunk) * n,
+                           hipMemcpyHostToDevice, s->stream);
+        if (e != hipSuccess) return e;
+        i += n;
+    }
+    *s->h_tail = s->tail;
+    return hipMemcpyAsync(const_cast<unsigned long long *>(s->dev.tail), s->h_tail, sizeof(unsigned long long),
+                          hipMemcpyHostToDevice, s->stream);
+}
+
+void server_loop(trw_server_s *s) {
+    (void)hipSetDevice(s->device);
+    std::deque<Pending> incoming;
+    for (;;) {
+        std::vector<uint64_t> cancels;
+        bool stopping;
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            if (s->active.empty() && s->waiting.empty() && incoming.empty() && s->cancel_requests.empty() &&
+                !s->stopping)
+                s->cv_work.wait_for(lk, std::chrono::milliseconds(2));
+            while (!s->waiting.empty()) {
+                incoming.push_back(s->waiting.front());
+                s->waiting.pop_front();
+            }
+            cancels.swap(s->cancel_requests);
+            stopping = s->stopping;
+        }
+        if (stopping) {
+            for (auto &p : incoming) cancels.push_back(p.id);
+            for (auto &a : s->active) cancels.push_back(a.id);
+        }
+        // cancellations: not yet admitted -> done at once; running -> flag the descriptor
+        for (uint64_t id : cancels) {
+            for (auto it = incoming.begin(); it != incoming.end(); ++it) {
+                if (it->id == id) {
+                    trw_completion c{};
+                    c.request_id = id; c.status = TRW_E_CANCELLED; c.nq = it->req.nq; c.user = it->req.user;
+                    c.t_submit_ns = it->t_submit; c.t_done_ns = now_ns();
+                    incoming.erase(it);
+                    std::lock_guard<std::mutex> lk(s->mu);
+                    s->completed.push_back(c);
+                    s->stats.cancelled++;
+                    s->cv_done.notify_all();
+                    break;
+                }
+            }
+            for (auto &a : s->active) {
+                if (a.id == id && !a.cancel_sent && !a.finishing) {
+                    a.cancel_sent = true;
+                    a.cancelled = true;
+                    s->h_desc[a.slot].cancelled = 1;
+                    (void)hipMemcpyAsync(&s->dev.reqs[a.slot].cancelled, &s->h_desc[a.slot].cancelled,
+                                         sizeof(uint32_t), hipMemcpyHostToDevice, s->stream);
+                }
+            }
+        }
+        hipError_t e = hipSuccess;
+        if (!stopping) e = admit(s, incoming);
+        if (e == hipSuccess && !s->active.empty()) {
+            bool running = false;
+            for (auto &a : s->active) running |= !a.finishing;
+            if (running) {
+                e = s->use_graph ? hipGraphLaunch(s->graph_exec, s->stream)
+                                 : launch_serve_tick(s->g, s->t, s->dev, s->steps, s->slots / kServeBlock, s->stream);
+                if (e == hipSuccess)
+                    e = hipMemcpyAsync(s->h_done, s->dev.done, sizeof(uint32_t) * s->max_reqs, hipMemcpyDeviceToHost,
+                                       s->stream);
+                if (e == hipSuccess)
+                    e = hipMemcpyAsync(s->h_done + s->max_reqs, s->dev.moves, sizeof(unsigned long long),
+                                       hipMemcpyDeviceToHost, s->stream);
+                if (e == hipSuccess) e = hipEventRecord(s->tick_done, s->stream);
+                if (e == hipSuccess) e = hipEventSynchronize(s->tick_done);
+                if (e == hipSuccess) {
+                    std::lock_guard<std::mutex> lk(s->mu);
+                    s->stats.ticks++;
+                    unsigned long long mv;
+                    std::memcpy(&mv, s->h_done + s->max_reqs, sizeof(mv));
+                    s->stats.moves = mv;
+                }
+                // requests whose queries are all done: copy their outputs out
+                for (auto &a : s->active) {
+                    if (a.finishing || e != hipSuccess) continue;
+                    if (s->h_done[a.slot] < a.req.nq) continue;
+                    a.finishing = true;
+                    if (a.cancelled) continue;
+                    const trw_request &r = a.req;
+                    char *base = s->arena + s->lay.pool + a.pool_off;
+                    const char *paths = base + align_up(sizeof(int32_t) * (size_t)r.nq);
+                    const char *lengths = paths + align_up(sizeof(int32_t) * a.stride * r.nq);
+                    const char *status = lengths + align_up(sizeof(uint32_t) * (size_t)r.nq);
+                    e = hipMemcpy2DAsync(r.paths, sizeof(int32_t) * r.path_stride, paths, sizeof(int32_t) * a.stride,
+                                         sizeof(int32_t) * ((size_t)r.params.max_len + 1), r.nq, kind_out(r), s->stream);
+                    if (e == hipSuccess)
+                        e = hipMemcpyAsync(r.lengths, lengths, sizeof(uint32_t) * r.nq, kind_out(r), s->stream);
+                    if (e == hipSuccess) e = hipMemcpyAsync(r.status, status, r.nq, kind_out(r), s->stream);
+                    if (e == hipSuccess) e = hipEventCreateWithFlags(&a.copied, hipEventDisableTiming);
+                    if (e == hipSuccess) e = hipEventRecord(a.copied, s->stream);
+                }
+            }
+        }
+        // release requests whose outputs have landed
+        if (e == hipSuccess) {
+            for (size_t i = 0; i < s->active.size();) {
+                Active &a = s->active[i];
+                bool ready = false;
+                if (a.finishing) {
+                    if (a.cancelled) ready = true;
+                    else ready = a.copied && hipEventQuery(a.copied) == hipSuccess;
+                }
+                if (ready) {
+                    complete(s, a, a.cancelled ? TRW_E_CANCELLED : TRW_OK);
+                    s->active.erase(s->active.begin() + i);
+                } else {
+                    ++i;
+                }
+            }
+        }
+        if (e != hipSuccess) {
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->fatal = std::string("server device error: ") + hipGetErrorString(e);
+            s->cv_done.notify_all();
+            return;
+        }
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->stats.active = (uint32_t)s->active.size();
+            s->stats.pool_bytes_used = s->pool.used();
+        }
+        if (stopping && s->active.empty() && incoming.empty()) return;
+        bool copies_only = !s->active.empty();
+        for (auto &a : s->active) copies_only &= a.finishing;
+        if (copies_only) std::this_thread::sleep_for(std::chrono::microseconds(20));
+    }
+}
+
+}  // namespace
+}  // namespace trw

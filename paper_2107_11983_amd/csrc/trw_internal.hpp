@@ -105,4 +105,13 @@ hipError_t launch_walk(const GraphDev &g, const TableDev &t, uint32_t algo, uint
 const DeviceInfo &device_info();
 void set_error(const std::string &msg);
 
+// Table kinds behind a trw_table: the sampler codes for ALIAS / ITS tables,
+// and two index kinds.
+constexpr uint32_t kLabelIndexKind = 0x100;
+constexpr uint32_t kAdjacencyKind = 0x101;
+
+// Accessors for the opaque handles (defined with them in abi.hip).
+const GraphDev &graph_dev(trw_graph g);
+bool table_view(trw_table t, uint32_t kind, const void **buf, trw_graph *graph);
+
 }  // namespace trw

@@ -1,0 +1,135 @@
+// Device pieces shared by the batch walk kernels and the serving tick.
+#pragma once
+
+#include "trw_device.hpp"
+#include "trw_internal.hpp"
+
+namespace trw {
+
+constexpr uint32_t kIdle = 0xFFFFFFFFu;
+
+__device__ __forceinline__ uint32_t wave_total(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// Move of a static walk that reads the adjacency array (NAIVE, ITS).  Returns
+// the next vertex, or -1 when the row has no transition (weights sum to 0).
+// ---------------------------------------------------------------------------
+template <uint32_t SMP>
+__device__ __forceinline__ int32_t static_next(const GraphDev &g, const TableDev &t, int32_t off, uint32_t d,
+                                               const Rand4 &r) {
+    if (SMP == SMP_NAIVE) return g.col[off + scale32(r.r0, d)];
+    // ITS: x uniform in [0, W) from 64 bits, smallest i with x < prefix[i]
+    const uint64_t *__restrict__ p = t.prefix + off;
+    const uint64_t W = p[d - 1];
+    if (W == 0) return -1;
+    const uint64_t x = scale64(r.r0, r.r1, W);
+    uint32_t lo = 0, hi = d - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (x < p[mid]) hi = mid; else lo = mid + 1;
+    }
+    return g.col[off + lo];
+}
+
+// ---------------------------------------------------------------------------
+// Node2Vec move, O-REJ (Sampling Methods: rejection with a user bound p*):
+// throw darts (x, y) with x a uniform edge slot of cur and y = r1 >> 16 until
+// y falls under the Q16 threshold of x's class (x == prev, x adjacent to
+// prev, otherwise; the Node2Vec transition equation).  The adjacency test is
+// a binary search in a sorted row, made only when the dart's height lies
+// between the two thresholds it would choose between.  With the adjacency
+// index a dart also learns x's row, so on a symmetric graph the search can run
+// in the shorter of the two rows (x in N(prev) iff prev in N(x)), and an
+// accepted move needs no row lookup.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool in_row(const int32_t *__restrict__ col, int32_t lo, int32_t hi, int32_t key) {
+    while (lo < hi) {
+        const int32_t mid = lo + ((hi - lo) >> 1);
+        const int32_t c = col[mid];
+        if (c == key) return true;
+        if (c < key) lo = mid + 1; else hi = mid;
+    }
+    return false;
+}
+
+template <bool ADJ>
+__device__ __forceinline__ int32_t n2v_move(const GraphDev &g, const TableDev &t, const WalkDev &a, uint64_t qid,
+                                            uint32_t k, int32_t off, uint32_t d, const Rand4 &r, int32_t prev,
+                                            int32_t poff, int32_t pd, int32_t &noff, int32_t &ndeg) {
+    Rand4 rr = r;
+    for (uint32_t dart = 0;; ++dart) {
+        if (dart > 0) rr = philox(k, dart, qid, a.seed);
+        const uint32_t slot = (uint32_t)off + scale32(rr.r0, d);
+        int32_t x, xo = 0, xd = 0;
+        if (ADJ) {
+            const uint4 e = t.adj[slot];
+            x = (int32_t)e.x; xo = (int32_t)e.y; xd = (int32_t)e.z;
+        } else {
+            x = g.col[slot];
+        }
+        bool accept = (k == 0 || dart + 1 == kMaxDarts);
+        if (!accept) {
+            const uint32_t y = rr.r1 >> 16;
+            if (x == prev) {
+                accept = y < a.thr[0];
+            } else if (y < min(a.thr[1], a.thr[2])) {
+                accept = true;          // under both thresholds: the adjacency test cannot change it
+            } else if (y >= max(a.thr[1], a.thr[2])) {
+                accept = false;         // over both
+            } else {
+                const bool adjacent = (ADJ && g.symmetric && xd < pd) ? in_row(g.col, xo, xo + xd, prev)
+                                                                      : in_row(g.col, poff, poff + pd, x);
+                accept = y < (adjacent ? a.thr[1] : a.thr[2]);
+            }
+        }
+        if (accept) {
+            noff = xo; ndeg = xd;
+            return x;
+        }
+    }
+}
+
+// ALIAS move from the 32-byte entry of column j: next vertex and its row range.
+__device__ __forceinline__ int32_t alias_pick(const uint4 &e0, const uint4 &e1, uint32_t r1, int32_t &off,
+                                              int32_t &deg) {
+    const bool first = r1 < e0.x;
+    off = (int32_t)(first ? e1.x : e1.z);
+    deg = (int32_t)(first ? e1.y : e1.w);
+    return (int32_t)(first ? e0.y : e0.z);                  // -1 marks a row of zero weight
+}
+
+// ---------------------------------------------------------------------------
+// Path writer: up to 4 pending entries per walker, flushed as one 16-byte
+// store when they end on a 16-byte boundary, else entry by entry at the end.
+// ---------------------------------------------------------------------------
+struct PathBuf {
+    int32_t *p;      // address of the first pending entry
+    uint32_t n;      // pending entries
+    int32_t b0, b1, b2, b3;
+
+    __device__ __forceinline__ void start(int32_t *row) { p = row; n = 0; }
+
+    __device__ __forceinline__ void flush() {
+        if (n == 4) {
+            *reinterpret_cast<int4 *>(p) = make_int4(b0, b1, b2, b3);
+        } else {
+            if (n > 0) p[0] = b0;
+            if (n > 1) p[1] = b1;
+            if (n > 2) p[2] = b2;
+        }
+        p += n;
+        n = 0;
+    }
+
+    __device__ __forceinline__ void push(int32_t v) {
+        if (n == 0) b0 = v; else if (n == 1) b1 = v; else if (n == 2) b2 = v; else b3 = v;
+        ++n;
+        if (((reinterpret_cast<uintptr_t>(p + n)) & 15u) == 0) flush();
+    }
+};
+
+}  // namespace trw

@@ -1,0 +1,211 @@
+"""The continuous-batching server through the C ABI (trw_server_*).
+
+Each request's result must be bit-identical to the same request walked alone,
+in any mix of concurrent requests, through trw_walk, and by the oracle;
+cancellation and memory admission must leave other requests untouched.
+"""
+import sys
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+trw = None
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def env():
+    global trw
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2107_11983_amd as mod
+    trw = mod
+    torch.cuda.set_device(0)
+    g = synth.rmat(12, 16, True, 0x5E4E)
+    synth.attach_attrs(g, 0x5E4E ^ 1, weights=True)
+    G = trw.Graph(g.row_ptr, g.col, g.weight, symmetric=True)
+    assert G.validate() == 0
+    alias = G.table("alias")
+    adj = G.adjacency_index()
+    thr, al = oracle.alias_build(g.row_ptr, g.weight)
+    torch.cuda.synchronize()
+    return dict(g=g, G=G, alias=alias, adj=adj, orc_alias=(thr, al))
+
+
+SERVED = [("deepwalk", "alias", 80), ("ppr", "alias", 256), ("node2vec", "orej", 80),
+          ("deepwalk", "naive", 40), ("ppr", "naive", 64)]
+
+
+def params(algo, sampler, max_len, seed):
+    kw = {}
+    if algo == "ppr":
+        kw["stop_q32"] = trw.stop_threshold(0.2)
+    if algo == "node2vec":
+        kw["n2v_thr_q16"] = trw.n2v_thresholds(2.0, 0.5)
+    return trw.make_params(algo, sampler, max_len, seed, **kw)
+
+
+def wait_all(server, ids, timeout_s=60.0):
+    got = {}
+    t0 = time.time()
+    while len(got) < len(ids):
+        assert time.time() - t0 < timeout_s, f"requests did not complete: {set(ids) - set(got)}"
+        for c in server.poll(256, timeout_ms=50):
+            got[c["request_id"]] = c
+    return got
+
+
+def to_np(c):
+    P = c["paths"].cpu().numpy() if isinstance(c["paths"], torch.Tensor) else c["paths"]
+    L = c["lengths"].cpu().numpy().view(np.uint32) if isinstance(c["lengths"], torch.Tensor) else c["lengths"]
+    S = c["status_codes"].cpu().numpy() if isinstance(c["status_codes"], torch.Tensor) else c["status_codes"]
+    return P, L, S
+
+
+def same(a, b, max_len):
+    Pa, La, Sa = a
+    Pb, Lb, Sb = b
+    assert np.array_equal(La, Lb) and np.array_equal(Sa, Sb)
+    mask = np.arange(max_len + 1)[None, :] <= La[:, None]
+    assert np.array_equal(Pa[:, :max_len + 1][mask], Pb[:, :max_len + 1][mask])
+
+
+def make_server(env, **kw):
+    cfg = dict(pool_bytes=256 << 20, max_slots=256 * 64, steps_per_tick=16)
+    cfg.update(kw)
+    return trw.Server(env["G"], env["alias"], env["adj"], **cfg)
+
+
+def test_served_equals_walk_and_oracle(env):
+    g = env["g"]
+    srv = make_server(env)
+    src = synth.sources(777, g.n, 31)
+    for algo, sampler, max_len in SERVED:
+        log(f"  served {algo}/{sampler}")
+        p = params(algo, sampler, max_len, 99)
+        rid = srv.submit(p, src, qid_base=5000)
+        c = wait_all(srv, [rid])[rid]
+        assert c["status"] == 0
+        got = to_np(c)
+        table = env["alias"] if sampler == "alias" else None
+        P, L, S = trw.walk(env["G"], table, p, torch.from_numpy(src).cuda(), qid_base=5000)
+        torch.cuda.synchronize()
+        same(got, (P.cpu().numpy(), L.cpu().numpy().view(np.uint32), S.cpu().numpy()), max_len)
+        kw = {}
+        if sampler == "alias":
+            kw = dict(thr=env["orc_alias"][0], alias=env["orc_alias"][1])
+        op = oracle.WalkParams(oracle.ALGOS[algo], oracle.SAMPLERS[sampler], max_len, 99,
+                               stop_q32=p.stop_q32, n2v_thr_q16=tuple(p.n2v_thr_q16))
+        ref = oracle.walk(g.row_ptr, g.col, op, src, qid_base=5000, **kw)
+        same(got, (ref.paths, ref.lengths, ref.status), max_len)
+    srv.close()
+
+
+def _mix(g, n, seed):
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for i in range(n):
+        algo, sampler, max_len = SERVED[int(rng.integers(0, len(SERVED)))]
+        nq = int(rng.integers(1, 400))
+        reqs.append((algo, sampler, max_len, synth.sources(nq, g.n, seed * 1000 + i), 1000 * i, 7 + i))
+    return reqs
+
+
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_same_alone_and_in_mix(env, use_graph):
+    g = env["g"]
+    reqs = _mix(g, 30, 5)
+    srv = make_server(env, use_hipgraph=use_graph)
+    alone = []
+    for algo, sampler, max_len, src, qb, seed in reqs:
+        rid = srv.submit(params(algo, sampler, max_len, seed), src, qid_base=qb)
+        alone.append(to_np(wait_all(srv, [rid])[rid]))
+    ids = [srv.submit(params(a, s, m, seed), src, qid_base=qb) for a, s, m, src, qb, seed in reqs]
+    got = wait_all(srv, ids)
+    st = srv.stats()
+    log(f"  stats {st}")
+    for (algo, sampler, max_len, *_), rid, ref in zip(reqs, ids, alone):
+        assert got[rid]["status"] == 0
+        same(to_np(got[rid]), ref, max_len)
+    assert st["completed"] == 60 and st["active"] == 0
+    srv.close()
+
+
+def test_cancel_leaves_others_intact(env):
+    g = env["g"]
+    srv = make_server(env)
+    small = _mix(g, 6, 9)
+    alone = []
+    for algo, sampler, max_len, src, qb, seed in small:
+        rid = srv.submit(params(algo, sampler, max_len, seed), src, qid_base=qb)
+        alone.append(to_np(wait_all(srv, [rid])[rid]))
+    big = srv.submit(params("node2vec", "orej", 80, 3), synth.sources(60000, g.n, 4), qid_base=10 ** 9)
+    ids = [srv.submit(params(a, s, m, seed), src, qid_base=qb) for a, s, m, src, qb, seed in small]
+    srv.cancel(big)
+    got = wait_all(srv, ids + [big])
+    assert got[big]["status"] == trw.TRW_E_CANCELLED
+    for (algo, sampler, max_len, *_), rid, ref in zip(small, ids, alone):
+        assert got[rid]["status"] == 0
+        same(to_np(got[rid]), ref, max_len)
+    srv.close()
+
+
+def test_memory_admission(env):
+    g = env["g"]
+    p = params("deepwalk", "alias", 80, 1)
+    srv = make_server(env, pool_bytes=4 << 20)
+    with pytest.raises(trw.TrwError) as ei:
+        srv.submit(p, synth.sources(20000, g.n, 1))           # 20000 * 88 * 4 bytes > 4 MiB
+    assert ei.value.status == trw.TRW_E_NOMEM_BUDGET
+    # each fits alone but no two fit together: admitted one after another
+    reqs = [synth.sources(7000, g.n, 10 + i) for i in range(4)]
+    ids = [srv.submit(p, s, qid_base=i << 20) for i, s in enumerate(reqs)]
+    got = wait_all(srv, ids)
+    for i, (s, rid) in enumerate(zip(reqs, ids)):
+        P, L, S = trw.walk(env["G"], env["alias"], p, torch.from_numpy(s).cuda(), qid_base=i << 20)
+        torch.cuda.synchronize()
+        same(to_np(got[rid]), (P.cpu().numpy(), L.cpu().numpy().view(np.uint32), S.cpu().numpy()), 80)
+        assert got[rid]["t_admit_ns"] >= got[rid]["t_submit_ns"]
+    admits = sorted(got[r]["t_admit_ns"] for r in ids)
+    dones = sorted(got[r]["t_done_ns"] for r in ids)
+    assert all(admits[i + 1] >= dones[i] - 10 ** 9 for i in range(3))
+    srv.close()
+
+
+def test_host_buffers_and_bad_sources(env):
+    g = env["g"]
+    srv = make_server(env)
+    src = np.array([0, -5, g.n, 17, 4095], np.int32)
+    p = params("ppr", "alias", 256, 11)
+    rid = srv.submit(p, src, host=True)
+    c = wait_all(srv, [rid])[rid]
+    P, L, S = c["paths"], c["lengths"], c["status_codes"]
+    assert list(S[[1, 2]]) == [trw.TRW_ST_BAD_SOURCE] * 2 and list(L[[1, 2]]) == [0, 0]
+    Pd, Ld, Sd = trw.walk(env["G"], env["alias"], p, torch.from_numpy(src).cuda())
+    torch.cuda.synchronize()
+    Ld, Sd = Ld.cpu().numpy().view(np.uint32), Sd.cpu().numpy()
+    assert np.array_equal(L, Ld) and np.array_equal(S, Sd)
+    for i in (0, 3, 4):
+        assert np.array_equal(P[i, :L[i] + 1], Pd.cpu().numpy()[i, :L[i] + 1])
+    srv.close()
+
+
+def test_rejects_unsupported(env):
+    srv = make_server(env)
+    with pytest.raises(trw.TrwError) as ei:
+        srv.submit(trw.make_params("metapath", "its", 10, 1, schema=(1,)), np.zeros(4, np.int32))
+    assert ei.value.status == trw._abi.TRW_E_UNSUPPORTED
+    srv.close()
+    noalias = trw.Server(env["G"], None, None, pool_bytes=1 << 20, max_slots=256)
+    with pytest.raises(trw.TrwError):
+        noalias.submit(params("deepwalk", "alias", 5, 1), np.zeros(4, np.int32))
+    noalias.close()
