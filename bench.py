@@ -81,6 +81,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-probe", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle CPU time")
+    ap.add_argument("--serve-requests", type=int, default=10000, help="measured requests (served workload)")
+    ap.add_argument("--serve-scale", type=int, default=0, help="override the served graph's scale (tests)")
+    ap.add_argument("--serve-slots-per-cu", type=int, default=2048)
+    ap.add_argument("--serve-steps", type=int, default=32, help="moves per walker slot per tick")
     ap.add_argument("--profile-pass", action="store_true",
                     help="short run for counter collection: a 1 GiB copy (calibration) then the walk only")
     args = ap.parse_args()
@@ -105,6 +109,8 @@ def main():
     log(f"device {props.name} cus={props.multi_processor_count}")
 
     wl = synth.WORKLOADS[args.workload]
+    if wl.algo == "mixed":
+        return bench_served(args, wl, np, torch, synth, trw, props)
     sampler = args.sampler or {"metapath": "its+index", "node2vec": "orej+adj",
                                "deepwalk": "naive+adj"}.get(wl.algo, wl.samplers[0])
     t0 = time.time()
@@ -273,6 +279,112 @@ def main():
         "preprocess_ms": {k: round(v, 3) for k, v in pre_ms.items()},
         "variants": variants,
         "gather_ceiling": gather,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_served(args, wl, np, torch, synth, trw, props):
+    """Served mixed workload: Poisson arrivals of requests of 1..4096 queries, each DeepWalk
+    (80 moves, ALIAS), PPR (stop 0.2, ALIAS) or Node2Vec (p=2, q=0.5, 80 moves), on a resident
+    weighted symmetric R-MAT graph; continuous batching with memory admission and graph-captured
+    ticks.  Reports p50/p99 request latency at 0.7x the saturated request rate, and steps/s."""
+    import ctypes
+    from paper_2107_11983_amd import _abi
+    t0 = time.time()
+    g = synth.make_graph(wl, scale=args.serve_scale or None)
+    log(f"graph {wl.name}: n={g.n} m={g.m} dmax={int(g.degrees().max())} ({time.time() - t0:.1f}s)")
+    G = trw.Graph(g.row_ptr, g.col, g.weight, symmetric=True, device="cuda:0")
+    assert G.validate() == 0
+    pre = {}
+    for name, fn in (("alias", lambda: G.table("alias")), ("adjacency", lambda: G.adjacency_index())):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        tab = fn()
+        e1.record()
+        torch.cuda.synchronize()
+        pre[name] = round(e0.elapsed_time(e1), 3)
+        if name == "alias":
+            alias = tab
+        else:
+            adj = tab
+    log(f"tables {pre}")
+    n_sat, n_warm, n_meas = 2000, 500, args.serve_requests
+    N = n_sat + n_warm + n_meas
+    sizes = 1 + synth.uniform_u32(N, 4096, wl.walk_seed ^ 0x5153).astype(np.int64)
+    kinds = synth.uniform_u32(N, 3, wl.walk_seed ^ 0xA160)
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    d_src = torch.from_numpy(synth.sources(int(offs[-1]), g.n, wl.src_seed)).cuda()
+    algo_p = [trw.make_params("deepwalk", "alias", 80, wl.walk_seed),
+              trw.make_params("ppr", "alias", 256, wl.walk_seed, stop_q32=trw.stop_threshold(0.2)),
+              trw.make_params("node2vec", "orej", 80, wl.walk_seed, n2v_thr_q16=trw.n2v_thresholds(2.0, 0.5))]
+    strides = [88, 264, 88]
+    path_off = np.concatenate([[0], np.cumsum(sizes * np.array(strides)[kinds])])
+    d_paths = torch.empty(int(path_off[-1]), dtype=torch.int32, device="cuda")
+    d_len = torch.empty(int(offs[-1]), dtype=torch.int32, device="cuda")
+    d_st = torch.empty(int(offs[-1]), dtype=torch.uint8, device="cuda")
+    reqs = (_abi.trw_request * N)()
+    for i in range(N):
+        r = reqs[i]
+        r.params = algo_p[kinds[i]]
+        r.nq = int(sizes[i])
+        r.sources = ctypes.c_void_p(d_src.data_ptr() + 4 * int(offs[i]))
+        r.qid_base = i << 32
+        r.paths = ctypes.c_void_p(d_paths.data_ptr() + 4 * int(path_off[i]))
+        r.path_stride = strides[kinds[i]]
+        r.lengths = ctypes.c_void_p(d_len.data_ptr() + 4 * int(offs[i]))
+        r.status = ctypes.c_void_p(d_st.data_ptr() + int(offs[i]))
+    torch.cuda.synchronize()
+    slots = props.multi_processor_count * args.serve_slots_per_cu
+    srv = trw.Server(G, alias, adj, pool_bytes=8 << 30, max_slots=slots, max_requests=1024,
+                     steps_per_tick=args.serve_steps)
+
+    def replay(lo, hi, arrivals):
+        comp = (_abi.trw_completion * (hi - lo))()
+        arr = (ctypes.c_uint64 * (hi - lo))(*[int(x) for x in arrivals])
+        m0 = srv.stats()["moves"]
+        t = time.perf_counter()
+        rc = _abi.trw_probe_serve_replay(srv.handle, hi - lo, ctypes.byref(reqs, ctypes.sizeof(_abi.trw_request) * lo),
+                                         arr, comp, 600_000)
+        wall = time.perf_counter() - t
+        assert rc == 0, f"replay failed: {rc} {_abi.trw_last_error()}"
+        assert all(comp[i].status == 0 for i in range(hi - lo))
+        return comp, wall, srv.stats()["moves"] - m0
+
+    # saturation: everything arrives at once
+    comp, wall, moves = replay(0, n_sat, np.zeros(n_sat))
+    sat_rps = n_sat / wall
+    sat_steps = moves / wall
+    st0 = srv.stats()
+    log(f"saturated: {n_sat} requests in {wall:.3f}s = {sat_rps:.0f} req/s, {sat_steps:.4g} steps/s; "
+        f"{st0['ticks']} ticks, device {st0['tick_device_ns'] / 1e6:.1f} ms")
+    # offered load 0.7x saturation, Poisson arrivals (exponential gaps from seeded uniforms)
+    rate = 0.7 * sat_rps
+    u = synth.uniform_f64(n_warm + n_meas, wl.walk_seed ^ 0x9015)
+    arrivals = np.cumsum(-np.log(u) / rate) * 1e9
+    comp, wall, moves = replay(n_sat, N, arrivals - arrivals[0])
+    lat = np.array([(comp[i].t_done_ns - comp[i].t_submit_ns) / 1e6 for i in range(n_warm, n_warm + n_meas)])
+    queue = np.array([(comp[i].t_admit_ns - comp[i].t_submit_ns) / 1e6 for i in range(n_warm, n_warm + n_meas)])
+    span = (comp[n_warm + n_meas - 1].t_done_ns - comp[n_warm].t_submit_ns) / 1e9
+    st = srv.stats()
+    srv.close()
+    out = {
+        "metric": "walk steps/sec + % HBM roofline (1 GPU); p50/p99 query latency served",
+        "value": round(moves / wall, 1), "unit": "steps/s", "n_gpus": 1, "steps": n_meas, "warmup": n_warm,
+        "ms_per_step": round(1000 * wall / (n_warm + n_meas), 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": f"{wl.name}: served mix of DeepWalk-80 ALIAS / PPR-0.2 ALIAS / Node2Vec p=2 q=0.5 "
+                               f"len 80, requests of U{{1..4096}} queries, Poisson arrivals at 0.7x saturation; "
+                               f"R-MAT 2^{int(np.log2(g.n))} symmetric avg deg {wl.avg_degree}, uint32 weights 1..255",
+                   "n": g.n, "m": g.m, "parallelism": "1 GPU"},
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3), "p99": round(float(np.percentile(lat, 99)), 3),
+                       "mean": round(float(lat.mean()), 3), "queue_p50": round(float(np.percentile(queue, 50)), 3),
+                       "queue_p99": round(float(np.percentile(queue, 99)), 3)},
+        "offered_req_per_s": round(rate, 1), "achieved_req_per_s": round(n_meas / span, 1),
+        "saturated": {"req_per_s": round(sat_rps, 1), "steps_per_s": round(sat_steps, 1)},
+        "server": {"ticks": st["ticks"], "steps_per_tick": args.serve_steps, "slots": slots,
+                   "max_requests": 1024, "pool_bytes": st["pool_bytes"],
+                   "tick_device_ms_mean": round(st["tick_device_ns"] / max(st["ticks"], 1) / 1e6, 4)},
+        "preprocess_ms": pre,
     }
     print(json.dumps(out), flush=True)
 

@@ -278,7 +278,7 @@ trw_status trw_autotune(trw_graph g, trw_table table, const trw_walk_params *p,
 typedef struct trw_server_s *trw_server;
 
 typedef struct {
-    uint32_t max_slots;        /* walker slots, a multiple of 256; 0 = 512 per CU */
+    uint32_t max_slots;        /* walker slots, a multiple of 256; 0 = 2048 per CU */
     uint32_t max_requests;     /* requests admitted at once, <= 65536; 0 = 1024 */
     uint32_t steps_per_tick;   /* moves per slot per tick; 0 = 32 */
     uint32_t use_hipgraph;     /* 1: replay the tick as a captured HIP graph */
@@ -289,7 +289,8 @@ enum { TRW_REQ_HOST = 1 };     /* sources / paths / lengths / status are host me
 
 typedef struct {
     trw_walk_params params;    /* DeepWalk / PPR with NAIVE or ALIAS, Node2Vec with OREJ */
-    const int32_t *sources;    /* nq sources; read when the request is admitted */
+    const int32_t *sources;    /* nq sources: host memory is copied at admission; device
+                                  memory is read in place until the request completes */
     uint32_t nq;               /* >= 1 */
     uint32_t flags;            /* TRW_REQ_HOST or 0 (device buffers) */
     uint64_t qid_base;         /* query i has id qid_base + i (same walks as trw_walk) */
@@ -314,6 +315,7 @@ typedef struct {
     uint64_t submitted, completed, cancelled, rejected, ticks, moves;
     uint32_t active, waiting;
     uint64_t pool_bytes, pool_bytes_used;
+    uint64_t tick_device_ns;   /* device time of the ticks and their counter read-back */
 } trw_server_stats;
 
 /* Device bytes of a server arena for `cfg` with a request pool of pool_bytes. */
@@ -336,8 +338,10 @@ trw_status trw_server_request_bytes(trw_server s, const trw_request *r, size_t *
  * Queue a request.  Returns at once with its id; the request is admitted when
  * a request slot and pool space are free, in submission order.  Errors:
  * TRW_E_NOMEM_BUDGET if it can never fit the pool, TRW_E_UNSUPPORTED /
- * TRW_E_INVALID as trw_walk.  The caller keeps sources valid until admission
- * and the output buffers until the completion is polled.
+ * TRW_E_INVALID as trw_walk.  The caller keeps the sources and the output
+ * buffers valid until the completion is polled.  Outputs are written when the
+ * request completes (device destinations by one copy launch per tick for all
+ * requests finishing together; host destinations by plain copies).
  */
 trw_status trw_server_submit(trw_server s, const trw_request *r, uint64_t *request_id);
 

@@ -32,6 +32,17 @@ int trw_probe_fill(void *d_buf, uint64_t bytes, uint32_t seed, void *stream);
 int trw_probe_gather(const void *d_buf, uint64_t bytes, uint32_t elem_bytes, uint32_t chains, uint32_t steps,
                      int dependent, uint32_t grid, uint32_t block, void *d_sink, void *stream);
 
+/*
+ * Replay a request trace against a server (trw.h): request i (trw_request) is
+ * submitted once arrival_ns[i] nanoseconds (non-decreasing) have passed since
+ * the call began, and its completion is stored in completions[i]
+ * (trw_completion).  Runs in the calling thread until all n complete.
+ * Returns 0, 1 (bad argument), 6 (timeout_ms passed), 10 + a trw_status from
+ * submit, or 20 + a trw_status from poll.
+ */
+int trw_probe_serve_replay(void *server, uint32_t n, const void *requests, const uint64_t *arrival_ns,
+                           void *completions, uint32_t timeout_ms);
+
 #ifdef __cplusplus
 }
 #endif

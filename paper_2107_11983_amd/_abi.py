@@ -65,7 +65,7 @@ class trw_server_stats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("cancelled", ctypes.c_uint64),
                 ("rejected", ctypes.c_uint64), ("ticks", ctypes.c_uint64), ("moves", ctypes.c_uint64),
                 ("active", ctypes.c_uint32), ("waiting", ctypes.c_uint32), ("pool_bytes", ctypes.c_uint64),
-                ("pool_bytes_used", ctypes.c_uint64)]
+                ("pool_bytes_used", ctypes.c_uint64), ("tick_device_ns", ctypes.c_uint64)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -118,6 +118,7 @@ _SIGS = {
     # measurement probe (include/trw_probe.h)
     "trw_probe_fill": (ctypes.c_int, [_P, _u64, _u32, _P]),
     "trw_probe_gather": (ctypes.c_int, [_P, _u64, _u32, _u32, _u32, ctypes.c_int, _u32, _u32, _P, _P]),
+    "trw_probe_serve_replay": (ctypes.c_int, [_P, _u32, _P, _P, _P, _u32]),
 }
 
 for _name, (_res, _args) in _SIGS.items():
@@ -165,3 +166,4 @@ trw_server_stats_get = lib.trw_server_stats_get
 trw_server_destroy = lib.trw_server_destroy
 trw_probe_fill = lib.trw_probe_fill
 trw_probe_gather = lib.trw_probe_gather
+trw_probe_serve_replay = lib.trw_probe_serve_replay

@@ -16,9 +16,30 @@
 namespace trw {
 namespace {
 
-__device__ __forceinline__ void finish(const ServeDev &s, const ReqDesc &d, SlotState &st, uint8_t status) {
-    d.lengths[st.qi] = st.k;
-    d.status[st.qi] = status;
+// The fields of a walker's request that every step needs, held in registers
+// (the descriptor table only changes between ticks).
+struct ReqRegs {
+    uint32_t algo, sampler, max_len, stop_q32, cancelled;
+    WalkDev wd;              // thresholds and seed in the layout the move functions take
+    uint64_t qid_base;
+    int32_t *paths;
+    uint64_t stride;
+    uint32_t *lengths;
+    uint8_t *status;
+};
+
+__device__ __forceinline__ void load_req(const ReqDesc &d, ReqRegs &q) {
+    q.algo = d.algo; q.sampler = d.sampler; q.max_len = d.max_len; q.stop_q32 = d.stop_q32;
+    q.cancelled = d.cancelled;
+    q.wd.thr[0] = d.thr[0]; q.wd.thr[1] = d.thr[1]; q.wd.thr[2] = d.thr[2];
+    q.wd.seed = d.seed;
+    q.qid_base = d.qid_base;
+    q.paths = d.paths; q.stride = d.stride; q.lengths = d.lengths; q.status = d.status;
+}
+
+__device__ __forceinline__ void finish(const ServeDev &s, const ReqRegs &q, SlotState &st, uint8_t status) {
+    q.lengths[st.qi] = st.k;
+    q.status[st.qi] = status;
     atomicAdd(&s.done[st.req], 1u);
     st.req = kIdle;
 }
@@ -31,9 +52,10 @@ __global__ void __launch_bounds__(256) k_serve_tick(GraphDev g, TableDev t, Serv
     WaveState ws = s.waves[wid];                       // same value in every lane
     const unsigned long long tail = *s.tail;           // chunks published before this tick
     PathBuf path;
+    ReqRegs q;
     if (st.req != kIdle) {
-        const ReqDesc &d = s.reqs[st.req];
-        path.start(d.paths + (uint64_t)st.qi * d.stride + st.k + 1);
+        load_req(s.reqs[st.req], q);
+        path.start(q.paths + (uint64_t)st.qi * q.stride + st.k + 1);
     }
     uint32_t moves = 0;
 
@@ -56,6 +78,7 @@ __global__ void __launch_bounds__(256) k_serve_tick(GraphDev g, TableDev t, Serv
             const uint32_t rk = rank_below(idle);
             if (((idle >> lane) & 1ull) && rk < avail) {
                 const ReqDesc &d = s.reqs[ws.req];
+                load_req(d, q);
                 st.req = ws.req;
                 st.qi = ws.next + rk;
                 st.k = 0;
@@ -63,13 +86,13 @@ __global__ void __launch_bounds__(256) k_serve_tick(GraphDev g, TableDev t, Serv
                 st.poff = 0; st.pdeg = 0;
                 const int32_t src = d.sources[st.qi];
                 if (src < 0 || src >= g.n) {
-                    finish(s, d, st, ST_BAD_SOURCE);
+                    finish(s, q, st, ST_BAD_SOURCE);
                 } else {
                     st.cur = src;
                     const int32_t lo = g.row_ptr[src];
                     st.off = lo;
                     st.deg = g.row_ptr[src + 1] - lo;
-                    path.start(d.paths + (uint64_t)st.qi * d.stride);
+                    path.start(q.paths + (uint64_t)st.qi * q.stride);
                     path.push(src);
                 }
             }
@@ -79,30 +102,26 @@ __global__ void __launch_bounds__(256) k_serve_tick(GraphDev g, TableDev t, Serv
         if (__ballot(st.req != kIdle) == 0) break;     // nothing to run this tick
 
         if (st.req != kIdle) {
-            const ReqDesc &d = s.reqs[st.req];
-            if (d.cancelled) {
+            if (q.cancelled) {
                 path.flush();
                 atomicAdd(&s.done[st.req], 1u);
                 st.req = kIdle;
                 continue;
             }
-            const uint64_t qid = d.qid_base + st.qi;
-            const Rand4 r = philox(st.k, 0, qid, d.seed);
+            const uint64_t qid = q.qid_base + st.qi;
+            const Rand4 r = philox(st.k, 0, qid, q.wd.seed);
             int32_t nxt = -1, noff = 0, ndeg = 0;
             if (st.deg != 0) {
-                if (d.algo == ALG_NODE2VEC) {
-                    WalkDev wd{};
-                    wd.thr[0] = d.thr[0]; wd.thr[1] = d.thr[1]; wd.thr[2] = d.thr[2];
-                    wd.seed = d.seed;
+                if (q.algo == ALG_NODE2VEC) {
                     if (t.adj) {
-                        nxt = n2v_move<true>(g, t, wd, qid, st.k, st.off, (uint32_t)st.deg, r, st.prev, st.poff,
+                        nxt = n2v_move<true>(g, t, q.wd, qid, st.k, st.off, (uint32_t)st.deg, r, st.prev, st.poff,
                                              st.pdeg, noff, ndeg);
                     } else {
-                        nxt = n2v_move<false>(g, t, wd, qid, st.k, st.off, (uint32_t)st.deg, r, st.prev, st.poff,
+                        nxt = n2v_move<false>(g, t, q.wd, qid, st.k, st.off, (uint32_t)st.deg, r, st.prev, st.poff,
                                               st.pdeg, noff, ndeg);
                         if (nxt >= 0) { noff = g.row_ptr[nxt]; ndeg = g.row_ptr[nxt + 1] - noff; }
                     }
-                } else if (d.sampler == SMP_ALIAS) {
+                } else if (q.sampler == SMP_ALIAS) {
                     const uint32_t e = (uint32_t)st.off + scale32(r.r0, (uint32_t)st.deg);
                     nxt = alias_pick(t.alias[2 * (uint64_t)e], t.alias[2 * (uint64_t)e + 1], r.r1, noff, ndeg);
                 } else {  // NAIVE
@@ -118,7 +137,7 @@ __global__ void __launch_bounds__(256) k_serve_tick(GraphDev g, TableDev t, Serv
             }
             if (nxt < 0) {
                 path.flush();
-                finish(s, d, st, ST_DEAD_END);
+                finish(s, q, st, ST_DEAD_END);
                 continue;
             }
             path.push(nxt);
@@ -127,11 +146,11 @@ __global__ void __launch_bounds__(256) k_serve_tick(GraphDev g, TableDev t, Serv
             st.cur = nxt; st.off = noff; st.deg = ndeg;
             st.k += 1;
             uint8_t status = 0;
-            if (d.algo == ALG_PPR && r.r2 < d.stop_q32) status = ST_STOPPED;
-            else if (st.k == d.max_len) status = ST_LENGTH;
+            if (q.algo == ALG_PPR && r.r2 < q.stop_q32) status = ST_STOPPED;
+            else if (st.k == q.max_len) status = ST_LENGTH;
             if (status) {
                 path.flush();
-                finish(s, d, st, status);
+                finish(s, q, st, status);
             }
         }
     }

@@ -8,10 +8,13 @@
 // request waits (first come, first served) until a descriptor slot and pool
 // space are free; one that could never fit is refused at submit.
 //
-// Per tick the thread (1) admits what fits, copying sources, descriptors and
-// ring chunks to the device, (2) launches the tick (a captured graph), (3)
-// reads the per-request completion counters back, and (4) copies the outputs
-// of finished requests to their destinations and releases their memory.
+// Per tick the thread (1) admits what fits and publishes the descriptor table
+// and the new ring chunks (one copy each), (2) launches the tick (a captured
+// graph), (3) reads all completion counters back in one copy, and (4)
+// delivers the outputs of finished requests: one scatter-copy launch for all
+// device destinations, plain copies for host ones.  The host cost per tick is
+// a fixed handful of calls, whatever the number of requests.  Device sources
+// are read in place; host sources are staged in the pool.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -33,6 +36,41 @@ namespace trw {
 __global__ void k_fill_bytes(uint32_t *p, size_t n_words, uint32_t v) {
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_words; i += stride) p[i] = v;
+}
+
+// A 2D copy of `rows` rows of `width` bytes; row_start = rows of all earlier
+// jobs of the same delivery (rows are the unit of work).
+struct CopyJob {
+    const char *src;
+    char *dst;
+    uint64_t src_pitch, dst_pitch, width, rows, row_start;
+};
+
+// Output delivery: every wave copies whole rows (of any job), rows spread over
+// the grid; 4-byte words when the row is 4-byte aligned, bytes otherwise.
+__global__ void __launch_bounds__(256) k_deliver(const CopyJob *__restrict__ jobs, uint32_t n_jobs,
+                                                 uint64_t total_rows) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+    for (uint64_t row = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); row < total_rows;
+         row += waves) {
+        uint32_t lo = 0, hi = n_jobs - 1;           // last job with row_start <= row
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi + 1) >> 1;
+            if (jobs[mid].row_start <= row) lo = mid; else hi = mid - 1;
+        }
+        const CopyJob jb = jobs[lo];
+        const uint64_t r = row - jb.row_start;
+        const char *src = jb.src + r * jb.src_pitch;
+        char *dst = jb.dst + r * jb.dst_pitch;
+        if (((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst) | jb.width) & 3) == 0) {
+            const uint32_t w = (uint32_t)(jb.width >> 2);
+            for (uint32_t c = lane; c < w; c += 64)
+                reinterpret_cast<uint32_t *>(dst)[c] = reinterpret_cast<const uint32_t *>(src)[c];
+        } else {
+            for (uint64_t c = lane; c < jb.width; c += 64) dst[c] = src[c];
+        }
+    }
 }
 
 namespace {
@@ -90,16 +128,21 @@ class RangeAllocator {
 };
 
 struct Layout {
-    size_t reqs, ring, counters, done, slots, waves, pool, fixed;
+    size_t reqs, ring, counters, done, done_bytes, jobs, slots, waves, pool, fixed;
 };
 
+// The completion counters are followed by the moves counter so that one copy
+// brings both back.
 Layout layout(uint32_t slots, uint32_t max_reqs, uint32_t ring) {
     Layout l{};
     size_t o = 0;
     l.reqs = o; o = align_up(o + sizeof(ReqDesc) * max_reqs);
     l.ring = o; o = align_up(o + sizeof(Chunk) * ring);
-    l.counters = o; o = align_up(o + 3 * sizeof(unsigned long long));   // head, tail, moves
-    l.done = o; o = align_up(o + sizeof(uint32_t) * max_reqs);
+    l.counters = o; o = align_up(o + 2 * sizeof(unsigned long long));   // head, tail
+    l.done = o;
+    l.done_bytes = (sizeof(uint32_t) * max_reqs + 7) / 8 * 8 + sizeof(unsigned long long);
+    o = align_up(o + l.done_bytes);
+    l.jobs = o; o = align_up(o + sizeof(CopyJob) * 3 * (size_t)max_reqs);
     l.slots = o; o = align_up(o + sizeof(SlotState) * slots);
     l.waves = o; o = align_up(o + sizeof(WaveState) * (slots / 64));
     l.pool = o;
@@ -120,11 +163,12 @@ struct Active {
     uint64_t t_submit, t_admit;
     size_t pool_off, pool_bytes;
     uint32_t slot;
+    uint32_t done_base;        // the slot's completion counter when this request was admitted
     uint64_t stride;
+    size_t out_off;            // offset of the outputs inside the request's pool range
     bool finishing = false;
-    bool cancel_sent = false;
     bool cancelled = false;
-    hipEvent_t copied = nullptr;
+    hipEvent_t copied = nullptr;   // host destinations: the output copies
 };
 
 }  // namespace
@@ -145,12 +189,16 @@ struct trw_server_s {
     ServeDev dev;
     RangeAllocator pool;
     // host staging (pinned)
-    ReqDesc *h_desc = nullptr;
+    ReqDesc *h_desc = nullptr;                // mirror of the device descriptor table
     Chunk *h_ring = nullptr;
     unsigned long long *h_tail = nullptr;
-    uint32_t *h_done = nullptr;              // max_reqs counters followed by the moves counter
+    uint32_t *h_done = nullptr;               // completion counters followed by the moves counter
+    CopyJob *h_jobs = nullptr;
+    hipEvent_t delivered = nullptr;
+    bool desc_dirty = false;
     hipStream_t stream = nullptr;
     hipEvent_t tick_done = nullptr;
+    hipEvent_t tick_start = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     // scheduling state (guarded by mu)
@@ -180,10 +228,15 @@ trw_status sfail(trw_status st, const std::string &m) {
     return st;
 }
 
+// Pool layout of an admitted request: [host sources copy], paths, lengths, status.
+size_t request_src_bytes(const trw_request &r) {
+    return (r.flags & TRW_REQ_HOST) ? align_up(sizeof(int32_t) * (size_t)r.nq) : 0;
+}
+
 size_t request_pool_bytes(const trw_request &r) {
     const uint64_t stride = ((uint64_t)r.params.max_len + 1 + 7) / 8 * 8;
-    return align_up(sizeof(int32_t) * (size_t)r.nq) + align_up(sizeof(int32_t) * stride * r.nq) +
-           align_up(sizeof(uint32_t) * (size_t)r.nq) + align_up((size_t)r.nq);
+    return request_src_bytes(r) + align_up(sizeof(int32_t) * stride * r.nq) + align_up(sizeof(uint32_t) * (size_t)r.nq) +
+           align_up((size_t)r.nq);
 }
 
 trw_status check_request(const trw_server_s *s, const trw_request *r) {
@@ -217,7 +270,7 @@ extern "C" {
 trw_status trw_server_arena_bytes(const trw_server_cfg *cfg, size_t pool_bytes, size_t *bytes) {
     if (!cfg || !bytes) return sfail(TRW_E_INVALID, "cfg / bytes is NULL");
     const DeviceInfo &di = device_info();
-    const uint32_t slots = cfg->max_slots ? cfg->max_slots : (uint32_t)di.num_cus * 512;
+    const uint32_t slots = cfg->max_slots ? cfg->max_slots : (uint32_t)di.num_cus * 2048;
     const uint32_t reqs = cfg->max_requests ? cfg->max_requests : 1024;
     if (slots % kServeBlock) return sfail(TRW_E_INVALID, "max_slots must be a multiple of 256");
     *bytes = layout(slots, reqs, 1u << 20).fixed + align_up(pool_bytes);
@@ -234,7 +287,7 @@ extern "C" trw_status trw_server_create(trw_graph g, trw_table alias, trw_table 
                                         void *d_arena, size_t arena_bytes, trw_server *out) {
     if (!g || !cfg || !out) return sfail(TRW_E_INVALID, "graph / cfg / out is NULL");
     const DeviceInfo &di = device_info();
-    const uint32_t slots = cfg->max_slots ? cfg->max_slots : (uint32_t)di.num_cus * 512;
+    const uint32_t slots = cfg->max_slots ? cfg->max_slots : (uint32_t)di.num_cus * 2048;
     const uint32_t reqs = cfg->max_requests ? cfg->max_requests : 1024;
     const uint32_t steps = cfg->steps_per_tick ? cfg->steps_per_tick : 32;
     if (slots % kServeBlock || slots > (1u << 24)) return sfail(TRW_E_INVALID, "max_slots must be a multiple of 256, <= 2^24");
@@ -272,17 +325,24 @@ extern "C" trw_status trw_server_create(trw_graph g, trw_table alias, trw_table 
     auto *ctr = reinterpret_cast<unsigned long long *>(a + lay.counters);
     s->dev.head = ctr;
     s->dev.tail = ctr + 1;
-    s->dev.moves = ctr + 2;
     s->dev.done = reinterpret_cast<uint32_t *>(a + lay.done);
+    s->dev.moves = reinterpret_cast<unsigned long long *>(a + lay.done + lay.done_bytes - sizeof(unsigned long long));
     s->dev.slots = reinterpret_cast<SlotState *>(a + lay.slots);
     s->dev.waves = reinterpret_cast<WaveState *>(a + lay.waves);
 
     hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->tick_done, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreate(&s->tick_done);
+    if (e == hipSuccess) e = hipEventCreate(&s->tick_start);
     if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_desc, sizeof(ReqDesc) * reqs, hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_ring, sizeof(Chunk) * ring, hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_tail, sizeof(unsigned long long), hipHostMallocDefault);
-    if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_done, sizeof(uint32_t) * reqs + 8, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_done, lay.done_bytes, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_jobs, sizeof(CopyJob) * 3 * (size_t)reqs, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->delivered, hipEventDisableTiming);
+    if (e == hipSuccess) {
+        std::memset(s->h_desc, 0, sizeof(ReqDesc) * reqs);
+        std::memset(s->h_done, 0, lay.done_bytes);
+    }
     if (e == hipSuccess) {
         // zero the counters, descriptors and waves; mark every slot free (0xFF bytes)
         auto fill = [&](size_t off, size_t bytes, uint32_t v) {
@@ -391,12 +451,15 @@ extern "C" trw_status trw_server_destroy(trw_server s) {
     if (s->graph_exec) (void)hipGraphExecDestroy(s->graph_exec);
     if (s->graph) (void)hipGraphDestroy(s->graph);
     if (s->tick_done) (void)hipEventDestroy(s->tick_done);
+    if (s->tick_start) (void)hipEventDestroy(s->tick_start);
     for (auto &a : s->active)
         if (a.copied) (void)hipEventDestroy(a.copied);
     if (s->h_desc) (void)hipHostFree(s->h_desc);
     if (s->h_ring) (void)hipHostFree(s->h_ring);
     if (s->h_tail) (void)hipHostFree(s->h_tail);
     if (s->h_done) (void)hipHostFree(s->h_done);
+    if (s->h_jobs) (void)hipHostFree(s->h_jobs);
+    if (s->delivered) (void)hipEventDestroy(s->delivered);
     if (s->stream) (void)hipStreamDestroy(s->stream);
     delete s;
     return TRW_OK;
@@ -427,10 +490,10 @@ void complete(trw_server_s *s, Active &a, int32_t status) {
     s->cv_done.notify_all();
 }
 
-// Admit waiting requests while a slot and pool space are free (first come, first served).
+// Admit waiting requests while a slot and pool space are free (first come,
+// first served), then publish the descriptor table, the new chunks and the tail.
 hipError_t admit(trw_server_s *s, std::deque<Pending> &incoming) {
     hipError_t e = hipSuccess;
-    bool any = false;
     const unsigned long long tail0 = s->tail;
     while (!incoming.empty() && !s->free_slots.empty()) {
         Pending &p = incoming.front();
@@ -441,14 +504,18 @@ hipError_t admit(trw_server_s *s, std::deque<Pending> &incoming) {
         const trw_request &r = p.req;
         const uint64_t stride = ((uint64_t)r.params.max_len + 1 + 7) / 8 * 8;
         char *base = s->arena + s->lay.pool + off;
-        int32_t *src = reinterpret_cast<int32_t *>(base);
-        int32_t *paths = reinterpret_cast<int32_t *>(base + align_up(sizeof(int32_t) * (size_t)r.nq));
+        const size_t src_bytes = request_src_bytes(r);
+        const int32_t *src = static_cast<const int32_t *>(r.sources);
+        if (r.flags & TRW_REQ_HOST) {
+            e = hipMemcpyAsync(base, r.sources, sizeof(int32_t) * r.nq, hipMemcpyHostToDevice, s->stream);
+            if (e != hipSuccess) return e;
+            src = reinterpret_cast<const int32_t *>(base);
+        }
+        int32_t *paths = reinterpret_cast<int32_t *>(base + src_bytes);
         uint32_t *lengths = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(paths) +
                                                          align_up(sizeof(int32_t) * stride * r.nq));
         uint8_t *status = reinterpret_cast<uint8_t *>(reinterpret_cast<char *>(lengths) +
                                                       align_up(sizeof(uint32_t) * (size_t)r.nq));
-        e = hipMemcpyAsync(src, r.sources, sizeof(int32_t) * r.nq, kind_in(r), s->stream);
-        if (e != hipSuccess) return e;
         ReqDesc &d = s->h_desc[slot];
         std::memset(&d, 0, sizeof(d));
         d.algo = r.params.algo;
@@ -464,12 +531,7 @@ hipError_t admit(trw_server_s *s, std::deque<Pending> &incoming) {
         d.status = status;
         d.stride = stride;
         d.nq = r.nq;
-        e = hipMemcpyAsync(s->dev.reqs + slot, &d, sizeof(d), hipMemcpyHostToDevice, s->stream);
-        if (e != hipSuccess) return e;
-        // zero this slot's completion counter (a one-word copy from the staging area)
-        s->h_done[slot] = 0;
-        e = hipMemcpyAsync(s->dev.done + slot, s->h_done + slot, sizeof(uint32_t), hipMemcpyHostToDevice, s->stream);
-        if (e != hipSuccess) return e;
+        s->desc_dirty = true;
         for (uint32_t b = 0; b < r.nq; b += kChunkQueries) {
             Chunk &c = s->h_ring[s->tail % s->ring];
             c.req = slot; c.begin = b; c.end = std::min<uint32_t>(r.nq, b + kChunkQueries); c.pad = 0;
@@ -478,11 +540,17 @@ hipError_t admit(trw_server_s *s, std::deque<Pending> &incoming) {
         Active a;
         a.id = p.id; a.req = r; a.t_submit = p.t_submit; a.t_admit = now_ns();
         a.pool_off = off; a.pool_bytes = p.bytes; a.slot = slot; a.stride = stride;
+        a.done_base = s->h_done[slot];   // unchanged on the device while the slot was free
+        a.out_off = src_bytes;
         s->active.push_back(a);
         incoming.pop_front();
-        any = true;
     }
-    if (!any) return hipSuccess;
+    if (s->desc_dirty) {
+        e = hipMemcpyAsync(s->dev.reqs, s->h_desc, sizeof(ReqDesc) * s->max_reqs, hipMemcpyHostToDevice, s->stream);
+        if (e != hipSuccess) return e;
+        s->desc_dirty = false;
+    }
+    if (s->tail == tail0) return hipSuccess;
     // copy the new ring entries (they may wrap around), then publish the tail
     for (unsigned long long i = tail0; i < s->tail;) {
         const unsigned long long pos = i % s->ring;
@@ -497,9 +565,22 @@ hipError_t admit(trw_server_s *s, std::deque<Pending> &incoming) {
                           hipMemcpyHostToDevice, s->stream);
 }
 
+// Outputs of a finished request: 2D copy of the path rows, lengths, status.
+void output_jobs(const trw_server_s *s, const Active &a, CopyJob *jobs) {
+    const trw_request &r = a.req;
+    const char *base = s->arena + s->lay.pool + a.pool_off + a.out_off;
+    const char *paths = base;
+    const char *lengths = paths + align_up(sizeof(int32_t) * a.stride * r.nq);
+    const char *status = lengths + align_up(sizeof(uint32_t) * (size_t)r.nq);
+    jobs[0] = CopyJob{paths, reinterpret_cast<char *>(r.paths), sizeof(int32_t) * a.stride,
+                      sizeof(int32_t) * r.path_stride, sizeof(int32_t) * ((size_t)r.params.max_len + 1), r.nq, 0};
+    jobs[1] = CopyJob{lengths, reinterpret_cast<char *>(r.lengths), 0, 0, sizeof(uint32_t) * (size_t)r.nq, 1, 0};
+    jobs[2] = CopyJob{status, reinterpret_cast<char *>(r.status), 0, 0, (size_t)r.nq, 1, 0};
+}
+
 void server_loop(trw_server_s *s) {
     (void)hipSetDevice(s->device);
-    std::deque<Pending> incoming;
+    std::deque<Pending> incoming, empty;
     for (;;) {
         std::vector<uint64_t> cancels;
         bool stopping;
@@ -535,56 +616,75 @@ void server_loop(trw_server_s *s) {
                 }
             }
             for (auto &a : s->active) {
-                if (a.id == id && !a.cancel_sent && !a.finishing) {
-                    a.cancel_sent = true;
+                if (a.id == id && !a.cancelled && !a.finishing) {
                     a.cancelled = true;
                     s->h_desc[a.slot].cancelled = 1;
-                    (void)hipMemcpyAsync(&s->dev.reqs[a.slot].cancelled, &s->h_desc[a.slot].cancelled,
-                                         sizeof(uint32_t), hipMemcpyHostToDevice, s->stream);
+                    s->desc_dirty = true;
                 }
             }
         }
-        hipError_t e = hipSuccess;
-        if (!stopping) e = admit(s, incoming);
+        hipError_t e = admit(s, stopping ? empty : incoming);
         if (e == hipSuccess && !s->active.empty()) {
             bool running = false;
             for (auto &a : s->active) running |= !a.finishing;
             if (running) {
-                e = s->use_graph ? hipGraphLaunch(s->graph_exec, s->stream)
-                                 : launch_serve_tick(s->g, s->t, s->dev, s->steps, s->slots / kServeBlock, s->stream);
+                e = hipEventRecord(s->tick_start, s->stream);
                 if (e == hipSuccess)
-                    e = hipMemcpyAsync(s->h_done, s->dev.done, sizeof(uint32_t) * s->max_reqs, hipMemcpyDeviceToHost,
-                                       s->stream);
+                    e = s->use_graph ? hipGraphLaunch(s->graph_exec, s->stream)
+                                     : launch_serve_tick(s->g, s->t, s->dev, s->steps, s->slots / kServeBlock, s->stream);
                 if (e == hipSuccess)
-                    e = hipMemcpyAsync(s->h_done + s->max_reqs, s->dev.moves, sizeof(unsigned long long),
-                                       hipMemcpyDeviceToHost, s->stream);
+                    e = hipMemcpyAsync(s->h_done, s->dev.done, s->lay.done_bytes, hipMemcpyDeviceToHost, s->stream);
                 if (e == hipSuccess) e = hipEventRecord(s->tick_done, s->stream);
                 if (e == hipSuccess) e = hipEventSynchronize(s->tick_done);
                 if (e == hipSuccess) {
+                    unsigned long long mv;
+                    std::memcpy(&mv, reinterpret_cast<char *>(s->h_done) + s->lay.done_bytes - sizeof(mv), sizeof(mv));
+                    float ms = 0;
+                    (void)hipEventElapsedTime(&ms, s->tick_start, s->tick_done);
                     std::lock_guard<std::mutex> lk(s->mu);
                     s->stats.ticks++;
-                    unsigned long long mv;
-                    std::memcpy(&mv, s->h_done + s->max_reqs, sizeof(mv));
                     s->stats.moves = mv;
+                    s->stats.tick_device_ns += (uint64_t)(ms * 1e6);
                 }
-                // requests whose queries are all done: copy their outputs out
-                for (auto &a : s->active) {
-                    if (a.finishing || e != hipSuccess) continue;
-                    if (s->h_done[a.slot] < a.req.nq) continue;
+                // finished requests: device destinations in one delivery launch, host ones by copies
+                uint32_t njobs = 0;
+                uint64_t total_rows = 0;
+                std::vector<size_t> delivered_now;
+                for (size_t i = 0; i < s->active.size() && e == hipSuccess; ++i) {
+                    Active &a = s->active[i];
+                    if (a.finishing || s->h_done[a.slot] - a.done_base < a.req.nq) continue;
                     a.finishing = true;
                     if (a.cancelled) continue;
-                    const trw_request &r = a.req;
-                    char *base = s->arena + s->lay.pool + a.pool_off;
-                    const char *paths = base + align_up(sizeof(int32_t) * (size_t)r.nq);
-                    const char *lengths = paths + align_up(sizeof(int32_t) * a.stride * r.nq);
-                    const char *status = lengths + align_up(sizeof(uint32_t) * (size_t)r.nq);
-                    e = hipMemcpy2DAsync(r.paths, sizeof(int32_t) * r.path_stride, paths, sizeof(int32_t) * a.stride,
-                                         sizeof(int32_t) * ((size_t)r.params.max_len + 1), r.nq, kind_out(r), s->stream);
-                    if (e == hipSuccess)
-                        e = hipMemcpyAsync(r.lengths, lengths, sizeof(uint32_t) * r.nq, kind_out(r), s->stream);
-                    if (e == hipSuccess) e = hipMemcpyAsync(r.status, status, r.nq, kind_out(r), s->stream);
-                    if (e == hipSuccess) e = hipEventCreateWithFlags(&a.copied, hipEventDisableTiming);
-                    if (e == hipSuccess) e = hipEventRecord(a.copied, s->stream);
+                    CopyJob jobs[3];
+                    output_jobs(s, a, jobs);
+                    if (a.req.flags & TRW_REQ_HOST) {
+                        e = hipMemcpy2DAsync(jobs[0].dst, jobs[0].dst_pitch, jobs[0].src, jobs[0].src_pitch,
+                                             jobs[0].width, jobs[0].rows, hipMemcpyDeviceToHost, s->stream);
+                        for (int k = 1; k < 3 && e == hipSuccess; ++k)
+                            e = hipMemcpyAsync(jobs[k].dst, jobs[k].src, jobs[k].width, hipMemcpyDeviceToHost, s->stream);
+                        if (e == hipSuccess) e = hipEventCreateWithFlags(&a.copied, hipEventDisableTiming);
+                        if (e == hipSuccess) e = hipEventRecord(a.copied, s->stream);
+                    } else {
+                        for (int k = 0; k < 3; ++k) {
+                            jobs[k].row_start = total_rows;
+                            total_rows += jobs[k].rows;
+                            s->h_jobs[njobs++] = jobs[k];
+                        }
+                        delivered_now.push_back(i);
+                    }
+                }
+                if (e == hipSuccess && njobs) {
+                    CopyJob *d_jobs = reinterpret_cast<CopyJob *>(s->arena + s->lay.jobs);
+                    e = hipMemcpyAsync(d_jobs, s->h_jobs, sizeof(CopyJob) * njobs, hipMemcpyHostToDevice, s->stream);
+                    if (e == hipSuccess) {
+                        const uint64_t blocks = std::min<uint64_t>((total_rows + 3) / 4, 4096);
+                        hipLaunchKernelGGL(k_deliver, dim3((uint32_t)blocks), dim3(256), 0, s->stream, d_jobs, njobs,
+                                           total_rows);
+                        e = hipGetLastError();
+                    }
+                    if (e == hipSuccess) e = hipEventRecord(s->delivered, s->stream);
+                    if (e == hipSuccess) e = hipEventSynchronize(s->delivered);
+                    for (size_t i : delivered_now) s->active[i].copied = nullptr;
                 }
             }
         }
@@ -594,7 +694,7 @@ void server_loop(trw_server_s *s) {
                 Active &a = s->active[i];
                 bool ready = false;
                 if (a.finishing) {
-                    if (a.cancelled) ready = true;
+                    if (a.cancelled || !(a.req.flags & TRW_REQ_HOST)) ready = true;   // device: delivered above
                     else ready = a.copied && hipEventQuery(a.copied) == hipSuccess;
                 }
                 if (ready) {
