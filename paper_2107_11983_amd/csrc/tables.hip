@@ -16,7 +16,12 @@
 // Each thread therefore walks its row with two cursors moving downwards and
 // keeps one demoted column in registers: O(d) time, O(1) state, no scratch.
 //
+// Rows above kBigRow slots get a workgroup each instead (same results): see
+// k_alias_build_big.
+//
 // ITS: inclusive running sum of the weights per row in uint64.
+#include <algorithm>
+
 #include "trw_device.hpp"
 #include "trw_internal.hpp"
 
@@ -59,12 +64,8 @@ __device__ __forceinline__ void put_entry(uint4 *__restrict__ row, int64_t j, co
     row[2 * j + 1] = make_uint4(a.x, a.y, b.x, b.y);
 }
 
-__global__ void k_alias_build(GraphDev g, uint4 *__restrict__ out) {
-    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= g.n) return;
-    const int64_t off = g.row_ptr[v];
-    const int64_t d = (int64_t)g.row_ptr[v + 1] - off;
-    if (d <= 0) return;
+// Sequential construction of one row by one thread.
+__device__ void alias_row_sequential(const GraphDev &g, int64_t off, int64_t d, uint4 *__restrict__ out) {
     const uint32_t *__restrict__ w = g.weight + off;
     const int32_t *__restrict__ col = g.col + off;
     uint4 *__restrict__ row = out + 2 * off;
@@ -109,15 +110,216 @@ __global__ void k_alias_build(GraphDev g, uint4 *__restrict__ out) {
     }
 }
 
+// Rows up to this many slots are built by one thread; longer ones (power-law
+// hubs, which would serialise a whole launch) by one workgroup.
+constexpr int64_t kBigRow = 1024;
+constexpr int kBuildBlock = 256;
+
+__global__ void k_alias_build(GraphDev g, uint4 *__restrict__ out) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= g.n) return;
+    const int64_t off = g.row_ptr[v];
+    const int64_t d = (int64_t)g.row_ptr[v + 1] - off;
+    if (d <= 0 || d > kBigRow) return;
+    alias_row_sequential(g, off, d, out);
+}
+
+// Inclusive scan over the kBuildBlock threads of a workgroup; `total` gets
+// the sum over the block.  Every thread must call it.
+template <typename T>
+__device__ __forceinline__ T block_inclusive_scan(T v, T *sh, T &total) {
+    const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const T t = __shfl_up(v, o);
+        if (lane >= (uint32_t)o) v += t;
+    }
+    if (lane == 63) sh[wv] = v;
+    __syncthreads();
+    T before = 0;
+    total = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < kBuildBlock / 64; ++k) {
+        if (k < wv) before += sh[k];
+        total += sh[k];
+    }
+    __syncthreads();
+    return v + before;
+}
+
+template <typename T>
+__device__ __forceinline__ T block_sum(T v, T *sh) {
+    T total;
+    (void)block_inclusive_scan(v, sh, total);
+    return total;
+}
+
+// Calls body(v, off, d) for every vertex whose row exceeds kBigRow slots,
+// workgroup-uniformly; the workgroup sweeps vertex chunks of kBuildBlock.
+template <typename Body>
+__device__ __forceinline__ void for_each_big_row(const GraphDev &g, Body body) {
+    __shared__ uint64_t flags[kBuildBlock / 64];
+    const uint32_t tid = threadIdx.x;
+    for (int64_t base = (int64_t)blockIdx.x * kBuildBlock; base < g.n; base += (int64_t)gridDim.x * kBuildBlock) {
+        const int64_t v = base + tid;
+        const bool big = v < g.n && (int64_t)g.row_ptr[v + 1] - g.row_ptr[v] > kBigRow;
+        const uint64_t m = __ballot(big);
+        if ((tid & 63) == 0) flags[tid >> 6] = m;
+        __syncthreads();
+        for (uint32_t wv = 0; wv < kBuildBlock / 64; ++wv) {
+            uint64_t bits = flags[wv];
+            while (bits) {
+                const int64_t u = base + 64 * wv + __builtin_ctzll(bits);
+                bits &= bits - 1;
+                const int64_t off = g.row_ptr[u];
+                body(u, off, (int64_t)g.row_ptr[u + 1] - off);
+                __syncthreads();
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Virtual 32-bit word k of the scratch area kept in the second 16-byte half of
+// a row's entries (that half is written last).
+__device__ __forceinline__ uint32_t *scratch_word(uint4 *row, uint64_t k) {
+    return reinterpret_cast<uint32_t *>(row) + 8 * (k >> 2) + 4 + (k & 3);
+}
+__device__ __forceinline__ uint64_t *scratch_u64(uint4 *row, uint64_t k) {   // k even
+    return reinterpret_cast<uint64_t *>(scratch_word(row, k));
+}
+
+// ALIAS for a long row, one workgroup, same result as the worklist procedure.
+// Number the original small columns in the order they are popped (descending
+// index) l_1, l_2, ..., with deficits W - s and prefix sums D_0 = 0, D_1, ...;
+// and the large columns likewise g_1, g_2, ... with surpluses s - W and prefix
+// sums S_1, S_2, ... (exact integers: D_total = S_total).  Deficits are charged
+// to the large columns in order, a large column being demoted once the charges
+// exceed its surplus, and a demoted column passes its excess on to the next.
+// Hence:
+//   * l_i is paired with the top of the large stack when it is popped,
+//     g_J with J = min{j : S_j >= D_(i-1)};
+//   * g_j with S_j >= D_total is never demoted (a full bucket);
+//   * otherwise g_j is demoted while serving l_i, i = min{i : D_i > S_j}, keeps
+//     mass W - (D_i - S_j) and is paired with the next large column g_(j+1).
+// Both prefix sums come from block scans; every bucket is then independent.
+//
+// Scratch words: [0, n_s) small indices in pop order, [n_s, d) large indices
+// in pop order, then (at an even word) the u64 array P with P[0] = 0,
+// P[1..n_s] = D, P[n_s+1 .. n_s+n_l] = S.  3d + 3 words fit in the 4d words
+// of the second halves for d > 3.
+__global__ void __launch_bounds__(kBuildBlock) k_alias_build_big(GraphDev g, uint4 *__restrict__ out) {
+    __shared__ uint64_t sh64[kBuildBlock / 64];
+    __shared__ uint32_t sh32[kBuildBlock / 64];
+    const uint32_t tid = threadIdx.x;
+    for_each_big_row(g, [&](int64_t v, int64_t off, int64_t d) {
+        const uint32_t *__restrict__ w = g.weight + off;
+        const int32_t *__restrict__ col = g.col + off;
+        uint4 *__restrict__ row = out + 2 * off;
+        const uint64_t ud = (uint64_t)d;
+        (void)v;
+
+        uint64_t part = 0;
+        for (int64_t i = tid; i < d; i += kBuildBlock) part += w[i];
+        const uint64_t W = block_sum(part, sh64);
+        if (W == 0 || W > ~0ull / ud) {                        // no transition, or d*W would overflow
+            if (tid == 0) alias_row_sequential(g, off, d, out);
+            return;
+        }
+        uint32_t cs = 0;
+        for (int64_t i = tid; i < d; i += kBuildBlock) cs += ((uint64_t)w[i] * ud < W);
+        const uint64_t n_s = block_sum(cs, sh32);
+        const uint64_t n_l = ud - n_s;
+        const uint64_t pbase = ud + (ud & 1);
+        if (tid == 0) *scratch_u64(row, pbase) = 0;
+        uint64_t carry_s = 0, carry_l = 0, carry_D = 0, carry_S = 0;
+        for (int64_t r0 = 0; r0 < d; r0 += kBuildBlock) {
+            const int64_t r = r0 + tid;                        // position in descending index order
+            const bool in = r < d;
+            const int64_t i = d - 1 - r;
+            const uint64_t s_i = in ? (uint64_t)w[i] * ud : 0;
+            const bool small = in && s_i < W;
+            const bool large = in && !small;
+            uint32_t ts, tl;
+            uint64_t tD, tS;
+            const uint32_t is = block_inclusive_scan((uint32_t)small, sh32, ts);
+            const uint32_t il = block_inclusive_scan((uint32_t)large, sh32, tl);
+            const uint64_t iD = block_inclusive_scan<uint64_t>(small ? W - s_i : 0ull, sh64, tD);
+            const uint64_t iS = block_inclusive_scan<uint64_t>(large ? s_i - W : 0ull, sh64, tS);
+            if (small) {
+                const uint64_t pos = carry_s + is - 1;
+                *scratch_word(row, pos) = (uint32_t)i;
+                *scratch_u64(row, pbase + 2 * (pos + 1)) = carry_D + iD;
+            } else if (large) {
+                const uint64_t pos = carry_l + il - 1;
+                *scratch_word(row, n_s + pos) = (uint32_t)i;
+                *scratch_u64(row, pbase + 2 * (n_s + 1 + pos)) = carry_S + iS;
+            }
+            carry_s += ts; carry_l += tl; carry_D += tD; carry_S += tS;
+        }
+        __syncthreads();
+        const uint64_t D_total = carry_D;
+        for (uint64_t pos = tid; pos < n_s; pos += kBuildBlock) {       // small columns
+            const uint32_t l = *scratch_word(row, pos);
+            const uint64_t x = *scratch_u64(row, pbase + 2 * pos);   // D_(i-1)
+            uint64_t lo = 0, hi = n_l - 1;
+            while (lo < hi) {
+                const uint64_t mid = (lo + hi) >> 1;
+                if (*scratch_u64(row, pbase + 2 * (n_s + 1 + mid)) >= x) hi = mid; else lo = mid + 1;
+            }
+            const uint32_t gl = *scratch_word(row, n_s + lo);
+            row[2 * l] = make_uint4(frac32((uint64_t)w[l] * ud, W), (uint32_t)col[l], (uint32_t)col[gl], 0u);
+        }
+        for (uint64_t pos = tid; pos < n_l; pos += kBuildBlock) {       // large columns
+            const uint32_t gl = *scratch_word(row, n_s + pos);
+            const uint64_t S = *scratch_u64(row, pbase + 2 * (n_s + 1 + pos));
+            if (S >= D_total) {
+                row[2 * gl] = make_uint4(0xFFFFFFFFu, (uint32_t)col[gl], (uint32_t)col[gl], 0u);
+            } else {
+                uint64_t lo = 1, hi = n_s;
+                while (lo < hi) {
+                    const uint64_t mid = (lo + hi) >> 1;
+                    if (*scratch_u64(row, pbase + 2 * mid) > S) hi = mid; else lo = mid + 1;
+                }
+                const uint64_t Di = *scratch_u64(row, pbase + 2 * lo);
+                const uint32_t nx = *scratch_word(row, n_s + pos + 1);
+                row[2 * gl] = make_uint4(frac32(W - (Di - S), W), (uint32_t)col[gl], (uint32_t)col[nx], 0u);
+            }
+        }
+        __syncthreads();
+        for (int64_t j = tid; j < d; j += kBuildBlock) {                // second halves, over the scratch
+            const uint4 e = row[2 * j];
+            const uint2 ra = row_of(g, (int32_t)e.y), rb = row_of(g, (int32_t)e.z);
+            row[2 * j + 1] = make_uint4(ra.x, ra.y, rb.x, rb.y);
+        }
+    });
+}
+
 __global__ void k_its_build(GraphDev g, uint64_t *__restrict__ out) {
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= g.n) return;
     const int64_t lo = g.row_ptr[v], hi = g.row_ptr[v + 1];
+    if (hi - lo > kBigRow) return;
     uint64_t acc = 0;
     for (int64_t e = lo; e < hi; ++e) {
         acc += g.weight[e];
         out[e] = acc;
     }
+}
+
+__global__ void __launch_bounds__(kBuildBlock) k_its_build_big(GraphDev g, uint64_t *__restrict__ out) {
+    __shared__ uint64_t sh64[kBuildBlock / 64];
+    for_each_big_row(g, [&](int64_t, int64_t off, int64_t d) {
+        uint64_t carry = 0;
+        for (int64_t r0 = 0; r0 < d; r0 += kBuildBlock) {
+            const int64_t e = off + r0 + threadIdx.x;
+            const bool in = r0 + threadIdx.x < d;
+            uint64_t tot;
+            const uint64_t inc = block_inclusive_scan<uint64_t>(in ? (uint64_t)g.weight[e] : 0ull, sh64, tot);
+            if (in) out[e] = carry + inc;
+            carry += tot;
+        }
+    });
 }
 
 __global__ void k_zero_u64(unsigned long long *p) { *p = 0; }
@@ -146,12 +348,14 @@ __global__ void k_validate(GraphDev g, unsigned long long *__restrict__ bad) {
 }
 
 // MetaPath label index: stable counting sort of each row by label, one pass
-// per label value (O(L * d) per row, L <= kMaxIndexLabels).
+// per label value (O(L * d) per row, L <= kMaxIndexLabels); a thread per row
+// up to kBigRow slots, a workgroup with block scans above.
 __global__ void k_label_index_build(GraphDev g, uint32_t nlab, int32_t *__restrict__ loff,
                                     int32_t *__restrict__ lcol) {
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= g.n) return;
     const int64_t off = g.row_ptr[v], end = g.row_ptr[v + 1];
+    if (end - off > kBigRow) return;
     int32_t *__restrict__ rec = loff + v * (int64_t)(nlab + 1);
     int64_t pos = off;
     for (uint32_t x = 0; x < nlab; ++x) {
@@ -161,6 +365,30 @@ __global__ void k_label_index_build(GraphDev g, uint32_t nlab, int32_t *__restri
     }
     rec[nlab] = (int32_t)pos;
     for (; pos < end; ++pos) lcol[pos] = -1;      // edges whose label is >= L
+}
+
+__global__ void __launch_bounds__(kBuildBlock) k_label_index_build_big(GraphDev g, uint32_t nlab,
+                                                                       int32_t *__restrict__ loff,
+                                                                       int32_t *__restrict__ lcol) {
+    __shared__ uint32_t sh32[kBuildBlock / 64];
+    for_each_big_row(g, [&](int64_t v, int64_t off, int64_t d) {
+        const int64_t end = off + d;
+        int32_t *__restrict__ rec = loff + v * (int64_t)(nlab + 1);
+        int64_t pos = off;
+        for (uint32_t x = 0; x < nlab; ++x) {
+            if (threadIdx.x == 0) rec[x] = (int32_t)pos;
+            for (int64_t e0 = off; e0 < end; e0 += kBuildBlock) {
+                const int64_t e = e0 + threadIdx.x;
+                const bool hit = e < end && g.label[e] == x;
+                uint32_t tot;
+                const uint32_t inc = block_inclusive_scan((uint32_t)hit, sh32, tot);
+                if (hit) lcol[pos + inc - 1] = g.col[e];
+                pos += tot;
+            }
+        }
+        if (threadIdx.x == 0) rec[nlab] = (int32_t)pos;
+        for (int64_t e = pos + threadIdx.x; e < end; e += kBuildBlock) lcol[e] = -1;
+    });
 }
 
 // Row-annotated adjacency: every edge slot carries its destination's row
@@ -195,23 +423,32 @@ __global__ void k_symmetry_check(GraphDev g, unsigned long long *__restrict__ ba
 
 constexpr int kBuildThreads = 256;
 
+// Workgroups for the big-row kernels (each sweeps its own vertex chunks).
+int big_row_blocks(const GraphDev &g) {
+    return (int)std::min<int64_t>(((int64_t)g.n + kBuildBlock - 1) / kBuildBlock, 2048);
+}
+
 }  // namespace
 
 hipError_t launch_alias_build(const GraphDev &g, uint4 *out, hipStream_t s) {
     const int blocks = (g.n + kBuildThreads - 1) / kBuildThreads;
     hipLaunchKernelGGL(k_alias_build, dim3(blocks), dim3(kBuildThreads), 0, s, g, out);
+    hipLaunchKernelGGL(k_alias_build_big, dim3(big_row_blocks(g)), dim3(kBuildBlock), 0, s, g, out);
     return hipGetLastError();
 }
 
 hipError_t launch_its_build(const GraphDev &g, uint64_t *out, hipStream_t s) {
     const int blocks = (g.n + kBuildThreads - 1) / kBuildThreads;
     hipLaunchKernelGGL(k_its_build, dim3(blocks), dim3(kBuildThreads), 0, s, g, out);
+    hipLaunchKernelGGL(k_its_build_big, dim3(big_row_blocks(g)), dim3(kBuildBlock), 0, s, g, out);
     return hipGetLastError();
 }
 
 hipError_t launch_label_index_build(const GraphDev &g, uint32_t nlab, int32_t *loff, int32_t *lcol, hipStream_t s) {
     const int blocks = (g.n + kBuildThreads - 1) / kBuildThreads;
     hipLaunchKernelGGL(k_label_index_build, dim3(blocks), dim3(kBuildThreads), 0, s, g, nlab, loff, lcol);
+    hipLaunchKernelGGL(k_label_index_build_big, dim3(big_row_blocks(g)), dim3(kBuildBlock), 0, s, g, nlab, loff,
+                       lcol);
     return hipGetLastError();
 }
 

@@ -213,6 +213,90 @@ def test_its_table_matches_oracle(rmat_dir):
         assert np.array_equal(got, oracle.its_build(g.row_ptr, g.weight))
 
 
+def _long_rows_graph(wmax, seed):
+    """Rows of 1025..5000 slots (one workgroup each) in every weight regime, a
+    70000-slot star whose d*W passes 2^64 at wmax = 2^32-1, and short rows."""
+    rng = np.random.default_rng(seed)
+    n = 70001
+    edges, ws = [], []
+    for v in range(24):
+        d = int(rng.integers(1025, 5000)) if v % 4 else int(rng.integers(1, 1025))
+        nb = np.sort(rng.choice(np.arange(24, n), size=d, replace=False))
+        kind = v % 6
+        if kind == 0:
+            w = rng.integers(1, wmax + 1, size=d, dtype=np.uint64)
+        elif kind == 1:
+            w = np.full(d, min(wmax, 77), np.uint64)                 # every bucket full
+        elif kind == 2:
+            w = (rng.random(d) < 0.02) * rng.integers(1, wmax + 1, size=d, dtype=np.uint64)
+        elif kind == 3:
+            w = np.ones(d, np.uint64); w[int(rng.integers(0, d))] = wmax   # one dominant column
+        elif kind == 4:
+            w = np.zeros(d, np.uint64)                               # no transition
+        else:
+            w = rng.integers(0, 3, size=d).astype(np.uint64)
+        if not w.any() and kind != 4:
+            w[0] = 1
+        edges += [(v, int(x)) for x in nb]
+        ws += w.astype(np.uint32).tolist()
+    star = n - 1
+    for x in range(n - 1):
+        edges.append((star, x))
+        ws.append(int(rng.integers(wmax - wmax // 16, wmax + 1)))
+    for x in range(24, 3000):
+        edges.append((x, int(rng.integers(0, 24))))
+        ws.append(int(rng.integers(1, wmax + 1)))
+    return synth.from_edges(n, edges, ws)
+
+
+@pytest.mark.parametrize("wmax", [255, 2**32 - 1])
+def test_tables_long_rows(wmax):
+    g = _long_rows_graph(wmax, 41 + (wmax & 7))
+    case = Case(g)
+    log(f"  long-row tables m={g.m} max_deg={int(np.diff(g.row_ptr).max())}")
+    t = case.dev_table("alias")
+    torch.cuda.synchronize()
+    thr, alias = oracle.alias_build(g.row_ptr, g.weight)
+    bad = np.nonzero((_alias_got(t, g.m) != _alias_expected(g, thr, alias)).any(axis=1))[0]
+    assert bad.size == 0, f"alias entries differ at edge slots {bad[:10]}"
+    t = case.dev_table("its")
+    torch.cuda.synchronize()
+    got = t.buf[:8 * g.m].view(torch.int64).cpu().numpy().view(np.uint64)
+    assert np.array_equal(got, oracle.its_build(g.row_ptr, g.weight))
+
+
+def test_label_index_records_long_rows():
+    """Label index of rows up to 6000 slots: per-label offsets and a stable sort by label."""
+    rng = np.random.default_rng(12)
+    n, L = 8000, 5
+    edges, labs = [], []
+    for v in range(n):
+        d = int(rng.integers(1025, 6000)) if v < 12 else int(rng.integers(0, 6))
+        nb = np.sort(rng.choice(n, size=d, replace=False))
+        edges += [(v, int(x)) for x in nb if x != v]
+    labs = rng.integers(0, L + 2, size=len(edges)).tolist()   # some labels >= L stay out
+    g = synth.from_edges(n, edges, labels=labs)
+    case = Case(g)
+    t = case.label_index(L)
+    torch.cuda.synchronize()
+    raw = t.buf.view(torch.int32).cpu().numpy()
+    head = n * (L + 1)
+    pad = ((head * 4 + 255) // 256) * 256 // 4
+    loff = raw[:head].reshape(n, L + 1)
+    lcol = raw[pad:pad + g.m]
+    rp = g.row_ptr.astype(np.int64)
+    lab = g.label.astype(np.int64)
+    for v in range(n):
+        a, b = rp[v], rp[v + 1]
+        pos = a
+        for x in range(L):
+            assert loff[v, x] == pos, (v, x)
+            sel = g.col[a:b][lab[a:b] == x]
+            assert np.array_equal(lcol[pos:pos + sel.size], sel), (v, x)
+            pos += sel.size
+        assert loff[v, L] == pos
+        assert (lcol[pos:b] == -1).all()
+
 def test_validate_rejects_bad_graphs():
     g = synth.from_edges(4, [(0, 1), (0, 2), (1, 0), (2, 3)])
     G = trw.Graph(g.row_ptr, g.col)
