@@ -14,6 +14,9 @@ HIPCC_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall",
     # keep the compiler from forming packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # atomics here are issued by one lane on purpose; the atomic optimizer's
+    # broadcast of the result would wait for it at once (claims are made ahead)
+    "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
 ]
 
 

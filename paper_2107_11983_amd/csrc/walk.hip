@@ -201,58 +201,92 @@ k_walk_persistent(GraphDev g, TableDev t, WalkDev a, unsigned long long *__restr
     Walker w[WPL];
 #pragma unroll
     for (int i = 0; i < WPL; ++i) w[i].qi = kIdle;
-    uint32_t pool_next = 0, pool_end = 0;   // this wave's claimed id range (wave-uniform)
-    bool exhausted = false;
     const uint32_t lane = lane_id();
     const unsigned long long n_waves = ((unsigned long long)gridDim.x * blockDim.x + 63) / 64;
-    unsigned long long seen = 0;            // queue head after this wave's last claim (wave-uniform)
 
-    for (;;) {
-        // Admission / refill: idle slots take the next ids of the wave's chunk.
+    // Query starts are prepared ahead of need, one stage per iteration, so a
+    // walker's first move never waits for its source and row range: the
+    // loads of both stages are in flight together with the moves' reads.
+    //   S: a claimed query index and its source (load issued);
+    //   R: a query ready to start: source and row range (loads issued).
+    // The loaded values are first used right after the moves' reads have
+    // arrived (s_bad, r_deg), never at the top of the next iteration: there a
+    // wait for them would also wait for this iteration's stores.
+    uint32_t s_qi = kIdle, r_qi = kIdle;
+    int32_t s_src = 0, r_src = 0, r_lo = 0, r_hi = 0, r_deg = 0;
+    bool s_bad = false;
+
+    // Id ranges come from the queue head one claim ahead: the next range is
+    // requested when the current one is taken into use, so its atomic's
+    // latency is hidden too.  Guided sizes: a share of what was left at the
+    // previous claim, between 64 ids and `chunk`, so that early claims are
+    // large (few atomics) and late ones small (waves finish together).
+    auto guided = [&](unsigned long long seen) -> uint32_t {
+        const unsigned long long left = seen < a.nq ? a.nq - seen : 0;
+        const uint32_t take = (uint32_t)min(left / (2ull * n_waves), (unsigned long long)chunk);
+        return max(take, min(64u, chunk));
+    };
+    uint32_t pool_next = 0, pool_end = 0;   // the wave's current id range (wave-uniform)
+    uint32_t ahead_take = guided(0);
+    unsigned long long ahead_base = 0;      // lane 0: result of the claim issued ahead
+    if (lane == 0) ahead_base = atomicAdd(queue_head, (unsigned long long)ahead_take);
+    unsigned long long ahead_seen = __shfl(ahead_base, 0);   // the same, wave-wide, once it has arrived
+    bool ahead_pending = false;             // claim issued this iteration, ahead_seen not updated yet
+    bool exhausted = false;
+
+    // The exit test sits at the bottom of the loop: a break in the middle
+    // gives the compiler a loop edge on which the prepared loads look
+    // outstanding, and it then waits for them (and for every store before
+    // them) at the top of each iteration.
+    bool more = true;
+    do {
+        // Start: an idle walker takes the ready query (its loads were issued
+        // in an earlier iteration).
+#pragma unroll
         for (int i = 0; i < WPL; ++i) {
-            uint64_t idle = __ballot(w[i].qi == kIdle);
-            while (idle != 0 && !exhausted) {
-                uint32_t avail = pool_end - pool_next;
-                if (avail == 0) {
-                    // Guided claim: a share of what was left at this wave's previous claim,
-                    // between 64 ids and `chunk`, so that early claims are large (few
-                    // atomics) and late ones small (waves finish together).
-                    const unsigned long long left = seen < a.nq ? a.nq - seen : 0;
-                    uint32_t take = (uint32_t)min(left / (2ull * n_waves), (unsigned long long)chunk);
-                    take = max(take, min(64u, chunk));
-                    unsigned long long base = 0;
-                    if (lane == 0) base = atomicAdd(queue_head, (unsigned long long)take);
-                    base = __shfl(base, 0);
-                    seen = base + take;
-                    if (base >= a.nq) { exhausted = true; break; }
-                    pool_next = (uint32_t)base;
-                    pool_end = (uint32_t)min(base + take, (unsigned long long)a.nq);
-                    avail = pool_end - pool_next;
-                }
-                const uint32_t rk = rank_below(idle);
-                if (((idle >> lane) & 1ull) && rk < avail) {
-                    const uint32_t qi = pool_next + rk;
-                    const int32_t s = a.sources[qi];
-                    if (s < 0 || s >= g.n) {
-                        a.lengths[qi] = 0;
-                        a.status[qi] = ST_BAD_SOURCE;
-                    } else {
-                        w[i].qi = qi; w[i].cur = s; w[i].prev = -1; w[i].k = 0;
-                        w[i].poff = 0; w[i].pdeg = 0; w[i].need_row = !kNoRows;
-                        w[i].off = 0; w[i].deg = 1;
-                        w[i].path.start(a.paths + (uint64_t)qi * a.stride);
-                        w[i].path.push(s);
-                    }
-                }
-                pool_next += min((uint32_t)__popcll(idle), avail);
-                idle = __ballot(w[i].qi == kIdle);
+            if (w[i].qi == kIdle && r_qi != kIdle) {
+                w[i].qi = r_qi; w[i].cur = r_src; w[i].prev = -1; w[i].k = 0;
+                w[i].poff = 0; w[i].pdeg = 0; w[i].need_row = false;
+                w[i].off = r_lo; w[i].deg = kNoRows ? 1 : r_deg;
+                w[i].path.start(a.paths + (uint64_t)r_qi * a.stride);
+                w[i].path.push(r_src);
+                r_qi = kIdle;
             }
         }
-        bool any = false;
-#pragma unroll
-        for (int i = 0; i < WPL; ++i) any |= (w[i].qi != kIdle);
-        if (__ballot(any) == 0) break;   // every slot idle after refill: the queue is drained
-
+        // S -> R: the source is known; reject it or request its row range.
+        if (r_qi == kIdle && s_qi != kIdle) {
+            if (s_bad) {
+                a.lengths[s_qi] = 0;
+                a.status[s_qi] = ST_BAD_SOURCE;
+            } else {
+                r_qi = s_qi; r_src = s_src;
+                if (!kNoRows) { r_lo = g.row_ptr[s_src]; r_hi = g.row_ptr[s_src + 1]; }
+            }
+            s_qi = kIdle;
+        }
+        // Claim: lanes with an empty S take the next ids of the wave's range.
+        uint64_t need = __ballot(s_qi == kIdle);
+        while (need != 0 && !exhausted) {
+            uint32_t avail = pool_end - pool_next;
+            if (avail == 0) {
+                if (ahead_pending) { ahead_seen = __shfl(ahead_base, 0); ahead_pending = false; }   // rare
+                const unsigned long long base = ahead_seen;
+                if (base >= a.nq) { exhausted = true; break; }
+                pool_next = (uint32_t)base;
+                pool_end = (uint32_t)min(base + ahead_take, (unsigned long long)a.nq);
+                avail = pool_end - pool_next;
+                ahead_take = guided(base + ahead_take);
+                if (lane == 0) ahead_base = atomicAdd(queue_head, (unsigned long long)ahead_take);
+                ahead_pending = true;
+            }
+            const uint32_t rk = rank_below(need);
+            if (((need >> lane) & 1ull) && rk < avail) {
+                s_qi = pool_next + rk;
+                s_src = a.sources[s_qi];
+            }
+            pool_next += min((uint32_t)__popcll(need), avail);
+            need = __ballot(s_qi == kIdle);
+        }
         // Gather: row ranges the walkers do not carry yet (independent loads).
 #pragma unroll
         for (int i = 0; i < WPL; ++i) {
@@ -329,6 +363,16 @@ k_walk_persistent(GraphDev g, TableDev t, WalkDev a, unsigned long long *__restr
             }
         }
 
+        // The prepared starts' loads were issued before the moves' reads and
+        // have arrived with them.  The empty asm reads the loaded registers
+        // here, on every path through the loop, so that the compiler knows
+        // they are complete at the top of the next iteration.
+        asm volatile("" ::"v"(s_src), "v"(r_lo), "v"(r_hi), "v"(ahead_base));
+        s_bad = (uint32_t)s_src >= (uint32_t)g.n;
+        r_deg = r_hi - r_lo;
+        ahead_seen = __shfl(ahead_base, 0);
+        ahead_pending = false;
+
         // Update.
 #pragma unroll
         for (int i = 0; i < WPL; ++i) {
@@ -351,7 +395,13 @@ k_walk_persistent(GraphDev g, TableDev t, WalkDev a, unsigned long long *__restr
                 w[i].qi = kIdle;
             }
         }
-    }
+
+        // Done when the queue is drained and nothing is running or prepared.
+        bool any = r_qi != kIdle || s_qi != kIdle;
+#pragma unroll
+        for (int i = 0; i < WPL; ++i) any |= (w[i].qi != kIdle);
+        more = !exhausted || __ballot(any) != 0;
+    } while (more);
 }
 
 // ---------------------------------------------------------------------------
