@@ -432,6 +432,23 @@ def probe_gather(trw, torch, dev, cus):
     res["dependent_best_GBps_at_64B"] = round(best[1] * 64 / 1e9, 1)
     res["independent_best_GBps_at_64B"] = round(best[0] * 64 / 1e9, 1)
     log(f"gather ceiling: dependent {best[1]:.4g} reads/s, independent {best[0]:.4g} reads/s")
+    # the write side: random 16 B stores, 64 B blocks and whole 128 B lines
+    res["scatter"] = {}
+    for eb in (16, 64, 128):
+        grid = cus * 4
+        steps_w = 16
+        args = (ctypes.c_void_p(buf.data_ptr()), nbytes, eb, steps_w, grid, 256, s)
+        assert _abi.trw_probe_scatter(*args) == 0
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        assert _abi.trw_probe_scatter(*args) == 0
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b)
+        n = grid * 256 * steps_w
+        res["scatter"][str(eb)] = {"writes_per_s": round(n / (ms * 1e-3), 1), "GBps": round(n * eb / (ms * 1e6), 1),
+                                   "ms": round(ms, 3)}
+        log(f"scatter {eb} B: {n / (ms * 1e-3):.4g} writes/s, {n * eb / (ms * 1e6):.1f} GB/s")
     del buf
     return res
 

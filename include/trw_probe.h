@@ -33,6 +33,16 @@ int trw_probe_gather(const void *d_buf, uint64_t bytes, uint32_t elem_bytes, uin
                      int dependent, uint32_t grid, uint32_t block, void *d_sink, void *stream);
 
 /*
+ * grid x block lanes each write `steps` elements of `elem_bytes` (16, 64 or
+ * 128, written as 16-byte stores) at hashed, element-aligned positions of the
+ * `bytes`-long buffer d_buf (128-byte aligned, bytes / elem_bytes < 2^32).
+ * The random-write counterpart of trw_probe_gather: a walk writes one path
+ * row per query.  block: 64..256, a multiple of 64.
+ */
+int trw_probe_scatter(void *d_buf, uint64_t bytes, uint32_t elem_bytes, uint32_t steps, uint32_t grid,
+                      uint32_t block, void *stream);
+
+/*
  * Replay a request trace against a server (trw.h): request i (trw_request) is
  * submitted once arrival_ns[i] nanoseconds (non-decreasing) have passed since
  * the call began, and its completion is stored in completions[i]

@@ -197,8 +197,8 @@ class WalkBuffers:
 
     def __init__(self, graph: Graph, p: trw_walk_params, nq: int, mode=TRW_M_PERSISTENT, stride: int = 0):
         self.nq = nq
-        # rows start on 32-byte boundaries: a short walk's path then lands in one memory sector
-        self.stride = stride or ((p.max_len + 1 + 7) // 8 * 8)
+        # 64-byte rows: a path's last block is then written whole (entries past a path's end are unspecified)
+        self.stride = stride or ((p.max_len + 1 + 15) // 16 * 16)
         dev = graph.device
         self.paths = torch.empty((nq, self.stride), dtype=torch.int32, device=dev)
         self.lengths = torch.empty(nq, dtype=torch.int32, device=dev)

@@ -118,6 +118,7 @@ _SIGS = {
     # measurement probe (include/trw_probe.h)
     "trw_probe_fill": (ctypes.c_int, [_P, _u64, _u32, _P]),
     "trw_probe_gather": (ctypes.c_int, [_P, _u64, _u32, _u32, _u32, ctypes.c_int, _u32, _u32, _P, _P]),
+    "trw_probe_scatter": (ctypes.c_int, [_P, _u64, _u32, _u32, _u32, _u32, _P]),
     "trw_probe_serve_replay": (ctypes.c_int, [_P, _u32, _P, _P, _P, _u32]),
 }
 
@@ -166,4 +167,5 @@ trw_server_stats_get = lib.trw_server_stats_get
 trw_server_destroy = lib.trw_server_destroy
 trw_probe_fill = lib.trw_probe_fill
 trw_probe_gather = lib.trw_probe_gather
+trw_probe_scatter = lib.trw_probe_scatter
 trw_probe_serve_replay = lib.trw_probe_serve_replay

@@ -8,6 +8,12 @@
 // dependent form the next index is a hash of the value just read (so the reads
 // of one chain serialise, as in a walk), in the independent form it is a hash
 // of (lane, hop) only (the throughput ceiling with unlimited parallelism).
+//
+// Random-scatter probe: the same for writes, the other half of a walk's
+// traffic (every query writes its own path row).  Each lane writes `steps`
+// elements of `elem_bytes` (16, 64 or 128: one store, a 64-byte block or a
+// whole 128-byte cache line, in 16-byte stores) at hashed, element-aligned
+// positions.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -77,6 +83,19 @@ hipError_t pick_chains(const uint32_t *buf, uint64_t n_elems, uint32_t steps, ui
     }
 }
 
+template <int EB>
+__global__ void __launch_bounds__(256) k_scatter(uint4 *__restrict__ buf, uint64_t n_elems, uint32_t steps) {
+    const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t h = mix32(gid + 0x51ED270Bu);
+    for (uint32_t s = 0; s < steps; ++s) {
+        const uint64_t idx = ((uint64_t)h * n_elems) >> 32;
+        uint4 *p = buf + idx * (EB / 16);
+#pragma unroll
+        for (int j = 0; j < EB / 16; ++j) p[j] = make_uint4(gid, s, (uint32_t)j, h);
+        h = mix32(h + s + 1);
+    }
+}
+
 }  // namespace
 
 extern "C" {
@@ -104,6 +123,21 @@ int trw_probe_gather(const void *d_buf, uint64_t bytes, uint32_t elem_bytes, uin
     else if (elem_bytes == 8) e = pick_chains<8>(buf, n_elems, steps, chains, dependent, grid, block, sink, s);
     else e = pick_chains<4>(buf, n_elems, steps, chains, dependent, grid, block, sink, s);
     return e == hipSuccess ? 0 : 3;
+}
+
+int trw_probe_scatter(void *d_buf, uint64_t bytes, uint32_t elem_bytes, uint32_t steps, uint32_t grid,
+                      uint32_t block, void *stream) {
+    if (!d_buf || bytes < 128 || (reinterpret_cast<uintptr_t>(d_buf) & 127)) return 1;
+    if (!(elem_bytes == 16 || elem_bytes == 64 || elem_bytes == 128)) return 1;
+    if (block == 0 || block > 256 || block % 64 || grid == 0) return 1;
+    const uint64_t n_elems = bytes / elem_bytes;
+    if (n_elems >= (uint64_t(1) << 32)) return 1;
+    auto *buf = static_cast<uint4 *>(d_buf);
+    auto s = static_cast<hipStream_t>(stream);
+    if (elem_bytes == 16) hipLaunchKernelGGL(k_scatter<16>, dim3(grid), dim3(block), 0, s, buf, n_elems, steps);
+    else if (elem_bytes == 64) hipLaunchKernelGGL(k_scatter<64>, dim3(grid), dim3(block), 0, s, buf, n_elems, steps);
+    else hipLaunchKernelGGL(k_scatter<128>, dim3(grid), dim3(block), 0, s, buf, n_elems, steps);
+    return hipGetLastError() == hipSuccess ? 0 : 3;
 }
 
 }  // extern "C"

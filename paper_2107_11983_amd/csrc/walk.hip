@@ -389,7 +389,7 @@ k_walk_persistent(GraphDev g, TableDev t, WalkDev a, unsigned long long *__restr
                 else if (w[i].k == a.max_len) st = ST_LENGTH;
             }
             if (st) {
-                w[i].path.flush();
+                w[i].path.finish(a.paths + ((uint64_t)w[i].qi + 1) * a.stride);
                 a.lengths[w[i].qi] = w[i].k;
                 a.status[w[i].qi] = st;
                 w[i].qi = kIdle;

@@ -125,6 +125,28 @@ struct PathBuf {
         n = 0;
     }
 
+    // Last flush of a walk.  The entries after a path's end are unspecified,
+    // so the rest of the 64-byte block that holds the last entry is filled
+    // (with -1) as far as the row reaches: the block then goes to memory as
+    // one whole write rather than a partial one, which HBM has to merge
+    // with the old contents.  row_end: one past the row's last entry.  Rows
+    // that do not start on 16 bytes (any stride is allowed) get plain writes.
+    __device__ __forceinline__ void finish(const int32_t *row_end) {
+        if ((reinterpret_cast<uintptr_t>(p) & 15u) != 0 || p + 4 > row_end) {
+            flush();
+            return;
+        }
+        if (n > 0) {
+            *reinterpret_cast<int4 *>(p) = make_int4(b0, n > 1 ? b1 : -1, n > 2 ? b2 : -1, -1);
+            p += 4;
+            n = 0;
+        }
+        while ((reinterpret_cast<uintptr_t>(p) & 63u) != 0 && p + 4 <= row_end) {
+            *reinterpret_cast<int4 *>(p) = make_int4(-1, -1, -1, -1);
+            p += 4;
+        }
+    }
+
     __device__ __forceinline__ void push(int32_t v) {
         if (n == 0) b0 = v; else if (n == 1) b1 = v; else if (n == 2) b2 = v; else b3 = v;
         ++n;

@@ -372,6 +372,34 @@ def test_edge_cases(rmat_sym, rmat_dir):
         assert_same(gpu, ref, 1)
 
 
+
+@pytest.mark.parametrize("stride", [13, 16, 20, 81])
+def test_path_padding_stays_in_row(rmat_dir, stride):
+    """A walk may fill the rest of its last 64-byte block with -1, but only
+    inside its own row: other rows and the memory after the last row keep
+    their contents, and the paths still equal the oracle's."""
+    case = rmat_dir
+    g = case.g
+    src = synth.sources(5000, g.n, 12)
+    p = trw.make_params("ppr", "alias", 12, 5, stop_q32=trw.stop_threshold(0.2))
+    ref = oracle.walk(g.row_ptr, g.col, oracle.WalkParams(oracle.PPR, oracle.ALIAS, 12, 5, stop_q32=p.stop_q32),
+                      src, **case.orc_tables("alias"))
+    sentinel = 0x7EEEEEEE
+    for mode in (1, 0):
+        bufs = trw.WalkBuffers(case.G, p, len(src), mode, stride)
+        big = torch.full((len(src) + 3, stride), sentinel, dtype=torch.int32, device="cuda")
+        bufs.paths = big[:len(src)]
+        _, L, S = trw.walk(case.G, case.dev_table("alias"), p, torch.from_numpy(src).cuda(), mode=mode, bufs=bufs)
+        torch.cuda.synchronize()
+        B = big.cpu().numpy()
+        L = L.cpu().numpy().view(np.uint32)
+        assert (B[len(src):] == sentinel).all(), "writes past the last row"
+        assert np.array_equal(L, ref.lengths) and np.array_equal(S.cpu().numpy(), ref.status)
+        inside = np.arange(stride)[None, :] <= L[:, None]
+        assert np.array_equal(B[:len(src), :13][inside[:, :13]], ref.paths[inside[:, :13]])
+        past = B[:len(src)][~inside]
+        assert np.isin(past, [sentinel, -1]).all(), "a row's entries past its end hold another row's data"
+
 def test_zero_weight_rows_are_dead_ends():
     g = _weighted_rows_graph(9, 255)
     case = Case(g)
