@@ -51,7 +51,7 @@ def kernel_source_hash():
 
 
 def read_traffic(tag):
-    """HBM bytes per launch from a committed rocprofv3 counter summary, if it is current."""
+    """HBM bytes per launch (total, read, written) from a committed rocprofv3 counter summary, if current."""
     path = os.path.join(ROOT, "profiles", f"counters_{tag}.md")
     if not os.path.exists(path):
         return None, None
@@ -60,7 +60,8 @@ def read_traffic(tag):
     if kv.get("kernel_source_sha256_16") != kernel_source_hash():
         return None, "stale"
     try:
-        return float(kv["traffic_bytes_per_launch"]), path
+        return {"total": float(kv["traffic_bytes_per_launch"]), "read": float(kv.get("read_bytes_per_launch", "nan")),
+                "write": float(kv.get("write_bytes_per_launch", "nan"))}, path
     except KeyError:
         return None, None
 
@@ -216,7 +217,8 @@ def main():
         row_reads = moves + main_r["dead_ends"]
         alg_bytes = 8 * row_reads + entry * moves + 4 * moves + PER_QUERY_BYTES * valid_q + 5 * main_r["bad_sources"]
         achieved = alg_bytes / (avg_launch_ms * 1e-3) / 1e9
-        traffic, src = read_traffic(f"{wl.name}_{sampler}_{args.mode}")
+        measured, src = read_traffic(f"{wl.name}_{sampler}_{args.mode}")
+        traffic = measured["total"] if measured else None
         roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBPS, 5), "traffic": traffic,
                     "kernel": f"k_walk_persistent<{wl.algo},{sampler}>" if args.mode == "persistent"
@@ -258,6 +260,14 @@ def main():
             roofline["issued_random_reads_per_s"] = round(acc_s, 1)
             roofline["frac_of_dependent_gather_ceiling"] = round(acc_s / gather["dependent_best_reads_per_s"], 4)
             roofline["frac_of_independent_gather_ceiling"] = round(acc_s / gather["independent_best_reads_per_s"], 4)
+            # Both halves of the traffic against their measured random ceilings: the issued random
+            # reads at the gather rate plus the bytes written (counters) at the 64 B scatter rate.
+            if measured and measured["write"] == measured["write"] and gather.get("scatter"):
+                t_r = roofline.get("issued_random_reads_per_launch", roofline["random_reads_per_launch"]) / \
+                    gather["dependent_best_reads_per_s"]
+                t_w = measured["write"] / (gather["scatter"]["64"]["GBps"] * 1e9)
+                roofline["random_ceiling_ms"] = round(1e3 * (t_r + t_w), 4)
+                roofline["frac_of_random_ceiling"] = round((t_r + t_w) / (avg_launch_ms * 1e-3), 4)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -46,7 +46,7 @@ static thread_local std::string g_last_error;
 
 void set_error(const std::string &msg) { g_last_error = msg; }
 
-const DeviceInfo &device_info() {
+DeviceInfo device_info() {
     static std::mutex mu;
     static std::vector<DeviceInfo> cache;
     int dev = 0;
@@ -54,12 +54,14 @@ const DeviceInfo &device_info() {
     std::lock_guard<std::mutex> lk(mu);
     for (const auto &d : cache)
         if (d.device == dev) return d;
-    DeviceInfo di{dev, 256};
-    int cus = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
-        di.num_cus = cus;
+    DeviceInfo di{dev, 256, 64 * 1024};
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+        di.num_cus = v;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) == hipSuccess && v > 0)
+        di.lds_per_cu = v;
     cache.push_back(di);
-    return cache.back();
+    return di;
 }
 
 namespace {

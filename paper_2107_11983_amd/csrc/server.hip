@@ -269,7 +269,7 @@ extern "C" {
 
 trw_status trw_server_arena_bytes(const trw_server_cfg *cfg, size_t pool_bytes, size_t *bytes) {
     if (!cfg || !bytes) return sfail(TRW_E_INVALID, "cfg / bytes is NULL");
-    const DeviceInfo &di = device_info();
+    const DeviceInfo di = device_info();
     const uint32_t slots = cfg->max_slots ? cfg->max_slots : (uint32_t)di.num_cus * 2048;
     const uint32_t reqs = cfg->max_requests ? cfg->max_requests : 1024;
     if (slots % kServeBlock) return sfail(TRW_E_INVALID, "max_slots must be a multiple of 256");
@@ -286,7 +286,7 @@ trw_status trw_server_destroy(trw_server s);
 extern "C" trw_status trw_server_create(trw_graph g, trw_table alias, trw_table adjacency, const trw_server_cfg *cfg,
                                         void *d_arena, size_t arena_bytes, trw_server *out) {
     if (!g || !cfg || !out) return sfail(TRW_E_INVALID, "graph / cfg / out is NULL");
-    const DeviceInfo &di = device_info();
+    const DeviceInfo di = device_info();
     const uint32_t slots = cfg->max_slots ? cfg->max_slots : (uint32_t)di.num_cus * 2048;
     const uint32_t reqs = cfg->max_requests ? cfg->max_requests : 1024;
     const uint32_t steps = cfg->steps_per_tick ? cfg->steps_per_tick : 32;

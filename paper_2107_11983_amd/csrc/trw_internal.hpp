@@ -87,6 +87,7 @@ struct Tuning {
 struct DeviceInfo {
     int device;
     int num_cus;
+    int lds_per_cu;     // bytes of LDS a CU holds
 };
 
 // Host launchers (tables.hip, walk.hip).  Return hipSuccess or the launch error.
@@ -102,7 +103,7 @@ hipError_t launch_walk(const GraphDev &g, const TableDev &t, uint32_t algo, uint
                        const WalkDev &w, uint32_t mode, const Tuning &tu, const DeviceInfo &di,
                        void *d_ws, size_t ws_bytes, hipStream_t s);
 
-const DeviceInfo &device_info();
+DeviceInfo device_info();
 void set_error(const std::string &msg);
 
 // Table kinds behind a trw_table: the sampler codes for ALIAS / ITS tables,

@@ -26,6 +26,8 @@
 // coin r1 < thr; ITS draw = high half of (r1:r0) * W and a binary search over
 // the uint64 prefix; O-REJ darts compare r1 >> 16 with Q16 thresholds;
 // MetaPath counts the matching labels of the row and takes the j-th.
+#include <algorithm>
+
 #include "trw_device.hpp"
 #include "trw_internal.hpp"
 #include "walk_common.hpp"
@@ -177,8 +179,24 @@ __device__ __forceinline__ int32_t metapath_move(const GraphDev &g, const TableD
 // ---------------------------------------------------------------------------
 // Persistent schedule
 // ---------------------------------------------------------------------------
+// Lengths and status of a wave's queries are gathered in LDS, one slot per id
+// range the wave claims, and written with coalesced stores when the range's
+// last query has ended; stored one by one as walks end they would land on
+// scattered, partly written lines.  A range that finds no free slot, or any
+// range when the launch has no slots, is written directly.  A query carries
+// its place as code = slot * kStageQueries + index in the range.
+constexpr uint32_t kStageQueries = 256;        // ids per staged range (queue_chunk <= this)
+constexpr uint32_t kStageDirect = 0xFFFFFFFFu;
+constexpr uint32_t kMaxStageSlots = 8;
+struct StageSlot {
+    uint32_t base, size, left, pad;            // size 0: free
+    uint16_t len[kStageQueries];               // moves (max_len <= 65535)
+    uint8_t st[kStageQueries];
+};
+
 struct Walker {
     uint32_t qi;     // index in the batch, kIdle when the slot is free
+    uint32_t code;   // where its length and status go (kStageDirect: straight to memory)
     int32_t cur;
     int32_t prev;
     uint32_t k;
@@ -193,7 +211,7 @@ struct Walker {
 template <uint32_t ALGO, uint32_t SMP, int WPL>
 __global__ void __launch_bounds__(256)
 k_walk_persistent(GraphDev g, TableDev t, WalkDev a, unsigned long long *__restrict__ queue_head,
-                  uint32_t chunk, uint32_t coop) {
+                  uint32_t chunk, uint32_t coop, uint32_t n_slots) {
     constexpr bool kStatic = (ALGO == ALG_DEEPWALK || ALGO == ALG_PPR);
     constexpr bool kAlias = kStatic && SMP == SMP_ALIAS;
     constexpr bool kOneRead = kAlias || (kStatic && SMP == SMP_NAIVE_ADJ);   // entry carries the next row
@@ -203,6 +221,24 @@ k_walk_persistent(GraphDev g, TableDev t, WalkDev a, unsigned long long *__restr
     for (int i = 0; i < WPL; ++i) w[i].qi = kIdle;
     const uint32_t lane = lane_id();
     const unsigned long long n_waves = ((unsigned long long)gridDim.x * blockDim.x + 63) / 64;
+    extern __shared__ StageSlot stage_mem[];
+    StageSlot *slots = stage_mem + (threadIdx.x >> 6) * n_slots;   // this wave's
+    for (uint32_t i = 0; i < n_slots; ++i)
+        if (lane == 0) slots[i].size = 0;
+    uint32_t done_slots = 0;                // per lane: slots whose last query this lane ended
+
+    // A query ended: record its length and status.
+    auto record = [&](uint32_t code, uint32_t qi, uint32_t k, uint8_t st) {
+        if (code == kStageDirect) {
+            a.lengths[qi] = k;
+            a.status[qi] = st;
+        } else {
+            StageSlot &sl = slots[code / kStageQueries];
+            sl.len[code % kStageQueries] = (uint16_t)k;
+            sl.st[code % kStageQueries] = st;
+            if (atomicSub(&sl.left, 1u) == 1u) done_slots |= 1u << (code / kStageQueries);
+        }
+    };
 
     // Query starts are prepared ahead of need, one stage per iteration, so a
     // walker's first move never waits for its source and row range: the
@@ -212,7 +248,7 @@ k_walk_persistent(GraphDev g, TableDev t, WalkDev a, unsigned long long *__restr
     // The loaded values are first used right after the moves' reads have
     // arrived (s_bad, r_deg), never at the top of the next iteration: there a
     // wait for them would also wait for this iteration's stores.
-    uint32_t s_qi = kIdle, r_qi = kIdle;
+    uint32_t s_qi = kIdle, r_qi = kIdle, s_code = kStageDirect, r_code = kStageDirect;
     int32_t s_src = 0, r_src = 0, r_lo = 0, r_hi = 0, r_deg = 0;
     bool s_bad = false;
 
@@ -227,6 +263,7 @@ k_walk_persistent(GraphDev g, TableDev t, WalkDev a, unsigned long long *__restr
         return max(take, min(64u, chunk));
     };
     uint32_t pool_next = 0, pool_end = 0;   // the wave's current id range (wave-uniform)
+    uint32_t pool_base = 0, pool_slot = kStageDirect;   // its first id and staging slot
     uint32_t ahead_take = guided(0);
     unsigned long long ahead_base = 0;      // lane 0: result of the claim issued ahead
     if (lane == 0) ahead_base = atomicAdd(queue_head, (unsigned long long)ahead_take);
@@ -245,7 +282,7 @@ k_walk_persistent(GraphDev g, TableDev t, WalkDev a, unsigned long long *__restr
 #pragma unroll
         for (int i = 0; i < WPL; ++i) {
             if (w[i].qi == kIdle && r_qi != kIdle) {
-                w[i].qi = r_qi; w[i].cur = r_src; w[i].prev = -1; w[i].k = 0;
+                w[i].qi = r_qi; w[i].code = r_code; w[i].cur = r_src; w[i].prev = -1; w[i].k = 0;
                 w[i].poff = 0; w[i].pdeg = 0; w[i].need_row = false;
                 w[i].off = r_lo; w[i].deg = kNoRows ? 1 : r_deg;
                 w[i].path.start(a.paths + (uint64_t)r_qi * a.stride);
@@ -256,10 +293,9 @@ k_walk_persistent(GraphDev g, TableDev t, WalkDev a, unsigned long long *__restr
         // S -> R: the source is known; reject it or request its row range.
         if (r_qi == kIdle && s_qi != kIdle) {
             if (s_bad) {
-                a.lengths[s_qi] = 0;
-                a.status[s_qi] = ST_BAD_SOURCE;
+                record(s_code, s_qi, 0, ST_BAD_SOURCE);
             } else {
-                r_qi = s_qi; r_src = s_src;
+                r_qi = s_qi; r_code = s_code; r_src = s_src;
                 if (!kNoRows) { r_lo = g.row_ptr[s_src]; r_hi = g.row_ptr[s_src + 1]; }
             }
             s_qi = kIdle;
@@ -275,6 +311,15 @@ k_walk_persistent(GraphDev g, TableDev t, WalkDev a, unsigned long long *__restr
                 pool_next = (uint32_t)base;
                 pool_end = (uint32_t)min(base + ahead_take, (unsigned long long)a.nq);
                 avail = pool_end - pool_next;
+                pool_base = pool_next;
+                pool_slot = kStageDirect;
+                for (uint32_t i = 0; i < n_slots; ++i) {
+                    if (slots[i].size == 0) {
+                        if (lane == 0) { slots[i].base = pool_base; slots[i].size = avail; slots[i].left = avail; }
+                        pool_slot = i;
+                        break;
+                    }
+                }
                 ahead_take = guided(base + ahead_take);
                 if (lane == 0) ahead_base = atomicAdd(queue_head, (unsigned long long)ahead_take);
                 ahead_pending = true;
@@ -282,6 +327,7 @@ k_walk_persistent(GraphDev g, TableDev t, WalkDev a, unsigned long long *__restr
             const uint32_t rk = rank_below(need);
             if (((need >> lane) & 1ull) && rk < avail) {
                 s_qi = pool_next + rk;
+                s_code = pool_slot == kStageDirect ? kStageDirect : pool_slot * kStageQueries + (s_qi - pool_base);
                 s_src = a.sources[s_qi];
             }
             pool_next += min((uint32_t)__popcll(need), avail);
@@ -390,9 +436,29 @@ k_walk_persistent(GraphDev g, TableDev t, WalkDev a, unsigned long long *__restr
             }
             if (st) {
                 w[i].path.finish(a.paths + ((uint64_t)w[i].qi + 1) * a.stride);
-                a.lengths[w[i].qi] = w[i].k;
-                a.status[w[i].qi] = st;
+                record(w[i].code, w[i].qi, w[i].k, st);
                 w[i].qi = kIdle;
+            }
+        }
+
+        // Ranges whose last query ended in this iteration: coalesced writes.
+        if (__ballot(done_slots != 0) != 0) {
+            uint32_t wave_done = done_slots;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) wave_done |= __shfl_xor(wave_done, o);
+            done_slots = 0;
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            while (wave_done != 0) {
+                const uint32_t sl_i = __builtin_ctz(wave_done);
+                wave_done &= wave_done - 1;
+                StageSlot &sl = slots[sl_i];
+                const uint32_t base = sl.base, size = sl.size;
+                for (uint32_t j = lane; j < size; j += 64) {
+                    a.lengths[base + j] = sl.len[j];
+                    a.status[base + j] = sl.st[j];
+                }
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                if (lane == 0) sl.size = 0;
             }
         }
 
@@ -545,15 +611,30 @@ hipError_t run_persistent(const GraphDev &g, const TableDev &t, const WalkDev &w
     const uint64_t max_useful = (waves_needed * 64 + threads - 1) / threads;
     if (blocks > max_useful) blocks = max_useful;
     if (blocks == 0) blocks = 1;
+    // Staging slots per wave: as many as the CU's LDS holds for blocks_per_cu
+    // resident blocks (so staging never lowers occupancy), at most
+    // kMaxStageSlots and 64 KiB per block; none when ranges can exceed a slot.
+    const uint32_t waves = threads / 64;
+    uint32_t n_slots = 0;
+    if (tu.queue_chunk <= kStageQueries) {
+        const uint64_t per_wave = (uint64_t)di.lds_per_cu / ((uint64_t)tu.blocks_per_cu * waves);
+        n_slots = (uint32_t)std::min<uint64_t>(per_wave / sizeof(StageSlot), kMaxStageSlots);
+        while (n_slots > 0 && (uint64_t)n_slots * waves * sizeof(StageSlot) > 64 * 1024) --n_slots;
+        if (n_slots < 2) n_slots = 0;
+    }
+    const size_t lds = (size_t)n_slots * waves * sizeof(StageSlot);
     switch (tu.walkers_per_lane) {
         case 2:
-            hipLaunchKernelGGL((k_walk_persistent<ALGO, SMP, 2>), dim3(blocks), dim3(threads), 0, s, g, t, w, head, tu.queue_chunk, tu.coop_degree);
+            hipLaunchKernelGGL((k_walk_persistent<ALGO, SMP, 2>), dim3(blocks), dim3(threads), lds, s, g, t, w, head,
+                               tu.queue_chunk, tu.coop_degree, n_slots);
             break;
         case 4:
-            hipLaunchKernelGGL((k_walk_persistent<ALGO, SMP, 4>), dim3(blocks), dim3(threads), 0, s, g, t, w, head, tu.queue_chunk, tu.coop_degree);
+            hipLaunchKernelGGL((k_walk_persistent<ALGO, SMP, 4>), dim3(blocks), dim3(threads), lds, s, g, t, w, head,
+                               tu.queue_chunk, tu.coop_degree, n_slots);
             break;
         default:
-            hipLaunchKernelGGL((k_walk_persistent<ALGO, SMP, 1>), dim3(blocks), dim3(threads), 0, s, g, t, w, head, tu.queue_chunk, tu.coop_degree);
+            hipLaunchKernelGGL((k_walk_persistent<ALGO, SMP, 1>), dim3(blocks), dim3(threads), lds, s, g, t, w, head,
+                               tu.queue_chunk, tu.coop_degree, n_slots);
     }
     return hipGetLastError();
 }
