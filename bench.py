@@ -28,8 +28,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
-KERNEL_SOURCES = ["paper_2107_11983_amd/csrc/walk.hip", "paper_2107_11983_amd/csrc/trw_device.hpp",
-                  "paper_2107_11983_amd/csrc/trw_internal.hpp"]
+KERNEL_SOURCES = ["paper_2107_11983_amd/csrc/walk.hip", "paper_2107_11983_amd/csrc/walk_common.hpp",
+                  "paper_2107_11983_amd/csrc/trw_device.hpp", "paper_2107_11983_amd/csrc/trw_internal.hpp"]
 
 # Algorithmic bytes ("Measurement"): per move the row range
 # (two int32 row offsets) 8 B, the sampling entry the move needs and the path

@@ -112,9 +112,23 @@ trw_status check_params(trw_graph g, const trw_walk_params *p) {
 // best at low occupancy (2 workgroups of 256 per CU: fewer requests queued in
 // the memory system), walks that scan rows or search adjacency at full
 // occupancy.
+// Defaults measured on MI355X (R-MAT workloads of the benchmark): walks that
+// make one random read per move reach the memory system's random-access
+// ceiling at low occupancy, where more requests in flight only add
+// contention; PPR's short walks also gain from two walkers per lane.
 Tuning resolve_tuning(const trw_walk_params *p, uint32_t mode, const trw_tuning *t) {
-    const bool table_walk = (p->algo == TRW_A_DEEPWALK || p->algo == TRW_A_PPR) && p->sampler == TRW_S_ALIAS;
-    Tuning tu{1, 256, (mode == TRW_M_PERSISTENT && table_walk) ? 2u : 8u, 256, 256};
+    const bool static_walk = p->algo == TRW_A_DEEPWALK || p->algo == TRW_A_PPR;
+    Tuning tu{1, 256, 8, 256, 256};
+    if (mode == TRW_M_PERSISTENT) {
+        if (static_walk && p->sampler == TRW_S_ALIAS) {
+            tu.blocks_per_cu = p->algo == TRW_A_PPR ? 1 : 2;
+            tu.walkers_per_lane = p->algo == TRW_A_PPR ? 2 : 1;
+        } else if (static_walk && p->sampler == TRW_S_ITS) {
+            tu.blocks_per_cu = 2;
+        } else if (p->algo == TRW_A_METAPATH) {
+            tu.blocks_per_cu = 4;
+        }
+    }
     if (t) {
         if (t->walkers_per_lane == 1 || t->walkers_per_lane == 2 || t->walkers_per_lane == 4)
             tu.walkers_per_lane = t->walkers_per_lane;
