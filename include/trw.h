@@ -225,7 +225,9 @@ typedef struct {
 trw_status trw_walk_workspace_bytes(trw_graph g, const trw_walk_params *p, uint64_t nq,
                                     uint32_t mode, size_t *bytes);
 
-/* The library's default tuning for this graph, params and mode. */
+/* The library's default tuning for this graph, params and mode (what trw_walk
+ * uses when given no tuning).  For METAPATH it is the default without a label
+ * index; with one, trw_walk runs 4 blocks per CU instead of 8. */
 trw_status trw_default_tuning(trw_graph g, const trw_walk_params *p, uint32_t mode, trw_tuning *out);
 
 /*

@@ -116,7 +116,7 @@ trw_status check_params(trw_graph g, const trw_walk_params *p) {
 // make one random read per move reach the memory system's random-access
 // ceiling at low occupancy, where more requests in flight only add
 // contention; PPR's short walks also gain from two walkers per lane.
-Tuning resolve_tuning(const trw_walk_params *p, uint32_t mode, const trw_tuning *t) {
+Tuning resolve_tuning(const trw_walk_params *p, uint32_t mode, const trw_tuning *t, bool label_index) {
     const bool static_walk = p->algo == TRW_A_DEEPWALK || p->algo == TRW_A_PPR;
     Tuning tu{1, 256, 8, 256, 256};
     if (mode == TRW_M_PERSISTENT) {
@@ -125,8 +125,8 @@ Tuning resolve_tuning(const trw_walk_params *p, uint32_t mode, const trw_tuning 
             tu.walkers_per_lane = p->algo == TRW_A_PPR ? 2 : 1;
         } else if (static_walk && p->sampler == TRW_S_ITS) {
             tu.blocks_per_cu = 2;
-        } else if (p->algo == TRW_A_METAPATH) {
-            tu.blocks_per_cu = 4;
+        } else if (p->algo == TRW_A_METAPATH && label_index) {
+            tu.blocks_per_cu = 4;       // the row scans without an index want the occupancy
         }
     }
     if (t) {
@@ -304,7 +304,7 @@ trw_status trw_default_tuning(trw_graph g, const trw_walk_params *p, uint32_t mo
     trw_status st = check_params(g, p);
     if (st != TRW_OK) return st;
     if (!out) return fail(TRW_E_INVALID, "out is NULL");
-    const Tuning tu = resolve_tuning(p, mode, nullptr);
+    const Tuning tu = resolve_tuning(p, mode, nullptr, false);
     std::memset(out, 0, sizeof(*out));
     out->walkers_per_lane = tu.walkers_per_lane;
     out->block_threads = tu.block_threads;
@@ -379,7 +379,7 @@ trw_status trw_walk(trw_graph g, trw_table table, const trw_walk_params *p, cons
                                                    label_index_loff_bytes(g->dev, table->nlab));
         t.nlab = table->nlab;
     }
-    const Tuning tu = resolve_tuning(p, mode, tuning);
+    const Tuning tu = resolve_tuning(p, mode, tuning, label_index);
     hipError_t e = launch_walk(g->dev, t, p->algo, p->sampler, w, mode, tu, device_info(), d_ws, ws_bytes,
                                static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return device_fail(e, "walk launch");
