@@ -85,7 +85,9 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=10000, help="measured requests (served workload)")
     ap.add_argument("--serve-scale", type=int, default=0, help="override the served graph's scale (tests)")
     ap.add_argument("--serve-slots-per-cu", type=int, default=2048)
-    ap.add_argument("--serve-steps", type=int, default=32, help="moves per walker slot per tick")
+    ap.add_argument("--serve-steps", type=int, default=16, help="moves per walker slot per tick")
+    ap.add_argument("--serve-pipelined", type=int, default=1, help="0: serial ticks (read each tick before queueing the next)")
+    ap.add_argument("--serve-rate", type=float, default=0.0, help="offered requests/s (0: 0.7x the saturated rate)")
     ap.add_argument("--profile-pass", action="store_true",
                     help="short run for counter collection: a 1 GiB copy (calibration) then the walk only")
     args = ap.parse_args()
@@ -354,7 +356,7 @@ def bench_served(args, wl, np, torch, synth, trw, props):
     torch.cuda.synchronize()
     slots = props.multi_processor_count * args.serve_slots_per_cu
     srv = trw.Server(G, alias, adj, pool_bytes=8 << 30, max_slots=slots, max_requests=1024,
-                     steps_per_tick=args.serve_steps)
+                     steps_per_tick=args.serve_steps, pipelined=bool(args.serve_pipelined))
 
     def replay(lo, hi, arrivals):
         comp = (_abi.trw_completion * (hi - lo))()
@@ -375,8 +377,8 @@ def bench_served(args, wl, np, torch, synth, trw, props):
     st0 = srv.stats()
     log(f"saturated: {n_sat} requests in {wall:.3f}s = {sat_rps:.0f} req/s, {sat_steps:.4g} steps/s; "
         f"{st0['ticks']} ticks, device {st0['tick_device_ns'] / 1e6:.1f} ms")
-    # offered load 0.7x saturation, Poisson arrivals (exponential gaps from seeded uniforms)
-    rate = 0.7 * sat_rps
+    # offered load 0.7x saturation (or a fixed rate), Poisson arrivals (exponential gaps from seeded uniforms)
+    rate = args.serve_rate or 0.7 * sat_rps
     u = synth.uniform_f64(n_warm + n_meas, wl.walk_seed ^ 0x9015)
     arrivals = np.cumsum(-np.log(u) / rate) * 1e9
     comp, wall, moves = replay(n_sat, N, arrivals - arrivals[0])
@@ -391,7 +393,8 @@ def bench_served(args, wl, np, torch, synth, trw, props):
         "ms_per_step": round(1000 * wall / (n_warm + n_meas), 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u32", "data": "synthetic",
         "config": {"workload": f"{wl.name}: served mix of DeepWalk-80 ALIAS / PPR-0.2 ALIAS / Node2Vec p=2 q=0.5 "
-                               f"len 80, requests of U{{1..4096}} queries, Poisson arrivals at 0.7x saturation; "
+                               f"len 80, requests of U{{1..4096}} queries, Poisson arrivals at "
+                               f"{'%.0f req/s' % args.serve_rate if args.serve_rate else '0.7x saturation'}; "
                                f"R-MAT 2^{int(np.log2(g.n))} symmetric avg deg {wl.avg_degree}, uint32 weights 1..255",
                    "n": g.n, "m": g.m, "parallelism": "1 GPU"},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3), "p99": round(float(np.percentile(lat, 99)), 3),
@@ -400,6 +403,7 @@ def bench_served(args, wl, np, torch, synth, trw, props):
         "offered_req_per_s": round(rate, 1), "achieved_req_per_s": round(n_meas / span, 1),
         "saturated": {"req_per_s": round(sat_rps, 1), "steps_per_s": round(sat_steps, 1)},
         "server": {"ticks": st["ticks"], "steps_per_tick": args.serve_steps, "slots": slots,
+                   "pipelined": bool(args.serve_pipelined),
                    "max_requests": 1024, "pool_bytes": st["pool_bytes"],
                    "tick_device_ms_mean": round(st["tick_device_ns"] / max(st["ticks"], 1) / 1e6, 4)},
         "preprocess_ms": pre,

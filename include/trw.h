@@ -282,9 +282,13 @@ typedef struct trw_server_s *trw_server;
 typedef struct {
     uint32_t max_slots;        /* walker slots, a multiple of 256; 0 = 2048 per CU */
     uint32_t max_requests;     /* requests admitted at once, <= 65536; 0 = 1024 */
-    uint32_t steps_per_tick;   /* moves per slot per tick; 0 = 32 */
+    uint32_t steps_per_tick;   /* moves per slot per tick; 0 = 16 */
     uint32_t use_hipgraph;     /* 1: replay the tick as a captured HIP graph */
-    uint32_t reserved[4];
+    uint32_t serial_ticks;     /* 0 (default): the next tick is queued before the host reads the
+                                  last one, whose finished requests are delivered on a second
+                                  stream while the next tick runs.  1: each tick is read as it
+                                  ends and its outputs delivered before the next one is queued */
+    uint32_t reserved[3];
 } trw_server_cfg;
 
 enum { TRW_REQ_HOST = 1 };     /* sources / paths / lengths / status are host memory */

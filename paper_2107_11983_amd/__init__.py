@@ -248,11 +248,12 @@ class Server:
 
     def __init__(self, graph: Graph, alias: Optional[Table] = None, adjacency: Optional[Table] = None,
                  pool_bytes: int = 1 << 30, max_slots: int = 0, max_requests: int = 0, steps_per_tick: int = 0,
-                 use_hipgraph: bool = True):
+                 use_hipgraph: bool = True, pipelined: bool = True):
         self.graph = graph
         cfg = trw_server_cfg()
         cfg.max_slots, cfg.max_requests, cfg.steps_per_tick = max_slots, max_requests, steps_per_tick
         cfg.use_hipgraph = 1 if use_hipgraph else 0
+        cfg.serial_ticks = 0 if pipelined else 1
         nbytes = ctypes.c_size_t(0)
         check(_abi.trw_server_arena_bytes(ctypes.byref(cfg), pool_bytes, ctypes.byref(nbytes)))
         self.arena = torch.empty(int(nbytes.value), dtype=torch.uint8, device=graph.device)

@@ -168,7 +168,14 @@ struct Active {
     size_t out_off;            // offset of the outputs inside the request's pool range
     bool finishing = false;
     bool cancelled = false;
-    hipEvent_t copied = nullptr;   // host destinations: the output copies
+};
+
+// Output copies of the requests that finished in one tick, in flight on the
+// delivery stream; the requests complete when `done` has been reached.
+struct Batch {
+    hipEvent_t done = nullptr;
+    int jobs_buf = 0;                  // which half of the pinned job table it used
+    std::vector<uint64_t> ids;
 };
 
 }  // namespace
@@ -182,23 +189,31 @@ struct trw_server_s {
     TableDev t;
     uint32_t slots, max_reqs, ring, steps;
     bool use_graph;
+    bool pipelined;
     int device;
     // device memory
     char *arena;
     Layout lay;
     ServeDev dev;
     RangeAllocator pool;
-    // host staging (pinned)
+    // host staging (pinned).  Ticks are pipelined one deep: while tick i runs
+    // the host reads tick i-1's counters and delivers its finished requests on
+    // a second stream, so the tail, the counter read-back and the job table
+    // have two halves, used by alternate ticks (batches).
     ReqDesc *h_desc = nullptr;                // mirror of the device descriptor table
     Chunk *h_ring = nullptr;
-    unsigned long long *h_tail = nullptr;
-    uint32_t *h_done = nullptr;               // completion counters followed by the moves counter
-    CopyJob *h_jobs = nullptr;
-    hipEvent_t delivered = nullptr;
+    unsigned long long *h_tail = nullptr;     // [2]
+    uint32_t *h_done = nullptr;               // [2] x (completion counters, then the moves counter)
+    CopyJob *h_jobs = nullptr;                // [2] x 3 * max_requests
     bool desc_dirty = false;
-    hipStream_t stream = nullptr;
-    hipEvent_t tick_done = nullptr;
-    hipEvent_t tick_start = nullptr;
+    hipStream_t stream = nullptr;             // ticks and the copies that feed them
+    hipStream_t deliver_stream = nullptr;     // output copies of finished requests
+    hipEvent_t tick_done[2] = {nullptr, nullptr};
+    hipEvent_t tick_start[2] = {nullptr, nullptr};
+    std::deque<Batch> batches;
+    std::vector<hipEvent_t> spare_events;
+    uint64_t n_batches = 0;
+    std::vector<uint32_t> slot_done;          // a request slot's completion counter once all its requests ended
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     // scheduling state (guarded by mu)
@@ -289,7 +304,7 @@ extern "C" trw_status trw_server_create(trw_graph g, trw_table alias, trw_table 
     const DeviceInfo di = device_info();
     const uint32_t slots = cfg->max_slots ? cfg->max_slots : (uint32_t)di.num_cus * 2048;
     const uint32_t reqs = cfg->max_requests ? cfg->max_requests : 1024;
-    const uint32_t steps = cfg->steps_per_tick ? cfg->steps_per_tick : 32;
+    const uint32_t steps = cfg->steps_per_tick ? cfg->steps_per_tick : 16;
     if (slots % kServeBlock || slots > (1u << 24)) return sfail(TRW_E_INVALID, "max_slots must be a multiple of 256, <= 2^24");
     if (reqs > 65536) return sfail(TRW_E_INVALID, "max_requests must be <= 65536");
     const uint32_t ring = 1u << 20;
@@ -315,6 +330,7 @@ extern "C" trw_status trw_server_create(trw_graph g, trw_table alias, trw_table 
     s->t = t;
     s->slots = slots; s->max_reqs = reqs; s->ring = ring; s->steps = steps;
     s->use_graph = cfg->use_hipgraph != 0;
+    s->pipelined = cfg->serial_ticks == 0;
     s->device = di.device;
     s->arena = static_cast<char *>(d_arena);
     s->lay = lay;
@@ -331,17 +347,20 @@ extern "C" trw_status trw_server_create(trw_graph g, trw_table alias, trw_table 
     s->dev.waves = reinterpret_cast<WaveState *>(a + lay.waves);
 
     hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipEventCreate(&s->tick_done);
-    if (e == hipSuccess) e = hipEventCreate(&s->tick_start);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->deliver_stream, hipStreamNonBlocking);
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+        e = hipEventCreate(&s->tick_done[i]);
+        if (e == hipSuccess) e = hipEventCreate(&s->tick_start[i]);
+    }
     if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_desc, sizeof(ReqDesc) * reqs, hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_ring, sizeof(Chunk) * ring, hipHostMallocDefault);
-    if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_tail, sizeof(unsigned long long), hipHostMallocDefault);
-    if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_done, lay.done_bytes, hipHostMallocDefault);
-    if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_jobs, sizeof(CopyJob) * 3 * (size_t)reqs, hipHostMallocDefault);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->delivered, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_tail, 2 * sizeof(unsigned long long), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_done, 2 * lay.done_bytes, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_jobs, 2 * sizeof(CopyJob) * 3 * (size_t)reqs, hipHostMallocDefault);
     if (e == hipSuccess) {
         std::memset(s->h_desc, 0, sizeof(ReqDesc) * reqs);
-        std::memset(s->h_done, 0, lay.done_bytes);
+        std::memset(s->h_done, 0, 2 * lay.done_bytes);
+        s->slot_done.assign(reqs, 0u);
     }
     if (e == hipSuccess) {
         // zero the counters, descriptors and waves; mark every slot free (0xFF bytes)
@@ -450,16 +469,20 @@ extern "C" trw_status trw_server_destroy(trw_server s) {
     if (s->stream) (void)hipStreamSynchronize(s->stream);
     if (s->graph_exec) (void)hipGraphExecDestroy(s->graph_exec);
     if (s->graph) (void)hipGraphDestroy(s->graph);
-    if (s->tick_done) (void)hipEventDestroy(s->tick_done);
-    if (s->tick_start) (void)hipEventDestroy(s->tick_start);
-    for (auto &a : s->active)
-        if (a.copied) (void)hipEventDestroy(a.copied);
+    if (s->deliver_stream) (void)hipStreamSynchronize(s->deliver_stream);
+    for (int i = 0; i < 2; ++i) {
+        if (s->tick_done[i]) (void)hipEventDestroy(s->tick_done[i]);
+        if (s->tick_start[i]) (void)hipEventDestroy(s->tick_start[i]);
+    }
+    for (auto &b : s->batches)
+        if (b.done) (void)hipEventDestroy(b.done);
+    for (auto ev : s->spare_events) (void)hipEventDestroy(ev);
     if (s->h_desc) (void)hipHostFree(s->h_desc);
     if (s->h_ring) (void)hipHostFree(s->h_ring);
     if (s->h_tail) (void)hipHostFree(s->h_tail);
     if (s->h_done) (void)hipHostFree(s->h_done);
     if (s->h_jobs) (void)hipHostFree(s->h_jobs);
-    if (s->delivered) (void)hipEventDestroy(s->delivered);
+    if (s->deliver_stream) (void)hipStreamDestroy(s->deliver_stream);
     if (s->stream) (void)hipStreamDestroy(s->stream);
     delete s;
     return TRW_OK;
@@ -481,8 +504,8 @@ void complete(trw_server_s *s, Active &a, int32_t status) {
     c.t_admit_ns = a.t_admit;
     c.t_done_ns = now_ns();
     s->pool.release(a.pool_off, a.pool_bytes);
+    s->slot_done[a.slot] = a.done_base + a.req.nq;    // every query of a request counts once
     s->free_slots.push_back(a.slot);
-    if (a.copied) (void)hipEventDestroy(a.copied);
     std::lock_guard<std::mutex> lk(s->mu);
     s->completed.push_back(c);
     if (status == TRW_OK) s->stats.completed++; else s->stats.cancelled++;
@@ -492,7 +515,7 @@ void complete(trw_server_s *s, Active &a, int32_t status) {
 
 // Admit waiting requests while a slot and pool space are free (first come,
 // first served), then publish the descriptor table, the new chunks and the tail.
-hipError_t admit(trw_server_s *s, std::deque<Pending> &incoming) {
+hipError_t admit(trw_server_s *s, std::deque<Pending> &incoming, int half) {
     hipError_t e = hipSuccess;
     const unsigned long long tail0 = s->tail;
     while (!incoming.empty() && !s->free_slots.empty()) {
@@ -540,7 +563,7 @@ hipError_t admit(trw_server_s *s, std::deque<Pending> &incoming) {
         Active a;
         a.id = p.id; a.req = r; a.t_submit = p.t_submit; a.t_admit = now_ns();
         a.pool_off = off; a.pool_bytes = p.bytes; a.slot = slot; a.stride = stride;
-        a.done_base = s->h_done[slot];   // unchanged on the device while the slot was free
+        a.done_base = s->slot_done[slot];   // the counter is not reset between requests
         a.out_off = src_bytes;
         s->active.push_back(a);
         incoming.pop_front();
@@ -560,8 +583,9 @@ hipError_t admit(trw_server_s *s, std::deque<Pending> &incoming) {
         if (e != hipSuccess) return e;
         i += n;
     }
-    *s->h_tail = s->tail;
-    return hipMemcpyAsync(const_cast<unsigned long long *>(s->dev.tail), s->h_tail, sizeof(unsigned long long),
+    // this half is not read by a pending copy: that copy preceded tick i-2, which has ended
+    s->h_tail[half] = s->tail;
+    return hipMemcpyAsync(const_cast<unsigned long long *>(s->dev.tail), &s->h_tail[half], sizeof(unsigned long long),
                           hipMemcpyHostToDevice, s->stream);
 }
 
@@ -581,13 +605,15 @@ void output_jobs(const trw_server_s *s, const Active &a, CopyJob *jobs) {
 void server_loop(trw_server_s *s) {
     (void)hipSetDevice(s->device);
     std::deque<Pending> incoming, empty;
+    int cur = 0;                  // half of the staging buffers the next tick uses
+    bool prev_launched = false;   // a tick was enqueued in the previous pass and not yet read
     for (;;) {
         std::vector<uint64_t> cancels;
         bool stopping;
         {
             std::unique_lock<std::mutex> lk(s->mu);
             if (s->active.empty() && s->waiting.empty() && incoming.empty() && s->cancel_requests.empty() &&
-                !s->stopping)
+                !s->stopping && !prev_launched && s->batches.empty())
                 s->cv_work.wait_for(lk, std::chrono::milliseconds(2));
             while (!s->waiting.empty()) {
                 incoming.push_back(s->waiting.front());
@@ -623,88 +649,127 @@ void server_loop(trw_server_s *s) {
                 }
             }
         }
-        hipError_t e = admit(s, stopping ? empty : incoming);
-        if (e == hipSuccess && !s->active.empty()) {
+        hipError_t e = admit(s, stopping ? empty : incoming, cur);
+        // Enqueue tick `cur` (it runs after the copies admit() queued), then
+        // take the previous tick's counters while this one runs.
+        bool launched = false;
+        if (e == hipSuccess) {
             bool running = false;
             for (auto &a : s->active) running |= !a.finishing;
             if (running) {
-                e = hipEventRecord(s->tick_start, s->stream);
+                uint32_t *done_half = s->h_done + cur * (s->lay.done_bytes / sizeof(uint32_t));
+                e = hipEventRecord(s->tick_start[cur], s->stream);
                 if (e == hipSuccess)
                     e = s->use_graph ? hipGraphLaunch(s->graph_exec, s->stream)
                                      : launch_serve_tick(s->g, s->t, s->dev, s->steps, s->slots / kServeBlock, s->stream);
                 if (e == hipSuccess)
-                    e = hipMemcpyAsync(s->h_done, s->dev.done, s->lay.done_bytes, hipMemcpyDeviceToHost, s->stream);
-                if (e == hipSuccess) e = hipEventRecord(s->tick_done, s->stream);
-                if (e == hipSuccess) e = hipEventSynchronize(s->tick_done);
-                if (e == hipSuccess) {
-                    unsigned long long mv;
-                    std::memcpy(&mv, reinterpret_cast<char *>(s->h_done) + s->lay.done_bytes - sizeof(mv), sizeof(mv));
-                    float ms = 0;
-                    (void)hipEventElapsedTime(&ms, s->tick_start, s->tick_done);
-                    std::lock_guard<std::mutex> lk(s->mu);
-                    s->stats.ticks++;
-                    s->stats.moves = mv;
-                    s->stats.tick_device_ns += (uint64_t)(ms * 1e6);
-                }
-                // finished requests: device destinations in one delivery launch, host ones by copies
-                uint32_t njobs = 0;
-                uint64_t total_rows = 0;
-                std::vector<size_t> delivered_now;
-                for (size_t i = 0; i < s->active.size() && e == hipSuccess; ++i) {
-                    Active &a = s->active[i];
-                    if (a.finishing || s->h_done[a.slot] - a.done_base < a.req.nq) continue;
-                    a.finishing = true;
-                    if (a.cancelled) continue;
-                    CopyJob jobs[3];
-                    output_jobs(s, a, jobs);
-                    if (a.req.flags & TRW_REQ_HOST) {
-                        e = hipMemcpy2DAsync(jobs[0].dst, jobs[0].dst_pitch, jobs[0].src, jobs[0].src_pitch,
-                                             jobs[0].width, jobs[0].rows, hipMemcpyDeviceToHost, s->stream);
-                        for (int k = 1; k < 3 && e == hipSuccess; ++k)
-                            e = hipMemcpyAsync(jobs[k].dst, jobs[k].src, jobs[k].width, hipMemcpyDeviceToHost, s->stream);
-                        if (e == hipSuccess) e = hipEventCreateWithFlags(&a.copied, hipEventDisableTiming);
-                        if (e == hipSuccess) e = hipEventRecord(a.copied, s->stream);
-                    } else {
-                        for (int k = 0; k < 3; ++k) {
-                            jobs[k].row_start = total_rows;
-                            total_rows += jobs[k].rows;
-                            s->h_jobs[njobs++] = jobs[k];
-                        }
-                        delivered_now.push_back(i);
-                    }
-                }
-                if (e == hipSuccess && njobs) {
-                    CopyJob *d_jobs = reinterpret_cast<CopyJob *>(s->arena + s->lay.jobs);
-                    e = hipMemcpyAsync(d_jobs, s->h_jobs, sizeof(CopyJob) * njobs, hipMemcpyHostToDevice, s->stream);
-                    if (e == hipSuccess) {
-                        const uint64_t blocks = std::min<uint64_t>((total_rows + 3) / 4, 4096);
-                        hipLaunchKernelGGL(k_deliver, dim3((uint32_t)blocks), dim3(256), 0, s->stream, d_jobs, njobs,
-                                           total_rows);
-                        e = hipGetLastError();
-                    }
-                    if (e == hipSuccess) e = hipEventRecord(s->delivered, s->stream);
-                    if (e == hipSuccess) e = hipEventSynchronize(s->delivered);
-                    for (size_t i : delivered_now) s->active[i].copied = nullptr;
-                }
+                    e = hipMemcpyAsync(done_half, s->dev.done, s->lay.done_bytes, hipMemcpyDeviceToHost, s->stream);
+                if (e == hipSuccess) e = hipEventRecord(s->tick_done[cur], s->stream);
+                launched = e == hipSuccess;
             }
         }
-        // release requests whose outputs have landed
-        if (e == hipSuccess) {
-            for (size_t i = 0; i < s->active.size();) {
+        // The tick whose counters are read now: the previous one when pipelined
+        // (the current one is queued behind it), else the one just queued.
+        const bool read_tick = s->pipelined ? prev_launched : launched;
+        hipStream_t out_stream = s->pipelined ? s->deliver_stream : s->stream;
+        if (e == hipSuccess && read_tick) {
+            const int prev = s->pipelined ? (cur ^ 1) : cur;
+            e = hipEventSynchronize(s->tick_done[prev]);
+            const uint32_t *done_prev = s->h_done + prev * (s->lay.done_bytes / sizeof(uint32_t));
+            if (e == hipSuccess) {
+                unsigned long long mv;
+                std::memcpy(&mv, reinterpret_cast<const char *>(done_prev) + s->lay.done_bytes - sizeof(mv), sizeof(mv));
+                float ms = 0;
+                (void)hipEventElapsedTime(&ms, s->tick_start[prev], s->tick_done[prev]);
+                std::lock_guard<std::mutex> lk(s->mu);
+                s->stats.ticks++;
+                s->stats.moves = mv;
+                s->stats.tick_device_ns += (uint64_t)(ms * 1e6);
+            }
+            // Requests that finished by that tick: their outputs are copied out
+            // (device destinations in one launch, host ones by copies), pipelined:
+            // on the delivery stream while the next tick runs (it touches none of
+            // them); serial: on the tick stream, ahead of the next tick.
+            Batch batch;
+            batch.jobs_buf = (int)(s->n_batches & 1);
+            CopyJob *jobs_half = s->h_jobs + (size_t)batch.jobs_buf * 3 * s->max_reqs;
+            uint32_t njobs = 0;
+            uint64_t total_rows = 0;
+            bool any_copy = false;
+            for (size_t i = 0; i < s->active.size() && e == hipSuccess; ++i) {
                 Active &a = s->active[i];
-                bool ready = false;
-                if (a.finishing) {
-                    if (a.cancelled || !(a.req.flags & TRW_REQ_HOST)) ready = true;   // device: delivered above
-                    else ready = a.copied && hipEventQuery(a.copied) == hipSuccess;
-                }
-                if (ready) {
-                    complete(s, a, a.cancelled ? TRW_E_CANCELLED : TRW_OK);
-                    s->active.erase(s->active.begin() + i);
+                if (a.finishing || done_prev[a.slot] - a.done_base < a.req.nq) continue;
+                a.finishing = true;
+                batch.ids.push_back(a.id);
+                if (a.cancelled) continue;
+                CopyJob jobs[3];
+                output_jobs(s, a, jobs);
+                if (a.req.flags & TRW_REQ_HOST) {
+                    e = hipMemcpy2DAsync(jobs[0].dst, jobs[0].dst_pitch, jobs[0].src, jobs[0].src_pitch, jobs[0].width,
+                                         jobs[0].rows, hipMemcpyDeviceToHost, out_stream);
+                    for (int k = 1; k < 3 && e == hipSuccess; ++k)
+                        e = hipMemcpyAsync(jobs[k].dst, jobs[k].src, jobs[k].width, hipMemcpyDeviceToHost,
+                                           out_stream);
+                    any_copy = true;
                 } else {
-                    ++i;
+                    for (int k = 0; k < 3; ++k) {
+                        jobs[k].row_start = total_rows;
+                        total_rows += jobs[k].rows;
+                        jobs_half[njobs++] = jobs[k];
+                    }
                 }
             }
+            if (e == hipSuccess && njobs) {
+                // the previous batch on this stream used the device job table; stream order keeps them apart
+                // (serial mode: the copy and the delivery run before the next tick, on the tick stream)
+                CopyJob *d_jobs = reinterpret_cast<CopyJob *>(s->arena + s->lay.jobs);
+                e = hipMemcpyAsync(d_jobs, jobs_half, sizeof(CopyJob) * njobs, hipMemcpyHostToDevice, out_stream);
+                if (e == hipSuccess) {
+                    const uint64_t blocks = std::min<uint64_t>((total_rows + 3) / 4, 4096);
+                    hipLaunchKernelGGL(k_deliver, dim3((uint32_t)blocks), dim3(256), 0, out_stream, d_jobs, njobs,
+                                       total_rows);
+                    e = hipGetLastError();
+                }
+                any_copy = true;
+            }
+            if (e == hipSuccess && !batch.ids.empty()) {
+                if (any_copy) {
+                    if (!s->spare_events.empty()) {
+                        batch.done = s->spare_events.back();
+                        s->spare_events.pop_back();
+                    } else {
+                        e = hipEventCreateWithFlags(&batch.done, hipEventDisableTiming);
+                    }
+                    if (e == hipSuccess) e = hipEventRecord(batch.done, out_stream);
+                }
+                s->n_batches++;
+                s->batches.push_back(std::move(batch));
+            }
         }
+        // Release the requests of delivered batches (in order); a job-table half
+        // is reused two batches later, so wait for that batch if it still runs.
+        while (e == hipSuccess && !s->batches.empty()) {
+            Batch &b = s->batches.front();
+            const bool must_wait = s->batches.size() >= 2;
+            if (b.done) {
+                hipError_t q = must_wait ? hipEventSynchronize(b.done) : hipEventQuery(b.done);
+                if (q == hipErrorNotReady) break;
+                if (q != hipSuccess) { e = q; break; }
+                s->spare_events.push_back(b.done);
+            }
+            for (uint64_t id : b.ids) {
+                for (size_t i = 0; i < s->active.size(); ++i) {
+                    if (s->active[i].id == id) {
+                        complete(s, s->active[i], s->active[i].cancelled ? TRW_E_CANCELLED : TRW_OK);
+                        s->active.erase(s->active.begin() + i);
+                        break;
+                    }
+                }
+            }
+            s->batches.pop_front();
+        }
+        prev_launched = s->pipelined && launched;
+        cur ^= 1;
         if (e != hipSuccess) {
             std::lock_guard<std::mutex> lk(s->mu);
             s->fatal = std::string("server device error: ") + hipGetErrorString(e);
@@ -716,8 +781,8 @@ void server_loop(trw_server_s *s) {
             s->stats.active = (uint32_t)s->active.size();
             s->stats.pool_bytes_used = s->pool.used();
         }
-        if (stopping && s->active.empty() && incoming.empty()) return;
-        bool copies_only = !s->active.empty();
+        if (stopping && s->active.empty() && incoming.empty() && !prev_launched && s->batches.empty()) return;
+        bool copies_only = !s->active.empty() && !prev_launched;
         for (auto &a : s->active) copies_only &= a.finishing;
         if (copies_only) std::this_thread::sleep_for(std::chrono::microseconds(20));
     }

@@ -120,11 +120,11 @@ def _mix(g, n, seed):
     return reqs
 
 
-@pytest.mark.parametrize("use_graph", [True, False])
-def test_same_alone_and_in_mix(env, use_graph):
+@pytest.mark.parametrize("use_graph,pipelined", [(True, False), (False, False), (True, True)])
+def test_same_alone_and_in_mix(env, use_graph, pipelined):
     g = env["g"]
     reqs = _mix(g, 30, 5)
-    srv = make_server(env, use_hipgraph=use_graph)
+    srv = make_server(env, use_hipgraph=use_graph, pipelined=pipelined)
     alone = []
     for algo, sampler, max_len, src, qb, seed in reqs:
         rid = srv.submit(params(algo, sampler, max_len, seed), src, qid_base=qb)
@@ -140,16 +140,23 @@ def test_same_alone_and_in_mix(env, use_graph):
     srv.close()
 
 
-def test_cancel_leaves_others_intact(env):
+@pytest.mark.parametrize("pipelined", [False, True])
+def test_cancel_leaves_others_intact(env, pipelined):
     g = env["g"]
-    srv = make_server(env)
+    srv = make_server(env, pipelined=pipelined)
     small = _mix(g, 6, 9)
     alone = []
     for algo, sampler, max_len, src, qb, seed in small:
         rid = srv.submit(params(algo, sampler, max_len, seed), src, qid_base=qb)
         alone.append(to_np(wait_all(srv, [rid])[rid]))
-    big = srv.submit(params("node2vec", "orej", 80, 3), synth.sources(60000, g.n, 4), qid_base=10 ** 9)
+    # large enough (48 M moves) that it is still running when the cancel arrives
+    big = srv.submit(params("node2vec", "orej", 80, 3), synth.sources(600000, g.n, 4), qid_base=10 ** 9)
     ids = [srv.submit(params(a, s, m, seed), src, qid_base=qb) for a, s, m, src, qb, seed in small]
+    moves0 = srv.stats()["moves"]
+    t0 = time.time()
+    while srv.stats()["moves"] == moves0:
+        assert time.time() - t0 < 10, "the server made no progress"
+        time.sleep(0.0002)
     srv.cancel(big)
     got = wait_all(srv, ids + [big])
     assert got[big]["status"] == trw.TRW_E_CANCELLED
