@@ -237,6 +237,21 @@ def main():
         if traffic is not None:
             roofline["traffic_frac_of_peak"] = round(traffic / (avg_launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)
 
+    # Autotuned launch (the paper's pre-execution tuning): candidates timed on a
+    # sample of the batch, then the whole batch timed with the winner.
+    autotuned = None
+    if not args.no_variants and not args.profile_pass:
+        n_tune = min(nq, 1 << 20)
+        t0 = time.perf_counter()
+        best, best_ms = trw.autotune(G, tables.get(sampler), params(sampler), d_src[:n_tune], mode=mode)
+        tune_s = time.perf_counter() - t0
+        r = run(sampler, mode, 1, args.steps, best)
+        v = r["moves"] * args.steps / r["wall_s"]
+        autotuned = {"tuning": best.as_dict(), "sample_queries": n_tune, "tune_s": round(tune_s, 3),
+                     "steps_per_s": round(v, 1), "ms_per_batch": round(1000 * r["wall_s"] / args.steps, 4),
+                     "vs_default": round(v / value, 4)}
+        log(f"autotuned {best.as_dict()}: {v:.4g} steps/s ({v / value:.3f}x default), tuning {tune_s:.2f}s")
+
     # Other samplers / schedules of the same workload (same queries, same graph).
     variants = {}
     if not args.no_variants:
@@ -297,6 +312,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "preprocess_ms": {k: round(v, 3) for k, v in pre_ms.items()},
+        "autotuned": autotuned,
         "variants": variants,
         "gather_ceiling": gather,
     }

@@ -227,7 +227,7 @@ trw_status trw_walk_workspace_bytes(trw_graph g, const trw_walk_params *p, uint6
 
 /* The library's default tuning for this graph, params and mode (what trw_walk
  * uses when given no tuning).  For METAPATH it is the default without a label
- * index; with one, trw_walk runs 4 blocks per CU instead of 8. */
+ * index; with one, trw_walk runs 2 blocks per CU with 2 walkers per lane. */
 trw_status trw_default_tuning(trw_graph g, const trw_walk_params *p, uint32_t mode, trw_tuning *out);
 
 /*
@@ -257,9 +257,12 @@ trw_status trw_walk(trw_graph g, trw_table table, const trw_walk_params *p,
 
 /*
  * Pick a tuning by pre-executing short walks (the paper tunes its ring sizes
- * the same way: Ring Size Tuning).  Runs up to `budget` candidate launches of
- * `nq` queries (length-capped at p->max_len) from d_sources in `mode`, timing
- * each with HIP events, and writes the fastest to *out.  d_paths, d_lengths,
+ * the same way: Ring Size Tuning).  Runs up to `budget` (0 = all) candidate
+ * launches of `nq` queries (a sample, length-capped at p->max_len) from
+ * d_sources in `mode`, timing each with HIP events, and writes the fastest to
+ * *out.  Candidates: the default tuning first, then walkers per lane x blocks
+ * per CU x queue chunk (persistent) or blocks per CU x block size (per step),
+ * and for METAPATH without a label index the wave-scan degree.  d_paths, d_lengths,
  * d_status and d_ws are scratch of the sizes trw_walk needs for nq queries.
  * Synchronises the stream.  Errors as trw_walk.
  */

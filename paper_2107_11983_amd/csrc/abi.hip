@@ -126,7 +126,8 @@ Tuning resolve_tuning(const trw_walk_params *p, uint32_t mode, const trw_tuning 
         } else if (static_walk && p->sampler == TRW_S_ITS) {
             tu.blocks_per_cu = 2;
         } else if (p->algo == TRW_A_METAPATH && label_index) {
-            tu.blocks_per_cu = 4;       // the row scans without an index want the occupancy
+            tu.blocks_per_cu = 2;       // the row scans without an index want the occupancy
+            tu.walkers_per_lane = 2;
         }
     }
     if (t) {
@@ -391,16 +392,28 @@ trw_status trw_autotune(trw_graph g, trw_table table, const trw_walk_params *p, 
                         uint8_t *d_status, uint32_t mode, uint32_t budget, void *d_ws, size_t ws_bytes,
                         trw_stream_t stream, trw_tuning *out, float *best_ms) {
     if (!out) return fail(TRW_E_INVALID, "out is NULL");
+    // Candidates: the launch shape (walkers per lane, blocks per CU), the queue
+    // chunk, and for MetaPath without a label index the degree at which a row
+    // is scanned by the whole wave.  The library default comes first, so a
+    // budget of 1 returns it.
     std::vector<trw_tuning> cands;
+    const bool scans = p->algo == TRW_A_METAPATH && table == nullptr;
     if (mode == TRW_M_PERSISTENT) {
+        const Tuning d = resolve_tuning(p, mode, nullptr, p->algo == TRW_A_METAPATH && table != nullptr);
+        trw_tuning def{};
+        def.walkers_per_lane = d.walkers_per_lane; def.block_threads = d.block_threads;
+        def.blocks_per_cu = d.blocks_per_cu; def.queue_chunk = d.queue_chunk; def.coop_degree = d.coop_degree;
+        cands.push_back(def);
         for (uint32_t wpl : {1u, 2u, 4u})
-            for (uint32_t bpc : {4u, 8u, 16u})
-                for (uint32_t chunk : {64u, 256u, 1024u}) {
-                    trw_tuning t{};
-                    t.walkers_per_lane = wpl; t.block_threads = 256; t.blocks_per_cu = bpc;
-                    t.queue_chunk = chunk; t.coop_degree = 256;
-                    cands.push_back(t);
-                }
+            for (uint32_t bpc : {1u, 2u, 4u, 8u})
+                for (uint32_t chunk : {128u, 256u})
+                    for (uint32_t coop : {64u, 256u, 1024u}) {
+                        if (!scans && coop != 256u) continue;
+                        trw_tuning t{};
+                        t.walkers_per_lane = wpl; t.block_threads = 256; t.blocks_per_cu = bpc;
+                        t.queue_chunk = chunk; t.coop_degree = coop;
+                        cands.push_back(t);
+                    }
     } else {
         for (uint32_t bpc : {2u, 4u, 8u, 16u})
             for (uint32_t threads : {128u, 256u}) {

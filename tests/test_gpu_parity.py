@@ -353,6 +353,26 @@ def test_tuning_does_not_change_results(rmat_sym, rmat_dir, algo, sampler, wpl, 
     assert_same(gpu, ref, max_len)
 
 
+
+@pytest.mark.parametrize("algo,sampler,index", [("ppr", "alias", None), ("metapath", "its", None),
+                                                ("node2vec", "orej", "adj")])
+def test_autotune_picks_a_candidate_and_results_do_not_change(rmat_sym, rmat_dir, algo, sampler, index):
+    case = rmat_dir if algo == "ppr" else rmat_sym
+    src = synth.sources(20000, case.g.n, 31)
+    kw = _args(algo)
+    p = trw.make_params(algo, sampler, 40, 9, stop_q32=kw.get("stop", 0), n2v_thr_q16=kw.get("thr", (65536,) * 3),
+                        schema=kw.get("schema", ()))
+    table = case.dev_table(sampler) if algo == "ppr" else (case.adjacency_index() if index == "adj" else None)
+    d_src = torch.from_numpy(src).cuda()
+    best, ms = trw.autotune(case.G, table, p, d_src, mode=trw.TRW_M_PERSISTENT)
+    assert ms > 0 and best.walkers_per_lane in (1, 2, 4) and best.blocks_per_cu >= 1
+    ref = [x.cpu().numpy() for x in trw.walk(case.G, table, p, d_src)]
+    got = [x.cpu().numpy() for x in trw.walk(case.G, table, p, d_src, tuning=best)]
+    L = ref[1].view(np.uint32)
+    assert np.array_equal(ref[1], got[1]) and np.array_equal(ref[2], got[2])
+    mask = np.arange(41)[None, :] <= L[:, None]
+    assert np.array_equal(ref[0][:, :41][mask], got[0][:, :41][mask])
+
 def test_edge_cases(rmat_sym, rmat_dir):
     n = rmat_dir.g.n
     deg = rmat_dir.g.degrees()
