@@ -114,7 +114,7 @@ def main():
     wl = synth.WORKLOADS[args.workload]
     if wl.algo == "mixed":
         return bench_served(args, wl, np, torch, synth, trw, props)
-    sampler = args.sampler or {"metapath": "its+index", "node2vec": "orej+adj",
+    sampler = args.sampler or {"metapath": "its+index", "node2vec": "orej+eidx",
                                "deepwalk": "naive+adj"}.get(wl.algo, wl.samplers[0])
     t0 = time.time()
     g = synth.make_graph(wl)
@@ -128,7 +128,7 @@ def main():
 
     # Preprocessing: per-vertex tables, timed separately from the walk.
     tables, pre_ms = {}, {}
-    variant_samplers = {"metapath": ("its+index", "its"), "node2vec": ("orej+adj", "orej"),
+    variant_samplers = {"metapath": ("its+index", "its"), "node2vec": ("orej+eidx", "orej+adj", "orej"),
                         "deepwalk": ("naive+adj", "naive")}.get(wl.algo, wl.samplers)
     need = {sampler} if (args.no_variants or args.profile_pass) else set(variant_samplers) | {sampler}
     for s in sorted(need):
@@ -139,6 +139,8 @@ def main():
                 tables[s] = G.label_index(wl.labels)
             elif s.endswith("+adj"):
                 tables[s] = G.adjacency_index()
+            elif s.endswith("+eidx"):
+                tables[s] = G.edge_index()
             else:
                 tables[s] = G.table(s)
             e1.record(stream)

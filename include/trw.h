@@ -157,6 +157,22 @@ trw_status trw_adjacency_index_build(trw_graph g, void *d_buf, size_t bytes, trw
                                      trw_table *out);
 
 /*
+ * Edge index (optional, for NAIVE and OREJ walks and the server): the
+ * adjacency index above, then a hash set of every edge (u, v).  Node2Vec's
+ * acceptance test asks whether a dart's vertex x is a neighbour of the
+ * previous vertex (the Node2Vec transition equation); the paper answers it by
+ * binary search in the sorted row, O(log d) dependent reads.  With the edge
+ * index it is one probe sequence of the hash set, usually one cache line.
+ * Membership is exact, so results are identical with and without it.
+ * Layout in d_buf (256-byte aligned): uint32x4 records[m] padded to 256 bytes,
+ * then uint64 keys[S], S = the smallest power of two >= max(64, 2m), key
+ * u << 32 | v, empty slots all ones, linear probing from SplitMix64's
+ * finalizer of the key.  Bytes: 16m rounded up to 256, plus 8S.
+ */
+trw_status trw_edge_index_bytes(trw_graph g, size_t *bytes);
+trw_status trw_edge_index_build(trw_graph g, void *d_buf, size_t bytes, trw_stream_t stream, trw_table *out);
+
+/*
  * MetaPath label index (optional).  A MetaPath move only considers the edges
  * of the current vertex whose label equals the schema's label for that move
  * (Random Walk based Algorithms, MetaPath); without an index every move
@@ -232,8 +248,9 @@ trw_status trw_default_tuning(trw_graph g, const trw_walk_params *p, uint32_t mo
 
 /*
  * Run nq queries, query i starting at d_sources[i] with id qid_base + i.
- *   table       ALIAS/ITS table built for p->sampler; for NAIVE and OREJ NULL or
- *               an adjacency index; for METAPATH NULL (scan rows) or a label index
+ *   table       ALIAS/ITS table built for p->sampler; for NAIVE and OREJ NULL,
+ *               an adjacency index or an edge index; for METAPATH NULL (scan
+ *               rows) or a label index
  *   d_paths     int32, row i at d_paths + i*path_stride, path_stride >= max_len+1:
  *               paths[i][0] = source, paths[i][1..lengths[i]] = the moves;
  *               entries beyond lengths[i] are left unspecified
@@ -332,8 +349,8 @@ trw_status trw_server_arena_bytes(const trw_server_cfg *cfg, size_t pool_bytes, 
 
 /*
  * Create a server on the current device.  alias: the graph's ALIAS table (or
- * NULL: then ALIAS requests are refused); adjacency: an adjacency index (or
- * NULL).  d_arena: caller-owned device memory (256-byte aligned) holding the
+ * NULL: then ALIAS requests are refused); adjacency: an adjacency or edge
+ * index (or NULL).  d_arena: caller-owned device memory (256-byte aligned) holding the
  * fixed server state and, after it, the request pool; keep it alive until
  * trw_server_destroy.  Starts the server thread.
  */

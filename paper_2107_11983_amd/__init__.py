@@ -119,6 +119,10 @@ class Graph:
         """Row-annotated adjacency for NAIVE / Node2Vec walks (identical results, fewer reads)."""
         return Table(self, "adjacency_index", stream)
 
+    def edge_index(self, stream=None) -> "Table":
+        """Adjacency index plus a hash set of the edges (Node2Vec's adjacency test in one probe)."""
+        return Table(self, "edge_index", stream)
+
     def label_index(self, n_labels: int, stream=None) -> "Table":
         """MetaPath label index (rows sorted by label + per-vertex label offsets)."""
         return Table(self, "label_index", stream, n_labels=n_labels)
@@ -151,6 +155,12 @@ class Table:
             self.buf = torch.empty(max(int(nbytes.value), 16), dtype=torch.uint8, device=graph.device)
             check(_abi.trw_adjacency_index_build(graph.handle, _dptr(self.buf), int(nbytes.value),
                                                  _stream_ptr(stream), ctypes.byref(h)))
+        elif sampler == "edge_index":
+            self.sampler = None
+            check(_abi.trw_edge_index_bytes(graph.handle, ctypes.byref(nbytes)))
+            self.buf = torch.empty(int(nbytes.value), dtype=torch.uint8, device=graph.device)
+            check(_abi.trw_edge_index_build(graph.handle, _dptr(self.buf), int(nbytes.value),
+                                            _stream_ptr(stream), ctypes.byref(h)))
         elif sampler == "label_index":
             self.sampler = None
             self.n_labels = n_labels

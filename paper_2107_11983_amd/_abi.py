@@ -116,6 +116,8 @@ _SIGS = {
     "trw_server_stats_get": (_st, [_P, ctypes.POINTER(trw_server_stats)]),
     "trw_server_destroy": (_st, [_P]),
     # measurement probe (include/trw_probe.h)
+    "trw_edge_index_bytes": (_st, [_P, ctypes.POINTER(_sz)]),
+    "trw_edge_index_build": (_st, [_P, _P, _sz, _P, _PP]),
     "trw_probe_fill": (ctypes.c_int, [_P, _u64, _u32, _P]),
     "trw_probe_gather": (ctypes.c_int, [_P, _u64, _u32, _u32, _u32, ctypes.c_int, _u32, _u32, _P, _P]),
     "trw_probe_scatter": (ctypes.c_int, [_P, _u64, _u32, _u32, _u32, _u32, _P]),
@@ -165,6 +167,8 @@ trw_server_cancel = lib.trw_server_cancel
 trw_server_poll = lib.trw_server_poll
 trw_server_stats_get = lib.trw_server_stats_get
 trw_server_destroy = lib.trw_server_destroy
+trw_edge_index_bytes = lib.trw_edge_index_bytes
+trw_edge_index_build = lib.trw_edge_index_build
 trw_probe_fill = lib.trw_probe_fill
 trw_probe_gather = lib.trw_probe_gather
 trw_probe_scatter = lib.trw_probe_scatter

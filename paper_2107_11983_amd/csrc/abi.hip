@@ -285,6 +285,31 @@ trw_status trw_adjacency_index_build(trw_graph g, void *d_buf, size_t bytes, trw
     return TRW_OK;
 }
 
+trw_status trw_edge_index_bytes(trw_graph g, size_t *bytes) {
+    if (!g || !bytes) return fail(TRW_E_INVALID, "graph / bytes is NULL");
+    *bytes = edge_index_records_bytes(g->dev.m) + sizeof(unsigned long long) * eset_slots(g->dev.m);
+    return TRW_OK;
+}
+
+trw_status trw_edge_index_build(trw_graph g, void *d_buf, size_t bytes, trw_stream_t stream, trw_table *out) {
+    if (!g || !out) return fail(TRW_E_INVALID, "graph / out is NULL");
+    const size_t rec = edge_index_records_bytes(g->dev.m);
+    const unsigned long long slots = eset_slots(g->dev.m);
+    if (bytes < rec + sizeof(unsigned long long) * slots) return fail(TRW_E_INVALID, "edge index buffer too small");
+    if (!d_buf || (reinterpret_cast<uintptr_t>(d_buf) & 255))
+        return fail(TRW_E_INVALID, "edge index buffer NULL or not 256-byte aligned");
+    auto s = static_cast<hipStream_t>(stream);
+    hipError_t e = g->dev.m > 0 ? launch_adjacency_build(g->dev, static_cast<uint4 *>(d_buf), s) : hipSuccess;
+    if (e == hipSuccess)
+        e = launch_edge_set_build(g->dev, reinterpret_cast<unsigned long long *>(static_cast<char *>(d_buf) + rec),
+                                  slots, s);
+    if (e != hipSuccess) return device_fail(e, "edge index build launch");
+    auto *t = new (std::nothrow) trw_table_s{g, kEdgeIndexKind, d_buf, 0};
+    if (!t) return fail(TRW_E_INVALID, "out of host memory");
+    *out = t;
+    return TRW_OK;
+}
+
 trw_status trw_table_destroy(trw_table t) {
     delete t;
     return TRW_OK;
@@ -333,8 +358,8 @@ trw_status trw_walk(trw_graph g, trw_table table, const trw_walk_params *p, cons
     const bool adjacency = !needs_table && p->algo != TRW_A_METAPATH && table != nullptr;
     if (adjacency) {
         if (table->graph != g) return fail(TRW_E_INVALID, "adjacency index was built for another graph");
-        if (table->sampler != kAdjacencyKind)
-            return fail(TRW_E_INVALID, "NAIVE / OREJ walks take an adjacency index or no table");
+        if (table->sampler != kAdjacencyKind && table->sampler != kEdgeIndexKind)
+            return fail(TRW_E_INVALID, "NAIVE / OREJ walks take an adjacency or edge index, or no table");
     }
     const bool label_index = p->algo == TRW_A_METAPATH && table != nullptr;
     if (label_index) {
@@ -370,6 +395,11 @@ trw_status trw_walk(trw_graph g, trw_table table, const trw_walk_params *p, cons
     w.status = d_status;
     TableDev t{nullptr, nullptr, nullptr, nullptr, 0, nullptr};
     if (adjacency) t.adj = static_cast<const uint4 *>(table->buf);
+    if (adjacency && table->sampler == kEdgeIndexKind) {
+        t.eset = reinterpret_cast<const unsigned long long *>(static_cast<const char *>(table->buf) +
+                                                              edge_index_records_bytes(g->dev.m));
+        t.eset_mask = eset_slots(g->dev.m) - 1;
+    }
     if (needs_table) {
         if (p->sampler == TRW_S_ALIAS) t.alias = static_cast<const uint4 *>(table->buf);
         else t.prefix = static_cast<const uint64_t *>(table->buf);

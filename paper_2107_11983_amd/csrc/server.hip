@@ -320,8 +320,13 @@ extern "C" trw_status trw_server_create(trw_graph g, trw_table alias, trw_table 
         t.alias = static_cast<const uint4 *>(buf);
     }
     if (adjacency) {
-        if (!table_view(adjacency, kAdjacencyKind, &buf, &tg) || tg != g)
-            return sfail(TRW_E_INVALID, "adjacency is not an adjacency index of this graph");
+        if (table_view(adjacency, kEdgeIndexKind, &buf, &tg) && tg == g) {
+            t.eset = reinterpret_cast<const unsigned long long *>(static_cast<const char *>(buf) +
+                                                                  edge_index_records_bytes(graph_dev(g).m));
+            t.eset_mask = eset_slots(graph_dev(g).m) - 1;
+        } else if (!table_view(adjacency, kAdjacencyKind, &buf, &tg) || tg != g) {
+            return sfail(TRW_E_INVALID, "adjacency is not an adjacency or edge index of this graph");
+        }
         t.adj = static_cast<const uint4 *>(buf);
     }
     auto *s = new (std::nothrow) trw_server_s(arena_bytes - lay.fixed);

@@ -418,6 +418,39 @@ __global__ void k_adjacency_build(GraphDev g, uint4 *__restrict__ out) {
     out[e] = make_uint4((uint32_t)v, r.x, r.y, 0u);
 }
 
+// Edge hash set (the edge index's membership test for Node2Vec): every edge
+// (u, v) inserted once as u << 32 | v by compare-and-swap with linear
+// probing; a thread per row up to kBigRow slots, a workgroup per longer row.
+__global__ void k_fill_u64(unsigned long long *p, unsigned long long n, unsigned long long v) {
+    for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (unsigned long long)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__device__ __forceinline__ void eset_insert(unsigned long long *keys, unsigned long long mask, unsigned long long key) {
+    for (unsigned long long h = eset_hash(key) & mask;; h = (h + 1) & mask) {
+        const unsigned long long old = atomicCAS(&keys[h], kEsetEmpty, key);
+        if (old == kEsetEmpty || old == key) return;
+    }
+}
+
+__global__ void k_edge_set_build(GraphDev g, unsigned long long *keys, unsigned long long mask) {
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= g.n) return;
+    const int64_t lo = g.row_ptr[u], hi = g.row_ptr[u + 1];
+    if (hi - lo > kBigRow) return;
+    for (int64_t e = lo; e < hi; ++e)
+        eset_insert(keys, mask, ((unsigned long long)u << 32) | (uint32_t)g.col[e]);
+}
+
+__global__ void __launch_bounds__(kBuildBlock) k_edge_set_build_big(GraphDev g, unsigned long long *keys,
+                                                                    unsigned long long mask) {
+    for_each_big_row(g, [&](int64_t u, int64_t off, int64_t d) {
+        for (int64_t e = off + threadIdx.x; e < off + d; e += kBuildBlock)
+            eset_insert(keys, mask, ((unsigned long long)u << 32) | (uint32_t)g.col[e]);
+    });
+}
+
 // Edges (u, v) whose reverse (v, u) is missing; rows must be sorted.
 __global__ void k_symmetry_check(GraphDev g, unsigned long long *__restrict__ bad) {
     const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -472,6 +505,14 @@ hipError_t launch_label_index_build(const GraphDev &g, uint32_t nlab, int32_t *l
 hipError_t launch_adjacency_build(const GraphDev &g, uint4 *out, hipStream_t s) {
     const int64_t blocks = ((int64_t)g.m + kBuildThreads - 1) / kBuildThreads;
     hipLaunchKernelGGL(k_adjacency_build, dim3((uint32_t)blocks), dim3(kBuildThreads), 0, s, g, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_edge_set_build(const GraphDev &g, unsigned long long *keys, unsigned long long slots, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_u64, dim3(4096), dim3(256), 0, s, keys, slots, kEsetEmpty);
+    const int blocks = (g.n + kBuildThreads - 1) / kBuildThreads;
+    hipLaunchKernelGGL(k_edge_set_build, dim3(blocks), dim3(kBuildThreads), 0, s, g, keys, slots - 1);
+    hipLaunchKernelGGL(k_edge_set_build_big, dim3(big_row_blocks(g)), dim3(kBuildBlock), 0, s, g, keys, slots - 1);
     return hipGetLastError();
 }
 

@@ -39,7 +39,26 @@ struct TableDev {
     const int32_t *lcol;      // label index: label-sorted destinations
     uint32_t nlab;            // label index: L
     const uint4 *adj;         // adjacency index: {dst, row_off(dst), deg(dst), 0} per edge slot
+    const unsigned long long *eset;   // edge index: hash set of the edges (u, v) as u << 32 | v
+    unsigned long long eset_mask;     // its slot count - 1 (a power of two)
 };
+
+// Edge hash set: open addressing, linear probing, at most half full; empty
+// slots hold kEsetEmpty (no key has both top bits set since ids are < 2^31).
+constexpr unsigned long long kEsetEmpty = ~0ull;
+
+__host__ __device__ inline unsigned long long eset_slots(int64_t m) {
+    unsigned long long cap = 64;
+    while (cap < 2ull * (unsigned long long)m) cap <<= 1;
+    return cap;
+}
+
+// SplitMix64's finalizer (Steele, Lea, Flood 2014) as the slot hash.
+__host__ __device__ inline unsigned long long eset_hash(unsigned long long k) {
+    k ^= k >> 30; k *= 0xBF58476D1CE4E5B9ull;
+    k ^= k >> 27; k *= 0x94D049BB133111EBull;
+    return k ^ (k >> 31);
+}
 constexpr size_t kAliasEntryBytes = 32;
 constexpr uint32_t kMaxIndexLabels = 64;
 
@@ -96,6 +115,7 @@ hipError_t launch_its_build(const GraphDev &g, uint64_t *out, hipStream_t s);
 hipError_t launch_validate(const GraphDev &g, unsigned long long *d_bad, hipStream_t s);
 hipError_t launch_label_index_build(const GraphDev &g, uint32_t nlab, int32_t *loff, int32_t *lcol, hipStream_t s);
 hipError_t launch_adjacency_build(const GraphDev &g, uint4 *out, hipStream_t s);
+hipError_t launch_edge_set_build(const GraphDev &g, unsigned long long *keys, unsigned long long slots, hipStream_t s);
 hipError_t launch_symmetry_check(const GraphDev &g, unsigned long long *d_bad, hipStream_t s);
 
 size_t walk_workspace_bytes(uint32_t mode, uint64_t nq, uint32_t max_len);
@@ -110,6 +130,10 @@ void set_error(const std::string &msg);
 // and two index kinds.
 constexpr uint32_t kLabelIndexKind = 0x100;
 constexpr uint32_t kAdjacencyKind = 0x101;
+constexpr uint32_t kEdgeIndexKind = 0x102;    // adjacency records, then the edge hash set
+
+// Bytes of the adjacency records at the start of an edge index (256-aligned).
+inline size_t edge_index_records_bytes(int64_t m) { return ((16 * (size_t)m) + 255) / 256 * 256; }
 
 // Accessors for the opaque handles (defined with them in abi.hip).
 const GraphDev &graph_dev(trw_graph g);

@@ -40,8 +40,9 @@ __device__ __forceinline__ int32_t static_next(const GraphDev &g, const TableDev
 // throw darts (x, y) with x a uniform edge slot of cur and y = r1 >> 16 until
 // y falls under the Q16 threshold of x's class (x == prev, x adjacent to
 // prev, otherwise; the Node2Vec transition equation).  The adjacency test is
-// a binary search in a sorted row, made only when the dart's height lies
-// between the two thresholds it would choose between.  With the adjacency
+// a binary search in a sorted row, or a probe of the edge index's hash set,
+// made only when the dart's height lies between the two thresholds it would
+// choose between.  With the adjacency
 // index a dart also learns x's row, so on a symmetric graph the search can run
 // in the shorter of the two rows (x in N(prev) iff prev in N(x)), and an
 // accepted move needs no row lookup.
@@ -54,6 +55,17 @@ __device__ __forceinline__ bool in_row(const int32_t *__restrict__ col, int32_t 
         if (c < key) lo = mid + 1; else hi = mid;
     }
     return false;
+}
+
+// Is (u, v) an edge?  Probes the edge index's hash set.
+__device__ __forceinline__ bool eset_has(const unsigned long long *__restrict__ keys, unsigned long long mask,
+                                         int32_t u, int32_t v) {
+    const unsigned long long key = ((unsigned long long)(uint32_t)u << 32) | (uint32_t)v;
+    for (unsigned long long h = eset_hash(key) & mask;; h = (h + 1) & mask) {
+        const unsigned long long k = keys[h];
+        if (k == key) return true;
+        if (k == kEsetEmpty) return false;
+    }
 }
 
 template <bool ADJ>
@@ -81,8 +93,13 @@ __device__ __forceinline__ int32_t n2v_move(const GraphDev &g, const TableDev &t
             } else if (y >= max(a.thr[1], a.thr[2])) {
                 accept = false;         // over both
             } else {
-                const bool adjacent = (ADJ && g.symmetric && xd < pd) ? in_row(g.col, xo, xo + xd, prev)
-                                                                      : in_row(g.col, poff, poff + pd, x);
+                bool adjacent;
+                if (t.eset) {               // edge index: one probe sequence, usually one line
+                    adjacent = eset_has(t.eset, t.eset_mask, prev, x);
+                } else {
+                    adjacent = (ADJ && g.symmetric && xd < pd) ? in_row(g.col, xo, xo + xd, prev)
+                                                               : in_row(g.col, poff, poff + pd, x);
+                }
                 accept = y < (adjacent ? a.thr[1] : a.thr[2]);
             }
         }

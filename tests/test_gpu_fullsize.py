@@ -127,7 +127,7 @@ def test_ppr_rmat22_every_query():
     G.close()
 
 
-@pytest.mark.parametrize("name,sampler,index", [("node2vec-rmat24", "orej", "adjacency"),
+@pytest.mark.parametrize("name,sampler,index", [("node2vec-rmat24", "orej", "edge"),
                                                 ("metapath-rmat24", "its", "label")])
 def test_rmat24_sampled_queries(name, sampler, index):
     wl = synth.WORKLOADS[name]
@@ -136,7 +136,7 @@ def test_rmat24_sampled_queries(name, sampler, index):
     log(f"  {name}: n={g.n} m={g.m} nq={len(src)}")
     G = trw.Graph(g.row_ptr, g.col, g.weight, g.label, symmetric=wl.symmetric)
     assert G.validate() == 0
-    table = G.adjacency_index() if index == "adjacency" else G.label_index(wl.labels)
+    table = G.edge_index() if index == "edge" else G.label_index(wl.labels)
     p = _params(wl, sampler)
     P, L, S = _walk_full(wl, G, table, p, src)
     Lh, Sh = L.cpu().numpy(), S.cpu().numpy()

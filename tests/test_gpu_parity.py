@@ -62,6 +62,11 @@ class Case:
             self._dev_tables["adj"] = self.G.adjacency_index()
         return self._dev_tables["adj"]
 
+    def edge_index(self):
+        if "eidx" not in self._dev_tables:
+            self._dev_tables["eidx"] = self.G.edge_index()
+        return self._dev_tables["eidx"]
+
     def label_index(self, n_labels):
         key = ("label_index", n_labels)
         if key not in self._dev_tables:
@@ -81,7 +86,7 @@ class Case:
 
 
 def run_both(case, algo, sampler, max_len, seed, src, mode, tuning=None, qid_base=0, stop=0,
-             thr=(65536, 65536, 65536), schema=(), stride=0, label_index=0, adjacency=False):
+             thr=(65536, 65536, 65536), schema=(), stride=0, label_index=0, adjacency=False, edge_index=False):
     g = case.g
     src = np.ascontiguousarray(src, dtype=np.int32)
     nq = len(src)
@@ -93,6 +98,9 @@ def run_both(case, algo, sampler, max_len, seed, src, mode, tuning=None, qid_bas
     table = case.dev_table(sampler) if algo in ("deepwalk", "ppr") else None
     if algo == "metapath" and label_index:
         table = case.label_index(label_index)
+    if edge_index:
+        assert sampler in ("naive", "orej")
+        table = case.edge_index()
     if adjacency:
         assert sampler in ("naive", "orej")
         table = case.adjacency_index()
@@ -574,6 +582,46 @@ def test_adjacency_index_parity(rmat_sym, rmat_dir, algo, sampler, mode):
             assert_same(gpu, ref, 50)
             if algo != "node2vec":
                 break
+
+
+
+@pytest.mark.parametrize("algo,sampler", [("deepwalk", "naive"), ("node2vec", "orej")])
+@pytest.mark.parametrize("mode", [1, 0])
+def test_edge_index_parity(rmat_sym, rmat_dir, algo, sampler, mode):
+    """Node2Vec's adjacency test by the edge index's hash set: same paths as the
+    oracle's binary search, on a symmetric and a directed graph (where the test
+    must ask about prev -> x, not x -> prev)."""
+    for case in (rmat_sym, rmat_dir):
+        n = case.g.n
+        src = np.concatenate([np.arange(n), synth.sources(77, n, 3)]).astype(np.int32)
+        for pq in ((2.0, 0.5), (0.25, 4.0), (1.0, 1.0)):
+            kw = _args(algo)
+            if algo == "node2vec":
+                kw["thr"] = oracle.n2v_thresholds(*pq)
+            gpu, ref = run_both(case, algo, sampler, 50, 4321, src, mode, edge_index=True, **kw)
+            assert_same(gpu, ref, 50)
+            if algo != "node2vec":
+                break
+
+
+def test_edge_index_layout(rmat_dir):
+    """The documented layout: adjacency records, then a hash set holding exactly the edges."""
+    g = rmat_dir.g
+    t = rmat_dir.edge_index()
+    torch.cuda.synchronize()
+    raw = t.buf.cpu().numpy()
+    rec_bytes = (16 * g.m + 255) // 256 * 256
+    rec = raw[:16 * g.m].view(np.uint32).reshape(-1, 4)
+    assert np.array_equal(rec[:, 0].view(np.int32), g.col)
+    slots = 64
+    while slots < 2 * g.m:
+        slots *= 2
+    keys = raw[rec_bytes:rec_bytes + 8 * slots].view(np.uint64)
+    assert raw.size >= rec_bytes + 8 * slots
+    full = keys[keys != np.uint64(0xFFFFFFFFFFFFFFFF)]
+    src = np.repeat(np.arange(g.n, dtype=np.uint64), np.diff(g.row_ptr.astype(np.int64)))
+    want = (src << np.uint64(32)) | g.col.astype(np.uint64)
+    assert np.array_equal(np.sort(full), np.sort(want))
 
 
 def test_validate_checks_symmetry():

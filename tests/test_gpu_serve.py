@@ -36,9 +36,10 @@ def env():
     assert G.validate() == 0
     alias = G.table("alias")
     adj = G.adjacency_index()
+    eidx = G.edge_index()
     thr, al = oracle.alias_build(g.row_ptr, g.weight)
     torch.cuda.synchronize()
-    return dict(g=g, G=G, alias=alias, adj=adj, orc_alias=(thr, al))
+    return dict(g=g, G=G, alias=alias, adj=adj, eidx=eidx, orc_alias=(thr, al))
 
 
 SERVED = [("deepwalk", "alias", 80), ("ppr", "alias", 256), ("node2vec", "orej", 80),
@@ -79,15 +80,16 @@ def same(a, b, max_len):
     assert np.array_equal(Pa[:, :max_len + 1][mask], Pb[:, :max_len + 1][mask])
 
 
-def make_server(env, **kw):
+def make_server(env, index="adj", **kw):
     cfg = dict(pool_bytes=256 << 20, max_slots=256 * 64, steps_per_tick=16)
     cfg.update(kw)
-    return trw.Server(env["G"], env["alias"], env["adj"], **cfg)
+    return trw.Server(env["G"], env["alias"], env[index], **cfg)
 
 
-def test_served_equals_walk_and_oracle(env):
+@pytest.mark.parametrize("index", ["adj", "eidx"])
+def test_served_equals_walk_and_oracle(env, index):
     g = env["g"]
-    srv = make_server(env)
+    srv = make_server(env, index=index)
     src = synth.sources(777, g.n, 31)
     for algo, sampler, max_len in SERVED:
         log(f"  served {algo}/{sampler}")
