@@ -334,7 +334,7 @@ def bench_served(args, wl, np, torch, synth, trw, props):
     G = trw.Graph(g.row_ptr, g.col, g.weight, symmetric=True, device="cuda:0")
     assert G.validate() == 0
     pre = {}
-    for name, fn in (("alias", lambda: G.table("alias")), ("adjacency", lambda: G.adjacency_index())):
+    for name, fn in (("alias", lambda: G.table("alias")), ("edge_index", lambda: G.edge_index())):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         tab = fn()

@@ -161,8 +161,8 @@ def test_served_rmat26_sampled_queries():
     G = trw.Graph(g.row_ptr, g.col, g.weight, symmetric=True)
     assert G.validate() == 0
     alias = G.table("alias")
-    adj = G.adjacency_index()
-    srv = trw.Server(G, alias, adj, pool_bytes=2 << 30)
+    eidx = G.edge_index()
+    srv = trw.Server(G, alias, eidx, pool_bytes=2 << 30)
     rng = np.random.default_rng(77)
     algos = [("deepwalk", "alias", 80), ("ppr", "alias", 256), ("node2vec", "orej", 80)]
     reqs = []
