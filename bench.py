@@ -269,6 +269,37 @@ def main():
                                             "moves": r["moves"]}
                 log(f"variant {s}/{mname}: {v:.4g} steps/s")
 
+    # The same walk written as a walk program (the step-centric programming
+    # model, compiled at run time): what the generic framework costs.
+    if not args.no_variants and not args.profile_pass:
+        prog_src, user, ptab = None, (), None
+        base = sampler.split("+")[0]
+        if wl.algo in ("ppr", "deepwalk") and base in ("naive", "alias", "its"):
+            prog_src = trw.programs.ppr(base) if wl.algo == "ppr" else trw.programs.deepwalk(base)
+            user = (kw.get("stop_q32", 0),)
+            ptab = tables.get(sampler) if base != "naive" else None
+        elif wl.algo == "node2vec":
+            prog_src, user = trw.programs.NODE2VEC, tuple(kw["n2v_thr_q16"])
+            ptab = tables.get("orej+eidx")
+        elif wl.algo == "metapath":
+            prog_src, user = trw.programs.METAPATH, (len(kw["schema"]),) + tuple(kw["schema"])
+        if prog_src is not None:
+            t0 = time.perf_counter()
+            prog = trw.Program(prog_src)
+            compile_s = time.perf_counter() - t0
+            prog.walk(G, ptab, d_src, wl.max_len, wl.walk_seed, user=user)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(3):
+                _, plen, _ = prog.walk(G, ptab, d_src, wl.max_len, wl.walk_seed, user=user)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            pm = int(plen.to(torch.int64).sum().item())
+            variants["program"] = {"steps_per_s": round(pm * 3 / wall, 1), "ms_per_batch": round(1000 * wall / 3, 3),
+                                   "moves": pm, "compile_s": round(compile_s, 2)}
+            log(f"variant program: {pm * 3 / wall:.4g} steps/s (compiled in {compile_s:.2f}s)")
+            prog.close()
+
     # Random-gather ceiling of the device (dependent and independent chains).
     gather = None
     if not args.no_probe:

@@ -290,6 +290,58 @@ trw_status trw_autotune(trw_graph g, trw_table table, const trw_walk_params *p,
                         trw_stream_t stream, trw_tuning *out, float *best_ms);
 
 /* ------------------------------------------------------------------------ */
+/* Walk programs (Step-centric Programming: the user picks the sampling      */
+/* method and writes Weight and Update).  A program is HIP C++ source that   */
+/* defines `struct TrwProgram` against paper_2107_11983_amd/csrc/            */
+/* program_rt.hpp (it documents the interface):                              */
+/*   static constexpr uint32_t kind;   trw_prog::STATIC_NAIVE, STATIC_ALIAS,  */
+/*                                     STATIC_ITS, DYNAMIC_REJ, DYNAMIC_ITS   */
+/*   __device__ uint32_t weight(walker, graph, params, slot) const;          */
+/*       DYNAMIC_REJ: Weight / MaxWeight as Q16 in [0, 65536] (O-REJ);        */
+/*       DYNAMIC_ITS: an integer weight (row sums below 2^32)                 */
+/*   __device__ bool update(walker, graph, params, r2) const;                */
+/*       after a move; true ends the walk (STOPPED)                           */
+/* The framework runs the batch with the random contract of trw_walk, so    */
+/* DeepWalk, PPR, Node2Vec and MetaPath written as programs reproduce the    */
+/* built-in walks bit for bit.  Compilation needs the csrc/ directory next   */
+/* to libtrw.so (the header is included at run time).                        */
+/* ------------------------------------------------------------------------ */
+typedef struct trw_program_s *trw_program;
+
+typedef struct {
+    uint32_t max_len;          /* moves, 1..65535 */
+    uint32_t reserved;
+    uint64_t seed;             /* Philox key */
+    uint32_t user[16];         /* the program's parameters (params.user in device code) */
+} trw_program_params;
+
+/* Compile a program for `arch` (e.g. "gfx950") without loading it: TRW_OK, or
+ * TRW_E_INVALID with the compiler's log in trw_last_error().  Needs no GPU. */
+trw_status trw_program_check(const char *source, const char *arch);
+
+/* Compile and load a program for the current device.  Errors as
+ * trw_program_check, TRW_E_DEVICE if the module cannot be loaded. */
+trw_status trw_program_create(const char *source, trw_program *out);
+
+/* The program's sampling method (TrwProgram::kind). */
+trw_status trw_program_kind(trw_program p, uint32_t *kind);
+
+/*
+ * Run nq queries of program p: query i starts at d_sources[i] with id
+ * qid_base + i; outputs as trw_walk (paths rows of path_stride >= max_len+1,
+ * lengths, status; sources outside [0, n) get BAD_SOURCE).  table: the ALIAS
+ * or ITS table for STATIC_ALIAS / STATIC_ITS programs; otherwise NULL or an
+ * edge index (then graph.is_neighbor probes its hash set).  d_ws: 8 bytes of
+ * device scratch, 8-byte aligned.  Asynchronous on `stream`.
+ */
+trw_status trw_program_walk(trw_program p, trw_graph g, trw_table table, const trw_program_params *params,
+                            const int32_t *d_sources, uint64_t nq, uint64_t qid_base, int32_t *d_paths,
+                            uint64_t path_stride, uint32_t *d_lengths, uint8_t *d_status, void *d_ws,
+                            size_t ws_bytes, trw_stream_t stream);
+
+trw_status trw_program_destroy(trw_program p);
+
+/* ------------------------------------------------------------------------ */
 /* Serving (all calls thread-safe).  A server keeps the graph, its tables and */
 /* a pool of walker slots resident on the GPU and runs a host thread that     */
 /* admits requests as memory and request slots free up (continuous batching: */

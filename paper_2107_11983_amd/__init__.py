@@ -12,7 +12,7 @@ from typing import Optional, Sequence
 import numpy as np
 import torch
 
-from . import _abi
+from . import _abi, programs  # noqa: F401  (programs: walk program sources)
 from ._abi import (TRW_E_CANCELLED, TRW_E_NOMEM_BUDGET, TRW_E_TIMEOUT, TRW_REQ_HOST, trw_completion,
                    trw_request, trw_server_cfg, trw_server_stats)
 from ._abi import (TRW_A_DEEPWALK, TRW_A_METAPATH, TRW_A_NODE2VEC, TRW_A_PPR, TRW_G_SYMMETRIC,
@@ -21,7 +21,7 @@ from ._abi import (TRW_A_DEEPWALK, TRW_A_METAPATH, TRW_A_NODE2VEC, TRW_A_PPR, TR
                    trw_tuning, trw_walk_params)
 
 __all__ = ["Graph", "Table", "walk", "make_params", "workspace_bytes", "default_tuning", "autotune",
-           "TrwError", "ALGOS", "SAMPLERS"]
+           "TrwError", "ALGOS", "SAMPLERS", "Program", "check_program", "programs", "Server"]
 
 ALGOS = {"deepwalk": TRW_A_DEEPWALK, "ppr": TRW_A_PPR, "node2vec": TRW_A_NODE2VEC, "metapath": TRW_A_METAPATH}
 SAMPLERS = {"naive": TRW_S_NAIVE, "alias": TRW_S_ALIAS, "its": TRW_S_ITS, "orej": TRW_S_OREJ}
@@ -333,6 +333,62 @@ class Server:
             _abi.trw_server_destroy(self.handle)
             self.handle = None
             self._live = {}
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------
+# Walk programs (C ABI trw_program_*): user-written sampling rules compiled at
+# run time against csrc/program_rt.hpp.
+# ---------------------------------------------------------------------------
+PROGRAM_KINDS = {"static_naive": 0, "static_alias": 1, "static_its": 2, "dynamic_rej": 3, "dynamic_its": 4}
+
+
+def check_program(source: str, arch: str = "gfx950") -> None:
+    """Compile a walk program without loading it (no GPU needed); raises TrwError with the log."""
+    check(_abi.trw_program_check(source.encode(), arch.encode()))
+
+
+class Program:
+    """A walk program: `struct TrwProgram` (kind, weight, update) in HIP C++."""
+
+    def __init__(self, source: str):
+        h = ctypes.c_void_p()
+        check(_abi.trw_program_create(source.encode(), ctypes.byref(h)))
+        self.handle = h
+        k = ctypes.c_uint32(0)
+        check(_abi.trw_program_kind(h, ctypes.byref(k)))
+        self.kind = int(k.value)
+
+    def walk(self, graph: Graph, table: Optional[Table], sources: torch.Tensor, max_len: int, seed: int,
+             user: Sequence[int] = (), qid_base: int = 0, stride: int = 0, stream=None):
+        """Run len(sources) queries; returns (paths int32[nq, stride], lengths, status) like walk()."""
+        nq = int(sources.numel())
+        pp = _abi.trw_program_params()
+        pp.max_len = int(max_len)
+        pp.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
+        for i, v in enumerate(user):
+            pp.user[i] = int(v) & 0xFFFFFFFF
+        stride = stride or ((max_len + 1 + 15) // 16 * 16)
+        dev = graph.device
+        paths = torch.empty((nq, stride), dtype=torch.int32, device=dev)
+        lengths = torch.empty(nq, dtype=torch.int32, device=dev)
+        status = torch.empty(nq, dtype=torch.uint8, device=dev)
+        ws = torch.empty(256, dtype=torch.uint8, device=dev)
+        check(_abi.trw_program_walk(self.handle, graph.handle, table.handle if table is not None else None,
+                                    ctypes.byref(pp), _dptr(sources), nq, qid_base, _dptr(paths), stride,
+                                    _dptr(lengths), _dptr(status), _dptr(ws), ws.numel(), _stream_ptr(stream)))
+        self._ws = ws
+        return paths, lengths, status
+
+    def close(self):
+        if self.handle:
+            _abi.trw_program_destroy(self.handle)
+            self.handle = None
 
     def __del__(self):
         try:

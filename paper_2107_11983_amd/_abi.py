@@ -48,6 +48,11 @@ class trw_server_cfg(ctypes.Structure):
 TRW_REQ_HOST = 1
 
 
+class trw_program_params(ctypes.Structure):
+    _fields_ = [("max_len", ctypes.c_uint32), ("reserved", ctypes.c_uint32), ("seed", ctypes.c_uint64),
+                ("user", ctypes.c_uint32 * 16)]
+
+
 class trw_request(ctypes.Structure):
     _fields_ = [("params", trw_walk_params), ("sources", ctypes.c_void_p), ("nq", ctypes.c_uint32),
                 ("flags", ctypes.c_uint32), ("qid_base", ctypes.c_uint64), ("paths", ctypes.c_void_p),
@@ -115,9 +120,15 @@ _SIGS = {
     "trw_server_poll": (_st, [_P, ctypes.POINTER(trw_completion), _u32, ctypes.POINTER(_u32), _u32]),
     "trw_server_stats_get": (_st, [_P, ctypes.POINTER(trw_server_stats)]),
     "trw_server_destroy": (_st, [_P]),
-    # measurement probe (include/trw_probe.h)
     "trw_edge_index_bytes": (_st, [_P, ctypes.POINTER(_sz)]),
     "trw_edge_index_build": (_st, [_P, _P, _sz, _P, _PP]),
+    "trw_program_check": (_st, [ctypes.c_char_p, ctypes.c_char_p]),
+    "trw_program_create": (_st, [ctypes.c_char_p, _PP]),
+    "trw_program_kind": (_st, [_P, ctypes.POINTER(_u32)]),
+    "trw_program_walk": (_st, [_P, _P, _P, ctypes.POINTER(trw_program_params), _P, _u64, _u64, _P, _u64, _P, _P,
+                               _P, _sz, _P]),
+    "trw_program_destroy": (_st, [_P]),
+    # measurement probe (include/trw_probe.h)
     "trw_probe_fill": (ctypes.c_int, [_P, _u64, _u32, _P]),
     "trw_probe_gather": (ctypes.c_int, [_P, _u64, _u32, _u32, _u32, ctypes.c_int, _u32, _u32, _P, _P]),
     "trw_probe_scatter": (ctypes.c_int, [_P, _u64, _u32, _u32, _u32, _u32, _P]),
@@ -167,6 +178,11 @@ trw_server_cancel = lib.trw_server_cancel
 trw_server_poll = lib.trw_server_poll
 trw_server_stats_get = lib.trw_server_stats_get
 trw_server_destroy = lib.trw_server_destroy
+trw_program_check = lib.trw_program_check
+trw_program_create = lib.trw_program_create
+trw_program_kind = lib.trw_program_kind
+trw_program_walk = lib.trw_program_walk
+trw_program_destroy = lib.trw_program_destroy
 trw_edge_index_bytes = lib.trw_edge_index_bytes
 trw_edge_index_build = lib.trw_edge_index_build
 trw_probe_fill = lib.trw_probe_fill

@@ -3,8 +3,20 @@
 // (gfx950), wave64.
 #pragma once
 
+#if !defined(__HIPCC_RTC__)
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#else   // runtime compilation (walk programs): the runtime is built in, the integer types namespaced
+using __hip_internal::int8_t;
+using __hip_internal::int16_t;
+using __hip_internal::int32_t;
+using __hip_internal::int64_t;
+using __hip_internal::uint8_t;
+using __hip_internal::uint16_t;
+using __hip_internal::uint32_t;
+using __hip_internal::uint64_t;
+typedef unsigned long uintptr_t;
+#endif
 
 namespace trw {
 
@@ -64,5 +76,90 @@ __device__ __forceinline__ uint32_t wave_append(uint32_t *counter, bool want) {
     base = __shfl(base, (int)leader);
     return base + rank_below(mask);
 }
+
+
+// Edge hash set of the edge index: open addressing with linear probing from
+// SplitMix64's finalizer (Steele, Lea, Flood 2014) of the key u << 32 | v;
+// empty slots hold kEsetEmpty (no key has its top bit set: ids are < 2^31).
+constexpr unsigned long long kEsetEmpty = ~0ull;
+
+__host__ __device__ inline unsigned long long eset_hash(unsigned long long k) {
+    k ^= k >> 30; k *= 0xBF58476D1CE4E5B9ull;
+    k ^= k >> 27; k *= 0x94D049BB133111EBull;
+    return k ^ (k >> 31);
+}
+
+// Is (u, v) in the set?  The set is at most half full, so a probe sequence
+// ends at an empty slot.
+__device__ __forceinline__ bool eset_has(const unsigned long long *__restrict__ keys, unsigned long long mask,
+                                         int32_t u, int32_t v) {
+    const unsigned long long key = ((unsigned long long)(uint32_t)u << 32) | (uint32_t)v;
+    for (unsigned long long h = eset_hash(key) & mask;; h = (h + 1) & mask) {
+        const unsigned long long k = keys[h];
+        if (k == key) return true;
+        if (k == kEsetEmpty) return false;
+    }
+}
+
+// ALIAS move from the 32-byte entry of column j: next vertex and its row range.
+__device__ __forceinline__ int32_t alias_pick(const uint4 &e0, const uint4 &e1, uint32_t r1, int32_t &off,
+                                              int32_t &deg) {
+    const bool first = r1 < e0.x;
+    off = (int32_t)(first ? e1.x : e1.z);
+    deg = (int32_t)(first ? e1.y : e1.w);
+    return (int32_t)(first ? e0.y : e0.z);                  // -1 marks a row of zero weight
+}
+
+// ---------------------------------------------------------------------------
+// Path writer: up to 4 pending entries per walker, flushed as one 16-byte
+// store when they end on a 16-byte boundary, else entry by entry at the end.
+// ---------------------------------------------------------------------------
+struct PathBuf {
+    int32_t *p;      // address of the first pending entry
+    uint32_t n;      // pending entries
+    int32_t b0, b1, b2, b3;
+
+    __device__ __forceinline__ void start(int32_t *row) { p = row; n = 0; }
+
+    __device__ __forceinline__ void flush() {
+        if (n == 4) {
+            *reinterpret_cast<int4 *>(p) = make_int4(b0, b1, b2, b3);
+        } else {
+            if (n > 0) p[0] = b0;
+            if (n > 1) p[1] = b1;
+            if (n > 2) p[2] = b2;
+        }
+        p += n;
+        n = 0;
+    }
+
+    // Last flush of a walk.  The entries after a path's end are unspecified,
+    // so the rest of the 64-byte block that holds the last entry is filled
+    // (with -1) as far as the row reaches: the block then goes to memory as
+    // one whole write rather than a partial one, which HBM has to merge
+    // with the old contents.  row_end: one past the row's last entry.  Rows
+    // that do not start on 16 bytes (any stride is allowed) get plain writes.
+    __device__ __forceinline__ void finish(const int32_t *row_end) {
+        if ((reinterpret_cast<uintptr_t>(p) & 15u) != 0 || p + 4 > row_end) {
+            flush();
+            return;
+        }
+        if (n > 0) {
+            *reinterpret_cast<int4 *>(p) = make_int4(b0, n > 1 ? b1 : -1, n > 2 ? b2 : -1, -1);
+            p += 4;
+            n = 0;
+        }
+        while ((reinterpret_cast<uintptr_t>(p) & 63u) != 0 && p + 4 <= row_end) {
+            *reinterpret_cast<int4 *>(p) = make_int4(-1, -1, -1, -1);
+            p += 4;
+        }
+    }
+
+    __device__ __forceinline__ void push(int32_t v) {
+        if (n == 0) b0 = v; else if (n == 1) b1 = v; else if (n == 2) b2 = v; else b3 = v;
+        ++n;
+        if (((reinterpret_cast<uintptr_t>(p + n)) & 15u) == 0) flush();
+    }
+};
 
 }  // namespace trw

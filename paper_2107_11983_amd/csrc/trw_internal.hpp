@@ -7,6 +7,7 @@
 #include <string>
 
 #include "../../include/trw.h"
+#include "trw_device.hpp"
 
 namespace trw {
 
@@ -43,21 +44,12 @@ struct TableDev {
     unsigned long long eset_mask;     // its slot count - 1 (a power of two)
 };
 
-// Edge hash set: open addressing, linear probing, at most half full; empty
-// slots hold kEsetEmpty (no key has both top bits set since ids are < 2^31).
-constexpr unsigned long long kEsetEmpty = ~0ull;
-
+// Edge hash set slots: at most half full (kEsetEmpty and eset_hash are in
+// trw_device.hpp, shared with walk programs).
 __host__ __device__ inline unsigned long long eset_slots(int64_t m) {
     unsigned long long cap = 64;
     while (cap < 2ull * (unsigned long long)m) cap <<= 1;
     return cap;
-}
-
-// SplitMix64's finalizer (Steele, Lea, Flood 2014) as the slot hash.
-__host__ __device__ inline unsigned long long eset_hash(unsigned long long k) {
-    k ^= k >> 30; k *= 0xBF58476D1CE4E5B9ull;
-    k ^= k >> 27; k *= 0x94D049BB133111EBull;
-    return k ^ (k >> 31);
 }
 constexpr size_t kAliasEntryBytes = 32;
 constexpr uint32_t kMaxIndexLabels = 64;

@@ -57,17 +57,6 @@ __device__ __forceinline__ bool in_row(const int32_t *__restrict__ col, int32_t 
     return false;
 }
 
-// Is (u, v) an edge?  Probes the edge index's hash set.
-__device__ __forceinline__ bool eset_has(const unsigned long long *__restrict__ keys, unsigned long long mask,
-                                         int32_t u, int32_t v) {
-    const unsigned long long key = ((unsigned long long)(uint32_t)u << 32) | (uint32_t)v;
-    for (unsigned long long h = eset_hash(key) & mask;; h = (h + 1) & mask) {
-        const unsigned long long k = keys[h];
-        if (k == key) return true;
-        if (k == kEsetEmpty) return false;
-    }
-}
-
 template <bool ADJ>
 __device__ __forceinline__ int32_t n2v_move(const GraphDev &g, const TableDev &t, const WalkDev &a, uint64_t qid,
                                             uint32_t k, int32_t off, uint32_t d, const Rand4 &r, int32_t prev,
@@ -109,66 +98,5 @@ __device__ __forceinline__ int32_t n2v_move(const GraphDev &g, const TableDev &t
         }
     }
 }
-
-// ALIAS move from the 32-byte entry of column j: next vertex and its row range.
-__device__ __forceinline__ int32_t alias_pick(const uint4 &e0, const uint4 &e1, uint32_t r1, int32_t &off,
-                                              int32_t &deg) {
-    const bool first = r1 < e0.x;
-    off = (int32_t)(first ? e1.x : e1.z);
-    deg = (int32_t)(first ? e1.y : e1.w);
-    return (int32_t)(first ? e0.y : e0.z);                  // -1 marks a row of zero weight
-}
-
-// ---------------------------------------------------------------------------
-// Path writer: up to 4 pending entries per walker, flushed as one 16-byte
-// store when they end on a 16-byte boundary, else entry by entry at the end.
-// ---------------------------------------------------------------------------
-struct PathBuf {
-    int32_t *p;      // address of the first pending entry
-    uint32_t n;      // pending entries
-    int32_t b0, b1, b2, b3;
-
-    __device__ __forceinline__ void start(int32_t *row) { p = row; n = 0; }
-
-    __device__ __forceinline__ void flush() {
-        if (n == 4) {
-            *reinterpret_cast<int4 *>(p) = make_int4(b0, b1, b2, b3);
-        } else {
-            if (n > 0) p[0] = b0;
-            if (n > 1) p[1] = b1;
-            if (n > 2) p[2] = b2;
-        }
-        p += n;
-        n = 0;
-    }
-
-    // Last flush of a walk.  The entries after a path's end are unspecified,
-    // so the rest of the 64-byte block that holds the last entry is filled
-    // (with -1) as far as the row reaches: the block then goes to memory as
-    // one whole write rather than a partial one, which HBM has to merge
-    // with the old contents.  row_end: one past the row's last entry.  Rows
-    // that do not start on 16 bytes (any stride is allowed) get plain writes.
-    __device__ __forceinline__ void finish(const int32_t *row_end) {
-        if ((reinterpret_cast<uintptr_t>(p) & 15u) != 0 || p + 4 > row_end) {
-            flush();
-            return;
-        }
-        if (n > 0) {
-            *reinterpret_cast<int4 *>(p) = make_int4(b0, n > 1 ? b1 : -1, n > 2 ? b2 : -1, -1);
-            p += 4;
-            n = 0;
-        }
-        while ((reinterpret_cast<uintptr_t>(p) & 63u) != 0 && p + 4 <= row_end) {
-            *reinterpret_cast<int4 *>(p) = make_int4(-1, -1, -1, -1);
-            p += 4;
-        }
-    }
-
-    __device__ __forceinline__ void push(int32_t v) {
-        if (n == 0) b0 = v; else if (n == 1) b1 = v; else if (n == 2) b2 = v; else b3 = v;
-        ++n;
-        if (((reinterpret_cast<uintptr_t>(p + n)) & 15u) == 0) flush();
-    }
-};
 
 }  // namespace trw
