@@ -203,3 +203,58 @@ def test_metapath_program_on_hub_rows():
                       label=g.label)
     _same(got, (orc.paths, orc.lengths, orc.status), 30)
     prog.close()
+
+
+def _second_move_law(P, cur_first, expect_fn):
+    """χ² of the second move's destination for each first-move vertex."""
+    for cur in np.unique(P[:, 1]):
+        sel = P[:, 1] == cur
+        nxt = P[sel, 2]
+        cand, expect = expect_fn(int(cur))
+        counts = np.array([(nxt == x).sum() for x in cand])
+        assert counts.sum() == sel.sum()
+        if len(cand) > 1:
+            _, pval = scipy.stats.chisquare(counts, np.array(expect, float) / sum(expect) * counts.sum())
+            log(f"  cur={cur} counts={counts.tolist()} p={pval:.3g}")
+            assert pval > 1e-6
+
+
+def test_node2vec_its_program_law():
+    """Node2Vec by dynamic ITS: P(x | prev, cur) proportional to the factor of x."""
+    pairs = [(0, 1), (1, 2), (0, 2), (2, 3), (1, 3)]
+    gt = undirected(4, pairs)
+    G = trw.Graph(gt.row_ptr, gt.col, None, symmetric=True)
+    assert G.validate() == 0
+    prog = trw.Program(trw.programs.NODE2VEC_ITS)
+    f = (1, 2, 4)                                   # 1/p, 1, 1/q for p = 2, q = 0.5, as integers
+    d_src = torch.ones(1 << 20, dtype=torch.int32, device="cuda")
+    P, L, S = _np(*prog.walk(G, None, d_src, 2, 99, user=f))
+    assert (L == 2).all()
+    rp, col = gt.row_ptr, gt.col
+    nb = {u: set(int(x) for x in col[rp[u]:rp[u + 1]]) for u in range(4)}
+    first = np.bincount(P[:, 1], minlength=4)[sorted(nb[1])]
+    _, pval = scipy.stats.chisquare(first)              # first move uniform
+    assert pval > 1e-6
+
+    def expect(cur):
+        cand = sorted(nb[cur])
+        return cand, [f[0] if x == 1 else (f[1] if x in nb[1] else f[2]) for x in cand]
+    _second_move_law(P, 1, expect)
+    prog.close()
+
+
+def test_weighted_rej_program_law():
+    """REJ with a global bound: each move follows e with probability w(e) / sum of the row."""
+    gt = synth.from_edges(5, [(0, 1), (0, 2), (0, 3), (0, 4), (1, 0), (2, 0), (3, 0), (4, 0)],
+                          weights=[1, 2, 3, 10, 1, 1, 1, 1])
+    G = trw.Graph(gt.row_ptr, gt.col, gt.weight)
+    assert G.validate() == 0
+    prog = trw.Program(trw.programs.WEIGHTED_REJ)
+    d_src = torch.zeros(1 << 20, dtype=torch.int32, device="cuda")
+    P, L, S = _np(*prog.walk(G, None, d_src, 1, 5, user=(16,)))    # 16 bounds every weight (exact Q16)
+    assert (L == 1).all()
+    counts = np.bincount(P[:, 1], minlength=5)[1:]
+    _, pval = scipy.stats.chisquare(counts, np.array([1, 2, 3, 10]) / 16 * counts.sum())
+    log(f"  counts={counts.tolist()} p={pval:.3g}")
+    assert pval > 1e-6
+    prog.close()

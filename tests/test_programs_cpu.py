@@ -11,6 +11,8 @@ SOURCES = {
     "node2vec": programs.NODE2VEC,
     "metapath": programs.METAPATH,
     "weighted-node2vec": programs.WEIGHTED_NODE2VEC,
+    "node2vec-its": programs.NODE2VEC_ITS,
+    "weighted-rej": programs.WEIGHTED_REJ,
 }
 
 
