@@ -8,7 +8,7 @@ two meet only through the seeded inputs of ``synth``.
 
 Parameter encoding used here (its own, not the library's):
   algo    : 0 DeepWalk, 1 PPR, 2 Node2Vec, 3 MetaPath
-  sampler : 0 NAIVE, 1 ALIAS, 2 ITS, 3 O-REJ
+  sampler : 0 NAIVE, 1 ALIAS, 2 ITS, 3 O-REJ, 4 REJ
   status  : 1 length reached, 2 PPR stop, 3 dead end, 4 source out of range
 """
 from __future__ import annotations
@@ -27,10 +27,10 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 DEEPWALK, PPR, NODE2VEC, METAPATH = 0, 1, 2, 3
-NAIVE, ALIAS, ITS, OREJ = 0, 1, 2, 3
+NAIVE, ALIAS, ITS, OREJ, REJ = 0, 1, 2, 3, 4
 ST_LENGTH, ST_STOPPED, ST_DEAD_END, ST_BAD_SOURCE = 1, 2, 3, 4
 ALGOS = {"deepwalk": DEEPWALK, "ppr": PPR, "node2vec": NODE2VEC, "metapath": METAPATH}
-SAMPLERS = {"naive": NAIVE, "alias": ALIAS, "its": ITS, "orej": OREJ}
+SAMPLERS = {"naive": NAIVE, "alias": ALIAS, "its": ITS, "orej": OREJ, "rej": REJ}
 
 
 def build(force: bool = True) -> str:
@@ -51,7 +51,8 @@ class _Params(ctypes.Structure):
 class Counters(ctypes.Structure):
     _fields_ = [("moves", ctypes.c_uint64), ("philox_blocks", ctypes.c_uint64),
                 ("its_probes", ctypes.c_uint64), ("orej_trials", ctypes.c_uint64),
-                ("adjacency_probes", ctypes.c_uint64), ("label_reads", ctypes.c_uint64)]
+                ("adjacency_probes", ctypes.c_uint64), ("label_reads", ctypes.c_uint64),
+                ("rej_trials", ctypes.c_uint64)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -70,10 +71,17 @@ def _load():
         lib.trwo_alias_build.argtypes = [ctypes.c_int64, P, P, P, P]
         lib.trwo_its_build.restype = ctypes.c_int
         lib.trwo_its_build.argtypes = [ctypes.c_int64, P, P, P]
+        lib.trwo_rej_build.restype = ctypes.c_int
+        lib.trwo_rej_build.argtypes = [ctypes.c_int64, P, P, P]
         lib.trwo_walk.restype = ctypes.c_int
-        lib.trwo_walk.argtypes = [ctypes.c_int64, P, P, P, P, P, P, ctypes.POINTER(_Params),
+        lib.trwo_walk.argtypes = [ctypes.c_int64, P, P, P, P, P, P, P, P, ctypes.POINTER(_Params),
                                   P, ctypes.c_int64, ctypes.c_uint64, P, P, ctypes.c_int64, P, P,
                                   ctypes.POINTER(Counters)]
+        lib.trwo_end_counts.restype = ctypes.c_int64
+        lib.trwo_end_counts.argtypes = [ctypes.c_int64, P, ctypes.c_int64, P, P, ctypes.c_int64,
+                                        ctypes.c_int64, P]
+        lib.trwo_topk.restype = ctypes.c_int
+        lib.trwo_topk.argtypes = [ctypes.c_int64, P, ctypes.c_int64, P, P]
         _lib = lib
     return _lib
 
@@ -102,6 +110,45 @@ def alias_build(row_ptr: np.ndarray, weight: np.ndarray):
     if rc != 0:
         raise RuntimeError(f"trwo_alias_build failed: {rc}")
     return thr, alias
+
+
+def rej_build(row_ptr: np.ndarray, weight: np.ndarray) -> np.ndarray:
+    """REJ's per-vertex bound p*_v: the largest weight of each row (0 if empty)."""
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    w = np.ascontiguousarray(weight, dtype=np.uint32)
+    pmax = np.zeros(len(rp) - 1, dtype=np.uint32)
+    _load().trwo_rej_build(len(rp) - 1, _p(rp), _p(w), _p(pmax))
+    return pmax
+
+
+def end_counts(n: int, paths: np.ndarray, lengths: np.ndarray, status: np.ndarray, group: int = 0,
+               counts: Optional[np.ndarray] = None):
+    """PPR end-vertex counts: (counts uint32[groups, n], skipped queries).
+
+    Query i adds one to counts[i // group, paths[i, lengths[i]]] (group 0: one
+    row for all queries); queries with a bad source are skipped.
+    """
+    P = np.ascontiguousarray(paths, dtype=np.int32)
+    L = np.ascontiguousarray(lengths, dtype=np.uint32)
+    S = np.ascontiguousarray(status, dtype=np.uint8)
+    nq = len(L)
+    groups = 1 if group <= 0 else max(1, -(-nq // group))
+    if counts is None:
+        counts = np.zeros((groups, n), dtype=np.uint32)
+    assert counts.dtype == np.uint32 and counts.flags.c_contiguous and counts.size >= groups * n
+    skipped = _load().trwo_end_counts(n, _p(P), P.shape[1], _p(L), _p(S), nq, group, _p(counts))
+    return counts, int(skipped)
+
+
+def topk(counts: np.ndarray, k: int):
+    """The k largest counts (ids int32[k], counts uint32[k]); ties: smaller id first."""
+    c = np.ascontiguousarray(counts, dtype=np.uint32).reshape(-1)
+    ids = np.zeros(k, dtype=np.int32)
+    vals = np.zeros(k, dtype=np.uint32)
+    rc = _load().trwo_topk(len(c), _p(c), k, _p(ids), _p(vals))
+    if rc != 0:
+        raise ValueError(f"trwo_topk failed: {rc}")
+    return ids, vals
 
 
 def its_build(row_ptr: np.ndarray, weight: np.ndarray) -> np.ndarray:
@@ -161,7 +208,7 @@ class WalkResult:
 
 
 def walk(row_ptr, col, params: WalkParams, sources, qid_base: int = 0, qids=None,
-         thr=None, alias=None, prefix=None, label=None) -> WalkResult:
+         thr=None, alias=None, prefix=None, label=None, weight=None, pmax=None) -> WalkResult:
     """Run every query to completion, one at a time, in query order."""
     rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
     cl = np.ascontiguousarray(col, dtype=np.int32)
@@ -172,6 +219,11 @@ def walk(row_ptr, col, params: WalkParams, sources, qid_base: int = 0, qids=None
         raise ValueError("ALIAS needs thr and alias tables")
     if params.sampler == ITS and params.algo != METAPATH and prefix is None:
         raise ValueError("ITS needs the prefix table")
+    if params.sampler == REJ:
+        if weight is None or pmax is None:
+            raise ValueError("REJ needs the weights and the p* table")
+        weight = np.ascontiguousarray(weight, dtype=np.uint32)
+        pmax = np.ascontiguousarray(pmax, dtype=np.uint32)
     if params.algo == METAPATH and (label is None or not params.schema):
         raise ValueError("MetaPath needs labels and a schema")
     stride = params.max_len + 1
@@ -181,7 +233,7 @@ def walk(row_ptr, col, params: WalkParams, sources, qid_base: int = 0, qids=None
     q = None if qids is None else np.ascontiguousarray(qids, dtype=np.uint64)
     cnt = Counters()
     cp = params.to_c()
-    _load().trwo_walk(n, _p(rp), _p(cl), _p(thr), _p(alias), _p(prefix), _p(label),
+    _load().trwo_walk(n, _p(rp), _p(cl), _p(thr), _p(alias), _p(prefix), _p(weight), _p(pmax), _p(label),
                       ctypes.byref(cp), _p(src), nq, qid_base & 0xFFFFFFFFFFFFFFFF, _p(q),
                       _p(paths), stride, _p(lengths), _p(status), ctypes.byref(cnt))
     return WalkResult(paths, lengths, status, cnt.as_dict())

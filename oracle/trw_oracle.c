@@ -12,12 +12,15 @@
  *     the current vertex, append it" until it terminates [Introduction,
  *     execution-paradigm algorithm; Step-centric Programming, framework
  *     algorithm: Gather, Move, Update in a do-while loop];
- *   - the sampling methods NAIVE, ITS, ALIAS and O-REJ [Sampling Methods];
+ *   - the sampling methods NAIVE, ITS, ALIAS, REJ and O-REJ [Sampling
+ *     Methods];
  *   - the preprocessing of static walks: one sampling table per vertex,
  *     built once [preprocessing algorithm];
  *   - the four applications PPR, DeepWalk, Node2Vec (the second-order
  *     transition equation and the Node2Vec listing), MetaPath [Random Walk
- *     based Algorithms].
+ *     based Algorithms];
+ *   - PPR's estimate from the end vertices of a source's queries, and the
+ *     k highest-scoring vertices [Random Walk based Algorithms, PPR].
  *
  * The paper uses real-valued uniforms; this build fixes one integer random
  * contract so that a second implementation can be compared bit for bit:
@@ -28,6 +31,8 @@
  *   ITS draw in [0, W)       = floor((r1:r0) * W / 2^64)  (64-bit word)
  *   PPR stop coin            = r2 < stop_q32              (after each move)
  *   O-REJ dart height        = r1 >> 16 against Q16 thresholds
+ *   REJ dart (x, y)          = x from r0, hit iff r1 * p*_v < w_x * 2^32
+ *                              (y = r1 * p*_v / 2^32 uniform in [0, p*_v))
  * Integer choices that the paper leaves open are listed with the readings in
  * the design notes of the repository.
  */
@@ -160,16 +165,35 @@ int trwo_its_build(int64_t n, const int32_t *row_ptr, const uint32_t *w, uint64_
 }
 
 /* ------------------------------------------------------------------------ */
+/* REJ initialization [Sampling Methods, rejection sampling]: per vertex the  */
+/* largest weight of its edges, p*_v (0 for a vertex without edges).        */
+/* ------------------------------------------------------------------------ */
+int trwo_rej_build(int64_t n, const int32_t *row_ptr, const uint32_t *w, uint32_t *pmax) {
+    for (int64_t v = 0; v < n; v++) {
+        uint32_t mx = 0;
+        for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; e++)
+            if (w[e] > mx) mx = w[e];
+        pmax[v] = mx;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Walk                                                                      */
 /* ------------------------------------------------------------------------ */
 enum { ORC_DEEPWALK = 0, ORC_PPR = 1, ORC_NODE2VEC = 2, ORC_METAPATH = 3 };
-enum { ORC_NAIVE = 0, ORC_ALIAS = 1, ORC_ITS = 2, ORC_OREJ = 3 };
+enum { ORC_NAIVE = 0, ORC_ALIAS = 1, ORC_ITS = 2, ORC_OREJ = 3, ORC_REJ = 4 };
 enum { ORC_ST_LENGTH = 1, ORC_ST_STOPPED = 2, ORC_ST_DEAD_END = 3, ORC_ST_BAD_SOURCE = 4 };
 
 /* Upper bound on O-REJ darts per move.  With every threshold >= 1 a dart is
    accepted with probability >= 2^-16, so 2^24 darts are exceeded with
    probability below e^-256; the last dart is then taken. */
 #define ORC_OREJ_MAX_TRIALS (1u << 24)
+
+/* The same cap for REJ darts.  A dart at the heaviest edge always hits, so
+   the cap is reached with probability (1 - sum w / (d p*))^(2^24): below
+   e^-65536 when weights differ by at most a factor 256. */
+#define ORC_REJ_MAX_TRIALS (1u << 24)
 
 typedef struct {
     uint32_t algo;
@@ -189,6 +213,7 @@ typedef struct {
     uint64_t orej_trials;      /* O-REJ darts */
     uint64_t adjacency_probes; /* entries read by Node2Vec adjacency tests */
     uint64_t label_reads;      /* labels read by MetaPath */
+    uint64_t rej_trials;       /* REJ darts */
 } trwo_counters;
 
 /* Is x in the sorted row [lo, hi) of col?  Textbook binary search. */
@@ -216,10 +241,12 @@ static int64_t its_search(const uint64_t *prefix, int64_t off, int64_t d, uint64
 /*
  * Run nq queries.  Query i starts at sources[i] and has id qids ? qids[i] : qid_base + i.
  * Its path goes to paths[i * path_stride + 0 .. lengths[i]]; status[i] says why it ended.
- * Tables: thr/alias for ALIAS, prefix for ITS; label for MetaPath.
+ * Tables: thr/alias for ALIAS, prefix for ITS, the weights w and p* for REJ;
+ * label for MetaPath.
  */
 int trwo_walk(int64_t n, const int32_t *row_ptr, const int32_t *col,
               const uint32_t *thr, const int32_t *alias, const uint64_t *prefix,
+              const uint32_t *w, const uint32_t *pmax,
               const uint8_t *label, const trwo_params *p,
               const int32_t *sources, int64_t nq, uint64_t qid_base, const uint64_t *qids,
               int32_t *paths, int64_t path_stride, uint32_t *lengths, uint8_t *status,
@@ -252,6 +279,19 @@ int trwo_walk(int64_t n, const int32_t *row_ptr, const int32_t *col,
                     const int32_t a = alias[off + j];
                     if (a < 0) { st = ORC_ST_DEAD_END; break; }
                     nxt = (r[1] < thr[off + j]) ? col[off + j] : col[off + a];
+                } else if (p->sampler == ORC_REJ) {
+                    /* darts (x, y): x a uniform edge slot, y uniform in
+                       [0, p*); the dart hits iff y < w_x.  The block of the
+                       hitting dart also gives the PPR stop coin. */
+                    const uint32_t ps = pmax[cur];
+                    if (ps == 0) { st = ORC_ST_DEAD_END; break; }
+                    for (uint32_t t = 0;; t++) {
+                        if (t > 0) { block(p->seed, qid, k, t, r); local.philox_blocks++; }
+                        local.rej_trials++;
+                        const uint32_t x = index_of(r[0], d);
+                        const int hit = (uint64_t)r[1] * ps < ((uint64_t)w[off + x] << 32);
+                        if (hit || t + 1 == ORC_REJ_MAX_TRIALS) { nxt = col[off + x]; break; }
+                    }
                 } else { /* ITS */
                     const uint64_t W = prefix[off + d - 1];
                     if (W == 0) { st = ORC_ST_DEAD_END; break; }
@@ -309,6 +349,50 @@ int trwo_walk(int64_t n, const int32_t *row_ptr, const int32_t *col,
         cnt->orej_trials += local.orej_trials;
         cnt->adjacency_probes += local.adjacency_probes;
         cnt->label_reads += local.label_reads;
+        cnt->rej_trials += local.rej_trials;
     }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* PPR estimate [Random Walk based Algorithms, PPR]: the score of v' for a   */
+/* source is the share of that source's queries whose walk ends at v'.       */
+/* Query i belongs to group i / group (every query to group 0 when group is  */
+/* 0); counts[g * n + v] is increased once for each query of group g whose   */
+/* path ends at v, i.e. paths[i * stride + lengths[i]] == v.  Queries with a */
+/* bad source, and paths whose end lies outside the row or outside [0, n),   */
+/* are skipped; their number is returned.                                    */
+/* ------------------------------------------------------------------------ */
+int64_t trwo_end_counts(int64_t n, const int32_t *paths, int64_t stride, const uint32_t *lengths,
+                        const uint8_t *status, int64_t nq, int64_t group, uint32_t *counts) {
+    int64_t skipped = 0;
+    for (int64_t i = 0; i < nq; i++) {
+        if (status[i] == ORC_ST_BAD_SOURCE || (int64_t)lengths[i] >= stride) { skipped++; continue; }
+        const int32_t v = paths[i * stride + lengths[i]];
+        if (v < 0 || (int64_t)v >= n) { skipped++; continue; }
+        const int64_t g = group > 0 ? i / group : 0;
+        counts[g * n + v]++;
+    }
+    return skipped;
+}
+
+/* The k highest counts, larger count first and the smaller vertex id first   */
+/* among equal counts: sort all (count, id) pairs in that order and take k.   */
+typedef struct { uint32_t count; int32_t id; } orc_scored;
+
+static int by_score(const void *a, const void *b) {
+    const orc_scored *x = (const orc_scored *)a, *y = (const orc_scored *)b;
+    if (x->count != y->count) return x->count > y->count ? -1 : 1;
+    return (x->id > y->id) - (x->id < y->id);
+}
+
+int trwo_topk(int64_t n, const uint32_t *counts, int64_t k, int32_t *ids, uint32_t *vals) {
+    if (k < 0 || k > n) return -1;
+    orc_scored *all = (orc_scored *)malloc(sizeof(orc_scored) * (size_t)(n > 0 ? n : 1));
+    if (!all) return -2;
+    for (int64_t v = 0; v < n; v++) { all[v].count = counts[v]; all[v].id = (int32_t)v; }
+    qsort(all, (size_t)n, sizeof(orc_scored), by_score);
+    for (int64_t i = 0; i < k; i++) { ids[i] = all[i].id; vals[i] = all[i].count; }
+    free(all);
     return 0;
 }

@@ -10,7 +10,8 @@ Each check is tied to something outside the oracle's own code:
   * PPR end-vertex distribution against power iteration, and the expected
     walk length of 5 at stop probability 0.2 that the paper states (Evaluation
     of Step Interleaving);
-  * the O-REJ expected number of darts d * p* / sum p (Sampling Methods).
+  * the O-REJ and REJ expected number of darts d * p* / sum p (Sampling
+    Methods).
 """
 import itertools
 import math
@@ -36,6 +37,8 @@ def _walk(g, algo, sampler, max_len, sources, seed=1, qid_base=0, qids=None, sto
         kw.update(thr=t, alias=a)
     if sampler == oracle.ITS and algo != oracle.METAPATH:
         kw.update(prefix=tables if tables is not None else oracle.its_build(g.row_ptr, g.weight))
+    if sampler == oracle.REJ:
+        kw.update(weight=g.weight, pmax=tables if tables is not None else oracle.rej_build(g.row_ptr, g.weight))
     if algo == oracle.METAPATH:
         kw.update(label=g.label)
     return oracle.walk(g.row_ptr, g.col, params, np.asarray(sources, np.int32), qid_base=qid_base,
@@ -76,13 +79,20 @@ def test_worked_first_moves(oracle_lib):
             s = oracle.ITS if kind == "its" else oracle.ALIAS
             r = _walk(g, oracle.DEEPWALK, s, 1, [0], seed=0)
             assert r.paths[0, 1] == int(kv["i"]) + 1, (kind, kv)
+        elif kind == "rej":
+            w = [int(x) for x in kv["weights"].split(",")]
+            g = star(len(w), weights=w)
+            r = _walk(g, oracle.DEEPWALK, oracle.REJ, 1, [0], seed=0)
+            assert (r.counters["rej_trials"] == 1) == bool(int(kv["hit"])), kv
+            if "i" in kv:
+                assert r.paths[0, 1] == int(kv["i"]) + 1, kv
         elif kind == "ppr":
             g = star(10)
             r = _walk(g, oracle.PPR, oracle.NAIVE, 5, [0], seed=0, stop=int(kv["stop_q32"]))
             stopped_first = r.lengths[0] == 1 and r.status[0] == oracle.ST_STOPPED
             assert stopped_first == bool(int(kv["stopped"]))
         n += 1
-    assert n == 9
+    assert n == 12
 
 
 # --------------------------------------------------------------------------- invariants
@@ -108,7 +118,7 @@ def _check_paths_are_edges(g, r, sources):
     return True
 
 
-@pytest.mark.parametrize("sampler", [oracle.NAIVE, oracle.ALIAS, oracle.ITS])
+@pytest.mark.parametrize("sampler", [oracle.NAIVE, oracle.ALIAS, oracle.ITS, oracle.REJ])
 def test_deepwalk_invariants(rmat_graphs, sampler):
     g, _ = rmat_graphs
     src = np.arange(g.n, dtype=np.int32)
@@ -123,7 +133,7 @@ def test_deepwalk_invariants(rmat_graphs, sampler):
     assert r.counters["moves"] == int(r.lengths.sum())
 
 
-@pytest.mark.parametrize("sampler", [oracle.NAIVE, oracle.ALIAS, oracle.ITS])
+@pytest.mark.parametrize("sampler", [oracle.NAIVE, oracle.ALIAS, oracle.ITS, oracle.REJ])
 def test_ppr_invariants(rmat_graphs, sampler):
     _, g = rmat_graphs
     src = synth.sources(5000, g.n, 77)
@@ -216,6 +226,31 @@ def test_identity_alias_uniform_is_naive(rmat_graphs):
     assert np.array_equal(a.paths, b.paths)
 
 
+@pytest.mark.parametrize("algo", [oracle.DEEPWALK, oracle.PPR])
+def test_identity_rej_uniform_is_naive(rmat_graphs, algo):
+    """Equal weights: every first dart hits, so REJ takes NAIVE's edge and stop coin."""
+    _, g = rmat_graphs
+    gu = synth.CSRGraph(g.n, g.row_ptr, g.col, weight=np.full(g.m, 17, np.uint32))
+    src = synth.sources(3000, g.n, 21)
+    stop = oracle.stop_q32(0.2) if algo == oracle.PPR else 0
+    a = _walk(gu, algo, oracle.REJ, 50, src, stop=stop)
+    b = _walk(gu, algo, oracle.NAIVE, 50, src, stop=stop)
+    assert np.array_equal(a.paths, b.paths) and np.array_equal(a.lengths, b.lengths)
+    assert np.array_equal(a.status, b.status)
+    assert a.counters["rej_trials"] == a.counters["moves"]
+
+
+def test_rej_zero_weights(oracle_lib):
+    """A zero-weight edge is never taken; a row whose weights are all zero is a dead end."""
+    # 0 -> {1, 2, 3} with weights 0, 5, 0; 2 -> {0, 4} with weights 0, 0; 1 and 3 -> 0
+    edges = [(0, 1), (0, 2), (0, 3), (1, 0), (2, 0), (2, 4), (3, 0)]
+    g = synth.from_edges(5, edges, [0, 5, 0, 1, 0, 0, 1])
+    r = _walk(g, oracle.DEEPWALK, oracle.REJ, 4, np.zeros(2000, np.int32), seed=8)
+    assert (r.paths[:, 1] == 2).all()
+    assert (r.lengths == 1).all() and (r.status == oracle.ST_DEAD_END).all()
+    assert list(oracle.rej_build(g.row_ptr, g.weight)) == [5, 1, 0, 1, 0]
+
+
 def test_identity_metapath_all_match_is_naive(rmat_graphs):
     g, _ = rmat_graphs
     gl = synth.CSRGraph(g.n, g.row_ptr, g.col, label=np.full(g.m, 2, np.uint8))
@@ -225,7 +260,7 @@ def test_identity_metapath_all_match_is_naive(rmat_graphs):
     assert np.array_equal(a.paths, b.paths) and np.array_equal(a.lengths, b.lengths)
 
 
-@pytest.mark.parametrize("sampler", [oracle.NAIVE, oracle.ALIAS, oracle.ITS])
+@pytest.mark.parametrize("sampler", [oracle.NAIVE, oracle.ALIAS, oracle.ITS, oracle.REJ])
 def test_identity_ppr_without_stop_is_fixed_length(rmat_graphs, sampler):
     _, g = rmat_graphs
     src = synth.sources(2000, g.n, 11)
@@ -234,7 +269,7 @@ def test_identity_ppr_without_stop_is_fixed_length(rmat_graphs, sampler):
     assert np.array_equal(a.paths, b.paths) and np.array_equal(a.status, b.status)
 
 
-@pytest.mark.parametrize("sampler", [oracle.ALIAS, oracle.ITS])
+@pytest.mark.parametrize("sampler", [oracle.ALIAS, oracle.ITS, oracle.REJ])
 def test_identity_weight_scaling(rmat_graphs, sampler):
     g, _ = rmat_graphs
     g2 = synth.CSRGraph(g.n, g.row_ptr, g.col, weight=g.weight * np.uint32(1000003))
@@ -249,7 +284,7 @@ N_STAT = 200_000
 
 
 @pytest.mark.parametrize("name", ["tri_tail", "k4", "star6", "path6"])
-@pytest.mark.parametrize("sampler", [oracle.NAIVE, oracle.ALIAS, oracle.ITS])
+@pytest.mark.parametrize("sampler", [oracle.NAIVE, oracle.ALIAS, oracle.ITS, oracle.REJ])
 def test_first_step_law(oracle_lib, name, sampler):
     g = zoo()[name]
     P = transition_matrix(g, use_weights=sampler != oracle.NAIVE)
@@ -345,7 +380,7 @@ def _ppr_end_law(g, s, alpha, L, use_weights):
     return end
 
 
-@pytest.mark.parametrize("sampler", [oracle.NAIVE, oracle.ALIAS, oracle.ITS])
+@pytest.mark.parametrize("sampler", [oracle.NAIVE, oracle.ALIAS, oracle.ITS, oracle.REJ])
 def test_ppr_end_distribution_power_iteration(oracle_lib, sampler):
     # directed weighted graph with one dangling vertex (5)
     edges = [(0, 1), (0, 2), (1, 2), (1, 3), (2, 0), (2, 4), (3, 0), (3, 5), (4, 1), (4, 3)]
@@ -391,6 +426,30 @@ def test_orej_expected_trials(oracle_lib, pq):
     trials_step1 = (r.counters["orej_trials"] - N) / N
     se = math.sqrt((1 - 1 / E) * E * E / N)
     assert abs(trials_step1 - E) < 5 * se, (trials_step1, E)
+
+
+@pytest.mark.parametrize("weights", [(1, 1, 2, 3, 5, 200), (4, 4, 4, 3), (1, 255), (255, 1, 1, 1, 1, 1, 1, 1)])
+def test_rej_expected_trials(oracle_lib, weights):
+    """Mean REJ darts per move = d * p* / sum w (Sampling Methods, REJ)."""
+    g = star(len(weights), weights=weights)
+    N = 100_000
+    r = _walk(g, oracle.DEEPWALK, oracle.REJ, 1, np.zeros(N, np.int32), seed=31)
+    d, pstar, W = len(weights), max(weights), sum(weights)
+    E = d * pstar / W
+    mean = r.counters["rej_trials"] / N
+    se = math.sqrt(max((1 - 1 / E) * E * E, 1e-12) / N)
+    assert abs(mean - E) < 5 * se + 1e-12, (mean, E)
+    counts = np.bincount(r.paths[:, 1], minlength=g.n)
+    assert _chi2(counts, [0] + list(weights)) > P_MIN
+
+
+def test_rej_table_worked_example(oracle_lib):
+    """p*_v by hand for the zoo graphs: the heaviest edge of each row."""
+    z = zoo()
+    # tri_tail: 0:{1:3, 2:4}  1:{0:3, 2:1, 3:9}  2:{0:4, 1:1, 3:1}  3:{1:9, 2:1, 4:5}  4:{3:5}
+    assert list(oracle.rej_build(z["tri_tail"].row_ptr, z["tri_tail"].weight)) == [4, 9, 4, 9, 5]
+    # star6: the hub's heaviest edge is 200; each leaf has its one edge
+    assert list(oracle.rej_build(z["star6"].row_ptr, z["star6"].weight)) == [200, 1, 1, 2, 3, 5, 200]
 
 
 @pytest.mark.parametrize("d", [1, 2, 3, 7, 8, 1000])
