@@ -129,10 +129,10 @@ def main():
     # Preprocessing: per-vertex tables, timed separately from the walk.
     tables, pre_ms = {}, {}
     variant_samplers = {"metapath": ("its+index", "its"), "node2vec": ("orej+eidx", "orej+adj", "orej"),
-                        "deepwalk": ("naive+adj", "naive")}.get(wl.algo, wl.samplers)
+                        "deepwalk": ("naive+adj", "naive"), "ppr": ("alias", "its", "rej")}.get(wl.algo, wl.samplers)
     need = {sampler} if (args.no_variants or args.profile_pass) else set(variant_samplers) | {sampler}
     for s in sorted(need):
-        if (s in ("alias", "its") and wl.algo in ("ppr", "deepwalk", "mixed")) or "+" in s:
+        if (s in ("alias", "its", "rej") and wl.algo in ("ppr", "deepwalk", "mixed")) or "+" in s:
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(stream)
             if s == "its+index":
@@ -261,13 +261,41 @@ def main():
             for mname in ("persistent", "per_step"):
                 if s == sampler and mname == args.mode:
                     continue
-                if ((wl.algo in ("ppr", "deepwalk") and s in ("alias", "its")) or "+" in s) and s not in tables:
+                if ((wl.algo in ("ppr", "deepwalk") and s in ("alias", "its", "rej")) or "+" in s) and s not in tables:
                     continue
                 r = run(s, trw.MODES[mname], 1, 3)
                 v = r["moves"] * 3 / r["wall_s"]
                 variants[f"{s}/{mname}"] = {"steps_per_s": round(v, 1), "ms_per_batch": round(1000 * r["wall_s"] / 3, 3),
                                             "moves": r["moves"]}
                 log(f"variant {s}/{mname}: {v:.4g} steps/s")
+
+    # The PPR estimate on the batch's outputs: each query's end vertex counted
+    # (Random Walk based Algorithms, PPR), then the 100 highest counts.
+    ppr_est = None
+    if wl.algo == "ppr" and not args.no_variants:
+        p = params(sampler)
+        bufs = trw.WalkBuffers(G, p, nq, mode)
+        trw.walk(G, tables.get(sampler), p, d_src, mode=mode, bufs=bufs)
+        counts = torch.zeros((1, g.n), dtype=torch.int32, device=dev)
+        skipped = torch.zeros(1, dtype=torch.int64, device=dev)
+        t_ec, t_tk = [], []
+        for _ in range(5):
+            counts.zero_()
+            a, b, c = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+            a.record(stream)
+            trw.ppr_end_counts(G, bufs.paths, bufs.lengths, bufs.status, counts=counts, skipped=skipped)
+            b.record(stream)
+            ids, vals = trw.topk(counts[0], 100)
+            c.record(stream)
+            torch.cuda.synchronize()
+            t_ec.append(a.elapsed_time(b))
+            t_tk.append(b.elapsed_time(c))
+        ppr_est = {"end_counts_ms": round(float(np.median(t_ec)), 4), "topk_ms": round(float(np.median(t_tk)), 4),
+                   "k": 100, "queries": nq, "vertices": g.n,
+                   "distinct_end_vertices": int((counts[0] != 0).sum().item()),
+                   "top_count": int(vals[0].item()), "walk_ms": round(avg_launch_ms, 4)}
+        log(f"ppr estimate: end counts {ppr_est['end_counts_ms']} ms, top-100 {ppr_est['topk_ms']} ms")
+        del bufs, counts
 
     # The same walk written as a walk program (the step-centric programming
     # model, compiled at run time): what the generic framework costs.
@@ -347,6 +375,7 @@ def main():
         "preprocess_ms": {k: round(v, 3) for k, v in pre_ms.items()},
         "autotuned": autotuned,
         "variants": variants,
+        "ppr_estimate": ppr_est,
         "gather_ceiling": gather,
     }
     print(json.dumps(out), flush=True)
@@ -533,6 +562,8 @@ def cpu_baseline(g, wl, sampler, src_np, kw, target_s):
         tab = dict(thr=t, alias=a)
     elif algo in (oracle.DEEPWALK, oracle.PPR) and smp == oracle.ITS:
         tab = dict(prefix=oracle.its_build(g.row_ptr, g.weight))
+    elif algo in (oracle.DEEPWALK, oracle.PPR) and smp == oracle.REJ:
+        tab = dict(weight=g.weight, pmax=oracle.rej_build(g.row_ptr, g.weight))
     if algo == oracle.METAPATH:
         tab = dict(label=g.label)
     log(f"cpu baseline: oracle tables {time.time() - t0:.1f}s")

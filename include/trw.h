@@ -113,12 +113,14 @@ typedef enum {
     TRW_S_NAIVE = 0,   /* uniform index; no table */
     TRW_S_ALIAS = 1,   /* Walker alias table, integer Vose construction */
     TRW_S_ITS = 2,     /* inverse transform: inclusive uint64 prefix + binary search */
-    TRW_S_OREJ = 3     /* rejection with a user bound p*; no table (Node2Vec) */
+    TRW_S_OREJ = 3,    /* rejection with a user bound p*; no table (Node2Vec) */
+    TRW_S_REJ = 4      /* rejection with p*_v = the row's largest weight (per-vertex table) */
 } trw_sampler;
 
 typedef struct trw_table_s *trw_table;
 
-/* Bytes of device memory the table for `sampler` needs: ALIAS 32*m, ITS 8*m. */
+/* Bytes of device memory the table for `sampler` needs: ALIAS 32*m, ITS 8*m,
+ * REJ 32*m rounded up to 256, plus 4*n. */
 trw_status trw_table_bytes(trw_graph g, uint32_t sampler, size_t *bytes);
 
 /*
@@ -137,6 +139,14 @@ trw_status trw_table_bytes(trw_graph g, uint32_t sampler, size_t *bytes);
  *          A row whose weights sum to 0 holds {0xFFFFFFFF, -1, -1, 0, 0, 0,
  *          0, 0}: a walk that reaches it ends as a dead end.
  *   ITS:   uint64 prefix[e] = sum of w over row v up to and including e.
+ *   REJ:   (Sampling Methods, rejection sampling: initialization finds
+ *          p*_v = max weight of v's row; generation throws darts (x, y) with x
+ *          uniform in [0, d_v), y uniform in [0, p*_v) until y < w_x.)
+ *          8 x uint32 per edge slot {w[e], col[e], row_off(col[e]), deg(col[e]),
+ *          p*(col[e]), 0, 0, 0}, then, at byte 32*m rounded up to 256,
+ *          uint32 p*[n] (0 for a vertex without edges, or whose weights are
+ *          all 0: a walk that reaches it ends as a dead end).  A dart is one
+ *          32-byte read that also carries everything the next move needs.
  * Errors: TRW_E_INVALID if the graph has no weights, bytes is too small or the
  * buffer is misaligned; TRW_E_UNSUPPORTED for NAIVE / OREJ (no table).
  */
@@ -210,7 +220,11 @@ typedef enum {
 
 typedef struct {
     uint32_t algo;             /* trw_algo */
-    uint32_t sampler;          /* DEEPWALK/PPR: NAIVE, ALIAS or ITS; NODE2VEC: OREJ; METAPATH: ITS */
+    uint32_t sampler;          /* DEEPWALK/PPR: NAIVE, ALIAS, ITS or REJ; NODE2VEC: OREJ;
+                                  METAPATH: ITS.  REJ darts of move k are Philox blocks
+                                  (k, t = 0, 1, ...): x = high half of r0 * d, hit iff
+                                  r1 * p*_v < w_x * 2^32; PPR's stop coin is r2 of the
+                                  block of the hitting dart */
     uint32_t max_len;          /* moves per query, 1..65535; a path holds max_len+1 vertices */
     uint32_t stop_q32;         /* PPR: stop after a move iff r2 < stop_q32 (0.2 -> 858993459) */
     uint32_t n2v_thr_q16[3];   /* NODE2VEC: accept a dart iff (r1 >> 16) < thr[c], c = 0 when
@@ -248,7 +262,7 @@ trw_status trw_default_tuning(trw_graph g, const trw_walk_params *p, uint32_t mo
 
 /*
  * Run nq queries, query i starting at d_sources[i] with id qid_base + i.
- *   table       ALIAS/ITS table built for p->sampler; for NAIVE and OREJ NULL,
+ *   table       ALIAS/ITS/REJ table built for p->sampler; for NAIVE and OREJ NULL,
  *               an adjacency index or an edge index; for METAPATH NULL (scan
  *               rows) or a label index
  *   d_paths     int32, row i at d_paths + i*path_stride, path_stride >= max_len+1:
@@ -288,6 +302,45 @@ trw_status trw_autotune(trw_graph g, trw_table table, const trw_walk_params *p,
                         uint64_t path_stride, uint32_t *d_lengths, uint8_t *d_status,
                         uint32_t mode, uint32_t budget, void *d_ws, size_t ws_bytes,
                         trw_stream_t stream, trw_tuning *out, float *best_ms);
+
+/* ------------------------------------------------------------------------ */
+/* PPR estimate (Random Walk based Algorithms, PPR): the score of vertex v   */
+/* for a source is the share of the source's queries whose walk ends at v;   */
+/* the highest-scoring vertices are the answer.                              */
+/* ------------------------------------------------------------------------ */
+/*
+ * Add the end vertices of a batch's walks to per-group counts.  Query i
+ * belongs to group i / group (group 0: every query to group 0) and adds one
+ * to d_counts[(i / group) * n + paths[i][lengths[i]]].  A walk that ended at
+ * a dead end counts its last vertex (a dangling source counts itself).
+ * Skipped, and added to *d_skipped (a device uint64, nullable): queries with
+ * status BAD_SOURCE, lengths[i] >= path_stride, or an end outside [0, n).
+ *   d_paths, path_stride, d_lengths, d_status   as trw_walk wrote them
+ *   d_counts    uint32, counts_len >= groups * n entries, groups = ceil(nq /
+ *               group) (1 when group is 0); added to, not cleared
+ * Asynchronous on `stream` (device atomics; the counts do not depend on
+ * their order).  Errors: TRW_E_INVALID for a NULL pointer with nq > 0,
+ * counts_len too small, path_stride 0 or nq >= 2^32.
+ */
+trw_status trw_ppr_end_counts(trw_graph g, const int32_t *d_paths, uint64_t path_stride,
+                              const uint32_t *d_lengths, const uint8_t *d_status, uint64_t nq,
+                              uint64_t group, uint32_t *d_counts, uint64_t counts_len,
+                              unsigned long long *d_skipped, trw_stream_t stream);
+
+/* Workspace bytes of trw_topk: 1280 + 8*k.  k <= min(n, 4096). */
+trw_status trw_topk_workspace_bytes(uint64_t n, uint32_t k, size_t *bytes);
+
+/*
+ * The k largest of d_counts[0..n) (n < 2^31), largest first; equal counts
+ * are ordered by the smaller index.  Writes d_ids[0..k) (int32) and
+ * d_vals[0..k) (the counts).  The result is unique, so it equals a sort of
+ * all n (count, index) pairs cut at k.  d_ws: >= trw_topk_workspace_bytes,
+ * 256-byte aligned.  Asynchronous on `stream`, no host synchronisation.
+ * Errors: TRW_E_INVALID for k > n, k > 4096, n >= 2^31, NULL pointers with
+ * k > 0, or a short or misaligned workspace.
+ */
+trw_status trw_topk(const uint32_t *d_counts, uint64_t n, uint32_t k, int32_t *d_ids, uint32_t *d_vals,
+                    void *d_ws, size_t ws_bytes, trw_stream_t stream);
 
 /* ------------------------------------------------------------------------ */
 /* Walk programs (Step-centric Programming: the user picks the sampling      */

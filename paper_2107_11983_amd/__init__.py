@@ -16,15 +16,16 @@ from . import _abi, programs  # noqa: F401  (programs: walk program sources)
 from ._abi import (TRW_E_CANCELLED, TRW_E_NOMEM_BUDGET, TRW_E_TIMEOUT, TRW_REQ_HOST, trw_completion,
                    trw_request, trw_server_cfg, trw_server_stats)
 from ._abi import (TRW_A_DEEPWALK, TRW_A_METAPATH, TRW_A_NODE2VEC, TRW_A_PPR, TRW_G_SYMMETRIC,
-                   TRW_M_PER_STEP, TRW_M_PERSISTENT, TRW_S_ALIAS, TRW_S_ITS, TRW_S_NAIVE, TRW_S_OREJ,
+                   TRW_M_PER_STEP, TRW_M_PERSISTENT, TRW_S_ALIAS, TRW_S_ITS, TRW_S_NAIVE, TRW_S_OREJ, TRW_S_REJ,
                    TRW_ST_BAD_SOURCE, TRW_ST_DEAD_END, TRW_ST_LENGTH, TRW_ST_STOPPED, TrwError, check,
                    trw_tuning, trw_walk_params)
 
 __all__ = ["Graph", "Table", "walk", "make_params", "workspace_bytes", "default_tuning", "autotune",
-           "TrwError", "ALGOS", "SAMPLERS", "Program", "check_program", "programs", "Server"]
+           "TrwError", "ALGOS", "SAMPLERS", "Program", "check_program", "programs", "Server", "ppr_end_counts",
+           "topk"]
 
 ALGOS = {"deepwalk": TRW_A_DEEPWALK, "ppr": TRW_A_PPR, "node2vec": TRW_A_NODE2VEC, "metapath": TRW_A_METAPATH}
-SAMPLERS = {"naive": TRW_S_NAIVE, "alias": TRW_S_ALIAS, "its": TRW_S_ITS, "orej": TRW_S_OREJ}
+SAMPLERS = {"naive": TRW_S_NAIVE, "alias": TRW_S_ALIAS, "its": TRW_S_ITS, "orej": TRW_S_OREJ, "rej": TRW_S_REJ}
 MODES = {"per_step": TRW_M_PER_STEP, "persistent": TRW_M_PERSISTENT}
 
 
@@ -143,7 +144,7 @@ class Graph:
 
 
 class Table:
-    """Per-vertex ALIAS or ITS table (built on the device, asynchronously)."""
+    """Per-vertex ALIAS, ITS or REJ table, or an index (built on the device, asynchronously)."""
 
     def __init__(self, graph: Graph, sampler, stream=None, n_labels: int = 0):
         self.graph = graph
@@ -248,6 +249,41 @@ def autotune(graph: Graph, table: Optional[Table], p: trw_walk_params, sources: 
                             _dptr(bufs.status), mode, budget, _dptr(bufs.ws), bufs.ws.numel(),
                             _stream_ptr(stream), ctypes.byref(out), ctypes.byref(ms)))
     return out, float(ms.value)
+
+
+def ppr_end_counts(graph: Graph, paths: torch.Tensor, lengths: torch.Tensor, status: torch.Tensor, group: int = 0,
+                   counts: Optional[torch.Tensor] = None, skipped: Optional[torch.Tensor] = None, stream=None):
+    """PPR estimate: add each query's end vertex to counts[query // group] (group 0: one row).
+
+    Returns counts (uint32 values in an int32 tensor [groups, n], added to when given) and
+    skipped (a one-element int64 tensor: bad sources and paths whose end is not a vertex).
+    """
+    nq = int(lengths.numel())
+    stride = int(paths.shape[1]) if paths.dim() == 2 else int(paths.stride(0))
+    groups = 1 if group <= 0 else max(1, -(-nq // group))
+    if counts is None:
+        counts = torch.zeros((groups, graph.n), dtype=torch.int32, device=graph.device)
+    if skipped is None:
+        skipped = torch.zeros(1, dtype=torch.int64, device=graph.device)
+    assert counts.dtype == torch.int32 and counts.is_contiguous() and skipped.dtype == torch.int64
+    assert paths.is_contiguous() or paths.stride(1) == 1
+    check(_abi.trw_ppr_end_counts(graph.handle, _dptr(paths), paths.stride(0), _dptr(lengths), _dptr(status), nq,
+                                  max(group, 0), _dptr(counts), counts.numel(), _dptr(skipped), _stream_ptr(stream)))
+    return counts, skipped
+
+
+def topk(counts: torch.Tensor, k: int, stream=None):
+    """The k largest counts of a 1-D uint32 (int32-held) tensor: (ids int32[k], counts int32[k]),
+    largest first, equal counts by the smaller index."""
+    assert counts.dim() == 1 and counts.is_contiguous() and counts.dtype == torch.int32
+    n = int(counts.numel())
+    nbytes = ctypes.c_size_t(0)
+    check(_abi.trw_topk_workspace_bytes(n, k, ctypes.byref(nbytes)))
+    ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device=counts.device)
+    ids = torch.empty(max(k, 1), dtype=torch.int32, device=counts.device)
+    vals = torch.empty(max(k, 1), dtype=torch.int32, device=counts.device)
+    check(_abi.trw_topk(_dptr(counts), n, k, _dptr(ids), _dptr(vals), _dptr(ws), ws.numel(), _stream_ptr(stream)))
+    return ids[:k], vals[:k]
 
 
 class Server:

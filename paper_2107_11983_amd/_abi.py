@@ -17,7 +17,7 @@ TRW_E_NOMEM_BUDGET, TRW_E_BUSY, TRW_E_TIMEOUT, TRW_E_CANCELLED = 4, 5, 6, 7
 STATUS_NAMES = {0: "TRW_OK", 1: "TRW_E_INVALID", 2: "TRW_E_UNSUPPORTED", 3: "TRW_E_DEVICE",
                 4: "TRW_E_NOMEM_BUDGET", 5: "TRW_E_BUSY", 6: "TRW_E_TIMEOUT", 7: "TRW_E_CANCELLED"}
 TRW_G_SYMMETRIC = 1
-TRW_S_NAIVE, TRW_S_ALIAS, TRW_S_ITS, TRW_S_OREJ = 0, 1, 2, 3
+TRW_S_NAIVE, TRW_S_ALIAS, TRW_S_ITS, TRW_S_OREJ, TRW_S_REJ = 0, 1, 2, 3, 4
 TRW_A_DEEPWALK, TRW_A_PPR, TRW_A_NODE2VEC, TRW_A_METAPATH = 0, 1, 2, 3
 TRW_ST_LENGTH, TRW_ST_STOPPED, TRW_ST_DEAD_END, TRW_ST_BAD_SOURCE = 1, 2, 3, 4
 TRW_M_PER_STEP, TRW_M_PERSISTENT = 0, 1
@@ -128,6 +128,9 @@ _SIGS = {
     "trw_program_walk": (_st, [_P, _P, _P, ctypes.POINTER(trw_program_params), _P, _u64, _u64, _P, _u64, _P, _P,
                                _P, _sz, _P]),
     "trw_program_destroy": (_st, [_P]),
+    "trw_ppr_end_counts": (_st, [_P, _P, _u64, _P, _P, _u64, _u64, _P, _u64, _P, _P]),
+    "trw_topk_workspace_bytes": (_st, [_u64, _u32, ctypes.POINTER(_sz)]),
+    "trw_topk": (_st, [_P, _u64, _u32, _P, _P, _P, _sz, _P]),
     # measurement probe (include/trw_probe.h)
     "trw_probe_fill": (ctypes.c_int, [_P, _u64, _u32, _P]),
     "trw_probe_gather": (ctypes.c_int, [_P, _u64, _u32, _u32, _u32, ctypes.c_int, _u32, _u32, _P, _P]),
@@ -183,6 +186,9 @@ trw_program_create = lib.trw_program_create
 trw_program_kind = lib.trw_program_kind
 trw_program_walk = lib.trw_program_walk
 trw_program_destroy = lib.trw_program_destroy
+trw_ppr_end_counts = lib.trw_ppr_end_counts
+trw_topk_workspace_bytes = lib.trw_topk_workspace_bytes
+trw_topk = lib.trw_topk
 trw_edge_index_bytes = lib.trw_edge_index_bytes
 trw_edge_index_build = lib.trw_edge_index_build
 trw_probe_fill = lib.trw_probe_fill

@@ -18,7 +18,7 @@ struct trw_graph_s {
 
 struct trw_table_s {
     trw_graph graph;
-    uint32_t sampler;   // TRW_S_ALIAS / TRW_S_ITS, or kLabelIndexKind
+    uint32_t sampler;   // TRW_S_ALIAS / TRW_S_ITS / TRW_S_REJ, or an index kind
     void *buf;
     uint32_t nlab;      // label index: number of labels L
 };
@@ -79,7 +79,7 @@ bool pair_supported(uint32_t algo, uint32_t sampler) {
     switch (algo) {
         case TRW_A_DEEPWALK:
         case TRW_A_PPR:
-            return sampler == TRW_S_NAIVE || sampler == TRW_S_ALIAS || sampler == TRW_S_ITS;
+            return sampler == TRW_S_NAIVE || sampler == TRW_S_ALIAS || sampler == TRW_S_ITS || sampler == TRW_S_REJ;
         case TRW_A_NODE2VEC:
             return sampler == TRW_S_OREJ;
         case TRW_A_METAPATH:
@@ -208,6 +208,7 @@ trw_status trw_table_bytes(trw_graph g, uint32_t sampler, size_t *bytes) {
     switch (sampler) {
         case TRW_S_ALIAS: *bytes = kAliasEntryBytes * (size_t)g->dev.m; return TRW_OK;
         case TRW_S_ITS: *bytes = sizeof(uint64_t) * (size_t)g->dev.m; return TRW_OK;
+        case TRW_S_REJ: *bytes = rej_records_bytes(g->dev.m) + sizeof(uint32_t) * (size_t)g->dev.n; return TRW_OK;
         case TRW_S_NAIVE:
         case TRW_S_OREJ: *bytes = 0; return fail(TRW_E_UNSUPPORTED, "sampler has no table");
         default: return fail(TRW_E_UNSUPPORTED, "unknown sampler");
@@ -222,11 +223,14 @@ trw_status trw_table_build(trw_graph g, uint32_t sampler, void *d_buf, size_t by
     if (st != TRW_OK) return st;
     if (!g->dev.weight) return fail(TRW_E_INVALID, "table needs edge weights");
     if (bytes < need) return fail(TRW_E_INVALID, "table buffer too small");
-    if (g->dev.m > 0 && (!d_buf || (reinterpret_cast<uintptr_t>(d_buf) & 31)))
+    if ((g->dev.m > 0 || sampler == TRW_S_REJ) && (!d_buf || (reinterpret_cast<uintptr_t>(d_buf) & 31)))
         return fail(TRW_E_INVALID, "table buffer NULL or not 32-byte aligned");
     auto s = static_cast<hipStream_t>(stream);
     hipError_t e = hipSuccess;
-    if (g->dev.m > 0) {
+    if (sampler == TRW_S_REJ) {
+        e = launch_rej_build(g->dev, static_cast<uint4 *>(d_buf),
+                             reinterpret_cast<uint32_t *>(static_cast<char *>(d_buf) + rej_records_bytes(g->dev.m)), s);
+    } else if (g->dev.m > 0) {
         e = sampler == TRW_S_ALIAS ? launch_alias_build(g->dev, static_cast<uint4 *>(d_buf), s)
                                    : launch_its_build(g->dev, static_cast<uint64_t *>(d_buf), s);
     }
@@ -349,9 +353,9 @@ trw_status trw_walk(trw_graph g, trw_table table, const trw_walk_params *p, cons
     if (mode > TRW_M_PERSISTENT) return fail(TRW_E_INVALID, "unknown mode");
     if (nq >= (uint64_t(1) << 32)) return fail(TRW_E_INVALID, "nq must be < 2^32");
     const bool needs_table = (p->algo == TRW_A_DEEPWALK || p->algo == TRW_A_PPR) &&
-                             (p->sampler == TRW_S_ALIAS || p->sampler == TRW_S_ITS);
+                             (p->sampler == TRW_S_ALIAS || p->sampler == TRW_S_ITS || p->sampler == TRW_S_REJ);
     if (needs_table) {
-        if (!table) return fail(TRW_E_INVALID, "ALIAS / ITS walks need a table");
+        if (!table) return fail(TRW_E_INVALID, "ALIAS / ITS / REJ walks need a table");
         if (table->graph != g) return fail(TRW_E_INVALID, "table was built for another graph");
         if (table->sampler != p->sampler) return fail(TRW_E_INVALID, "table was built for another sampler");
     }
@@ -401,8 +405,15 @@ trw_status trw_walk(trw_graph g, trw_table table, const trw_walk_params *p, cons
         t.eset_mask = eset_slots(g->dev.m) - 1;
     }
     if (needs_table) {
-        if (p->sampler == TRW_S_ALIAS) t.alias = static_cast<const uint4 *>(table->buf);
-        else t.prefix = static_cast<const uint64_t *>(table->buf);
+        if (p->sampler == TRW_S_ALIAS) {
+            t.alias = static_cast<const uint4 *>(table->buf);
+        } else if (p->sampler == TRW_S_REJ) {
+            t.rej = static_cast<const uint4 *>(table->buf);
+            t.pmax = reinterpret_cast<const uint32_t *>(static_cast<const char *>(table->buf) +
+                                                        rej_records_bytes(g->dev.m));
+        } else {
+            t.prefix = static_cast<const uint64_t *>(table->buf);
+        }
     }
     if (label_index) {
         t.loff = static_cast<const int32_t *>(table->buf);

@@ -20,6 +20,9 @@
 // k_alias_build_big.
 //
 // ITS: inclusive running sum of the weights per row in uint64.
+//
+// REJ: the largest weight per row, and per edge slot a record with the
+// destination's row and bound (k_rej_records).
 #include <algorithm>
 
 #include "trw_device.hpp"
@@ -418,6 +421,47 @@ __global__ void k_adjacency_build(GraphDev g, uint4 *__restrict__ out) {
     out[e] = make_uint4((uint32_t)v, r.x, r.y, 0u);
 }
 
+// REJ (rejection sampling): the initialization finds p*_v, the largest
+// weight of v's row, kept per vertex after the slot records.  Every slot's
+// record then carries its weight and the destination's id, row range and
+// p*, so a dart is one 32-byte read and a hit needs no further lookup:
+//   [0] {w, dst, row_off(dst), deg(dst)}   [1] {p*(dst), 0, 0, 0}
+__global__ void k_rej_pmax(GraphDev g, uint32_t *__restrict__ pmax) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= g.n) return;
+    const int64_t lo = g.row_ptr[v], hi = g.row_ptr[v + 1];
+    if (hi - lo > kBigRow) return;
+    uint32_t mx = 0;
+    for (int64_t e = lo; e < hi; ++e) mx = max(mx, g.weight[e]);
+    pmax[v] = mx;
+}
+
+__global__ void __launch_bounds__(kBuildBlock) k_rej_pmax_big(GraphDev g, uint32_t *__restrict__ pmax) {
+    __shared__ uint32_t sh[kBuildBlock / 64];
+    for_each_big_row(g, [&](int64_t v, int64_t off, int64_t d) {
+        uint32_t mx = 0;
+        for (int64_t e = off + threadIdx.x; e < off + d; e += kBuildBlock) mx = max(mx, g.weight[e]);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) mx = max(mx, (uint32_t)__shfl_xor(mx, o));
+        if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = mx;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t m = 0;
+            for (uint32_t i = 0; i < kBuildBlock / 64; ++i) m = max(m, sh[i]);
+            pmax[v] = m;
+        }
+    });
+}
+
+__global__ void k_rej_records(GraphDev g, const uint32_t *__restrict__ pmax, uint4 *__restrict__ out) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= g.m) return;
+    const int32_t v = g.col[e];
+    const uint2 r = row_of(g, v);
+    out[2 * e] = make_uint4(g.weight[e], (uint32_t)v, r.x, r.y);
+    out[2 * e + 1] = make_uint4(pmax[v], 0u, 0u, 0u);
+}
+
 // Edge hash set (the edge index's membership test for Node2Vec): every edge
 // (u, v) inserted once as u << 32 | v by compare-and-swap with linear
 // probing; a thread per row up to kBigRow slots, a workgroup per longer row.
@@ -505,6 +549,17 @@ hipError_t launch_label_index_build(const GraphDev &g, uint32_t nlab, int32_t *l
 hipError_t launch_adjacency_build(const GraphDev &g, uint4 *out, hipStream_t s) {
     const int64_t blocks = ((int64_t)g.m + kBuildThreads - 1) / kBuildThreads;
     hipLaunchKernelGGL(k_adjacency_build, dim3((uint32_t)blocks), dim3(kBuildThreads), 0, s, g, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_rej_build(const GraphDev &g, uint4 *records, uint32_t *pmax, hipStream_t s) {
+    const int blocks = (g.n + kBuildThreads - 1) / kBuildThreads;
+    hipLaunchKernelGGL(k_rej_pmax, dim3(blocks), dim3(kBuildThreads), 0, s, g, pmax);
+    hipLaunchKernelGGL(k_rej_pmax_big, dim3(big_row_blocks(g)), dim3(kBuildBlock), 0, s, g, pmax);
+    if (g.m > 0) {
+        const int64_t eblocks = ((int64_t)g.m + kBuildThreads - 1) / kBuildThreads;
+        hipLaunchKernelGGL(k_rej_records, dim3((uint32_t)eblocks), dim3(kBuildThreads), 0, s, g, pmax, records);
+    }
     return hipGetLastError();
 }
 

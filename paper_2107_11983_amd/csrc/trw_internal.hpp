@@ -42,6 +42,8 @@ struct TableDev {
     const uint4 *adj;         // adjacency index: {dst, row_off(dst), deg(dst), 0} per edge slot
     const unsigned long long *eset;   // edge index: hash set of the edges (u, v) as u << 32 | v
     unsigned long long eset_mask;     // its slot count - 1 (a power of two)
+    const uint4 *rej;         // REJ: 2 x uint4 per edge slot {w, dst, row_off(dst), deg(dst)}, {p*(dst), 0, 0, 0}
+    const uint32_t *pmax;     // REJ: p*_v per vertex
 };
 
 // Edge hash set slots: at most half full (kEsetEmpty and eset_hash are in
@@ -77,14 +79,17 @@ enum : uint32_t { ALG_DEEPWALK = 0, ALG_PPR = 1, ALG_NODE2VEC = 2, ALG_METAPATH 
 // Internal sampler codes: the public four, plus the same samplers reading an
 // index (identical results, fewer dependent reads).
 enum : uint32_t {
-    SMP_NAIVE = 0, SMP_ALIAS = 1, SMP_ITS = 2, SMP_OREJ = 3,
-    SMP_LABEL_INDEX = 4,   // MetaPath with a label index
-    SMP_NAIVE_ADJ = 5,     // NAIVE with the adjacency index
-    SMP_OREJ_ADJ = 6       // Node2Vec O-REJ with the adjacency index
+    SMP_NAIVE = 0, SMP_ALIAS = 1, SMP_ITS = 2, SMP_OREJ = 3, SMP_REJ = 4,
+    SMP_LABEL_INDEX = 5,   // MetaPath with a label index
+    SMP_NAIVE_ADJ = 6,     // NAIVE with the adjacency index
+    SMP_OREJ_ADJ = 7       // Node2Vec O-REJ with the adjacency index
 };
 
-// Darts per O-REJ move at most (then the last dart is taken); with every
-// threshold >= 1 the cap is reached with probability below e^-256.
+// Darts per O-REJ or REJ move at most (then the last dart is taken).  O-REJ:
+// with every threshold >= 1 the cap is reached with probability below
+// e^-256.  REJ: a dart at the row's heaviest edge always hits, so the cap is
+// reached with probability (1 - sum w / (d p*))^(2^24), below e^-65536 when
+// the row's weights differ by at most a factor 256.
 constexpr uint32_t kMaxDarts = 1u << 24;
 
 struct Tuning {
@@ -109,6 +114,7 @@ hipError_t launch_label_index_build(const GraphDev &g, uint32_t nlab, int32_t *l
 hipError_t launch_adjacency_build(const GraphDev &g, uint4 *out, hipStream_t s);
 hipError_t launch_edge_set_build(const GraphDev &g, unsigned long long *keys, unsigned long long slots, hipStream_t s);
 hipError_t launch_symmetry_check(const GraphDev &g, unsigned long long *d_bad, hipStream_t s);
+hipError_t launch_rej_build(const GraphDev &g, uint4 *records, uint32_t *pmax, hipStream_t s);
 
 size_t walk_workspace_bytes(uint32_t mode, uint64_t nq, uint32_t max_len);
 hipError_t launch_walk(const GraphDev &g, const TableDev &t, uint32_t algo, uint32_t sampler,
@@ -123,6 +129,9 @@ void set_error(const std::string &msg);
 constexpr uint32_t kLabelIndexKind = 0x100;
 constexpr uint32_t kAdjacencyKind = 0x101;
 constexpr uint32_t kEdgeIndexKind = 0x102;    // adjacency records, then the edge hash set
+
+// Bytes of the slot records at the start of a REJ table (256-aligned); p*[n] follows.
+inline size_t rej_records_bytes(int64_t m) { return ((32 * (size_t)m) + 255) / 256 * 256; }
 
 // Bytes of the adjacency records at the start of an edge index (256-aligned).
 inline size_t edge_index_records_bytes(int64_t m) { return ((16 * (size_t)m) + 255) / 256 * 256; }

@@ -24,8 +24,9 @@
 //
 // Sampling is integer throughout: uniform index = high half of r * d; ALIAS
 // coin r1 < thr; ITS draw = high half of (r1:r0) * W and a binary search over
-// the uint64 prefix; O-REJ darts compare r1 >> 16 with Q16 thresholds;
-// MetaPath counts the matching labels of the row and takes the j-th.
+// the uint64 prefix; O-REJ darts compare r1 >> 16 with Q16 thresholds; REJ
+// darts compare r1 * p* with w * 2^32; MetaPath counts the matching labels of
+// the row and takes the j-th.
 #include <algorithm>
 
 #include "trw_device.hpp"
@@ -204,9 +205,13 @@ struct Walker {
     int32_t deg;
     int32_t poff;    // row of prev (Node2Vec)
     int32_t pdeg;
+    uint32_t dart;   // REJ: darts thrown for the current move
+    uint32_t pm;     // REJ: p* of cur
     bool need_row;
     PathBuf path;
 };
+
+constexpr int32_t kMissed = -2;   // REJ: this iteration's dart missed; no move
 
 template <uint32_t ALGO, uint32_t SMP, int WPL>
 __global__ void __launch_bounds__(256)
@@ -216,6 +221,7 @@ k_walk_persistent(GraphDev g, TableDev t, WalkDev a, unsigned long long *__restr
     constexpr bool kAlias = kStatic && SMP == SMP_ALIAS;
     constexpr bool kOneRead = kAlias || (kStatic && SMP == SMP_NAIVE_ADJ);   // entry carries the next row
     constexpr bool kNoRows = (SMP == SMP_LABEL_INDEX);   // the label index replaces the row lookup
+    constexpr bool kRej = kStatic && SMP == SMP_REJ;
     Walker w[WPL];
 #pragma unroll
     for (int i = 0; i < WPL; ++i) w[i].qi = kIdle;
@@ -250,6 +256,7 @@ k_walk_persistent(GraphDev g, TableDev t, WalkDev a, unsigned long long *__restr
     // wait for them would also wait for this iteration's stores.
     uint32_t s_qi = kIdle, r_qi = kIdle, s_code = kStageDirect, r_code = kStageDirect;
     int32_t s_src = 0, r_src = 0, r_lo = 0, r_hi = 0, r_deg = 0;
+    uint32_t r_pm = 0;                      // REJ: p* of the ready query's source
     bool s_bad = false;
 
     // Id ranges come from the queue head one claim ahead: the next range is
@@ -284,6 +291,7 @@ k_walk_persistent(GraphDev g, TableDev t, WalkDev a, unsigned long long *__restr
             if (w[i].qi == kIdle && r_qi != kIdle) {
                 w[i].qi = r_qi; w[i].code = r_code; w[i].cur = r_src; w[i].prev = -1; w[i].k = 0;
                 w[i].poff = 0; w[i].pdeg = 0; w[i].need_row = false;
+                w[i].dart = 0; w[i].pm = r_pm;
                 w[i].off = r_lo; w[i].deg = kNoRows ? 1 : r_deg;
                 w[i].path.start(a.paths + (uint64_t)r_qi * a.stride);
                 w[i].path.push(r_src);
@@ -297,6 +305,7 @@ k_walk_persistent(GraphDev g, TableDev t, WalkDev a, unsigned long long *__restr
             } else {
                 r_qi = s_qi; r_code = s_code; r_src = s_src;
                 if (!kNoRows) { r_lo = g.row_ptr[s_src]; r_hi = g.row_ptr[s_src + 1]; }
+                if (kRej) r_pm = t.pmax[s_src];
             }
             s_qi = kIdle;
         }
@@ -345,7 +354,7 @@ k_walk_persistent(GraphDev g, TableDev t, WalkDev a, unsigned long long *__restr
         }
         Rand4 r[WPL];
 #pragma unroll
-        for (int i = 0; i < WPL; ++i) r[i] = philox(w[i].k, 0, a.qid_base + w[i].qi, a.seed);
+        for (int i = 0; i < WPL; ++i) r[i] = philox(w[i].k, kRej ? w[i].dart : 0u, a.qid_base + w[i].qi, a.seed);
 
         // Move.
         int32_t nxt[WPL];
@@ -397,6 +406,34 @@ k_walk_persistent(GraphDev g, TableDev t, WalkDev a, unsigned long long *__restr
                     w[i].need_row = !kAdj;
                 }
             }
+        } else if (kRej) {
+            // One dart per walker per iteration: a walker whose dart misses
+            // keeps its state and throws its next dart in the next iteration,
+            // so the lanes of a wave never wait for each other's misses.
+            uint4 e0[WPL];
+            uint32_t e_pm[WPL];
+#pragma unroll
+            for (int i = 0; i < WPL; ++i) {
+                if (w[i].qi != kIdle && w[i].deg != 0 && w[i].pm != 0) {
+                    const uint64_t e = (uint64_t)(uint32_t)w[i].off + scale32(r[i].r0, (uint32_t)w[i].deg);
+                    e0[i] = t.rej[2 * e];
+                    e_pm[i] = t.rej[2 * e + 1].x;
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < WPL; ++i) {
+                nxt[i] = -1;
+                if (w[i].qi != kIdle && w[i].deg != 0 && w[i].pm != 0) {
+                    if (rej_hit(r[i].r1, w[i].pm, e0[i].x) || w[i].dart + 1 == kMaxDarts) {
+                        nxt[i] = (int32_t)e0[i].y;
+                        w[i].off = (int32_t)e0[i].z; w[i].deg = (int32_t)e0[i].w;
+                        w[i].pm = e_pm[i]; w[i].dart = 0;
+                    } else {
+                        nxt[i] = kMissed;
+                        w[i].dart += 1;
+                    }
+                }
+            }
         } else {
 #pragma unroll
             for (int i = 0; i < WPL; ++i) {
@@ -414,6 +451,7 @@ k_walk_persistent(GraphDev g, TableDev t, WalkDev a, unsigned long long *__restr
         // here, on every path through the loop, so that the compiler knows
         // they are complete at the top of the next iteration.
         asm volatile("" ::"v"(s_src), "v"(r_lo), "v"(r_hi), "v"(ahead_base));
+        if (kRej) asm volatile("" ::"v"(r_pm));
         s_bad = (uint32_t)s_src >= (uint32_t)g.n;
         r_deg = r_hi - r_lo;
         ahead_seen = __shfl(ahead_base, 0);
@@ -423,6 +461,7 @@ k_walk_persistent(GraphDev g, TableDev t, WalkDev a, unsigned long long *__restr
 #pragma unroll
         for (int i = 0; i < WPL; ++i) {
             if (w[i].qi == kIdle) continue;
+            if (kRej && nxt[i] == kMissed) continue;
             uint8_t st = 0;
             if (nxt[i] < 0) {
                 st = ST_DEAD_END;
@@ -475,6 +514,8 @@ k_walk_persistent(GraphDev g, TableDev t, WalkDev a, unsigned long long *__restr
 // ---------------------------------------------------------------------------
 // A live walker between launches: query index, current vertex and two words
 // that are the row range of cur for ALIAS walks, and (prev, unused) otherwise.
+// REJ walks keep p* of cur in place of cur (the vertex itself is not needed
+// again) and its row range in the two words.
 struct alignas(16) Rec {
     uint32_t qi;
     int32_t cur;
@@ -487,8 +528,10 @@ __global__ void k_fill_u32(uint32_t *p, uint32_t n, uint32_t v) {
     if (i < n) p[i] = v;
 }
 
-template <bool ALIAS_ROWS>
-__global__ void __launch_bounds__(256) k_bsp_init(GraphDev g, WalkDev a, Rec *__restrict__ out,
+// CARRY: 0 records hold (source, -1, 0); 1 the source's row range; 2 for REJ
+// also its p*.
+template <uint32_t CARRY>
+__global__ void __launch_bounds__(256) k_bsp_init(GraphDev g, TableDev t, WalkDev a, Rec *__restrict__ out,
                                                   uint32_t *__restrict__ count) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t base = 0; base < a.nq; base += stride) {
@@ -507,9 +550,10 @@ __global__ void __launch_bounds__(256) k_bsp_init(GraphDev g, WalkDev a, Rec *__
         }
         const uint32_t slot = wave_append(count, keep);
         if (keep) {
-            if (ALIAS_ROWS) {
+            if (CARRY != 0) {
                 const int32_t lo = g.row_ptr[s];
-                out[slot] = Rec{(uint32_t)i, s, lo, g.row_ptr[s + 1] - lo};
+                const int32_t first = CARRY == 2 ? (int32_t)t.pmax[s] : s;
+                out[slot] = Rec{(uint32_t)i, first, lo, g.row_ptr[s + 1] - lo};
             } else {
                 out[slot] = Rec{(uint32_t)i, s, -1, 0};
             }
@@ -524,7 +568,8 @@ __global__ void __launch_bounds__(256) k_bsp_step(GraphDev g, TableDev t, WalkDe
                                                   uint32_t coop) {
     constexpr bool kStatic = (ALGO == ALG_DEEPWALK || ALGO == ALG_PPR);
     constexpr bool kAlias = kStatic && SMP == SMP_ALIAS;
-    constexpr bool kCarry = kAlias || (kStatic && SMP == SMP_NAIVE_ADJ);   // records carry cur's row
+    constexpr bool kRej = kStatic && SMP == SMP_REJ;
+    constexpr bool kCarry = kAlias || kRej || (kStatic && SMP == SMP_NAIVE_ADJ);   // records carry cur's row
     const uint32_t n_in = *count_in;
     const uint32_t stride = gridDim.x * blockDim.x;
     for (uint32_t base = 0; base < n_in; base += stride) {
@@ -543,11 +588,15 @@ __global__ void __launch_bounds__(256) k_bsp_step(GraphDev g, TableDev t, WalkDe
             }
         }
         int32_t nxt = -1, noff = 0, ndeg = 0;
+        uint32_t npm = 0;
         if (ALGO == ALG_METAPATH) {
             nxt = metapath_move<SMP>(g, t, a, act, k, rc.cur, off, d, r.r0, coop);
         } else if (act) {
             if (kCarry) {
-                if (rc.b != 0) {
+                if (rc.b != 0 && kRej) {
+                    nxt = rej_move(t, a, a.qid_base + rc.qi, k, rc.a, (uint32_t)rc.b, (uint32_t)rc.cur, r, noff, ndeg,
+                                   npm);
+                } else if (rc.b != 0) {
                     const uint32_t e = (uint32_t)rc.a + scale32(r.r0, (uint32_t)rc.b);
                     if (kAlias) {
                         nxt = alias_pick(t.alias[2 * (uint64_t)e], t.alias[2 * (uint64_t)e + 1], r.r1, noff, ndeg);
@@ -586,7 +635,8 @@ __global__ void __launch_bounds__(256) k_bsp_step(GraphDev g, TableDev t, WalkDe
                 a.status[rc.qi] = st;
             } else {
                 keep = true;
-                nr = kCarry ? Rec{rc.qi, nxt, noff, ndeg} : Rec{rc.qi, nxt, rc.cur, 0};
+                nr = kRej ? Rec{rc.qi, (int32_t)npm, noff, ndeg}
+                          : kCarry ? Rec{rc.qi, nxt, noff, ndeg} : Rec{rc.qi, nxt, rc.cur, 0};
             }
         }
         const uint32_t slot = wave_append(count_out, keep);
@@ -642,7 +692,8 @@ hipError_t run_persistent(const GraphDev &g, const TableDev &t, const WalkDev &w
 template <uint32_t ALGO, uint32_t SMP>
 hipError_t run_bsp(const GraphDev &g, const TableDev &t, const WalkDev &w, const Tuning &tu,
                    const DeviceInfo &di, void *ws, hipStream_t s) {
-    constexpr bool kCarry = (ALGO == ALG_DEEPWALK || ALGO == ALG_PPR) && (SMP == SMP_ALIAS || SMP == SMP_NAIVE_ADJ);
+    constexpr bool kStatic = ALGO == ALG_DEEPWALK || ALGO == ALG_PPR;
+    constexpr uint32_t kCarry = !kStatic ? 0u : SMP == SMP_REJ ? 2u : (SMP == SMP_ALIAS || SMP == SMP_NAIVE_ADJ) ? 1u : 0u;
     char *base = reinterpret_cast<char *>(ws);
     uint32_t *counts = reinterpret_cast<uint32_t *>(base);
     const size_t counts_bytes = round_up(sizeof(uint32_t) * (w.max_len + 2));
@@ -655,7 +706,7 @@ hipError_t run_bsp(const GraphDev &g, const TableDev &t, const WalkDev &w, const
     const uint64_t need = ((uint64_t)w.nq + threads - 1) / threads;
     if (blocks > need) blocks = need;
     if (blocks == 0) blocks = 1;
-    hipLaunchKernelGGL(k_bsp_init<kCarry>, dim3(blocks), dim3(threads), 0, s, g, w, lists[0], counts);
+    hipLaunchKernelGGL(k_bsp_init<kCarry>, dim3(blocks), dim3(threads), 0, s, g, t, w, lists[0], counts);
     for (uint32_t k = 0; k < w.max_len; ++k) {
         hipLaunchKernelGGL((k_bsp_step<ALGO, SMP>), dim3(blocks), dim3(threads), 0, s, g, t, w, k,
                            lists[k & 1], counts + k, lists[(k + 1) & 1], counts + k + 1, tu.coop_degree);
@@ -686,11 +737,13 @@ hipError_t launch_walk(const GraphDev &g, const TableDev &t, uint32_t algo, uint
             if (sampler == SMP_NAIVE && t.adj) return run<ALG_DEEPWALK, SMP_NAIVE_ADJ>(g, t, w, mode, tu, di, ws, s);
             if (sampler == SMP_NAIVE) return run<ALG_DEEPWALK, SMP_NAIVE>(g, t, w, mode, tu, di, ws, s);
             if (sampler == SMP_ALIAS) return run<ALG_DEEPWALK, SMP_ALIAS>(g, t, w, mode, tu, di, ws, s);
+            if (sampler == SMP_REJ) return run<ALG_DEEPWALK, SMP_REJ>(g, t, w, mode, tu, di, ws, s);
             return run<ALG_DEEPWALK, SMP_ITS>(g, t, w, mode, tu, di, ws, s);
         case ALG_PPR:
             if (sampler == SMP_NAIVE && t.adj) return run<ALG_PPR, SMP_NAIVE_ADJ>(g, t, w, mode, tu, di, ws, s);
             if (sampler == SMP_NAIVE) return run<ALG_PPR, SMP_NAIVE>(g, t, w, mode, tu, di, ws, s);
             if (sampler == SMP_ALIAS) return run<ALG_PPR, SMP_ALIAS>(g, t, w, mode, tu, di, ws, s);
+            if (sampler == SMP_REJ) return run<ALG_PPR, SMP_REJ>(g, t, w, mode, tu, di, ws, s);
             return run<ALG_PPR, SMP_ITS>(g, t, w, mode, tu, di, ws, s);
         case ALG_NODE2VEC:
             if (t.adj) return run<ALG_NODE2VEC, SMP_OREJ_ADJ>(g, t, w, mode, tu, di, ws, s);

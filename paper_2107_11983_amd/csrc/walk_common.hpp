@@ -36,6 +36,38 @@ __device__ __forceinline__ int32_t static_next(const GraphDev &g, const TableDev
 }
 
 // ---------------------------------------------------------------------------
+// REJ (Sampling Methods, rejection sampling): a dart (x, y) has x a uniform
+// edge slot of cur and y = r1 * p*(cur) / 2^32 uniform in [0, p*); it hits
+// iff y < w_x, i.e. r1 * p* < w_x * 2^32 in exact 64-bit integers.  Dart t of
+// move k uses Philox block (k, t); the hitting dart's block also gives PPR's
+// stop coin.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool rej_hit(uint32_t r1, uint32_t pmax, uint32_t w) {
+    return (uint64_t)r1 * pmax < ((uint64_t)w << 32);
+}
+
+// Throws darts until one hits (the per-step schedule; the persistent kernel
+// throws one dart per iteration instead).  r holds dart 0's block on entry
+// and the hitting dart's block on return.  Returns the next vertex and its
+// row and p*, or -1 when cur has no transition (p* == 0).
+__device__ __forceinline__ int32_t rej_move(const TableDev &t, const WalkDev &a, uint64_t qid, uint32_t k,
+                                            int32_t off, uint32_t d, uint32_t pm, Rand4 &r, int32_t &noff,
+                                            int32_t &ndeg, uint32_t &npm) {
+    if (pm == 0) return -1;
+    for (uint32_t dart = 0;; ++dart) {
+        if (dart > 0) r = philox(k, dart, qid, a.seed);
+        const uint64_t e = (uint64_t)(uint32_t)off + scale32(r.r0, d);
+        const uint4 rec = t.rej[2 * e];
+        if (rej_hit(r.r1, pm, rec.x) || dart + 1 == kMaxDarts) {
+            noff = (int32_t)rec.z;
+            ndeg = (int32_t)rec.w;
+            npm = t.rej[2 * e + 1].x;
+            return (int32_t)rec.y;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Node2Vec move, O-REJ (Sampling Methods: rejection with a user bound p*):
 // throw darts (x, y) with x a uniform edge slot of cur and y = r1 >> 16 until
 // y falls under the Q16 threshold of x's class (x == prev, x adjacent to

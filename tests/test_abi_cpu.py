@@ -132,3 +132,46 @@ def test_default_tuning(abi):
     assert abi.trw_default_tuning(g, ctypes.byref(p), 1, ctypes.byref(t)) == abi.TRW_OK
     assert t.walkers_per_lane in (1, 2, 4) and t.block_threads % 64 == 0 and t.queue_chunk >= 1
     abi.trw_graph_destroy(g)
+
+
+def test_rej_table_and_walk_checks(abi):
+    g = _fake_graph(abi, weights=True)
+    sz = ctypes.c_size_t()
+    assert abi.trw_table_bytes(g, abi.TRW_S_REJ, ctypes.byref(sz)) == abi.TRW_OK
+    assert sz.value == 32 * 1000 + 4 * 100          # 32 B per slot (already 256-aligned), then p*[n]
+    fake = ctypes.c_void_p(0x1000)
+    p = _params(abi, "ppr", "rej")
+    assert abi.trw_walk(g, None, ctypes.byref(p), fake, 5, 0, fake, 11, fake, fake, 1, None,
+                        ctypes.c_void_p(0x10000), 1 << 20, None) == abi.TRW_E_INVALID   # REJ needs its table
+    assert _params(abi, "node2vec", "rej").sampler == abi.TRW_S_REJ
+    assert abi.trw_walk_workspace_bytes(g, ctypes.byref(_params(abi, "node2vec", "rej")), 1, 1,
+                                        ctypes.byref(sz)) == abi.TRW_E_UNSUPPORTED
+    t = ctypes.c_void_p()
+    gn = _fake_graph(abi)
+    assert abi.trw_table_build(gn, abi.TRW_S_REJ, fake, 40000, None, ctypes.byref(t)) == abi.TRW_E_INVALID  # no w
+    abi.trw_graph_destroy(g)
+    abi.trw_graph_destroy(gn)
+
+
+def test_ppr_estimate_argument_checks(abi):
+    sz = ctypes.c_size_t()
+    assert abi.trw_topk_workspace_bytes(100, 10, ctypes.byref(sz)) == abi.TRW_OK and sz.value == 1280 + 80
+    assert abi.trw_topk_workspace_bytes(100, 101, ctypes.byref(sz)) == abi.TRW_E_INVALID
+    assert abi.trw_topk_workspace_bytes(10**6, 4097, ctypes.byref(sz)) == abi.TRW_E_INVALID
+    fake = ctypes.c_void_p(0x1000)
+    ws = ctypes.c_void_p(0x10000)
+    assert abi.trw_topk(fake, 100, 10, fake, fake, ws, 1000, None) == abi.TRW_E_INVALID          # short ws
+    assert abi.trw_topk(fake, 100, 10, fake, fake, ctypes.c_void_p(0x10010), 4096, None) == abi.TRW_E_INVALID
+    assert abi.trw_topk(None, 100, 10, fake, fake, ws, 4096, None) == abi.TRW_E_INVALID
+    assert abi.trw_topk(fake, 2**31, 10, fake, fake, ws, 4096, None) == abi.TRW_E_INVALID
+    assert abi.trw_topk(fake, 100, 0, None, None, None, 0, None) == abi.TRW_OK                   # k = 0
+    g = _fake_graph(abi)                                                                        # n = 100
+    def ec(nq, group, counts_len, stride=11, paths=fake):
+        return abi.trw_ppr_end_counts(g, paths, stride, fake, fake, nq, group, fake, counts_len, None, None)
+    assert ec(10, 0, 99) == abi.TRW_E_INVALID            # counts shorter than n
+    assert ec(10, 3, 399) == abi.TRW_E_INVALID           # 4 groups of 3 need 400
+    assert ec(10, 0, 100, stride=0) == abi.TRW_E_INVALID
+    assert ec(10, 0, 100, paths=None) == abi.TRW_E_INVALID
+    assert ec(2**32, 0, 100) == abi.TRW_E_INVALID
+    assert ec(0, 0, 100) == abi.TRW_OK                   # nothing to do
+    abi.trw_graph_destroy(g)

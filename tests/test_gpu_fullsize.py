@@ -2,7 +2,9 @@
 times (persistent schedule, default tuning, the same tables and indexes).
 
 * PPR on R-MAT 2^22 (10^7 queries): every query compared with the oracle,
-  paths included, in chunks of 10^6.
+  paths included, in chunks of 10^6; the end counts of five groups of
+  2 M queries and their top 4096 compared whole; the same batch with REJ
+  compared on a seeded sample.
 * Node2Vec and MetaPath on R-MAT 2^24 (one query per vertex): a seeded sample
   of queries compared with the oracle, which walks exactly those query ids;
   the termination rules checked on every query and the hops of a sample
@@ -118,12 +120,40 @@ def test_ppr_rmat22_every_query():
     thr, al = oracle.alias_build(g.row_ptr, g.weight)
     op = _oracle_params(p)
     chunk = 1_000_000
+    group = 2_000_000
+    exp_counts = np.zeros((len(src) // group, g.n), np.uint32)
     for lo in range(0, len(src), chunk):
         hi = min(len(src), lo + chunk)
         ref = oracle.walk(g.row_ptr, g.col, op, src[lo:hi], qid_base=lo, thr=thr, alias=al)
         Pc = P[lo:hi].cpu().numpy()
         _compare(Pc, Lh[lo:hi], Sh[lo:hi], ref, wl.max_len, f"ppr-rmat22 queries {lo}..{hi}")
         log(f"  ppr-rmat22 queries {lo}..{hi} identical")
+        # the oracle's end counts of the same queries (groups of 2 M queries hold whole chunks)
+        oracle.end_counts(g.n, ref.paths, ref.lengths, ref.status, counts=exp_counts[lo // group])
+    # PPR estimate at full size: end counts per group and the top 4096 of each group
+    counts, skipped = trw.ppr_end_counts(G, P, L, S, group=group)
+    torch.cuda.synchronize()
+    assert int(skipped.item()) == 0
+    got = counts.cpu().numpy().view(np.uint32)
+    assert np.array_equal(got, exp_counts), "end counts differ"
+    for gi in range(exp_counts.shape[0]):
+        ids, vals = trw.topk(counts[gi], 4096)
+        eid, ev = oracle.topk(exp_counts[gi], 4096)
+        assert np.array_equal(ids.cpu().numpy(), eid) and np.array_equal(vals.cpu().numpy().view(np.uint32), ev)
+    log("  ppr-rmat22 end counts and top-4096 identical")
+    del counts, P, L, S
+    # REJ on the same batch: a seeded sample of queries against the oracle
+    rej = G.table("rej")
+    pr = _params(wl, "rej")
+    P, L, S = _walk_full(wl, G, rej, pr, src)
+    Lh, Sh = L.cpu().numpy(), S.cpu().numpy()
+    _check_rules(wl, Lh, Sh)
+    idx = np.unique(np.concatenate([np.random.default_rng(7).choice(len(src), 20000, replace=False),
+                                    [0, len(src) - 1]]))
+    ref = oracle.walk(g.row_ptr, g.col, _oracle_params(pr), src[idx], qids=idx.astype(np.uint64),
+                      weight=g.weight, pmax=oracle.rej_build(g.row_ptr, g.weight))
+    _compare(_rows(P, idx), Lh[idx], Sh[idx], ref, wl.max_len, "ppr-rmat22 REJ sample")
+    log("  ppr-rmat22 REJ sample identical")
     G.close()
 
 

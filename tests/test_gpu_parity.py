@@ -37,7 +37,7 @@ def log(msg):
 
 
 ORC_ALGO = {"deepwalk": oracle.DEEPWALK, "ppr": oracle.PPR, "node2vec": oracle.NODE2VEC, "metapath": oracle.METAPATH}
-ORC_SMP = {"naive": oracle.NAIVE, "alias": oracle.ALIAS, "its": oracle.ITS, "orej": oracle.OREJ}
+ORC_SMP = {"naive": oracle.NAIVE, "alias": oracle.ALIAS, "its": oracle.ITS, "orej": oracle.OREJ, "rej": oracle.REJ}
 
 
 class Case:
@@ -51,7 +51,7 @@ class Case:
         self._orc_tables = {}
 
     def dev_table(self, sampler):
-        if sampler not in ("alias", "its"):
+        if sampler not in ("alias", "its", "rej"):
             return None
         if sampler not in self._dev_tables:
             self._dev_tables[sampler] = self.G.table(sampler)
@@ -80,6 +80,9 @@ class Case:
                 self._orc_tables[sampler] = dict(thr=t, alias=a)
             elif sampler == "its":
                 self._orc_tables[sampler] = dict(prefix=oracle.its_build(self.g.row_ptr, self.g.weight))
+            elif sampler == "rej":
+                self._orc_tables[sampler] = dict(weight=self.g.weight,
+                                                 pmax=oracle.rej_build(self.g.row_ptr, self.g.weight))
             else:
                 self._orc_tables[sampler] = {}
         return self._orc_tables[sampler]
@@ -221,6 +224,37 @@ def test_its_table_matches_oracle(rmat_dir):
         assert np.array_equal(got, oracle.its_build(g.row_ptr, g.weight))
 
 
+def _rej_expected(g, pmax):
+    """The documented REJ table: 32-byte slot records, then p*[n] at 32*m rounded to 256."""
+    rp, col = g.row_ptr.astype(np.int64), g.col.astype(np.int64)
+    deg = np.diff(rp)
+    exp = np.zeros((g.m, 8), dtype=np.int64)
+    exp[:, 0] = g.weight
+    exp[:, 1] = col
+    exp[:, 2] = rp[col]
+    exp[:, 3] = deg[col]
+    exp[:, 4] = pmax[col]
+    return exp.astype(np.uint32)
+
+
+def _rej_check(case):
+    g = case.g
+    t = case.dev_table("rej")
+    torch.cuda.synchronize()
+    raw = t.buf.view(torch.int32).cpu().numpy().view(np.uint32)
+    pmax = oracle.rej_build(g.row_ptr, g.weight)
+    rec_words = ((32 * g.m + 255) // 256 * 256) // 4
+    assert np.array_equal(raw[rec_words:rec_words + g.n], pmax), "p* differs"
+    got = raw[:8 * g.m].reshape(-1, 8)
+    bad = np.nonzero((got != _rej_expected(g, pmax)).any(axis=1))[0]
+    assert bad.size == 0, f"REJ records differ at edge slots {bad[:10]}"
+
+
+def test_rej_table_matches_oracle(rmat_dir):
+    _rej_check(rmat_dir)
+    _rej_check(Case(_weighted_rows_graph(9, 2**32 - 1)))
+
+
 def _long_rows_graph(wmax, seed):
     """Rows of 1025..5000 slots (one workgroup each) in every weight regime, a
     70000-slot star whose d*W passes 2^64 at wmax = 2^32-1, and short rows."""
@@ -271,6 +305,7 @@ def test_tables_long_rows(wmax):
     torch.cuda.synchronize()
     got = t.buf[:8 * g.m].view(torch.int64).cpu().numpy().view(np.uint64)
     assert np.array_equal(got, oracle.its_build(g.row_ptr, g.weight))
+    _rej_check(case)
 
 
 def test_label_index_records_long_rows():
@@ -320,8 +355,8 @@ def test_validate_rejects_bad_graphs():
 
 
 # --------------------------------------------------------------------------- walks
-PAIRS = [("deepwalk", "naive"), ("deepwalk", "alias"), ("deepwalk", "its"),
-         ("ppr", "naive"), ("ppr", "alias"), ("ppr", "its"),
+PAIRS = [("deepwalk", "naive"), ("deepwalk", "alias"), ("deepwalk", "its"), ("deepwalk", "rej"),
+         ("ppr", "naive"), ("ppr", "alias"), ("ppr", "its"), ("ppr", "rej"),
          ("node2vec", "orej"), ("metapath", "its")]
 
 
@@ -349,7 +384,7 @@ def test_walk_parity(rmat_sym, rmat_dir, algo, sampler, mode):
 
 
 @pytest.mark.parametrize("algo,sampler", [("ppr", "alias"), ("node2vec", "orej"), ("metapath", "its"),
-                                          ("deepwalk", "its")])
+                                          ("deepwalk", "its"), ("ppr", "rej")])
 @pytest.mark.parametrize("wpl,bpc,chunk,threads", [(2, 8, 256, 256), (4, 4, 64, 256), (1, 1, 1, 64),
                                                    (2, 3, 1000, 128)])
 def test_tuning_does_not_change_results(rmat_sym, rmat_dir, algo, sampler, wpl, bpc, chunk, threads):
@@ -380,6 +415,20 @@ def test_autotune_picks_a_candidate_and_results_do_not_change(rmat_sym, rmat_dir
     assert np.array_equal(ref[1], got[1]) and np.array_equal(ref[2], got[2])
     mask = np.arange(41)[None, :] <= L[:, None]
     assert np.array_equal(ref[0][:, :41][mask], got[0][:, :41][mask])
+
+@pytest.mark.parametrize("mode", [1, 0])
+@pytest.mark.parametrize("algo", ["deepwalk", "ppr"])
+def test_rej_walk_zero_weights_and_long_rows(algo, mode):
+    """REJ where rows have zero weights (dead ends), skewed weights (many
+    misses) and rows of thousands of slots."""
+    for case in (Case(_weighted_rows_graph(17, 255)), Case(_long_rows_graph(2**32 - 1, 5))):
+        n = case.g.n
+        src = np.concatenate([np.arange(min(n, 3000)), synth.sources(1000 + 29, n, 8)]).astype(np.int32)
+        max_len = 30
+        gpu, ref = run_both(case, algo, "rej", max_len, 21 + mode, src, mode, **_args(algo))
+        assert_same(gpu, ref, max_len)
+        assert ref.counters["rej_trials"] > ref.counters["moves"]   # darts did miss
+
 
 def test_edge_cases(rmat_sym, rmat_dir):
     n = rmat_dir.g.n
