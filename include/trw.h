@@ -119,8 +119,8 @@ typedef enum {
 
 typedef struct trw_table_s *trw_table;
 
-/* Bytes of device memory the table for `sampler` needs: ALIAS 32*m, ITS 8*m,
- * REJ 32*m rounded up to 256, plus 4*n. */
+/* Bytes of device memory the table for `sampler` needs: ALIAS 32*m; ITS 8*m and
+ * 32*m, each rounded up to 256, plus 8*n; REJ 32*m rounded up to 256, plus 4*n. */
 trw_status trw_table_bytes(trw_graph g, uint32_t sampler, size_t *bytes);
 
 /*
@@ -138,7 +138,12 @@ trw_status trw_table_bytes(trw_graph g, uint32_t sampler, size_t *bytes);
  *          candidates ride along so that a move needs one 32-byte read.
  *          A row whose weights sum to 0 holds {0xFFFFFFFF, -1, -1, 0, 0, 0,
  *          0, 0}: a walk that reaches it ends as a dead end.
- *   ITS:   uint64 prefix[e] = sum of w over row v up to and including e.
+ *   ITS:   uint64 prefix[e] = sum of w over row v up to and including e; then,
+ *          at byte 8*m rounded up to 256, 8 x uint32 per edge slot {col[e],
+ *          row_off(col[e]), deg(col[e]), 0, W lo, W hi, 0, 0} with W the
+ *          weight sum of col[e]'s row; then, at 32*m further (rounded up to
+ *          256), uint64 W[n].  A move searches the prefix and reads the
+ *          chosen slot's record, which carries the next row and its total.
  *   REJ:   (Sampling Methods, rejection sampling: initialization finds
  *          p*_v = max weight of v's row; generation throws darts (x, y) with x
  *          uniform in [0, d_v), y uniform in [0, p*_v) until y < w_x.)

@@ -124,6 +124,8 @@ Tuning resolve_tuning(const trw_walk_params *p, uint32_t mode, const trw_tuning 
             tu.blocks_per_cu = p->algo == TRW_A_PPR ? 1 : 2;
             tu.walkers_per_lane = p->algo == TRW_A_PPR ? 2 : 1;
         } else if (static_walk && p->sampler == TRW_S_ITS) {
+            tu.blocks_per_cu = 4;
+        } else if (static_walk && p->sampler == TRW_S_REJ) {
             tu.blocks_per_cu = 2;
         } else if (p->algo == TRW_A_METAPATH && label_index) {
             tu.blocks_per_cu = 2;       // the row scans without an index want the occupancy
@@ -207,7 +209,9 @@ trw_status trw_table_bytes(trw_graph g, uint32_t sampler, size_t *bytes) {
     if (!g || !bytes) return fail(TRW_E_INVALID, "graph / bytes is NULL");
     switch (sampler) {
         case TRW_S_ALIAS: *bytes = kAliasEntryBytes * (size_t)g->dev.m; return TRW_OK;
-        case TRW_S_ITS: *bytes = sizeof(uint64_t) * (size_t)g->dev.m; return TRW_OK;
+        case TRW_S_ITS:
+            *bytes = its_prefix_bytes(g->dev.m) + its_next_bytes(g->dev.m) + sizeof(uint64_t) * (size_t)g->dev.n;
+            return TRW_OK;
         case TRW_S_REJ: *bytes = rej_records_bytes(g->dev.m) + sizeof(uint32_t) * (size_t)g->dev.n; return TRW_OK;
         case TRW_S_NAIVE:
         case TRW_S_OREJ: *bytes = 0; return fail(TRW_E_UNSUPPORTED, "sampler has no table");
@@ -223,16 +227,20 @@ trw_status trw_table_build(trw_graph g, uint32_t sampler, void *d_buf, size_t by
     if (st != TRW_OK) return st;
     if (!g->dev.weight) return fail(TRW_E_INVALID, "table needs edge weights");
     if (bytes < need) return fail(TRW_E_INVALID, "table buffer too small");
-    if ((g->dev.m > 0 || sampler == TRW_S_REJ) && (!d_buf || (reinterpret_cast<uintptr_t>(d_buf) & 31)))
+    if ((g->dev.m > 0 || sampler != TRW_S_ALIAS) && (!d_buf || (reinterpret_cast<uintptr_t>(d_buf) & 31)))
         return fail(TRW_E_INVALID, "table buffer NULL or not 32-byte aligned");
     auto s = static_cast<hipStream_t>(stream);
     hipError_t e = hipSuccess;
+    char *base = static_cast<char *>(d_buf);
     if (sampler == TRW_S_REJ) {
         e = launch_rej_build(g->dev, static_cast<uint4 *>(d_buf),
-                             reinterpret_cast<uint32_t *>(static_cast<char *>(d_buf) + rej_records_bytes(g->dev.m)), s);
+                             reinterpret_cast<uint32_t *>(base + rej_records_bytes(g->dev.m)), s);
+    } else if (sampler == TRW_S_ITS) {
+        const size_t pb = its_prefix_bytes(g->dev.m);
+        e = launch_its_build(g->dev, static_cast<uint64_t *>(d_buf), reinterpret_cast<uint4 *>(base + pb),
+                             reinterpret_cast<uint64_t *>(base + pb + its_next_bytes(g->dev.m)), s);
     } else if (g->dev.m > 0) {
-        e = sampler == TRW_S_ALIAS ? launch_alias_build(g->dev, static_cast<uint4 *>(d_buf), s)
-                                   : launch_its_build(g->dev, static_cast<uint64_t *>(d_buf), s);
+        e = launch_alias_build(g->dev, static_cast<uint4 *>(d_buf), s);
     }
     if (e != hipSuccess) return device_fail(e, "table build launch");
     auto *t = new (std::nothrow) trw_table_s{g, sampler, d_buf, 0};
@@ -412,7 +420,10 @@ trw_status trw_walk(trw_graph g, trw_table table, const trw_walk_params *p, cons
             t.pmax = reinterpret_cast<const uint32_t *>(static_cast<const char *>(table->buf) +
                                                         rej_records_bytes(g->dev.m));
         } else {
+            const char *base = static_cast<const char *>(table->buf);
             t.prefix = static_cast<const uint64_t *>(table->buf);
+            t.its_next = reinterpret_cast<const uint4 *>(base + its_prefix_bytes(g->dev.m));
+            t.its_w = reinterpret_cast<const uint64_t *>(base + its_prefix_bytes(g->dev.m) + its_next_bytes(g->dev.m));
         }
     }
     if (label_index) {

@@ -19,7 +19,9 @@
 // Rows above kBigRow slots get a workgroup each instead (same results): see
 // k_alias_build_big.
 //
-// ITS: inclusive running sum of the weights per row in uint64.
+// ITS: inclusive running sum of the weights per row in uint64, then each
+// vertex's total and per edge slot a record with the destination's row and
+// total (k_its_next).
 //
 // REJ: the largest weight per row, and per edge slot a record with the
 // destination's row and bound (k_rej_records).
@@ -421,6 +423,28 @@ __global__ void k_adjacency_build(GraphDev g, uint4 *__restrict__ out) {
     out[e] = make_uint4((uint32_t)v, r.x, r.y, 0u);
 }
 
+// ITS next records: per vertex its weight sum W (the last prefix of its row),
+// and per edge slot the destination's id, row range and W, so that a move is
+// the search over the prefix plus one 32-byte read, with no lookup of the
+// chosen slot's destination, its row or its total:
+//   [0] {dst, row_off(dst), deg(dst), 0}   [1] {W(dst) lo, W(dst) hi, 0, 0}
+__global__ void k_its_vw(GraphDev g, const uint64_t *__restrict__ prefix, uint64_t *__restrict__ vw) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= g.n) return;
+    const int64_t hi = g.row_ptr[v + 1];
+    vw[v] = hi > g.row_ptr[v] ? prefix[hi - 1] : 0ull;
+}
+
+__global__ void k_its_next(GraphDev g, const uint64_t *__restrict__ vw, uint4 *__restrict__ out) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= g.m) return;
+    const int32_t v = g.col[e];
+    const uint2 r = row_of(g, v);
+    const uint64_t W = vw[v];
+    out[2 * e] = make_uint4((uint32_t)v, r.x, r.y, 0u);
+    out[2 * e + 1] = make_uint4((uint32_t)W, (uint32_t)(W >> 32), 0u, 0u);
+}
+
 // REJ (rejection sampling): the initialization finds p*_v, the largest
 // weight of v's row, kept per vertex after the slot records.  Every slot's
 // record then carries its weight and the destination's id, row range and
@@ -531,10 +555,17 @@ hipError_t launch_alias_build(const GraphDev &g, uint4 *out, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_its_build(const GraphDev &g, uint64_t *out, hipStream_t s) {
+hipError_t launch_its_build(const GraphDev &g, uint64_t *prefix, uint4 *next, uint64_t *vw, hipStream_t s) {
     const int blocks = (g.n + kBuildThreads - 1) / kBuildThreads;
-    hipLaunchKernelGGL(k_its_build, dim3(blocks), dim3(kBuildThreads), 0, s, g, out);
-    hipLaunchKernelGGL(k_its_build_big, dim3(big_row_blocks(g)), dim3(kBuildBlock), 0, s, g, out);
+    if (g.m > 0) {
+        hipLaunchKernelGGL(k_its_build, dim3(blocks), dim3(kBuildThreads), 0, s, g, prefix);
+        hipLaunchKernelGGL(k_its_build_big, dim3(big_row_blocks(g)), dim3(kBuildBlock), 0, s, g, prefix);
+    }
+    hipLaunchKernelGGL(k_its_vw, dim3(blocks), dim3(kBuildThreads), 0, s, g, prefix, vw);
+    if (g.m > 0) {
+        const int64_t eblocks = ((int64_t)g.m + kBuildThreads - 1) / kBuildThreads;
+        hipLaunchKernelGGL(k_its_next, dim3((uint32_t)eblocks), dim3(kBuildThreads), 0, s, g, vw, next);
+    }
     return hipGetLastError();
 }
 

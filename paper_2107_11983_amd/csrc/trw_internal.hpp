@@ -36,6 +36,8 @@ struct GraphDev {
 struct TableDev {
     const uint4 *alias;       // ALIAS: 2 x uint4 per edge slot
     const uint64_t *prefix;   // ITS: inclusive prefix per row
+    const uint4 *its_next;    // ITS: 2 x uint4 per edge slot {dst, row_off(dst), deg(dst), 0}, {W(dst) lo, hi, 0, 0}
+    const uint64_t *its_w;    // ITS: W per vertex (its row's weight sum)
     const int32_t *loff;      // label index: (L + 1) offsets per vertex
     const int32_t *lcol;      // label index: label-sorted destinations
     uint32_t nlab;            // label index: L
@@ -108,7 +110,7 @@ struct DeviceInfo {
 
 // Host launchers (tables.hip, walk.hip).  Return hipSuccess or the launch error.
 hipError_t launch_alias_build(const GraphDev &g, uint4 *out, hipStream_t s);
-hipError_t launch_its_build(const GraphDev &g, uint64_t *out, hipStream_t s);
+hipError_t launch_its_build(const GraphDev &g, uint64_t *prefix, uint4 *next, uint64_t *vw, hipStream_t s);
 hipError_t launch_validate(const GraphDev &g, unsigned long long *d_bad, hipStream_t s);
 hipError_t launch_label_index_build(const GraphDev &g, uint32_t nlab, int32_t *loff, int32_t *lcol, hipStream_t s);
 hipError_t launch_adjacency_build(const GraphDev &g, uint4 *out, hipStream_t s);
@@ -129,6 +131,10 @@ void set_error(const std::string &msg);
 constexpr uint32_t kLabelIndexKind = 0x100;
 constexpr uint32_t kAdjacencyKind = 0x101;
 constexpr uint32_t kEdgeIndexKind = 0x102;    // adjacency records, then the edge hash set
+
+// ITS table: the prefix (256-aligned), then the next-slot records, then W[n].
+inline size_t its_prefix_bytes(int64_t m) { return ((8 * (size_t)m) + 255) / 256 * 256; }
+inline size_t its_next_bytes(int64_t m) { return ((32 * (size_t)m) + 255) / 256 * 256; }
 
 // Bytes of the slot records at the start of a REJ table (256-aligned); p*[n] follows.
 inline size_t rej_records_bytes(int64_t m) { return ((32 * (size_t)m) + 255) / 256 * 256; }

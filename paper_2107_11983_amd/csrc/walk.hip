@@ -207,6 +207,7 @@ struct Walker {
     int32_t pdeg;
     uint32_t dart;   // REJ: darts thrown for the current move
     uint32_t pm;     // REJ: p* of cur
+    uint64_t W;      // ITS: weight sum of cur's row
     bool need_row;
     PathBuf path;
 };
@@ -222,6 +223,7 @@ k_walk_persistent(GraphDev g, TableDev t, WalkDev a, unsigned long long *__restr
     constexpr bool kOneRead = kAlias || (kStatic && SMP == SMP_NAIVE_ADJ);   // entry carries the next row
     constexpr bool kNoRows = (SMP == SMP_LABEL_INDEX);   // the label index replaces the row lookup
     constexpr bool kRej = kStatic && SMP == SMP_REJ;
+    constexpr bool kIts = kStatic && SMP == SMP_ITS;    // search, then the chosen slot's next record
     Walker w[WPL];
 #pragma unroll
     for (int i = 0; i < WPL; ++i) w[i].qi = kIdle;
@@ -257,6 +259,7 @@ k_walk_persistent(GraphDev g, TableDev t, WalkDev a, unsigned long long *__restr
     uint32_t s_qi = kIdle, r_qi = kIdle, s_code = kStageDirect, r_code = kStageDirect;
     int32_t s_src = 0, r_src = 0, r_lo = 0, r_hi = 0, r_deg = 0;
     uint32_t r_pm = 0;                      // REJ: p* of the ready query's source
+    uint64_t r_W = 0;                       // ITS: weight sum of the ready query's source
     bool s_bad = false;
 
     // Id ranges come from the queue head one claim ahead: the next range is
@@ -291,7 +294,7 @@ k_walk_persistent(GraphDev g, TableDev t, WalkDev a, unsigned long long *__restr
             if (w[i].qi == kIdle && r_qi != kIdle) {
                 w[i].qi = r_qi; w[i].code = r_code; w[i].cur = r_src; w[i].prev = -1; w[i].k = 0;
                 w[i].poff = 0; w[i].pdeg = 0; w[i].need_row = false;
-                w[i].dart = 0; w[i].pm = r_pm;
+                w[i].dart = 0; w[i].pm = r_pm; w[i].W = r_W;
                 w[i].off = r_lo; w[i].deg = kNoRows ? 1 : r_deg;
                 w[i].path.start(a.paths + (uint64_t)r_qi * a.stride);
                 w[i].path.push(r_src);
@@ -306,6 +309,7 @@ k_walk_persistent(GraphDev g, TableDev t, WalkDev a, unsigned long long *__restr
                 r_qi = s_qi; r_code = s_code; r_src = s_src;
                 if (!kNoRows) { r_lo = g.row_ptr[s_src]; r_hi = g.row_ptr[s_src + 1]; }
                 if (kRej) r_pm = t.pmax[s_src];
+                if (kIts) r_W = t.its_w[s_src];
             }
             s_qi = kIdle;
         }
@@ -406,6 +410,25 @@ k_walk_persistent(GraphDev g, TableDev t, WalkDev a, unsigned long long *__restr
                     w[i].need_row = !kAdj;
                 }
             }
+        } else if (kIts) {
+            // x uniform in [0, W) from 64 bits; the smallest i with x < prefix[i]
+            // (its_search); the slot's record then gives the next vertex, its
+            // row and its W.
+#pragma unroll
+            for (int i = 0; i < WPL; ++i) {
+                nxt[i] = -1;
+                if (w[i].qi != kIdle && w[i].deg != 0 && w[i].W != 0) {
+                    const uint64_t *__restrict__ pr = t.prefix + (uint32_t)w[i].off;
+                    const uint64_t x = scale64(r[i].r0, r[i].r1, w[i].W);
+                    const uint32_t lo = its_search(pr, (uint32_t)w[i].deg, x, ((uint64_t)r[i].r1 << 32) | r[i].r0);
+                    const uint64_t e = (uint64_t)(uint32_t)w[i].off + lo;
+                    const uint4 n0 = t.its_next[2 * e];
+                    const uint4 n1 = t.its_next[2 * e + 1];
+                    nxt[i] = (int32_t)n0.x;
+                    w[i].off = (int32_t)n0.y; w[i].deg = (int32_t)n0.z;
+                    w[i].W = (uint64_t)n1.x | ((uint64_t)n1.y << 32);
+                }
+            }
         } else if (kRej) {
             // One dart per walker per iteration: a walker whose dart misses
             // keeps its state and throws its next dart in the next iteration,
@@ -452,6 +475,7 @@ k_walk_persistent(GraphDev g, TableDev t, WalkDev a, unsigned long long *__restr
         // they are complete at the top of the next iteration.
         asm volatile("" ::"v"(s_src), "v"(r_lo), "v"(r_hi), "v"(ahead_base));
         if (kRej) asm volatile("" ::"v"(r_pm));
+        if (kIts) asm volatile("" ::"v"(r_W));
         s_bad = (uint32_t)s_src >= (uint32_t)g.n;
         r_deg = r_hi - r_lo;
         ahead_seen = __shfl(ahead_base, 0);

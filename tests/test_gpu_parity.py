@@ -215,13 +215,35 @@ def test_alias_table_rmat(rmat_dir):
     assert np.array_equal(got, _alias_expected(g, thr, alias))
 
 
+def _its_check(case):
+    """The documented ITS table: the oracle's prefix, then per slot {dst, row(dst), W(dst)}, then W[n]."""
+    g = case.g
+    t = case.dev_table("its")
+    torch.cuda.synchronize()
+    raw = t.buf.cpu().numpy()
+    prefix = oracle.its_build(g.row_ptr, g.weight)
+    assert np.array_equal(raw[:8 * g.m].view(np.uint64), prefix)
+    rp = g.row_ptr.astype(np.int64)
+    deg = np.diff(rp)
+    W = np.where(deg > 0, prefix[np.clip(rp[1:] - 1, 0, None)] if g.m else 0, 0).astype(np.uint64)
+    pb = (8 * g.m + 255) // 256 * 256
+    nb = (32 * g.m + 255) // 256 * 256
+    assert np.array_equal(raw[pb + nb:pb + nb + 8 * g.n].view(np.uint64), W), "W[n] differs"
+    rec = raw[pb:pb + 32 * g.m].view(np.uint32).reshape(-1, 8)
+    col = g.col.astype(np.int64)
+    exp = np.zeros((g.m, 8), np.uint64)
+    exp[:, 0] = col
+    exp[:, 1] = rp[col]
+    exp[:, 2] = deg[col]
+    exp[:, 4] = W[col] & np.uint64(0xFFFFFFFF)
+    exp[:, 5] = W[col] >> np.uint64(32)
+    bad = np.nonzero((rec != exp.astype(np.uint32)).any(axis=1))[0]
+    assert bad.size == 0, f"ITS records differ at edge slots {bad[:10]}"
+
+
 def test_its_table_matches_oracle(rmat_dir):
     for case in (rmat_dir, Case(_weighted_rows_graph(5, 2**32 - 1))):
-        g = case.g
-        t = case.dev_table("its")
-        torch.cuda.synchronize()
-        got = t.buf[:8 * g.m].view(torch.int64).cpu().numpy().view(np.uint64)
-        assert np.array_equal(got, oracle.its_build(g.row_ptr, g.weight))
+        _its_check(case)
 
 
 def _rej_expected(g, pmax):
@@ -301,10 +323,7 @@ def test_tables_long_rows(wmax):
     thr, alias = oracle.alias_build(g.row_ptr, g.weight)
     bad = np.nonzero((_alias_got(t, g.m) != _alias_expected(g, thr, alias)).any(axis=1))[0]
     assert bad.size == 0, f"alias entries differ at edge slots {bad[:10]}"
-    t = case.dev_table("its")
-    torch.cuda.synchronize()
-    got = t.buf[:8 * g.m].view(torch.int64).cpu().numpy().view(np.uint64)
-    assert np.array_equal(got, oracle.its_build(g.row_ptr, g.weight))
+    _its_check(case)
     _rej_check(case)
 
 
@@ -418,16 +437,18 @@ def test_autotune_picks_a_candidate_and_results_do_not_change(rmat_sym, rmat_dir
 
 @pytest.mark.parametrize("mode", [1, 0])
 @pytest.mark.parametrize("algo", ["deepwalk", "ppr"])
-def test_rej_walk_zero_weights_and_long_rows(algo, mode):
-    """REJ where rows have zero weights (dead ends), skewed weights (many
-    misses) and rows of thousands of slots."""
+@pytest.mark.parametrize("sampler", ["rej", "its", "alias"])
+def test_weighted_walk_zero_weights_and_long_rows(sampler, algo, mode):
+    """Weighted samplers where rows have zero weights (dead ends), skewed
+    weights (many REJ misses, deep ITS searches) and thousands of slots."""
     for case in (Case(_weighted_rows_graph(17, 255)), Case(_long_rows_graph(2**32 - 1, 5))):
         n = case.g.n
         src = np.concatenate([np.arange(min(n, 3000)), synth.sources(1000 + 29, n, 8)]).astype(np.int32)
         max_len = 30
-        gpu, ref = run_both(case, algo, "rej", max_len, 21 + mode, src, mode, **_args(algo))
+        gpu, ref = run_both(case, algo, sampler, max_len, 21 + mode, src, mode, **_args(algo))
         assert_same(gpu, ref, max_len)
-        assert ref.counters["rej_trials"] > ref.counters["moves"]   # darts did miss
+        if sampler == "rej":
+            assert ref.counters["rej_trials"] > ref.counters["moves"]   # darts did miss
 
 
 def test_edge_cases(rmat_sym, rmat_dir):
