@@ -294,8 +294,25 @@ def main():
                    "k": 100, "queries": nq, "vertices": g.n,
                    "distinct_end_vertices": int((counts[0] != 0).sum().item()),
                    "top_count": int(vals[0].item()), "walk_ms": round(avg_launch_ms, 4)}
-        log(f"ppr estimate: end counts {ppr_est['end_counts_ms']} ms, top-100 {ppr_est['topk_ms']} ms")
-        del bufs, counts
+        del bufs
+        # the counting walk: the same PPR walk counting end vertices, no paths written
+        counts2 = torch.zeros_like(counts)
+        t_cw = []
+        for _ in range(5):
+            counts2.zero_()
+            a, b = (torch.cuda.Event(enable_timing=True) for _ in range(2))
+            a.record(stream)
+            trw.ppr_walk_counts(G, tables.get(sampler), p, d_src, counts=counts2)
+            b.record(stream)
+            torch.cuda.synchronize()
+            t_cw.append(a.elapsed_time(b))
+        same = bool(torch.equal(counts, counts2))
+        ppr_est["counting_walk_ms"] = round(float(np.median(t_cw)), 4)
+        ppr_est["counting_walk_steps_per_s"] = round(moves / (ppr_est["counting_walk_ms"] * 1e-3), 1)
+        ppr_est["counting_walk_counts_equal"] = same
+        log(f"ppr estimate: end counts {ppr_est['end_counts_ms']} ms, top-100 {ppr_est['topk_ms']} ms; "
+            f"counting walk {ppr_est['counting_walk_ms']} ms (counts equal: {same})")
+        del counts, counts2
 
     # The same walk written as a walk program (the step-centric programming
     # model, compiled at run time): what the generic framework costs.

@@ -332,6 +332,25 @@ trw_status trw_ppr_end_counts(trw_graph g, const int32_t *d_paths, uint64_t path
                               uint64_t group, uint32_t *d_counts, uint64_t counts_len,
                               unsigned long long *d_skipped, trw_stream_t stream);
 
+/*
+ * PPR walks that count end vertices instead of writing paths: the same walk
+ * as trw_walk (PPR, persistent schedule, same random contract and tuning),
+ * but query i, when it ends, adds one to d_counts[(i / group) * n + its last
+ * vertex] (group 0: one row), the counts trw_ppr_end_counts would give for
+ * trw_walk's outputs.  No path is stored, so the walk writes no path rows.
+ *   table, p, d_sources, nq, qid_base, tuning   as trw_walk (p->algo = PPR)
+ *   d_counts    uint32, counts_len >= groups * n entries; added to, not cleared
+ *   d_lengths, d_status   as trw_walk (bad sources: BAD_SOURCE, not counted)
+ *   d_ws        trw_walk_workspace_bytes for TRW_M_PERSISTENT, 256-byte aligned
+ * Errors as trw_walk; TRW_E_UNSUPPORTED unless p->algo is PPR; TRW_E_INVALID
+ * for a NULL d_counts or counts_len too small.
+ */
+trw_status trw_ppr_walk_counts(trw_graph g, trw_table table, const trw_walk_params *p,
+                               const int32_t *d_sources, uint64_t nq, uint64_t qid_base, uint64_t group,
+                               uint32_t *d_counts, uint64_t counts_len, uint32_t *d_lengths,
+                               uint8_t *d_status, const trw_tuning *tuning, void *d_ws, size_t ws_bytes,
+                               trw_stream_t stream);
+
 /* Workspace bytes of trw_topk: 1280 + 8*k.  k <= min(n, 4096). */
 trw_status trw_topk_workspace_bytes(uint64_t n, uint32_t k, size_t *bytes);
 

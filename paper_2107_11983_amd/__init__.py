@@ -22,7 +22,7 @@ from ._abi import (TRW_A_DEEPWALK, TRW_A_METAPATH, TRW_A_NODE2VEC, TRW_A_PPR, TR
 
 __all__ = ["Graph", "Table", "walk", "make_params", "workspace_bytes", "default_tuning", "autotune",
            "TrwError", "ALGOS", "SAMPLERS", "Program", "check_program", "programs", "Server", "ppr_end_counts",
-           "topk"]
+           "ppr_walk_counts", "topk"]
 
 ALGOS = {"deepwalk": TRW_A_DEEPWALK, "ppr": TRW_A_PPR, "node2vec": TRW_A_NODE2VEC, "metapath": TRW_A_METAPATH}
 SAMPLERS = {"naive": TRW_S_NAIVE, "alias": TRW_S_ALIAS, "its": TRW_S_ITS, "orej": TRW_S_OREJ, "rej": TRW_S_REJ}
@@ -270,6 +270,28 @@ def ppr_end_counts(graph: Graph, paths: torch.Tensor, lengths: torch.Tensor, sta
     check(_abi.trw_ppr_end_counts(graph.handle, _dptr(paths), paths.stride(0), _dptr(lengths), _dptr(status), nq,
                                   max(group, 0), _dptr(counts), counts.numel(), _dptr(skipped), _stream_ptr(stream)))
     return counts, skipped
+
+
+def ppr_walk_counts(graph: Graph, table: Optional[Table], p: trw_walk_params, sources: torch.Tensor, group: int = 0,
+                    qid_base: int = 0, counts: Optional[torch.Tensor] = None, tuning: Optional[trw_tuning] = None,
+                    stream=None):
+    """PPR walks that count their end vertices instead of writing paths.
+
+    Returns (counts [groups, n] as in ppr_end_counts, lengths, status); counts are added to when given.
+    """
+    nq = int(sources.numel())
+    groups = 1 if group <= 0 else max(1, -(-nq // group))
+    if counts is None:
+        counts = torch.zeros((groups, graph.n), dtype=torch.int32, device=graph.device)
+    lengths = torch.empty(max(nq, 1), dtype=torch.int32, device=graph.device)
+    status = torch.empty(max(nq, 1), dtype=torch.uint8, device=graph.device)
+    ws = torch.empty(max(workspace_bytes(graph, p, nq, TRW_M_PERSISTENT), 256), dtype=torch.uint8,
+                     device=graph.device)
+    check(_abi.trw_ppr_walk_counts(graph.handle, table.handle if table is not None else None, ctypes.byref(p),
+                                   _dptr(sources), nq, qid_base, max(group, 0), _dptr(counts), counts.numel(),
+                                   _dptr(lengths), _dptr(status), ctypes.byref(tuning) if tuning is not None else None,
+                                   _dptr(ws), ws.numel(), _stream_ptr(stream)))
+    return counts, lengths[:nq], status[:nq]
 
 
 def topk(counts: torch.Tensor, k: int, stream=None):

@@ -130,6 +130,8 @@ _SIGS = {
     "trw_program_destroy": (_st, [_P]),
     "trw_ppr_end_counts": (_st, [_P, _P, _u64, _P, _P, _u64, _u64, _P, _u64, _P, _P]),
     "trw_topk_workspace_bytes": (_st, [_u64, _u32, ctypes.POINTER(_sz)]),
+    "trw_ppr_walk_counts": (_st, [_P, _P, ctypes.POINTER(trw_walk_params), _P, _u64, _u64, _u64, _P, _u64, _P, _P,
+                                  ctypes.POINTER(trw_tuning), _P, _sz, _P]),
     "trw_topk": (_st, [_P, _u64, _u32, _P, _P, _P, _sz, _P]),
     # measurement probe (include/trw_probe.h)
     "trw_probe_fill": (ctypes.c_int, [_P, _u64, _u32, _P]),
@@ -189,6 +191,7 @@ trw_program_destroy = lib.trw_program_destroy
 trw_ppr_end_counts = lib.trw_ppr_end_counts
 trw_topk_workspace_bytes = lib.trw_topk_workspace_bytes
 trw_topk = lib.trw_topk
+trw_ppr_walk_counts = lib.trw_ppr_walk_counts
 trw_edge_index_bytes = lib.trw_edge_index_bytes
 trw_edge_index_build = lib.trw_edge_index_build
 trw_probe_fill = lib.trw_probe_fill

@@ -352,12 +352,26 @@ trw_status trw_default_tuning(trw_graph g, const trw_walk_params *p, uint32_t mo
     return TRW_OK;
 }
 
-trw_status trw_walk(trw_graph g, trw_table table, const trw_walk_params *p, const int32_t *d_sources,
-                    uint64_t nq, uint64_t qid_base, int32_t *d_paths, uint64_t path_stride,
-                    uint32_t *d_lengths, uint8_t *d_status, uint32_t mode, const trw_tuning *tuning,
-                    void *d_ws, size_t ws_bytes, trw_stream_t stream) {
+}  // extern "C"
+
+namespace {
+
+// trw_walk, and with d_counts the PPR estimate walk (no paths: each query's
+// end vertex is counted instead).
+trw_status walk_impl(trw_graph g, trw_table table, const trw_walk_params *p, const int32_t *d_sources,
+                     uint64_t nq, uint64_t qid_base, int32_t *d_paths, uint64_t path_stride,
+                     uint32_t *d_lengths, uint8_t *d_status, uint32_t mode, const trw_tuning *tuning,
+                     void *d_ws, size_t ws_bytes, trw_stream_t stream, uint32_t *d_counts, uint64_t group,
+                     uint64_t counts_len) {
     trw_status st = check_params(g, p);
     if (st != TRW_OK) return st;
+    const bool counts = d_counts != nullptr;
+    if (counts) {
+        if (p->algo != TRW_A_PPR) return fail(TRW_E_UNSUPPORTED, "end-vertex counting walks are PPR walks");
+        const uint64_t groups = group ? (nq + group - 1) / group : 1;
+        if (counts_len < std::max<uint64_t>(groups, 1) * (uint64_t)g->dev.n)
+            return fail(TRW_E_INVALID, "counts holds fewer than groups * n entries");
+    }
     if (mode > TRW_M_PERSISTENT) return fail(TRW_E_INVALID, "unknown mode");
     if (nq >= (uint64_t(1) << 32)) return fail(TRW_E_INVALID, "nq must be < 2^32");
     const bool needs_table = (p->algo == TRW_A_DEEPWALK || p->algo == TRW_A_PPR) &&
@@ -380,9 +394,9 @@ trw_status trw_walk(trw_graph g, trw_table table, const trw_walk_params *p, cons
         for (uint32_t i = 0; i < p->schema_len; ++i)
             if (p->schema[i] >= table->nlab) return fail(TRW_E_INVALID, "schema label >= label index n_labels");
     }
-    if (path_stride < (uint64_t)p->max_len + 1) return fail(TRW_E_INVALID, "path_stride < max_len + 1");
+    if (!counts && path_stride < (uint64_t)p->max_len + 1) return fail(TRW_E_INVALID, "path_stride < max_len + 1");
     if (nq == 0) return TRW_OK;
-    if (!d_sources || !d_paths || !d_lengths || !d_status)
+    if (!d_sources || (!counts && !d_paths) || !d_lengths || !d_status)
         return fail(TRW_E_INVALID, "sources / paths / lengths / status is NULL");
     const size_t need = walk_workspace_bytes(mode, nq, p->max_len);
     if (!d_ws || ws_bytes < need || (reinterpret_cast<uintptr_t>(d_ws) & 255))
@@ -405,6 +419,8 @@ trw_status trw_walk(trw_graph g, trw_table table, const trw_walk_params *p, cons
     w.stride = path_stride;
     w.lengths = d_lengths;
     w.status = d_status;
+    w.end_counts = d_counts;
+    w.end_group = group;
     TableDev t{nullptr, nullptr, nullptr, nullptr, 0, nullptr};
     if (adjacency) t.adj = static_cast<const uint4 *>(table->buf);
     if (adjacency && table->sampler == kEdgeIndexKind) {
@@ -433,10 +449,33 @@ trw_status trw_walk(trw_graph g, trw_table table, const trw_walk_params *p, cons
         t.nlab = table->nlab;
     }
     const Tuning tu = resolve_tuning(p, mode, tuning, label_index);
-    hipError_t e = launch_walk(g->dev, t, p->algo, p->sampler, w, mode, tu, device_info(), d_ws, ws_bytes,
-                               static_cast<hipStream_t>(stream));
+    hipError_t e = counts ? launch_ppr_counts(g->dev, t, p->sampler, w, tu, device_info(), d_ws,
+                                              static_cast<hipStream_t>(stream))
+                          : launch_walk(g->dev, t, p->algo, p->sampler, w, mode, tu, device_info(), d_ws, ws_bytes,
+                                        static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return device_fail(e, "walk launch");
     return TRW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+trw_status trw_walk(trw_graph g, trw_table table, const trw_walk_params *p, const int32_t *d_sources,
+                    uint64_t nq, uint64_t qid_base, int32_t *d_paths, uint64_t path_stride,
+                    uint32_t *d_lengths, uint8_t *d_status, uint32_t mode, const trw_tuning *tuning,
+                    void *d_ws, size_t ws_bytes, trw_stream_t stream) {
+    return walk_impl(g, table, p, d_sources, nq, qid_base, d_paths, path_stride, d_lengths, d_status, mode, tuning,
+                     d_ws, ws_bytes, stream, nullptr, 0, 0);
+}
+
+trw_status trw_ppr_walk_counts(trw_graph g, trw_table table, const trw_walk_params *p, const int32_t *d_sources,
+                               uint64_t nq, uint64_t qid_base, uint64_t group, uint32_t *d_counts,
+                               uint64_t counts_len, uint32_t *d_lengths, uint8_t *d_status,
+                               const trw_tuning *tuning, void *d_ws, size_t ws_bytes, trw_stream_t stream) {
+    if (!d_counts) return fail(TRW_E_INVALID, "counts is NULL");
+    return walk_impl(g, table, p, d_sources, nq, qid_base, nullptr, 0, d_lengths, d_status, TRW_M_PERSISTENT,
+                     tuning, d_ws, ws_bytes, stream, d_counts, group, counts_len);
 }
 
 trw_status trw_autotune(trw_graph g, trw_table table, const trw_walk_params *p, const int32_t *d_sources,

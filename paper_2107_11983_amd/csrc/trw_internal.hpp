@@ -74,6 +74,8 @@ struct WalkDev {
     uint64_t stride;
     uint32_t *lengths;
     uint8_t *status;
+    uint32_t *end_counts;     // PPR estimate walks: counts[(qi / end_group) * n + end vertex]
+    uint64_t end_group;       // queries per counts row (0: one row)
 };
 
 enum : uint8_t { ST_LENGTH = 1, ST_STOPPED = 2, ST_DEAD_END = 3, ST_BAD_SOURCE = 4 };
@@ -122,6 +124,9 @@ size_t walk_workspace_bytes(uint32_t mode, uint64_t nq, uint32_t max_len);
 hipError_t launch_walk(const GraphDev &g, const TableDev &t, uint32_t algo, uint32_t sampler,
                        const WalkDev &w, uint32_t mode, const Tuning &tu, const DeviceInfo &di,
                        void *d_ws, size_t ws_bytes, hipStream_t s);
+// PPR in the persistent schedule, counting end vertices instead of writing paths.
+hipError_t launch_ppr_counts(const GraphDev &g, const TableDev &t, uint32_t sampler, const WalkDev &w,
+                             const Tuning &tu, const DeviceInfo &di, void *ws, hipStream_t s);
 
 DeviceInfo device_info();
 void set_error(const std::string &msg);

@@ -214,7 +214,9 @@ struct Walker {
 
 constexpr int32_t kMissed = -2;   // REJ: this iteration's dart missed; no move
 
-template <uint32_t ALGO, uint32_t SMP, int WPL>
+// COUNTS: instead of writing paths, a walk that ends adds one to
+// a.end_counts[group of its query][its last vertex] (PPR's estimate).
+template <uint32_t ALGO, uint32_t SMP, int WPL, bool COUNTS = false>
 __global__ void __launch_bounds__(256)
 k_walk_persistent(GraphDev g, TableDev t, WalkDev a, unsigned long long *__restrict__ queue_head,
                   uint32_t chunk, uint32_t coop, uint32_t n_slots) {
@@ -296,8 +298,10 @@ k_walk_persistent(GraphDev g, TableDev t, WalkDev a, unsigned long long *__restr
                 w[i].poff = 0; w[i].pdeg = 0; w[i].need_row = false;
                 w[i].dart = 0; w[i].pm = r_pm; w[i].W = r_W;
                 w[i].off = r_lo; w[i].deg = kNoRows ? 1 : r_deg;
-                w[i].path.start(a.paths + (uint64_t)r_qi * a.stride);
-                w[i].path.push(r_src);
+                if (!COUNTS) {
+                    w[i].path.start(a.paths + (uint64_t)r_qi * a.stride);
+                    w[i].path.push(r_src);
+                }
                 r_qi = kIdle;
             }
         }
@@ -490,7 +494,7 @@ k_walk_persistent(GraphDev g, TableDev t, WalkDev a, unsigned long long *__restr
             if (nxt[i] < 0) {
                 st = ST_DEAD_END;
             } else {
-                w[i].path.push(nxt[i]);
+                if (!COUNTS) w[i].path.push(nxt[i]);
                 w[i].prev = w[i].cur;
                 w[i].cur = nxt[i];
                 w[i].k += 1;
@@ -498,7 +502,12 @@ k_walk_persistent(GraphDev g, TableDev t, WalkDev a, unsigned long long *__restr
                 else if (w[i].k == a.max_len) st = ST_LENGTH;
             }
             if (st) {
-                w[i].path.finish(a.paths + ((uint64_t)w[i].qi + 1) * a.stride);
+                if (COUNTS) {
+                    const uint64_t row = a.end_group ? (uint64_t)w[i].qi / a.end_group : 0;
+                    atomicAdd(&a.end_counts[row * (uint64_t)g.n + (uint32_t)w[i].cur], 1u);
+                } else {
+                    w[i].path.finish(a.paths + ((uint64_t)w[i].qi + 1) * a.stride);
+                }
                 record(w[i].code, w[i].qi, w[i].k, st);
                 w[i].qi = kIdle;
             }
@@ -674,7 +683,7 @@ __global__ void __launch_bounds__(256) k_bsp_step(GraphDev g, TableDev t, WalkDe
 constexpr size_t kAlign = 256;
 inline size_t round_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-template <uint32_t ALGO, uint32_t SMP>
+template <uint32_t ALGO, uint32_t SMP, bool COUNTS = false>
 hipError_t run_persistent(const GraphDev &g, const TableDev &t, const WalkDev &w, const Tuning &tu,
                           const DeviceInfo &di, void *ws, hipStream_t s) {
     auto *head = reinterpret_cast<unsigned long long *>(ws);
@@ -699,15 +708,15 @@ hipError_t run_persistent(const GraphDev &g, const TableDev &t, const WalkDev &w
     const size_t lds = (size_t)n_slots * waves * sizeof(StageSlot);
     switch (tu.walkers_per_lane) {
         case 2:
-            hipLaunchKernelGGL((k_walk_persistent<ALGO, SMP, 2>), dim3(blocks), dim3(threads), lds, s, g, t, w, head,
+            hipLaunchKernelGGL((k_walk_persistent<ALGO, SMP, 2, COUNTS>), dim3(blocks), dim3(threads), lds, s, g, t, w, head,
                                tu.queue_chunk, tu.coop_degree, n_slots);
             break;
         case 4:
-            hipLaunchKernelGGL((k_walk_persistent<ALGO, SMP, 4>), dim3(blocks), dim3(threads), lds, s, g, t, w, head,
+            hipLaunchKernelGGL((k_walk_persistent<ALGO, SMP, 4, COUNTS>), dim3(blocks), dim3(threads), lds, s, g, t, w, head,
                                tu.queue_chunk, tu.coop_degree, n_slots);
             break;
         default:
-            hipLaunchKernelGGL((k_walk_persistent<ALGO, SMP, 1>), dim3(blocks), dim3(threads), lds, s, g, t, w, head,
+            hipLaunchKernelGGL((k_walk_persistent<ALGO, SMP, 1, COUNTS>), dim3(blocks), dim3(threads), lds, s, g, t, w, head,
                                tu.queue_chunk, tu.coop_degree, n_slots);
     }
     return hipGetLastError();
@@ -746,6 +755,19 @@ hipError_t run(const GraphDev &g, const TableDev &t, const WalkDev &w, uint32_t 
 }
 
 }  // namespace
+
+hipError_t launch_ppr_counts(const GraphDev &g, const TableDev &t, uint32_t sampler, const WalkDev &w,
+                             const Tuning &tu, const DeviceInfo &di, void *ws, hipStream_t s) {
+    if (w.nq == 0) return hipSuccess;
+    switch (sampler) {
+        case SMP_NAIVE:
+            if (t.adj) return run_persistent<ALG_PPR, SMP_NAIVE_ADJ, true>(g, t, w, tu, di, ws, s);
+            return run_persistent<ALG_PPR, SMP_NAIVE, true>(g, t, w, tu, di, ws, s);
+        case SMP_ALIAS: return run_persistent<ALG_PPR, SMP_ALIAS, true>(g, t, w, tu, di, ws, s);
+        case SMP_REJ: return run_persistent<ALG_PPR, SMP_REJ, true>(g, t, w, tu, di, ws, s);
+        default: return run_persistent<ALG_PPR, SMP_ITS, true>(g, t, w, tu, di, ws, s);
+    }
+}
 
 size_t walk_workspace_bytes(uint32_t mode, uint64_t nq, uint32_t max_len) {
     if (mode == TRW_M_PERSISTENT) return kAlign;

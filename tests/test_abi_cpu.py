@@ -176,3 +176,19 @@ def test_ppr_estimate_argument_checks(abi):
     assert ec(2**32, 0, 100) == abi.TRW_E_INVALID
     assert ec(0, 0, 100) == abi.TRW_OK                   # nothing to do
     abi.trw_graph_destroy(g)
+
+
+def test_ppr_walk_counts_argument_checks(abi):
+    g = _fake_graph(abi, weights=True)                # n = 100
+    fake = ctypes.c_void_p(0x1000)
+    ws = ctypes.c_void_p(0x10000)
+    def pc(p, counts=fake, counts_len=100, group=0, nq=5):
+        return abi.trw_ppr_walk_counts(g, None, ctypes.byref(p), fake, nq, 0, group, counts, counts_len, fake,
+                                       fake, None, ws, 1 << 20, None)
+    assert pc(_params(abi, "deepwalk", "naive")) == abi.TRW_E_UNSUPPORTED
+    assert pc(_params(abi, "ppr", "naive"), counts=None) == abi.TRW_E_INVALID
+    assert pc(_params(abi, "ppr", "naive"), counts_len=99) == abi.TRW_E_INVALID
+    assert pc(_params(abi, "ppr", "naive"), group=2, counts_len=200) == abi.TRW_E_INVALID   # 3 groups
+    assert pc(_params(abi, "ppr", "alias")) == abi.TRW_E_INVALID                            # no table
+    assert pc(_params(abi, "ppr", "naive"), nq=0) == abi.TRW_OK
+    abi.trw_graph_destroy(g)

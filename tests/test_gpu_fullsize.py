@@ -3,7 +3,8 @@ times (persistent schedule, default tuning, the same tables and indexes).
 
 * PPR on R-MAT 2^22 (10^7 queries): every query compared with the oracle,
   paths included, in chunks of 10^6; the end counts of five groups of
-  2 M queries and their top 4096 compared whole; the same batch with REJ
+  2 M queries and their top 4096 compared whole, also from the counting
+  walk that writes no paths; the same batch with REJ
   compared on a seeded sample.
 * Node2Vec and MetaPath on R-MAT 2^24 (one query per vertex): a seeded sample
   of queries compared with the oracle, which walks exactly those query ids;
@@ -142,6 +143,13 @@ def test_ppr_rmat22_every_query():
         assert np.array_equal(ids.cpu().numpy(), eid) and np.array_equal(vals.cpu().numpy().view(np.uint32), ev)
     log("  ppr-rmat22 end counts and top-4096 identical")
     del counts, P, L, S
+    # the counting walk (no paths) gives the same counts, lengths and status
+    counts, L2, S2 = trw.ppr_walk_counts(G, alias, p, torch.from_numpy(src).cuda(), group=group)
+    torch.cuda.synchronize()
+    assert np.array_equal(counts.cpu().numpy().view(np.uint32), exp_counts), "counting walk differs"
+    assert np.array_equal(L2.cpu().numpy(), Lh) and np.array_equal(S2.cpu().numpy(), Sh)
+    log("  ppr-rmat22 counting walk identical")
+    del counts, L2, S2
     # REJ on the same batch: a seeded sample of queries against the oracle
     rej = G.table("rej")
     pr = _params(wl, "rej")

@@ -136,3 +136,52 @@ def test_topk_rejects_bad_arguments():
         trw.topk(big, 4097)
     ids, vals = trw.topk(d, 0)
     assert ids.numel() == 0 and vals.numel() == 0
+
+
+@pytest.mark.parametrize("sampler,index", [("alias", None), ("its", None), ("rej", None), ("naive", None),
+                                           ("naive", "adj")])
+@pytest.mark.parametrize("group,wpl", [(0, 0), (1000, 2), (7, 4), (0, 1)])
+def test_ppr_walk_counts_match_oracle(rmat_dir, sampler, index, group, wpl):
+    """Counting walks (no paths) give the oracle's end counts, lengths and status."""
+    g = rmat_dir
+    G = trw.Graph(g.row_ptr, g.col, g.weight)
+    table = G.adjacency_index() if index == "adj" else (G.table(sampler) if sampler != "naive" else None)
+    n = g.n
+    src = np.concatenate([np.repeat(np.array([5, 900], np.int32), 3000), synth.sources(4099, n, 43),
+                          np.array([-5, n + 1], np.int32)])
+    stop = oracle.stop_q32(0.2)
+    p = trw.make_params("ppr", sampler, 256, 321, stop_q32=stop)
+    tu = trw.make_tuning(walkers_per_lane=wpl) if wpl else None
+    log(f"  counting walk {sampler}/{index} group={group} wpl={wpl} nq={len(src)}")
+    counts, L, S = trw.ppr_walk_counts(G, table, p, torch.from_numpy(src).cuda(), group=group, qid_base=11,
+                                       tuning=tu)
+    torch.cuda.synchronize()
+    kw = {}
+    if sampler == "alias":
+        kw = dict(zip(("thr", "alias"), oracle.alias_build(g.row_ptr, g.weight)))
+    elif sampler == "its":
+        kw = dict(prefix=oracle.its_build(g.row_ptr, g.weight))
+    elif sampler == "rej":
+        kw = dict(weight=g.weight, pmax=oracle.rej_build(g.row_ptr, g.weight))
+    ref = oracle.walk(g.row_ptr, g.col, oracle.WalkParams(oracle.PPR, oracle.SAMPLERS[sampler], 256, 321,
+                                                          stop_q32=stop), src, qid_base=11, **kw)
+    exp, skipped = oracle.end_counts(n, ref.paths, ref.lengths, ref.status, group=group)
+    assert skipped == 2
+    assert np.array_equal(L.cpu().numpy().view(np.uint32), ref.lengths)
+    assert np.array_equal(S.cpu().numpy(), ref.status)
+    assert np.array_equal(_u32(counts).reshape(exp.shape), exp)
+    G.close()
+
+
+def test_ppr_walk_counts_rejects_bad_arguments(rmat_dir):
+    g = rmat_dir
+    G = trw.Graph(g.row_ptr, g.col, g.weight)
+    src = torch.zeros(10, dtype=torch.int32, device="cuda")
+    with pytest.raises(trw.TrwError):           # not a PPR walk
+        trw.ppr_walk_counts(G, None, trw.make_params("deepwalk", "naive", 10, 1), src)
+    with pytest.raises(trw.TrwError):           # counts too short for 4 groups
+        trw.ppr_walk_counts(G, None, trw.make_params("ppr", "naive", 10, 1), src, group=3,
+                            counts=torch.zeros((3, g.n), dtype=torch.int32, device="cuda"))
+    with pytest.raises(trw.TrwError):           # ALIAS without its table
+        trw.ppr_walk_counts(G, None, trw.make_params("ppr", "alias", 10, 1), src)
+    G.close()
