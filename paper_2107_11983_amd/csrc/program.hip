@@ -184,7 +184,10 @@ trw_status trw_program_walk(trw_program prog, trw_graph g, trw_table table, cons
     hipLaunchKernelGGL(k_zero_head, dim3(1), dim3(1), 0, s, a.head);
     const DeviceInfo di = device_info();
     const uint64_t waves = (nq + 63) / 64;
-    const uint32_t blocks = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((waves + 3) / 4, (uint64_t)di.num_cus * 8));
+    // Launch shape measured on MI355X: static programs (one random read per
+    // move) peak at 2 workgroups per CU, dynamic ones at full occupancy.
+    const uint64_t per_cu = prog->kind <= trw_prog::STATIC_ITS ? 2 : 8;
+    const uint32_t blocks = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((waves + 3) / 4, (uint64_t)di.num_cus * per_cu));
     void *args[] = {&a};
     hipError_t e = hipGetLastError();
     if (e == hipSuccess)

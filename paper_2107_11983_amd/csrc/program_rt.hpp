@@ -39,6 +39,7 @@ namespace trw_prog {
 
 using trw::alias_pick;
 using trw::eset_has;
+using trw::its_search;
 using trw::lane_id;
 using trw::PathBuf;
 using trw::philox;
@@ -130,12 +131,7 @@ __device__ __forceinline__ int32_t program_move(const P &prog, const Args &a, co
         const uint64_t W = pr[w.deg - 1];
         if (W == 0) return -1;
         const uint64_t x = scale64(r.r0, r.r1, W);
-        uint32_t lo = 0, hi = w.deg - 1;
-        while (lo < hi) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (x < pr[mid]) hi = mid; else lo = mid + 1;
-        }
-        nxt = g.col[w.off + lo];
+        nxt = g.col[w.off + its_search(pr, w.deg, x, ((uint64_t)r.r1 << 32) | r.r0)];
     } else if (P::kind == DYNAMIC_REJ) {
         Rand4 rr = r;
         for (uint32_t t = 0;; ++t) {

@@ -54,6 +54,53 @@ __device__ __forceinline__ uint64_t scale64(uint32_t lo, uint32_t hi, uint64_t W
     return __umul64hi(r, W);
 }
 
+// ---------------------------------------------------------------------------
+// ITS search: the smallest i in [0, d) with x < p[i], where p is a row's
+// non-decreasing inclusive prefix (p[d-1] = W > x) and x = high half of
+// r64 * W.  The same random fraction scaled to d, g = high half of r64 * d,
+// is where a row whose prefix grows evenly has its answer, so the search
+// probes g first, gallops outwards (1, 2, 4, ... slots) until the answer is
+// bracketed, and finishes by bisection.  With near-uniform weights the
+// answer is a few slots from g and the probes share one or two cache lines;
+// with skewed weights the gallop costs at most about twice a plain binary
+// search.  Any correct search returns the same slot.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t its_search(const uint64_t *__restrict__ p, uint32_t d, uint64_t x,
+                                               uint64_t r64) {
+    const uint32_t g = (uint32_t)__umul64hi(r64, (uint64_t)d);   // < d
+    uint32_t lo, hi;                                              // the answer lies in [lo, hi]
+    if (x < p[g]) {
+        hi = g;
+        lo = 0;
+        for (uint32_t step = 1; step <= hi; step <<= 1) {
+            const uint32_t j = hi - step;
+            if (x < p[j]) {
+                hi = j;
+            } else {
+                lo = j + 1;
+                break;
+            }
+        }
+    } else {
+        lo = g + 1;
+        hi = d - 1;
+        for (uint32_t step = 1;; step <<= 1) {
+            const uint32_t j = lo + step - 1;
+            if (j >= d - 1) break;
+            if (x < p[j]) {
+                hi = j;
+                break;
+            }
+            lo = j + 1;
+        }
+    }
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (x < p[mid]) hi = mid; else lo = mid + 1;
+    }
+    return lo;
+}
+
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
 // Number of set bits of `mask` below this lane.
