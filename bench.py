@@ -314,6 +314,45 @@ def main():
             f"counting walk {ppr_est['counting_walk_ms']} ms (counts equal: {same})")
         del counts, counts2
 
+    # Streamed output: the same batch in chunks, packed on the device and copied
+    # by DMA into pinned host buffers while the next chunk walks (the chunk
+    # function does nothing, so this is the PCIe-inclusive rate of the path).
+    streamed = None
+    if wl.algo == "ppr" and not args.no_variants:
+        import ctypes
+        p = params(sampler)
+        chunk = 1 << 21
+        dbytes, hbytes = ctypes.c_size_t(0), ctypes.c_size_t(0)
+        trw.check(trw._abi.trw_walk_stream_bytes(G.handle, ctypes.byref(p), chunk, ctypes.byref(dbytes),
+                                                 ctypes.byref(hbytes)))
+        dkeep, dws = trw._aligned(int(dbytes.value), device=dev)
+        hkeep, hbuf = trw._aligned(int(hbytes.value), pin=True)
+        got = {"entries": 0}
+
+        def _count(_u, cp):
+            c = cp.contents
+            got["entries"] += int(ctypes.cast(c.offsets, ctypes.POINTER(ctypes.c_uint64))[c.nq])
+            return 0
+        cb = trw._abi.TRW_CHUNK_FN(_count)
+        walls = []
+        for rep in range(3):
+            got["entries"] = 0
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            trw.check(trw._abi.trw_walk_stream(G.handle, tables[sampler].handle if sampler in tables else None,
+                                               ctypes.byref(p), ctypes.c_void_p(d_src.data_ptr()), nq, 0, chunk, None,
+                                               ctypes.c_void_p(dws.data_ptr()), dws.numel(),
+                                               ctypes.c_void_p(hbuf.data_ptr()), hbuf.numel(), cb, None,
+                                               ctypes.c_void_p(stream.cuda_stream)))
+            walls.append(time.perf_counter() - t0)
+        w = float(np.median(walls[1:]))
+        streamed = {"chunk_queries": chunk, "ms_per_batch": round(1e3 * w, 3),
+                    "steps_per_s_pcie_inclusive": round(moves / w, 1), "entries_to_host": got["entries"],
+                    "bytes_to_host": got["entries"] * 4 + nq * 13}
+        log(f"streamed to host: {streamed['ms_per_batch']} ms per batch, "
+            f"{streamed['steps_per_s_pcie_inclusive']:.4g} steps/s PCIe-inclusive")
+        del dkeep, dws, hkeep, hbuf
+
     # The same walk written as a walk program (the step-centric programming
     # model, compiled at run time): what the generic framework costs.
     if not args.no_variants and not args.profile_pass:
@@ -393,6 +432,7 @@ def main():
         "autotuned": autotuned,
         "variants": variants,
         "ppr_estimate": ppr_est,
+        "streamed_to_host": streamed,
         "gather_ceiling": gather,
     }
     print(json.dumps(out), flush=True)

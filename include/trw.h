@@ -309,6 +309,50 @@ trw_status trw_autotune(trw_graph g, trw_table table, const trw_walk_params *p,
                         trw_stream_t stream, trw_tuning *out, float *best_ms);
 
 /* ------------------------------------------------------------------------ */
+/* Streamed output (Implementation details, input and output: the engine     */
+/* fills one buffer while the other is written out).  The batch runs in      */
+/* chunks; each chunk's paths are packed on the device, copied by DMA into   */
+/* one of two pinned host buffers and handed to the caller while the next    */
+/* chunk walks, so output never needs nq * (max_len + 1) entries of memory.  */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    uint64_t qid_base;         /* id of the chunk's first query */
+    uint32_t nq;               /* queries in the chunk */
+    uint32_t reserved;
+    const uint32_t *lengths;   /* [nq] moves made */
+    const uint8_t *status;     /* [nq] trw_walk_status */
+    const uint64_t *offsets;   /* [nq + 1]: query i's path is entries[offsets[i] .. offsets[i+1]) */
+    const int32_t *entries;    /* packed paths (source first); a bad source has an empty path */
+} trw_chunk;
+
+/* Called on the calling thread once per chunk, in order; the chunk's arrays
+ * are valid until it returns.  Nonzero return: stop the stream. */
+typedef int (*trw_chunk_fn)(void *user, const trw_chunk *chunk);
+
+/* Device workspace and pinned host bytes trw_walk_stream needs for chunks of
+ * chunk_queries queries (two chunk sets each, plus the walk's workspace). */
+trw_status trw_walk_stream_bytes(trw_graph g, const trw_walk_params *p, uint32_t chunk_queries,
+                                 size_t *device_bytes, size_t *host_bytes);
+
+/*
+ * Run nq queries like trw_walk (persistent schedule, query i has id
+ * qid_base + i, the same paths), chunk_queries at a time, and call fn for
+ * each chunk with its packed output in host memory.  Synchronous: returns
+ * when every chunk was delivered, fn stopped the stream (TRW_E_CANCELLED), or
+ * a device error occurred; nothing is in flight on the buffers on return.
+ *   d_ws        device workspace, >= device_bytes, 256-byte aligned
+ *   h_pinned    host memory from hipHostMalloc (pinned), >= host_bytes,
+ *               256-byte aligned
+ * The walk and packing run on `stream`; the copies run on a stream of the
+ * library's own.  Errors as trw_walk, and TRW_E_INVALID for chunk_queries 0,
+ * a NULL fn or a short or misaligned buffer.
+ */
+trw_status trw_walk_stream(trw_graph g, trw_table table, const trw_walk_params *p,
+                           const int32_t *d_sources, uint64_t nq, uint64_t qid_base, uint32_t chunk_queries,
+                           const trw_tuning *tuning, void *d_ws, size_t d_ws_bytes, void *h_pinned,
+                           size_t h_bytes, trw_chunk_fn fn, void *user, trw_stream_t stream);
+
+/* ------------------------------------------------------------------------ */
 /* PPR estimate (Random Walk based Algorithms, PPR): the score of vertex v   */
 /* for a source is the share of the source's queries whose walk ends at v;   */
 /* the highest-scoring vertices are the answer.                              */

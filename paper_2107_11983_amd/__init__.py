@@ -22,7 +22,7 @@ from ._abi import (TRW_A_DEEPWALK, TRW_A_METAPATH, TRW_A_NODE2VEC, TRW_A_PPR, TR
 
 __all__ = ["Graph", "Table", "walk", "make_params", "workspace_bytes", "default_tuning", "autotune",
            "TrwError", "ALGOS", "SAMPLERS", "Program", "check_program", "programs", "Server", "ppr_end_counts",
-           "ppr_walk_counts", "topk"]
+           "ppr_walk_counts", "topk", "walk_stream"]
 
 ALGOS = {"deepwalk": TRW_A_DEEPWALK, "ppr": TRW_A_PPR, "node2vec": TRW_A_NODE2VEC, "metapath": TRW_A_METAPATH}
 SAMPLERS = {"naive": TRW_S_NAIVE, "alias": TRW_S_ALIAS, "its": TRW_S_ITS, "orej": TRW_S_OREJ, "rej": TRW_S_REJ}
@@ -292,6 +292,61 @@ def ppr_walk_counts(graph: Graph, table: Optional[Table], p: trw_walk_params, so
                                    _dptr(lengths), _dptr(status), ctypes.byref(tuning) if tuning is not None else None,
                                    _dptr(ws), ws.numel(), _stream_ptr(stream)))
     return counts, lengths[:nq], status[:nq]
+
+
+def _aligned(nbytes: int, device=None, pin: bool = False):
+    """A uint8 tensor of at least nbytes whose storage starts on 256 bytes (and the tensor kept alive)."""
+    t = torch.empty(nbytes + 256, dtype=torch.uint8, device=device, pin_memory=pin)
+    off = (-t.data_ptr()) % 256
+    return t, t[off:off + nbytes]
+
+
+def walk_stream(graph: Graph, table: Optional[Table], p: trw_walk_params, sources: torch.Tensor, chunk_queries: int,
+                fn, qid_base: int = 0, tuning: Optional[trw_tuning] = None, stream=None) -> int:
+    """Streamed walk (trw_walk_stream): the batch runs chunk_queries at a time and fn(chunk) is
+    called on this thread for each chunk, in order, while the next chunk walks.  chunk is a dict
+    with qid_base, nq and numpy copies of lengths, status, offsets (nq + 1) and entries (the
+    packed paths: query i's path is entries[offsets[i]:offsets[i + 1]]).  fn returning True stops
+    the stream (TrwError TRW_E_CANCELLED).  Returns the number of chunks delivered."""
+    nq = int(sources.numel())
+    dbytes, hbytes = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    check(_abi.trw_walk_stream_bytes(graph.handle, ctypes.byref(p), chunk_queries, ctypes.byref(dbytes),
+                                     ctypes.byref(hbytes)))
+    d_keep, d_ws = _aligned(int(dbytes.value), device=graph.device)
+    h_keep, h_buf = _aligned(int(hbytes.value), pin=True)
+    delivered = [0]
+    err = []
+
+    def _cb(_user, cp):
+        try:
+            c = cp.contents
+            n = int(c.nq)
+            offs = np.ctypeslib.as_array(ctypes.cast(c.offsets, ctypes.POINTER(ctypes.c_uint64)), (n + 1,)).copy()
+            total = int(offs[n])
+            ent = (np.ctypeslib.as_array(ctypes.cast(c.entries, ctypes.POINTER(ctypes.c_int32)), (total,)).copy()
+                   if total else np.zeros(0, np.int32))
+            chunk = {"qid_base": int(c.qid_base), "nq": n,
+                     "lengths": np.ctypeslib.as_array(ctypes.cast(c.lengths, ctypes.POINTER(ctypes.c_uint32)),
+                                                      (n,)).copy(),
+                     "status": np.ctypeslib.as_array(ctypes.cast(c.status, ctypes.POINTER(ctypes.c_uint8)),
+                                                     (n,)).copy(),
+                     "offsets": offs, "entries": ent}
+            delivered[0] += 1
+            return 1 if fn(chunk) else 0
+        except Exception as e:   # surface the callback's error after the call
+            err.append(e)
+            return 1
+
+    cb = _abi.TRW_CHUNK_FN(_cb)
+    st = _abi.trw_walk_stream(graph.handle, table.handle if table is not None else None, ctypes.byref(p),
+                              _dptr(sources), nq, qid_base, chunk_queries,
+                              ctypes.byref(tuning) if tuning is not None else None, _dptr(d_ws), d_ws.numel(),
+                              ctypes.c_void_p(h_buf.data_ptr()), h_buf.numel(), cb, None, _stream_ptr(stream))
+    del d_keep, h_keep
+    if err:
+        raise err[0]
+    check(st)
+    return delivered[0]
 
 
 def topk(counts: torch.Tensor, k: int, stream=None):

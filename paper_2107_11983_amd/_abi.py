@@ -53,6 +53,15 @@ class trw_program_params(ctypes.Structure):
                 ("user", ctypes.c_uint32 * 16)]
 
 
+class trw_chunk(ctypes.Structure):
+    _fields_ = [("qid_base", ctypes.c_uint64), ("nq", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("lengths", ctypes.c_void_p), ("status", ctypes.c_void_p), ("offsets", ctypes.c_void_p),
+                ("entries", ctypes.c_void_p)]
+
+
+TRW_CHUNK_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(trw_chunk))
+
+
 class trw_request(ctypes.Structure):
     _fields_ = [("params", trw_walk_params), ("sources", ctypes.c_void_p), ("nq", ctypes.c_uint32),
                 ("flags", ctypes.c_uint32), ("qid_base", ctypes.c_uint64), ("paths", ctypes.c_void_p),
@@ -130,6 +139,10 @@ _SIGS = {
     "trw_program_destroy": (_st, [_P]),
     "trw_ppr_end_counts": (_st, [_P, _P, _u64, _P, _P, _u64, _u64, _P, _u64, _P, _P]),
     "trw_topk_workspace_bytes": (_st, [_u64, _u32, ctypes.POINTER(_sz)]),
+    "trw_walk_stream_bytes": (_st, [_P, ctypes.POINTER(trw_walk_params), _u32, ctypes.POINTER(_sz),
+                                    ctypes.POINTER(_sz)]),
+    "trw_walk_stream": (_st, [_P, _P, ctypes.POINTER(trw_walk_params), _P, _u64, _u64, _u32,
+                              ctypes.POINTER(trw_tuning), _P, _sz, _P, _sz, TRW_CHUNK_FN, _P, _P]),
     "trw_ppr_walk_counts": (_st, [_P, _P, ctypes.POINTER(trw_walk_params), _P, _u64, _u64, _u64, _P, _u64, _P, _P,
                                   ctypes.POINTER(trw_tuning), _P, _sz, _P]),
     "trw_topk": (_st, [_P, _u64, _u32, _P, _P, _P, _sz, _P]),
@@ -192,6 +205,8 @@ trw_ppr_end_counts = lib.trw_ppr_end_counts
 trw_topk_workspace_bytes = lib.trw_topk_workspace_bytes
 trw_topk = lib.trw_topk
 trw_ppr_walk_counts = lib.trw_ppr_walk_counts
+trw_walk_stream_bytes = lib.trw_walk_stream_bytes
+trw_walk_stream = lib.trw_walk_stream
 trw_edge_index_bytes = lib.trw_edge_index_bytes
 trw_edge_index_build = lib.trw_edge_index_build
 trw_probe_fill = lib.trw_probe_fill

@@ -192,3 +192,24 @@ def test_ppr_walk_counts_argument_checks(abi):
     assert pc(_params(abi, "ppr", "alias")) == abi.TRW_E_INVALID                            # no table
     assert pc(_params(abi, "ppr", "naive"), nq=0) == abi.TRW_OK
     abi.trw_graph_destroy(g)
+
+
+def test_walk_stream_argument_checks(abi):
+    g = _fake_graph(abi)
+    p = _params(abi, "ppr", "naive", max_len=10)
+    dsz, hsz = ctypes.c_size_t(), ctypes.c_size_t()
+    assert abi.trw_walk_stream_bytes(g, ctypes.byref(p), 0, ctypes.byref(dsz), ctypes.byref(hsz)) == abi.TRW_E_INVALID
+    assert abi.trw_walk_stream_bytes(g, ctypes.byref(p), 100, ctypes.byref(dsz), ctypes.byref(hsz)) == abi.TRW_OK
+    assert dsz.value > 2 * 100 * 16 * 4 and hsz.value > 2 * 100 * 11 * 4     # two chunk sets each
+    fake = ctypes.c_void_p(0x1000)
+    noop = abi.TRW_CHUNK_FN(lambda u, c: 0)
+    def ws(d=ctypes.c_void_p(0x100000), db=None, h=ctypes.c_void_p(0x200000), hb=None, fn=noop, chunk=100):
+        return abi.trw_walk_stream(g, None, ctypes.byref(p), fake, 5, 0, chunk, None, d,
+                                   dsz.value if db is None else db, h, hsz.value if hb is None else hb,
+                                   fn, None, None)
+    assert ws(chunk=0) == abi.TRW_E_INVALID
+    assert ws(db=100) == abi.TRW_E_INVALID
+    assert ws(hb=100) == abi.TRW_E_INVALID
+    assert ws(h=ctypes.c_void_p(0x200010)) == abi.TRW_E_INVALID
+    assert ws(fn=abi.TRW_CHUNK_FN()) == abi.TRW_E_INVALID                     # NULL function
+    abi.trw_graph_destroy(g)
