@@ -298,7 +298,8 @@ trw_status trw_walk(trw_graph g, trw_table table, const trw_walk_params *p,
  * d_sources in `mode`, timing each with HIP events, and writes the fastest to
  * *out.  Candidates: the default tuning first, then walkers per lane x blocks
  * per CU x queue chunk (persistent) or blocks per CU x block size (per step),
- * and for METAPATH without a label index the wave-scan degree.  d_paths, d_lengths,
+ * and for METAPATH without a label index the wave-scan degree.  The default is
+ * kept unless a candidate is at least 3% faster.  d_paths, d_lengths,
  * d_status and d_ws are scratch of the sizes trw_walk needs for nq queries.
  * Synchronises the stream.  Errors as trw_walk.
  */
