@@ -61,7 +61,8 @@ def read_traffic(tag):
         return None, "stale"
     try:
         return {"total": float(kv["traffic_bytes_per_launch"]), "read": float(kv.get("read_bytes_per_launch", "nan")),
-                "write": float(kv.get("write_bytes_per_launch", "nan"))}, path
+                "write": float(kv.get("write_bytes_per_launch", "nan")),
+                "l2_hit_rate": float(kv["l2_hit_rate"]) if "l2_hit_rate" in kv else None}, path
     except KeyError:
         return None, None
 
@@ -238,6 +239,7 @@ def main():
             roofline["issued_random_reads_per_launch"] = issued
         if traffic is not None:
             roofline["traffic_frac_of_peak"] = round(traffic / (avg_launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)
+            roofline["l2_hit_rate"] = measured.get("l2_hit_rate")
 
     # Autotuned launch (the paper's pre-execution tuning): candidates timed on a
     # sample of the batch, then the whole batch timed with the winner.
