@@ -544,8 +544,9 @@ def test_deepwalk_rmat12_full():
     case = Case(g, symmetric=True)
     src = synth.make_sources(wl, g)
     for mode in (1, 0):
-        gpu, ref = run_both(case, "deepwalk", "naive", 80, wl.walk_seed, src, mode)
-        assert_same(gpu, ref, 80)
+        for adjacency in (False, True):          # bench.py times the adjacency index
+            gpu, ref = run_both(case, "deepwalk", "naive", 80, wl.walk_seed, src, mode, adjacency=adjacency)
+            assert_same(gpu, ref, 80)
 
 
 @pytest.mark.parametrize("name", ["ppr-rmat22", "node2vec-rmat24", "metapath-rmat24"])
