@@ -417,12 +417,14 @@ trw_status trw_topk(const uint32_t *d_counts, uint64_t n, uint32_t k, int32_t *d
 /* defines `struct TrwProgram` against paper_2107_11983_amd/csrc/            */
 /* program_rt.hpp (it documents the interface):                              */
 /*   static constexpr uint32_t kind;   trw_prog::STATIC_NAIVE, STATIC_ALIAS,  */
-/*                                     STATIC_ITS, DYNAMIC_REJ, DYNAMIC_ITS   */
+/*                                     STATIC_ITS, STATIC_REJ, DYNAMIC_REJ,   */
+/*                                     DYNAMIC_ITS                            */
 /*   __device__ uint32_t weight(walker, graph, params, slot) const;          */
 /*       DYNAMIC_REJ: Weight / MaxWeight as Q16 in [0, 65536] (O-REJ);        */
 /*       DYNAMIC_ITS: an integer weight (row sums below 2^32)                 */
 /*   __device__ bool update(walker, graph, params, r2) const;                */
-/*       after a move; true ends the walk (STOPPED)                           */
+/*       after a move; true ends the walk (STOPPED); for the rejection kinds */
+/*       r2 comes from the accepted dart's block, as in trw_walk's REJ       */
 /* The framework runs the batch with the random contract of trw_walk, so    */
 /* DeepWalk, PPR, Node2Vec and MetaPath written as programs reproduce the    */
 /* built-in walks bit for bit.  Compilation needs the csrc/ directory next   */

@@ -458,7 +458,8 @@ class Server:
 # Walk programs (C ABI trw_program_*): user-written sampling rules compiled at
 # run time against csrc/program_rt.hpp.
 # ---------------------------------------------------------------------------
-PROGRAM_KINDS = {"static_naive": 0, "static_alias": 1, "static_its": 2, "dynamic_rej": 3, "dynamic_its": 4}
+PROGRAM_KINDS = {"static_naive": 0, "static_alias": 1, "static_its": 2, "dynamic_rej": 3, "dynamic_its": 4,
+                 "static_rej": 5}
 
 
 def check_program(source: str, arch: str = "gfx950") -> None:

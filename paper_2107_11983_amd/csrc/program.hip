@@ -116,7 +116,7 @@ trw_status trw_program_create(const char *source, trw_program *out) {
         delete p;
         return pfail(TRW_E_DEVICE, std::string("walk program load: ") + hipGetErrorString(e));
     }
-    if (p->kind > trw_prog::DYNAMIC_ITS) {
+    if (p->kind > trw_prog::STATIC_REJ) {
         (void)hipModuleUnload(p->module);
         delete p;
         return pfail(TRW_E_INVALID, "TrwProgram::kind is not a sampling method");
@@ -150,12 +150,20 @@ trw_status trw_program_walk(trw_program prog, trw_graph g, trw_table table, cons
     a.g.symmetric = gd.symmetric ? 1u : 0u;
     const void *buf = nullptr;
     trw_graph tg = nullptr;
-    if (prog->kind == trw_prog::STATIC_ALIAS || prog->kind == trw_prog::STATIC_ITS) {
-        const uint32_t want = prog->kind == trw_prog::STATIC_ALIAS ? TRW_S_ALIAS : TRW_S_ITS;
+    if (prog->kind == trw_prog::STATIC_ALIAS || prog->kind == trw_prog::STATIC_ITS ||
+        prog->kind == trw_prog::STATIC_REJ) {
+        const uint32_t want = prog->kind == trw_prog::STATIC_ALIAS ? TRW_S_ALIAS
+                              : prog->kind == trw_prog::STATIC_ITS ? TRW_S_ITS : TRW_S_REJ;
         if (!table_view(table, want, &buf, &tg) || tg != g)
-            return pfail(TRW_E_INVALID, "a STATIC_ALIAS / STATIC_ITS program needs that table of this graph");
-        if (want == TRW_S_ALIAS) a.alias = static_cast<const uint4 *>(buf);
-        else a.prefix = static_cast<const uint64_t *>(buf);
+            return pfail(TRW_E_INVALID, "a STATIC_ALIAS / STATIC_ITS / STATIC_REJ program needs that table of this graph");
+        if (want == TRW_S_ALIAS) {
+            a.alias = static_cast<const uint4 *>(buf);
+        } else if (want == TRW_S_ITS) {
+            a.prefix = static_cast<const uint64_t *>(buf);
+        } else {
+            a.rej = static_cast<const uint4 *>(buf);
+            a.pmax = reinterpret_cast<const uint32_t *>(static_cast<const char *>(buf) + rej_records_bytes(gd.m));
+        }
     } else if (table) {
         if (!table_view(table, kEdgeIndexKind, &buf, &tg) || tg != g)
             return pfail(TRW_E_INVALID, "a NAIVE / dynamic program takes an edge index of this graph or no table");
@@ -186,7 +194,8 @@ trw_status trw_program_walk(trw_program prog, trw_graph g, trw_table table, cons
     const uint64_t waves = (nq + 63) / 64;
     // Launch shape measured on MI355X: static programs (one random read per
     // move) peak at 2 workgroups per CU, dynamic ones at full occupancy.
-    const uint64_t per_cu = prog->kind <= trw_prog::STATIC_ITS ? 2 : 8;
+    const bool static_kind = prog->kind <= trw_prog::STATIC_ITS || prog->kind == trw_prog::STATIC_REJ;
+    const uint64_t per_cu = static_kind ? 2 : 8;
     const uint32_t blocks = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((waves + 3) / 4, (uint64_t)di.num_cus * per_cu));
     void *args[] = {&a};
     hipError_t e = hipGetLastError();

@@ -13,7 +13,8 @@
 //       __device__ uint32_t weight(const trw_prog::Walker &w, const trw_prog::Graph &g,
 //                                  const trw_prog::Params &p, uint32_t slot) const;
 //       // Update after a move (w already at the new vertex, w.k moves made):
-//       // true ends the walk (status STOPPED).  r2 is the step's third random word.
+//       // true ends the walk (status STOPPED).  r2 is the step's third random word
+//       // (for the rejection kinds: that of the dart that was accepted).
 //       __device__ bool update(const trw_prog::Walker &w, const trw_prog::Graph &g,
 //                              const trw_prog::Params &p, uint32_t r2) const;
 //   };
@@ -23,6 +24,8 @@
 //   STATIC_NAIVE  uniform slot mulhi32(r0, d)                      (no table)
 //   STATIC_ALIAS  the ALIAS table's bucket mulhi32(r0, d), coin r1  (ALIAS table)
 //   STATIC_ITS    x = high half of (r1:r0) * W, first prefix > x    (ITS table)
+//   STATIC_REJ    darts t = 0, 1, ...: slot mulhi32(r0, d), accept iff
+//                 r1 * p*_v < w * 2^32, p*_v the row's largest weight (REJ table)
 //   DYNAMIC_REJ   darts t = 0, 1, ...: slot mulhi32(r0, d), accept iff
 //                 (r1 >> 16) < weight (O-REJ with the program's bound)
 //   DYNAMIC_ITS   weights of the row computed on the fly, W their sum,
@@ -48,7 +51,8 @@ using trw::rank_below;
 using trw::scale32;
 using trw::scale64;
 
-enum : uint32_t { STATIC_NAIVE = 0, STATIC_ALIAS = 1, STATIC_ITS = 2, DYNAMIC_REJ = 3, DYNAMIC_ITS = 4 };
+enum : uint32_t { STATIC_NAIVE = 0, STATIC_ALIAS = 1, STATIC_ITS = 2, DYNAMIC_REJ = 3, DYNAMIC_ITS = 4,
+                  STATIC_REJ = 5 };
 enum : uint8_t { ST_LENGTH = 1, ST_STOPPED = 2, ST_DEAD_END = 3, ST_BAD_SOURCE = 4 };
 constexpr uint32_t kIdle = 0xFFFFFFFFu;
 constexpr uint32_t kMaxDarts = 1u << 24;   // the last dart of a move is accepted (as the built-ins)
@@ -87,6 +91,7 @@ struct Walker {
     int32_t src, cur, prev;   // prev = -1 before the first move
     int32_t off;           // cur's row
     uint32_t deg;
+    uint32_t pm;           // STATIC_REJ: p* of cur (its row's largest weight)
 };
 
 struct Params {
@@ -100,6 +105,8 @@ struct Args {
     Graph g;
     const uint4 *alias;            // STATIC_ALIAS: 32-byte entries per slot
     const uint64_t *prefix;        // STATIC_ITS: inclusive prefix per row
+    const uint4 *rej;              // STATIC_REJ: 32-byte slot records {w, dst, row(dst)}, {p*(dst), ...}
+    const uint32_t *pmax;          // STATIC_REJ: p* per vertex
     const int32_t *sources;
     uint32_t nq, chunk;
     uint64_t qid_base;
@@ -111,10 +118,11 @@ struct Args {
     Params p;
 };
 
-// One move of walker w under program P; returns the next vertex or -1.
+// One move of walker w under program P; returns the next vertex or -1.  For
+// the rejection kinds r ends as the accepted dart's block.
 template <class P>
-__device__ __forceinline__ int32_t program_move(const P &prog, const Args &a, const Walker &w, const Rand4 &r,
-                                                int32_t &noff, uint32_t &ndeg) {
+__device__ __forceinline__ int32_t program_move(const P &prog, const Args &a, const Walker &w, Rand4 &r,
+                                                int32_t &noff, uint32_t &ndeg, uint32_t &npm) {
     const Graph &g = a.g;
     if (w.deg == 0) return -1;
     int32_t nxt = -1;
@@ -132,12 +140,24 @@ __device__ __forceinline__ int32_t program_move(const P &prog, const Args &a, co
         if (W == 0) return -1;
         const uint64_t x = scale64(r.r0, r.r1, W);
         nxt = g.col[w.off + its_search(pr, w.deg, x, ((uint64_t)r.r1 << 32) | r.r0)];
-    } else if (P::kind == DYNAMIC_REJ) {
-        Rand4 rr = r;
+    } else if (P::kind == STATIC_REJ) {
+        if (w.pm == 0) return -1;
         for (uint32_t t = 0;; ++t) {
-            if (t > 0) rr = philox(w.k, t, w.qid, a.p.seed);
-            const uint32_t slot = (uint32_t)w.off + scale32(rr.r0, w.deg);
-            if (t + 1 == kMaxDarts || (rr.r1 >> 16) < prog.weight(w, g, a.p, slot)) {
+            if (t > 0) r = philox(w.k, t, w.qid, a.p.seed);
+            const uint64_t e = (uint64_t)(uint32_t)w.off + scale32(r.r0, w.deg);
+            const uint4 rec = a.rej[2 * e];
+            if (t + 1 == kMaxDarts || (uint64_t)r.r1 * w.pm < ((uint64_t)rec.x << 32)) {
+                noff = (int32_t)rec.z;
+                ndeg = rec.w;
+                npm = a.rej[2 * e + 1].x;
+                return (int32_t)rec.y;
+            }
+        }
+    } else if (P::kind == DYNAMIC_REJ) {
+        for (uint32_t t = 0;; ++t) {
+            if (t > 0) r = philox(w.k, t, w.qid, a.p.seed);
+            const uint32_t slot = (uint32_t)w.off + scale32(r.r0, w.deg);
+            if (t + 1 == kMaxDarts || (r.r1 >> 16) < prog.weight(w, g, a.p, slot)) {
                 nxt = g.col[slot];
                 break;
             }
@@ -271,6 +291,7 @@ __device__ void run(const Args &a) {
                     qi = q;
                     w.qid = a.qid_base + q; w.k = 0; w.src = s; w.cur = s; w.prev = -1;
                     w.off = g.row_ptr[s]; w.deg = (uint32_t)(g.row_ptr[s + 1] - w.off);
+                    if (P::kind == STATIC_REJ) w.pm = a.pmax[s];
                     path.start(a.paths + (uint64_t)q * a.stride);
                     path.push(s);
                 }
@@ -279,15 +300,15 @@ __device__ void run(const Args &a) {
             idle = __ballot(qi == kIdle);
         }
         if (__ballot(qi != kIdle) == 0) break;
-        const Rand4 r = philox(w.k, 0, w.qid, a.p.seed);
+        Rand4 r = philox(w.k, 0, w.qid, a.p.seed);
         const bool coop = P::kind == DYNAMIC_ITS && qi != kIdle && w.deg >= kCoopSlots;
         int32_t nxt = -1;
         if (P::kind == DYNAMIC_ITS) wave_its_moves(prog, a, w, r, coop, nxt);   // whole wave, uniform
         if (qi != kIdle) {
             int32_t noff = 0;
-            uint32_t ndeg = 0;
+            uint32_t ndeg = 0, npm = 0;
             if (!coop) {
-                nxt = program_move(prog, a, w, r, noff, ndeg);
+                nxt = program_move(prog, a, w, r, noff, ndeg, npm);
             } else if (nxt >= 0) {
                 noff = g.row_ptr[nxt]; ndeg = (uint32_t)(g.row_ptr[nxt + 1] - noff);
             }
@@ -296,7 +317,7 @@ __device__ void run(const Args &a) {
                 st = ST_DEAD_END;
             } else {
                 path.push(nxt);
-                w.prev = w.cur; w.cur = nxt; w.off = noff; w.deg = ndeg; w.k += 1;
+                w.prev = w.cur; w.cur = nxt; w.off = noff; w.deg = ndeg; w.pm = npm; w.k += 1;
                 if (prog.update(w, g, a.p, r.r2)) st = ST_STOPPED;
                 else if (w.k == a.p.max_len) st = ST_LENGTH;
             }

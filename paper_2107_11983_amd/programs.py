@@ -30,11 +30,11 @@ struct TrwProgram {{
 }};
 """
 
-_KINDS = {"naive": "STATIC_NAIVE", "alias": "STATIC_ALIAS", "its": "STATIC_ITS"}
+_KINDS = {"naive": "STATIC_NAIVE", "alias": "STATIC_ALIAS", "its": "STATIC_ITS", "rej": "STATIC_REJ"}
 
 
 def deepwalk(sampler: str = "alias") -> str:
-    """DeepWalk: a static walk of fixed length (max_len moves)."""
+    """DeepWalk: a static walk of fixed length (max_len moves); sampler naive, alias, its or rej."""
     return _STATIC.format(kind=_KINDS[sampler], stop="false")
 
 

@@ -38,7 +38,8 @@ def env():
     for name, g, symmetric in (("sym", sym, True), ("dir", dirg, False)):
         G = trw.Graph(g.row_ptr, g.col, g.weight, g.label, symmetric=symmetric)
         assert G.validate() == 0
-        out[name] = dict(g=g, G=G, alias=G.table("alias"), its=G.table("its"), eidx=G.edge_index())
+        out[name] = dict(g=g, G=G, alias=G.table("alias"), its=G.table("its"), rej=G.table("rej"),
+                         eidx=G.edge_index())
     torch.cuda.synchronize()
     return out
 
@@ -61,7 +62,7 @@ def _sources(n, seed):
 
 
 @pytest.mark.parametrize("algo", ["deepwalk", "ppr"])
-@pytest.mark.parametrize("sampler", ["naive", "alias", "its"])
+@pytest.mark.parametrize("sampler", ["naive", "alias", "its", "rej"])
 def test_static_programs_equal_builtin_and_oracle(env, algo, sampler):
     case = env["dir" if algo == "ppr" else "sym"]
     g, G = case["g"], case["G"]
@@ -81,6 +82,8 @@ def test_static_programs_equal_builtin_and_oracle(env, algo, sampler):
         kw = dict(zip(("thr", "alias"), oracle.alias_build(g.row_ptr, g.weight)))
     elif sampler == "its":
         kw = dict(prefix=oracle.its_build(g.row_ptr, g.weight))
+    elif sampler == "rej":
+        kw = dict(weight=g.weight, pmax=oracle.rej_build(g.row_ptr, g.weight))
     op = oracle.WalkParams(oracle.ALGOS[algo], oracle.SAMPLERS[sampler], max_len, 77, stop_q32=stop)
     orc = oracle.walk(g.row_ptr, g.col, op, src, qid_base=9, **kw)
     _same(got, (orc.paths, orc.lengths, orc.status), max_len)

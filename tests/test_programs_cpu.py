@@ -6,8 +6,8 @@ import pytest
 from paper_2107_11983_amd import TrwError, check_program, programs
 
 SOURCES = {
-    **{f"deepwalk-{s}": programs.deepwalk(s) for s in ("naive", "alias", "its")},
-    **{f"ppr-{s}": programs.ppr(s) for s in ("naive", "alias", "its")},
+    **{f"deepwalk-{s}": programs.deepwalk(s) for s in ("naive", "alias", "its", "rej")},
+    **{f"ppr-{s}": programs.ppr(s) for s in ("naive", "alias", "its", "rej")},
     "node2vec": programs.NODE2VEC,
     "metapath": programs.METAPATH,
     "weighted-node2vec": programs.WEIGHTED_NODE2VEC,
