@@ -213,3 +213,24 @@ def test_walk_stream_argument_checks(abi):
     assert ws(h=ctypes.c_void_p(0x200010)) == abi.TRW_E_INVALID
     assert ws(fn=abi.TRW_CHUNK_FN()) == abi.TRW_E_INVALID                     # NULL function
     abi.trw_graph_destroy(g)
+
+
+def test_headers_are_plain_c(tmp_path):
+    """include/*.h compile as strict C99 and as C++ (no C++ or torch types in the boundary)."""
+    import subprocess
+    src = tmp_path / "h.c"
+    src.write_text('#include "trw.h"\n#include "trw_probe.h"\nint main(void) { return (int)trw_abi_version(); }\n')
+    inc = os.path.join(ROOT, "include")
+    subprocess.check_call(["gcc", "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-fsyntax-only",
+                           "-I", inc, str(src)])
+    subprocess.check_call(["g++", "-std=c++11", "-Wall", "-Werror", "-fsyntax-only", "-x", "c++", "-I", inc, str(src)])
+
+
+def test_c_driver_builds(tmp_path):
+    """The plain-C driver of the ABI compiles and links against libtrw.so with gcc."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("c_abi_build", os.path.join(ROOT, "tests", "c_abi", "build.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    out = mod.build(str(tmp_path / "walk_from_c"))
+    assert os.path.exists(out)
