@@ -309,11 +309,25 @@ def main():
             torch.cuda.synchronize()
             t_cw.append(a.elapsed_time(b))
         same = bool(torch.equal(counts, counts2))
+        # and with only the counts kept (no per-query lengths or status)
+        t_cn = []
+        for _ in range(5):
+            counts2.zero_()
+            a, b = (torch.cuda.Event(enable_timing=True) for _ in range(2))
+            a.record(stream)
+            trw.ppr_walk_counts(G, tables.get(sampler), p, d_src, counts=counts2, outputs=False)
+            b.record(stream)
+            torch.cuda.synchronize()
+            t_cn.append(a.elapsed_time(b))
+        same_n = bool(torch.equal(counts, counts2))
         ppr_est["counting_walk_ms"] = round(float(np.median(t_cw)), 4)
         ppr_est["counting_walk_steps_per_s"] = round(moves / (ppr_est["counting_walk_ms"] * 1e-3), 1)
         ppr_est["counting_walk_counts_equal"] = same
+        ppr_est["counts_only_walk_ms"] = round(float(np.median(t_cn)), 4)
+        ppr_est["counts_only_walk_counts_equal"] = same_n
         log(f"ppr estimate: end counts {ppr_est['end_counts_ms']} ms, top-100 {ppr_est['topk_ms']} ms; "
-            f"counting walk {ppr_est['counting_walk_ms']} ms (counts equal: {same})")
+            f"counting walk {ppr_est['counting_walk_ms']} ms (counts equal: {same}); counts only "
+            f"{ppr_est['counts_only_walk_ms']} ms (counts equal: {same_n})")
         del counts, counts2
 
     # Streamed output: the same batch in chunks, packed on the device and copied

@@ -385,7 +385,8 @@ trw_status trw_ppr_end_counts(trw_graph g, const int32_t *d_paths, uint64_t path
  * trw_walk's outputs.  No path is stored, so the walk writes no path rows.
  *   table, p, d_sources, nq, qid_base, tuning   as trw_walk (p->algo = PPR)
  *   d_counts    uint32, counts_len >= groups * n entries; added to, not cleared
- *   d_lengths, d_status   as trw_walk (bad sources: BAD_SOURCE, not counted)
+ *   d_lengths, d_status   as trw_walk (bad sources: BAD_SOURCE, not counted); both
+ *               may be NULL, and then nothing is stored per query, only the counts
  *   d_ws        trw_walk_workspace_bytes for TRW_M_PERSISTENT, 256-byte aligned
  * Errors as trw_walk; TRW_E_UNSUPPORTED unless p->algo is PPR; TRW_E_INVALID
  * for a NULL d_counts or counts_len too small.

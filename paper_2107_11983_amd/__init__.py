@@ -274,23 +274,27 @@ def ppr_end_counts(graph: Graph, paths: torch.Tensor, lengths: torch.Tensor, sta
 
 def ppr_walk_counts(graph: Graph, table: Optional[Table], p: trw_walk_params, sources: torch.Tensor, group: int = 0,
                     qid_base: int = 0, counts: Optional[torch.Tensor] = None, tuning: Optional[trw_tuning] = None,
-                    stream=None):
+                    outputs: bool = True, stream=None):
     """PPR walks that count their end vertices instead of writing paths.
 
     Returns (counts [groups, n] as in ppr_end_counts, lengths, status); counts are added to when given.
+    With outputs=False nothing is stored per query and lengths and status are None.
     """
     nq = int(sources.numel())
     groups = 1 if group <= 0 else max(1, -(-nq // group))
     if counts is None:
         counts = torch.zeros((groups, graph.n), dtype=torch.int32, device=graph.device)
-    lengths = torch.empty(max(nq, 1), dtype=torch.int32, device=graph.device)
-    status = torch.empty(max(nq, 1), dtype=torch.uint8, device=graph.device)
+    lengths = torch.empty(max(nq, 1), dtype=torch.int32, device=graph.device) if outputs else None
+    status = torch.empty(max(nq, 1), dtype=torch.uint8, device=graph.device) if outputs else None
     ws = torch.empty(max(workspace_bytes(graph, p, nq, TRW_M_PERSISTENT), 256), dtype=torch.uint8,
                      device=graph.device)
     check(_abi.trw_ppr_walk_counts(graph.handle, table.handle if table is not None else None, ctypes.byref(p),
                                    _dptr(sources), nq, qid_base, max(group, 0), _dptr(counts), counts.numel(),
-                                   _dptr(lengths), _dptr(status), ctypes.byref(tuning) if tuning is not None else None,
+                                   _dptr(lengths) if outputs else None, _dptr(status) if outputs else None,
+                                   ctypes.byref(tuning) if tuning is not None else None,
                                    _dptr(ws), ws.numel(), _stream_ptr(stream)))
+    if not outputs:
+        return counts, None, None
     return counts, lengths[:nq], status[:nq]
 
 

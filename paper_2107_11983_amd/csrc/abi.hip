@@ -396,7 +396,8 @@ trw_status walk_impl(trw_graph g, trw_table table, const trw_walk_params *p, con
     }
     if (!counts && path_stride < (uint64_t)p->max_len + 1) return fail(TRW_E_INVALID, "path_stride < max_len + 1");
     if (nq == 0) return TRW_OK;
-    if (!d_sources || (!counts && !d_paths) || !d_lengths || !d_status)
+    if (!d_sources || (!counts && !d_paths) || (!counts && (!d_lengths || !d_status)) ||
+        (counts && (d_lengths == nullptr) != (d_status == nullptr)))
         return fail(TRW_E_INVALID, "sources / paths / lengths / status is NULL");
     const size_t need = walk_workspace_bytes(mode, nq, p->max_len);
     if (!d_ws || ws_bytes < need || (reinterpret_cast<uintptr_t>(d_ws) & 255))

@@ -239,6 +239,7 @@ k_walk_persistent(GraphDev g, TableDev t, WalkDev a, unsigned long long *__restr
 
     // A query ended: record its length and status.
     auto record = [&](uint32_t code, uint32_t qi, uint32_t k, uint8_t st) {
+        if (COUNTS && a.lengths == nullptr) return;     // a counting walk that keeps only the counts
         if (code == kStageDirect) {
             a.lengths[qi] = k;
             a.status[qi] = st;
@@ -699,7 +700,7 @@ hipError_t run_persistent(const GraphDev &g, const TableDev &t, const WalkDev &w
     // kMaxStageSlots and 64 KiB per block; none when ranges can exceed a slot.
     const uint32_t waves = threads / 64;
     uint32_t n_slots = 0;
-    if (tu.queue_chunk <= kStageQueries) {
+    if (tu.queue_chunk <= kStageQueries && !(COUNTS && w.lengths == nullptr)) {
         const uint64_t per_wave = (uint64_t)di.lds_per_cu / ((uint64_t)tu.blocks_per_cu * waves);
         n_slots = (uint32_t)std::min<uint64_t>(per_wave / sizeof(StageSlot), kMaxStageSlots);
         while (n_slots > 0 && (uint64_t)n_slots * waves * sizeof(StageSlot) > 64 * 1024) --n_slots;

@@ -191,6 +191,9 @@ def test_ppr_walk_counts_argument_checks(abi):
     assert pc(_params(abi, "ppr", "naive"), group=2, counts_len=200) == abi.TRW_E_INVALID   # 3 groups
     assert pc(_params(abi, "ppr", "alias")) == abi.TRW_E_INVALID                            # no table
     assert pc(_params(abi, "ppr", "naive"), nq=0) == abi.TRW_OK
+    p = _params(abi, "ppr", "naive")                  # lengths and status: both or neither
+    assert abi.trw_ppr_walk_counts(g, None, ctypes.byref(p), fake, 5, 0, 0, fake, 100, None, fake, None, ws,
+                                   1 << 20, None) == abi.TRW_E_INVALID
     abi.trw_graph_destroy(g)
 
 

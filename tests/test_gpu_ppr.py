@@ -173,6 +173,23 @@ def test_ppr_walk_counts_match_oracle(rmat_dir, sampler, index, group, wpl):
     G.close()
 
 
+@pytest.mark.parametrize("sampler", ["alias", "its"])
+def test_ppr_walk_counts_without_outputs(rmat_dir, sampler):
+    """Without lengths and status the counting walk stores only the counts, the same counts."""
+    g = rmat_dir
+    G = trw.Graph(g.row_ptr, g.col, g.weight)
+    table = G.table(sampler)
+    src = np.concatenate([synth.sources(9001, g.n, 47), np.array([-3], np.int32)])
+    p = trw.make_params("ppr", sampler, 256, 99, stop_q32=oracle.stop_q32(0.2))
+    d_src = torch.from_numpy(src).cuda()
+    a, L, S = trw.ppr_walk_counts(G, table, p, d_src, group=1000)
+    b, L2, S2 = trw.ppr_walk_counts(G, table, p, d_src, group=1000, outputs=False)
+    torch.cuda.synchronize()
+    assert L2 is None and S2 is None
+    assert torch.equal(a, b) and int(b.sum().item()) == len(src) - 1
+    G.close()
+
+
 def test_ppr_walk_counts_rejects_bad_arguments(rmat_dir):
     g = rmat_dir
     G = trw.Graph(g.row_ptr, g.col, g.weight)
