@@ -31,7 +31,7 @@ HBM_PEAK_GBPS = 8000.0
 KERNEL_SOURCES = ["paper_2107_11983_amd/csrc/walk.hip", "paper_2107_11983_amd/csrc/walk_common.hpp",
                   "paper_2107_11983_amd/csrc/trw_device.hpp", "paper_2107_11983_amd/csrc/trw_internal.hpp"]
 
-# Algorithmic bytes ("Measurement"): per move the row range
+# Algorithmic bytes: per move the row range
 # (two int32 row offsets) 8 B, the sampling entry the move needs and the path
 # entry written 4 B; per query the source read, path[0], length and status.
 ENTRY_BYTES = {"alias": 12, "naive": 4, "its": None, "orej": None}
@@ -95,8 +95,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this engine runs on one GPU; queries shard across GPUs with no exchange "
-              "(see DESIGN.md), but only the 1-GPU figure is measured. Use --gpus 1.", file=sys.stderr)
+        print("bench.py: this engine runs on one GPU; queries shard across GPUs with no exchange, "
+              "since each walk reads only the shared graph, but only the 1-GPU figure is measured. Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
