@@ -369,6 +369,45 @@ def main():
             f"{streamed['steps_per_s_pcie_inclusive']:.4g} steps/s PCIe-inclusive")
         del dkeep, dws, hkeep, hbuf
 
+    # Graphs larger than HBM: the same batch with the CSR arrays and / or the
+    # ALIAS table in pinned host memory, read in place over the host link.
+    host_res = None
+    if wl.algo == "ppr" and sampler == "alias" and not args.no_variants:
+        p = params(sampler)
+        ref = trw.WalkBuffers(G, p, nq, mode)
+        trw.walk(G, tables[sampler], p, d_src, mode=mode, bufs=ref)
+        t0 = time.perf_counter()
+        Gh = trw.Graph(g.row_ptr, g.col, g.weight, placement="host")
+        pin_s = time.perf_counter() - t0
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        th = Gh.table(sampler)                       # built into host memory
+        e1.record(stream)
+        torch.cuda.synchronize()
+        host_res = {"graph_pin_s": round(pin_s, 3), "table_build_into_host_ms": round(e0.elapsed_time(e1), 2)}
+        th_d = G.table(sampler, placement="host")    # the device graph's table, in host memory
+        td_h = Gh.table(sampler, placement="device")
+        torch.cuda.synchronize()
+        bufs = trw.WalkBuffers(G, p, nq, mode)
+        for key, GG, tt in (("table_in_host", G, th_d), ("graph_and_table_in_host", Gh, th),
+                            ("graph_in_host", Gh, td_h)):
+            t_h = []
+            for _ in range(3):
+                a, b = (torch.cuda.Event(enable_timing=True) for _ in range(2))
+                a.record(stream)
+                trw.walk(GG, tt, p, d_src, mode=mode, bufs=bufs)
+                b.record(stream)
+                torch.cuda.synchronize()
+                t_h.append(a.elapsed_time(b))
+            same = bool(torch.equal(bufs.lengths, ref.lengths) and torch.equal(bufs.status, ref.status))
+            ms_h = float(np.median(t_h))
+            host_res[key] = {"ms_per_batch": round(ms_h, 3), "steps_per_s": round(moves / (ms_h * 1e-3), 1),
+                             "lengths_status_equal": same}
+            log(f"host memory, {key}: {ms_h:.2f} ms per batch, {moves / (ms_h * 1e-3):.4g} steps/s (equal: {same})")
+        th_d.close()
+        del bufs, ref, th, th_d, td_h
+        Gh.close()
+
     # The same walk written as a walk program (the step-centric programming
     # model, compiled at run time): what the generic framework costs.
     if not args.no_variants and not args.profile_pass:
@@ -450,6 +489,7 @@ def main():
         "variants": variants,
         "ppr_estimate": ppr_est,
         "streamed_to_host": streamed,
+        "host_resident": host_res,
         "gather_ceiling": gather,
     }
     print(json.dumps(out), flush=True)

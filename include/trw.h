@@ -73,7 +73,17 @@ typedef struct trw_graph_s *trw_graph;
 enum { TRW_G_SYMMETRIC = 1 };
 
 /*
- * Wrap a device-resident CSR graph.
+ * Memory.  Every array and buffer passed to the library is addressed by the
+ * device.  Graph arrays and table / index buffers may be device memory or
+ * pinned host memory mapped for the device (hipHostMalloc): a graph and
+ * tables larger than HBM stay in host memory and every move reads them over
+ * the host link (slower, identical results).  The edge index is the
+ * exception: its build uses device atomics and must be in device memory.
+ * Walk outputs, counts and workspaces are device memory.
+ */
+
+/*
+ * Wrap a CSR graph the device can read (device memory, or pinned host memory).
  *   n          vertices, 1 <= n < 2^31
  *   m          directed edges, 0 <= m < 2^31
  *   d_row_ptr  int32[n+1]: row v is col[row_ptr[v] .. row_ptr[v+1])
@@ -179,6 +189,8 @@ trw_status trw_adjacency_index_build(trw_graph g, void *d_buf, size_t bytes, trw
  * binary search in the sorted row, O(log d) dependent reads.  With the edge
  * index it is one probe sequence of the hash set, usually one cache line.
  * Membership is exact, so results are identical with and without it.
+ * d_buf must be device memory (the set is filled with device atomics):
+ * TRW_E_UNSUPPORTED for pinned host memory.
  * Layout in d_buf (256-byte aligned): uint32x4 records[m] padded to 256 bytes,
  * then uint64 keys[S], S = the smallest power of two >= max(64, 2m), key
  * u << 32 | v, empty slots all ones, linear probing from SplitMix64's

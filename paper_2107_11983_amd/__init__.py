@@ -48,6 +48,23 @@ def _as_device(a, dtype_np, device) -> torch.Tensor:
     return torch.from_numpy(a).to(device)
 
 
+def _as_pinned(a, dtype_np) -> torch.Tensor:
+    """numpy array or tensor -> pinned host tensor with the same bits, which the device reads in place."""
+    if isinstance(a, torch.Tensor):
+        src = a.detach().to("cpu")
+    else:
+        a = np.ascontiguousarray(a, dtype=dtype_np)
+        if dtype_np == np.uint32:
+            a = a.view(np.int32)
+        src = torch.from_numpy(a)
+    out = torch.empty(src.shape, dtype=src.dtype, pin_memory=True)
+    out.copy_(src)
+    return out
+
+
+PLACEMENTS = ("device", "host")
+
+
 def stop_threshold(prob: float) -> int:
     """PPR stop coin threshold: a walk stops after a move iff r2 < floor(prob * 2^32)."""
     if not 0.0 <= prob <= 1.0:
@@ -84,19 +101,28 @@ def make_params(algo, sampler, max_len: int, seed: int, stop_q32: int = 0,
 
 
 class Graph:
-    """A device-resident CSR graph wrapped in a trw_graph handle.
+    """A CSR graph wrapped in a trw_graph handle.
 
     row_ptr int32[n+1], col int32[m] (rows sorted, no duplicates), optional
     weight uint32[m] and label uint8[m].  The tensors live as long as the Graph.
+    placement "device" copies them to the GPU; "host" keeps them in pinned host
+    memory that the kernels read in place over the host link, for graphs larger
+    than HBM (identical results, slower moves).  Tables follow the graph's
+    placement unless told otherwise; walk outputs stay on the GPU.
     """
 
     def __init__(self, row_ptr, col, weight=None, label=None, symmetric: bool = False,
-                 device: str = "cuda"):
+                 device: str = "cuda", placement: str = "device"):
+        if placement not in PLACEMENTS:
+            raise ValueError(f"placement must be one of {PLACEMENTS}")
         self.device = torch.device(device)
-        self.row_ptr = _as_device(row_ptr, np.int32, self.device)
-        self.col = _as_device(col, np.int32, self.device)
-        self.weight = None if weight is None else _as_device(weight, np.uint32, self.device)
-        self.label = None if label is None else _as_device(label, np.uint8, self.device)
+        self.placement = placement
+        conv = ((lambda a, dt: _as_pinned(a, dt)) if placement == "host"
+                else (lambda a, dt: _as_device(a, dt, self.device)))
+        self.row_ptr = conv(row_ptr, np.int32)
+        self.col = conv(col, np.int32)
+        self.weight = None if weight is None else conv(weight, np.uint32)
+        self.label = None if label is None else conv(label, np.uint8)
         self.n = self.row_ptr.numel() - 1
         self.m = self.col.numel()
         h = ctypes.c_void_p()
@@ -113,23 +139,24 @@ class Graph:
             check(st)
         return int(bad.value)
 
-    def table(self, sampler, stream=None) -> "Table":
-        return Table(self, sampler, stream)
+    def table(self, sampler, stream=None, placement: Optional[str] = None) -> "Table":
+        return Table(self, sampler, stream, placement=placement)
 
-    def adjacency_index(self, stream=None) -> "Table":
+    def adjacency_index(self, stream=None, placement: Optional[str] = None) -> "Table":
         """Row-annotated adjacency for NAIVE / Node2Vec walks (identical results, fewer reads)."""
-        return Table(self, "adjacency_index", stream)
+        return Table(self, "adjacency_index", stream, placement=placement)
 
-    def edge_index(self, stream=None) -> "Table":
-        """Adjacency index plus a hash set of the edges (Node2Vec's adjacency test in one probe)."""
-        return Table(self, "edge_index", stream)
+    def edge_index(self, stream=None, placement: str = "device") -> "Table":
+        """Adjacency index plus a hash set of the edges (Node2Vec's adjacency test in one probe).
+        Built with device atomics, so in device memory whatever the graph's placement."""
+        return Table(self, "edge_index", stream, placement=placement)
 
-    def label_index(self, n_labels: int, stream=None) -> "Table":
+    def label_index(self, n_labels: int, stream=None, placement: Optional[str] = None) -> "Table":
         """MetaPath label index (rows sorted by label + per-vertex label offsets)."""
-        return Table(self, "label_index", stream, n_labels=n_labels)
+        return Table(self, "label_index", stream, n_labels=n_labels, placement=placement)
 
     def close(self):
-        for t in self._tables:
+        for t in list(self._tables):
             t.close()
         self._tables = []
         if self.handle:
@@ -144,44 +171,60 @@ class Graph:
 
 
 class Table:
-    """Per-vertex ALIAS, ITS or REJ table, or an index (built on the device, asynchronously)."""
+    """Per-vertex ALIAS, ITS or REJ table, or an index (built by the device, asynchronously,
+    into device memory or, with placement "host", pinned host memory)."""
 
-    def __init__(self, graph: Graph, sampler, stream=None, n_labels: int = 0):
+    def __init__(self, graph: Graph, sampler, stream=None, n_labels: int = 0, placement: Optional[str] = None):
         self.graph = graph
+        self.placement = placement or graph.placement
+        if self.placement not in PLACEMENTS:
+            raise ValueError(f"placement must be one of {PLACEMENTS}")
         nbytes = ctypes.c_size_t(0)
         h = ctypes.c_void_p()
+
+        def buf(nb: int) -> torch.Tensor:
+            if self.placement == "host":
+                self._keep, t = _aligned(nb, pin=True)
+                return t
+            return torch.empty(nb, dtype=torch.uint8, device=graph.device)
+
         if sampler == "adjacency_index":
             self.sampler = None
             check(_abi.trw_adjacency_index_bytes(graph.handle, ctypes.byref(nbytes)))
-            self.buf = torch.empty(max(int(nbytes.value), 16), dtype=torch.uint8, device=graph.device)
+            self.buf = buf(max(int(nbytes.value), 16))
             check(_abi.trw_adjacency_index_build(graph.handle, _dptr(self.buf), int(nbytes.value),
                                                  _stream_ptr(stream), ctypes.byref(h)))
         elif sampler == "edge_index":
             self.sampler = None
             check(_abi.trw_edge_index_bytes(graph.handle, ctypes.byref(nbytes)))
-            self.buf = torch.empty(int(nbytes.value), dtype=torch.uint8, device=graph.device)
+            self.buf = buf(int(nbytes.value))
             check(_abi.trw_edge_index_build(graph.handle, _dptr(self.buf), int(nbytes.value),
                                             _stream_ptr(stream), ctypes.byref(h)))
         elif sampler == "label_index":
             self.sampler = None
             self.n_labels = n_labels
             check(_abi.trw_label_index_bytes(graph.handle, n_labels, ctypes.byref(nbytes)))
-            self.buf = torch.empty(max(int(nbytes.value), 256), dtype=torch.uint8, device=graph.device)
+            self.buf = buf(max(int(nbytes.value), 256))
             check(_abi.trw_label_index_build(graph.handle, n_labels, _dptr(self.buf), int(nbytes.value),
                                              _stream_ptr(stream), ctypes.byref(h)))
         else:
             self.sampler = SAMPLERS[sampler] if isinstance(sampler, str) else int(sampler)
             check(_abi.trw_table_bytes(graph.handle, self.sampler, ctypes.byref(nbytes)))
-            self.buf = torch.empty(max(int(nbytes.value), 16), dtype=torch.uint8, device=graph.device)
+            self.buf = buf(max(int(nbytes.value), 16))
             check(_abi.trw_table_build(graph.handle, self.sampler, _dptr(self.buf), int(nbytes.value),
                                        _stream_ptr(stream), ctypes.byref(h)))
         self.handle = h
         graph._tables.append(self)
 
     def close(self):
+        """Destroy the handle and release the table's memory (the graph forgets it too)."""
         if self.handle:
             _abi.trw_table_destroy(self.handle)
             self.handle = None
+        self.buf = None
+        self._keep = None
+        if self in self.graph._tables:
+            self.graph._tables.remove(self)
 
 
 def workspace_bytes(graph: Graph, p: trw_walk_params, nq: int, mode=TRW_M_PERSISTENT) -> int:

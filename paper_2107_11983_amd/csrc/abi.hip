@@ -310,6 +310,15 @@ trw_status trw_edge_index_build(trw_graph g, void *d_buf, size_t bytes, trw_stre
     if (bytes < rec + sizeof(unsigned long long) * slots) return fail(TRW_E_INVALID, "edge index buffer too small");
     if (!d_buf || (reinterpret_cast<uintptr_t>(d_buf) & 255))
         return fail(TRW_E_INVALID, "edge index buffer NULL or not 256-byte aligned");
+    // The hash set is filled with device atomics, which host memory across
+    // the host link does not promise to support.
+    hipPointerAttribute_t attr{};
+    if (hipPointerGetAttributes(&attr, d_buf) == hipSuccess) {
+        if (attr.type == hipMemoryTypeHost)
+            return fail(TRW_E_UNSUPPORTED, "the edge index must be built in device memory");
+    } else {
+        (void)hipGetLastError();   // a pointer the runtime does not know: left to the launch
+    }
     auto s = static_cast<hipStream_t>(stream);
     hipError_t e = g->dev.m > 0 ? launch_adjacency_build(g->dev, static_cast<uint4 *>(d_buf), s) : hipSuccess;
     if (e == hipSuccess)

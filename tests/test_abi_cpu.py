@@ -237,3 +237,14 @@ def test_c_driver_builds(tmp_path):
     spec.loader.exec_module(mod)
     out = mod.build(str(tmp_path / "walk_from_c"))
     assert os.path.exists(out)
+
+
+def test_placement_is_checked_before_any_device_call():
+    """Graph and table placements other than device / host memory are refused in the binding."""
+    import numpy as np
+    import paper_2107_11983_amd as trw
+    rp = np.array([0, 1, 1], np.int32)
+    col = np.array([1], np.int32)
+    with pytest.raises(ValueError):
+        trw.Graph(rp, col, placement="disk")
+    assert trw.PLACEMENTS == ("device", "host")
