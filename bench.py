@@ -270,6 +270,14 @@ def main():
                 variants[f"{s}/{mname}"] = {"steps_per_s": round(v, 1), "ms_per_batch": round(1000 * r["wall_s"] / 3, 3),
                                             "moves": r["moves"]}
                 log(f"variant {s}/{mname}: {v:.4g} steps/s")
+        if wl.algo in ("ppr", "deepwalk") and sampler.startswith("naive") and args.mode == "persistent":
+            # the general persistent kernel on a graph the LDS path would take
+            r = run(sampler, mode, 1, 3, trw.make_tuning(no_lds_graph=1))
+            v = r["moves"] * 3 / r["wall_s"]
+            variants[f"{sampler}/persistent/no_lds_graph"] = {"steps_per_s": round(v, 1),
+                                                              "ms_per_batch": round(1000 * r["wall_s"] / 3, 3),
+                                                              "moves": r["moves"]}
+            log(f"variant {sampler}/persistent/no_lds_graph: {v:.4g} steps/s")
 
     # The PPR estimate on the batch's outputs: each query's end vertex counted
     # (Random Walk based Algorithms, PPR), then the 100 highest counts.

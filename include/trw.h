@@ -265,7 +265,12 @@ typedef struct {
     uint32_t queue_chunk;       /* persistent: queries claimed per wave per queue access */
     uint32_t coop_degree;       /* MetaPath without an index: rows at least this long are
                                    scanned by the whole wave, shorter ones by their lane */
-    uint32_t reserved[3];
+    uint32_t no_lds_graph;      /* persistent NAIVE DeepWalk / PPR on a graph whose CSR fits one
+                                   workgroup's LDS (4(n+1) + 2m bytes, rounded to 16 each, within
+                                   the device's per-workgroup limit, n <= 65536): the graph is
+                                   copied into LDS and walked there, with its own launch shape
+                                   (the fields above do not apply).  Nonzero: never. */
+    uint32_t reserved[2];
 } trw_tuning;
 
 /* Workspace bytes trw_walk needs for nq queries in `mode`. */

@@ -54,12 +54,14 @@ DeviceInfo device_info() {
     std::lock_guard<std::mutex> lk(mu);
     for (const auto &d : cache)
         if (d.device == dev) return d;
-    DeviceInfo di{dev, 256, 64 * 1024};
+    DeviceInfo di{dev, 256, 64 * 1024, 64 * 1024};
     int v = 0;
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
         di.num_cus = v;
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) == hipSuccess && v > 0)
         di.lds_per_cu = v;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
+        di.lds_per_block = v;
     cache.push_back(di);
     return di;
 }
@@ -118,7 +120,7 @@ trw_status check_params(trw_graph g, const trw_walk_params *p) {
 // contention; PPR's short walks also gain from two walkers per lane.
 Tuning resolve_tuning(const trw_walk_params *p, uint32_t mode, const trw_tuning *t, bool label_index) {
     const bool static_walk = p->algo == TRW_A_DEEPWALK || p->algo == TRW_A_PPR;
-    Tuning tu{1, 256, 8, 256, 256};
+    Tuning tu{1, 256, 8, 256, 256, true};
     if (mode == TRW_M_PERSISTENT) {
         if (static_walk && p->sampler == TRW_S_ALIAS) {
             tu.blocks_per_cu = p->algo == TRW_A_PPR ? 1 : 2;
@@ -140,6 +142,7 @@ Tuning resolve_tuning(const trw_walk_params *p, uint32_t mode, const trw_tuning 
         if (t->blocks_per_cu >= 1 && t->blocks_per_cu <= 64) tu.blocks_per_cu = t->blocks_per_cu;
         if (t->queue_chunk >= 1) tu.queue_chunk = t->queue_chunk;
         if (t->coop_degree >= 1) tu.coop_degree = t->coop_degree;
+        if (t->no_lds_graph) tu.lds_graph = false;
     }
     return tu;
 }

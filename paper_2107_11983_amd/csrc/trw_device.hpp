@@ -35,8 +35,12 @@ __device__ __forceinline__ Rand4 philox(uint32_t k, uint32_t t, uint64_t qid, ui
     uint32_t ka = (uint32_t)seed, kb = (uint32_t)(seed >> 32);
 #pragma unroll
     for (int i = 0; i < 10; ++i) {
-        const uint32_t hiA = __umulhi(kMulA, x0), loA = kMulA * x0;
-        const uint32_t hiB = __umulhi(kMulB, x2), loB = kMulB * x2;
+        // Each 32x32 -> 64 product as one 64-bit multiply: the compiler then
+        // emits one v_mad_u64_u32 for both halves instead of a separate
+        // high and low multiply (all quarter-rate).
+        const uint64_t pA = (uint64_t)kMulA * x0, pB = (uint64_t)kMulB * x2;
+        const uint32_t hiA = (uint32_t)(pA >> 32), loA = (uint32_t)pA;
+        const uint32_t hiB = (uint32_t)(pB >> 32), loB = (uint32_t)pB;
         const uint32_t y0 = hiB ^ x1 ^ ka;
         const uint32_t y2 = hiA ^ x3 ^ kb;
         x0 = y0; x1 = loB; x2 = y2; x3 = loA;

@@ -102,16 +102,24 @@ struct Tuning {
     uint32_t blocks_per_cu;
     uint32_t queue_chunk;
     uint32_t coop_degree;     // MetaPath scan: rows at least this long are scanned by the whole wave
+    bool lds_graph;           // NAIVE DeepWalk / PPR on a graph that fits one workgroup's LDS: walk it there
 };
 
 struct DeviceInfo {
     int device;
     int num_cus;
     int lds_per_cu;     // bytes of LDS a CU holds
+    int lds_per_block;  // bytes of LDS one workgroup may allocate
 };
 
 // Host launchers (tables.hip, walk.hip).  Return hipSuccess or the launch error.
 hipError_t launch_alias_build(const GraphDev &g, uint4 *out, hipStream_t s);
+// Small graphs (walk_small.hip): does the CSR fit one workgroup's LDS (int32
+// row offsets, uint16 destinations)?  If so, persistent NAIVE DeepWalk / PPR
+// walk with the graph in LDS; same results as the persistent kernel.
+bool small_graph_fits(const GraphDev &g, const DeviceInfo &di);
+hipError_t launch_walk_small(const GraphDev &g, const WalkDev &w, uint32_t algo, const DeviceInfo &di, void *ws,
+                             hipStream_t s);
 hipError_t launch_its_build(const GraphDev &g, uint64_t *prefix, uint4 *next, uint64_t *vw, hipStream_t s);
 hipError_t launch_validate(const GraphDev &g, unsigned long long *d_bad, hipStream_t s);
 hipError_t launch_label_index_build(const GraphDev &g, uint32_t nlab, int32_t *loff, int32_t *lcol, hipStream_t s);

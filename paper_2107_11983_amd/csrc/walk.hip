@@ -779,6 +779,9 @@ hipError_t launch_walk(const GraphDev &g, const TableDev &t, uint32_t algo, uint
                        const WalkDev &w, uint32_t mode, const Tuning &tu, const DeviceInfo &di,
                        void *ws, size_t, hipStream_t s) {
     if (w.nq == 0) return hipSuccess;
+    if ((algo == ALG_DEEPWALK || algo == ALG_PPR) && sampler == SMP_NAIVE && mode == TRW_M_PERSISTENT &&
+        tu.lds_graph && small_graph_fits(g, di))
+        return launch_walk_small(g, w, algo, di, ws, s);
     switch (algo) {
         case ALG_DEEPWALK:
             if (sampler == SMP_NAIVE && t.adj) return run<ALG_DEEPWALK, SMP_NAIVE_ADJ>(g, t, w, mode, tu, di, ws, s);
