@@ -470,6 +470,31 @@ def main():
     if not args.no_cpu_baseline:
         cpu, cpu_par = cpu_baseline(g, wl, sampler, src_np, kw, args.cpu_seconds)
 
+    # Node2Vec and MetaPath: a move's algorithmic bytes depend on its darts, the
+    # adjacency test's probes (binary search in the previous row) and the labels
+    # it reads, which the oracle counts.  Their rates per move on the oracle's
+    # sample of this batch scale the batch's moves.
+    if roofline is None and cpu and cpu.get("oracle_counters") and wl.algo in ("node2vec", "metapath"):
+        c = cpu["oracle_counters"]
+        om = max(int(c.get("moves", 0)), 1)
+        if wl.algo == "node2vec":
+            per_move = 8 + 4 * c["orej_trials"] / om + 4 * c["adjacency_probes"] / om + 4
+        else:
+            per_move = 8 + c["label_reads"] / om + 4 + 4
+        alg_bytes = int(per_move * moves + PER_QUERY_BYTES * valid_q + 5 * main_r["bad_sources"])
+        achieved = alg_bytes / (avg_launch_ms * 1e-3) / 1e9
+        measured, src = read_traffic(f"{wl.name}_{sampler}_{args.mode}")
+        traffic = measured["total"] if measured else None
+        roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBPS, 5), "traffic": traffic,
+                    "kernel": f"k_walk_persistent<{wl.algo},{sampler}>", "alg_bytes_per_launch": alg_bytes,
+                    "avg_launch_ms": round(avg_launch_ms, 4), "alg_bytes_per_move": round(per_move, 3),
+                    "alg_bytes_from": "oracle counters on the cpu_baseline sample, per move"}
+        if traffic is not None:
+            roofline["traffic_frac_of_peak"] = round(traffic / (avg_launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)
+            roofline["l2_hit_rate"] = measured.get("l2_hit_rate")
+        log(f"roofline ({wl.algo}): {per_move:.2f} algorithmic bytes per move, {achieved:.1f} GB/s")
+
     out = {
         "metric": "walk steps/sec + % HBM roofline (1 GPU); p50/p99 query latency served",
         "value": round(value, 1),
@@ -710,16 +735,19 @@ def cpu_baseline(g, wl, sampler, src_np, kw, target_s):
     nsamp = int(min(len(src_np), max(n0, target_s / per_q)))
     piece = max(1, (2 << 30) // (4 * (wl.max_len + 1)))          # host paths buffer <= 2 GiB per call
     moves, dt = 0, 0.0
+    counters = {}
     for lo in range(0, nsamp, piece):
         t0 = time.perf_counter()
         r = oracle.walk(g.row_ptr, g.col, p, src_np[lo:min(nsamp, lo + piece)], qid_base=lo, **tab)
         dt += time.perf_counter() - t0
         moves += int(r.lengths.sum())
+        for k, v in r.counters.items():
+            counters[k] = counters.get(k, 0) + int(v)
         del r
     log(f"cpu baseline: {nsamp} queries, {moves} moves in {dt:.2f}s")
     single = {"value": round(moves / dt, 1), "unit": "steps/s", "cores": 1, "kind": "oracle",
               "sample": f"first {nsamp} of {len(src_np)} queries of the same batch ({moves} moves, {dt:.1f} s, "
-                        f"single thread, tables prebuilt)"}
+                        f"single thread, tables prebuilt)", "oracle_counters": counters}
     # The same sample sharded by query range over the host's cores (the
     # oracle unchanged; ctypes releases the interpreter lock during each call).
     import concurrent.futures
