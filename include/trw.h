@@ -296,6 +296,9 @@ trw_status trw_default_tuning(trw_graph g, const trw_walk_params *p, uint32_t mo
  *   d_ws        workspace of >= trw_walk_workspace_bytes, 256-byte aligned
  * Asynchronous on `stream`.  Sources outside [0, n) get status BAD_SOURCE and
  * length 0 (path row untouched); they are not an error of the call.
+ * A persistent NAIVE DeepWalk or PPR walk on a graph whose CSR fits one
+ * workgroup's LDS (see trw_tuning.no_lds_graph) copies the graph into LDS and
+ * walks there; the results are the same bits either way.
  * Errors: TRW_E_UNSUPPORTED for an (algo, sampler) pair outside the list
  * above; TRW_E_INVALID for max_len outside 1..65535, thresholds > 65536 or
  * 0, schema_len outside 1..16, a missing or mismatched table, missing labels
