@@ -472,15 +472,22 @@ def main():
 
     # Node2Vec and MetaPath: a move's algorithmic bytes depend on its darts, the
     # adjacency test's probes (binary search in the previous row) and the labels
-    # it reads, which the oracle counts.  Their rates per move on the oracle's
-    # sample of this batch scale the batch's moves.
-    if roofline is None and cpu and cpu.get("oracle_counters") and wl.algo in ("node2vec", "metapath"):
-        c = cpu["oracle_counters"]
-        om = max(int(c.get("moves", 0)), 1)
+    # it scans, which the oracle counts.  Their rates per move on the oracle's
+    # sample of this batch scale the batch's moves.  The label index replaces
+    # the scan by two offsets and one destination, so a MetaPath walk through
+    # it needs no counts.
+    counts = cpu.get("oracle_counters") if cpu else None
+    per_move, alg_from = None, None
+    if wl.algo == "metapath" and sampler == "its+index":
+        per_move, alg_from = 8 + 4 + 4, "label index: two offsets, one destination, the path entry"
+    elif counts and wl.algo in ("node2vec", "metapath"):
+        om = max(int(counts.get("moves", 0)), 1)
         if wl.algo == "node2vec":
-            per_move = 8 + 4 * c["orej_trials"] / om + 4 * c["adjacency_probes"] / om + 4
+            per_move = 8 + 4 * counts["orej_trials"] / om + 4 * counts["adjacency_probes"] / om + 4
         else:
-            per_move = 8 + c["label_reads"] / om + 4 + 4
+            per_move = 8 + counts["label_reads"] / om + 4 + 4
+        alg_from = "oracle counters on the cpu_baseline sample, per move"
+    if roofline is None and per_move is not None:
         alg_bytes = int(per_move * moves + PER_QUERY_BYTES * valid_q + 5 * main_r["bad_sources"])
         achieved = alg_bytes / (avg_launch_ms * 1e-3) / 1e9
         measured, src = read_traffic(f"{wl.name}_{sampler}_{args.mode}")
@@ -489,7 +496,7 @@ def main():
                     "frac": round(achieved / HBM_PEAK_GBPS, 5), "traffic": traffic,
                     "kernel": f"k_walk_persistent<{wl.algo},{sampler}>", "alg_bytes_per_launch": alg_bytes,
                     "avg_launch_ms": round(avg_launch_ms, 4), "alg_bytes_per_move": round(per_move, 3),
-                    "alg_bytes_from": "oracle counters on the cpu_baseline sample, per move"}
+                    "alg_bytes_from": alg_from}
         if traffic is not None:
             roofline["traffic_frac_of_peak"] = round(traffic / (avg_launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)
             roofline["l2_hit_rate"] = measured.get("l2_hit_rate")
