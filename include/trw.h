@@ -212,7 +212,11 @@ trw_status trw_edge_index_build(trw_graph g, void *d_buf, size_t bytes, trw_stre
  *             and schemas used with it must have every label < L
  * Layout in d_buf (256-byte aligned): int32 loff[n][L+1] (absolute offsets
  * into lcol; loff[v][L] = end of v's indexed edges), padded to 256 bytes,
- * then int32 lcol[m].
+ * then int32 lcol[m] (-1 in the slots of edges left out).  For L <= 6, then,
+ * padded to 256 bytes, 8 x int32 per slot e {lcol[e], loff[lcol[e]][0..L],
+ * 0...}: a persistent walk's move reads one such entry, which also holds the
+ * next move's label run.  Bytes: 4n(L+1) and 4m, each rounded up to 256,
+ * plus 32m when L <= 6.
  */
 trw_status trw_label_index_bytes(trw_graph g, uint32_t n_labels, size_t *bytes);
 trw_status trw_label_index_build(trw_graph g, uint32_t n_labels, void *d_buf, size_t bytes,

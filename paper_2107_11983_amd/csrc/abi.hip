@@ -29,6 +29,12 @@ static size_t label_index_loff_bytes(const trw::GraphDev &g, uint32_t nlab) {
     return (b + 255) / 256 * 256;
 }
 
+// Where a label index's fused entries start (0: the index has none).
+static size_t label_index_fused_offset(const trw::GraphDev &g, uint32_t nlab) {
+    if (nlab > trw::kMaxFusedLabels) return 0;
+    return label_index_loff_bytes(g, nlab) + (sizeof(int32_t) * (size_t)g.m + 255) / 256 * 256;
+}
+
 namespace trw {
 
 __global__ void k_zero_first(unsigned long long *p) { *p = 0; }
@@ -110,10 +116,6 @@ trw_status check_params(trw_graph g, const trw_walk_params *p) {
     return TRW_OK;
 }
 
-// Defaults measured on MI355X: static walks (one random read per move) run
-// best at low occupancy (2 workgroups of 256 per CU: fewer requests queued in
-// the memory system), walks that scan rows or search adjacency at full
-// occupancy.
 // Defaults measured on MI355X (R-MAT workloads of the benchmark): walks that
 // make one random read per move reach the memory system's random-access
 // ceiling at low occupancy, where more requests in flight only add
@@ -255,7 +257,9 @@ trw_status trw_table_build(trw_graph g, uint32_t sampler, void *d_buf, size_t by
 trw_status trw_label_index_bytes(trw_graph g, uint32_t n_labels, size_t *bytes) {
     if (!g || !bytes) return fail(TRW_E_INVALID, "graph / bytes is NULL");
     if (n_labels == 0 || n_labels > kMaxIndexLabels) return fail(TRW_E_INVALID, "n_labels must be in 1..64");
-    *bytes = label_index_loff_bytes(g->dev, n_labels) + sizeof(int32_t) * (size_t)g->dev.m;
+    const size_t fused = label_index_fused_offset(g->dev, n_labels);
+    *bytes = fused ? fused + 2 * sizeof(uint4) * (size_t)g->dev.m
+                   : label_index_loff_bytes(g->dev, n_labels) + sizeof(int32_t) * (size_t)g->dev.m;
     return TRW_OK;
 }
 
@@ -272,6 +276,11 @@ trw_status trw_label_index_build(trw_graph g, uint32_t n_labels, void *d_buf, si
     auto *loff = static_cast<int32_t *>(d_buf);
     auto *lcol = reinterpret_cast<int32_t *>(static_cast<char *>(d_buf) + label_index_loff_bytes(g->dev, n_labels));
     hipError_t e = launch_label_index_build(g->dev, n_labels, loff, lcol, static_cast<hipStream_t>(stream));
+    const size_t fused = label_index_fused_offset(g->dev, n_labels);
+    if (e == hipSuccess && fused)
+        e = launch_label_fused_build(g->dev, n_labels, loff, lcol,
+                                     reinterpret_cast<uint4 *>(static_cast<char *>(d_buf) + fused),
+                                     static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return device_fail(e, "label index build launch");
     auto *t = new (std::nothrow) trw_table_s{g, kLabelIndexKind, d_buf, n_labels};
     if (!t) return fail(TRW_E_INVALID, "out of host memory");
@@ -460,6 +469,8 @@ trw_status walk_impl(trw_graph g, trw_table table, const trw_walk_params *p, con
         t.lcol = reinterpret_cast<const int32_t *>(static_cast<const char *>(table->buf) +
                                                    label_index_loff_bytes(g->dev, table->nlab));
         t.nlab = table->nlab;
+        if (const size_t fused = label_index_fused_offset(g->dev, table->nlab))
+            t.lfused = reinterpret_cast<const uint4 *>(static_cast<const char *>(table->buf) + fused);
     }
     const Tuning tu = resolve_tuning(p, mode, tuning, label_index);
     hipError_t e = counts ? launch_ppr_counts(g->dev, t, p->sampler, w, tu, device_info(), d_ws,

@@ -389,6 +389,26 @@ __global__ void k_label_index_build(GraphDev g, uint32_t nlab, int32_t *__restri
     for (; pos < end; ++pos) lcol[pos] = -1;      // edges whose label is >= L
 }
 
+// Fused entries (L <= kMaxFusedLabels): slot e of the label-sorted rows holds
+// its destination and that vertex's L + 1 label offsets, so a MetaPath move
+// reads one 32-byte entry that also tells the next move where its label's run
+// is.  Slots of edges left out of the index (label >= L) hold destination -1.
+__global__ void k_label_fused(GraphDev g, uint32_t nlab, const int32_t *__restrict__ loff,
+                              const int32_t *__restrict__ lcol, uint4 *__restrict__ out) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= g.m) return;
+    const int32_t v = lcol[e];
+    int32_t o[kMaxFusedLabels + 1] = {0, 0, 0, 0, 0, 0, 0};
+    if (v >= 0 && v < g.n) {
+        const int32_t *rec = loff + (int64_t)v * (nlab + 1);
+#pragma unroll
+        for (uint32_t i = 0; i <= kMaxFusedLabels; ++i)
+            if (i <= nlab) o[i] = rec[i];
+    }
+    out[2 * e] = make_uint4((uint32_t)v, (uint32_t)o[0], (uint32_t)o[1], (uint32_t)o[2]);
+    out[2 * e + 1] = make_uint4((uint32_t)o[3], (uint32_t)o[4], (uint32_t)o[5], (uint32_t)o[6]);
+}
+
 __global__ void __launch_bounds__(kBuildBlock) k_label_index_build_big(GraphDev g, uint32_t nlab,
                                                                        int32_t *__restrict__ loff,
                                                                        int32_t *__restrict__ lcol) {
@@ -566,6 +586,14 @@ hipError_t launch_its_build(const GraphDev &g, uint64_t *prefix, uint4 *next, ui
         const int64_t eblocks = ((int64_t)g.m + kBuildThreads - 1) / kBuildThreads;
         hipLaunchKernelGGL(k_its_next, dim3((uint32_t)eblocks), dim3(kBuildThreads), 0, s, g, vw, next);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_label_fused_build(const GraphDev &g, uint32_t nlab, const int32_t *loff, const int32_t *lcol,
+                                    uint4 *out, hipStream_t s) {
+    const int64_t eblocks = ((int64_t)g.m + kBuildThreads - 1) / kBuildThreads;
+    if (eblocks > 0)
+        hipLaunchKernelGGL(k_label_fused, dim3((uint32_t)eblocks), dim3(kBuildThreads), 0, s, g, nlab, loff, lcol, out);
     return hipGetLastError();
 }
 

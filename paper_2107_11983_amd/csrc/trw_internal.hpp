@@ -46,6 +46,8 @@ struct TableDev {
     unsigned long long eset_mask;     // its slot count - 1 (a power of two)
     const uint4 *rej;         // REJ: 2 x uint4 per edge slot {w, dst, row_off(dst), deg(dst)}, {p*(dst), 0, 0, 0}
     const uint32_t *pmax;     // REJ: p*_v per vertex
+    const uint4 *lfused;      // label index with L <= kMaxFusedLabels: 2 x uint4 per destination slot
+                              // {lcol[e], loff[lcol[e]][0..L]} (unused offsets 0)
 };
 
 // Edge hash set slots: at most half full (kEsetEmpty and eset_hash are in
@@ -57,6 +59,9 @@ __host__ __device__ inline unsigned long long eset_slots(int64_t m) {
 }
 constexpr size_t kAliasEntryBytes = 32;
 constexpr uint32_t kMaxIndexLabels = 64;
+// Label indexes over at most this many labels also hold fused entries: a
+// destination and its L + 1 label offsets in 32 bytes.
+constexpr uint32_t kMaxFusedLabels = 6;
 
 // Parameters of one batch of queries as the kernels see them.
 struct WalkDev {
@@ -86,7 +91,8 @@ enum : uint32_t {
     SMP_NAIVE = 0, SMP_ALIAS = 1, SMP_ITS = 2, SMP_OREJ = 3, SMP_REJ = 4,
     SMP_LABEL_INDEX = 5,   // MetaPath with a label index
     SMP_NAIVE_ADJ = 6,     // NAIVE with the adjacency index
-    SMP_OREJ_ADJ = 7       // Node2Vec O-REJ with the adjacency index
+    SMP_OREJ_ADJ = 7,      // Node2Vec O-REJ with the adjacency index
+    SMP_LABEL_FUSED = 8    // MetaPath with a label index that has fused entries (persistent schedule)
 };
 
 // Darts per O-REJ or REJ move at most (then the last dart is taken).  O-REJ:
@@ -123,6 +129,8 @@ hipError_t launch_walk_small(const GraphDev &g, const WalkDev &w, uint32_t algo,
 hipError_t launch_its_build(const GraphDev &g, uint64_t *prefix, uint4 *next, uint64_t *vw, hipStream_t s);
 hipError_t launch_validate(const GraphDev &g, unsigned long long *d_bad, hipStream_t s);
 hipError_t launch_label_index_build(const GraphDev &g, uint32_t nlab, int32_t *loff, int32_t *lcol, hipStream_t s);
+hipError_t launch_label_fused_build(const GraphDev &g, uint32_t nlab, const int32_t *loff, const int32_t *lcol,
+                                    uint4 *out, hipStream_t s);
 hipError_t launch_adjacency_build(const GraphDev &g, uint4 *out, hipStream_t s);
 hipError_t launch_edge_set_build(const GraphDev &g, unsigned long long *keys, unsigned long long slots, hipStream_t s);
 hipError_t launch_symmetry_check(const GraphDev &g, unsigned long long *d_bad, hipStream_t s);

@@ -136,6 +136,20 @@ __device__ int64_t wave_pick(uintptr_t l, uint32_t d, uint32_t want4, uint32_t r
     return -1;
 }
 
+// The label the schema gives move k.
+__device__ __forceinline__ uint32_t schema_label(const WalkDev &a, uint32_t k) {
+    const uint32_t si = k % a.schema_len;
+    const uint64_t word = si < 8 ? a.schema_lo : a.schema_hi;
+    return (uint32_t)(uint8_t)(word >> ((si & 7u) * 8u));
+}
+
+// Label offset i (0..kMaxFusedLabels) of a fused entry {dst, offsets...}.
+__device__ __forceinline__ int32_t fused_offset(const uint4 &f0, const uint4 &f1, uint32_t i) {
+    const uint32_t v = i == 0 ? f0.y : i == 1 ? f0.z : i == 2 ? f0.w : i == 3 ? f1.x : i == 4 ? f1.y : i == 5 ? f1.z
+                                                                                                               : f1.w;
+    return (int32_t)v;
+}
+
 // One MetaPath move for every lane of the wave (call with uniform control
 // flow; `active` says whether this lane has a walker).  Returns the next
 // vertex or -1 (no eligible edge).
@@ -226,6 +240,10 @@ k_walk_persistent(GraphDev g, TableDev t, WalkDev a, unsigned long long *__restr
     constexpr bool kNoRows = (SMP == SMP_LABEL_INDEX);   // the label index replaces the row lookup
     constexpr bool kRej = kStatic && SMP == SMP_REJ;
     constexpr bool kIts = kStatic && SMP == SMP_ITS;    // search, then the chosen slot's next record
+    // MetaPath through fused label-index entries: off / deg hold the run of the
+    // label the walker's next move wants; the entry a move reads carries the
+    // destination's label offsets, so the next run needs no further read.
+    constexpr bool kLabelFused = ALGO == ALG_METAPATH && SMP == SMP_LABEL_FUSED;
     Walker w[WPL];
 #pragma unroll
     for (int i = 0; i < WPL; ++i) w[i].qi = kIdle;
@@ -312,7 +330,15 @@ k_walk_persistent(GraphDev g, TableDev t, WalkDev a, unsigned long long *__restr
                 record(s_code, s_qi, 0, ST_BAD_SOURCE);
             } else {
                 r_qi = s_qi; r_code = s_code; r_src = s_src;
-                if (!kNoRows) { r_lo = g.row_ptr[s_src]; r_hi = g.row_ptr[s_src + 1]; }
+                if (kLabelFused) {
+                    const int32_t *lrec = t.loff + (uint64_t)s_src * (t.nlab + 1);
+                    const uint32_t l0 = schema_label(a, 0);
+                    r_lo = lrec[l0];
+                    r_hi = lrec[l0 + 1];
+                } else if (!kNoRows) {
+                    r_lo = g.row_ptr[s_src];
+                    r_hi = g.row_ptr[s_src + 1];
+                }
                 if (kRej) r_pm = t.pmax[s_src];
                 if (kIts) r_W = t.its_w[s_src];
             }
@@ -391,6 +417,27 @@ k_walk_persistent(GraphDev g, TableDev t, WalkDev a, unsigned long long *__restr
                     } else {
                         nxt[i] = (int32_t)e0[i].x; w[i].off = (int32_t)e0[i].y; w[i].deg = (int32_t)e0[i].z;
                     }
+                }
+            }
+        } else if (kLabelFused) {
+            uint4 f0[WPL], f1[WPL];
+#pragma unroll
+            for (int i = 0; i < WPL; ++i) {
+                if (w[i].qi != kIdle && w[i].deg != 0) {
+                    const uint64_t e = (uint64_t)(uint32_t)w[i].off + scale32(r[i].r0, (uint32_t)w[i].deg);
+                    f0[i] = t.lfused[2 * e];
+                    f1[i] = t.lfused[2 * e + 1];
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < WPL; ++i) {
+                nxt[i] = -1;
+                if (w[i].qi != kIdle && w[i].deg != 0) {
+                    nxt[i] = (int32_t)f0[i].x;
+                    const uint32_t nl = schema_label(a, w[i].k + 1);
+                    const int32_t lo = fused_offset(f0[i], f1[i], nl);
+                    w[i].off = lo;
+                    w[i].deg = fused_offset(f0[i], f1[i], nl + 1) - lo;
                 }
             }
         } else if (ALGO == ALG_METAPATH) {
@@ -799,6 +846,8 @@ hipError_t launch_walk(const GraphDev &g, const TableDev &t, uint32_t algo, uint
             if (t.adj) return run<ALG_NODE2VEC, SMP_OREJ_ADJ>(g, t, w, mode, tu, di, ws, s);
             return run<ALG_NODE2VEC, SMP_OREJ>(g, t, w, mode, tu, di, ws, s);
         default:
+            if (t.loff && t.lfused && mode == TRW_M_PERSISTENT)
+                return run_persistent<ALG_METAPATH, SMP_LABEL_FUSED>(g, t, w, tu, di, ws, s);
             if (t.loff) return run<ALG_METAPATH, SMP_LABEL_INDEX>(g, t, w, mode, tu, di, ws, s);
             return run<ALG_METAPATH, SMP_ITS>(g, t, w, mode, tu, di, ws, s);
     }

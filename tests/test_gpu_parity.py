@@ -358,6 +358,14 @@ def test_label_index_records_long_rows():
             pos += sel.size
         assert loff[v, L] == pos
         assert (lcol[pos:b] == -1).all()
+    # L <= 6: fused entries {lcol[e], loff[lcol[e]][0..L], 0...} after lcol, 256-byte aligned
+    fpad = pad + ((g.m * 4 + 255) // 256) * 256 // 4
+    fused = raw[fpad:fpad + 8 * g.m].reshape(g.m, 8)
+    assert np.array_equal(fused[:, 0], lcol)
+    ok = lcol >= 0
+    assert np.array_equal(fused[ok, 1:L + 2], loff[lcol[ok]])
+    assert (fused[ok, L + 2:] == 0).all() and (fused[~ok, 1:] == 0).all()
+
 
 def test_validate_rejects_bad_graphs():
     g = synth.from_edges(4, [(0, 1), (0, 2), (1, 0), (2, 3)])
