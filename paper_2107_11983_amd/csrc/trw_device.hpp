@@ -105,6 +105,56 @@ __device__ __forceinline__ uint32_t its_search(const uint64_t *__restrict__ p, u
     return lo;
 }
 
+// ITS search that starts from the whole 64-byte block around the guess: the
+// block's eight prefixes arrive with one round trip and usually bracket the
+// answer; otherwise the search gallops outwards from the block's edge and
+// ends by bisection.  Same slot as any correct search.  Slots of the block
+// outside [0, d) belong to other rows (or to the padding of the prefix
+// region, which is rounded up to 256 bytes) and are ignored.
+__device__ __forceinline__ uint32_t its_search_block(const uint64_t *__restrict__ p, uint32_t d, uint64_t x,
+                                                     uint64_t r64) {
+    const uint32_t g = (uint32_t)__umul64hi(r64, (uint64_t)d);   // < d
+    const uintptr_t ga = reinterpret_cast<uintptr_t>(p + g);
+    const uint4 *blk = reinterpret_cast<const uint4 *>(ga & ~(uintptr_t)63);
+    const int32_t b0 = (int32_t)g - (int32_t)((ga & 63) >> 3);    // slot of the block's first prefix
+    const uint4 q0 = blk[0], q1 = blk[1], q2 = blk[2], q3 = blk[3];
+    const uint64_t v[8] = {(uint64_t)q0.x | ((uint64_t)q0.y << 32), (uint64_t)q0.z | ((uint64_t)q0.w << 32),
+                           (uint64_t)q1.x | ((uint64_t)q1.y << 32), (uint64_t)q1.z | ((uint64_t)q1.w << 32),
+                           (uint64_t)q2.x | ((uint64_t)q2.y << 32), (uint64_t)q2.z | ((uint64_t)q2.w << 32),
+                           (uint64_t)q3.x | ((uint64_t)q3.y << 32), (uint64_t)q3.z | ((uint64_t)q3.w << 32)};
+    int32_t lo = -1, hi = (int32_t)d;       // p[lo] <= x (or lo = -1), x < p[hi] (or hi = d)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int32_t i = b0 + j;
+        if (i >= 0 && i < (int32_t)d) {
+            if (x < v[j]) hi = min(hi, i);
+            else lo = max(lo, i);
+        }
+    }
+    if (hi == lo + 1) return (uint32_t)hi;
+    if (hi == (int32_t)d) {                  // above the block: gallop up from its last slot
+        hi = (int32_t)d - 1;                 // x < p[d - 1] = W
+        for (int32_t step = 1;; step <<= 1) {
+            const int32_t j = lo + step;
+            if (j >= hi) break;
+            if (x < p[j]) { hi = j; break; }
+            lo = j;
+        }
+    } else {                                 // below the block: gallop down from its first slot
+        for (int32_t step = 1;; step <<= 1) {
+            const int32_t j = hi - step;
+            if (j <= lo) break;
+            if (x < p[j]) hi = j;
+            else { lo = j; break; }
+        }
+    }
+    while (hi - lo > 1) {
+        const int32_t mid = lo + ((hi - lo) >> 1);
+        if (x < p[mid]) hi = mid; else lo = mid;
+    }
+    return (uint32_t)hi;
+}
+
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
 // Number of set bits of `mask` below this lane.

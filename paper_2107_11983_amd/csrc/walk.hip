@@ -464,15 +464,15 @@ k_walk_persistent(GraphDev g, TableDev t, WalkDev a, unsigned long long *__restr
             }
         } else if (kIts) {
             // x uniform in [0, W) from 64 bits; the smallest i with x < prefix[i]
-            // (its_search); the slot's record then gives the next vertex, its
-            // row and its W.
+            // (its_search_block); the slot's record then gives the next vertex,
+            // its row and its W.
 #pragma unroll
             for (int i = 0; i < WPL; ++i) {
                 nxt[i] = -1;
                 if (w[i].qi != kIdle && w[i].deg != 0 && w[i].W != 0) {
                     const uint64_t *__restrict__ pr = t.prefix + (uint32_t)w[i].off;
                     const uint64_t x = scale64(r[i].r0, r[i].r1, w[i].W);
-                    const uint32_t lo = its_search(pr, (uint32_t)w[i].deg, x, ((uint64_t)r[i].r1 << 32) | r[i].r0);
+                    const uint32_t lo = its_search_block(pr, (uint32_t)w[i].deg, x, ((uint64_t)r[i].r1 << 32) | r[i].r0);
                     const uint64_t e = (uint64_t)(uint32_t)w[i].off + lo;
                     const uint4 n0 = t.its_next[2 * e];
                     const uint4 n1 = t.its_next[2 * e + 1];
