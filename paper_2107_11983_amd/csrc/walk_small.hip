@@ -10,6 +10,9 @@
 // the same index map, the same termination tests and the same outputs, so the
 // results are identical; lanes refill from the same device queue.
 #include <algorithm>
+#include <mutex>
+#include <utility>
+#include <vector>
 
 #include "trw_device.hpp"
 #include "trw_internal.hpp"
@@ -163,10 +166,18 @@ hipError_t launch_walk_small(const GraphDev &g, const WalkDev &w, uint32_t algo,
     const uint32_t rpb = (uint32_t)small_rp_bytes(g);
     const void *fn = algo == ALG_PPR ? reinterpret_cast<const void *>(&k_walk_small<ALG_PPR>)
                                      : reinterpret_cast<const void *>(&k_walk_small<ALG_DEEPWALK>);
-    // Dynamic LDS above 64 KiB: declared to the runtime; the launch reports
-    // any refusal itself.
-    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
-        (void)hipGetLastError();
+    // Dynamic LDS above 64 KiB: declared to the runtime once per kernel and
+    // device, for the most any graph can ask; a launch reports any refusal itself.
+    {
+        static std::mutex mu;
+        static std::vector<std::pair<int, const void *>> done;
+        std::lock_guard<std::mutex> lk(mu);
+        if (std::find(done.begin(), done.end(), std::make_pair(di.device, fn)) == done.end()) {
+            if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, di.lds_per_block) != hipSuccess)
+                (void)hipGetLastError();
+            done.emplace_back(di.device, fn);
+        }
+    }
     if (algo == ALG_PPR)
         hipLaunchKernelGGL(k_walk_small<ALG_PPR>, dim3(blocks), dim3(threads), lds, s, g, w, head, rpb);
     else
