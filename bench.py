@@ -500,6 +500,15 @@ def main():
         if traffic is not None:
             roofline["traffic_frac_of_peak"] = round(traffic / (avg_launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)
             roofline["l2_hit_rate"] = measured.get("l2_hit_rate")
+        if wl.algo == "metapath" and sampler == "its+index":
+            # one fused entry per move, plus the source's label offsets per query
+            roofline["issued_random_reads_per_launch"] = moves + valid_q
+            if gather:
+                acc_s = (moves + valid_q) / (avg_launch_ms * 1e-3)
+                roofline["issued_random_reads_per_s"] = round(acc_s, 1)
+                roofline["frac_of_dependent_gather_ceiling"] = round(acc_s / gather["dependent_best_reads_per_s"], 4)
+                roofline["frac_of_independent_gather_ceiling"] = round(
+                    acc_s / gather["independent_best_reads_per_s"], 4)
         log(f"roofline ({wl.algo}): {per_move:.2f} algorithmic bytes per move, {achieved:.1f} GB/s")
 
     out = {
