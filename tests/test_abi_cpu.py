@@ -250,3 +250,18 @@ def test_placement_is_checked_before_any_device_call():
     with pytest.raises(ValueError):
         trw.Graph(rp, col, placement="disk")
     assert trw.PLACEMENTS == ("device", "host")
+
+
+def test_label_index_sizes(abi):
+    """Offsets, destinations, and for at most 6 labels the 32-byte fused entries (the documented layout)."""
+    g = _fake_graph(abi, labels=True)               # n = 100, m = 1000
+    r256 = lambda b: (b + 255) // 256 * 256
+    b = ctypes.c_size_t(0)
+    for L in (1, 5, 6):
+        assert abi.trw_label_index_bytes(g, L, ctypes.byref(b)) == abi.TRW_OK
+        assert b.value == r256(4 * 100 * (L + 1)) + r256(4 * 1000) + 32 * 1000, L
+    for L in (7, 64):
+        assert abi.trw_label_index_bytes(g, L, ctypes.byref(b)) == abi.TRW_OK
+        assert b.value == r256(4 * 100 * (L + 1)) + 4 * 1000, L
+    assert abi.trw_label_index_bytes(g, 65, ctypes.byref(b)) == abi.TRW_E_INVALID
+    abi.trw_graph_destroy(g)
