@@ -105,3 +105,45 @@ def _check(P, L, S, ref, max_len):
     mask = (np.arange(max_len + 1)[None, :] <= ref.lengths[:, None]) & ok[:, None]
     assert not ((gp[:, :max_len + 1] != ref.paths) & mask).any()
     assert (ref.status == oracle.ST_BAD_SOURCE).sum() == 2
+
+
+def test_counting_walk_at_max_queries():
+    """nq = 2^32 - 1, the most one call takes: query indices reach one below the value that marks an
+    idle lane.  The counting walk stores no per-query outputs, so the batch is the sources (17 GB) and
+    the counts.  The counts sum to nq, and the last group's counts equal the oracle's."""
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    free, _ = torch.cuda.mem_get_info()
+    if free < 40 * (1 << 30):
+        pytest.skip(f"needs ~40 GB of free device memory, {free >> 30} GB free")
+    import paper_2107_11983_amd as trw
+    import synth
+    g = synth.attach_attrs(synth.rmat(16, 16, False, 0x3A7), 0x3A8, weights=True)
+    G = trw.Graph(g.row_ptr, g.col, g.weight)
+    table = G.table("alias")
+    nq, group = (1 << 32) - 1, 1 << 20
+    log(f"  max queries: {nq} sources on the device")
+    src = torch.empty(nq, dtype=torch.int32, device="cuda")
+    step = 1 << 27
+    for c in range(0, nq, step):
+        idx = torch.arange(c, min(nq, c + step), dtype=torch.int64, device="cuda")
+        src[c:c + idx.numel()] = ((idx * 40503 + 17) % g.n).to(torch.int32)
+    del idx
+    stop = oracle.stop_q32(0.2)
+    p = trw.make_params("ppr", "alias", 256, 36, stop_q32=stop)
+    log("  max queries: counting walk")
+    counts, L, S = trw.ppr_walk_counts(G, table, p, src, group=group, outputs=False)
+    torch.cuda.synchronize()
+    assert L is None and counts.shape == (-(-nq // group), g.n)
+    assert int(counts.to(torch.int64).sum().item()) == nq
+    first = (nq // group) * group
+    last_src = ((np.arange(first, nq, dtype=np.int64) * 40503 + 17) % g.n).astype(np.int32)
+    log(f"  max queries: oracle on the last {nq - first} queries")
+    thr, alias = oracle.alias_build(g.row_ptr, g.weight)
+    ref = oracle.walk(g.row_ptr, g.col, oracle.WalkParams(oracle.PPR, oracle.ALIAS, 256, 36, stop_q32=stop),
+                      last_src, qid_base=first, thr=thr, alias=alias)
+    exp, skipped = oracle.end_counts(g.n, ref.paths, ref.lengths, ref.status)
+    assert skipped == 0
+    assert np.array_equal(counts[-1].cpu().numpy().view(np.uint32), exp[0])
+    del src, counts
+    G.close()
+    torch.cuda.empty_cache()
