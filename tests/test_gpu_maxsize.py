@@ -30,6 +30,7 @@ def log(msg):
 @pytest.fixture(scope="module")
 def big():
     assert torch.cuda.is_available(), "GPU tests need a GPU"
+    torch.cuda.empty_cache()                        # what earlier tests left in torch's cache
     free, _ = torch.cuda.mem_get_info()
     if free < 110 * (1 << 30):
         pytest.skip(f"needs ~110 GB of free device memory, {free >> 30} GB free")
@@ -112,6 +113,7 @@ def test_counting_walk_at_max_queries():
     idle lane.  The counting walk stores no per-query outputs, so the batch is the sources (17 GB) and
     the counts.  The counts sum to nq, and the last group's counts equal the oracle's."""
     assert torch.cuda.is_available(), "GPU tests need a GPU"
+    torch.cuda.empty_cache()                        # what earlier tests left in torch's cache
     free, _ = torch.cuda.mem_get_info()
     if free < 40 * (1 << 30):
         pytest.skip(f"needs ~40 GB of free device memory, {free >> 30} GB free")
