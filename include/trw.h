@@ -115,6 +115,23 @@ trw_status trw_graph_validate(trw_graph g, void *d_ws, size_t ws_bytes, trw_stre
 
 trw_status trw_graph_destroy(trw_graph g);
 
+/*
+ * Count the query sources outside [0, n).  A query starts at a vertex of the
+ * graph (Preliminary: a walk is a sequence of vertices of G; Other
+ * Implementation Details, input: the caller names each query's source).
+ * trw_walk does not fail for such sources: each gets status BAD_SOURCE and
+ * length 0, asynchronously.  A caller who wants a hard error runs this first.
+ *   d_sources  int32[nq], device memory or pinned host memory
+ *   d_ws       device scratch of at least 8 bytes, 8-byte aligned (cleared by
+ *              the call's own kernel)
+ * Synchronises the stream, writes the count to *n_bad and returns
+ * TRW_E_INVALID if it is not 0.  Errors: TRW_E_INVALID for a NULL graph or
+ * n_bad, NULL sources with nq > 0, nq >= 2^32, or a short or misaligned
+ * workspace (*n_bad untouched); TRW_E_DEVICE if a HIP call fails.
+ */
+trw_status trw_validate_sources(trw_graph g, const int32_t *d_sources, uint64_t nq, void *d_ws, size_t ws_bytes,
+                                trw_stream_t stream, uint64_t *n_bad);
+
 /* ------------------------------------------------------------------------ */
 /* Sampling tables (Sampling Methods; preprocessing algorithm for static      */
 /* walks: one table C_v per vertex, built once before the queries run).      */

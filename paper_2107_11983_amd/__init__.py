@@ -139,6 +139,16 @@ class Graph:
             check(st)
         return int(bad.value)
 
+    def validate_sources(self, sources: torch.Tensor, stream=None) -> int:
+        """Number of sources outside [0, n) (trw_validate_sources; synchronises the stream)."""
+        ws = torch.empty(8, dtype=torch.uint8, device=self.device)
+        bad = ctypes.c_uint64(0)
+        st = _abi.trw_validate_sources(self.handle, _dptr(sources), int(sources.numel()), _dptr(ws), 8,
+                                       _stream_ptr(stream), ctypes.byref(bad))
+        if st not in (0, _abi.TRW_E_INVALID) or (st != 0 and bad.value == 0):
+            check(st)
+        return int(bad.value)
+
     def table(self, sampler, stream=None, placement: Optional[str] = None) -> "Table":
         return Table(self, sampler, stream, placement=placement)
 

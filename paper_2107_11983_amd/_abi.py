@@ -108,6 +108,7 @@ _SIGS = {
     "trw_graph_create": (_st, [_i64, _i64, _P, _P, _P, _P, _u32, _PP]),
     "trw_graph_validate": (_st, [_P, _P, _sz, _P, ctypes.POINTER(_u64)]),
     "trw_graph_destroy": (_st, [_P]),
+    "trw_validate_sources": (_st, [_P, _P, _u64, _P, _sz, _P, ctypes.POINTER(_u64)]),
     "trw_table_bytes": (_st, [_P, _u32, ctypes.POINTER(_sz)]),
     "trw_table_build": (_st, [_P, _u32, _P, _sz, _P, _PP]),
     "trw_table_destroy": (_st, [_P]),
@@ -177,6 +178,7 @@ trw_abi_version = lib.trw_abi_version
 trw_graph_create = lib.trw_graph_create
 trw_graph_validate = lib.trw_graph_validate
 trw_graph_destroy = lib.trw_graph_destroy
+trw_validate_sources = lib.trw_validate_sources
 trw_table_bytes = lib.trw_table_bytes
 trw_table_build = lib.trw_table_build
 trw_table_destroy = lib.trw_table_destroy

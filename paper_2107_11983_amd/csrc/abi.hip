@@ -210,6 +210,26 @@ trw_status trw_graph_destroy(trw_graph g) {
     return TRW_OK;
 }
 
+trw_status trw_validate_sources(trw_graph g, const int32_t *d_sources, uint64_t nq, void *d_ws, size_t ws_bytes,
+                                trw_stream_t stream, uint64_t *n_bad) {
+    if (!g || !n_bad) return fail(TRW_E_INVALID, "graph / n_bad is NULL");
+    if (nq >= (uint64_t(1) << 32)) return fail(TRW_E_INVALID, "nq must be < 2^32");
+    if (nq > 0 && !d_sources) return fail(TRW_E_INVALID, "sources is NULL");
+    if (!d_ws || ws_bytes < 8 || (reinterpret_cast<uintptr_t>(d_ws) & 7))
+        return fail(TRW_E_INVALID, "validate_sources needs >= 8 bytes of 8-byte aligned device scratch");
+    auto s = static_cast<hipStream_t>(stream);
+    auto *bad = static_cast<unsigned long long *>(d_ws);
+    hipError_t e = launch_validate_sources(d_sources, nq, g->dev.n, bad, s);
+    if (e != hipSuccess) return device_fail(e, "validate_sources launch");
+    unsigned long long h = 0;
+    e = hipMemcpyAsync(&h, bad, sizeof(h), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return device_fail(e, "validate_sources readback");
+    *n_bad = h;
+    if (h) return fail(TRW_E_INVALID, std::to_string(h) + " sources outside [0, n)");
+    return TRW_OK;
+}
+
 trw_status trw_table_bytes(trw_graph g, uint32_t sampler, size_t *bytes) {
     if (!g || !bytes) return fail(TRW_E_INVALID, "graph / bytes is NULL");
     switch (sampler) {
@@ -492,6 +512,7 @@ trw_status trw_walk(trw_graph g, trw_table table, const trw_walk_params *p, cons
     return walk_impl(g, table, p, d_sources, nq, qid_base, d_paths, path_stride, d_lengths, d_status, mode, tuning,
                      d_ws, ws_bytes, stream, nullptr, 0, 0);
 }
+
 
 trw_status trw_ppr_walk_counts(trw_graph g, trw_table table, const trw_walk_params *p, const int32_t *d_sources,
                                uint64_t nq, uint64_t qid_base, uint64_t group, uint32_t *d_counts,

@@ -636,6 +636,30 @@ hipError_t launch_symmetry_check(const GraphDev &g, unsigned long long *d_bad, h
     return hipGetLastError();
 }
 
+// Sources outside [0, n): a grid-stride count, summed per wave, one atomic per
+// wave.  At most 4096 x 256 threads, so a wave's sum of its lanes' counts
+// (each below 2^32 / 2^20 = 4096) fits 32 bits.
+__global__ void __launch_bounds__(256) k_count_bad_sources(const int32_t *__restrict__ src, uint64_t nq, int32_t n,
+                                                           unsigned long long *__restrict__ bad) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    uint32_t nbad = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nq; i += stride)
+        nbad += (uint32_t)src[i] >= (uint32_t)n ? 1u : 0u;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) nbad += __shfl_xor(nbad, o);
+    if ((threadIdx.x & 63) == 0 && nbad) atomicAdd(bad, (unsigned long long)nbad);
+}
+
+hipError_t launch_validate_sources(const int32_t *src, uint64_t nq, int32_t n, unsigned long long *d_bad,
+                                   hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, d_bad);
+    if (nq > 0) {
+        const uint64_t blocks = std::min<uint64_t>((nq + 255) / 256, 4096);
+        hipLaunchKernelGGL(k_count_bad_sources, dim3((uint32_t)blocks), dim3(256), 0, s, src, nq, n, d_bad);
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_validate(const GraphDev &g, unsigned long long *d_bad, hipStream_t s) {
     const int blocks = (g.n + 1 + kBuildThreads - 1) / kBuildThreads;
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, d_bad);

@@ -128,6 +128,9 @@ hipError_t launch_walk_small(const GraphDev &g, const WalkDev &w, uint32_t algo,
                              hipStream_t s);
 hipError_t launch_its_build(const GraphDev &g, uint64_t *prefix, uint4 *next, uint64_t *vw, hipStream_t s);
 hipError_t launch_validate(const GraphDev &g, unsigned long long *d_bad, hipStream_t s);
+// Counts sources outside [0, n) into *d_bad (cleared first by a kernel).
+hipError_t launch_validate_sources(const int32_t *src, uint64_t nq, int32_t n, unsigned long long *d_bad,
+                                   hipStream_t s);
 hipError_t launch_label_index_build(const GraphDev &g, uint32_t nlab, int32_t *loff, int32_t *lcol, hipStream_t s);
 hipError_t launch_label_fused_build(const GraphDev &g, uint32_t nlab, const int32_t *loff, const int32_t *lcol,
                                     uint4 *out, hipStream_t s);

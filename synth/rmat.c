@@ -102,33 +102,84 @@ int64_t synth_rmat_csr(int scale, int64_t n_samples, double a, double b, double 
         for (int lvl = 0; lvl < scale; lvl++) {
             if ((lvl & 1) == 0) r = hash2(seed, (uint64_t)i * 32u + (uint64_t)(lvl >> 1));
             uint64_t x = (lvl & 1) ? (r >> 32) : (r & 0xFFFFFFFFull);
-            u <<= 1; v <<= 1;
-            if (x < ta) { }
-            else if (x < tb) { v |= 1; }
-            else if (x < tc) { u |= 1; }
-            else { u |= 1; v |= 1; }
+            /* quadrant (u bit, v bit): [0,ta) -> (0,0), [ta,tb) -> (0,1),
+               [tb,tc) -> (1,0), [tc,2^32) -> (1,1); written without branches */
+            u = (u << 1) | (uint64_t)(x >= tb);
+            v = (v << 1) | ((uint64_t)(x >= ta) ^ (uint64_t)(x >= tb) ^ (uint64_t)(x >= tc));
         }
         int32_t pu = perm[u], pv = perm[v];
         if (pu == pv) { su[i] = -1; sv[i] = -1; }
         else { su[i] = pu; sv[i] = pv; }
     }
 
-    /* 2./3. counting sort by source */
-    for (int64_t i = 0; i < n_samples; i++) {
-        if (su[i] < 0) continue;
-        cnt[su[i] + 1]++;
-        if (symmetric) cnt[sv[i] + 1]++;
+    /* 2./3. counting sort by source, in two levels so that the scattered
+       writes stay within caches: the directed edges are first partitioned by
+       source block (each thread writes its share of every block), then each
+       block is counting-sorted by source into its rows.  Rows are sorted and
+       deduplicated afterwards, so the order of a row's entries here does not
+       matter. */
+    const int nthr = omp_get_max_threads();
+    const int blk_bits = scale > 10 ? scale - 10 : 0;        /* at most 1024 source blocks */
+    const int64_t nblk = ((n - 1) >> blk_bits) + 1;
+    const int64_t m_cap = n_samples * (symmetric ? 2 : 1);
+    int64_t *bcnt = (int64_t *)calloc((size_t)(nblk * nthr + 1), sizeof(int64_t));
+    uint64_t *pairs = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(m_cap > 0 ? m_cap : 1));
+    if (!bcnt || !pairs) { free(bcnt); free(pairs); free(perm); free(su); free(sv); free(cnt); return -1; }
+#pragma omp parallel num_threads(nthr)
+    {
+        const int t = omp_get_thread_num();
+        const int64_t lo = n_samples * t / nthr, hi = n_samples * (t + 1) / nthr;
+        int64_t *mine = bcnt + (int64_t)t * nblk;
+        for (int64_t i = lo; i < hi; i++) {
+            if (su[i] < 0) continue;
+            mine[su[i] >> blk_bits]++;
+            if (symmetric) mine[sv[i] >> blk_bits]++;
+        }
+#pragma omp barrier
+#pragma omp single
+        {   /* block-major, thread-minor offsets */
+            int64_t acc = 0;
+            for (int64_t b = 0; b < nblk; b++)
+                for (int tt = 0; tt < nthr; tt++) {
+                    int64_t c = bcnt[(int64_t)tt * nblk + b];
+                    bcnt[(int64_t)tt * nblk + b] = acc;
+                    acc += c;
+                }
+            bcnt[(int64_t)nthr * nblk] = acc;
+        }
+        for (int64_t i = lo; i < hi; i++) {
+            if (su[i] < 0) continue;
+            const uint64_t u = (uint32_t)su[i], v = (uint32_t)sv[i];
+            pairs[mine[u >> blk_bits]++] = (u << 32) | v;
+            if (symmetric) pairs[mine[v >> blk_bits]++] = (v << 32) | u;
+        }
     }
+    const int64_t m_raw = bcnt[(int64_t)nthr * nblk];
+    free(su); free(sv); free(perm);
+    /* block b's edges are pairs[start_b, end_b): start_b is thread 0's start,
+       end_b the next block's (after the second loop each thread's offset has
+       advanced to the next thread's start) */
+    int64_t *bstart = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nblk + 1));
+    if (!bstart) { free(bcnt); free(pairs); free(cnt); return -1; }
+    bstart[0] = 0;
+    for (int64_t b = 1; b < nblk; b++) bstart[b] = bcnt[(int64_t)(nthr - 1) * nblk + (b - 1)];
+    bstart[nblk] = m_raw;
+    free(bcnt);
+    /* row sizes, then row offsets, then each block sorted into its rows */
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t b = 0; b < nblk; b++)
+        for (int64_t e = bstart[b]; e < bstart[b + 1]; e++) cnt[(pairs[e] >> 32) + 1]++;
     for (int64_t v = 0; v < n; v++) cnt[v + 1] += cnt[v];
     int64_t *cur = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
-    if (!cur) { free(perm); free(su); free(sv); free(cnt); return -1; }
+    if (!cur) { free(bstart); free(pairs); free(cnt); return -1; }
     memcpy(cur, cnt, sizeof(int64_t) * (size_t)n);
-    for (int64_t i = 0; i < n_samples; i++) {
-        if (su[i] < 0) continue;
-        col[cur[su[i]]++] = sv[i];
-        if (symmetric) col[cur[sv[i]]++] = su[i];
-    }
-    free(su); free(sv); free(cur); free(perm);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t b = 0; b < nblk; b++)
+        for (int64_t e = bstart[b]; e < bstart[b + 1]; e++) {
+            const uint64_t pr = pairs[e];
+            col[cur[pr >> 32]++] = (int32_t)(uint32_t)pr;
+        }
+    free(cur); free(bstart); free(pairs);
 
     /* sort rows, drop duplicates (in place, per row) */
     int64_t *newdeg = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
@@ -143,13 +194,19 @@ int64_t synth_rmat_csr(int scale, int64_t n_samples, double a, double b, double 
             if (k == 0 || p[i] != p[k - 1]) p[k++] = p[i];
         newdeg[v] = k;
     }
-    /* compact rows to the left (sequential: rows only move left) */
+    /* compact the rows to the left: through a second array, in parallel
+       (an in-place move in parallel could overwrite rows not yet moved) */
     row_ptr[0] = 0;
-    for (int64_t v = 0; v < n; v++) {
-        int64_t dst = row_ptr[v], src = cnt[v], len = newdeg[v];
-        if (dst != src) memmove(col + dst, col + src, sizeof(int32_t) * (size_t)len);
-        row_ptr[v + 1] = dst + len;
-    }
+    for (int64_t v = 0; v < n; v++) row_ptr[v + 1] = row_ptr[v] + newdeg[v];
+    const int64_t m = row_ptr[n];
+    int32_t *packed = (int32_t *)malloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1));
+    if (!packed) { free(newdeg); free(cnt); return -1; }
+#pragma omp parallel for schedule(dynamic, 4096)
+    for (int64_t v = 0; v < n; v++)
+        memcpy(packed + row_ptr[v], col + cnt[v], sizeof(int32_t) * (size_t)newdeg[v]);
+#pragma omp parallel for schedule(static)
+    for (int64_t e = 0; e < m; e++) col[e] = packed[e];
+    free(packed);
     free(newdeg); free(cnt);
     return row_ptr[n];
 }

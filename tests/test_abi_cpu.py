@@ -125,6 +125,25 @@ def test_walk_argument_checks(abi):
     abi.trw_graph_destroy(gn)
 
 
+def test_validate_sources_argument_checks(abi):
+    """trw_validate_sources rejects bad arguments before any device work (none is done here)."""
+    g = _fake_graph(abi)
+    fake = ctypes.c_void_p(0x1000)
+    ws = ctypes.c_void_p(0x10000)
+    bad = ctypes.c_uint64(77)
+    assert abi.trw_validate_sources(None, fake, 5, ws, 8, None, ctypes.byref(bad)) == abi.TRW_E_INVALID
+    assert abi.trw_validate_sources(g, fake, 5, ws, 8, None, None) == abi.TRW_E_INVALID
+    assert abi.trw_validate_sources(g, fake, 2**32, ws, 8, None, ctypes.byref(bad)) == abi.TRW_E_INVALID
+    assert b"nq" in abi.trw_last_error()
+    assert abi.trw_validate_sources(g, None, 5, ws, 8, None, ctypes.byref(bad)) == abi.TRW_E_INVALID
+    assert abi.trw_validate_sources(g, fake, 5, None, 8, None, ctypes.byref(bad)) == abi.TRW_E_INVALID
+    assert abi.trw_validate_sources(g, fake, 5, ws, 4, None, ctypes.byref(bad)) == abi.TRW_E_INVALID
+    assert abi.trw_validate_sources(g, fake, 5, ctypes.c_void_p(0x10004), 8, None,
+                                    ctypes.byref(bad)) == abi.TRW_E_INVALID
+    assert bad.value == 77                           # untouched by a failing call
+    abi.trw_graph_destroy(g)
+
+
 def test_default_tuning(abi):
     from paper_2107_11983_amd import default_tuning
     g = _fake_graph(abi)

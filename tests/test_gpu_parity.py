@@ -479,6 +479,31 @@ def test_edge_cases(rmat_sym, rmat_dir):
 
 
 
+def test_validate_sources(rmat_dir):
+    """trw_validate_sources counts the sources outside [0, n) exactly (TRW_E_INVALID when any)."""
+    import ctypes
+    from paper_2107_11983_amd import _abi
+    G = rmat_dir.G
+    n = rmat_dir.g.n
+    ws = torch.empty(8, dtype=torch.int64, device="cuda")
+    rng = np.random.default_rng(11)
+    edge = np.array([0, n - 1, n, -1, -2**31, 2**31 - 1, n + 1, 1], np.int32)
+    big = rng.integers(0, n, size=5_000_017, dtype=np.int64).astype(np.int32)
+    where = rng.choice(big.size, size=1234, replace=False)
+    big[where] = rng.choice([-1, n, 2**31 - 1, -2**31], size=where.size)
+    cases = [np.zeros(0, np.int32), np.arange(n, dtype=np.int32), edge, big, np.full(1000, -7, np.int32)]
+    for src in cases:
+        expect = int(((src < 0) | (src >= n)).sum())
+        d = torch.from_numpy(src).cuda() if src.size else torch.zeros(1, dtype=torch.int32, device="cuda")
+        bad = ctypes.c_uint64(12345)
+        st = _abi.trw_validate_sources(G.handle, ctypes.c_void_p(d.data_ptr()), int(src.size),
+                                       ctypes.c_void_p(ws.data_ptr()), 8, None, ctypes.byref(bad))
+        assert int(bad.value) == expect, (src.size, int(bad.value), expect)
+        assert st == (_abi.TRW_E_INVALID if expect else _abi.TRW_OK)
+        assert G.validate_sources(d[:src.size]) == expect
+    log(f"  validate_sources: {len(cases)} arrays counted exactly")
+
+
 @pytest.mark.parametrize("stride", [13, 16, 20, 81])
 def test_path_padding_stays_in_row(rmat_dir, stride):
     """A walk may fill the rest of its last 64-byte block with -1, but only
