@@ -8,7 +8,8 @@ two meet only through the seeded inputs of ``synth``.
 
 Parameter encoding used here (its own, not the library's):
   algo    : 0 DeepWalk, 1 PPR, 2 Node2Vec, 3 MetaPath
-  sampler : 0 NAIVE, 1 ALIAS, 2 ITS, 3 O-REJ, 4 REJ
+  sampler : 0 NAIVE, 1 ALIAS, 2 ITS, 3 O-REJ, 4 REJ (Node2Vec: O-REJ, REJ on
+            weights with the per-vertex bound, or ITS over per-step weights)
   status  : 1 length reached, 2 PPR stop, 3 dead end, 4 source out of range
 """
 from __future__ import annotations
@@ -217,7 +218,7 @@ def walk(row_ptr, col, params: WalkParams, sources, qid_base: int = 0, qids=None
     n = len(rp) - 1
     if params.sampler == ALIAS and (thr is None or alias is None):
         raise ValueError("ALIAS needs thr and alias tables")
-    if params.sampler == ITS and params.algo != METAPATH and prefix is None:
+    if params.sampler == ITS and params.algo in (DEEPWALK, PPR) and prefix is None:
         raise ValueError("ITS needs the prefix table")
     if params.sampler == REJ:
         if weight is None or pmax is None:

@@ -19,6 +19,12 @@
  *   - the four applications PPR, DeepWalk, Node2Vec (the second-order
  *     transition equation and the Node2Vec listing), MetaPath [Random Walk
  *     based Algorithms];
+ *   - Node2Vec on a weighted graph, whose transition weight is the edge
+ *     weight times the second-order factor [Random Walk based Algorithms,
+ *     Node2Vec], sampled by rejection against the row's largest weight
+ *     [Sampling Methods, rejection sampling]; and Node2Vec sampled by ITS
+ *     over weights computed at each step, the default the paper recommends
+ *     for dynamic walks [Analysis, recommendation];
  *   - PPR's estimate from the end vertices of a source's queries, and the
  *     k highest-scoring vertices [Random Walk based Algorithms, PPR].
  *
@@ -33,6 +39,11 @@
  *   O-REJ dart height        = r1 >> 16 against Q16 thresholds
  *   REJ dart (x, y)          = x from r0, hit iff r1 * p*_v < w_x * 2^32
  *                              (y = r1 * p*_v / 2^32 uniform in [0, p*_v))
+ *   weighted Node2Vec dart   = x from r0, hit iff r1 * p*_v < w_x * a_x * 2^16
+ *                              (a_x the Q16 second-order factor, 65536 for
+ *                              the first move; y = r1 * p*_v * 2^16 / 2^32)
+ *   dynamic ITS draw in [0, W) = floor(r0 * W / 2^32) while W < 2^32, else
+ *                              floor((r1:r0) * W / 2^64)
  * Integer choices that the paper leaves open are listed with the readings in
  * the design notes of the repository.
  */
@@ -238,11 +249,32 @@ static int64_t its_search(const uint64_t *prefix, int64_t off, int64_t d, uint64
     return lo;
 }
 
+/* The second-order factor of Node2Vec's transition equation, Q16: moving
+   to x from cur, having come from prev, weighs thr[0] (the 1/p term) when x
+   is prev, thr[1] (the 1 term) when x is a neighbour of prev, thr[2] (the
+   1/q term) otherwise.  The first move (no prev) weighs 65536 everywhere. */
+static uint32_t n2v_factor(const int32_t *row_ptr, const int32_t *col, const trwo_params *p,
+                           uint32_t k, int32_t prev, int32_t x, uint64_t *probes) {
+    if (k == 0) return 65536u;
+    if (x == prev) return p->n2v_thr_q16[0];
+    if (in_sorted_row(col, row_ptr[prev], row_ptr[prev + 1], x, probes)) return p->n2v_thr_q16[1];
+    return p->n2v_thr_q16[2];
+}
+
+/* A uniform draw in [0, W) for dynamic ITS: floor(r0 * W / 2^32) while W fits
+   32 bits, else the high 64 bits of the 64-bit word (r1:r0) times W. */
+static uint64_t dynamic_its_draw(const uint32_t r[4], uint64_t W) {
+    if (W < ((uint64_t)1 << 32)) return ((uint64_t)r[0] * W) >> 32;
+    const uint64_t r64 = ((uint64_t)r[1] << 32) | r[0];
+    return (uint64_t)(((unsigned __int128)r64 * W) >> 64);
+}
+
 /*
  * Run nq queries.  Query i starts at sources[i] and has id qids ? qids[i] : qid_base + i.
  * Its path goes to paths[i * path_stride + 0 .. lengths[i]]; status[i] says why it ended.
  * Tables: thr/alias for ALIAS, prefix for ITS, the weights w and p* for REJ;
- * label for MetaPath.
+ * label for MetaPath.  Node2Vec takes the sampler O-REJ (unweighted), REJ
+ * (weighted: w and p*) or ITS (weights computed per step; no table).
  */
 int trwo_walk(int64_t n, const int32_t *row_ptr, const int32_t *col,
               const uint32_t *thr, const int32_t *alias, const uint64_t *prefix,
@@ -298,6 +330,42 @@ int trwo_walk(int64_t n, const int32_t *row_ptr, const int32_t *col,
                     const uint64_t r64 = ((uint64_t)r[1] << 32) | r[0];
                     const uint64_t t = (uint64_t)(((unsigned __int128)r64 * W) >> 64);
                     nxt = col[off + its_search(prefix, off, d, t, &local.its_probes)];
+                }
+            } else if (p->algo == ORC_NODE2VEC && p->sampler == ORC_REJ) {
+                /* Weighted Node2Vec by rejection: the transition weight of
+                   edge x is w_x * a_x, bounded by p*_v * 65536 (p*_v the
+                   row's largest weight, a_x <= 65536).  Darts (x, y): x a
+                   uniform slot, y uniform in [0, p*_v * 65536); hit iff
+                   y < w_x * a_x, i.e. r1 * p*_v < w_x * a_x * 2^16. */
+                const uint32_t ps = pmax[cur];
+                if (ps == 0) { st = ORC_ST_DEAD_END; break; }
+                for (uint32_t t = 0;; t++) {
+                    block(p->seed, qid, k, t, r);
+                    local.philox_blocks++;
+                    local.orej_trials++;
+                    const uint32_t j = index_of(r[0], d);
+                    const int32_t x = col[off + j];
+                    const uint64_t a = n2v_factor(row_ptr, col, p, k, prev, x, &local.adjacency_probes);
+                    const int hit = (uint64_t)r[1] * ps < (((uint64_t)w[off + j] * a) << 16);
+                    if (hit || t + 1 == ORC_OREJ_MAX_TRIALS) { nxt = x; break; }
+                }
+            } else if (p->algo == ORC_NODE2VEC && p->sampler == ORC_ITS) {
+                /* Node2Vec by ITS over weights computed at this step: each
+                   edge of the row weighs its second-order factor a_x; the
+                   move takes the first edge whose running sum exceeds a
+                   uniform draw in [0, W), W the row's total. */
+                uint64_t W = 0;
+                for (uint32_t i2 = 0; i2 < d; i2++)
+                    W += n2v_factor(row_ptr, col, p, k, prev, col[off + i2], &local.adjacency_probes);
+                if (W == 0) { st = ORC_ST_DEAD_END; break; }
+                block(p->seed, qid, k, 0, r);
+                local.philox_blocks++;
+                const uint64_t t = dynamic_its_draw(r, W);
+                uint64_t acc = 0;
+                for (uint32_t i2 = 0; i2 < d; i2++) {
+                    acc += n2v_factor(row_ptr, col, p, k, prev, col[off + i2], &local.adjacency_probes);
+                    local.its_probes++;
+                    if (t < acc) { nxt = col[off + i2]; break; }
                 }
             } else if (p->algo == ORC_NODE2VEC) {
                 /* O-REJ: darts (x, y) until y falls under p(x) / p*; the
