@@ -152,7 +152,8 @@ trw_status trw_table_bytes(trw_graph g, uint32_t sampler, size_t *bytes);
 
 /*
  * Build the per-vertex table for `sampler` from the graph's weights into
- * d_buf (caller-owned, >= trw_table_bytes, 32-byte aligned), asynchronously.
+ * d_buf (caller-owned, >= trw_table_bytes, 32-byte aligned; 256-byte aligned
+ * for ITS, whose search reads whole 64-byte blocks of the prefix), asynchronously.
  * The graph must be valid (trw_graph_validate); rows are read as given.
  * Layout (per directed edge slot e of row v, in CSR order):
  *   ALIAS: 8 x uint32 {thr, dst_first, dst_second, 0,
@@ -526,7 +527,11 @@ typedef struct {
                                   last one, whose finished requests are delivered on a second
                                   stream while the next tick runs.  1: each tick is read as it
                                   ends and its outputs delivered before the next one is queued */
-    uint32_t reserved[3];
+    uint32_t ring_chunks;      /* entries of the device queue of 64-query chunks, 16..2^24;
+                                  0 = 2^20.  A request holds at most 32 * ring_chunks - 1 queries;
+                                  admission waits while the chunks the device may still read and
+                                  the new request's would not fit the ring together */
+    uint32_t reserved[2];
 } trw_server_cfg;
 
 enum { TRW_REQ_HOST = 1 };     /* sources / paths / lengths / status are host memory */
@@ -559,7 +564,7 @@ typedef struct {
     uint64_t submitted, completed, cancelled, rejected, ticks, moves;
     uint32_t active, waiting;
     uint64_t pool_bytes, pool_bytes_used;
-    uint64_t tick_device_ns;   /* device time of the ticks and their counter read-back */
+    uint64_t tick_device_ns;   /* device time of the tick kernels (HIP events around each launch) */
 } trw_server_stats;
 
 /* Device bytes of a server arena for `cfg` with a request pool of pool_bytes. */

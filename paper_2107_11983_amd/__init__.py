@@ -13,7 +13,8 @@ import numpy as np
 import torch
 
 from . import _abi, programs  # noqa: F401  (programs: walk program sources)
-from ._abi import (TRW_E_CANCELLED, TRW_E_NOMEM_BUDGET, TRW_E_TIMEOUT, TRW_REQ_HOST, trw_completion,
+from ._abi import (TRW_E_CANCELLED, TRW_E_INVALID, TRW_E_NOMEM_BUDGET, TRW_E_TIMEOUT, TRW_E_UNSUPPORTED,
+                   TRW_REQ_HOST, trw_completion,
                    trw_request, trw_server_cfg, trw_server_stats)
 from ._abi import (TRW_A_DEEPWALK, TRW_A_METAPATH, TRW_A_NODE2VEC, TRW_A_PPR, TRW_G_SYMMETRIC,
                    TRW_M_PER_STEP, TRW_M_PERSISTENT, TRW_S_ALIAS, TRW_S_ITS, TRW_S_NAIVE, TRW_S_OREJ, TRW_S_REJ,
@@ -428,12 +429,13 @@ class Server:
 
     def __init__(self, graph: Graph, alias: Optional[Table] = None, adjacency: Optional[Table] = None,
                  pool_bytes: int = 1 << 30, max_slots: int = 0, max_requests: int = 0, steps_per_tick: int = 0,
-                 use_hipgraph: bool = True, pipelined: bool = True):
+                 use_hipgraph: bool = True, pipelined: bool = True, ring_chunks: int = 0):
         self.graph = graph
         cfg = trw_server_cfg()
         cfg.max_slots, cfg.max_requests, cfg.steps_per_tick = max_slots, max_requests, steps_per_tick
         cfg.use_hipgraph = 1 if use_hipgraph else 0
         cfg.serial_ticks = 0 if pipelined else 1
+        cfg.ring_chunks = ring_chunks
         nbytes = ctypes.c_size_t(0)
         check(_abi.trw_server_arena_bytes(ctypes.byref(cfg), pool_bytes, ctypes.byref(nbytes)))
         self.arena = torch.empty(int(nbytes.value), dtype=torch.uint8, device=graph.device)

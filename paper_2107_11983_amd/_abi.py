@@ -42,7 +42,8 @@ class trw_tuning(ctypes.Structure):
 class trw_server_cfg(ctypes.Structure):
     _fields_ = [("max_slots", ctypes.c_uint32), ("max_requests", ctypes.c_uint32),
                 ("steps_per_tick", ctypes.c_uint32), ("use_hipgraph", ctypes.c_uint32),
-                ("serial_ticks", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 3)]
+                ("serial_ticks", ctypes.c_uint32), ("ring_chunks", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 2)]
 
 
 TRW_REQ_HOST = 1

@@ -254,6 +254,10 @@ trw_status trw_table_build(trw_graph g, uint32_t sampler, void *d_buf, size_t by
     if (bytes < need) return fail(TRW_E_INVALID, "table buffer too small");
     if ((g->dev.m > 0 || sampler != TRW_S_ALIAS) && (!d_buf || (reinterpret_cast<uintptr_t>(d_buf) & 31)))
         return fail(TRW_E_INVALID, "table buffer NULL or not 32-byte aligned");
+    // the ITS search reads whole 64-byte blocks of the prefix array, whose parts
+    // are laid out at 256-byte offsets from the base
+    if (sampler == TRW_S_ITS && (reinterpret_cast<uintptr_t>(d_buf) & 255))
+        return fail(TRW_E_INVALID, "ITS table buffer not 256-byte aligned");
     auto s = static_cast<hipStream_t>(stream);
     hipError_t e = hipSuccess;
     char *base = static_cast<char *>(d_buf);

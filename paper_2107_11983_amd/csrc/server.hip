@@ -162,6 +162,7 @@ struct Active {
     trw_request req;
     uint64_t t_submit, t_admit;
     size_t pool_off, pool_bytes;
+    unsigned long long first_chunk;   // ring index of the request's first chunk
     uint32_t slot;
     uint32_t done_base;        // the slot's completion counter when this request was admitted
     uint64_t stride;
@@ -210,6 +211,7 @@ struct trw_server_s {
     hipStream_t deliver_stream = nullptr;     // output copies of finished requests
     hipEvent_t tick_done[2] = {nullptr, nullptr};
     hipEvent_t tick_start[2] = {nullptr, nullptr};
+    hipEvent_t tick_end[2] = {nullptr, nullptr};     // right after the tick kernel, before the read-back
     std::deque<Batch> batches;
     std::vector<hipEvent_t> spare_events;
     uint64_t n_batches = 0;
@@ -288,7 +290,9 @@ trw_status trw_server_arena_bytes(const trw_server_cfg *cfg, size_t pool_bytes, 
     const uint32_t slots = cfg->max_slots ? cfg->max_slots : (uint32_t)di.num_cus * 2048;
     const uint32_t reqs = cfg->max_requests ? cfg->max_requests : 1024;
     if (slots % kServeBlock) return sfail(TRW_E_INVALID, "max_slots must be a multiple of 256");
-    *bytes = layout(slots, reqs, 1u << 20).fixed + align_up(pool_bytes);
+    const uint32_t ring = cfg->ring_chunks ? cfg->ring_chunks : (1u << 20);
+    if (ring < 16 || ring > (1u << 24)) return sfail(TRW_E_INVALID, "ring_chunks must be in 16..2^24");
+    *bytes = layout(slots, reqs, ring).fixed + align_up(pool_bytes);
     return TRW_OK;
 }
 
@@ -307,7 +311,8 @@ extern "C" trw_status trw_server_create(trw_graph g, trw_table alias, trw_table 
     const uint32_t steps = cfg->steps_per_tick ? cfg->steps_per_tick : 16;
     if (slots % kServeBlock || slots > (1u << 24)) return sfail(TRW_E_INVALID, "max_slots must be a multiple of 256, <= 2^24");
     if (reqs > 65536) return sfail(TRW_E_INVALID, "max_requests must be <= 65536");
-    const uint32_t ring = 1u << 20;
+    const uint32_t ring = cfg->ring_chunks ? cfg->ring_chunks : (1u << 20);
+    if (ring < 16 || ring > (1u << 24)) return sfail(TRW_E_INVALID, "ring_chunks must be in 16..2^24");
     const Layout lay = layout(slots, reqs, ring);
     if (!d_arena || (reinterpret_cast<uintptr_t>(d_arena) & 255)) return sfail(TRW_E_INVALID, "arena NULL or not 256-byte aligned");
     if (arena_bytes < lay.fixed + kA) return sfail(TRW_E_INVALID, "arena smaller than the fixed server state");
@@ -356,6 +361,7 @@ extern "C" trw_status trw_server_create(trw_graph g, trw_table alias, trw_table 
     for (int i = 0; i < 2 && e == hipSuccess; ++i) {
         e = hipEventCreate(&s->tick_done[i]);
         if (e == hipSuccess) e = hipEventCreate(&s->tick_start[i]);
+        if (e == hipSuccess) e = hipEventCreate(&s->tick_end[i]);
     }
     if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_desc, sizeof(ReqDesc) * reqs, hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_ring, sizeof(Chunk) * ring, hipHostMallocDefault);
@@ -478,6 +484,7 @@ extern "C" trw_status trw_server_destroy(trw_server s) {
     for (int i = 0; i < 2; ++i) {
         if (s->tick_done[i]) (void)hipEventDestroy(s->tick_done[i]);
         if (s->tick_start[i]) (void)hipEventDestroy(s->tick_start[i]);
+        if (s->tick_end[i]) (void)hipEventDestroy(s->tick_end[i]);
     }
     for (auto &b : s->batches)
         if (b.done) (void)hipEventDestroy(b.done);
@@ -518,13 +525,27 @@ void complete(trw_server_s *s, Active &a, int32_t status) {
     s->cv_done.notify_all();
 }
 
-// Admit waiting requests while a slot and pool space are free (first come,
-// first served), then publish the descriptor table, the new chunks and the tail.
+// Admit waiting requests while a slot, pool space and ring entries are free
+// (first come, first served), then publish the descriptor table, the new
+// chunks and the tail.
+//
+// Ring entries: the device may still read a published chunk only while its
+// request has queries not yet counted done (a query is counted once its walk
+// ends or it is cancelled, both after its chunk was read).  So every entry the
+// device may still read lies in [oldest, tail), where `oldest` is the first
+// chunk of the oldest admitted request not yet known to be finished.  New
+// chunks go to [tail, tail + c); they overwrite none of those entries as long
+// as tail + c - oldest <= ring.
 hipError_t admit(trw_server_s *s, std::deque<Pending> &incoming, int half) {
     hipError_t e = hipSuccess;
     const unsigned long long tail0 = s->tail;
+    unsigned long long oldest = s->tail;
+    for (const Active &a : s->active)
+        if (!a.finishing) oldest = std::min(oldest, a.first_chunk);
     while (!incoming.empty() && !s->free_slots.empty()) {
         Pending &p = incoming.front();
+        const unsigned long long chunks = (p.req.nq + kChunkQueries - 1) / kChunkQueries;
+        if (s->tail + chunks - oldest > s->ring) break;
         size_t off = 0;
         if (!s->pool.alloc(p.bytes, &off)) break;
         const uint32_t slot = s->free_slots.back();
@@ -560,6 +581,7 @@ hipError_t admit(trw_server_s *s, std::deque<Pending> &incoming, int half) {
         d.stride = stride;
         d.nq = r.nq;
         s->desc_dirty = true;
+        const unsigned long long first_chunk = s->tail;
         for (uint32_t b = 0; b < r.nq; b += kChunkQueries) {
             Chunk &c = s->h_ring[s->tail % s->ring];
             c.req = slot; c.begin = b; c.end = std::min<uint32_t>(r.nq, b + kChunkQueries); c.pad = 0;
@@ -568,6 +590,7 @@ hipError_t admit(trw_server_s *s, std::deque<Pending> &incoming, int half) {
         Active a;
         a.id = p.id; a.req = r; a.t_submit = p.t_submit; a.t_admit = now_ns();
         a.pool_off = off; a.pool_bytes = p.bytes; a.slot = slot; a.stride = stride;
+        a.first_chunk = first_chunk;
         a.done_base = s->slot_done[slot];   // the counter is not reset between requests
         a.out_off = src_bytes;
         s->active.push_back(a);
@@ -667,6 +690,7 @@ void server_loop(trw_server_s *s) {
                 if (e == hipSuccess)
                     e = s->use_graph ? hipGraphLaunch(s->graph_exec, s->stream)
                                      : launch_serve_tick(s->g, s->t, s->dev, s->steps, s->slots / kServeBlock, s->stream);
+                if (e == hipSuccess) e = hipEventRecord(s->tick_end[cur], s->stream);
                 if (e == hipSuccess)
                     e = hipMemcpyAsync(done_half, s->dev.done, s->lay.done_bytes, hipMemcpyDeviceToHost, s->stream);
                 if (e == hipSuccess) e = hipEventRecord(s->tick_done[cur], s->stream);
@@ -685,7 +709,7 @@ void server_loop(trw_server_s *s) {
                 unsigned long long mv;
                 std::memcpy(&mv, reinterpret_cast<const char *>(done_prev) + s->lay.done_bytes - sizeof(mv), sizeof(mv));
                 float ms = 0;
-                (void)hipEventElapsedTime(&ms, s->tick_start[prev], s->tick_done[prev]);
+                (void)hipEventElapsedTime(&ms, s->tick_start[prev], s->tick_end[prev]);
                 std::lock_guard<std::mutex> lk(s->mu);
                 s->stats.ticks++;
                 s->stats.moves = mv;

@@ -119,6 +119,12 @@ def test_walk_argument_checks(abi):
     assert abi.trw_table_build(g, abi.TRW_S_ALIAS, fake, 10, None, ctypes.byref(t)) == abi.TRW_E_INVALID
     assert abi.trw_table_build(g, abi.TRW_S_ALIAS, ctypes.c_void_p(0x1010), 32000, None,
                                ctypes.byref(t)) == abi.TRW_E_INVALID
+    # ITS: the search reads whole 64-byte prefix blocks, so the buffer must start on 256 bytes
+    its_bytes = 8192 + 32000 + 8 * 100
+    for misaligned in (0x1020, 0x1040, 0x1080):
+        assert abi.trw_table_build(g, abi.TRW_S_ITS, ctypes.c_void_p(misaligned), its_bytes, None,
+                                   ctypes.byref(t)) == abi.TRW_E_INVALID
+        assert b"256-byte" in abi.trw_last_error()
     gn = _fake_graph(abi)
     assert abi.trw_table_build(gn, abi.TRW_S_ITS, fake, 8000, None, ctypes.byref(t)) == abi.TRW_E_INVALID
     abi.trw_graph_destroy(g)
@@ -284,3 +290,4 @@ def test_label_index_sizes(abi):
         assert b.value == r256(4 * 100 * (L + 1)) + 4 * 1000, L
     assert abi.trw_label_index_bytes(g, 65, ctypes.byref(b)) == abi.TRW_E_INVALID
     abi.trw_graph_destroy(g)
+

@@ -218,3 +218,33 @@ def test_rejects_unsupported(env):
     with pytest.raises(trw.TrwError):
         noalias.submit(params("deepwalk", "alias", 5, 1), np.zeros(4, np.int32))
     noalias.close()
+
+
+def test_small_ring_admits_more_than_it_holds(env):
+    """A ring of 16 chunks (requests of at most 511 queries) and 40 requests holding
+    about 200 chunks in all, submitted at once: admission waits for ring entries the
+    device has read, so no published chunk is overwritten and every request's result
+    equals the same walk through trw_walk."""
+    g = env["g"]
+    srv = make_server(env, ring_chunks=16)
+    with pytest.raises(trw.TrwError) as ei:
+        srv.submit(params("deepwalk", "alias", 80, 1), synth.sources(512, g.n, 1))
+    assert ei.value.status == trw.TRW_E_INVALID
+    rng = np.random.default_rng(17)
+    reqs = []
+    for i in range(40):
+        algo, sampler, max_len = SERVED[i % len(SERVED)]
+        nq = int(rng.integers(64, 512))
+        reqs.append((algo, sampler, max_len, synth.sources(nq, g.n, 900 + i), (i + 1) << 24, 40 + i))
+    assert sum(-(-len(r[3]) // 64) for r in reqs) > 10 * 16
+    ids = [srv.submit(params(a, s, m, seed), src, qid_base=qb) for a, s, m, src, qb, seed in reqs]
+    got = wait_all(srv, ids)
+    for (algo, sampler, max_len, src, qb, seed), rid in zip(reqs, ids):
+        assert got[rid]["status"] == 0
+        p = params(algo, sampler, max_len, seed)
+        table = env["alias"] if sampler == "alias" else None
+        P, L, S = trw.walk(env["G"], table, p, torch.from_numpy(src).cuda(), qid_base=qb)
+        torch.cuda.synchronize()
+        same(to_np(got[rid]), (P.cpu().numpy(), L.cpu().numpy().view(np.uint32), S.cpu().numpy()), max_len)
+    assert srv.stats()["completed"] == 40
+    srv.close()
