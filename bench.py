@@ -1,20 +1,24 @@
 #!/usr/bin/env python3
 """Walk-throughput benchmark on one MI355X.
 
-Default workload: PPR walks (stop probability 0.2 after each move, at most 256
-moves) from 10^7 uniformly random sources on a weighted directed R-MAT graph
-with 2^22 vertices and average degree 32 (uint32 weights in [1, 255]),
-sampled with the integer ALIAS table, one persistent launch per batch.  A
-"step" of this benchmark is one batch: all 10^7 queries walked to completion.
+Default (the driver's ``--gpus 1 --steps K --warmup W``): the served mixed
+workload on a resident weighted symmetric R-MAT graph with 2^26 vertices and
+average degree 16 (about 1.06 G directed edges): requests of 1..4096 queries,
+each DeepWalk (80 moves, ALIAS), PPR (stop 0.2 after each move, ALIAS) or
+Node2Vec (p = 2, q = 0.5, 80 moves, O-REJ), served by continuous batching with
+memory admission and graph-captured ticks.  A "step" is one saturated replay
+of 2000 requests (all submitted at once; admitted as slots and memory free
+up); W replays warm up, K are timed.  Then p50/p99 request latency is measured
+with Poisson arrivals at 0.7x the saturated request rate.
 
-Metric: walk steps (moves) per second of walk time, graph and tables resident
-in HBM (the paper's throughput: steps of all queries / execution time, table
-preprocessing timed separately; Experimental Setup, "Metrics").
+The four batch workloads (deepwalk-rmat12, ppr-rmat22, node2vec-rmat24,
+metapath-rmat24) run first and are reported as nested objects, each with its
+own roofline, schedules and oracle baseline.  ``--workload NAME`` runs one
+workload alone and prints its own line.
 
-Printed: one JSON line with the throughput, a roofline object for the walk
-kernel, the oracle's single-core throughput on a bounded sample, the other
-sampler / schedule variants of the same workload, and the random-gather
-ceiling measured on the device.
+Metric: walk steps (moves) per second of walk time, graph and tables
+resident in HBM (the paper's throughput: steps of all queries / execution
+time, table preprocessing timed separately; Experimental Setup, "Metrics").
 """
 import argparse
 import hashlib
@@ -28,8 +32,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
-KERNEL_SOURCES = ["paper_2107_11983_amd/csrc/walk.hip", "paper_2107_11983_amd/csrc/walk_common.hpp",
-                  "paper_2107_11983_amd/csrc/trw_device.hpp", "paper_2107_11983_amd/csrc/trw_internal.hpp"]
+CSRC = "paper_2107_11983_amd/csrc/"
+WALK_SOURCES = [CSRC + f for f in ("walk.hip", "walk_common.hpp", "trw_device.hpp", "trw_internal.hpp")]
+SERVE_SOURCES = [CSRC + f for f in ("serve_kernel.hip", "serve_internal.hpp", "walk_common.hpp", "trw_device.hpp",
+                                    "trw_internal.hpp")]
+BATCH_WORKLOADS = ("deepwalk-rmat12", "ppr-rmat22", "node2vec-rmat24", "metapath-rmat24")
+SERVED_WORKLOAD = "served-rmat26"
+BOX_CPU_SHARE = 16     # host threads the oracle's parallel baseline may use
 
 # Algorithmic bytes: per move the row range
 # (two int32 row offsets) 8 B, the sampling entry the move needs and the path
@@ -42,29 +51,64 @@ def log(msg):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_source_hash():
+def source_hash(files):
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in files:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def read_traffic(tag):
-    """HBM bytes per launch (total, read, written) from a committed rocprofv3 counter summary, if current."""
+def read_traffic(tag, files):
+    """HBM bytes per launch (total, read, written) from a committed rocprofv3 counter summary,
+    if it was taken on the current kernel sources."""
     path = os.path.join(ROOT, "profiles", f"counters_{tag}.md")
     if not os.path.exists(path):
         return None, None
     text = open(path).read()
     kv = dict(re.findall(r"^- (\w+): ([0-9a-fA-F.e+]+)\s*$", text, flags=re.M))
-    if kv.get("kernel_source_sha256_16") != kernel_source_hash():
+    if kv.get("kernel_source_sha256_16") != source_hash(files):
         return None, "stale"
     try:
         return {"total": float(kv["traffic_bytes_per_launch"]), "read": float(kv.get("read_bytes_per_launch", "nan")),
                 "write": float(kv.get("write_bytes_per_launch", "nan")),
-                "l2_hit_rate": float(kv["l2_hit_rate"]) if "l2_hit_rate" in kv else None}, path
+                "l2_hit_rate": float(kv["l2_hit_rate"]) if "l2_hit_rate" in kv else None,
+                "method": kv.get("traffic_method")}, path
     except KeyError:
         return None, None
+
+
+def host_info():
+    """CPU model and thread counts of this host (recorded with every oracle figure)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = os.cpu_count()
+    return {"cpu_model": model, "nproc": affinity, "os_cpu_count": os.cpu_count()}
+
+
+class Ctx:
+    """Modules and device handles shared by the benchmark's parts."""
+
+    def __init__(self, np, torch, synth, trw, props, dev):
+        self.np, self.torch, self.synth, self.trw = np, torch, synth, trw
+        self.props, self.dev = props, dev
+        self.gather = None
+
+    def release(self):
+        import gc
+        gc.collect()
+        self.torch.cuda.synchronize()
+        self.torch.cuda.empty_cache()
 
 
 def main():
@@ -72,7 +116,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="ppr-rmat22")
+    ap.add_argument("--workload", default=None, help="one workload alone (default: the served headline, "
+                                                     "with the batch workloads nested)")
     ap.add_argument("--sampler", default=None, help="default: the workload's first sampler")
     ap.add_argument("--mode", default="persistent", choices=["persistent", "per_step"])
     ap.add_argument("--wpl", type=int, default=0, help="walkers per lane (0 = library default)")
@@ -80,23 +125,27 @@ def main():
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--nq", type=int, default=0, help="override the number of queries (throughput-vs-batch sweeps)")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="headline only, without the nested batch workloads")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-probe", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle CPU time")
-    ap.add_argument("--serve-requests", type=int, default=10000, help="measured requests (served workload)")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle CPU time (headline)")
+    ap.add_argument("--cpu-seconds-nested", type=float, default=4.0, help="target oracle CPU time per nested workload")
+    ap.add_argument("--serve-replay", type=int, default=2000, help="requests per saturated replay (one step)")
+    ap.add_argument("--serve-requests", type=int, default=10000, help="measured requests of the latency phase")
     ap.add_argument("--serve-scale", type=int, default=0, help="override the served graph's scale (tests)")
     ap.add_argument("--serve-slots-per-cu", type=int, default=2048)
     ap.add_argument("--serve-steps", type=int, default=16, help="moves per walker slot per tick")
     ap.add_argument("--serve-pipelined", type=int, default=1, help="0: serial ticks (read each tick before queueing the next)")
     ap.add_argument("--serve-rate", type=float, default=0.0, help="offered requests/s (0: 0.7x the saturated rate)")
     ap.add_argument("--profile-pass", action="store_true",
-                    help="short run for counter collection: a 1 GiB copy (calibration) then the walk only")
+                    help="short run for counter collection: a 1 GiB copy (calibration) then the timed kernel only")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py: this engine runs on one GPU; queries shard across GPUs with no exchange, "
-              "since each walk reads only the shared graph, but only the 1-GPU figure is measured. Use --gpus 1.", file=sys.stderr)
+              "since each walk reads only the shared graph, but only the 1-GPU figure is measured. Use --gpus 1.",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -107,20 +156,47 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    dev = torch.device("cuda:0")
-    stream = torch.cuda.current_stream()
     props = torch.cuda.get_device_properties(0)
     log(f"device {props.name} cus={props.multi_processor_count}")
+    ctx = Ctx(np, torch, synth, trw, props, torch.device("cuda:0"))
+    if not args.no_probe and not args.profile_pass:
+        ctx.gather = probe_gather(trw, torch, ctx.dev, props.multi_processor_count)
+        ctx.release()
 
-    wl = synth.WORKLOADS[args.workload]
-    if wl.algo == "mixed":
-        return bench_served(args, wl, np, torch, synth, trw, props)
-    sampler = args.sampler or {"metapath": "its+index", "node2vec": "orej+eidx",
+    if args.workload:
+        wl = synth.WORKLOADS[args.workload]
+        out = bench_served(args, wl, ctx) if wl.algo == "mixed" else bench_batch(args, wl, ctx)
+        if out is not None:
+            print(json.dumps(out), flush=True)
+        return
+
+    nested = {}
+    if not args.no_batch and not args.profile_pass:
+        for name in BATCH_WORKLOADS:
+            t0 = time.time()
+            nested[name] = bench_batch(args, synth.WORKLOADS[name], ctx, nested=True)
+            ctx.release()
+            log(f"nested {name}: {time.time() - t0:.1f}s")
+    out = bench_served(args, synth.WORKLOADS[SERVED_WORKLOAD], ctx)
+    if out is None:
+        return
+    out["batch_workloads"] = nested
+    print(json.dumps(out), flush=True)
+
+
+def bench_batch(args, wl, ctx, nested=False):
+    """One batch workload: every query of the batch walked per launch.  Returns the bench line
+    (nested=True: the same object without the driver's top-level keys, default launch knobs)."""
+    np, torch, synth, trw = ctx.np, ctx.torch, ctx.synth, ctx.trw
+    dev = ctx.dev
+    stream = torch.cuda.current_stream()
+    gather = ctx.gather
+    sampler = (None if nested else args.sampler) or {"metapath": "its+index", "node2vec": "orej+eidx",
                                "deepwalk": "naive+adj"}.get(wl.algo, wl.samplers[0])
     t0 = time.time()
     g = synth.make_graph(wl)
     log(f"graph {wl.name}: n={g.n} m={g.m} dmax={int(g.degrees().max())} ({time.time() - t0:.1f}s)")
-    src_np = synth.make_sources(wl, g, nq=args.nq or None)
+    src_np = synth.make_sources(wl, g, nq=(None if nested else args.nq) or None)
     nq = len(src_np)
     G = trw.Graph(g.row_ptr, g.col, g.weight, g.label, symmetric=wl.symmetric, device="cuda:0")
     nbad = G.validate()
@@ -162,6 +238,8 @@ def main():
 
     def tuning_for():
         t = {}
+        if nested:
+            return None
         if args.wpl:
             t["walkers_per_lane"] = args.wpl
         if args.blocks_per_cu:
@@ -194,7 +272,8 @@ def main():
         del bufs
         return dict(moves=moves, dead_ends=dead, bad_sources=badsrc, wall_s=wall, per_launch_ms=per_launch_ms)
 
-    mode = trw.MODES[args.mode]
+    mode_name = "persistent" if nested else args.mode
+    mode = trw.MODES[mode_name]
     if args.profile_pass:
         # calibration: a plain device copy of exactly 1 GiB, then the walk
         a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
@@ -204,9 +283,9 @@ def main():
         del a, b
         r = run(sampler, mode, 1, max(args.steps, 1), tuning_for())
         log(f"profile pass: {r['moves']} moves per launch, {np.mean(r['per_launch_ms']):.3f} ms per launch")
-        return
+        return None
 
-    log(f"main: {wl.algo}/{sampler} {args.mode} warmup={args.warmup} steps={args.steps}")
+    log(f"main: {wl.algo}/{sampler} {mode_name} warmup={args.warmup} steps={args.steps}")
     main_r = run(sampler, mode, args.warmup, args.steps, tuning_for())
     ms_step = 1000.0 * main_r["wall_s"] / args.steps
     avg_launch_ms = float(np.mean(main_r["per_launch_ms"]))
@@ -222,11 +301,11 @@ def main():
         row_reads = moves + main_r["dead_ends"]
         alg_bytes = 8 * row_reads + entry * moves + 4 * moves + PER_QUERY_BYTES * valid_q + 5 * main_r["bad_sources"]
         achieved = alg_bytes / (avg_launch_ms * 1e-3) / 1e9
-        measured, src = read_traffic(f"{wl.name}_{sampler}_{args.mode}")
+        measured, src = read_traffic(f"{wl.name}_{sampler}_{mode_name}", WALK_SOURCES)
         traffic = measured["total"] if measured else None
         roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBPS, 5), "traffic": traffic,
-                    "kernel": f"k_walk_persistent<{wl.algo},{sampler}>" if args.mode == "persistent"
+                    "kernel": f"k_walk_persistent<{wl.algo},{sampler}>" if mode_name == "persistent"
                     else f"k_bsp_step<{wl.algo},{sampler}>",
                     "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": round(avg_launch_ms, 4),
                     "random_reads_per_launch": row_reads + moves}
@@ -261,7 +340,7 @@ def main():
     if not args.no_variants:
         for s in variant_samplers:
             for mname in ("persistent", "per_step"):
-                if s == sampler and mname == args.mode:
+                if s == sampler and mname == mode_name:
                     continue
                 if ((wl.algo in ("ppr", "deepwalk") and s in ("alias", "its", "rej")) or "+" in s) and s not in tables:
                     continue
@@ -270,7 +349,7 @@ def main():
                 variants[f"{s}/{mname}"] = {"steps_per_s": round(v, 1), "ms_per_batch": round(1000 * r["wall_s"] / 3, 3),
                                             "moves": r["moves"]}
                 log(f"variant {s}/{mname}: {v:.4g} steps/s")
-        if wl.algo in ("ppr", "deepwalk") and sampler.startswith("naive") and args.mode == "persistent":
+        if wl.algo in ("ppr", "deepwalk") and sampler.startswith("naive") and mode_name == "persistent":
             # the general persistent kernel on a graph the LDS path would take
             r = run(sampler, mode, 1, 3, trw.make_tuning(no_lds_graph=1))
             v = r["moves"] * 3 / r["wall_s"]
@@ -447,28 +526,18 @@ def main():
             log(f"variant program: {pm * 3 / wall:.4g} steps/s (compiled in {compile_s:.2f}s)")
             prog.close()
 
-    # Random-gather ceiling of the device (dependent and independent chains).
-    gather = None
-    if not args.no_probe:
-        gather = probe_gather(trw, torch, dev, props.multi_processor_count)
-        if roofline is not None and gather:
-            acc_s = roofline.get("issued_random_reads_per_launch", roofline["random_reads_per_launch"]) / (
-                avg_launch_ms * 1e-3)
-            roofline["issued_random_reads_per_s"] = round(acc_s, 1)
-            roofline["frac_of_dependent_gather_ceiling"] = round(acc_s / gather["dependent_best_reads_per_s"], 4)
-            roofline["frac_of_independent_gather_ceiling"] = round(acc_s / gather["independent_best_reads_per_s"], 4)
-            # Both halves of the traffic against their measured random ceilings: the issued random
-            # reads at the gather rate plus the bytes written (counters) at the 64 B scatter rate.
-            if measured and measured["write"] == measured["write"] and gather.get("scatter"):
-                t_r = roofline.get("issued_random_reads_per_launch", roofline["random_reads_per_launch"]) / \
-                    gather["dependent_best_reads_per_s"]
-                t_w = measured["write"] / (gather["scatter"]["64"]["GBps"] * 1e9)
-                roofline["random_ceiling_ms"] = round(1e3 * (t_r + t_w), 4)
-                roofline["frac_of_random_ceiling"] = round((t_r + t_w) / (avg_launch_ms * 1e-3), 4)
+    # Issued random reads against the device's measured random-gather ceiling.
+    if roofline is not None and gather:
+        acc_s = roofline.get("issued_random_reads_per_launch", roofline["random_reads_per_launch"]) / (
+            avg_launch_ms * 1e-3)
+        roofline["issued_random_reads_per_s"] = round(acc_s, 1)
+        roofline["frac_of_dependent_gather_ceiling"] = round(acc_s / gather["dependent_best_reads_per_s"], 4)
+        roofline["frac_of_independent_gather_ceiling"] = round(acc_s / gather["independent_best_reads_per_s"], 4)
 
     cpu = cpu_par = None
     if not args.no_cpu_baseline:
-        cpu, cpu_par = cpu_baseline(g, wl, sampler, src_np, kw, args.cpu_seconds)
+        cpu, cpu_par = cpu_baseline(g, wl, sampler, src_np, kw,
+                                    args.cpu_seconds_nested if nested else args.cpu_seconds)
 
     # Node2Vec and MetaPath: a move's algorithmic bytes depend on its darts, the
     # adjacency test's probes (binary search in the previous row) and the labels
@@ -490,7 +559,7 @@ def main():
     if roofline is None and per_move is not None:
         alg_bytes = int(per_move * moves + PER_QUERY_BYTES * valid_q + 5 * main_r["bad_sources"])
         achieved = alg_bytes / (avg_launch_ms * 1e-3) / 1e9
-        measured, src = read_traffic(f"{wl.name}_{sampler}_{args.mode}")
+        measured, src = read_traffic(f"{wl.name}_{sampler}_{mode_name}", WALK_SOURCES)
         traffic = measured["total"] if measured else None
         roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBPS, 5), "traffic": traffic,
@@ -511,6 +580,21 @@ def main():
                     acc_s / gather["independent_best_reads_per_s"], 4)
         log(f"roofline ({wl.algo}): {per_move:.2f} algorithmic bytes per move, {achieved:.1f} GB/s")
 
+    # MetaPath without the label index: the row scan's bytes priced by the oracle's label count per move
+    if wl.algo == "metapath" and counts and "its/persistent" in variants:
+        om = max(int(counts.get("moves", 0)), 1)
+        per_scan = 8 + counts["label_reads"] / om + 4 + 4
+        v = variants["its/persistent"]
+        ab = int(per_scan * v["moves"] + PER_QUERY_BYTES * valid_q)
+        ach = ab / (v["ms_per_batch"] * 1e-3) / 1e9
+        v["roofline"] = {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                         "frac": round(ach / HBM_PEAK_GBPS, 5), "alg_bytes_per_move": round(per_scan, 2),
+                         "alg_bytes_per_launch": ab, "kernel": "k_walk_persistent<metapath,its>",
+                         "alg_bytes_from": "oracle label reads per move on the cpu_baseline sample"}
+        traffic, _ = read_traffic(f"{wl.name}_its_persistent", WALK_SOURCES)
+        v["roofline"]["traffic"] = traffic["total"] if traffic else None
+        log(f"metapath row scan: {per_scan:.1f} algorithmic bytes per move, {ach:.1f} GB/s")
+
     out = {
         "metric": "walk steps/sec + % HBM roofline (1 GPU); p50/p99 query latency served",
         "value": round(value, 1),
@@ -524,7 +608,7 @@ def main():
         "vs_baseline": None,
         "dtype": "u32",
         "data": "synthetic",
-        "config": {"workload": f"{wl.name}: {wl.algo} sampler={sampler} mode={args.mode}; R-MAT 2^{wl.scale} "
+        "config": {"workload": f"{wl.name}: {wl.algo} sampler={sampler} mode={mode_name}; R-MAT 2^{wl.scale} "
                                f"{'symmetric' if wl.symmetric else 'directed'} avg deg {wl.avg_degree}"
                                f"{', uint32 weights 1..255' if wl.weights else ''}"
                                f"{', ' + str(wl.labels) + ' labels' if wl.labels else ''}; {nq} queries, max {wl.max_len} moves"
@@ -541,16 +625,26 @@ def main():
         "host_resident": host_res,
         "gather_ceiling": gather,
     }
-    print(json.dumps(out), flush=True)
+    if nested:
+        for k in ("metric", "unit", "n_gpus", "steps", "warmup", "higher_is_better", "scaling", "vs_baseline",
+                  "data", "gather_ceiling"):
+            out.pop(k)
+        out["steps_per_s"] = out.pop("value")
+        out["ms_per_batch"] = out.pop("ms_per_step")
+        out["batches"] = {"timed": args.steps, "warmup": args.warmup}
+    return out
 
 
-def bench_served(args, wl, np, torch, synth, trw, props):
-    """Served mixed workload: Poisson arrivals of requests of 1..4096 queries, each DeepWalk
-    (80 moves, ALIAS), PPR (stop 0.2, ALIAS) or Node2Vec (p=2, q=0.5, 80 moves), on a resident
+
+def bench_served(args, wl, ctx):
+    """Served mixed workload: requests of 1..4096 queries, each DeepWalk (80 moves, ALIAS), PPR
+    (stop 0.2, ALIAS) or Node2Vec (p=2, q=0.5, 80 moves, O-REJ with the edge index), on a resident
     weighted symmetric R-MAT graph; continuous batching with memory admission and graph-captured
-    ticks.  Reports p50/p99 request latency at 0.7x the saturated request rate, and steps/s."""
+    ticks.  Timed: K saturated replays of `serve_replay` requests each (W more warm up).  Then
+    p50/p99 request latency at 0.7x the saturated request rate, with Poisson arrivals."""
     import ctypes
     from paper_2107_11983_amd import _abi
+    np, torch, synth, trw = ctx.np, ctx.torch, ctx.synth, ctx.trw
     t0 = time.time()
     g = synth.make_graph(wl, scale=args.serve_scale or None)
     log(f"graph {wl.name}: n={g.n} m={g.m} dmax={int(g.degrees().max())} ({time.time() - t0:.1f}s)")
@@ -567,98 +661,246 @@ def bench_served(args, wl, np, torch, synth, trw, props):
         if name == "alias":
             alias = tab
         else:
-            adj = tab
+            eidx = tab
     log(f"tables {pre}")
-    n_sat, n_warm, n_meas = 2000, 500, args.serve_requests
-    n_trials = 4                    # saturation replays: a warm-up, then three timed, each on its own requests
-    N = n_trials * n_sat + n_warm + n_meas
-    sizes = 1 + synth.uniform_u32(N, 4096, wl.walk_seed ^ 0x5153).astype(np.int64)
-    kinds = synth.uniform_u32(N, 3, wl.walk_seed ^ 0xA160)
-    offs = np.concatenate([[0], np.cumsum(sizes)])
-    d_src = torch.from_numpy(synth.sources(int(offs[-1]), g.n, wl.src_seed)).cuda()
+    if args.profile_pass:
+        # calibration for the counter passes: a plain device copy of exactly 1 GiB
+        a = torch.empty(1 << 30, dtype=torch.uint8, device=ctx.dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    R, W, K = args.serve_replay, max(args.warmup, 0), max(args.steps, 1)
+    n_lat_warm, n_lat = (0, 0) if args.profile_pass else (500, args.serve_requests)
+    N = (W + K) * R + n_lat_warm + n_lat
+    sizes, kinds, offs, src_np = synth.served_requests(wl, N, g.n)
+    d_src = torch.from_numpy(src_np).cuda()
+    d_kind = torch.repeat_interleave(torch.from_numpy(kinds.astype(np.int8)), torch.from_numpy(sizes)).cuda()
+    stop_q32 = trw.stop_threshold(wl.stop_prob)
+    n2v_thr = trw.n2v_thresholds(*wl.n2v_pq)
     algo_p = [trw.make_params("deepwalk", "alias", 80, wl.walk_seed),
-              trw.make_params("ppr", "alias", 256, wl.walk_seed, stop_q32=trw.stop_threshold(0.2)),
-              trw.make_params("node2vec", "orej", 80, wl.walk_seed, n2v_thr_q16=trw.n2v_thresholds(2.0, 0.5))]
-    strides = [88, 264, 88]
-    path_off = np.concatenate([[0], np.cumsum(sizes * np.array(strides)[kinds])])
-    d_paths = torch.empty(int(path_off[-1]), dtype=torch.int32, device="cuda")
+              trw.make_params("ppr", "alias", 256, wl.walk_seed, stop_q32=stop_q32),
+              trw.make_params("node2vec", "orej", 80, wl.walk_seed, n2v_thr_q16=n2v_thr)]
+    strides = np.array([88, 264, 88])
+    replays = [(i * R, (i + 1) * R) for i in range(W + K)]
+    if n_lat:
+        replays.append(((W + K) * R, N))
+    # Paths: one buffer reused by every replay (rows from its start); lengths and status: a
+    # place for every query, so that the timed replays are tallied after the timed region.
+    path_need = max(int((sizes[lo:hi] * strides[kinds[lo:hi]]).sum()) for lo, hi in replays)
+    d_paths = torch.empty(path_need, dtype=torch.int32, device="cuda")
     d_len = torch.empty(int(offs[-1]), dtype=torch.int32, device="cuda")
     d_st = torch.empty(int(offs[-1]), dtype=torch.uint8, device="cuda")
-    reqs = (_abi.trw_request * N)()
-    for i in range(N):
-        r = reqs[i]
-        r.params = algo_p[kinds[i]]
-        r.nq = int(sizes[i])
-        r.sources = ctypes.c_void_p(d_src.data_ptr() + 4 * int(offs[i]))
-        r.qid_base = i << 32
-        r.paths = ctypes.c_void_p(d_paths.data_ptr() + 4 * int(path_off[i]))
-        r.path_stride = strides[kinds[i]]
-        r.lengths = ctypes.c_void_p(d_len.data_ptr() + 4 * int(offs[i]))
-        r.status = ctypes.c_void_p(d_st.data_ptr() + int(offs[i]))
+
+    def make_reqs(lo, hi):
+        """trw_request array for requests [lo, hi)."""
+        reqs = (_abi.trw_request * (hi - lo))()
+        poff = np.concatenate([[0], np.cumsum(sizes[lo:hi] * strides[kinds[lo:hi]])])
+        for j, i in enumerate(range(lo, hi)):
+            r = reqs[j]
+            r.params = algo_p[kinds[i]]
+            r.nq = int(sizes[i])
+            r.sources = ctypes.c_void_p(d_src.data_ptr() + 4 * int(offs[i]))
+            r.qid_base = i << 32
+            r.paths = ctypes.c_void_p(d_paths.data_ptr() + 4 * int(poff[j]))
+            r.path_stride = int(strides[kinds[i]])
+            r.lengths = ctypes.c_void_p(d_len.data_ptr() + 4 * int(offs[i]))
+            r.status = ctypes.c_void_p(d_st.data_ptr() + int(offs[i]))
+        return reqs
+
+    req_arrays = [make_reqs(lo, hi) for lo, hi in replays]
+    arrivals_zero = [(ctypes.c_uint64 * (hi - lo))() for lo, hi in replays]
+    completions = [(_abi.trw_completion * (hi - lo))() for lo, hi in replays]
+
     torch.cuda.synchronize()
-    slots = props.multi_processor_count * args.serve_slots_per_cu
-    srv = trw.Server(G, alias, adj, pool_bytes=8 << 30, max_slots=slots, max_requests=1024,
+    slots = ctx.props.multi_processor_count * args.serve_slots_per_cu
+    srv = trw.Server(G, alias, eidx, pool_bytes=8 << 30, max_slots=slots, max_requests=1024,
                      steps_per_tick=args.serve_steps, pipelined=bool(args.serve_pipelined))
 
-    def replay(lo, hi, arrivals):
-        comp = (_abi.trw_completion * (hi - lo))()
-        arr = (ctypes.c_uint64 * (hi - lo))(*[int(x) for x in arrivals])
-        m0 = srv.stats()["moves"]
+    def replay(ri, arrivals=None):
+        """Serve replay ri (requests arriving at the given offsets, default all at once)."""
+        lo, hi = replays[ri]
+        arr = arrivals_zero[ri] if arrivals is None else arrivals
+        s0 = srv.stats()
         t = time.perf_counter()
-        rc = _abi.trw_probe_serve_replay(srv.handle, hi - lo, ctypes.byref(reqs, ctypes.sizeof(_abi.trw_request) * lo),
-                                         arr, comp, 600_000)
+        rc = _abi.trw_probe_serve_replay(srv.handle, hi - lo, req_arrays[ri], arr, completions[ri], 600_000)
         wall = time.perf_counter() - t
+        s1 = srv.stats()
         assert rc == 0, f"replay failed: {rc} {_abi.trw_last_error()}"
-        assert all(comp[i].status == 0 for i in range(hi - lo))
-        return comp, wall, srv.stats()["moves"] - m0
+        return completions[ri], wall, {k: s1[k] - s0[k] for k in ("moves", "ticks", "tick_device_ns")}
 
-    # saturation: everything arrives at once; a warm-up replay, then the
-    # median of three (one 20 ms replay varies by tens of percent), each on
-    # requests of its own so that no replay finds the previous one's rows cached
-    trials = []
-    for rep in range(n_trials):
-        comp, wall, moves = replay(rep * n_sat, (rep + 1) * n_sat, np.zeros(n_sat))
-        if rep:
-            trials.append((wall, moves))
-    wall, moves = sorted(trials)[1]
-    sat_rps = n_sat / wall
-    sat_steps = moves / wall
-    st0 = srv.stats()
-    log(f"saturated: {n_sat} requests in {wall:.3f}s (median of {[round(n_sat / w) for w, _ in trials]} req/s) = "
-        f"{sat_rps:.0f} req/s, {sat_steps:.4g} steps/s; {st0['ticks']} ticks, device {st0['tick_device_ns'] / 1e6:.1f} ms")
-    # offered load 0.7x saturation (or a fixed rate), Poisson arrivals (exponential gaps from seeded uniforms)
+    for r in range(W):
+        _, wall, d = replay(r)
+        log(f"warm-up replay {r}: {R / wall:.0f} req/s, {d['moves'] / wall:.4g} steps/s")
+    tick0 = srv.stats()["ticks"]
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    walls, moves, ticks, tick_ns = [], 0, 0, 0
+    for r in range(W, W + K):
+        _, wall, d = replay(r)
+        walls.append(wall)
+        moves += d["moves"]
+        ticks += d["ticks"]
+        tick_ns += d["tick_device_ns"]
+    torch.cuda.synchronize()
+    region = time.perf_counter() - t_start
+    value = moves / region
+    for r in range(W, W + K):
+        lo, hi = replays[r]
+        assert all(completions[r][i].status == 0 for i in range(hi - lo))
+    # per-kind moves, dead ends and queries of the timed replays
+    q_lo, q_hi = int(offs[replays[W][0]]), int(offs[replays[W + K - 1][1]])
+    kq = d_kind[q_lo:q_hi].to(torch.int64)
+    L = d_len[q_lo:q_hi].to(torch.int64)
+    dead = (d_st[q_lo:q_hi] == trw.TRW_ST_DEAD_END).to(torch.int64)
+    per_kind = np.array([[int(torch.where(kq == k, L, 0).sum()), int(torch.where(kq == k, dead, 0).sum()),
+                          int((kq == k).sum())] for k in range(3)])
+    assert int(per_kind[:, 0].sum()) == moves, "moves counted by the server and by the lengths differ"
+    sat_rps = K * R / region
+    log(f"timed: {K} saturated replays of {R} requests, {region:.3f}s: {sat_rps:.0f} req/s, {value:.4g} steps/s; "
+        f"{ticks} ticks (tick {tick0}..{tick0 + ticks - 1} of this server), {tick_ns / max(ticks, 1) / 1e6:.4f} ms "
+        f"device time per tick")
+    if args.profile_pass:
+        srv.close()
+        return None
+
+    # Latency: Poisson arrivals at 0.7x the saturated request rate (or a fixed rate).
     rate = args.serve_rate or 0.7 * sat_rps
-    u = synth.uniform_f64(n_warm + n_meas, wl.walk_seed ^ 0x9015)
+    lat_lo, lat_hi = replays[-1]
+    u = synth.uniform_f64(lat_hi - lat_lo, wl.walk_seed ^ 0x9015)
     arrivals = np.cumsum(-np.log(u) / rate) * 1e9
-    comp, wall, moves = replay(n_trials * n_sat, N, arrivals - arrivals[0])
-    lat = np.array([(comp[i].t_done_ns - comp[i].t_submit_ns) / 1e6 for i in range(n_warm, n_warm + n_meas)])
-    queue = np.array([(comp[i].t_admit_ns - comp[i].t_submit_ns) / 1e6 for i in range(n_warm, n_warm + n_meas)])
-    span = (comp[n_warm + n_meas - 1].t_done_ns - comp[n_warm].t_submit_ns) / 1e9
+    arrivals -= arrivals[0]
+    comp, wall_l, d_l = replay(len(replays) - 1, (ctypes.c_uint64 * (lat_hi - lat_lo))(*[int(x) for x in arrivals]))
+    assert all(comp[i].status == 0 for i in range(lat_hi - lat_lo))
+    lat = np.array([(comp[i].t_done_ns - comp[i].t_submit_ns) / 1e6 for i in range(n_lat_warm, n_lat_warm + n_lat)])
+    queue = np.array([(comp[i].t_admit_ns - comp[i].t_submit_ns) / 1e6 for i in range(n_lat_warm, n_lat_warm + n_lat)])
+    span = (comp[n_lat_warm + n_lat - 1].t_done_ns - comp[n_lat_warm].t_submit_ns) / 1e9
+    log(f"latency at {rate:.0f} req/s offered: p50 {np.percentile(lat, 50):.3f} ms, p99 {np.percentile(lat, 99):.3f} ms")
     st = srv.stats()
     srv.close()
+
+    # The same queries through the batch walker, per kind: the persistent kernel and the plain
+    # one-launch-per-step schedule (the first timed replay's requests).
+    lo, hi = replays[W]
+    batch = {}
+    for k, name in enumerate(synth.SERVED_KINDS):
+        idx = [i for i in range(lo, hi) if kinds[i] == k]
+        src_k = torch.from_numpy(np.concatenate([src_np[offs[i]:offs[i + 1]] for i in idx])).cuda()
+        p = algo_p[k]
+        table = alias if k < 2 else eidx
+        for mname in ("persistent", "per_step"):
+            mode = trw.MODES[mname]
+            bufs = trw.WalkBuffers(G, p, int(src_k.numel()), mode)
+            trw.walk(G, table, p, src_k, mode=mode, bufs=bufs)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(3):
+                trw.walk(G, table, p, src_k, mode=mode, bufs=bufs)
+            b.record()
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b) / 3
+            mv = int(bufs.lengths.to(torch.int64).sum().item())
+            batch.setdefault(mname, {})[name] = {"queries": int(src_k.numel()), "moves": mv, "ms": round(ms, 4)}
+            del bufs
+    for mname, d in batch.items():
+        mv = sum(v["moves"] for v in d.values())
+        ms = sum(v["ms"] for v in d.values())
+        d["all"] = {"moves": mv, "ms": round(ms, 4), "steps_per_s": round(mv / (ms * 1e-3), 1)}
+        log(f"same queries, batch {mname}: {mv / (ms * 1e-3):.4g} steps/s")
+    served_replay_sps = moves / region
+
+    # Oracle on the same requests' queries (1 thread, then the same sample over the host's threads).
+    cpu = cpu_par = None
+    if not args.no_cpu_baseline:
+        cpu, cpu_par = cpu_baseline_served(g, wl, ctx, replays[W], sizes, kinds, offs, src_np, stop_q32, n2v_thr,
+                                           args.cpu_seconds)
+
+    # Roofline of the tick kernel over the timed region: algorithmic bytes of the moves made
+    # (ALIAS moves as the paper's method reads them; Node2Vec's darts and binary-search probes
+    # per move from the oracle's counts on its sample), per tick, over the ticks' device time.
+    counts = (cpu or {}).get("oracle_counters", {}).get("node2vec")
+    moves_k = per_kind[:, 0]
+    dead_k = per_kind[:, 1]
+    queries = int(per_kind[:, 2].sum())
+    if counts and counts.get("moves"):
+        om = counts["moves"]
+        n2v_per_move = 8 + 4 * counts["orej_trials"] / om + 4 * counts["adjacency_probes"] / om + 4
+        darts_per_move = counts["orej_trials"] / om
+        n2v_from = "oracle counters on the cpu_baseline sample, per move"
+    else:
+        n2v_per_move, darts_per_move, n2v_from = None, None, None
+    alias_per_move = 8 + ENTRY_BYTES["alias"] + 4
+    roofline = None
+    if ticks and n2v_per_move is not None:
+        alg_bytes = (alias_per_move * (moves_k[0] + moves_k[1]) + n2v_per_move * moves_k[2] + 8 * dead_k.sum()
+                     + PER_QUERY_BYTES * queries)
+        dev_s = tick_ns * 1e-9
+        achieved = alg_bytes / dev_s / 1e9
+        measured, _ = read_traffic(f"{wl.name}_serve_tick", SERVE_SOURCES)
+        roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBPS, 5), "traffic": measured["total"] if measured else None,
+                    "kernel": "k_serve_tick", "launches": ticks, "avg_launch_ms": round(tick_ns / ticks / 1e6, 4),
+                    "alg_bytes_per_launch": int(alg_bytes / ticks),
+                    "alg_bytes_per_move": {"deepwalk_alias": alias_per_move, "ppr_alias": alias_per_move,
+                                           "node2vec_orej": round(n2v_per_move, 3)},
+                    "alg_bytes_from": f"ALIAS: row range, threshold and two destination ids, path entry; "
+                                      f"Node2Vec: {n2v_from}",
+                    "moves_by_kind": {k: int(v) for k, v in zip(synth.SERVED_KINDS, moves_k)},
+                    "device_time_s": round(dev_s, 4), "timed_region_s": round(region, 4),
+                    "device_busy_frac": round(dev_s / region, 4)}
+        if measured:
+            roofline["traffic_frac_of_peak"] = round(measured["total"] / (tick_ns / ticks * 1e-9) / 1e9 /
+                                                     HBM_PEAK_GBPS, 4)
+            roofline["l2_hit_rate"] = measured.get("l2_hit_rate")
+            roofline["traffic_method"] = measured.get("method")
+        if ctx.gather:
+            # one random read per ALIAS move (the fused 32-byte entry), per Node2Vec dart (its
+            # 16-byte adjacency record) and per query (the source's row range); the edge-set
+            # probes of Node2Vec's neighbourhood test come on top, so this is a lower bound
+            reads = (moves_k[0] + moves_k[1]) + darts_per_move * moves_k[2] + queries
+            rs = reads / dev_s
+            roofline["issued_random_reads_lower_bound_per_launch"] = int(reads / ticks)
+            roofline["issued_random_reads_per_s"] = round(rs, 1)
+            roofline["frac_of_dependent_gather_ceiling"] = round(rs / ctx.gather["dependent_best_reads_per_s"], 4)
+        log(f"roofline (serve tick): {achieved:.1f} GB/s algorithmic, frac {achieved / HBM_PEAK_GBPS:.4f}")
+
     out = {
         "metric": "walk steps/sec + % HBM roofline (1 GPU); p50/p99 query latency served",
-        "value": round(moves / wall, 1), "unit": "steps/s", "n_gpus": 1, "steps": n_meas, "warmup": n_warm,
-        "ms_per_step": round(1000 * wall / (n_warm + n_meas), 4), "higher_is_better": True, "scaling": "weak",
+        "value": round(value, 1), "unit": "steps/s", "n_gpus": 1, "steps": K, "warmup": W,
+        "ms_per_step": round(1000 * region / K, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u32", "data": "synthetic",
         "config": {"workload": f"{wl.name}: served mix of DeepWalk-80 ALIAS / PPR-0.2 ALIAS / Node2Vec p=2 q=0.5 "
-                               f"len 80, requests of U{{1..4096}} queries, Poisson arrivals at "
+                               f"len 80 (O-REJ, edge index), requests of U{{1..4096}} queries; a step is one "
+                               f"saturated replay of {R} requests (all submitted at once, continuous batching); "
+                               f"latency at Poisson arrivals "
                                f"{'%.0f req/s' % args.serve_rate if args.serve_rate else '0.7x saturation'}; "
                                f"R-MAT 2^{int(np.log2(g.n))} symmetric avg deg {wl.avg_degree}, uint32 weights 1..255",
-                   "n": g.n, "m": g.m, "parallelism": "1 GPU"},
+                   "n": g.n, "m": g.m, "requests_per_step": R, "queries_timed": queries, "moves_timed": moves,
+                   "parallelism": "1 GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "cpu_baseline_parallel": cpu_par,
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3), "p99": round(float(np.percentile(lat, 99)), 3),
                        "mean": round(float(lat.mean()), 3), "queue_p50": round(float(np.percentile(queue, 50)), 3),
-                       "queue_p99": round(float(np.percentile(queue, 99)), 3)},
-        "offered_req_per_s": round(rate, 1), "achieved_req_per_s": round(n_meas / span, 1),
-        "saturated": {"req_per_s": round(sat_rps, 1), "steps_per_s": round(sat_steps, 1),
-                      "trials_req_per_s": [round(n_sat / w, 1) for w, _ in trials]},
+                       "queue_p99": round(float(np.percentile(queue, 99)), 3), "requests": n_lat,
+                       "warmup_requests": n_lat_warm},
+        "offered_req_per_s": round(rate, 1), "achieved_req_per_s": round(n_lat / span, 1),
+        "steps_per_s_at_offered": round(d_l["moves"] / wall_l, 1),
+        "saturated": {"req_per_s": round(sat_rps, 1), "steps_per_s": round(value, 1),
+                      "replay_req_per_s": [round(R / w, 1) for w in walls]},
+        "same_queries_batch_walker": batch,
+        "served_vs_batch": {"served_saturated_steps_per_s": round(served_replay_sps, 1),
+                            "vs_persistent": round(served_replay_sps / batch["persistent"]["all"]["steps_per_s"], 4),
+                            "vs_per_step": round(served_replay_sps / batch["per_step"]["all"]["steps_per_s"], 4)},
         "server": {"ticks": st["ticks"], "steps_per_tick": args.serve_steps, "slots": slots,
-                   "pipelined": bool(args.serve_pipelined),
-                   "max_requests": 1024, "pool_bytes": st["pool_bytes"],
-                   "tick_device_ms_mean": round(st["tick_device_ns"] / max(st["ticks"], 1) / 1e6, 4)},
+                   "pipelined": bool(args.serve_pipelined), "max_requests": 1024, "pool_bytes": st["pool_bytes"],
+                   "timed_ticks": ticks, "first_timed_tick": tick0},
         "preprocess_ms": pre,
+        "gather_ceiling": ctx.gather,
     }
-    print(json.dumps(out), flush=True)
+    del G, alias, eidx, d_paths, d_len, d_st, d_src, d_kind, req_arrays, completions
+    return out
 
 
 def probe_gather(trw, torch, dev, cus):
@@ -761,13 +1003,14 @@ def cpu_baseline(g, wl, sampler, src_np, kw, target_s):
             counters[k] = counters.get(k, 0) + int(v)
         del r
     log(f"cpu baseline: {nsamp} queries, {moves} moves in {dt:.2f}s")
+    info = host_info()
     single = {"value": round(moves / dt, 1), "unit": "steps/s", "cores": 1, "kind": "oracle",
               "sample": f"first {nsamp} of {len(src_np)} queries of the same batch ({moves} moves, {dt:.1f} s, "
-                        f"single thread, tables prebuilt)", "oracle_counters": counters}
+                        f"single thread, tables prebuilt)", "oracle_counters": counters, **info}
     # The same sample sharded by query range over the host's cores (the
     # oracle unchanged; ctypes releases the interpreter lock during each call).
     import concurrent.futures
-    workers = max(1, min(16, os.cpu_count() or 1))
+    workers = max(1, min(BOX_CPU_SHARE, info["nproc"] or 1))
     shard = max(1, min(-(-nsamp // workers), piece))
     ranges = [(lo, min(nsamp, lo + shard)) for lo in range(0, nsamp, shard)]
 
@@ -783,7 +1026,65 @@ def cpu_baseline(g, wl, sampler, src_np, kw, target_s):
     log(f"cpu baseline, {workers} threads: {pmoves} moves in {pdt:.2f}s")
     parallel = {"value": round(pmoves / pdt, 1), "unit": "steps/s", "cores": workers, "kind": "oracle",
                 "sample": f"the same {nsamp} queries in {len(ranges)} query ranges over {workers} threads "
-                          f"({pdt:.1f} s)"}
+                          f"({pdt:.1f} s)", **info}
+    return single, parallel
+
+
+def cpu_baseline_served(g, wl, ctx, replay, sizes, kinds, offs, src_np, stop_q32, n2v_thr, target_s):
+    """The oracle (single-threaded C) on the requests of one timed replay, in submission order,
+    until about target_s of walking: one thread, then the same requests spread over the host's
+    threads.  Returns (single, parallel); single carries the oracle's counters per request kind."""
+    import synth
+    try:
+        import oracle
+        oracle._load()
+    except Exception as e:  # the oracle is test infrastructure; the GPU number does not depend on it
+        log(f"cpu baseline skipped: {e}")
+        return None, None
+    t0 = time.time()
+    thr, al = oracle.alias_build(g.row_ptr, g.weight)
+    log(f"cpu baseline: oracle ALIAS table {time.time() - t0:.1f}s")
+    params = [oracle.WalkParams(oracle.DEEPWALK, oracle.ALIAS, 80, wl.walk_seed),
+              oracle.WalkParams(oracle.PPR, oracle.ALIAS, 256, wl.walk_seed, stop_q32=stop_q32),
+              oracle.WalkParams(oracle.NODE2VEC, oracle.OREJ, 80, wl.walk_seed, n2v_thr_q16=tuple(n2v_thr))]
+
+    def run(i):
+        k = int(kinds[i])
+        kw = dict(thr=thr, alias=al) if k < 2 else {}
+        r = oracle.walk(g.row_ptr, g.col, params[k], src_np[offs[i]:offs[i + 1]], qid_base=i << 32, **kw)
+        return k, int(r.lengths.sum()), r.counters
+
+    lo, hi = replay
+    done, moves, dt = [], 0, 0.0
+    counters = {name: {} for name in synth.SERVED_KINDS}
+    for i in range(lo, hi):
+        t = time.perf_counter()
+        k, mv, c = run(i)
+        dt += time.perf_counter() - t
+        done.append(i)
+        moves += mv
+        for key, v in c.items():
+            counters[synth.SERVED_KINDS[k]][key] = counters[synth.SERVED_KINDS[k]].get(key, 0) + int(v)
+        if dt >= target_s:
+            break
+    nq = int(sum(sizes[i] for i in done))
+    log(f"cpu baseline: {len(done)} requests, {nq} queries, {moves} moves in {dt:.2f}s")
+    info = host_info()
+    single = {"value": round(moves / dt, 1), "unit": "steps/s", "cores": 1, "kind": "oracle",
+              "sample": f"the first {len(done)} requests ({nq} queries, {moves} moves) of the first timed replay, "
+                        f"in submission order, one thread, ALIAS table prebuilt ({dt:.1f} s)",
+              "oracle_counters": counters, **info}
+    import concurrent.futures
+    workers = max(1, min(BOX_CPU_SHARE, info["nproc"] or 1))
+    t = time.perf_counter()
+    with concurrent.futures.ThreadPoolExecutor(max_workers=workers) as ex:
+        pmoves = sum(mv for _, mv, _ in ex.map(run, done))
+    pdt = time.perf_counter() - t
+    assert pmoves == moves
+    log(f"cpu baseline, {workers} threads: {pmoves} moves in {pdt:.2f}s")
+    parallel = {"value": round(pmoves / pdt, 1), "unit": "steps/s", "cores": workers, "kind": "oracle",
+                "sample": f"the same {len(done)} requests, one per task, over {workers} threads ({pdt:.1f} s)", **info}
+    del thr, al
     return single, parallel
 
 

@@ -227,3 +227,17 @@ def make_sources(wl: Workload, g: CSRGraph, nq: Optional[int] = None) -> np.ndar
 def make_schema(wl: Workload) -> np.ndarray:
     """MetaPath schema: schema_len labels drawn with replacement from the label set."""
     return uniform_u32(wl.schema_len, wl.labels, wl.walk_seed ^ 0x5C4E3A).astype(np.uint8)
+
+
+SERVED_KINDS = ("deepwalk", "ppr", "node2vec")    # request kinds of the served mix, in draw order
+
+
+def served_requests(wl: Workload, count: int, n: int):
+    """The served workload's first `count` requests: sizes uniform in 1..4096, kinds (indexes
+    into SERVED_KINDS), query offsets (count + 1) and the sources of all their queries, uniform
+    in [0, n).  Every draw depends only on its index, so the first k requests are the same for
+    any count."""
+    sizes = 1 + uniform_u32(count, 4096, wl.walk_seed ^ 0x5153).astype(np.int64)
+    kinds = uniform_u32(count, 3, wl.walk_seed ^ 0xA160).astype(np.int64)
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    return sizes, kinds, offs, sources(int(offs[-1]), n, wl.src_seed)
