@@ -162,14 +162,21 @@ trw_status trw_program_walk(trw_program prog, trw_graph g, trw_table table, cons
             a.prefix = static_cast<const uint64_t *>(buf);
         } else {
             a.rej = static_cast<const uint4 *>(buf);
-            a.pmax = reinterpret_cast<const uint32_t *>(static_cast<const char *>(buf) + rej_records_bytes(gd.m));
+            a.g.pmax = reinterpret_cast<const uint32_t *>(static_cast<const char *>(buf) + rej_records_bytes(gd.m));
         }
     } else if (table) {
-        if (!table_view(table, kEdgeIndexKind, &buf, &tg) || tg != g)
-            return pfail(TRW_E_INVALID, "a NAIVE / dynamic program takes an edge index of this graph or no table");
-        a.g.eset = reinterpret_cast<const unsigned long long *>(static_cast<const char *>(buf) +
-                                                                edge_index_records_bytes(gd.m));
-        a.g.eset_mask = eset_slots(gd.m) - 1;
+        // a NAIVE or dynamic program: an edge index (for is_neighbor) or a REJ
+        // table (for the per-vertex bound p*, Walker::pm)
+        if (table_view(table, kEdgeIndexKind, &buf, &tg) && tg == g) {
+            a.g.eset = reinterpret_cast<const unsigned long long *>(static_cast<const char *>(buf) +
+                                                                    edge_index_records_bytes(gd.m));
+            a.g.eset_mask = eset_slots(gd.m) - 1;
+        } else if (table_view(table, TRW_S_REJ, &buf, &tg) && tg == g) {
+            a.g.pmax = reinterpret_cast<const uint32_t *>(static_cast<const char *>(buf) + rej_records_bytes(gd.m));
+        } else {
+            return pfail(TRW_E_INVALID,
+                         "a NAIVE / dynamic program takes an edge index or a REJ table of this graph, or no table");
+        }
     }
     if (nq == 0) return TRW_OK;
     if (!d_sources || !d_paths || !d_lengths || !d_status)

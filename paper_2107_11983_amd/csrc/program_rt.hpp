@@ -5,13 +5,17 @@
 //
 //   struct TrwProgram {
 //       static constexpr uint32_t kind = trw_prog::DYNAMIC_REJ;   // the sampling method
-//       // Weight of moving along edge slot `slot` of the current row (to
-//       // g.col[slot]; g.weight[slot], g.label[slot] when the graph has them)
-//       // for the walker as it stands:
-//       //   DYNAMIC_REJ: the acceptance Weight / MaxWeight as Q16 in [0, 65536];
-//       //   DYNAMIC_ITS: an integer weight (a row's weights must sum below 2^32).
-//       __device__ uint32_t weight(const trw_prog::Walker &w, const trw_prog::Graph &g,
+//       // Weight (the paper's Weight): the transition weight of edge slot
+//       // `slot` of the current row (to g.col[slot]; g.weight[slot],
+//       // g.label[slot] when the graph has them) for the walker as it
+//       // stands.  Used by DYNAMIC_REJ and DYNAMIC_ITS; a row's weights must
+//       // sum below 2^64.
+//       __device__ uint64_t weight(const trw_prog::Walker &w, const trw_prog::Graph &g,
 //                                  const trw_prog::Params &p, uint32_t slot) const;
+//       // MaxWeight (DYNAMIC_REJ only): a bound on weight() over the current
+//       // row; 0 means the row has no transition (the walk ends, DEAD_END).
+//       __device__ uint64_t max_weight(const trw_prog::Walker &w, const trw_prog::Graph &g,
+//                                      const trw_prog::Params &p) const;
 //       // Update after a move (w already at the new vertex, w.k moves made):
 //       // true ends the walk (status STOPPED).  r2 is the step's third random word
 //       // (for the rejection kinds: that of the dart that was accepted).
@@ -27,9 +31,12 @@
 //   STATIC_REJ    darts t = 0, 1, ...: slot mulhi32(r0, d), accept iff
 //                 r1 * p*_v < w * 2^32, p*_v the row's largest weight (REJ table)
 //   DYNAMIC_REJ   darts t = 0, 1, ...: slot mulhi32(r0, d), accept iff
-//                 (r1 >> 16) < weight (O-REJ with the program's bound)
-//   DYNAMIC_ITS   weights of the row computed on the fly, W their sum,
-//                 j = mulhi32(r0, W), the slot whose prefix range holds j
+//                 r1 * MaxWeight < Weight(slot) * 2^32, compared exactly (the
+//                 dart height y = r1 * MaxWeight / 2^32 is uniform in
+//                 [0, MaxWeight); the move is taken iff y < Weight)
+//   DYNAMIC_ITS   weights of the row computed on the fly, W their sum; the
+//                 draw j = mulhi32(r0, W) while W < 2^32, else the high half
+//                 of (r1:r0) * W; the slot whose running-sum range holds j
 // A walk ends after max_len moves (LENGTH), when update says so (STOPPED,
 // checked first), or when the row has no transition (DEAD_END).  DeepWalk,
 // PPR, Node2Vec and MetaPath written as programs give the built-in walks'
@@ -67,6 +74,7 @@ struct Graph {
     uint32_t pad;
     const unsigned long long *eset;     // edge index hash set, or NULL
     unsigned long long eset_mask;
+    const uint32_t *pmax;               // with a REJ table: p* per vertex (its row's largest weight), else NULL
 
     __device__ int32_t row_off(int32_t v) const { return row_ptr[v]; }
     __device__ uint32_t degree(int32_t v) const { return (uint32_t)(row_ptr[v + 1] - row_ptr[v]); }
@@ -91,7 +99,7 @@ struct Walker {
     int32_t src, cur, prev;   // prev = -1 before the first move
     int32_t off;           // cur's row
     uint32_t deg;
-    uint32_t pm;           // STATIC_REJ: p* of cur (its row's largest weight)
+    uint32_t pm;           // with a REJ table (g.pmax): p* of cur (its row's largest weight), else 0
 };
 
 struct Params {
@@ -106,7 +114,6 @@ struct Args {
     const uint4 *alias;            // STATIC_ALIAS: 32-byte entries per slot
     const uint64_t *prefix;        // STATIC_ITS: inclusive prefix per row
     const uint4 *rej;              // STATIC_REJ: 32-byte slot records {w, dst, row(dst)}, {p*(dst), ...}
-    const uint32_t *pmax;          // STATIC_REJ: p* per vertex
     const int32_t *sources;
     uint32_t nq, chunk;
     uint64_t qid_base;
@@ -118,6 +125,13 @@ struct Args {
     Params p;
 };
 
+// DYNAMIC_ITS's draw in [0, W): mulhi32(r0, W) while W fits 32 bits (so a
+// 0/1 weighting picks the j-th match exactly as the built-in MetaPath does),
+// else the high half of the 64-bit word (r1:r0) times W.
+__device__ __forceinline__ uint64_t dynamic_its_draw(uint32_t r0, uint32_t r1, uint64_t W) {
+    return W < (1ull << 32) ? (uint64_t)scale32(r0, (uint32_t)W) : scale64(r0, r1, W);
+}
+
 // One move of walker w under program P; returns the next vertex or -1.  For
 // the rejection kinds r ends as the accepted dart's block.
 template <class P>
@@ -126,21 +140,21 @@ __device__ __forceinline__ int32_t program_move(const P &prog, const Args &a, co
     const Graph &g = a.g;
     if (w.deg == 0) return -1;
     int32_t nxt = -1;
-    if (P::kind == STATIC_NAIVE) {
+    if constexpr (P::kind == STATIC_NAIVE) {
         nxt = g.col[w.off + scale32(r.r0, w.deg)];
-    } else if (P::kind == STATIC_ALIAS) {
+    } else if constexpr (P::kind == STATIC_ALIAS) {
         const uint64_t e = (uint64_t)(w.off + scale32(r.r0, w.deg));
         int32_t o, d;
         nxt = alias_pick(a.alias[2 * e], a.alias[2 * e + 1], r.r1, o, d);
         if (nxt >= 0) { noff = o; ndeg = (uint32_t)d; }
         return nxt;
-    } else if (P::kind == STATIC_ITS) {
+    } else if constexpr (P::kind == STATIC_ITS) {
         const uint64_t *pr = a.prefix + w.off;
         const uint64_t W = pr[w.deg - 1];
         if (W == 0) return -1;
         const uint64_t x = scale64(r.r0, r.r1, W);
         nxt = g.col[w.off + its_search(pr, w.deg, x, ((uint64_t)r.r1 << 32) | r.r0)];
-    } else if (P::kind == STATIC_REJ) {
+    } else if constexpr (P::kind == STATIC_REJ) {
         if (w.pm == 0) return -1;
         for (uint32_t t = 0;; ++t) {
             if (t > 0) r = philox(w.k, t, w.qid, a.p.seed);
@@ -153,11 +167,14 @@ __device__ __forceinline__ int32_t program_move(const P &prog, const Args &a, co
                 return (int32_t)rec.y;
             }
         }
-    } else if (P::kind == DYNAMIC_REJ) {
+    } else if constexpr (P::kind == DYNAMIC_REJ) {
+        const uint64_t bound = prog.max_weight(w, g, a.p);
+        if (bound == 0) return -1;
         for (uint32_t t = 0;; ++t) {
             if (t > 0) r = philox(w.k, t, w.qid, a.p.seed);
             const uint32_t slot = (uint32_t)w.off + scale32(r.r0, w.deg);
-            if (t + 1 == kMaxDarts || (r.r1 >> 16) < prog.weight(w, g, a.p, slot)) {
+            if (t + 1 == kMaxDarts ||
+                (unsigned __int128)r.r1 * bound < ((unsigned __int128)prog.weight(w, g, a.p, slot) << 32)) {
                 nxt = g.col[slot];
                 break;
             }
@@ -166,7 +183,7 @@ __device__ __forceinline__ int32_t program_move(const P &prog, const Args &a, co
         uint64_t W = 0;
         for (uint32_t i = 0; i < w.deg; ++i) W += prog.weight(w, g, a.p, (uint32_t)w.off + i);
         if (W == 0) return -1;
-        const uint32_t j = scale32(r.r0, (uint32_t)W);
+        const uint64_t j = dynamic_its_draw(r.r0, r.r1, W);
         uint64_t acc = 0;
         for (uint32_t i = 0; i < w.deg; ++i) {
             const uint32_t slot = (uint32_t)w.off + i;
@@ -174,7 +191,11 @@ __device__ __forceinline__ int32_t program_move(const P &prog, const Args &a, co
             if (j < acc) { nxt = g.col[slot]; break; }
         }
     }
-    if (nxt >= 0) { noff = g.row_ptr[nxt]; ndeg = (uint32_t)(g.row_ptr[nxt + 1] - noff); }
+    if (nxt >= 0) {
+        noff = g.row_ptr[nxt];
+        ndeg = (uint32_t)(g.row_ptr[nxt + 1] - noff);
+        if (g.pmax) npm = g.pmax[nxt];
+    }
     return nxt;
 }
 
@@ -207,8 +228,8 @@ __device__ __forceinline__ void wave_its_moves(const P &prog, const Args &a, con
         Walker v;                                    // the owner's walker, in every lane
         v.qid = __shfl(w.qid, o); v.k = __shfl(w.k, o); v.src = __shfl(w.src, o);
         v.cur = __shfl(w.cur, o); v.prev = __shfl(w.prev, o); v.off = __shfl(w.off, o);
-        v.deg = __shfl(w.deg, o);
-        const uint32_t r0 = __shfl(r.r0, o);
+        v.deg = __shfl(w.deg, o); v.pm = __shfl(w.pm, o);
+        const uint32_t r0 = __shfl(r.r0, o), r1 = __shfl(r.r1, o);
         uint64_t W = 0;
         for (uint32_t base = 0; base < v.deg; base += 256) {
             uint64_t part = 0;
@@ -221,7 +242,7 @@ __device__ __forceinline__ void wave_its_moves(const P &prog, const Args &a, con
         }
         int32_t pick = -1;
         if (W != 0) {
-            const uint64_t j = scale32(r0, (uint32_t)W);
+            const uint64_t j = dynamic_its_draw(r0, r1, W);
             uint64_t acc = 0;
             for (uint32_t base = 0; base < v.deg; base += 256) {
                 uint32_t wq[4];
@@ -291,7 +312,7 @@ __device__ void run(const Args &a) {
                     qi = q;
                     w.qid = a.qid_base + q; w.k = 0; w.src = s; w.cur = s; w.prev = -1;
                     w.off = g.row_ptr[s]; w.deg = (uint32_t)(g.row_ptr[s + 1] - w.off);
-                    if (P::kind == STATIC_REJ) w.pm = a.pmax[s];
+                    if (g.pmax) w.pm = g.pmax[s];
                     path.start(a.paths + (uint64_t)q * a.stride);
                     path.push(s);
                 }
@@ -311,6 +332,7 @@ __device__ void run(const Args &a) {
                 nxt = program_move(prog, a, w, r, noff, ndeg, npm);
             } else if (nxt >= 0) {
                 noff = g.row_ptr[nxt]; ndeg = (uint32_t)(g.row_ptr[nxt + 1] - noff);
+                if (g.pmax) npm = g.pmax[nxt];
             }
             uint8_t st = 0;
             if (nxt < 0) {

@@ -2,8 +2,10 @@
 
 DeepWalk, PPR, Node2Vec and MetaPath written as programs must give the
 built-in walks' outputs bit for bit, and so the oracle's.  Weighted Node2Vec,
-which has no built-in walk, is checked against its exact second-order law on
-a small graph.
+Node2Vec by dynamic ITS and the weighted walk by rejection, which have no
+built-in walk, must give the oracle's walks of the same name bit for bit
+(weights in [1, 255], with the per-vertex bound of a REJ table and with a
+global bound), and follow their exact laws on small graphs.
 """
 import numpy as np
 import pytest
@@ -128,11 +130,88 @@ def test_metapath_program_equals_builtin_and_oracle(env):
     prog.close()
 
 
+@pytest.mark.parametrize("bound", ["rej_table", "global", "global+eidx"])
+@pytest.mark.parametrize("graph", ["sym", "dir"])
+def test_weighted_node2vec_program_equals_oracle(env, graph, bound):
+    """Weighted Node2Vec (transition weight w(e) times the second-order factor) by rejection:
+    a dart hits iff r1 * bound < w * factor * 2^16, exactly, as the oracle's."""
+    case = env[graph]
+    g, G = case["g"], case["G"]
+    assert g.weight.min() >= 1 and g.weight.max() <= 255
+    src = _sources(g.n, 8)
+    d_src = torch.from_numpy(src).cuda()
+    prog = trw.Program(trw.programs.WEIGHTED_NODE2VEC)
+    table = {"rej_table": case["rej"], "global": None, "global+eidx": case["eidx"]}[bound]
+    pmax = oracle.rej_build(g.row_ptr, g.weight) if bound == "rej_table" else np.full(g.n, 255, np.uint32)
+    for pq in ((2.0, 0.5), (0.25, 4.0)):
+        thr = trw.n2v_thresholds(*pq)
+        got = _np(*prog.walk(G, table, d_src, 40, 321, user=tuple(thr) + (255,), qid_base=1 << 36))
+        op = oracle.WalkParams(oracle.NODE2VEC, oracle.REJ, 40, 321, n2v_thr_q16=tuple(thr))
+        orc = oracle.walk(g.row_ptr, g.col, op, src, qid_base=1 << 36, weight=g.weight, pmax=pmax)
+        _same(got, (orc.paths, orc.lengths, orc.status), 40)
+        log(f"  {graph} {bound} p,q={pq}: {int(orc.lengths.sum())} moves identical")
+    prog.close()
+
+
+@pytest.mark.parametrize("index", [False, True])
+@pytest.mark.parametrize("graph", ["sym", "dir"])
+def test_node2vec_its_program_equals_oracle(env, graph, index):
+    """Node2Vec by dynamic ITS (lane scans below 128 slots, wave scans above) against the oracle."""
+    case = env[graph]
+    g, G = case["g"], case["G"]
+    assert g.degrees().max() >= 128
+    src = _sources(g.n, 9)
+    d_src = torch.from_numpy(src).cuda()
+    prog = trw.Program(trw.programs.NODE2VEC_ITS)
+    for thr in (trw.n2v_thresholds(2.0, 0.5), (1, 2, 4), (0, 7, 3)):
+        got = _np(*prog.walk(G, case["eidx"] if index else None, d_src, 30, 55, user=tuple(thr)))
+        op = oracle.WalkParams(oracle.NODE2VEC, oracle.ITS, 30, 55, n2v_thr_q16=tuple(thr))
+        orc = oracle.walk(g.row_ptr, g.col, op, src)
+        _same(got, (orc.paths, orc.lengths, orc.status), 30)
+        log(f"  {graph} thresholds {tuple(thr)}: {int(orc.lengths.sum())} moves identical")
+    prog.close()
+
+
+def test_node2vec_its_program_wide_draw():
+    """A hub of 70,000 slots: the first move's total 65536 * d exceeds 2^32, so the draw is the
+    high half of (r1:r0) * W (wave scan), as in the oracle."""
+    from helpers import star
+    g = star(70_000)
+    G = trw.Graph(g.row_ptr, g.col, None)
+    assert G.validate() == 0
+    src = np.concatenate([np.zeros(3000), np.arange(1, 200)]).astype(np.int32)
+    prog = trw.Program(trw.programs.NODE2VEC_ITS)
+    thr = trw.n2v_thresholds(2.0, 0.5)
+    got = _np(*prog.walk(G, None, torch.from_numpy(src).cuda(), 6, 4, user=tuple(thr)))
+    orc = oracle.walk(g.row_ptr, g.col, oracle.WalkParams(oracle.NODE2VEC, oracle.ITS, 6, 4, n2v_thr_q16=tuple(thr)),
+                      src)
+    _same(got, (orc.paths, orc.lengths, orc.status), 6)
+    assert len(np.unique(got[0][:3000, 1])) > 2500
+    prog.close()
+
+
+@pytest.mark.parametrize("bound", ["rej_table", "global"])
+def test_weighted_rej_program_equals_oracle(env, bound):
+    """The weighted walk by rejection against the oracle's REJ with the same bound (the row's
+    largest weight from a REJ table, or 255 for every row)."""
+    case = env["dir"]
+    g, G = case["g"], case["G"]
+    src = _sources(g.n, 10)
+    prog = trw.Program(trw.programs.WEIGHTED_REJ)
+    got = _np(*prog.walk(G, case["rej"] if bound == "rej_table" else None, torch.from_numpy(src).cuda(), 50, 66,
+                         user=(255,)))
+    pmax = oracle.rej_build(g.row_ptr, g.weight) if bound == "rej_table" else np.full(g.n, 255, np.uint32)
+    orc = oracle.walk(g.row_ptr, g.col, oracle.WalkParams(oracle.DEEPWALK, oracle.REJ, 50, 66), src,
+                      weight=g.weight, pmax=pmax)
+    _same(got, (orc.paths, orc.lengths, orc.status), 50)
+    prog.close()
+
+
 def test_weighted_node2vec_second_order_law(env):
     """Two-move walks on a small weighted graph: the second move's frequencies
     against the exact law P(x | prev, cur) ~ factor(prev, x) * w(cur, x)."""
-    # triangle 0-1-2 with a tail 2-3 and a chord 1-3; weights 1..8 so that
-    # factor_q16 * w / 8 is an integer and the acceptance is exact
+    # triangle 0-1-2 with a tail 2-3 and a chord 1-3; a global bound of 255 that divides
+    # none of the products factor * w (the acceptance is compared exactly)
     pairs = [(0, 1), (1, 2), (0, 2), (2, 3), (1, 3)]
     weights = [3, 5, 2, 8, 1]
     gt = undirected(4, pairs, weights=weights)
@@ -142,7 +221,7 @@ def test_weighted_node2vec_second_order_law(env):
     thr = trw.n2v_thresholds(2.0, 0.5)          # 16384, 32768, 65536
     nq = 1 << 20
     d_src = torch.ones(nq, dtype=torch.int32, device="cuda")      # every walk starts at vertex 1
-    P, L, S = _np(*prog.walk(G, None, d_src, 2, 2024, user=tuple(thr) + (8,)))
+    P, L, S = _np(*prog.walk(G, None, d_src, 2, 2024, user=tuple(thr) + (255,)))
     assert (L == 2).all()
     rp, col, w = gt.row_ptr, gt.col, gt.weight
     adj = {(int(u), int(col[e])): int(w[e]) for u in range(4) for e in range(rp[u], rp[u + 1])}
@@ -254,7 +333,7 @@ def test_weighted_rej_program_law():
     assert G.validate() == 0
     prog = trw.Program(trw.programs.WEIGHTED_REJ)
     d_src = torch.zeros(1 << 20, dtype=torch.int32, device="cuda")
-    P, L, S = _np(*prog.walk(G, None, d_src, 1, 5, user=(16,)))    # 16 bounds every weight (exact Q16)
+    P, L, S = _np(*prog.walk(G, None, d_src, 1, 5, user=(255,)))    # 255 bounds every weight
     assert (L == 1).all()
     counts = np.bincount(P[:, 1], minlength=5)[1:]
     _, pval = scipy.stats.chisquare(counts, np.array([1, 2, 3, 10]) / 16 * counts.sum())
