@@ -39,12 +39,21 @@ namespace {
 
 // ---------------------------------------------------------------------------
 // MetaPath Gather (the dynamic walk: only edges whose label is the schema's
-// label for this move are eligible).  Degree-bucketed: a lane compares the
-// labels of a short row four at a time (SWAR on 32-bit words); rows of at
-// least `coop` labels are scanned by the whole wave, 256 bytes per coalesced
-// load, one such row after another.  With a label index (rows sorted by
-// label, per-vertex label offsets) the Gather is two reads instead.
+// label for this move are eligible).  Degree-bucketed:
+//  * a row below `coop` labels is scanned by its own lane, 16 bytes per load
+//    with kScanLoads loads in flight: one pass counts the matches m, a second
+//    stops at the block that holds the j-th one (j = mulhi32(r0, m));
+//  * a longer row is scanned by the whole wave, 1 KiB per coalesced load
+//    round (16 bytes a lane), the wave's rows one after another.  The row's
+//    1 KiB chunks fall into 64 segments whose match counts stay in the lanes'
+//    registers (lane s holds segment s), so the second pass rereads one
+//    segment instead of the row.
+// Labels are compared 16 at a time (SWAR on four 32-bit words).  With a label
+// index (rows sorted by label, per-vertex label offsets) the Gather is two
+// reads instead.
 // ---------------------------------------------------------------------------
+constexpr uint32_t kScanLoads = 4;
+
 __device__ __forceinline__ uint32_t match_bits(uint32_t word, uint32_t want4) {
     const uint32_t x = word ^ want4;
     return ~(((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x | 0x7F7F7F7Fu);   // 0x80 where a byte equals want
@@ -52,40 +61,91 @@ __device__ __forceinline__ uint32_t match_bits(uint32_t word, uint32_t want4) {
 
 // 0x80 flags of the bytes of the word at wa that lie in [lo, hi).
 __device__ __forceinline__ uint32_t byte_window(uintptr_t wa, uintptr_t lo, uintptr_t hi) {
+    if (wa >= hi || wa + 4 <= lo) return 0u;
     uint32_t m = 0x80808080u;
     if (lo > wa) m &= 0xFFFFFFFFu << (8u * (uint32_t)(lo - wa));
     if (hi < wa + 4) m &= (1u << (8u * (uint32_t)(hi - wa))) - 1u;
     return m;
 }
 
-// Aligned word at wa; bytes past the end of the label array read as 0 (masked anyway).
-__device__ __forceinline__ uint32_t load_word(uintptr_t wa, uintptr_t arr_end) {
-    if (wa + 4 <= arr_end) return *reinterpret_cast<const uint32_t *>(wa);
-    uint32_t w = 0;
-    for (uint32_t b = 0; b < 4 && wa + b < arr_end; ++b) w |= (uint32_t)(*reinterpret_cast<const uint8_t *>(wa + b)) << (8u * b);
-    return w;
+// The 16-byte-aligned block at ba of the label array [arr_lo, arr_hi); bytes
+// outside the array are not read (they read as 0 and lie outside every row,
+// so the row window masks them).
+__device__ __forceinline__ uint4 load_block(uintptr_t ba, uintptr_t arr_lo, uintptr_t arr_hi) {
+    if (ba >= arr_lo && ba + 16 <= arr_hi) return *reinterpret_cast<const uint4 *>(ba);
+    uint32_t w[4] = {0u, 0u, 0u, 0u};
+    for (uint32_t b = 0; b < 16; ++b)
+        if (ba + b >= arr_lo && ba + b < arr_hi)
+            w[b >> 2] |= (uint32_t)(*reinterpret_cast<const uint8_t *>(ba + b)) << (8u * (b & 3u));
+    return make_uint4(w[0], w[1], w[2], w[3]);
 }
 
-__device__ __forceinline__ uint32_t lane_count(uintptr_t l, uint32_t d, uint32_t want4, uintptr_t arr_end) {
-    const uintptr_t h = l + d;
-    uint32_t m = 0;
-    for (uintptr_t wa = l & ~(uintptr_t)3; wa < h; wa += 4)
-        m += __popc(match_bits(load_word(wa, arr_end), want4) & byte_window(wa, l, h));
-    return m;
+// Match flags (0x80 per matching byte) of the four words of the block at ba,
+// restricted to the row [lo, hi).
+struct BlockBits {
+    uint32_t w[4];
+};
+
+__device__ __forceinline__ BlockBits block_bits(const uint4 &v, uintptr_t ba, uintptr_t lo, uintptr_t hi,
+                                                uint32_t want4) {
+    BlockBits b;
+    b.w[0] = match_bits(v.x, want4) & byte_window(ba, lo, hi);
+    b.w[1] = match_bits(v.y, want4) & byte_window(ba + 4, lo, hi);
+    b.w[2] = match_bits(v.z, want4) & byte_window(ba + 8, lo, hi);
+    b.w[3] = match_bits(v.w, want4) & byte_window(ba + 12, lo, hi);
+    return b;
 }
 
-// Offset from l of the j-th (0-based) matching label; j < number of matches.
-__device__ __forceinline__ uint32_t lane_find(uintptr_t l, uint32_t d, uint32_t want4, uint32_t j, uintptr_t arr_end) {
-    const uintptr_t h = l + d;
-    for (uintptr_t wa = l & ~(uintptr_t)3;; wa += 4) {
-        uint32_t bits = match_bits(load_word(wa, arr_end), want4) & byte_window(wa, l, h);
-        const uint32_t c = __popc(bits);
+__device__ __forceinline__ uint32_t bits_count(const BlockBits &b) {
+    return __popc(b.w[0]) + __popc(b.w[1]) + __popc(b.w[2]) + __popc(b.w[3]);
+}
+
+// Offset from ba of the j-th (0-based) flagged byte of the block; j < bits_count(b).
+__device__ __forceinline__ uint32_t bits_select(BlockBits b, uint32_t j) {
+#pragma unroll
+    for (uint32_t q = 0; q < 4; ++q) {
+        const uint32_t c = __popc(b.w[q]);
         if (j < c) {
+            uint32_t bits = b.w[q];
             for (; j > 0; --j) bits &= bits - 1u;
-            return (uint32_t)(wa + (__builtin_ctz(bits) >> 3) - l);
+            return 4u * q + (uint32_t)(__builtin_ctz(bits) >> 3);
         }
         j -= c;
     }
+    return 16u;
+}
+
+// One lane, a whole row [l, l + d): the offset from l of the j-th matching
+// label, j = mulhi32(r0, m) with m the row's number of matches; -1 when m = 0.
+__device__ __forceinline__ int64_t lane_pick(uintptr_t l, uint32_t d, uint32_t want4, uint32_t r0, uintptr_t arr_lo,
+                                             uintptr_t arr_hi) {
+    const uintptr_t h = l + d;
+    const uintptr_t b0 = l & ~(uintptr_t)15;
+    uint32_t m = 0;
+    for (uintptr_t ba = b0; ba < h; ba += 16 * kScanLoads) {
+        uint4 v[kScanLoads];
+#pragma unroll
+        for (uint32_t u = 0; u < kScanLoads; ++u)
+            v[u] = ba + 16 * u < h ? load_block(ba + 16 * u, arr_lo, arr_hi) : make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+        for (uint32_t u = 0; u < kScanLoads; ++u) m += bits_count(block_bits(v[u], ba + 16 * u, l, h, want4));
+    }
+    if (m == 0) return -1;
+    uint32_t j = scale32(r0, m);                 // < m: the second pass stops inside the row
+    for (uintptr_t ba = b0; ba < h; ba += 16 * kScanLoads) {
+        uint4 v[kScanLoads];
+#pragma unroll
+        for (uint32_t u = 0; u < kScanLoads; ++u)
+            v[u] = ba + 16 * u < h ? load_block(ba + 16 * u, arr_lo, arr_hi) : make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+        for (uint32_t u = 0; u < kScanLoads; ++u) {
+            const BlockBits b = block_bits(v[u], ba + 16 * u, l, h, want4);
+            const uint32_t c = bits_count(b);
+            if (j < c) return (int64_t)(ba + 16 * u + bits_select(b, j)) - (int64_t)l;
+            j -= c;
+        }
+    }
+    return -1;
 }
 
 __device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v) {
@@ -98,40 +158,68 @@ __device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v) {
     return v;
 }
 
-// Whole wave, uniform arguments: offset from l of the j-th matching label with
-// j = scale32(r0, m), m the number of matches; -1 when m == 0.
-__device__ int64_t wave_pick(uintptr_t l, uint32_t d, uint32_t want4, uint32_t r0, uintptr_t arr_end) {
+// Whole wave, uniform arguments: the offset from l of the j-th matching label
+// with j = mulhi32(r0, m), m the number of matches; -1 when m == 0.  Chunk c
+// is the 1 KiB at b0 + 1024 c (lane i reads its 16 bytes at + 16 i); chunks
+// [s cps, (s + 1) cps) form segment s, whose match count lane s keeps.
+__device__ int64_t wave_pick(uintptr_t l, uint32_t d, uint32_t want4, uint32_t r0, uintptr_t arr_lo,
+                             uintptr_t arr_hi) {
     const uint32_t lane = lane_id();
     const uintptr_t h = l + d;
-    const uintptr_t w0 = l & ~(uintptr_t)3;
-    const uint32_t nwords = (uint32_t)((h - w0 + 3) >> 2);
-    uint32_t cnt = 0;
-    for (uint32_t i = lane; i < nwords; i += 64) {
-        const uintptr_t wa = w0 + 4 * (uintptr_t)i;
-        cnt += __popc(match_bits(load_word(wa, arr_end), want4) & byte_window(wa, l, h));
-    }
-    const uint32_t m = wave_total(cnt);
-    if (m == 0) return -1;
-    uint32_t j = scale32(r0, m);
-    for (uint32_t base = 0; base < nwords; base += 64) {
-        const uint32_t i = base + lane;
-        const uintptr_t wa = w0 + 4 * (uintptr_t)i;
-        uint32_t bits = 0;
-        if (i < nwords) bits = match_bits(load_word(wa, arr_end), want4) & byte_window(wa, l, h);
-        const uint32_t c = __popc(bits);
-        const uint32_t incl = wave_inclusive_scan(c);
-        const uint32_t total = __shfl(incl, 63);
-        if (j < total) {
-            const bool mine = c != 0 && incl - c <= j && j < incl;
-            int64_t pos = -1;
-            if (mine) {
-                for (uint32_t jj = j - (incl - c); jj > 0; --jj) bits &= bits - 1u;
-                pos = (int64_t)(wa + (__builtin_ctz(bits) >> 3)) - (int64_t)l;
-            }
-            const uint64_t who = __ballot(mine);
-            return __shfl(pos, (int)__builtin_ctzll(who));
+    const uintptr_t b0 = l & ~(uintptr_t)15;
+    const uint32_t nchunk = (uint32_t)((h - b0 + 1023) >> 10);
+    const uint32_t cps = (nchunk + 63) >> 6;
+    uint32_t seg = 0, run = 0;
+    for (uint32_t c0 = 0; c0 < nchunk; c0 += kScanLoads) {
+        uint4 v[kScanLoads];
+#pragma unroll
+        for (uint32_t u = 0; u < kScanLoads; ++u) {
+            const uintptr_t ba = b0 + 1024 * (uintptr_t)(c0 + u) + 16 * lane;
+            v[u] = c0 + u < nchunk && ba < h ? load_block(ba, arr_lo, arr_hi) : make_uint4(0u, 0u, 0u, 0u);
         }
-        j -= total;
+#pragma unroll
+        for (uint32_t u = 0; u < kScanLoads; ++u) {
+            const uint32_t c = c0 + u;
+            if (c >= nchunk) break;
+            run += bits_count(block_bits(v[u], b0 + 1024 * (uintptr_t)c + 16 * lane, l, h, want4));
+            if ((c + 1) % cps == 0 || c + 1 == nchunk) {       // end of segment c / cps
+                const uint32_t tot = wave_total(run);
+                if (lane == c / cps) seg = tot;
+                run = 0;
+            }
+        }
+    }
+    const uint32_t incl = wave_inclusive_scan(seg);
+    const uint32_t m = __shfl(incl, 63);
+    if (m == 0) return -1;
+    const uint32_t j = scale32(r0, m);
+    const int s = (int)__builtin_ctzll(__ballot(j < incl));      // the segment holding match j
+    uint32_t jj = j - (uint32_t)__shfl(incl - seg, s);
+    const uint32_t c_end = min(nchunk, (uint32_t)(s + 1) * cps);
+    for (uint32_t c0 = (uint32_t)s * cps; c0 < c_end; c0 += kScanLoads) {
+        uint4 v[kScanLoads];
+#pragma unroll
+        for (uint32_t u = 0; u < kScanLoads; ++u) {
+            const uintptr_t ba = b0 + 1024 * (uintptr_t)(c0 + u) + 16 * lane;
+            v[u] = c0 + u < c_end && ba < h ? load_block(ba, arr_lo, arr_hi) : make_uint4(0u, 0u, 0u, 0u);
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < kScanLoads; ++u) {
+            const uint32_t c = c0 + u;
+            if (c >= c_end) break;
+            const uintptr_t ba = b0 + 1024 * (uintptr_t)c + 16 * lane;
+            const BlockBits b = block_bits(v[u], ba, l, h, want4);
+            const uint32_t cnt = bits_count(b);
+            const uint32_t ci = wave_inclusive_scan(cnt);
+            const uint32_t total = __shfl(ci, 63);
+            if (jj < total) {
+                const bool mine = cnt != 0 && ci - cnt <= jj && jj < ci;
+                int64_t pos = -1;
+                if (mine) pos = (int64_t)(ba + bits_select(b, jj - (ci - cnt))) - (int64_t)l;
+                return __shfl(pos, (int)__builtin_ctzll(__ballot(mine)));
+            }
+            jj -= total;
+        }
     }
     return -1;
 }
@@ -173,9 +261,8 @@ __device__ __forceinline__ int32_t metapath_move(const GraphDev &g, const TableD
     int32_t nxt = -1;
     const bool big = active && d >= coop;
     if (active && !big && d > 0) {
-        const uintptr_t l = base + (uintptr_t)off;
-        const uint32_t m = lane_count(l, d, want4, arr_end);
-        if (m) nxt = g.col[off + lane_find(l, d, want4, scale32(r0, m), arr_end)];
+        const int64_t pos = lane_pick(base + (uintptr_t)off, d, want4, r0, base, arr_end);
+        if (pos >= 0) nxt = g.col[off + pos];
     }
     uint64_t todo = __ballot(big);
     while (todo) {
@@ -185,7 +272,7 @@ __device__ __forceinline__ int32_t metapath_move(const GraphDev &g, const TableD
         const uint32_t d_s = __shfl(d, src);
         const uint32_t want4_s = __shfl(want4, src);
         const uint32_t r0_s = __shfl(r0, src);
-        const int64_t pos = wave_pick(base + (uintptr_t)off_s, d_s, want4_s, r0_s, arr_end);
+        const int64_t pos = wave_pick(base + (uintptr_t)off_s, d_s, want4_s, r0_s, base, arr_end);
         if (lane_id() == (uint32_t)src && pos >= 0) nxt = g.col[off_s + pos];
     }
     return nxt;

@@ -1,19 +1,25 @@
 """Parity at the benchmark's full sizes, in the launch configuration bench.py
 times (persistent schedule, default tuning, the same tables and indexes).
+Every query of every configuration is compared with the oracle, paths
+included; the oracle runs over query ranges on the host's threads (ctypes
+releases the interpreter lock while it walks), and the GPU outputs are copied
+back in chunks of 2^20 queries.
 
-* PPR on R-MAT 2^22 (10^7 queries): every query compared with the oracle,
-  paths included, in chunks of 10^6; the end counts of five groups of
-  2 M queries and their top 4096 compared whole, also from the counting
-  walk that writes no paths; the same batch with REJ
-  compared on a seeded sample.
-* Node2Vec and MetaPath on R-MAT 2^24 (one query per vertex): a seeded sample
-  of queries compared with the oracle, which walks exactly those query ids;
-  the termination rules checked on every query and the hops of a sample
-  checked against the CSR rows.
-* The served mix on R-MAT 2^26 (about 1.07 G directed edges): requests of
-  every algorithm through the server, a sample of each compared with the
-  oracle.
+* PPR on R-MAT 2^22 (10^7 queries) with ALIAS: every query; the end counts of
+  five groups of 2 M queries and their top 4096 compared whole, also from the
+  counting walk that writes no paths.  The same batch with REJ: every query.
+* Node2Vec on R-MAT 2^24 (one query per vertex) with the edge index: every
+  query.
+* MetaPath on R-MAT 2^24 (one query per vertex): every query, once through
+  the label index and once by row scans (no index).
+* The served mix on R-MAT 2^26 (about 1.06 G directed edges): the bench's
+  first replay of 2000 requests submitted at once (saturated), every query of
+  every request.
 """
+import concurrent.futures
+import os
+import time
+
 import numpy as np
 import pytest
 import torch
@@ -24,6 +30,8 @@ import synth
 pytestmark = pytest.mark.gpu
 
 trw = None
+CHUNK = 1 << 20
+WORKERS = max(1, min(16, len(os.sched_getaffinity(0))))
 
 
 def log(msg):
@@ -61,11 +69,6 @@ def _oracle_params(p):
                              schema=tuple(int(p.schema[i]) for i in range(p.schema_len)))
 
 
-def _rows(t, idx):
-    """Rows idx of a device tensor, on the host."""
-    return t[torch.from_numpy(idx).to(t.device)].cpu().numpy()
-
-
 def _compare(P, L, S, ref, max_len, what):
     L = L.view(np.uint32) if L.dtype != np.uint32 else L
     bad = np.nonzero((L != ref.lengths) | (S != ref.status))[0]
@@ -89,7 +92,7 @@ def _check_rules(wl, L, S):
 
 
 def _check_hops(g, P, L):
-    """Every hop of the sampled paths is an edge of the CSR graph."""
+    """Every hop of the given paths is an edge of the CSR graph."""
     rp = g.row_ptr.astype(np.int64)
     for i in range(P.shape[0]):
         for k in range(int(L[i])):
@@ -99,13 +102,57 @@ def _check_hops(g, P, L):
             assert j < row.size and row[j] == v, f"hop {u}->{v} is not an edge"
 
 
-def _walk_full(wl, G, table, p, src):
+class _Merged:
+    """Oracle results of consecutive query ranges, joined."""
+
+    def __init__(self, parts):
+        self.paths = np.concatenate([r.paths for r in parts])
+        self.lengths = np.concatenate([r.lengths for r in parts])
+        self.status = np.concatenate([r.status for r in parts])
+        self.counters = {}
+        for r in parts:
+            for k, v in r.counters.items():
+                self.counters[k] = self.counters.get(k, 0) + int(v)
+
+
+def _oracle_range(g, op, src, lo, hi, **tables):
+    """The oracle on queries [lo, hi) (ids lo..hi-1), split over the host's threads."""
+    step = max(1, -(-(hi - lo) // WORKERS))
+    ranges = [(a, min(hi, a + step)) for a in range(lo, hi, step)]
+
+    def run(r):
+        return oracle.walk(g.row_ptr, g.col, op, src[r[0]:r[1]], qid_base=r[0], **tables)
+    with concurrent.futures.ThreadPoolExecutor(max_workers=WORKERS) as ex:
+        return _Merged(list(ex.map(run, ranges)))
+
+
+def _every_query(name, g, src, outputs, op, max_len, **tables):
+    """Compare every query of each (paths, lengths, status) output (device tensors) with the
+    oracle, chunk by chunk (the oracle walks each chunk once); returns the oracle's counters."""
+    counters = {}
+    t0 = time.time()
+    for lo in range(0, len(src), CHUNK):
+        hi = min(len(src), lo + CHUNK)
+        ref = _oracle_range(g, op, src, lo, hi, **tables)
+        for j, (P, L, S) in enumerate(outputs):
+            _compare(P[lo:hi].cpu().numpy(), L[lo:hi].cpu().numpy(), S[lo:hi].cpu().numpy(), ref, max_len,
+                     f"{name} (output {j}) queries {lo}..{hi}")
+        for k, v in ref.counters.items():
+            counters[k] = counters.get(k, 0) + v
+        del ref
+    log(f"  {name}: every query identical ({len(src)} queries, {counters.get('moves', 0)} moves, "
+        f"{len(outputs)} output(s), oracle on {WORKERS} threads {time.time() - t0:.1f}s)")
+    return counters
+
+
+def _walk_full(G, table, p, src):
     d_src = torch.from_numpy(src).cuda()
     P, L, S = trw.walk(G, table, p, d_src)      # persistent, default tuning (as timed by bench.py)
     torch.cuda.synchronize()
     return P, L, S
 
 
+@pytest.mark.timeout(900)
 def test_ppr_rmat22_every_query():
     wl = synth.WORKLOADS["ppr-rmat22"]
     g = synth.make_graph(wl)
@@ -115,22 +162,21 @@ def test_ppr_rmat22_every_query():
     assert G.validate() == 0
     alias = G.table("alias")
     p = _params(wl, "alias")
-    P, L, S = _walk_full(wl, G, alias, p, src)
+    P, L, S = _walk_full(G, alias, p, src)
     Lh, Sh = L.cpu().numpy(), S.cpu().numpy()
     _check_rules(wl, Lh, Sh)
     thr, al = oracle.alias_build(g.row_ptr, g.weight)
     op = _oracle_params(p)
-    chunk = 1_000_000
     group = 2_000_000
     exp_counts = np.zeros((len(src) // group, g.n), np.uint32)
-    for lo in range(0, len(src), chunk):
-        hi = min(len(src), lo + chunk)
-        ref = oracle.walk(g.row_ptr, g.col, op, src[lo:hi], qid_base=lo, thr=thr, alias=al)
-        Pc = P[lo:hi].cpu().numpy()
-        _compare(Pc, Lh[lo:hi], Sh[lo:hi], ref, wl.max_len, f"ppr-rmat22 queries {lo}..{hi}")
+    for lo in range(0, len(src), group):
+        hi = min(len(src), lo + group)
+        ref = _oracle_range(g, op, src, lo, hi, thr=thr, alias=al)
+        _compare(P[lo:hi].cpu().numpy(), Lh[lo:hi], Sh[lo:hi], ref, wl.max_len, f"ppr-rmat22 queries {lo}..{hi}")
         log(f"  ppr-rmat22 queries {lo}..{hi} identical")
-        # the oracle's end counts of the same queries (groups of 2 M queries hold whole chunks)
+        # the oracle's end counts of the same queries (one group per range)
         oracle.end_counts(g.n, ref.paths, ref.lengths, ref.status, counts=exp_counts[lo // group])
+        del ref
     # PPR estimate at full size: end counts per group and the top 4096 of each group
     counts, skipped = trw.ppr_end_counts(G, P, L, S, group=group)
     torch.cuda.synchronize()
@@ -149,50 +195,61 @@ def test_ppr_rmat22_every_query():
     assert np.array_equal(counts.cpu().numpy().view(np.uint32), exp_counts), "counting walk differs"
     assert np.array_equal(L2.cpu().numpy(), Lh) and np.array_equal(S2.cpu().numpy(), Sh)
     log("  ppr-rmat22 counting walk identical")
-    del counts, L2, S2
-    # REJ on the same batch: a seeded sample of queries against the oracle
+    del counts, L2, S2, thr, al
+    alias.close()
+    # REJ on the same batch: every query
     rej = G.table("rej")
     pr = _params(wl, "rej")
-    P, L, S = _walk_full(wl, G, rej, pr, src)
-    Lh, Sh = L.cpu().numpy(), S.cpu().numpy()
-    _check_rules(wl, Lh, Sh)
-    idx = np.unique(np.concatenate([np.random.default_rng(7).choice(len(src), 20000, replace=False),
-                                    [0, len(src) - 1]]))
-    ref = oracle.walk(g.row_ptr, g.col, _oracle_params(pr), src[idx], qids=idx.astype(np.uint64),
-                      weight=g.weight, pmax=oracle.rej_build(g.row_ptr, g.weight))
-    _compare(_rows(P, idx), Lh[idx], Sh[idx], ref, wl.max_len, "ppr-rmat22 REJ sample")
-    log("  ppr-rmat22 REJ sample identical")
+    P, L, S = _walk_full(G, rej, pr, src)
+    _check_rules(wl, L.cpu().numpy(), S.cpu().numpy())
+    _every_query("ppr-rmat22 REJ", g, src, [(P, L, S)], _oracle_params(pr), wl.max_len,
+                 weight=g.weight, pmax=oracle.rej_build(g.row_ptr, g.weight))
     G.close()
 
 
-@pytest.mark.parametrize("name,sampler,index", [("node2vec-rmat24", "orej", "edge"),
-                                                ("metapath-rmat24", "its", "label")])
-def test_rmat24_sampled_queries(name, sampler, index):
-    wl = synth.WORKLOADS[name]
+@pytest.mark.timeout(900)
+def test_node2vec_rmat24_every_query():
+    wl = synth.WORKLOADS["node2vec-rmat24"]
     g = synth.make_graph(wl)
     src = synth.make_sources(wl, g)
-    log(f"  {name}: n={g.n} m={g.m} nq={len(src)}")
-    G = trw.Graph(g.row_ptr, g.col, g.weight, g.label, symmetric=wl.symmetric)
+    log(f"  node2vec-rmat24: n={g.n} m={g.m} nq={len(src)}")
+    G = trw.Graph(g.row_ptr, g.col, symmetric=wl.symmetric)
     assert G.validate() == 0
-    table = G.edge_index() if index == "edge" else G.label_index(wl.labels)
-    p = _params(wl, sampler)
-    P, L, S = _walk_full(wl, G, table, p, src)
+    eidx = G.edge_index()
+    p = _params(wl, "orej")
+    P, L, S = _walk_full(G, eidx, p, src)
     Lh, Sh = L.cpu().numpy(), S.cpu().numpy()
     _check_rules(wl, Lh, Sh)
-    rng = np.random.default_rng(2024)
-    n_sample = 20000 if wl.algo == "node2vec" else 6000
-    idx = np.sort(rng.choice(len(src), size=n_sample, replace=False))
-    idx = np.unique(np.concatenate([idx, [0, len(src) - 1]]))     # the first and last query too
-    ref = oracle.walk(g.row_ptr, g.col, _oracle_params(p), src[idx], qids=idx.astype(np.uint64),
-                      label=g.label if wl.algo == "metapath" else None)
-    Ps = _rows(P, idx)
-    _compare(Ps, Lh[idx], Sh[idx], ref, wl.max_len, name)
-    _check_hops(g, Ps[:300], Lh[idx][:300].view(np.uint32))
-    log(f"  {name}: {idx.size} sampled queries identical, rules hold for all {len(src)}")
+    _check_hops(g, P[:300].cpu().numpy(), Lh[:300].view(np.uint32))
+    _every_query("node2vec-rmat24", g, src, [(P, L, S)], _oracle_params(p), wl.max_len)
     G.close()
 
 
-def test_served_rmat26_sampled_queries():
+@pytest.mark.timeout(900)
+def test_metapath_rmat24_every_query():
+    """With the label index and by row scans: both equal the oracle on every query."""
+    wl = synth.WORKLOADS["metapath-rmat24"]
+    g = synth.make_graph(wl)
+    src = synth.make_sources(wl, g)
+    log(f"  metapath-rmat24: n={g.n} m={g.m} nq={len(src)}")
+    G = trw.Graph(g.row_ptr, g.col, None, g.label, symmetric=wl.symmetric)
+    assert G.validate() == 0
+    index = G.label_index(wl.labels)
+    p = _params(wl, "its")
+    P, L, S = _walk_full(G, index, p, src)
+    _check_rules(wl, L.cpu().numpy(), S.cpu().numpy())
+    P2, L2, S2 = _walk_full(G, None, p, src)             # row scans
+    _every_query("metapath-rmat24, label index and row scans", g, src, [(P, L, S), (P2, L2, S2)],
+                 _oracle_params(p), wl.max_len, label=g.label)
+    G.close()
+
+
+@pytest.mark.timeout(900)
+def test_served_rmat26_saturated_replay_every_query():
+    """The bench's first replay of the served mix (2000 requests, all submitted at once) through
+    the server in the bench's configuration; every query of every request against the oracle."""
+    import ctypes
+    from paper_2107_11983_amd import _abi
     wl = synth.WORKLOADS["served-rmat26"]
     g = synth.make_graph(wl)
     log(f"  served-rmat26: n={g.n} m={g.m}")
@@ -200,42 +257,57 @@ def test_served_rmat26_sampled_queries():
     assert G.validate() == 0
     alias = G.table("alias")
     eidx = G.edge_index()
-    srv = trw.Server(G, alias, eidx, pool_bytes=2 << 30)
-    rng = np.random.default_rng(77)
-    algos = [("deepwalk", "alias", 80), ("ppr", "alias", 256), ("node2vec", "orej", 80)]
-    reqs = []
-    for r in range(12):
-        algo, sampler, max_len = algos[r % 3]
-        nq = int(rng.integers(1, 4097))
-        src = synth.sources(nq, g.n, 0x5AC0000005 + r)
-        kw = {}
-        if algo == "ppr":
-            kw["stop_q32"] = trw.stop_threshold(0.2)
-        if algo == "node2vec":
-            kw["n2v_thr_q16"] = trw.n2v_thresholds(2.0, 0.5)
-        p = trw.make_params(algo, sampler, max_len, wl.walk_seed + r, **kw)
-        rid = srv.submit(p, src, qid_base=(r + 1) << 32)
-        reqs.append((rid, p, src, (r + 1) << 32))
-    got = {}
-    import time
+    R = 2000
+    sizes, kinds, offs, src = synth.served_requests(wl, R, g.n)
+    algo_p = [trw.make_params("deepwalk", "alias", 80, wl.walk_seed),
+              trw.make_params("ppr", "alias", 256, wl.walk_seed, stop_q32=trw.stop_threshold(wl.stop_prob)),
+              trw.make_params("node2vec", "orej", 80, wl.walk_seed, n2v_thr_q16=trw.n2v_thresholds(*wl.n2v_pq))]
+    strides = np.array([88, 264, 88])
+    poff = np.concatenate([[0], np.cumsum(sizes * strides[kinds])])
+    d_src = torch.from_numpy(src).cuda()
+    d_paths = torch.full((int(poff[-1]),), -7, dtype=torch.int32, device="cuda")
+    d_len = torch.empty(int(offs[-1]), dtype=torch.int32, device="cuda")
+    d_st = torch.empty(int(offs[-1]), dtype=torch.uint8, device="cuda")
+    reqs = (_abi.trw_request * R)()
+    for i in range(R):
+        r = reqs[i]
+        r.params = algo_p[kinds[i]]
+        r.nq = int(sizes[i])
+        r.sources = ctypes.c_void_p(d_src.data_ptr() + 4 * int(offs[i]))
+        r.qid_base = i << 32
+        r.paths = ctypes.c_void_p(d_paths.data_ptr() + 4 * int(poff[i]))
+        r.path_stride = int(strides[kinds[i]])
+        r.lengths = ctypes.c_void_p(d_len.data_ptr() + 4 * int(offs[i]))
+        r.status = ctypes.c_void_p(d_st.data_ptr() + int(offs[i]))
+    torch.cuda.synchronize()
+    slots = torch.cuda.get_device_properties(0).multi_processor_count * 2048
+    srv = trw.Server(G, alias, eidx, pool_bytes=8 << 30, max_slots=slots, max_requests=1024, steps_per_tick=16)
+    comp = (_abi.trw_completion * R)()
+    arr = (ctypes.c_uint64 * R)()
     t0 = time.time()
-    while len(got) < len(reqs):
-        assert time.time() - t0 < 60, "served requests did not complete"
-        for c in srv.poll(64, timeout_ms=100):
-            got[c["request_id"]] = c
-    thr, al = oracle.alias_build(g.row_ptr, g.weight)
-    for rid, p, src, qb in reqs:
-        c = got[rid]
-        assert c["status"] == 0
-        nq = len(src)
-        idx = np.unique(np.concatenate([rng.choice(nq, size=min(nq, 200), replace=False), [0, nq - 1]]))
-        kw = dict(thr=thr, alias=al) if int(p.sampler) == trw.SAMPLERS["alias"] else {}
-        ref = oracle.walk(g.row_ptr, g.col, _oracle_params(p), src[idx], qids=(qb + idx).astype(np.uint64), **kw)
-        Pd, Ld, Sd = c["paths"], c["lengths"], c["status_codes"]
-        Ps = _rows(Pd, idx) if isinstance(Pd, torch.Tensor) else Pd[idx]
-        Ls = (_rows(Ld, idx) if isinstance(Ld, torch.Tensor) else Ld[idx]).view(np.uint32)
-        Ss = _rows(Sd, idx) if isinstance(Sd, torch.Tensor) else Sd[idx]
-        _compare(Ps, Ls, Ss, ref, int(p.max_len), f"served request {rid}")
-    log(f"  served-rmat26: {len(reqs)} requests, sampled queries identical")
+    rc = _abi.trw_probe_serve_replay(srv.handle, R, reqs, arr, comp, 600_000)
+    assert rc == 0, f"replay failed: {rc} {_abi.trw_last_error()}"
+    assert all(comp[i].status == 0 for i in range(R))
+    log(f"  served-rmat26: {R} requests ({int(offs[-1])} queries) served in {time.time() - t0:.2f}s, "
+        f"{srv.stats()['ticks']} ticks")
     srv.close()
+    paths = d_paths.cpu().numpy()
+    lengths = d_len.cpu().numpy().view(np.uint32)
+    status = d_st.cpu().numpy()
+    thr, al = oracle.alias_build(g.row_ptr, g.weight)
+    ops = [_oracle_params(p) for p in algo_p]
+
+    def run(i):
+        kw = dict(thr=thr, alias=al) if kinds[i] < 2 else {}
+        return oracle.walk(g.row_ptr, g.col, ops[kinds[i]], src[offs[i]:offs[i + 1]], qid_base=i << 32, **kw)
+    t0 = time.time()
+    moves = 0
+    with concurrent.futures.ThreadPoolExecutor(max_workers=WORKERS) as ex:
+        for i, ref in enumerate(ex.map(run, range(R))):
+            nq, stride, ml = int(sizes[i]), int(strides[kinds[i]]), int(algo_p[kinds[i]].max_len)
+            P = paths[poff[i]:poff[i + 1]].reshape(nq, stride)
+            _compare(P, lengths[offs[i]:offs[i + 1]], status[offs[i]:offs[i + 1]], ref, ml, f"served request {i}")
+            moves += int(ref.lengths.sum())
+    log(f"  served-rmat26: every query of {R} requests identical ({int(offs[-1])} queries, {moves} moves, "
+        f"oracle on {WORKERS} threads {time.time() - t0:.1f}s)")
     G.close()
