@@ -334,6 +334,27 @@ trw_status trw_walk(trw_graph g, trw_table table, const trw_walk_params *p,
                     trw_stream_t stream);
 
 /*
+ * trw_walk without a workspace argument, for callers that cannot allocate
+ * device memory (code under graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  The workspace trw_walk would take lives in a
+ * device array inside the library, TRW_NOALLOC_SCRATCH_BYTES per GPU, held
+ * until the process ends; the call itself allocates nothing.  Every call on a
+ * GPU shares that GPU's array: calls that overlap on one GPU (on different
+ * streams, or from several threads) race and must not be issued.  The array
+ * is cleared by the call's own kernels wherever a walk needs zeros.
+ * Limit: trw_walk_workspace_bytes(g, p, nq, mode) <= TRW_NOALLOC_SCRATCH_BYTES
+ * (persistent: any nq; per step: 32 bytes per query plus 4 * (max_len + 2),
+ * each rounded up to 256), else TRW_E_INVALID before any device work.  Other
+ * arguments, outputs and errors as trw_walk.
+ */
+#define TRW_NOALLOC_SCRATCH_BYTES (8u << 20)
+trw_status trw_walk_noalloc(trw_graph g, trw_table table, const trw_walk_params *p,
+                            const int32_t *d_sources, uint64_t nq, uint64_t qid_base,
+                            int32_t *d_paths, uint64_t path_stride, uint32_t *d_lengths,
+                            uint8_t *d_status, uint32_t mode, const trw_tuning *tuning,
+                            trw_stream_t stream);
+
+/*
  * Pick a tuning by pre-executing short walks (the paper tunes its ring sizes
  * the same way: Ring Size Tuning).  Runs up to `budget` (0 = all) candidate
  * launches of `nq` queries (a sample, length-capped at p->max_len) from

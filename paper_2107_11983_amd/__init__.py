@@ -23,7 +23,7 @@ from ._abi import (TRW_A_DEEPWALK, TRW_A_METAPATH, TRW_A_NODE2VEC, TRW_A_PPR, TR
 
 __all__ = ["Graph", "Table", "walk", "make_params", "workspace_bytes", "default_tuning", "autotune",
            "TrwError", "ALGOS", "SAMPLERS", "Program", "check_program", "programs", "Server", "ppr_end_counts",
-           "ppr_walk_counts", "topk", "walk_stream"]
+           "ppr_walk_counts", "topk", "walk_stream", "walk_noalloc"]
 
 ALGOS = {"deepwalk": TRW_A_DEEPWALK, "ppr": TRW_A_PPR, "node2vec": TRW_A_NODE2VEC, "metapath": TRW_A_METAPATH}
 SAMPLERS = {"naive": TRW_S_NAIVE, "alias": TRW_S_ALIAS, "its": TRW_S_ITS, "orej": TRW_S_OREJ, "rej": TRW_S_REJ}
@@ -288,6 +288,20 @@ def walk(graph: Graph, table: Optional[Table], p: trw_walk_params, sources: torc
                         _dptr(bufs.status), mode, ctypes.byref(tuning) if tuning is not None else None,
                         _dptr(bufs.ws), bufs.ws.numel(), _stream_ptr(stream)))
     return bufs.paths, bufs.lengths, bufs.status
+
+
+def walk_noalloc(graph: Graph, table: Optional[Table], p: trw_walk_params, sources: torch.Tensor,
+                 paths: torch.Tensor, lengths: torch.Tensor, status: torch.Tensor, qid_base: int = 0,
+                 mode=TRW_M_PERSISTENT, tuning: Optional[trw_tuning] = None, stream=None):
+    """trw_walk_noalloc: the walk with the library's own device workspace (no allocation in the
+    call); the caller passes the outputs (paths int32[nq, stride], lengths, status)."""
+    mode = MODES.get(mode, mode)
+    nq = int(sources.numel())
+    check(_abi.trw_walk_noalloc(graph.handle, table.handle if table is not None else None, ctypes.byref(p),
+                                _dptr(sources), nq, qid_base, _dptr(paths), paths.stride(0), _dptr(lengths),
+                                _dptr(status), mode, ctypes.byref(tuning) if tuning is not None else None,
+                                _stream_ptr(stream)))
+    return paths, lengths, status
 
 
 def autotune(graph: Graph, table: Optional[Table], p: trw_walk_params, sources: torch.Tensor,

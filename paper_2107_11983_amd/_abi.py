@@ -117,6 +117,8 @@ _SIGS = {
     "trw_default_tuning": (_st, [_P, ctypes.POINTER(trw_walk_params), _u32, ctypes.POINTER(trw_tuning)]),
     "trw_walk": (_st, [_P, _P, ctypes.POINTER(trw_walk_params), _P, _u64, _u64, _P, _u64, _P, _P, _u32,
                        ctypes.POINTER(trw_tuning), _P, _sz, _P]),
+    "trw_walk_noalloc": (_st, [_P, _P, ctypes.POINTER(trw_walk_params), _P, _u64, _u64, _P, _u64, _P, _P, _u32,
+                               ctypes.POINTER(trw_tuning), _P]),
     "trw_autotune": (_st, [_P, _P, ctypes.POINTER(trw_walk_params), _P, _u64, _P, _u64, _P, _P, _u32, _u32,
                            _P, _sz, _P, ctypes.POINTER(trw_tuning), ctypes.POINTER(ctypes.c_float)]),
     "trw_adjacency_index_bytes": (_st, [_P, ctypes.POINTER(_sz)]),

@@ -518,6 +518,59 @@ trw_status trw_walk(trw_graph g, trw_table table, const trw_walk_params *p, cons
 }
 
 
+}  // extern "C"
+
+namespace {
+
+// Workspace of trw_walk_noalloc: a device array in this library's code object,
+// one copy per GPU.  In host code its name is only a stand-in for the symbol;
+// the device address comes from hipGetSymbolAddress, looked up once per device
+// (with that device current) and kept.
+__device__ __align__(256) unsigned char scratch[TRW_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex scratch_mu;
+void *scratch_ptr[kMaxScratchDevices] = {};
+
+trw_status scratch_of_current_device(void **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return device_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxScratchDevices) return fail(TRW_E_UNSUPPORTED, "device index beyond 63");
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    if (!scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) return device_fail(e, "hipGetSymbolAddress(scratch)");
+        scratch_ptr[dev] = ptr;
+    }
+    *out = scratch_ptr[dev];
+    return TRW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+trw_status trw_walk_noalloc(trw_graph g, trw_table table, const trw_walk_params *p, const int32_t *d_sources,
+                            uint64_t nq, uint64_t qid_base, int32_t *d_paths, uint64_t path_stride,
+                            uint32_t *d_lengths, uint8_t *d_status, uint32_t mode, const trw_tuning *tuning,
+                            trw_stream_t stream) {
+    if (!g || !p) return fail(TRW_E_INVALID, "graph / params is NULL");
+    if (mode > TRW_M_PERSISTENT) return fail(TRW_E_INVALID, "unknown mode");
+    const size_t need = walk_workspace_bytes(mode, nq, p->max_len);
+    if (need > TRW_NOALLOC_SCRATCH_BYTES)
+        return fail(TRW_E_INVALID, "the walk needs " + std::to_string(need) +
+                                       " bytes of workspace; trw_walk_noalloc holds " +
+                                       std::to_string((size_t)TRW_NOALLOC_SCRATCH_BYTES) +
+                                       " (use trw_walk with a caller workspace)");
+    void *ws = nullptr;
+    trw_status st = scratch_of_current_device(&ws);
+    if (st != TRW_OK) return st;
+    return walk_impl(g, table, p, d_sources, nq, qid_base, d_paths, path_stride, d_lengths, d_status, mode, tuning,
+                     ws, TRW_NOALLOC_SCRATCH_BYTES, stream, nullptr, 0, 0);
+}
+
 trw_status trw_ppr_walk_counts(trw_graph g, trw_table table, const trw_walk_params *p, const int32_t *d_sources,
                                uint64_t nq, uint64_t qid_base, uint64_t group, uint32_t *d_counts,
                                uint64_t counts_len, uint32_t *d_lengths, uint8_t *d_status,

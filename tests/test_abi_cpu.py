@@ -291,3 +291,22 @@ def test_label_index_sizes(abi):
     assert abi.trw_label_index_bytes(g, 65, ctypes.byref(b)) == abi.TRW_E_INVALID
     abi.trw_graph_destroy(g)
 
+
+def test_walk_noalloc_size_limit(abi):
+    """trw_walk_noalloc refuses a walk whose workspace exceeds its device array before any
+    device work (the per-step schedule needs 32 bytes per query); nothing runs here."""
+    g = _fake_graph(abi)
+    fake = ctypes.c_void_p(0x1000)
+    p = _params(abi, "deepwalk", "naive")
+    limit = int(re.search(r"#define TRW_NOALLOC_SCRATCH_BYTES \((\d+)u << (\d+)\)", open(HEADER).read())
+                .expand(r"\1")) << 20
+    assert limit == 8 << 20
+    nq = limit // 32 + 1
+    st = abi.trw_walk_noalloc(g, None, ctypes.byref(p), fake, nq, 0, fake, 11, fake, fake, abi.TRW_M_PER_STEP,
+                              None, None)
+    assert st == abi.TRW_E_INVALID and b"workspace" in abi.trw_last_error()
+    assert abi.trw_walk_noalloc(g, None, ctypes.byref(p), fake, 5, 0, fake, 11, fake, fake, 7, None,
+                                None) == abi.TRW_E_INVALID         # unknown mode
+    assert abi.trw_walk_noalloc(g, None, None, fake, 5, 0, fake, 11, fake, fake, 1, None,
+                                None) == abi.TRW_E_INVALID         # no params
+    abi.trw_graph_destroy(g)
