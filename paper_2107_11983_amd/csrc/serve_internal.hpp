@@ -50,11 +50,13 @@ struct SlotState {
     int32_t pad[3];
 };
 
-// A wave's position in the chunk ring between ticks.
+// A wave's position in the chunk ring between ticks: the chunk it is
+// starting queries from and the one after it, already taken from the ring
+// (their sources and row ranges are loaded ahead of need, one query per lane).
 struct WaveState {
-    unsigned long long claim;   // ring index claimed and not yet read
-    uint32_t next, end;         // queries [next, end) of request `req` not yet started
-    uint32_t req;
+    unsigned long long claim;   // ring index claimed and not yet read (when has_claim)
+    uint32_t req, begin, next, end;         // current chunk: queries [next, end) not yet started
+    uint32_t n_req, n_begin, n_end;         // following chunk (n_end == n_begin: none)
     uint32_t has_claim;
     uint32_t pad[2];
 };
