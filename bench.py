@@ -73,7 +73,8 @@ def read_traffic(tag, files):
         return {"total": float(kv["traffic_bytes_per_launch"]), "read": float(kv.get("read_bytes_per_launch", "nan")),
                 "write": float(kv.get("write_bytes_per_launch", "nan")),
                 "l2_hit_rate": float(kv["l2_hit_rate"]) if "l2_hit_rate" in kv else None,
-                "method": kv.get("traffic_method")}, path
+                "method": {"1": "request sizes (32/64/128-byte read requests, 32/64-byte writes)"}.get(
+                    kv.get("traffic_method"), "FETCH_SIZE scaled by a 1 GiB copy")}, path
     except KeyError:
         return None, None
 
@@ -123,6 +124,7 @@ def main():
     ap.add_argument("--wpl", type=int, default=0, help="walkers per lane (0 = library default)")
     ap.add_argument("--blocks-per-cu", type=int, default=0)
     ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--coop", type=int, default=0, help="MetaPath row-scan wave threshold (0 = library default)")
     ap.add_argument("--nq", type=int, default=0, help="override the number of queries (throughput-vs-batch sweeps)")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="headline only, without the nested batch workloads")
@@ -134,7 +136,7 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=10000, help="measured requests of the latency phase")
     ap.add_argument("--serve-scale", type=int, default=0, help="override the served graph's scale (tests)")
     ap.add_argument("--serve-slots-per-cu", type=int, default=2048)
-    ap.add_argument("--serve-steps", type=int, default=16, help="moves per walker slot per tick")
+    ap.add_argument("--serve-steps", type=int, default=32, help="moves per walker slot per tick")
     ap.add_argument("--serve-pipelined", type=int, default=1, help="0: serial ticks (read each tick before queueing the next)")
     ap.add_argument("--serve-rate", type=float, default=0.0, help="offered requests/s (0: 0.7x the saturated rate)")
     ap.add_argument("--profile-pass", action="store_true",
@@ -246,6 +248,8 @@ def bench_batch(args, wl, ctx, nested=False):
             t["blocks_per_cu"] = args.blocks_per_cu
         if args.chunk:
             t["queue_chunk"] = args.chunk
+        if args.coop:
+            t["coop_degree"] = args.coop
         return trw.make_tuning(**t) if t else None
 
     def run(s, mode, warmup, steps, tuning=None):
@@ -324,16 +328,24 @@ def bench_batch(args, wl, ctx, nested=False):
     # sample of the batch, then the whole batch timed with the winner.
     autotuned = None
     if not args.no_variants and not args.profile_pass:
-        n_tune = min(nq, 1 << 20)
+        # the whole batch when one launch of it is short, else a sample of 2^20 queries
+        n_tune = nq if avg_launch_ms < 50 else min(nq, 1 << 20)
         t0 = time.perf_counter()
         best, best_ms = trw.autotune(G, tables.get(sampler), params(sampler), d_src[:n_tune], mode=mode)
         tune_s = time.perf_counter() - t0
-        r = run(sampler, mode, 1, args.steps, best)
-        v = r["moves"] * args.steps / r["wall_s"]
-        autotuned = {"tuning": best.as_dict(), "sample_queries": n_tune, "tune_s": round(tune_s, 3),
-                     "steps_per_s": round(v, 1), "ms_per_batch": round(1000 * r["wall_s"] / args.steps, 4),
+        # the autotuner's first candidate is the library default for this walk and table
+        default, _ = trw.autotune(G, tables.get(sampler), params(sampler), d_src[:64], mode=mode, budget=1)
+        kept = best.as_dict() == default.as_dict()
+        if kept:       # the default itself: the batch's own timing stands
+            v, ms_b = value, ms_step
+        else:
+            r = run(sampler, mode, 1, args.steps, best)
+            v, ms_b = r["moves"] * args.steps / r["wall_s"], 1000 * r["wall_s"] / args.steps
+        autotuned = {"tuning": best.as_dict(), "default_kept": kept, "tuned_on_queries": n_tune,
+                     "tune_s": round(tune_s, 3), "steps_per_s": round(v, 1), "ms_per_batch": round(ms_b, 4),
                      "vs_default": round(v / value, 4)}
-        log(f"autotuned {best.as_dict()}: {v:.4g} steps/s ({v / value:.3f}x default), tuning {tune_s:.2f}s")
+        log(f"autotuned {best.as_dict()} ({'default kept' if kept else 'candidate'}): {v:.4g} steps/s "
+            f"({v / value:.3f}x default), tuning {tune_s:.2f}s")
 
     # Other samplers / schedules of the same workload (same queries, same graph).
     variants = {}

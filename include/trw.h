@@ -362,7 +362,9 @@ trw_status trw_walk_noalloc(trw_graph g, trw_table table, const trw_walk_params 
  * *out.  Candidates: the default tuning first, then walkers per lane x blocks
  * per CU x queue chunk (persistent) or blocks per CU x block size (per step),
  * and for METAPATH without a label index the wave-scan degree.  The default is
- * kept unless a candidate is at least 3% faster.  d_paths, d_lengths,
+ * kept unless a candidate is at least 3% faster, first in the scan and again
+ * in five alternating timings of the two (medians).  Pass the whole batch when
+ * a launch of it is short; a sample otherwise.  d_paths, d_lengths,
  * d_status and d_ws are scratch of the sizes trw_walk needs for nq queries.
  * Synchronises the stream.  Errors as trw_walk.
  */
