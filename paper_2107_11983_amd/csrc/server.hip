@@ -38,37 +38,47 @@ __global__ void k_fill_bytes(uint32_t *p, size_t n_words, uint32_t v) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_words; i += stride) p[i] = v;
 }
 
-// A 2D copy of `rows` rows of `width` bytes; row_start = rows of all earlier
-// jobs of the same delivery (rows are the unit of work).
+// A 2D copy of `rows` rows of `width` bytes, cut into 16-byte segments
+// (seg_per_row per row, the last one of a row possibly short); seg_start =
+// segments of all earlier jobs of the same delivery.
 struct CopyJob {
     const char *src;
     char *dst;
-    uint64_t src_pitch, dst_pitch, width, rows, row_start;
+    uint64_t src_pitch, dst_pitch, width, rows, seg_start;
+    uint64_t seg_per_row;
 };
 
-// Output delivery: every wave copies whole rows (of any job), rows spread over
-// the grid; 4-byte words when the row is 4-byte aligned, bytes otherwise.
+constexpr uint32_t kDeliverSegs = 16;     // segments per thread: a block copies 64 KiB
+
+// Output delivery: block b copies segments [b, b + 1) * 256 * kDeliverSegs of
+// all jobs together, consecutive threads on consecutive segments.  The job of
+// the block's first segment is found once (binary search); later segments
+// step forward through the jobs.  A full segment whose source and
+// destination are 16-byte aligned moves as one 16-byte load and store, the
+// others byte by byte.
 __global__ void __launch_bounds__(256) k_deliver(const CopyJob *__restrict__ jobs, uint32_t n_jobs,
-                                                 uint64_t total_rows) {
-    const uint32_t lane = threadIdx.x & 63;
-    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
-    for (uint64_t row = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); row < total_rows;
-         row += waves) {
-        uint32_t lo = 0, hi = n_jobs - 1;           // last job with row_start <= row
-        while (lo < hi) {
-            const uint32_t mid = (lo + hi + 1) >> 1;
-            if (jobs[mid].row_start <= row) lo = mid; else hi = mid - 1;
-        }
-        const CopyJob jb = jobs[lo];
-        const uint64_t r = row - jb.row_start;
-        const char *src = jb.src + r * jb.src_pitch;
-        char *dst = jb.dst + r * jb.dst_pitch;
-        if (((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst) | jb.width) & 3) == 0) {
-            const uint32_t w = (uint32_t)(jb.width >> 2);
-            for (uint32_t c = lane; c < w; c += 64)
-                reinterpret_cast<uint32_t *>(dst)[c] = reinterpret_cast<const uint32_t *>(src)[c];
+                                                 uint64_t total_segs) {
+    const uint64_t base = (uint64_t)blockIdx.x * 256 * kDeliverSegs;
+    uint32_t lo = 0, hi = n_jobs - 1;                   // last job with seg_start <= base
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].seg_start <= base) lo = mid; else hi = mid - 1;
+    }
+    uint32_t j = lo;
+    for (uint32_t i = 0; i < kDeliverSegs; ++i) {
+        const uint64_t g = base + threadIdx.x + 256 * (uint64_t)i;
+        if (g >= total_segs) break;
+        while (j + 1 < n_jobs && jobs[j + 1].seg_start <= g) ++j;
+        const CopyJob &jb = jobs[j];
+        const uint64_t s = g - jb.seg_start;
+        const uint64_t row = s / jb.seg_per_row, col = 16 * (s % jb.seg_per_row);
+        const char *src = jb.src + row * jb.src_pitch + col;
+        char *dst = jb.dst + row * jb.dst_pitch + col;
+        const uint64_t n = min((uint64_t)16, jb.width - col);
+        if (n == 16 && ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 15) == 0) {
+            *reinterpret_cast<uint4 *>(dst) = *reinterpret_cast<const uint4 *>(src);
         } else {
-            for (uint64_t c = lane; c < jb.width; c += 64) dst[c] = src[c];
+            for (uint64_t c = 0; c < n; ++c) dst[c] = src[c];
         }
     }
 }
@@ -169,13 +179,20 @@ struct Active {
     size_t out_off;            // offset of the outputs inside the request's pool range
     bool finishing = false;
     bool cancelled = false;
+    uint64_t batch_seq = 0;    // the delivery batch it finished in (when finishing)
 };
+
+constexpr int kJobBufs = 4;    // pinned job tables: a batch's is reused kJobBufs batches later
+
+// Mark descriptor slot i as changed (copied to the device before the next tick).
+void desc_touch(trw_server_s *s, uint32_t i);
 
 // Output copies of the requests that finished in one tick, in flight on the
 // delivery stream; the requests complete when `done` has been reached.
 struct Batch {
     hipEvent_t done = nullptr;
-    int jobs_buf = 0;                  // which half of the pinned job table it used
+    int jobs_buf = 0;                  // which of the pinned job tables it used
+    uint64_t seq = 0;                  // its sequence number (Active::batch_seq of its requests)
     std::vector<uint64_t> ids;
 };
 
@@ -205,8 +222,8 @@ struct trw_server_s {
     Chunk *h_ring = nullptr;
     unsigned long long *h_tail = nullptr;     // [2]
     uint32_t *h_done = nullptr;               // [2] x (completion counters, then the moves counter)
-    CopyJob *h_jobs = nullptr;                // [2] x 3 * max_requests
-    bool desc_dirty = false;
+    CopyJob *h_jobs = nullptr;                // [kJobBufs] x 3 * max_requests
+    uint32_t desc_lo = 0, desc_hi = 0;        // descriptor slots changed since the last copy: [lo, hi)
     hipStream_t stream = nullptr;             // ticks and the copies that feed them
     hipStream_t deliver_stream = nullptr;     // output copies of finished requests
     hipEvent_t tick_done[2] = {nullptr, nullptr};
@@ -367,7 +384,8 @@ extern "C" trw_status trw_server_create(trw_graph g, trw_table alias, trw_table 
     if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_ring, sizeof(Chunk) * ring, hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_tail, 2 * sizeof(unsigned long long), hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_done, 2 * lay.done_bytes, hipHostMallocDefault);
-    if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_jobs, 2 * sizeof(CopyJob) * 3 * (size_t)reqs, hipHostMallocDefault);
+    if (e == hipSuccess)
+        e = hipHostMalloc((void **)&s->h_jobs, kJobBufs * sizeof(CopyJob) * 3 * (size_t)reqs, hipHostMallocDefault);
     if (e == hipSuccess) {
         std::memset(s->h_desc, 0, sizeof(ReqDesc) * reqs);
         std::memset(s->h_done, 0, 2 * lay.done_bytes);
@@ -503,26 +521,47 @@ extern "C" trw_status trw_server_destroy(trw_server s) {
 namespace trw {
 namespace {
 
-hipMemcpyKind kind_in(const trw_request &r) { return (r.flags & TRW_REQ_HOST) ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice; }
-hipMemcpyKind kind_out(const trw_request &r) { return (r.flags & TRW_REQ_HOST) ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice; }
-
-void complete(trw_server_s *s, Active &a, int32_t status) {
-    trw_completion c{};
-    c.request_id = a.id;
-    c.status = status;
-    c.nq = a.req.nq;
-    c.user = a.req.user;
-    c.t_submit_ns = a.t_submit;
-    c.t_admit_ns = a.t_admit;
-    c.t_done_ns = now_ns();
-    s->pool.release(a.pool_off, a.pool_bytes);
-    s->slot_done[a.slot] = a.done_base + a.req.nq;    // every query of a request counts once
-    s->free_slots.push_back(a.slot);
+// The requests of delivered batch `seq` complete: their pool ranges and
+// request slots are freed, and their completions are handed over under one
+// lock with one wake-up.
+void complete_batch(trw_server_s *s, uint64_t seq) {
+    std::vector<trw_completion> out;
+    const uint64_t t = now_ns();
+    for (const Active &a : s->active) {
+        if (!a.finishing || a.batch_seq != seq) continue;
+        trw_completion c{};
+        c.request_id = a.id;
+        c.status = a.cancelled ? TRW_E_CANCELLED : TRW_OK;
+        c.nq = a.req.nq;
+        c.user = a.req.user;
+        c.t_submit_ns = a.t_submit;
+        c.t_admit_ns = a.t_admit;
+        c.t_done_ns = t;
+        s->pool.release(a.pool_off, a.pool_bytes);
+        s->slot_done[a.slot] = a.done_base + a.req.nq;    // every query of a request counts once
+        s->free_slots.push_back(a.slot);
+        out.push_back(c);
+    }
+    s->active.erase(std::remove_if(s->active.begin(), s->active.end(),
+                                   [seq](const Active &a) { return a.finishing && a.batch_seq == seq; }),
+                    s->active.end());
     std::lock_guard<std::mutex> lk(s->mu);
-    s->completed.push_back(c);
-    if (status == TRW_OK) s->stats.completed++; else s->stats.cancelled++;
-    s->stats.active = (uint32_t)s->active.size() - 1;
+    for (const trw_completion &c : out) {
+        s->completed.push_back(c);
+        if (c.status == TRW_OK) s->stats.completed++; else s->stats.cancelled++;
+    }
+    s->stats.active = (uint32_t)s->active.size();
     s->cv_done.notify_all();
+}
+
+void desc_touch(trw_server_s *s, uint32_t i) {
+    if (s->desc_hi == s->desc_lo) {
+        s->desc_lo = i;
+        s->desc_hi = i + 1;
+    } else {
+        s->desc_lo = std::min(s->desc_lo, i);
+        s->desc_hi = std::max(s->desc_hi, i + 1);
+    }
 }
 
 // Admit waiting requests while a slot, pool space and ring entries are free
@@ -580,7 +619,7 @@ hipError_t admit(trw_server_s *s, std::deque<Pending> &incoming, int half) {
         d.status = status;
         d.stride = stride;
         d.nq = r.nq;
-        s->desc_dirty = true;
+        desc_touch(s, slot);
         const unsigned long long first_chunk = s->tail;
         for (uint32_t b = 0; b < r.nq; b += kChunkQueries) {
             Chunk &c = s->h_ring[s->tail % s->ring];
@@ -596,10 +635,11 @@ hipError_t admit(trw_server_s *s, std::deque<Pending> &incoming, int half) {
         s->active.push_back(a);
         incoming.pop_front();
     }
-    if (s->desc_dirty) {
-        e = hipMemcpyAsync(s->dev.reqs, s->h_desc, sizeof(ReqDesc) * s->max_reqs, hipMemcpyHostToDevice, s->stream);
+    if (s->desc_hi > s->desc_lo) {            // the changed range of the descriptor table only
+        e = hipMemcpyAsync(s->dev.reqs + s->desc_lo, s->h_desc + s->desc_lo, sizeof(ReqDesc) * (s->desc_hi - s->desc_lo),
+                           hipMemcpyHostToDevice, s->stream);
         if (e != hipSuccess) return e;
-        s->desc_dirty = false;
+        s->desc_lo = s->desc_hi = 0;
     }
     if (s->tail == tail0) return hipSuccess;
     // copy the new ring entries (they may wrap around), then publish the tail
@@ -625,9 +665,10 @@ void output_jobs(const trw_server_s *s, const Active &a, CopyJob *jobs) {
     const char *lengths = paths + align_up(sizeof(int32_t) * a.stride * r.nq);
     const char *status = lengths + align_up(sizeof(uint32_t) * (size_t)r.nq);
     jobs[0] = CopyJob{paths, reinterpret_cast<char *>(r.paths), sizeof(int32_t) * a.stride,
-                      sizeof(int32_t) * r.path_stride, sizeof(int32_t) * ((size_t)r.params.max_len + 1), r.nq, 0};
-    jobs[1] = CopyJob{lengths, reinterpret_cast<char *>(r.lengths), 0, 0, sizeof(uint32_t) * (size_t)r.nq, 1, 0};
-    jobs[2] = CopyJob{status, reinterpret_cast<char *>(r.status), 0, 0, (size_t)r.nq, 1, 0};
+                      sizeof(int32_t) * r.path_stride, sizeof(int32_t) * ((size_t)r.params.max_len + 1), r.nq, 0, 0};
+    jobs[1] = CopyJob{lengths, reinterpret_cast<char *>(r.lengths), 0, 0, sizeof(uint32_t) * (size_t)r.nq, 1, 0, 0};
+    jobs[2] = CopyJob{status, reinterpret_cast<char *>(r.status), 0, 0, (size_t)r.nq, 1, 0, 0};
+    for (int k = 0; k < 3; ++k) jobs[k].seg_per_row = (jobs[k].width + 15) / 16;
 }
 
 void server_loop(trw_server_s *s) {
@@ -673,7 +714,7 @@ void server_loop(trw_server_s *s) {
                 if (a.id == id && !a.cancelled && !a.finishing) {
                     a.cancelled = true;
                     s->h_desc[a.slot].cancelled = 1;
-                    s->desc_dirty = true;
+                    desc_touch(s, a.slot);
                 }
             }
         }
@@ -720,15 +761,17 @@ void server_loop(trw_server_s *s) {
             // on the delivery stream while the next tick runs (it touches none of
             // them); serial: on the tick stream, ahead of the next tick.
             Batch batch;
-            batch.jobs_buf = (int)(s->n_batches & 1);
+            batch.jobs_buf = (int)(s->n_batches % kJobBufs);
+            batch.seq = s->n_batches;
             CopyJob *jobs_half = s->h_jobs + (size_t)batch.jobs_buf * 3 * s->max_reqs;
             uint32_t njobs = 0;
-            uint64_t total_rows = 0;
+            uint64_t total_segs = 0;
             bool any_copy = false;
             for (size_t i = 0; i < s->active.size() && e == hipSuccess; ++i) {
                 Active &a = s->active[i];
                 if (a.finishing || done_prev[a.slot] - a.done_base < a.req.nq) continue;
                 a.finishing = true;
+                a.batch_seq = batch.seq;
                 batch.ids.push_back(a.id);
                 if (a.cancelled) continue;
                 CopyJob jobs[3];
@@ -742,8 +785,8 @@ void server_loop(trw_server_s *s) {
                     any_copy = true;
                 } else {
                     for (int k = 0; k < 3; ++k) {
-                        jobs[k].row_start = total_rows;
-                        total_rows += jobs[k].rows;
+                        jobs[k].seg_start = total_segs;
+                        total_segs += jobs[k].rows * jobs[k].seg_per_row;
                         jobs_half[njobs++] = jobs[k];
                     }
                 }
@@ -754,9 +797,10 @@ void server_loop(trw_server_s *s) {
                 CopyJob *d_jobs = reinterpret_cast<CopyJob *>(s->arena + s->lay.jobs);
                 e = hipMemcpyAsync(d_jobs, jobs_half, sizeof(CopyJob) * njobs, hipMemcpyHostToDevice, out_stream);
                 if (e == hipSuccess) {
-                    const uint64_t blocks = std::min<uint64_t>((total_rows + 3) / 4, 4096);
+                    const uint64_t per_block = 256 * (uint64_t)kDeliverSegs;
+                    const uint64_t blocks = (total_segs + per_block - 1) / per_block;
                     hipLaunchKernelGGL(k_deliver, dim3((uint32_t)blocks), dim3(256), 0, out_stream, d_jobs, njobs,
-                                       total_rows);
+                                       total_segs);
                     e = hipGetLastError();
                 }
                 any_copy = true;
@@ -779,22 +823,14 @@ void server_loop(trw_server_s *s) {
         // is reused two batches later, so wait for that batch if it still runs.
         while (e == hipSuccess && !s->batches.empty()) {
             Batch &b = s->batches.front();
-            const bool must_wait = s->batches.size() >= 2;
+            const bool must_wait = s->batches.size() >= (size_t)kJobBufs;
             if (b.done) {
                 hipError_t q = must_wait ? hipEventSynchronize(b.done) : hipEventQuery(b.done);
                 if (q == hipErrorNotReady) break;
                 if (q != hipSuccess) { e = q; break; }
                 s->spare_events.push_back(b.done);
             }
-            for (uint64_t id : b.ids) {
-                for (size_t i = 0; i < s->active.size(); ++i) {
-                    if (s->active[i].id == id) {
-                        complete(s, s->active[i], s->active[i].cancelled ? TRW_E_CANCELLED : TRW_OK);
-                        s->active.erase(s->active.begin() + i);
-                        break;
-                    }
-                }
-            }
+            complete_batch(s, b.seq);
             s->batches.pop_front();
         }
         prev_launched = s->pipelined && launched;
