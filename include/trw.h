@@ -292,7 +292,13 @@ typedef struct {
                                    the device's per-workgroup limit, n <= 65536): the graph is
                                    copied into LDS and walked there, with its own launch shape
                                    (the fields above do not apply).  Nonzero: never. */
-    uint32_t reserved[2];
+    uint32_t its_gallop_degree; /* ITS DeepWalk / PPR: rows of at least this many slots start
+                                   the search at the slot the random fraction points to and
+                                   gallop from it; shorter rows bisect the whole row.  Default 1
+                                   (every row searches from its guess) */
+    uint32_t n2v_search_degree; /* Node2Vec with an edge index: when the previous vertex has at
+                                   most this many edges, the adjacency test searches its sorted
+                                   row instead of probing the hash set.  Default: never */
 } trw_tuning;
 
 /* Workspace bytes trw_walk needs for nq queries in `mode`. */
@@ -361,7 +367,10 @@ trw_status trw_walk_noalloc(trw_graph g, trw_table table, const trw_walk_params 
  * d_sources in `mode`, timing each with HIP events, and writes the fastest to
  * *out.  Candidates: the default tuning first, then walkers per lane x blocks
  * per CU x queue chunk (persistent) or blocks per CU x block size (per step),
- * and for METAPATH without a label index the wave-scan degree.  The default is
+ * and for METAPATH without a label index the wave-scan degree; then, with the
+ * best of those, the walk's degree threshold if it has one (ITS DeepWalk /
+ * PPR: its_gallop_degree 8, 64, 512; Node2Vec with an edge index:
+ * n2v_search_degree 4, 16, 64).  The default is
  * kept unless a candidate is at least 3% faster, first in the scan and again
  * in five alternating timings of the two (medians).  Pass the whole batch when
  * a launch of it is short; a sample otherwise.  d_paths, d_lengths,

@@ -33,10 +33,11 @@ class trw_walk_params(ctypes.Structure):
 class trw_tuning(ctypes.Structure):
     _fields_ = [("walkers_per_lane", ctypes.c_uint32), ("block_threads", ctypes.c_uint32),
                 ("blocks_per_cu", ctypes.c_uint32), ("queue_chunk", ctypes.c_uint32),
-                ("coop_degree", ctypes.c_uint32), ("no_lds_graph", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 2)]
+                ("coop_degree", ctypes.c_uint32), ("no_lds_graph", ctypes.c_uint32),
+                ("its_gallop_degree", ctypes.c_uint32), ("n2v_search_degree", ctypes.c_uint32)]
 
     def as_dict(self):
-        return {k: int(getattr(self, k)) for k, _ in self._fields_ if k != "reserved"}
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
 class trw_server_cfg(ctypes.Structure):

@@ -122,7 +122,7 @@ trw_status check_params(trw_graph g, const trw_walk_params *p) {
 // contention; PPR's short walks also gain from two walkers per lane.
 Tuning resolve_tuning(const trw_walk_params *p, uint32_t mode, const trw_tuning *t, bool label_index) {
     const bool static_walk = p->algo == TRW_A_DEEPWALK || p->algo == TRW_A_PPR;
-    Tuning tu{1, 256, 8, 256, 256, true};
+    Tuning tu{1, 256, 8, 256, 256, 1, 0, true};
     if (mode == TRW_M_PERSISTENT) {
         if (static_walk && p->sampler == TRW_S_ALIAS) {
             tu.blocks_per_cu = p->algo == TRW_A_PPR ? 1 : 2;
@@ -144,6 +144,8 @@ Tuning resolve_tuning(const trw_walk_params *p, uint32_t mode, const trw_tuning 
         if (t->blocks_per_cu >= 1 && t->blocks_per_cu <= 64) tu.blocks_per_cu = t->blocks_per_cu;
         if (t->queue_chunk >= 1) tu.queue_chunk = t->queue_chunk;
         if (t->coop_degree >= 1) tu.coop_degree = t->coop_degree;
+        if (t->its_gallop_degree >= 1) tu.its_gallop_degree = t->its_gallop_degree;
+        if (t->n2v_search_degree >= 1) tu.n2v_search_degree = t->n2v_search_degree;
         if (t->no_lds_graph) tu.lds_graph = false;
     }
     return tu;
@@ -394,6 +396,8 @@ trw_status trw_default_tuning(trw_graph g, const trw_walk_params *p, uint32_t mo
     out->blocks_per_cu = tu.blocks_per_cu;
     out->queue_chunk = tu.queue_chunk;
     out->coop_degree = tu.coop_degree;
+    out->its_gallop_degree = tu.its_gallop_degree;
+    out->n2v_search_degree = tu.n2v_search_degree;
     return TRW_OK;
 }
 
@@ -497,6 +501,8 @@ trw_status walk_impl(trw_graph g, trw_table table, const trw_walk_params *p, con
             t.lfused = reinterpret_cast<const uint4 *>(static_cast<const char *>(table->buf) + fused);
     }
     const Tuning tu = resolve_tuning(p, mode, tuning, label_index);
+    w.its_gallop = tu.its_gallop_degree;
+    w.n2v_search = tu.n2v_search_degree;
     hipError_t e = counts ? launch_ppr_counts(g->dev, t, p->sampler, w, tu, device_info(), d_ws,
                                               static_cast<hipStream_t>(stream))
                           : launch_walk(g->dev, t, p->algo, p->sampler, w, mode, tu, device_info(), d_ws, ws_bytes,
@@ -588,35 +594,48 @@ trw_status trw_autotune(trw_graph g, trw_table table, const trw_walk_params *p, 
     // Candidates: the launch shape (walkers per lane, blocks per CU), the queue
     // chunk, and for MetaPath without a label index the degree at which a row
     // is scanned by the whole wave.  The library default comes first, so a
-    // budget of 1 returns it.
+    // budget of 1 returns it.  A second phase then tries the degree thresholds
+    // of the walk, if it has one, with the best launch shape of the first: the
+    // row degree from which ITS searches from its guess (shorter rows bisect),
+    // and the degree up to which Node2Vec's adjacency test searches the
+    // previous vertex's row instead of probing the edge index.
     std::vector<trw_tuning> cands;
     const bool scans = p->algo == TRW_A_METAPATH && table == nullptr;
+    const bool its_walk = (p->algo == TRW_A_DEEPWALK || p->algo == TRW_A_PPR) && p->sampler == TRW_S_ITS;
+    const bool n2v_eset = p->algo == TRW_A_NODE2VEC && table != nullptr && table->sampler == kEdgeIndexKind;
     if (mode == TRW_M_PERSISTENT) {
         const Tuning d = resolve_tuning(p, mode, nullptr, p->algo == TRW_A_METAPATH && table != nullptr);
         trw_tuning def{};
         def.walkers_per_lane = d.walkers_per_lane; def.block_threads = d.block_threads;
         def.blocks_per_cu = d.blocks_per_cu; def.queue_chunk = d.queue_chunk; def.coop_degree = d.coop_degree;
+        def.its_gallop_degree = d.its_gallop_degree; def.n2v_search_degree = d.n2v_search_degree;
         cands.push_back(def);
         for (uint32_t wpl : {1u, 2u, 4u})
             for (uint32_t bpc : {1u, 2u, 4u, 8u})
                 for (uint32_t chunk : {128u, 256u})
                     for (uint32_t coop : {256u, 1024u, 4096u, 16384u}) {
                         if (!scans && coop != 256u) continue;
-                        trw_tuning t{};
+                        trw_tuning t = def;
                         t.walkers_per_lane = wpl; t.block_threads = 256; t.blocks_per_cu = bpc;
                         t.queue_chunk = chunk; t.coop_degree = coop;
                         cands.push_back(t);
                     }
     } else {
+        const Tuning d = resolve_tuning(p, mode, nullptr, false);
         for (uint32_t bpc : {2u, 4u, 8u, 16u})
             for (uint32_t threads : {128u, 256u}) {
                 trw_tuning t{};
                 t.walkers_per_lane = 1; t.block_threads = threads; t.blocks_per_cu = bpc;
                 t.queue_chunk = 256; t.coop_degree = 256;
+                t.its_gallop_degree = d.its_gallop_degree; t.n2v_search_degree = d.n2v_search_degree;
                 cands.push_back(t);
             }
     }
-    if (budget > 0 && budget < cands.size()) cands.resize(budget);
+    std::vector<uint32_t> degrees;       // second phase: values of the walk's threshold
+    if (its_walk) degrees = {8u, 64u, 512u};
+    else if (n2v_eset) degrees = {4u, 16u, 64u};
+    const size_t limit = budget > 0 ? budget : cands.size() + degrees.size();
+    if (cands.size() > limit) cands.resize(limit);
     auto s = static_cast<hipStream_t>(stream);
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
@@ -628,7 +647,7 @@ trw_status trw_autotune(trw_graph g, trw_table table, const trw_walk_params *p, 
     float best = -1.0f, default_ms = -1.0f;
     trw_tuning best_t{};
     trw_status result = TRW_OK;
-    for (const auto &c : cands) {
+    auto try_candidate = [&](const trw_tuning &c) {
         // one untimed run (warm caches), one timed run
         for (int rep = 0; rep < 2 && result == TRW_OK; ++rep) {
             (void)hipEventRecord(e0, s);
@@ -636,8 +655,8 @@ trw_status trw_autotune(trw_graph g, trw_table table, const trw_walk_params *p, 
                               &c, d_ws, ws_bytes, stream);
             (void)hipEventRecord(e1, s);
         }
-        if (result != TRW_OK) break;
-        if (hipEventSynchronize(e1) != hipSuccess) { result = fail(TRW_E_DEVICE, "event sync failed"); break; }
+        if (result != TRW_OK) return;
+        if (hipEventSynchronize(e1) != hipSuccess) { result = fail(TRW_E_DEVICE, "event sync failed"); return; }
         float ms = 0;
         (void)hipEventElapsedTime(&ms, e0, e1);
         if (best < 0) {
@@ -647,6 +666,17 @@ trw_status trw_autotune(trw_graph g, trw_table table, const trw_walk_params *p, 
             best = ms;
             best_t = c;
         }
+    };
+    for (const auto &c : cands) {
+        try_candidate(c);
+        if (result != TRW_OK) break;
+    }
+    const trw_tuning shape = best_t;
+    for (size_t i = 0; i < degrees.size() && cands.size() + i < limit && result == TRW_OK; ++i) {
+        trw_tuning c = shape;
+        if (its_walk) c.its_gallop_degree = degrees[i];
+        else c.n2v_search_degree = degrees[i];
+        try_candidate(c);
     }
     // Confirm a winner against the default: five alternating timings of the
     // two (after a warm run of each); the winner is kept only if its median is

@@ -33,6 +33,7 @@ __device__ __forceinline__ void load_req(const ReqDesc &d, ReqRegs &q) {
     q.cancelled = d.cancelled;
     q.wd.thr[0] = d.thr[0]; q.wd.thr[1] = d.thr[1]; q.wd.thr[2] = d.thr[2];
     q.wd.seed = d.seed;
+    q.wd.n2v_search = 0;     // Node2Vec's adjacency test probes the edge index's hash set for every row
     q.qid_base = d.qid_base;
     q.lengths = d.lengths; q.status = d.status;
 }

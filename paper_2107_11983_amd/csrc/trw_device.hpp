@@ -105,6 +105,18 @@ __device__ __forceinline__ uint32_t its_search(const uint64_t *__restrict__ p, u
     return lo;
 }
 
+// ITS search by plain bisection over the whole row, with no guess: the
+// smallest i in [0, d) with x < p[i] (x < p[d-1] = W).  Same slot as the two
+// searches around it; the walks use it for rows below a tuned degree.
+__device__ __forceinline__ uint32_t its_bisect(const uint64_t *__restrict__ p, uint32_t d, uint64_t x) {
+    uint32_t lo = 0, hi = d - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (x < p[mid]) hi = mid; else lo = mid + 1;
+    }
+    return lo;
+}
+
 // ITS search that starts from the whole 64-byte block around the guess: the
 // block's eight prefixes arrive with one round trip and usually bracket the
 // answer; otherwise the search gallops outwards from the block's edge and

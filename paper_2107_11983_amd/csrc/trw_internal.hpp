@@ -81,6 +81,9 @@ struct WalkDev {
     uint8_t *status;
     uint32_t *end_counts;     // PPR estimate walks: counts[(qi / end_group) * n + end vertex]
     uint64_t end_group;       // queries per counts row (0: one row)
+    uint32_t its_gallop;      // ITS: rows of at least this many slots search from the guess (0, 1: all)
+    uint32_t n2v_search;      // Node2Vec with an edge index: prev rows of at most this many
+                              // edges are searched instead of probing the hash set (0: none)
 };
 
 enum : uint8_t { ST_LENGTH = 1, ST_STOPPED = 2, ST_DEAD_END = 3, ST_BAD_SOURCE = 4 };
@@ -108,6 +111,8 @@ struct Tuning {
     uint32_t blocks_per_cu;
     uint32_t queue_chunk;
     uint32_t coop_degree;     // MetaPath scan: rows at least this long are scanned by the whole wave
+    uint32_t its_gallop_degree;   // ITS: rows at least this long search from the guessed slot
+    uint32_t n2v_search_degree;   // Node2Vec + edge index: prev rows at most this long are searched
     bool lds_graph;           // NAIVE DeepWalk / PPR on a graph that fits one workgroup's LDS: walk it there
 };
 

@@ -551,7 +551,7 @@ k_walk_persistent(GraphDev g, TableDev t, WalkDev a, unsigned long long *__restr
             }
         } else if (kIts) {
             // x uniform in [0, W) from 64 bits; the smallest i with x < prefix[i]
-            // (its_search_block); the slot's record then gives the next vertex,
+            // (its_search_block; bisection for rows below a tuned degree); the slot's record then gives the next vertex,
             // its row and its W.
 #pragma unroll
             for (int i = 0; i < WPL; ++i) {
@@ -559,7 +559,10 @@ k_walk_persistent(GraphDev g, TableDev t, WalkDev a, unsigned long long *__restr
                 if (w[i].qi != kIdle && w[i].deg != 0 && w[i].W != 0) {
                     const uint64_t *__restrict__ pr = t.prefix + (uint32_t)w[i].off;
                     const uint64_t x = scale64(r[i].r0, r[i].r1, w[i].W);
-                    const uint32_t lo = its_search_block(pr, (uint32_t)w[i].deg, x, ((uint64_t)r[i].r1 << 32) | r[i].r0);
+                    const uint32_t dg = (uint32_t)w[i].deg;
+                    const uint32_t lo = dg >= a.its_gallop
+                                            ? its_search_block(pr, dg, x, ((uint64_t)r[i].r1 << 32) | r[i].r0)
+                                            : its_bisect(pr, dg, x);
                     const uint64_t e = (uint64_t)(uint32_t)w[i].off + lo;
                     const uint4 n0 = t.its_next[2 * e];
                     const uint4 n1 = t.its_next[2 * e + 1];
@@ -601,7 +604,7 @@ k_walk_persistent(GraphDev g, TableDev t, WalkDev a, unsigned long long *__restr
             for (int i = 0; i < WPL; ++i) {
                 nxt[i] = -1;
                 if (w[i].qi != kIdle && w[i].deg != 0) {
-                    nxt[i] = static_next<SMP>(g, t, w[i].off, (uint32_t)w[i].deg, r[i]);
+                    nxt[i] = static_next<SMP>(g, t, w[i].off, (uint32_t)w[i].deg, r[i], a.its_gallop);
                     w[i].poff = w[i].off; w[i].pdeg = w[i].deg;
                     w[i].need_row = true;
                 }
@@ -782,7 +785,7 @@ __global__ void __launch_bounds__(256) k_bsp_step(GraphDev g, TableDev t, WalkDe
                 if (d != 0)
                     nxt = n2v_move<SMP == SMP_OREJ_ADJ>(g, t, a, a.qid_base + rc.qi, k, off, d, r, rc.a, poff, pd, no, nd);
             } else {
-                if (d != 0) nxt = static_next<SMP>(g, t, off, d, r);
+                if (d != 0) nxt = static_next<SMP>(g, t, off, d, r, a.its_gallop);
             }
         }
         bool keep = false;

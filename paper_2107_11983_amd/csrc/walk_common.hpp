@@ -20,14 +20,16 @@ __device__ __forceinline__ uint32_t wave_total(uint32_t v) {
 // ---------------------------------------------------------------------------
 template <uint32_t SMP>
 __device__ __forceinline__ int32_t static_next(const GraphDev &g, const TableDev &t, int32_t off, uint32_t d,
-                                               const Rand4 &r) {
+                                               const Rand4 &r, uint32_t gallop_min) {
     if (SMP == SMP_NAIVE) return g.col[off + scale32(r.r0, d)];
-    // ITS: x uniform in [0, W) from 64 bits, smallest i with x < prefix[i]
+    // ITS: x uniform in [0, W) from 64 bits, smallest i with x < prefix[i];
+    // rows of at least gallop_min slots search from the guess, shorter ones bisect
     const uint64_t *__restrict__ p = t.prefix + off;
     const uint64_t W = p[d - 1];
     if (W == 0) return -1;
     const uint64_t x = scale64(r.r0, r.r1, W);
-    return g.col[off + its_search(p, d, x, ((uint64_t)r.r1 << 32) | r.r0)];
+    const uint32_t i = d >= gallop_min ? its_search(p, d, x, ((uint64_t)r.r1 << 32) | r.r0) : its_bisect(p, d, x);
+    return g.col[off + i];
 }
 
 // ---------------------------------------------------------------------------
@@ -110,8 +112,10 @@ __device__ __forceinline__ int32_t n2v_move(const GraphDev &g, const TableDev &t
                 accept = false;         // over both
             } else {
                 bool adjacent;
-                if (t.eset) {               // edge index: one probe sequence, usually one line
+                if (t.eset && (uint32_t)pd > a.n2v_search) {   // edge index: one probe sequence, usually one line
                     adjacent = eset_has(t.eset, t.eset_mask, prev, x);
+                } else if (t.eset) {        // a short row of prev: search it (a tuned degree)
+                    adjacent = in_row(g.col, poff, poff + pd, x);
                 } else {
                     adjacent = (ADJ && g.symmetric && xd < pd) ? in_row(g.col, xo, xo + xd, prev)
                                                                : in_row(g.col, poff, poff + pd, x);

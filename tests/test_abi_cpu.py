@@ -158,7 +158,9 @@ def test_default_tuning(abi):
     assert abi.trw_default_tuning(g, ctypes.byref(p), 1, ctypes.byref(t)) == abi.TRW_OK
     assert t.walkers_per_lane in (1, 2, 4) and t.block_threads % 64 == 0 and t.queue_chunk >= 1
     assert t.no_lds_graph == 0                       # small graphs walk from LDS unless told not to
-    assert ctypes.sizeof(abi.trw_tuning) == 32       # the switch took a reserved word; the size is unchanged
+    assert t.its_gallop_degree == 1                  # every ITS row searches from its guess
+    assert t.n2v_search_degree == 0                  # Node2Vec always probes the edge index
+    assert ctypes.sizeof(abi.trw_tuning) == 32       # the degree thresholds took the reserved words
     abi.trw_graph_destroy(g)
 
 

@@ -425,14 +425,16 @@ def test_tuning_does_not_change_results(rmat_sym, rmat_dir, algo, sampler, wpl, 
 
 
 @pytest.mark.parametrize("algo,sampler,index", [("ppr", "alias", None), ("metapath", "its", None),
-                                                ("node2vec", "orej", "adj")])
+                                                ("node2vec", "orej", "adj"), ("node2vec", "orej", "eidx"),
+                                                ("ppr", "its", None)])
 def test_autotune_picks_a_candidate_and_results_do_not_change(rmat_sym, rmat_dir, algo, sampler, index):
     case = rmat_dir if algo == "ppr" else rmat_sym
     src = synth.sources(20000, case.g.n, 31)
     kw = _args(algo)
     p = trw.make_params(algo, sampler, 40, 9, stop_q32=kw.get("stop", 0), n2v_thr_q16=kw.get("thr", (65536,) * 3),
                         schema=kw.get("schema", ()))
-    table = case.dev_table(sampler) if algo == "ppr" else (case.adjacency_index() if index == "adj" else None)
+    table = case.dev_table(sampler) if algo == "ppr" else (
+        case.adjacency_index() if index == "adj" else case.edge_index() if index == "eidx" else None)
     d_src = torch.from_numpy(src).cuda()
     best, ms = trw.autotune(case.G, table, p, d_src, mode=trw.TRW_M_PERSISTENT)
     assert ms > 0 and best.walkers_per_lane in (1, 2, 4) and best.blocks_per_cu >= 1
@@ -706,6 +708,35 @@ def test_edge_index_parity(rmat_sym, rmat_dir, algo, sampler, mode):
             assert_same(gpu, ref, 50)
             if algo != "node2vec":
                 break
+
+
+@pytest.mark.parametrize("mode", [1, 0])
+@pytest.mark.parametrize("degree", [8, 64, 1 << 30])
+def test_its_gallop_degree_does_not_change_results(rmat_sym, rmat_dir, degree, mode):
+    """ITS rows below the tuned degree bisect the whole row instead of searching
+    from the guessed slot (1 << 30: every row bisects); the slot is the same."""
+    for algo, case in (("deepwalk", rmat_sym), ("ppr", rmat_dir)):
+        n = case.g.n
+        src = np.concatenate([np.arange(n), synth.sources(61, n, 8)]).astype(np.int32)
+        tu = trw.make_tuning(its_gallop_degree=degree)
+        gpu, ref = run_both(case, algo, "its", 48, 606, src, mode, tuning=tu, **_args(algo))
+        assert_same(gpu, ref, 48)
+
+
+@pytest.mark.parametrize("mode", [1, 0])
+@pytest.mark.parametrize("degree", [4, 64, 1 << 30])
+def test_n2v_search_degree_does_not_change_results(rmat_sym, rmat_dir, degree, mode):
+    """Node2Vec with the edge index: rows of the previous vertex up to the tuned
+    degree are searched instead of probing the hash set (1 << 30: every row);
+    the same paths as the oracle, on a symmetric and a directed graph."""
+    for case in (rmat_sym, rmat_dir):
+        n = case.g.n
+        src = np.concatenate([np.arange(n), synth.sources(53, n, 12)]).astype(np.int32)
+        tu = trw.make_tuning(n2v_search_degree=degree)
+        for pq in ((2.0, 0.5), (0.25, 4.0)):
+            gpu, ref = run_both(case, "node2vec", "orej", 50, 808, src, mode, tuning=tu, edge_index=True,
+                                thr=oracle.n2v_thresholds(*pq))
+            assert_same(gpu, ref, 50)
 
 
 def test_edge_index_layout(rmat_dir):
