@@ -6,10 +6,11 @@ workload on a resident weighted symmetric R-MAT graph with 2^26 vertices and
 average degree 16 (about 1.06 G directed edges): requests of 1..4096 queries,
 each DeepWalk (80 moves, ALIAS), PPR (stop 0.2 after each move, ALIAS) or
 Node2Vec (p = 2, q = 0.5, 80 moves, O-REJ), served by continuous batching with
-memory admission and graph-captured ticks.  A "step" is one saturated replay
-of 2000 requests (all submitted at once; admitted as slots and memory free
-up); W replays warm up, K are timed.  Then p50/p99 request latency is measured
-with Poisson arrivals at 0.7x the saturated request rate.
+memory admission and graph-captured ticks.  W bursts of 2000 requests warm up;
+the timed region serves K x 2000 requests submitted at once (a backlog, so the
+server is saturated: admitted as slots and memory free up), and a "step" is
+2000 of them.  Then p50/p99 request latency is measured with Poisson arrivals
+at 0.7x the saturated request rate.
 
 The four batch workloads (deepwalk-rmat12, ppr-rmat22, node2vec-rmat24,
 metapath-rmat24) run first and are reported as nested objects, each with its
@@ -132,12 +133,13 @@ def main():
     ap.add_argument("--no-probe", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle CPU time (headline)")
     ap.add_argument("--cpu-seconds-nested", type=float, default=4.0, help="target oracle CPU time per nested workload")
-    ap.add_argument("--serve-replay", type=int, default=2000, help="requests per saturated replay (one step)")
+    ap.add_argument("--serve-replay", type=int, default=2000, help="requests per step: one block of the timed backlog, and one warm-up burst")
     ap.add_argument("--serve-requests", type=int, default=10000, help="measured requests of the latency phase")
     ap.add_argument("--serve-scale", type=int, default=0, help="override the served graph's scale (tests)")
     ap.add_argument("--serve-slots-per-cu", type=int, default=2048)
     ap.add_argument("--serve-steps", type=int, default=32, help="moves per walker slot per tick")
     ap.add_argument("--serve-pipelined", type=int, default=1, help="0: serial ticks (read each tick before queueing the next)")
+    ap.add_argument("--serve-max-requests", type=int, default=4096, help="requests the server holds admitted at once")
     ap.add_argument("--serve-rate", type=float, default=0.0, help="offered requests/s (0: 0.7x the saturated rate)")
     ap.add_argument("--profile-pass", action="store_true",
                     help="short run for counter collection: a 1 GiB copy (calibration) then the timed kernel only")
@@ -652,8 +654,9 @@ def bench_served(args, wl, ctx):
     """Served mixed workload: requests of 1..4096 queries, each DeepWalk (80 moves, ALIAS), PPR
     (stop 0.2, ALIAS) or Node2Vec (p=2, q=0.5, 80 moves, O-REJ with the edge index), on a resident
     weighted symmetric R-MAT graph; continuous batching with memory admission and graph-captured
-    ticks.  Timed: K saturated replays of `serve_replay` requests each (W more warm up).  Then
-    p50/p99 request latency at 0.7x the saturated request rate, with Poisson arrivals."""
+    ticks.  W bursts of `serve_replay` requests warm up; timed: K such blocks submitted at once as
+    one backlog (saturation).  Then p50/p99 request latency at 0.7x the saturated request rate,
+    with Poisson arrivals."""
     import ctypes
     from paper_2107_11983_amd import _abi
     np, torch, synth, trw = ctx.np, ctx.torch, ctx.synth, ctx.trw
@@ -695,27 +698,40 @@ def bench_served(args, wl, ctx):
               trw.make_params("ppr", "alias", 256, wl.walk_seed, stop_q32=stop_q32),
               trw.make_params("node2vec", "orej", 80, wl.walk_seed, n2v_thr_q16=n2v_thr)]
     strides = np.array([88, 264, 88])
+    # Requests in blocks of R: W warm-up bursts, the K timed blocks (served as one backlog),
+    # then the latency run.
     replays = [(i * R, (i + 1) * R) for i in range(W + K)]
     if n_lat:
         replays.append(((W + K) * R, N))
-    # Paths: one buffer reused by every replay (rows from its start); lengths and status: a
-    # place for every query, so that the timed replays are tallied after the timed region.
-    path_need = max(int((sizes[lo:hi] * strides[kinds[lo:hi]]).sum()) for lo, hi in replays)
-    d_paths = torch.empty(path_need, dtype=torch.int32, device="cuda")
+    # Paths: every request of the timed backlog has rows of its own, so no two requests in
+    # flight at once share any; past 64 GiB of rows (a long --steps) its blocks of R requests
+    # wrap round, and requests that share rows are then 64 GiB of rows apart.  The warm-up
+    # bursts (each drained before the next) and the latency run take rows from the start again.
+    # Lengths and status: a place for every query, tallied after the timed region.
+    entries = sizes * strides[kinds]
+    blk = np.arange(N) // R
+    cs = np.concatenate([[0], np.cumsum(entries)])
+    within = cs[:-1] - cs[blk * R]
+    n_blk = int(blk[-1]) + 1
+    block_need = int(max(cs[min(b * R + R, N)] - cs[b * R] for b in range(n_blk)))
+    cap = max(1, (64 << 30) // (4 * block_need))
+    n_parts = min(max(K, n_blk - (W + K)), cap)
+    part = np.where(blk < W, 0, np.where(blk < W + K, blk - W, blk - (W + K))) % n_parts
+    poff_all = part * block_need + within
+    d_paths = torch.empty(n_parts * block_need, dtype=torch.int32, device="cuda")
     d_len = torch.empty(int(offs[-1]), dtype=torch.int32, device="cuda")
     d_st = torch.empty(int(offs[-1]), dtype=torch.uint8, device="cuda")
 
     def make_reqs(lo, hi):
         """trw_request array for requests [lo, hi)."""
         reqs = (_abi.trw_request * (hi - lo))()
-        poff = np.concatenate([[0], np.cumsum(sizes[lo:hi] * strides[kinds[lo:hi]])])
         for j, i in enumerate(range(lo, hi)):
             r = reqs[j]
             r.params = algo_p[kinds[i]]
             r.nq = int(sizes[i])
             r.sources = ctypes.c_void_p(d_src.data_ptr() + 4 * int(offs[i]))
             r.qid_base = i << 32
-            r.paths = ctypes.c_void_p(d_paths.data_ptr() + 4 * int(poff[j]))
+            r.paths = ctypes.c_void_p(d_paths.data_ptr() + 4 * int(poff_all[i]))
             r.path_stride = int(strides[kinds[i]])
             r.lengths = ctypes.c_void_p(d_len.data_ptr() + 4 * int(offs[i]))
             r.status = ctypes.c_void_p(d_st.data_ptr() + int(offs[i]))
@@ -724,45 +740,50 @@ def bench_served(args, wl, ctx):
     req_arrays = [make_reqs(lo, hi) for lo, hi in replays]
     arrivals_zero = [(ctypes.c_uint64 * (hi - lo))() for lo, hi in replays]
     completions = [(_abi.trw_completion * (hi - lo))() for lo, hi in replays]
+    backlog = (W * R, (W + K) * R)
+    req_backlog = make_reqs(*backlog)
+    arrivals_backlog = (ctypes.c_uint64 * (K * R))()
+    comp_backlog = (_abi.trw_completion * (K * R))()
 
     torch.cuda.synchronize()
     slots = ctx.props.multi_processor_count * args.serve_slots_per_cu
-    srv = trw.Server(G, alias, eidx, pool_bytes=8 << 30, max_slots=slots, max_requests=1024,
+    srv = trw.Server(G, alias, eidx, pool_bytes=8 << 30, max_slots=slots, max_requests=args.serve_max_requests,
                      steps_per_tick=args.serve_steps, pipelined=bool(args.serve_pipelined))
 
-    def replay(ri, arrivals=None):
-        """Serve replay ri (requests arriving at the given offsets, default all at once)."""
-        lo, hi = replays[ri]
-        arr = arrivals_zero[ri] if arrivals is None else arrivals
+    def serve(n, reqs, arrivals, comps):
+        """Serve n requests arriving at the given offsets (ns from the start); returns the wall
+        time and the server's moves, ticks and tick device time over the run."""
         s0 = srv.stats()
         t = time.perf_counter()
-        rc = _abi.trw_probe_serve_replay(srv.handle, hi - lo, req_arrays[ri], arr, completions[ri], 600_000)
+        rc = _abi.trw_probe_serve_replay(srv.handle, n, reqs, arrivals, comps, 600_000)
         wall = time.perf_counter() - t
         s1 = srv.stats()
         assert rc == 0, f"replay failed: {rc} {_abi.trw_last_error()}"
-        return completions[ri], wall, {k: s1[k] - s0[k] for k in ("moves", "ticks", "tick_device_ns")}
+        return wall, {k: s1[k] - s0[k] for k in ("moves", "ticks", "tick_device_ns")}
+
+    def replay(ri, arrivals=None):
+        """Serve block ri (requests arriving at the given offsets, default all at once)."""
+        lo, hi = replays[ri]
+        wall, d = serve(hi - lo, req_arrays[ri], arrivals_zero[ri] if arrivals is None else arrivals,
+                        completions[ri])
+        return completions[ri], wall, d
 
     for r in range(W):
         _, wall, d = replay(r)
-        log(f"warm-up replay {r}: {R / wall:.0f} req/s, {d['moves'] / wall:.4g} steps/s")
+        log(f"warm-up burst {r}: {R / wall:.0f} req/s, {d['moves'] / wall:.4g} steps/s")
+    # Timed: the K blocks as one backlog, every request submitted at the start, so admission
+    # always has a request waiting (saturation); one ramp at the start and one drain at the end.
     tick0 = srv.stats()["ticks"]
     torch.cuda.synchronize()
     t_start = time.perf_counter()
-    walls, moves, ticks, tick_ns = [], 0, 0, 0
-    for r in range(W, W + K):
-        _, wall, d = replay(r)
-        walls.append(wall)
-        moves += d["moves"]
-        ticks += d["ticks"]
-        tick_ns += d["tick_device_ns"]
+    _, d = serve(K * R, req_backlog, arrivals_backlog, comp_backlog)
     torch.cuda.synchronize()
     region = time.perf_counter() - t_start
+    moves, ticks, tick_ns = d["moves"], d["ticks"], d["tick_device_ns"]
     value = moves / region
-    for r in range(W, W + K):
-        lo, hi = replays[r]
-        assert all(completions[r][i].status == 0 for i in range(hi - lo))
-    # per-kind moves, dead ends and queries of the timed replays
-    q_lo, q_hi = int(offs[replays[W][0]]), int(offs[replays[W + K - 1][1]])
+    assert all(comp_backlog[i].status == 0 for i in range(K * R))
+    # per-kind moves, dead ends and queries of the timed backlog
+    q_lo, q_hi = int(offs[backlog[0]]), int(offs[backlog[1]])
     kq = d_kind[q_lo:q_hi].to(torch.int64)
     L = d_len[q_lo:q_hi].to(torch.int64)
     dead = (d_st[q_lo:q_hi] == trw.TRW_ST_DEAD_END).to(torch.int64)
@@ -770,12 +791,23 @@ def bench_served(args, wl, ctx):
                           int((kq == k).sum())] for k in range(3)])
     assert int(per_kind[:, 0].sum()) == moves, "moves counted by the server and by the lengths differ"
     sat_rps = K * R / region
-    log(f"timed: {K} saturated replays of {R} requests, {region:.3f}s: {sat_rps:.0f} req/s, {value:.4g} steps/s; "
+    log(f"timed: a backlog of {K} x {R} requests, {region:.3f}s: {sat_rps:.0f} req/s, {value:.4g} steps/s; "
         f"{ticks} ticks (tick {tick0}..{tick0 + ticks - 1} of this server), {tick_ns / max(ticks, 1) / 1e6:.4f} ms "
         f"device time per tick")
     if args.profile_pass:
         srv.close()
         return None
+    # The same K blocks again as bursts, each drained before the next is submitted: the server
+    # ramps up and drains once per block (context for the backlog figure, not timed with it).
+    burst_walls, burst_moves = [], 0
+    for r in range(W, W + K):
+        _, wall, d = replay(r)
+        burst_walls.append(wall)
+        burst_moves += d["moves"]
+    assert burst_moves == moves
+    bursts = {"req_per_s": round(K * R / sum(burst_walls), 1), "steps_per_s": round(burst_moves / sum(burst_walls), 1),
+              "burst_req_per_s": [round(R / w, 1) for w in burst_walls]}
+    log(f"the same blocks as {K} bursts of {R}: {bursts['req_per_s']:.0f} req/s, {bursts['steps_per_s']:.4g} steps/s")
 
     # Latency: Poisson arrivals at 0.7x the saturated request rate (or a fixed rate).
     rate = args.serve_rate or 0.7 * sat_rps
@@ -883,8 +915,8 @@ def bench_served(args, wl, ctx):
         "ms_per_step": round(1000 * region / K, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u32", "data": "synthetic",
         "config": {"workload": f"{wl.name}: served mix of DeepWalk-80 ALIAS / PPR-0.2 ALIAS / Node2Vec p=2 q=0.5 "
-                               f"len 80 (O-REJ, edge index), requests of U{{1..4096}} queries; a step is one "
-                               f"saturated replay of {R} requests (all submitted at once, continuous batching); "
+                               f"len 80 (O-REJ, edge index), requests of U{{1..4096}} queries; a step is {R} "
+                               f"requests of a backlog of {K * R} submitted at once (continuous batching); "
                                f"latency at Poisson arrivals "
                                f"{'%.0f req/s' % args.serve_rate if args.serve_rate else '0.7x saturation'}; "
                                f"R-MAT 2^{int(np.log2(g.n))} symmetric avg deg {wl.avg_degree}, uint32 weights 1..255",
@@ -899,14 +931,14 @@ def bench_served(args, wl, ctx):
                        "warmup_requests": n_lat_warm},
         "offered_req_per_s": round(rate, 1), "achieved_req_per_s": round(n_lat / span, 1),
         "steps_per_s_at_offered": round(d_l["moves"] / wall_l, 1),
-        "saturated": {"req_per_s": round(sat_rps, 1), "steps_per_s": round(value, 1),
-                      "replay_req_per_s": [round(R / w, 1) for w in walls]},
+        "saturated": {"req_per_s": round(sat_rps, 1), "steps_per_s": round(value, 1), "backlog_requests": K * R,
+                      "bursts": bursts},
         "same_queries_batch_walker": batch,
         "served_vs_batch": {"served_saturated_steps_per_s": round(served_replay_sps, 1),
                             "vs_persistent": round(served_replay_sps / batch["persistent"]["all"]["steps_per_s"], 4),
                             "vs_per_step": round(served_replay_sps / batch["per_step"]["all"]["steps_per_s"], 4)},
         "server": {"ticks": st["ticks"], "steps_per_tick": args.serve_steps, "slots": slots,
-                   "pipelined": bool(args.serve_pipelined), "max_requests": 1024, "pool_bytes": st["pool_bytes"],
+                   "pipelined": bool(args.serve_pipelined), "max_requests": args.serve_max_requests, "pool_bytes": st["pool_bytes"],
                    "timed_ticks": ticks, "first_timed_tick": tick0},
         "preprocess_ms": pre,
         "gather_ceiling": ctx.gather,
