@@ -830,6 +830,8 @@ def bench_served(args, wl, ctx):
     batch = {}
     for k, name in enumerate(synth.SERVED_KINDS):
         idx = [i for i in range(lo, hi) if kinds[i] == k]
+        if not idx:
+            continue
         src_k = torch.from_numpy(np.concatenate([src_np[offs[i]:offs[i + 1]] for i in idx])).cuda()
         p = algo_p[k]
         table = alias if k < 2 else eidx

@@ -575,7 +575,8 @@ typedef struct {
     uint32_t nq;               /* >= 1 */
     uint32_t flags;            /* TRW_REQ_HOST or 0 (device buffers) */
     uint64_t qid_base;         /* query i has id qid_base + i (same walks as trw_walk) */
-    int32_t *paths;            /* nq rows of path_stride entries, written at completion */
+    int32_t *paths;            /* nq rows of path_stride entries; device buffers are written in
+                                  place as the walks run, host ones at completion */
     uint64_t path_stride;      /* >= max_len + 1 */
     uint32_t *lengths;         /* nq */
     uint8_t *status;           /* nq, trw_walk_status */
@@ -612,7 +613,8 @@ trw_status trw_server_arena_bytes(const trw_server_cfg *cfg, size_t pool_bytes, 
 trw_status trw_server_create(trw_graph g, trw_table alias, trw_table adjacency, const trw_server_cfg *cfg,
                              void *d_arena, size_t arena_bytes, trw_server *out);
 
-/* Pool bytes a request occupies while admitted (its sources and outputs). */
+/* Pool bytes a request occupies while admitted: for host buffers its sources
+ * and outputs, staged on the device; 0 for device buffers (used in place). */
 trw_status trw_server_request_bytes(trw_server s, const trw_request *r, size_t *bytes);
 
 /*
@@ -620,9 +622,10 @@ trw_status trw_server_request_bytes(trw_server s, const trw_request *r, size_t *
  * a request slot and pool space are free, in submission order.  Errors:
  * TRW_E_NOMEM_BUDGET if it can never fit the pool, TRW_E_UNSUPPORTED /
  * TRW_E_INVALID as trw_walk.  The caller keeps the sources and the output
- * buffers valid until the completion is polled.  Outputs are written when the
- * request completes (device destinations by one copy launch per tick for all
- * requests finishing together; host destinations by plain copies).
+ * buffers valid until the completion is polled, and reads the outputs only
+ * then.  Device outputs are written in place by the walks (no copy at the
+ * end; after a cancellation their contents are unspecified); host outputs
+ * are staged in the pool and copied out when the request completes.
  */
 trw_status trw_server_submit(trw_server s, const trw_request *r, uint64_t *request_id);
 

@@ -1,20 +1,20 @@
 // Serving: a resident graph and tables, a fixed pool of walker slots on the
-// device, and a host thread that admits requests by memory, publishes their
-// queries in chunks and replays the tick graph while anything is in flight.
+// device, and a host thread that admits requests, publishes their queries in
+// chunks and replays the tick graph while anything is in flight.
 //
 // Memory: one caller-provided arena holds the fixed device state (request
-// descriptors, chunk ring, counters, walker slots) followed by a pool from
-// which every admitted request gets its input copy and output rows.  A
-// request waits (first come, first served) until a descriptor slot and pool
-// space are free; one that could never fit is refused at submit.
+// descriptors, chunk ring, counters, walker slots) followed by a pool.  A
+// request with device buffers is read and written in place and takes no pool
+// space; one with host buffers gets its input copy and output rows from the
+// pool.  A request waits (first come, first served) until a descriptor slot
+// and pool space are free; one that could never fit is refused at submit.
 //
 // Per tick the thread (1) admits what fits and publishes the descriptor table
 // and the new ring chunks (one copy each), (2) launches the tick (a captured
 // graph), (3) reads all completion counters back in one copy, and (4)
-// delivers the outputs of finished requests: one scatter-copy launch for all
-// device destinations, plain copies for host ones.  The host cost per tick is
-// a fixed handful of calls, whatever the number of requests.  Device sources
-// are read in place; host sources are staged in the pool.
+// completes the requests that finished: device outputs are already in place,
+// host outputs are copied out of the pool.  The host cost per tick is a fixed
+// handful of calls, whatever the number of requests.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -38,50 +38,12 @@ __global__ void k_fill_bytes(uint32_t *p, size_t n_words, uint32_t v) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_words; i += stride) p[i] = v;
 }
 
-// A 2D copy of `rows` rows of `width` bytes, cut into 16-byte segments
-// (seg_per_row per row, the last one of a row possibly short); seg_start =
-// segments of all earlier jobs of the same delivery.
+// A 2D copy of `rows` rows of `width` bytes (host outputs of a finished request).
 struct CopyJob {
     const char *src;
     char *dst;
-    uint64_t src_pitch, dst_pitch, width, rows, seg_start;
-    uint64_t seg_per_row;
+    uint64_t src_pitch, dst_pitch, width, rows;
 };
-
-constexpr uint32_t kDeliverSegs = 16;     // segments per thread: a block copies 64 KiB
-
-// Output delivery: block b copies segments [b, b + 1) * 256 * kDeliverSegs of
-// all jobs together, consecutive threads on consecutive segments.  The job of
-// the block's first segment is found once (binary search); later segments
-// step forward through the jobs.  A full segment whose source and
-// destination are 16-byte aligned moves as one 16-byte load and store, the
-// others byte by byte.
-__global__ void __launch_bounds__(256) k_deliver(const CopyJob *__restrict__ jobs, uint32_t n_jobs,
-                                                 uint64_t total_segs) {
-    const uint64_t base = (uint64_t)blockIdx.x * 256 * kDeliverSegs;
-    uint32_t lo = 0, hi = n_jobs - 1;                   // last job with seg_start <= base
-    while (lo < hi) {
-        const uint32_t mid = (lo + hi + 1) >> 1;
-        if (jobs[mid].seg_start <= base) lo = mid; else hi = mid - 1;
-    }
-    uint32_t j = lo;
-    for (uint32_t i = 0; i < kDeliverSegs; ++i) {
-        const uint64_t g = base + threadIdx.x + 256 * (uint64_t)i;
-        if (g >= total_segs) break;
-        while (j + 1 < n_jobs && jobs[j + 1].seg_start <= g) ++j;
-        const CopyJob &jb = jobs[j];
-        const uint64_t s = g - jb.seg_start;
-        const uint64_t row = s / jb.seg_per_row, col = 16 * (s % jb.seg_per_row);
-        const char *src = jb.src + row * jb.src_pitch + col;
-        char *dst = jb.dst + row * jb.dst_pitch + col;
-        const uint64_t n = min((uint64_t)16, jb.width - col);
-        if (n == 16 && ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 15) == 0) {
-            *reinterpret_cast<uint4 *>(dst) = *reinterpret_cast<const uint4 *>(src);
-        } else {
-            for (uint64_t c = 0; c < n; ++c) dst[c] = src[c];
-        }
-    }
-}
 
 namespace {
 
@@ -138,7 +100,7 @@ class RangeAllocator {
 };
 
 struct Layout {
-    size_t reqs, ring, counters, done, done_bytes, jobs, slots, waves, pool, fixed;
+    size_t reqs, ring, counters, done, done_bytes, slots, waves, pool, fixed;
 };
 
 // The completion counters are followed by the moves counter so that one copy
@@ -152,7 +114,6 @@ Layout layout(uint32_t slots, uint32_t max_reqs, uint32_t ring) {
     l.done = o;
     l.done_bytes = (sizeof(uint32_t) * max_reqs + 7) / 8 * 8 + sizeof(unsigned long long);
     o = align_up(o + l.done_bytes);
-    l.jobs = o; o = align_up(o + sizeof(CopyJob) * 3 * (size_t)max_reqs);
     l.slots = o; o = align_up(o + sizeof(SlotState) * slots);
     l.waves = o; o = align_up(o + sizeof(WaveState) * (slots / 64));
     l.pool = o;
@@ -182,16 +143,14 @@ struct Active {
     uint64_t batch_seq = 0;    // the delivery batch it finished in (when finishing)
 };
 
-constexpr int kJobBufs = 4;    // pinned job tables: a batch's is reused kJobBufs batches later
-
 // Mark descriptor slot i as changed (copied to the device before the next tick).
 void desc_touch(trw_server_s *s, uint32_t i);
 
-// Output copies of the requests that finished in one tick, in flight on the
-// delivery stream; the requests complete when `done` has been reached.
+// The requests that finished in one tick.  Host outputs are copied on the
+// delivery stream; the requests complete when `done` has been reached (no
+// event when the batch had nothing to copy).
 struct Batch {
     hipEvent_t done = nullptr;
-    int jobs_buf = 0;                  // which of the pinned job tables it used
     uint64_t seq = 0;                  // its sequence number (Active::batch_seq of its requests)
     std::vector<uint64_t> ids;
 };
@@ -215,17 +174,16 @@ struct trw_server_s {
     ServeDev dev;
     RangeAllocator pool;
     // host staging (pinned).  Ticks are pipelined one deep: while tick i runs
-    // the host reads tick i-1's counters and delivers its finished requests on
-    // a second stream, so the tail, the counter read-back and the job table
-    // have two halves, used by alternate ticks (batches).
+    // the host reads tick i-1's counters and completes its finished requests
+    // (host outputs copied on a second stream), so the tail and the counter
+    // read-back have two halves, used by alternate ticks.
     ReqDesc *h_desc = nullptr;                // mirror of the device descriptor table
     Chunk *h_ring = nullptr;
     unsigned long long *h_tail = nullptr;     // [2]
     uint32_t *h_done = nullptr;               // [2] x (completion counters, then the moves counter)
-    CopyJob *h_jobs = nullptr;                // [kJobBufs] x 3 * max_requests
     uint32_t desc_lo = 0, desc_hi = 0;        // descriptor slots changed since the last copy: [lo, hi)
     hipStream_t stream = nullptr;             // ticks and the copies that feed them
-    hipStream_t deliver_stream = nullptr;     // output copies of finished requests
+    hipStream_t deliver_stream = nullptr;     // host output copies of finished requests
     hipEvent_t tick_done[2] = {nullptr, nullptr};
     hipEvent_t tick_start[2] = {nullptr, nullptr};
     hipEvent_t tick_end[2] = {nullptr, nullptr};     // right after the tick kernel, before the read-back
@@ -262,12 +220,16 @@ trw_status sfail(trw_status st, const std::string &m) {
     return st;
 }
 
-// Pool layout of an admitted request: [host sources copy], paths, lengths, status.
+// Pool layout of an admitted request with host buffers: sources copy, paths,
+// lengths, status (copied to the host at completion).  A request with device
+// buffers takes no pool space: its sources are read and its outputs written
+// in place.
 size_t request_src_bytes(const trw_request &r) {
     return (r.flags & TRW_REQ_HOST) ? align_up(sizeof(int32_t) * (size_t)r.nq) : 0;
 }
 
 size_t request_pool_bytes(const trw_request &r) {
+    if (!(r.flags & TRW_REQ_HOST)) return 0;
     const uint64_t stride = ((uint64_t)r.params.max_len + 1 + 7) / 8 * 8;
     return request_src_bytes(r) + align_up(sizeof(int32_t) * stride * r.nq) + align_up(sizeof(uint32_t) * (size_t)r.nq) +
            align_up((size_t)r.nq);
@@ -384,8 +346,6 @@ extern "C" trw_status trw_server_create(trw_graph g, trw_table alias, trw_table 
     if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_ring, sizeof(Chunk) * ring, hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_tail, 2 * sizeof(unsigned long long), hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_done, 2 * lay.done_bytes, hipHostMallocDefault);
-    if (e == hipSuccess)
-        e = hipHostMalloc((void **)&s->h_jobs, kJobBufs * sizeof(CopyJob) * 3 * (size_t)reqs, hipHostMallocDefault);
     if (e == hipSuccess) {
         std::memset(s->h_desc, 0, sizeof(ReqDesc) * reqs);
         std::memset(s->h_done, 0, 2 * lay.done_bytes);
@@ -511,7 +471,6 @@ extern "C" trw_status trw_server_destroy(trw_server s) {
     if (s->h_ring) (void)hipHostFree(s->h_ring);
     if (s->h_tail) (void)hipHostFree(s->h_tail);
     if (s->h_done) (void)hipHostFree(s->h_done);
-    if (s->h_jobs) (void)hipHostFree(s->h_jobs);
     if (s->deliver_stream) (void)hipStreamDestroy(s->deliver_stream);
     if (s->stream) (void)hipStreamDestroy(s->stream);
     delete s;
@@ -537,7 +496,7 @@ void complete_batch(trw_server_s *s, uint64_t seq) {
         c.t_submit_ns = a.t_submit;
         c.t_admit_ns = a.t_admit;
         c.t_done_ns = t;
-        s->pool.release(a.pool_off, a.pool_bytes);
+        if (a.pool_bytes) s->pool.release(a.pool_off, a.pool_bytes);
         s->slot_done[a.slot] = a.done_base + a.req.nq;    // every query of a request counts once
         s->free_slots.push_back(a.slot);
         out.push_back(c);
@@ -566,7 +525,10 @@ void desc_touch(trw_server_s *s, uint32_t i) {
 
 // Admit waiting requests while a slot, pool space and ring entries are free
 // (first come, first served), then publish the descriptor table, the new
-// chunks and the tail.
+// chunks and the tail.  The chunks admitted together are published grouped
+// by walk kind (algorithm and sampler), in admission order within a kind:
+// waves take chunks in ring order, so a wave's lanes then mostly run one kind
+// of move, and a wave does not step at the pace of its slowest kind.
 //
 // Ring entries: the device may still read a published chunk only while its
 // request has queries not yet counted done (a query is counted once its walk
@@ -581,16 +543,19 @@ hipError_t admit(trw_server_s *s, std::deque<Pending> &incoming, int half) {
     unsigned long long oldest = s->tail;
     for (const Active &a : s->active)
         if (!a.finishing) oldest = std::min(oldest, a.first_chunk);
+    const size_t first_new = s->active.size();
+    unsigned long long new_chunks = 0;
     while (!incoming.empty() && !s->free_slots.empty()) {
         Pending &p = incoming.front();
         const unsigned long long chunks = (p.req.nq + kChunkQueries - 1) / kChunkQueries;
-        if (s->tail + chunks - oldest > s->ring) break;
+        if (tail0 + new_chunks + chunks - oldest > s->ring) break;
         size_t off = 0;
-        if (!s->pool.alloc(p.bytes, &off)) break;
+        if (p.bytes && !s->pool.alloc(p.bytes, &off)) break;
         const uint32_t slot = s->free_slots.back();
         s->free_slots.pop_back();
         const trw_request &r = p.req;
-        const uint64_t stride = ((uint64_t)r.params.max_len + 1 + 7) / 8 * 8;
+        const bool in_place = !(r.flags & TRW_REQ_HOST);
+        const uint64_t stride = in_place ? r.path_stride : ((uint64_t)r.params.max_len + 1 + 7) / 8 * 8;
         char *base = s->arena + s->lay.pool + off;
         const size_t src_bytes = request_src_bytes(r);
         const int32_t *src = static_cast<const int32_t *>(r.sources);
@@ -599,11 +564,16 @@ hipError_t admit(trw_server_s *s, std::deque<Pending> &incoming, int half) {
             if (e != hipSuccess) return e;
             src = reinterpret_cast<const int32_t *>(base);
         }
-        int32_t *paths = reinterpret_cast<int32_t *>(base + src_bytes);
-        uint32_t *lengths = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(paths) +
-                                                         align_up(sizeof(int32_t) * stride * r.nq));
-        uint8_t *status = reinterpret_cast<uint8_t *>(reinterpret_cast<char *>(lengths) +
-                                                      align_up(sizeof(uint32_t) * (size_t)r.nq));
+        int32_t *paths = r.paths;
+        uint32_t *lengths = r.lengths;
+        uint8_t *status = r.status;
+        if (!in_place) {                       // staged in the pool, copied to the host at completion
+            paths = reinterpret_cast<int32_t *>(base + src_bytes);
+            lengths = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(paths) +
+                                                   align_up(sizeof(int32_t) * stride * r.nq));
+            status = reinterpret_cast<uint8_t *>(reinterpret_cast<char *>(lengths) +
+                                                 align_up(sizeof(uint32_t) * (size_t)r.nq));
+        }
         ReqDesc &d = s->h_desc[slot];
         std::memset(&d, 0, sizeof(d));
         d.algo = r.params.algo;
@@ -620,20 +590,29 @@ hipError_t admit(trw_server_s *s, std::deque<Pending> &incoming, int half) {
         d.stride = stride;
         d.nq = r.nq;
         desc_touch(s, slot);
-        const unsigned long long first_chunk = s->tail;
-        for (uint32_t b = 0; b < r.nq; b += kChunkQueries) {
-            Chunk &c = s->h_ring[s->tail % s->ring];
-            c.req = slot; c.begin = b; c.end = std::min<uint32_t>(r.nq, b + kChunkQueries); c.pad = 0;
-            s->tail++;
-        }
+        new_chunks += chunks;
         Active a;
         a.id = p.id; a.req = r; a.t_submit = p.t_submit; a.t_admit = now_ns();
         a.pool_off = off; a.pool_bytes = p.bytes; a.slot = slot; a.stride = stride;
-        a.first_chunk = first_chunk;
+        a.first_chunk = 0;                  // set below, when the chunks are placed
         a.done_base = s->slot_done[slot];   // the counter is not reset between requests
         a.out_off = src_bytes;
         s->active.push_back(a);
         incoming.pop_front();
+    }
+    // Place the new requests' chunks in [tail0, tail0 + new_chunks), kind by kind.
+    std::vector<size_t> order(s->active.size() - first_new);
+    for (size_t i = 0; i < order.size(); ++i) order[i] = first_new + i;
+    auto kind = [&](size_t i) { return s->active[i].req.params.algo * 16u + s->active[i].req.params.sampler; };
+    std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return kind(x) < kind(y); });
+    for (size_t i : order) {
+        Active &a = s->active[i];
+        a.first_chunk = s->tail;
+        for (uint32_t b = 0; b < a.req.nq; b += kChunkQueries) {
+            Chunk &c = s->h_ring[s->tail % s->ring];
+            c.req = a.slot; c.begin = b; c.end = std::min<uint32_t>(a.req.nq, b + kChunkQueries); c.pad = 0;
+            s->tail++;
+        }
     }
     if (s->desc_hi > s->desc_lo) {            // the changed range of the descriptor table only
         e = hipMemcpyAsync(s->dev.reqs + s->desc_lo, s->h_desc + s->desc_lo, sizeof(ReqDesc) * (s->desc_hi - s->desc_lo),
@@ -665,10 +644,9 @@ void output_jobs(const trw_server_s *s, const Active &a, CopyJob *jobs) {
     const char *lengths = paths + align_up(sizeof(int32_t) * a.stride * r.nq);
     const char *status = lengths + align_up(sizeof(uint32_t) * (size_t)r.nq);
     jobs[0] = CopyJob{paths, reinterpret_cast<char *>(r.paths), sizeof(int32_t) * a.stride,
-                      sizeof(int32_t) * r.path_stride, sizeof(int32_t) * ((size_t)r.params.max_len + 1), r.nq, 0, 0};
-    jobs[1] = CopyJob{lengths, reinterpret_cast<char *>(r.lengths), 0, 0, sizeof(uint32_t) * (size_t)r.nq, 1, 0, 0};
-    jobs[2] = CopyJob{status, reinterpret_cast<char *>(r.status), 0, 0, (size_t)r.nq, 1, 0, 0};
-    for (int k = 0; k < 3; ++k) jobs[k].seg_per_row = (jobs[k].width + 15) / 16;
+                      sizeof(int32_t) * r.path_stride, sizeof(int32_t) * ((size_t)r.params.max_len + 1), r.nq};
+    jobs[1] = CopyJob{lengths, reinterpret_cast<char *>(r.lengths), 0, 0, sizeof(uint32_t) * (size_t)r.nq, 1};
+    jobs[2] = CopyJob{status, reinterpret_cast<char *>(r.status), 0, 0, (size_t)r.nq, 1};
 }
 
 void server_loop(trw_server_s *s) {
@@ -756,16 +734,12 @@ void server_loop(trw_server_s *s) {
                 s->stats.moves = mv;
                 s->stats.tick_device_ns += (uint64_t)(ms * 1e6);
             }
-            // Requests that finished by that tick: their outputs are copied out
-            // (device destinations in one launch, host ones by copies), pipelined:
+            // Requests that finished by that tick.  Device outputs were written in
+            // place by the ticks; host outputs are copied out of the pool, pipelined:
             // on the delivery stream while the next tick runs (it touches none of
             // them); serial: on the tick stream, ahead of the next tick.
             Batch batch;
-            batch.jobs_buf = (int)(s->n_batches % kJobBufs);
             batch.seq = s->n_batches;
-            CopyJob *jobs_half = s->h_jobs + (size_t)batch.jobs_buf * 3 * s->max_reqs;
-            uint32_t njobs = 0;
-            uint64_t total_segs = 0;
             bool any_copy = false;
             for (size_t i = 0; i < s->active.size() && e == hipSuccess; ++i) {
                 Active &a = s->active[i];
@@ -773,36 +747,13 @@ void server_loop(trw_server_s *s) {
                 a.finishing = true;
                 a.batch_seq = batch.seq;
                 batch.ids.push_back(a.id);
-                if (a.cancelled) continue;
+                if (a.cancelled || !(a.req.flags & TRW_REQ_HOST)) continue;
                 CopyJob jobs[3];
                 output_jobs(s, a, jobs);
-                if (a.req.flags & TRW_REQ_HOST) {
-                    e = hipMemcpy2DAsync(jobs[0].dst, jobs[0].dst_pitch, jobs[0].src, jobs[0].src_pitch, jobs[0].width,
-                                         jobs[0].rows, hipMemcpyDeviceToHost, out_stream);
-                    for (int k = 1; k < 3 && e == hipSuccess; ++k)
-                        e = hipMemcpyAsync(jobs[k].dst, jobs[k].src, jobs[k].width, hipMemcpyDeviceToHost,
-                                           out_stream);
-                    any_copy = true;
-                } else {
-                    for (int k = 0; k < 3; ++k) {
-                        jobs[k].seg_start = total_segs;
-                        total_segs += jobs[k].rows * jobs[k].seg_per_row;
-                        jobs_half[njobs++] = jobs[k];
-                    }
-                }
-            }
-            if (e == hipSuccess && njobs) {
-                // the previous batch on this stream used the device job table; stream order keeps them apart
-                // (serial mode: the copy and the delivery run before the next tick, on the tick stream)
-                CopyJob *d_jobs = reinterpret_cast<CopyJob *>(s->arena + s->lay.jobs);
-                e = hipMemcpyAsync(d_jobs, jobs_half, sizeof(CopyJob) * njobs, hipMemcpyHostToDevice, out_stream);
-                if (e == hipSuccess) {
-                    const uint64_t per_block = 256 * (uint64_t)kDeliverSegs;
-                    const uint64_t blocks = (total_segs + per_block - 1) / per_block;
-                    hipLaunchKernelGGL(k_deliver, dim3((uint32_t)blocks), dim3(256), 0, out_stream, d_jobs, njobs,
-                                       total_segs);
-                    e = hipGetLastError();
-                }
+                e = hipMemcpy2DAsync(jobs[0].dst, jobs[0].dst_pitch, jobs[0].src, jobs[0].src_pitch, jobs[0].width,
+                                     jobs[0].rows, hipMemcpyDeviceToHost, out_stream);
+                for (int k = 1; k < 3 && e == hipSuccess; ++k)
+                    e = hipMemcpyAsync(jobs[k].dst, jobs[k].src, jobs[k].width, hipMemcpyDeviceToHost, out_stream);
                 any_copy = true;
             }
             if (e == hipSuccess && !batch.ids.empty()) {
@@ -819,13 +770,11 @@ void server_loop(trw_server_s *s) {
                 s->batches.push_back(std::move(batch));
             }
         }
-        // Release the requests of delivered batches (in order); a job-table half
-        // is reused two batches later, so wait for that batch if it still runs.
+        // Complete the batches whose copies have ended, in order.
         while (e == hipSuccess && !s->batches.empty()) {
             Batch &b = s->batches.front();
-            const bool must_wait = s->batches.size() >= (size_t)kJobBufs;
             if (b.done) {
-                hipError_t q = must_wait ? hipEventSynchronize(b.done) : hipEventQuery(b.done);
+                hipError_t q = hipEventQuery(b.done);
                 if (q == hipErrorNotReady) break;
                 if (q != hipSuccess) { e = q; break; }
                 s->spare_events.push_back(b.done);

@@ -223,6 +223,16 @@ __device__ __forceinline__ int32_t alias_pick(const uint4 &e0, const uint4 &e1, 
     return (int32_t)(first ? e0.y : e0.z);                  // -1 marks a row of zero weight
 }
 
+// The same address as a pointer into global memory.  A pointer read from
+// memory (a request's output row, say) is generic, and generic (flat)
+// accesses count in both wait counters: a later wait for an LDS exchange or a
+// scalar load would then also wait for those stores to reach memory.  Global
+// accesses count in the vector-memory counter only.
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *global_ptr(T *p) {
+    return (__attribute__((address_space(1))) T *)p;
+}
+
 // ---------------------------------------------------------------------------
 // Path writer: up to 4 pending entries per walker, flushed as one 16-byte
 // store when they end on a 16-byte boundary, else entry by entry at the end.

@@ -86,17 +86,20 @@ __device__ __forceinline__ bool in_row(const int32_t *__restrict__ col, int32_t 
     return false;
 }
 
-template <bool ADJ>
+// FIRST: the caller has already read the first dart's adjacency record
+// (slot off + scale32(r.r0, d)) and passes it as `first`.
+template <bool ADJ, bool FIRST = false>
 __device__ __forceinline__ int32_t n2v_move(const GraphDev &g, const TableDev &t, const WalkDev &a, uint64_t qid,
                                             uint32_t k, int32_t off, uint32_t d, const Rand4 &r, int32_t prev,
-                                            int32_t poff, int32_t pd, int32_t &noff, int32_t &ndeg) {
+                                            int32_t poff, int32_t pd, int32_t &noff, int32_t &ndeg,
+                                            const uint4 &first = uint4{}) {
     Rand4 rr = r;
     for (uint32_t dart = 0;; ++dart) {
         if (dart > 0) rr = philox(k, dart, qid, a.seed);
         const uint32_t slot = (uint32_t)off + scale32(rr.r0, d);
         int32_t x, xo = 0, xd = 0;
         if (ADJ) {
-            const uint4 e = t.adj[slot];
+            const uint4 e = (FIRST && dart == 0) ? first : t.adj[slot];
             x = (int32_t)e.x; xo = (int32_t)e.y; xd = (int32_t)e.z;
         } else {
             x = g.col[slot];

@@ -169,15 +169,17 @@ def test_cancel_leaves_others_intact(env, pipelined):
 
 
 def test_memory_admission(env):
+    """Requests with host buffers are staged in the pool: one that can never fit
+    is refused, and ones that fit only one at a time are admitted in turn."""
     g = env["g"]
     p = params("deepwalk", "alias", 80, 1)
     srv = make_server(env, pool_bytes=4 << 20)
     with pytest.raises(trw.TrwError) as ei:
-        srv.submit(p, synth.sources(20000, g.n, 1))           # 20000 * 88 * 4 bytes > 4 MiB
+        srv.submit(p, synth.sources(20000, g.n, 1), host=True)   # 20000 * (88 * 4 + 9) bytes > 4 MiB
     assert ei.value.status == trw.TRW_E_NOMEM_BUDGET
     # each fits alone but no two fit together: admitted one after another
     reqs = [synth.sources(7000, g.n, 10 + i) for i in range(4)]
-    ids = [srv.submit(p, s, qid_base=i << 20) for i, s in enumerate(reqs)]
+    ids = [srv.submit(p, s, qid_base=i << 20, host=True) for i, s in enumerate(reqs)]
     got = wait_all(srv, ids)
     for i, (s, rid) in enumerate(zip(reqs, ids)):
         P, L, S = trw.walk(env["G"], env["alias"], p, torch.from_numpy(s).cuda(), qid_base=i << 20)
@@ -187,6 +189,27 @@ def test_memory_admission(env):
     admits = sorted(got[r]["t_admit_ns"] for r in ids)
     dones = sorted(got[r]["t_done_ns"] for r in ids)
     assert all(admits[i + 1] >= dones[i] - 10 ** 9 for i in range(3))
+    srv.close()
+
+
+def test_device_buffers_in_place(env):
+    """Requests with device buffers take no pool space: written in place, they
+    run together even when their outputs together are far larger than the pool,
+    and give the same results as the batch walker."""
+    g = env["g"]
+    srv = make_server(env, pool_bytes=4 << 20)
+    kinds = [("deepwalk", "alias", 80), ("ppr", "alias", 256), ("node2vec", "orej", 80)]
+    reqs = [(kinds[i % 3], synth.sources(20000, g.n, 40 + i)) for i in range(6)]
+    ids = [srv.submit(params(a, s, m, 5 + i), src, qid_base=i << 24)
+           for i, ((a, s, m), src) in enumerate(reqs)]
+    assert srv.stats()["pool_bytes_used"] == 0
+    got = wait_all(srv, ids)
+    for i, (((a, s, m), src), rid) in enumerate(zip(reqs, ids)):
+        assert got[rid]["status"] == 0
+        table = env["alias"] if s == "alias" else env["eidx"]
+        P, L, S = trw.walk(env["G"], table, params(a, s, m, 5 + i), torch.from_numpy(src).cuda(), qid_base=i << 24)
+        torch.cuda.synchronize()
+        same(to_np(got[rid]), (P.cpu().numpy(), L.cpu().numpy().view(np.uint32), S.cpu().numpy()), m)
     srv.close()
 
 
