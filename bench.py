@@ -136,8 +136,8 @@ def main():
     ap.add_argument("--serve-replay", type=int, default=2000, help="requests per step: one block of the timed backlog, and one warm-up burst")
     ap.add_argument("--serve-requests", type=int, default=10000, help="measured requests of the latency phase")
     ap.add_argument("--serve-scale", type=int, default=0, help="override the served graph's scale (tests)")
-    ap.add_argument("--serve-slots-per-cu", type=int, default=2048)
-    ap.add_argument("--serve-steps", type=int, default=32, help="moves per walker slot per tick")
+    ap.add_argument("--serve-slots-per-cu", type=int, default=4096)
+    ap.add_argument("--serve-steps", type=int, default=64, help="moves per walker slot per tick")
     ap.add_argument("--serve-pipelined", type=int, default=1, help="0: serial ticks (read each tick before queueing the next)")
     ap.add_argument("--serve-max-requests", type=int, default=4096, help="requests the server holds admitted at once")
     ap.add_argument("--serve-rate", type=float, default=0.0, help="offered requests/s (0: 0.7x the saturated rate)")

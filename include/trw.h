@@ -404,6 +404,15 @@ typedef struct {
  * are valid until it returns.  Nonzero return: stop the stream. */
 typedef int (*trw_chunk_fn)(void *user, const trw_chunk *chunk);
 
+/* A trw_chunk_fn that appends each chunk to a file (the paper's dump of the
+ * output to disk while the engine fills the other buffer: Other
+ * Implementation Details, input and output).  user: pointer to an open file
+ * descriptor (int).  Record per chunk, native byte order: {qid_base u64,
+ * nq u32, 0 u32}, lengths u32[nq], status u8[nq] zero-padded to a multiple of
+ * 8 bytes, offsets u64[nq + 1], entries i32[offsets[nq]].  Returns nonzero
+ * (stopping the stream) when a write fails. */
+int trw_chunk_to_fd(void *user, const trw_chunk *chunk);
+
 /* Device workspace and pinned host bytes trw_walk_stream needs for chunks of
  * chunk_queries queries (two chunk sets each, plus the walk's workspace). */
 trw_status trw_walk_stream_bytes(trw_graph g, const trw_walk_params *p, uint32_t chunk_queries,

@@ -7,6 +7,7 @@ The binding marshals arguments and raises TrwError on any failing call.
 from __future__ import annotations
 
 import ctypes
+import os
 from typing import Optional, Sequence
 
 import numpy as np
@@ -373,6 +374,15 @@ def _aligned(nbytes: int, device=None, pin: bool = False):
     return t, t[off:off + nbytes]
 
 
+def _stream_buffers(graph: Graph, p: trw_walk_params, chunk_queries: int):
+    dbytes, hbytes = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    check(_abi.trw_walk_stream_bytes(graph.handle, ctypes.byref(p), chunk_queries, ctypes.byref(dbytes),
+                                     ctypes.byref(hbytes)))
+    d_keep, d_ws = _aligned(int(dbytes.value), device=graph.device)
+    h_keep, h_buf = _aligned(int(hbytes.value), pin=True)
+    return d_keep, d_ws, h_keep, h_buf
+
+
 def walk_stream(graph: Graph, table: Optional[Table], p: trw_walk_params, sources: torch.Tensor, chunk_queries: int,
                 fn, qid_base: int = 0, tuning: Optional[trw_tuning] = None, stream=None) -> int:
     """Streamed walk (trw_walk_stream): the batch runs chunk_queries at a time and fn(chunk) is
@@ -381,11 +391,7 @@ def walk_stream(graph: Graph, table: Optional[Table], p: trw_walk_params, source
     packed paths: query i's path is entries[offsets[i]:offsets[i + 1]]).  fn returning True stops
     the stream (TrwError TRW_E_CANCELLED).  Returns the number of chunks delivered."""
     nq = int(sources.numel())
-    dbytes, hbytes = ctypes.c_size_t(0), ctypes.c_size_t(0)
-    check(_abi.trw_walk_stream_bytes(graph.handle, ctypes.byref(p), chunk_queries, ctypes.byref(dbytes),
-                                     ctypes.byref(hbytes)))
-    d_keep, d_ws = _aligned(int(dbytes.value), device=graph.device)
-    h_keep, h_buf = _aligned(int(hbytes.value), pin=True)
+    d_keep, d_ws, h_keep, h_buf = _stream_buffers(graph, p, chunk_queries)
     delivered = [0]
     err = []
 
@@ -419,6 +425,51 @@ def walk_stream(graph: Graph, table: Optional[Table], p: trw_walk_params, source
         raise err[0]
     check(st)
     return delivered[0]
+
+
+def walk_stream_to_file(graph: Graph, table: Optional[Table], p: trw_walk_params, sources: torch.Tensor,
+                        chunk_queries: int, path: str, qid_base: int = 0, tuning: Optional[trw_tuning] = None,
+                        stream=None) -> int:
+    """Streamed walk whose chunks the library itself appends to the file at `path`
+    (trw_chunk_to_fd: the disk write of one chunk overlaps the walk of the next).  The file is
+    created or truncated; read it back with read_stream_file.  Returns the bytes written."""
+    nq = int(sources.numel())
+    d_keep, d_ws, h_keep, h_buf = _stream_buffers(graph, p, chunk_queries)
+    fd = os.open(path, os.O_WRONLY | os.O_CREAT | os.O_TRUNC, 0o644)
+    try:
+        fd_box = ctypes.c_int(fd)
+        st = _abi.trw_walk_stream(graph.handle, table.handle if table is not None else None, ctypes.byref(p),
+                                  _dptr(sources), nq, qid_base, chunk_queries,
+                                  ctypes.byref(tuning) if tuning is not None else None, _dptr(d_ws), d_ws.numel(),
+                                  ctypes.c_void_p(h_buf.data_ptr()), h_buf.numel(), _abi.TRW_CHUNK_TO_FD,
+                                  ctypes.byref(fd_box), _stream_ptr(stream))
+    finally:
+        os.close(fd)
+    del d_keep, h_keep
+    check(st)
+    return os.path.getsize(path)
+
+
+def read_stream_file(path: str):
+    """The chunks of a file written by walk_stream_to_file, in order, as the dicts walk_stream
+    hands to its function."""
+    data = np.fromfile(path, dtype=np.uint8)
+    pos = 0
+    while pos < data.size:
+        qid_base = int(data[pos:pos + 8].view(np.uint64)[0])
+        n = int(data[pos + 8:pos + 12].view(np.uint32)[0])
+        pos += 16
+        lengths = data[pos:pos + 4 * n].view(np.uint32).copy()
+        pos += 4 * n
+        status = data[pos:pos + n].copy()
+        pos += n + (8 - n % 8) % 8
+        offs = data[pos:pos + 8 * (n + 1)].view(np.uint64).copy()
+        pos += 8 * (n + 1)
+        total = int(offs[n])
+        entries = data[pos:pos + 4 * total].view(np.int32).copy()
+        pos += 4 * total
+        yield {"qid_base": qid_base, "nq": n, "lengths": lengths, "status": status, "offsets": offs,
+               "entries": entries}
 
 
 def topk(counts: torch.Tensor, k: int, stream=None):

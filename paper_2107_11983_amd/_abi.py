@@ -148,6 +148,7 @@ _SIGS = {
                                     ctypes.POINTER(_sz)]),
     "trw_walk_stream": (_st, [_P, _P, ctypes.POINTER(trw_walk_params), _P, _u64, _u64, _u32,
                               ctypes.POINTER(trw_tuning), _P, _sz, _P, _sz, TRW_CHUNK_FN, _P, _P]),
+    "trw_chunk_to_fd": (ctypes.c_int, [_P, ctypes.POINTER(trw_chunk)]),
     "trw_ppr_walk_counts": (_st, [_P, _P, ctypes.POINTER(trw_walk_params), _P, _u64, _u64, _u64, _P, _u64, _P, _P,
                                   ctypes.POINTER(trw_tuning), _P, _sz, _P]),
     "trw_topk": (_st, [_P, _u64, _u32, _P, _P, _P, _sz, _P]),
@@ -213,6 +214,8 @@ trw_topk = lib.trw_topk
 trw_ppr_walk_counts = lib.trw_ppr_walk_counts
 trw_walk_stream_bytes = lib.trw_walk_stream_bytes
 trw_walk_stream = lib.trw_walk_stream
+trw_chunk_to_fd = lib.trw_chunk_to_fd
+TRW_CHUNK_TO_FD = TRW_CHUNK_FN(("trw_chunk_to_fd", lib))   # the library's file sink as a chunk function
 trw_edge_index_bytes = lib.trw_edge_index_bytes
 trw_edge_index_build = lib.trw_edge_index_build
 trw_probe_fill = lib.trw_probe_fill

@@ -145,7 +145,11 @@ __device__ __forceinline__ int32_t program_move(const P &prog, const Args &a, co
     } else if constexpr (P::kind == STATIC_ALIAS) {
         const uint64_t e = (uint64_t)(w.off + scale32(r.r0, w.deg));
         int32_t o, d;
-        nxt = alias_pick(a.alias[2 * e], a.alias[2 * e + 1], r.r1, o, d);
+        // the whole 32-byte entry in one read, then the pick (picking from the
+        // loads lets the compiler read the threshold first, then the half)
+        const uint4 e0 = a.alias[2 * e], e1 = a.alias[2 * e + 1];
+        asm volatile("" ::"v"(e0.x), "v"(e0.y), "v"(e0.z), "v"(e1.x), "v"(e1.y), "v"(e1.z), "v"(e1.w));
+        nxt = alias_pick(e0, e1, r.r1, o, d);
         if (nxt >= 0) { noff = o; ndeg = (uint32_t)d; }
         return nxt;
     } else if constexpr (P::kind == STATIC_ITS) {

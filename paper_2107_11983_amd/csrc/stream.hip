@@ -7,6 +7,9 @@
 // chunk buffers, so chunk i+1 walks while chunk i is packed and copied.
 #include <hip/hip_runtime.h>
 
+#include <errno.h>
+#include <unistd.h>
+
 #include <algorithm>
 #include <cstring>
 #include <string>
@@ -286,6 +289,40 @@ trw_status trw_walk_stream(trw_graph g, trw_table table, const trw_walk_params *
     (void)hipStreamSynchronize(copy_s);
     cleanup();
     return result;
+}
+
+// One chunk appended to the file descriptor *(int *)user as a record:
+// header {qid_base u64, nq u32, reserved u32}, lengths u32[nq], status u8[nq]
+// padded with zeros to a multiple of 8 bytes, offsets u64[nq + 1], entries
+// i32[offsets[nq]].  Runs on the stream's calling thread while the next chunk
+// walks, so the disk write overlaps the walk (the engine's double buffering).
+int trw_chunk_to_fd(void *user, const trw_chunk *c) {
+    if (!user || !c) return 1;
+    const int fd = *static_cast<const int *>(user);
+    auto put = [fd](const void *data, size_t bytes) -> bool {
+        const char *q = static_cast<const char *>(data);
+        while (bytes > 0) {
+            const ssize_t w = ::write(fd, q, bytes);
+            if (w < 0 && errno == EINTR) continue;
+            if (w <= 0) return false;
+            q += w;
+            bytes -= (size_t)w;
+        }
+        return true;
+    };
+    struct {
+        uint64_t qid_base;
+        uint32_t nq, reserved;
+    } head{c->qid_base, c->nq, 0};
+    static const uint8_t zeros[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const size_t pad = (8 - c->nq % 8) % 8;
+    const uint64_t n_entries = c->offsets[c->nq];
+    return put(&head, sizeof(head)) && put(c->lengths, sizeof(uint32_t) * (size_t)c->nq) &&
+                   put(c->status, (size_t)c->nq) && put(zeros, pad) &&
+                   put(c->offsets, sizeof(uint64_t) * ((size_t)c->nq + 1)) &&
+                   put(c->entries, sizeof(int32_t) * (size_t)n_entries)
+               ? 0
+               : 1;
 }
 
 }  // extern "C"

@@ -770,7 +770,12 @@ __global__ void __launch_bounds__(256) k_bsp_step(GraphDev g, TableDev t, WalkDe
                 } else if (rc.b != 0) {
                     const uint32_t e = (uint32_t)rc.a + scale32(r.r0, (uint32_t)rc.b);
                     if (kAlias) {
-                        nxt = alias_pick(t.alias[2 * (uint64_t)e], t.alias[2 * (uint64_t)e + 1], r.r1, noff, ndeg);
+                        // the whole 32-byte entry in one read, then the pick (picking from
+                        // the loads lets the compiler read the threshold, then the half)
+                        const uint4 e0 = t.alias[2 * (uint64_t)e], e1 = t.alias[2 * (uint64_t)e + 1];
+                        asm volatile("" ::"v"(e0.x), "v"(e0.y), "v"(e0.z), "v"(e1.x), "v"(e1.y), "v"(e1.z),
+                                     "v"(e1.w));
+                        nxt = alias_pick(e0, e1, r.r1, noff, ndeg);
                     } else {
                         const uint4 rec = t.adj[e];
                         nxt = (int32_t)rec.x; noff = (int32_t)rec.y; ndeg = (int32_t)rec.z;

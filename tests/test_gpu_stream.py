@@ -113,3 +113,26 @@ def test_stream_stop_and_empty(graphs):
     assert ei.value.status == trw._abi.TRW_E_CANCELLED and seen == [0, 1000]
     assert trw.walk_stream(G, None, p, src[:0], 1000, seen.append) == 0
     G.close()
+
+
+@pytest.mark.parametrize("chunk", [4097, 1 << 20])
+def test_stream_to_disk(graphs, chunk, tmp_path):
+    """The library's own file sink (trw_chunk_to_fd): the chunks written to disk
+    while the next chunk walks, read back, hold exactly the oracle's walks."""
+    g, _ = graphs
+    G = trw.Graph(g.row_ptr, g.col, g.weight)
+    alias = G.table("alias")
+    src = np.concatenate([synth.sources(20011, g.n, 6), np.array([-3], np.int32)])
+    stop = oracle.stop_q32(0.2)
+    p = trw.make_params("ppr", "alias", 256, 19, stop_q32=stop)
+    path = str(tmp_path / "walks.bin")
+    log(f"  stream to disk chunk={chunk} nq={len(src)}")
+    nbytes = trw.walk_stream_to_file(G, alias, p, torch.from_numpy(src).cuda(), chunk, path, qid_base=5)
+    chunks = list(trw.read_stream_file(path))
+    assert nbytes == sum(16 + 4 * c["nq"] + c["nq"] + (8 - c["nq"] % 8) % 8 + 8 * (c["nq"] + 1)
+                         + 4 * len(c["entries"]) for c in chunks)
+    thr, al = oracle.alias_build(g.row_ptr, g.weight)
+    ref = oracle.walk(g.row_ptr, g.col, oracle.WalkParams(oracle.PPR, oracle.ALIAS, 256, 19, stop_q32=stop), src,
+                      qid_base=5, thr=thr, alias=al)
+    _check(chunks, ref, src, chunk, 5)
+    G.close()
