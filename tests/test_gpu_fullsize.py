@@ -280,8 +280,8 @@ def test_served_rmat26_saturated_replay_every_query():
         r.lengths = ctypes.c_void_p(d_len.data_ptr() + 4 * int(offs[i]))
         r.status = ctypes.c_void_p(d_st.data_ptr() + int(offs[i]))
     torch.cuda.synchronize()
-    slots = torch.cuda.get_device_properties(0).multi_processor_count * 2048
-    srv = trw.Server(G, alias, eidx, pool_bytes=8 << 30, max_slots=slots, max_requests=1024, steps_per_tick=16)
+    slots = torch.cuda.get_device_properties(0).multi_processor_count * 4096
+    srv = trw.Server(G, alias, eidx, pool_bytes=8 << 30, max_slots=slots, max_requests=4096, steps_per_tick=64)
     comp = (_abi.trw_completion * R)()
     arr = (ctypes.c_uint64 * R)()
     t0 = time.time()
