@@ -565,9 +565,10 @@ typedef struct {
     uint32_t steps_per_tick;   /* moves per slot per tick; 0 = 16 */
     uint32_t use_hipgraph;     /* 1: replay the tick as a captured HIP graph */
     uint32_t serial_ticks;     /* 0 (default): the next tick is queued before the host reads the
-                                  last one, whose finished requests are delivered on a second
-                                  stream while the next tick runs.  1: each tick is read as it
-                                  ends and its outputs delivered before the next one is queued */
+                                  last one, whose finished requests complete (host outputs copied
+                                  on a second stream) while the next tick runs.  1: each tick is
+                                  read as it ends and its requests completed before the next one
+                                  is queued */
     uint32_t ring_chunks;      /* entries of the device queue of 64-query chunks, 16..2^24;
                                   0 = 2^20.  A request holds at most 32 * ring_chunks - 1 queries;
                                   admission waits while the chunks the device may still read and
@@ -597,7 +598,7 @@ typedef struct {
     int32_t status;            /* TRW_OK or TRW_E_CANCELLED */
     uint32_t nq;
     void *user;
-    uint64_t t_submit_ns;      /* host steady clock: submit, admission, outputs delivered */
+    uint64_t t_submit_ns;      /* host steady clock: submit, admission, outputs complete */
     uint64_t t_admit_ns;
     uint64_t t_done_ns;
 } trw_completion;
