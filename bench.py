@@ -80,6 +80,16 @@ def read_traffic(tag, files):
         return None, None
 
 
+def gather_by_lines(roofline, measured, launch_ms, gather):
+    """Every read request reaching HBM is a 128-byte line on gfx950: the counters' read bytes per
+    launch / 128 over the launch time, against the measured random-gather ceiling."""
+    if measured.get("read") is None or measured["read"] != measured["read"]:
+        return
+    lines_s = measured["read"] / 128 / (launch_ms * 1e-3)
+    roofline["read_lines_per_s"] = round(lines_s, 1)
+    roofline["frac_of_dependent_gather_ceiling_by_lines"] = round(lines_s / gather["dependent_best_reads_per_s"], 4)
+
+
 def host_info():
     """CPU model and thread counts of this host (recorded with every oracle figure)."""
     model = "unknown"
@@ -325,6 +335,8 @@ def bench_batch(args, wl, ctx, nested=False):
         if traffic is not None:
             roofline["traffic_frac_of_peak"] = round(traffic / (avg_launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)
             roofline["l2_hit_rate"] = measured.get("l2_hit_rate")
+            if gather:
+                gather_by_lines(roofline, measured, avg_launch_ms, gather)
 
     # Autotuned launch (the paper's pre-execution tuning): candidates timed on a
     # sample of the batch, then the whole batch timed with the winner.
@@ -583,6 +595,8 @@ def bench_batch(args, wl, ctx, nested=False):
         if traffic is not None:
             roofline["traffic_frac_of_peak"] = round(traffic / (avg_launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)
             roofline["l2_hit_rate"] = measured.get("l2_hit_rate")
+            if gather:
+                gather_by_lines(roofline, measured, avg_launch_ms, gather)
         if wl.algo == "metapath" and sampler == "its+index":
             # one fused entry per move, plus the source's label offsets per query
             roofline["issued_random_reads_per_launch"] = moves + valid_q
@@ -900,6 +914,8 @@ def bench_served(args, wl, ctx):
                                                      HBM_PEAK_GBPS, 4)
             roofline["l2_hit_rate"] = measured.get("l2_hit_rate")
             roofline["traffic_method"] = measured.get("method")
+            if ctx.gather:
+                gather_by_lines(roofline, measured, tick_ns / ticks * 1e-6, ctx.gather)
         if ctx.gather:
             # one random read per ALIAS move (the fused 32-byte entry), per Node2Vec dart (its
             # 16-byte adjacency record) and per query (the source's row range); the edge-set
