@@ -28,7 +28,7 @@
  *   - PPR's estimate from the end vertices of a source's queries, and the
  *     k highest-scoring vertices [Random Walk based Algorithms, PPR].
  *
- * The paper uses real-valued uniforms; this build fixes one integer random
+ * The paper uses real-valued uniforms; the oracle fixes one integer random
  * contract so that a second implementation can be compared bit for bit:
  *   block(k, t) = Philox4x32-10(counter = (k, t, qid_lo, qid_hi),
  *                               key = (seed_lo, seed_hi))  -> words r0..r3
