@@ -39,7 +39,7 @@ SERVE_SOURCES = [CSRC + f for f in ("serve_kernel.hip", "serve_internal.hpp", "w
                                     "trw_internal.hpp")]
 BATCH_WORKLOADS = ("deepwalk-rmat12", "ppr-rmat22", "node2vec-rmat24", "metapath-rmat24")
 SERVED_WORKLOAD = "served-rmat26"
-BOX_CPU_SHARE = 16     # host threads the oracle's parallel baseline may use
+HOST_CPU_SHARE = 16    # host threads the oracle's parallel baseline may use
 
 # Algorithmic bytes: per move the row range
 # (two int32 row offsets) 8 B, the sampling entry the move needs and the path
@@ -1072,7 +1072,7 @@ def cpu_baseline(g, wl, sampler, src_np, kw, target_s):
     # The same sample sharded by query range over the host's cores (the
     # oracle unchanged; ctypes releases the interpreter lock during each call).
     import concurrent.futures
-    workers = max(1, min(BOX_CPU_SHARE, info["nproc"] or 1))
+    workers = max(1, min(HOST_CPU_SHARE, info["nproc"] or 1))
     shard = max(1, min(-(-nsamp // workers), piece))
     ranges = [(lo, min(nsamp, lo + shard)) for lo in range(0, nsamp, shard)]
 
@@ -1137,7 +1137,7 @@ def cpu_baseline_served(g, wl, ctx, replay, sizes, kinds, offs, src_np, stop_q32
                         f"in submission order, one thread, ALIAS table prebuilt ({dt:.1f} s)",
               "oracle_counters": counters, **info}
     import concurrent.futures
-    workers = max(1, min(BOX_CPU_SHARE, info["nproc"] or 1))
+    workers = max(1, min(HOST_CPU_SHARE, info["nproc"] or 1))
     t = time.perf_counter()
     with concurrent.futures.ThreadPoolExecutor(max_workers=workers) as ex:
         pmoves = sum(mv for _, mv, _ in ex.map(run, done))
