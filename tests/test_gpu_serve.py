@@ -213,6 +213,32 @@ def test_device_buffers_in_place(env):
     srv.close()
 
 
+@pytest.mark.parametrize("stride", [81, 83, 97])
+def test_in_place_rows_of_any_stride(env, stride):
+    """Device rows written in place at a stride that is not a multiple of 4 entries (rows
+    start at every 4-byte alignment, so the writer mixes single entries and 16-byte blocks):
+    the entries up to each path's end equal the batch walker's."""
+    g = env["g"]
+    srv = make_server(env)
+    kinds = [("deepwalk", "alias", 80), ("node2vec", "orej", 80), ("ppr", "alias", 64)]
+    ids, reqs = [], []
+    for i, (a, s, m) in enumerate(kinds):
+        src = synth.sources(3001, g.n, 70 + i)
+        p = params(a, s, m, 9 + i)
+        rid = srv.submit(p, src, qid_base=i << 20, stride=stride)
+        ids.append(rid)
+        reqs.append((a, s, m, src, p, rid))
+    got = wait_all(srv, ids)
+    for i, (a, s, m, src, p, rid) in enumerate(reqs):
+        P, L, S = to_np(got[rid])
+        assert P.shape[1] == stride
+        table = env["alias"] if s == "alias" else env["eidx"]
+        Pr, Lr, Sr = trw.walk(env["G"], table, p, torch.from_numpy(src).cuda(), qid_base=i << 20)
+        torch.cuda.synchronize()
+        same((P, L, S), (Pr.cpu().numpy(), Lr.cpu().numpy().view(np.uint32), Sr.cpu().numpy()), m)
+    srv.close()
+
+
 def test_host_buffers_and_bad_sources(env):
     g = env["g"]
     srv = make_server(env)
