@@ -239,6 +239,38 @@ def test_in_place_rows_of_any_stride(env, stride):
     srv.close()
 
 
+def test_extreme_requests(env):
+    """One query, max_len 1, and requests larger than every other in flight, of each kind,
+    submitted together with bad sources at both ends: each equals the batch walker and the
+    oracle's termination rules."""
+    g = env["g"]
+    srv = make_server(env, steps_per_tick=7)      # a tick length that divides no walk evenly
+    cases = []
+    for i, (a, s, m) in enumerate([("deepwalk", "alias", 1), ("ppr", "alias", 1), ("node2vec", "orej", 1),
+                                   ("deepwalk", "alias", 80), ("ppr", "alias", 256), ("node2vec", "orej", 80)]):
+        n = 1 if i < 3 else 70001
+        src = synth.sources(n, g.n, 90 + i)
+        if n > 2:
+            src[0], src[-1] = -1, g.n                 # bad sources at both ends of the request
+        cases.append((a, s, m, src, params(a, s, m, 31 + i), i << 24))
+    ids = [srv.submit(p, src, qid_base=qb) for a, s, m, src, p, qb in cases]
+    got = wait_all(srv, ids)
+    for (a, s, m, src, p, qb), rid in zip(cases, ids):
+        assert got[rid]["status"] == 0
+        table = env["alias"] if s == "alias" else env["eidx"]
+        Pr, Lr, Sr = trw.walk(env["G"], table, p, torch.from_numpy(src).cuda(), qid_base=qb)
+        torch.cuda.synchronize()
+        P, L, S = to_np(got[rid])
+        Sr = Sr.cpu().numpy()
+        assert np.array_equal(L, Lr.cpu().numpy().view(np.uint32)) and np.array_equal(S, Sr)
+        ok = Sr != oracle.ST_BAD_SOURCE
+        mask = (np.arange(m + 1)[None, :] <= L[:, None]) & ok[:, None]
+        assert np.array_equal(P[:, :m + 1][mask], Pr.cpu().numpy()[:, :m + 1][mask])
+        if len(src) > 2:
+            assert S[0] == oracle.ST_BAD_SOURCE and S[-1] == oracle.ST_BAD_SOURCE and L[0] == 0
+    srv.close()
+
+
 def test_host_buffers_and_bad_sources(env):
     g = env["g"]
     srv = make_server(env)
