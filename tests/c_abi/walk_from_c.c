@@ -1,17 +1,25 @@
 /*
  * The C ABI driven from plain C (no Python, no torch): device buffers from
  * hipMalloc, a CSR graph, its ALIAS table, a PPR walk, the end-vertex counts
- * and their top 10.  Test input and output are raw little-endian files in
- * one directory:
+ * and their top 10; the same walk streamed to a file by the library's file
+ * sink; and a server given six requests of three kinds (one with host
+ * buffers).  Test input and output are raw little-endian files in one
+ * directory:
  *   in : meta.txt ("n m nq max_len seed stop_q32"), row_ptr, col, weight, sources
- *   out: lengths, status, paths (nq rows of max_len + 1 int32), counts, top_ids, top_vals
+ *   out: lengths, status, paths (nq rows of max_len + 1 int32), counts, top_ids, top_vals,
+ *        stream.bin (trw_chunk_to_fd records), srv<i>_{paths,lengths,status} for request i
+ *        (sources [i nq / 6, (i + 1) nq / 6), qid_base its first index; kinds PPR ALIAS,
+ *        DeepWalk ALIAS, Node2Vec O-REJ in turn; max_len, 40 and 40; path_stride
+ *        max_len + 1; request 3 with host buffers)
  * Exit status 0 on success; any failing call prints trw_last_error().
  */
 #define __HIP_PLATFORM_AMD__
 #include <hip/hip_runtime_api.h>
+#include <fcntl.h>
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+#include <unistd.h>
 
 #include "trw.h"
 
@@ -144,8 +152,119 @@ int main(int argc, char **argv) {
     write_file("top_ids", h_ids, sizeof(int32_t) * k);
     write_file("top_vals", h_vals, sizeof(uint32_t) * k);
 
+    /* The same walk streamed to disk by the library's file sink. */
+    {
+        const uint32_t chunk = 4097;
+        size_t sdb = 0, shb = 0;
+        TRW(trw_walk_stream_bytes(g, &p, chunk, &sdb, &shb));
+        void *d_sws = dalloc(sdb);
+        void *h_pin = NULL;
+        HIP(hipHostMalloc(&h_pin, shb, hipHostMallocDefault));
+        snprintf(path, sizeof(path), "%s/stream.bin", dir);
+        int fd = open(path, O_WRONLY | O_CREAT | O_TRUNC, 0644);
+        if (fd < 0) return 2;
+        TRW(trw_walk_stream(g, alias, &p, d_src, (uint64_t)nq, 0, chunk, NULL, d_sws, sdb, h_pin, shb,
+                            trw_chunk_to_fd, &fd, NULL));
+        close(fd);
+        HIP(hipHostFree(h_pin));
+        HIP(hipFree(d_sws));
+    }
+
+    /* A server: six requests of three kinds; request 3 with host buffers. */
+    {
+        size_t eb = 0;
+        TRW(trw_edge_index_bytes(g, &eb));
+        void *d_eidx = dalloc(eb);
+        trw_table eidx;
+        TRW(trw_edge_index_build(g, d_eidx, eb, NULL, &eidx));
+        trw_server_cfg cfg;
+        memset(&cfg, 0, sizeof(cfg));
+        cfg.use_hipgraph = 1;
+        size_t ab = 0;
+        TRW(trw_server_arena_bytes(&cfg, (size_t)64 << 20, &ab));
+        void *d_arena = dalloc(ab);
+        trw_server srv;
+        TRW(trw_server_create(g, alias, eidx, &cfg, d_arena, ab, &srv));
+        enum { R = 6 };
+        trw_request req[R];
+        void *outs[R][3];
+        uint64_t ids[R];
+        for (int i = 0; i < R; ++i) {
+            const long long lo = nq * i / R, hi = nq * (i + 1) / R;
+            const int kind = i % 3;
+            trw_request *r = &req[i];
+            memset(r, 0, sizeof(*r));
+            r->params.algo = kind == 0 ? TRW_A_PPR : kind == 1 ? TRW_A_DEEPWALK : TRW_A_NODE2VEC;
+            r->params.sampler = kind == 2 ? TRW_S_OREJ : TRW_S_ALIAS;
+            r->params.max_len = kind == 0 ? max_len : 40;
+            r->params.stop_q32 = kind == 0 ? stop : 0;
+            r->params.n2v_thr_q16[0] = 16384;      /* p = 2, q = 0.5: 1/p, 1, 1/q over their maximum 2 */
+            r->params.n2v_thr_q16[1] = 32768;
+            r->params.n2v_thr_q16[2] = 65536;
+            r->params.seed = seed + (unsigned long long)i;
+            r->nq = (uint32_t)(hi - lo);
+            r->qid_base = (uint64_t)lo;
+            r->path_stride = r->params.max_len + 1;
+            const size_t pb = sizeof(int32_t) * r->nq * r->path_stride, lb = sizeof(uint32_t) * r->nq;
+            if (i == 3) {
+                r->flags = TRW_REQ_HOST;
+                r->sources = h_src + lo;
+                outs[i][0] = malloc(pb); outs[i][1] = malloc(lb); outs[i][2] = malloc(r->nq);
+            } else {
+                r->sources = d_src + lo;
+                outs[i][0] = dalloc(pb); outs[i][1] = dalloc(lb); outs[i][2] = dalloc(r->nq);
+            }
+            r->paths = outs[i][0];
+            r->lengths = outs[i][1];
+            r->status = outs[i][2];
+            TRW(trw_server_submit(srv, r, &ids[i]));
+        }
+        int done = 0;
+        trw_completion comp[R];
+        for (int tries = 0; done < R && tries < 600; ++tries) {
+            uint32_t got = 0;
+            trw_status st = trw_server_poll(srv, comp, R, &got, 100);
+            if (st != TRW_OK && st != TRW_E_TIMEOUT) TRW(st);
+            for (uint32_t c = 0; c < got; ++c) {
+                if (comp[c].status != TRW_OK) {
+                    fprintf(stderr, "request %llu ended with %d\n", (unsigned long long)comp[c].request_id,
+                            (int)comp[c].status);
+                    return 5;
+                }
+            }
+            done += (int)got;
+        }
+        if (done < R) {
+            fprintf(stderr, "the server completed %d of %d requests\n", done, R);
+            return 5;
+        }
+        for (int i = 0; i < R; ++i) {
+            const trw_request *r = &req[i];
+            const size_t pb = sizeof(int32_t) * r->nq * r->path_stride, lb = sizeof(uint32_t) * r->nq;
+            void *hp = outs[i][0], *hl = outs[i][1], *hs = outs[i][2];
+            if (i != 3) {
+                hp = malloc(pb); hl = malloc(lb); hs = malloc(r->nq);
+                HIP(hipMemcpy(hp, outs[i][0], pb, hipMemcpyDeviceToHost));
+                HIP(hipMemcpy(hl, outs[i][1], lb, hipMemcpyDeviceToHost));
+                HIP(hipMemcpy(hs, outs[i][2], r->nq, hipMemcpyDeviceToHost));
+            }
+            char name[64];
+            snprintf(name, sizeof(name), "srv%d_paths", i); write_file(name, hp, pb);
+            snprintf(name, sizeof(name), "srv%d_lengths", i); write_file(name, hl, lb);
+            snprintf(name, sizeof(name), "srv%d_status", i); write_file(name, hs, r->nq);
+            if (i != 3) {
+                for (int k = 0; k < 3; ++k) HIP(hipFree(outs[i][k]));
+            }
+            free(hp); free(hl); free(hs);
+        }
+        TRW(trw_server_destroy(srv));
+        TRW(trw_table_destroy(eidx));
+        HIP(hipFree(d_arena));
+        HIP(hipFree(d_eidx));
+    }
+
     TRW(trw_table_destroy(alias));
     TRW(trw_graph_destroy(g));
-    printf("walked %lld queries from C\n", nq);
+    printf("walked %lld queries from C (batch, streamed to disk, served)\n", nq);
     return 0;
 }
