@@ -437,6 +437,87 @@ trw_status trw_walk_stream(trw_graph g, trw_table table, const trw_walk_params *
                            size_t h_bytes, trw_chunk_fn fn, void *user, trw_stream_t stream);
 
 /* ------------------------------------------------------------------------ */
+/* Graphs on disk (Future Extension: a graph too large for memory is hosted   */
+/* on disk; Related Work: the I/O-efficient single-machine scheme that splits */
+/* the graph into partitions, loads the partition holding the most queries,   */
+/* runs each query there until it ends or leaves, and repeats).  Here the     */
+/* partitions are vertex ranges of the CSR file, one resident on the device   */
+/* at a time, its sampling table built on the device at each load, and the   */
+/* walks are those trw_walk gives on the whole graph.                         */
+/* ------------------------------------------------------------------------ */
+/*
+ * CSR file, native byte order:
+ *   char   magic[8] = "TRWCSR1" (with its NUL)
+ *   uint64 n, m, flags          flags bit 0: weights present, bit 1: labels present
+ *   int64  row_ptr[n + 1]       row_ptr[0] = 0, non-decreasing, row_ptr[n] = m
+ *   int32  col[m]               in [0, n)
+ *   uint32 weight[m]            if flags bit 0
+ *   uint8  label[m]             if flags bit 1
+ * 1 <= n < 2^31.  m may exceed 2^31: only a partition's edges (fewer than 2^31)
+ * are ever in device memory.
+ */
+typedef struct trw_disk_graph_s *trw_disk_graph;
+
+enum { TRW_DISK_WEIGHTS = 1, TRW_DISK_LABELS = 2 };
+
+/* Write a CSR file from host arrays (weight, label: NULL when absent).
+ * TRW_E_INVALID for sizes out of range or a failed write. */
+trw_status trw_disk_graph_write(const char *path, int64_t n, int64_t m, const int64_t *row_ptr,
+                                const int32_t *col, const uint32_t *weight, const uint8_t *label);
+
+/*
+ * Open a CSR file and split its vertices into consecutive ranges of at most
+ * part_edges edges each (a row longer than that gets a range of its own;
+ * part_edges 0: 2^31 - 1).  Reads the header and row_ptr, which stay in host
+ * memory (8(n + 1) bytes); the edges are read at each load.  Errors:
+ * TRW_E_INVALID for a file that cannot be read, a bad magic, flags or size, a
+ * row_ptr that breaks the rules above, a row of 2^31 edges or more, or
+ * part_edges >= 2^31.
+ */
+trw_status trw_disk_graph_open(const char *path, uint64_t part_edges, trw_disk_graph *out);
+trw_status trw_disk_graph_info(trw_disk_graph g, uint64_t *n, uint64_t *m, uint32_t *flags, uint32_t *parts);
+/* Partition i: vertices [v_begin, v_end) and their edges [e_begin, e_end). */
+trw_status trw_disk_graph_partition(trw_disk_graph g, uint32_t i, int64_t *v_begin, int64_t *v_end,
+                                    int64_t *e_begin, int64_t *e_end);
+trw_status trw_disk_graph_close(trw_disk_graph g);
+
+typedef struct {
+    uint64_t runs;             /* partition visits: each walks every query waiting in it */
+    uint64_t loads;            /* partitions read and copied to the device (a visit to the
+                                  resident partition loads nothing) */
+    uint64_t bytes_read;       /* file bytes read */
+    uint64_t read_ns;          /* host time spent reading the file */
+    uint64_t total_ns;         /* host time of the whole call */
+} trw_disk_walk_stats;
+
+/* Device workspace and pinned host bytes trw_disk_walk needs for nq queries. */
+trw_status trw_disk_walk_bytes(trw_disk_graph g, const trw_walk_params *p, uint64_t nq, size_t *device_bytes,
+                               size_t *host_bytes);
+
+/*
+ * Run nq queries over the file's graph: the same paths, lengths and status as
+ * trw_walk over the whole graph (query i has id qid_base + i).  DeepWalk and
+ * PPR with NAIVE, ALIAS, ITS or REJ, and MetaPath; Node2Vec is refused
+ * (TRW_E_UNSUPPORTED): its acceptance test reads the previous vertex's row,
+ * which may lie in another partition.  Until every query ends, the partition
+ * holding the most waiting queries (the lowest index among equals) is loaded
+ * (its edges read into h_pinned, copied to the device, its table built there)
+ * and every query in it moves until it ends or steps into another partition.
+ *   d_sources, d_paths, path_stride, d_lengths, d_status   as trw_walk
+ *   d_ws        device workspace, >= device_bytes, 256-byte aligned
+ *   h_pinned    host memory from hipHostMalloc, >= host_bytes, 256-byte aligned
+ *   stats       filled on return (NULL: not wanted)
+ * Synchronous: returns when every query has ended; runs on `stream`.  Errors
+ * as trw_walk (TRW_E_INVALID for a file whose weights or labels the walk needs
+ * are absent), TRW_E_INVALID for a destination outside [0, n) in a loaded
+ * partition or a failed read, TRW_E_DEVICE for a device error.
+ */
+trw_status trw_disk_walk(trw_disk_graph g, const trw_walk_params *p, const int32_t *d_sources, uint64_t nq,
+                         uint64_t qid_base, int32_t *d_paths, uint64_t path_stride, uint32_t *d_lengths,
+                         uint8_t *d_status, void *d_ws, size_t ws_bytes, void *h_pinned, size_t h_bytes,
+                         trw_disk_walk_stats *stats, trw_stream_t stream);
+
+/* ------------------------------------------------------------------------ */
 /* PPR estimate (Random Walk based Algorithms, PPR): the score of vertex v   */
 /* for a source is the share of the source's queries whose walk ends at v;   */
 /* the highest-scoring vertices are the answer.                              */

@@ -24,7 +24,7 @@ from ._abi import (TRW_A_DEEPWALK, TRW_A_METAPATH, TRW_A_NODE2VEC, TRW_A_PPR, TR
 
 __all__ = ["Graph", "Table", "walk", "make_params", "workspace_bytes", "default_tuning", "autotune",
            "TrwError", "ALGOS", "SAMPLERS", "Program", "check_program", "programs", "Server", "ppr_end_counts",
-           "ppr_walk_counts", "topk", "walk_stream", "walk_noalloc"]
+           "ppr_walk_counts", "topk", "walk_stream", "walk_noalloc", "DiskGraph", "write_disk_graph"]
 
 ALGOS = {"deepwalk": TRW_A_DEEPWALK, "ppr": TRW_A_PPR, "node2vec": TRW_A_NODE2VEC, "metapath": TRW_A_METAPATH}
 SAMPLERS = {"naive": TRW_S_NAIVE, "alias": TRW_S_ALIAS, "its": TRW_S_ITS, "orej": TRW_S_OREJ, "rej": TRW_S_REJ}
@@ -470,6 +470,75 @@ def read_stream_file(path: str):
         pos += 4 * total
         yield {"qid_base": qid_base, "nq": n, "lengths": lengths, "status": status, "offsets": offs,
                "entries": entries}
+
+
+def write_disk_graph(path: str, row_ptr, col, weight=None, label=None) -> None:
+    """Write a CSR file for DiskGraph (trw_disk_graph_write) from host arrays: row_ptr as
+    int64[n + 1], col int32[m], optional weight uint32[m] and label uint8[m]."""
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    c = np.ascontiguousarray(col, dtype=np.int32)
+    w = None if weight is None else np.ascontiguousarray(weight, dtype=np.uint32)
+    lab = None if label is None else np.ascontiguousarray(label, dtype=np.uint8)
+    n, m = rp.size - 1, c.size
+    check(_abi.trw_disk_graph_write(path.encode(), n, m, rp.ctypes.data, c.ctypes.data if m else None,
+                                    None if w is None else w.ctypes.data, None if lab is None else lab.ctypes.data))
+
+
+class DiskGraph:
+    """A CSR graph kept in a file (trw_disk_graph_*): walks load one vertex-range partition
+    of at most part_edges edges onto the device at a time."""
+
+    def __init__(self, path: str, part_edges: int = 0):
+        h = ctypes.c_void_p()
+        check(_abi.trw_disk_graph_open(path.encode(), part_edges, ctypes.byref(h)))
+        self.handle = h
+        n, m = ctypes.c_uint64(0), ctypes.c_uint64(0)
+        flags, parts = ctypes.c_uint32(0), ctypes.c_uint32(0)
+        check(_abi.trw_disk_graph_info(h, ctypes.byref(n), ctypes.byref(m), ctypes.byref(flags), ctypes.byref(parts)))
+        self.n, self.m, self.flags, self.parts = int(n.value), int(m.value), int(flags.value), int(parts.value)
+
+    def partition(self, i: int):
+        """(v_begin, v_end, e_begin, e_end) of partition i."""
+        vals = [ctypes.c_int64(0) for _ in range(4)]
+        check(_abi.trw_disk_graph_partition(self.handle, i, *[ctypes.byref(v) for v in vals]))
+        return tuple(int(v.value) for v in vals)
+
+    def walk_bytes(self, p: trw_walk_params, nq: int):
+        d, h = ctypes.c_size_t(0), ctypes.c_size_t(0)
+        check(_abi.trw_disk_walk_bytes(self.handle, ctypes.byref(p), nq, ctypes.byref(d), ctypes.byref(h)))
+        return int(d.value), int(h.value)
+
+    def walk(self, p: trw_walk_params, sources: torch.Tensor, qid_base: int = 0, stride: Optional[int] = None,
+             stream=None):
+        """Run len(sources) queries (device int32 sources); returns (paths int32[nq, stride],
+        lengths, status, stats dict), the outputs those of trw_walk on the whole graph."""
+        nq = int(sources.numel())
+        dev = sources.device
+        stride = stride or int(p.max_len) + 1
+        paths = torch.empty((nq, stride), dtype=torch.int32, device=dev)
+        lengths = torch.empty(nq, dtype=torch.int32, device=dev)
+        status = torch.empty(nq, dtype=torch.uint8, device=dev)
+        dbytes, hbytes = self.walk_bytes(p, nq) if nq else (0, 0)
+        d_keep, d_ws = _aligned(max(dbytes, 256), device=dev)
+        h_keep, h_buf = _aligned(max(hbytes, 256), pin=True)
+        stats = _abi.trw_disk_walk_stats()
+        check(_abi.trw_disk_walk(self.handle, ctypes.byref(p), _dptr(sources), nq, qid_base, _dptr(paths), stride,
+                                 _dptr(lengths), _dptr(status), _dptr(d_ws), d_ws.numel(),
+                                 ctypes.c_void_p(h_buf.data_ptr()), h_buf.numel(), ctypes.byref(stats),
+                                 _stream_ptr(stream)))
+        del d_keep, h_keep
+        return paths, lengths, status, stats.as_dict()
+
+    def close(self):
+        if self.handle:
+            check(_abi.trw_disk_graph_close(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def topk(counts: torch.Tensor, k: int, stream=None):

@@ -87,6 +87,17 @@ class trw_server_stats(ctypes.Structure):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
+TRW_DISK_WEIGHTS, TRW_DISK_LABELS = 1, 2
+
+
+class trw_disk_walk_stats(ctypes.Structure):
+    _fields_ = [("runs", ctypes.c_uint64), ("loads", ctypes.c_uint64), ("bytes_read", ctypes.c_uint64),
+                ("read_ns", ctypes.c_uint64), ("total_ns", ctypes.c_uint64)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
 class TrwError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
@@ -126,6 +137,17 @@ _SIGS = {
     "trw_adjacency_index_build": (_st, [_P, _P, _sz, _P, _PP]),
     "trw_label_index_bytes": (_st, [_P, _u32, ctypes.POINTER(_sz)]),
     "trw_label_index_build": (_st, [_P, _u32, _P, _sz, _P, _PP]),
+    "trw_disk_graph_write": (_st, [ctypes.c_char_p, _i64, _i64, _P, _P, _P, _P]),
+    "trw_disk_graph_open": (_st, [ctypes.c_char_p, _u64, _PP]),
+    "trw_disk_graph_info": (_st, [_P, ctypes.POINTER(_u64), ctypes.POINTER(_u64), ctypes.POINTER(_u32),
+                                  ctypes.POINTER(_u32)]),
+    "trw_disk_graph_partition": (_st, [_P, _u32, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i64),
+                                       ctypes.POINTER(_i64)]),
+    "trw_disk_graph_close": (_st, [_P]),
+    "trw_disk_walk_bytes": (_st, [_P, ctypes.POINTER(trw_walk_params), _u64, ctypes.POINTER(_sz),
+                                  ctypes.POINTER(_sz)]),
+    "trw_disk_walk": (_st, [_P, ctypes.POINTER(trw_walk_params), _P, _u64, _u64, _P, _u64, _P, _P, _P, _sz, _P, _sz,
+                            ctypes.POINTER(trw_disk_walk_stats), _P]),
     "trw_server_arena_bytes": (_st, [ctypes.POINTER(trw_server_cfg), _sz, ctypes.POINTER(_sz)]),
     "trw_server_create": (_st, [_P, _P, _P, ctypes.POINTER(trw_server_cfg), _P, _sz, _PP]),
     "trw_server_request_bytes": (_st, [_P, ctypes.POINTER(trw_request), ctypes.POINTER(_sz)]),
@@ -217,6 +239,13 @@ trw_walk_stream = lib.trw_walk_stream
 trw_chunk_to_fd = lib.trw_chunk_to_fd
 TRW_CHUNK_TO_FD = TRW_CHUNK_FN(("trw_chunk_to_fd", lib))   # the library's file sink as a chunk function
 trw_edge_index_bytes = lib.trw_edge_index_bytes
+trw_disk_graph_write = lib.trw_disk_graph_write
+trw_disk_graph_open = lib.trw_disk_graph_open
+trw_disk_graph_info = lib.trw_disk_graph_info
+trw_disk_graph_partition = lib.trw_disk_graph_partition
+trw_disk_graph_close = lib.trw_disk_graph_close
+trw_disk_walk_bytes = lib.trw_disk_walk_bytes
+trw_disk_walk = lib.trw_disk_walk
 trw_edge_index_build = lib.trw_edge_index_build
 trw_probe_fill = lib.trw_probe_fill
 trw_probe_gather = lib.trw_probe_gather
