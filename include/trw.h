@@ -441,9 +441,10 @@ trw_status trw_walk_stream(trw_graph g, trw_table table, const trw_walk_params *
 /* on disk; Related Work: the I/O-efficient single-machine scheme that splits */
 /* the graph into partitions, loads the partition holding the most queries,   */
 /* runs each query there until it ends or leaves, and repeats).  Here the     */
-/* partitions are vertex ranges of the CSR file, one resident on the device   */
-/* at a time, its sampling table built on the device at each load, and the   */
-/* walks are those trw_walk gives on the whole graph.                         */
+/* partitions are vertex ranges of the CSR file, up to `slots` of them        */
+/* resident on the device at once (walks cross between resident ones in      */
+/* place), each partition's sampling table built on the device at its load,  */
+/* and the walks are those trw_walk gives on the whole graph.                 */
 /* ------------------------------------------------------------------------ */
 /*
  * CSR file, native byte order:
@@ -482,28 +483,35 @@ trw_status trw_disk_graph_partition(trw_disk_graph g, uint32_t i, int64_t *v_beg
 trw_status trw_disk_graph_close(trw_disk_graph g);
 
 typedef struct {
-    uint64_t runs;             /* partition visits: each walks every query waiting in it */
-    uint64_t loads;            /* partitions read and copied to the device (a visit to the
-                                  resident partition loads nothing) */
+    uint64_t runs;             /* rounds: each walks every query waiting in a resident partition */
+    uint64_t loads;            /* partitions read and copied to the device */
     uint64_t bytes_read;       /* file bytes read */
     uint64_t read_ns;          /* host time spent reading the file */
     uint64_t total_ns;         /* host time of the whole call */
 } trw_disk_walk_stats;
 
-/* Device workspace and pinned host bytes trw_disk_walk needs for nq queries. */
-trw_status trw_disk_walk_bytes(trw_disk_graph g, const trw_walk_params *p, uint64_t nq, size_t *device_bytes,
-                               size_t *host_bytes);
+/* Device workspace and pinned host bytes trw_disk_walk needs for nq queries
+ * with `slots` partitions resident at once (1 .. the partition count; 0 counts
+ * as 1, more than the partitions as all of them).  Per slot: 4(n + 1) bytes of
+ * row offsets plus the largest partition's edges (4 B each, 4 more for
+ * weights, 1 for labels) and table (ALIAS 32 B per edge; ITS 40 B per edge +
+ * 8n; REJ 32 B per edge + 4n). */
+trw_status trw_disk_walk_bytes(trw_disk_graph g, const trw_walk_params *p, uint64_t nq, uint32_t slots,
+                               size_t *device_bytes, size_t *host_bytes);
 
 /*
  * Run nq queries over the file's graph: the same paths, lengths and status as
  * trw_walk over the whole graph (query i has id qid_base + i).  DeepWalk and
  * PPR with NAIVE, ALIAS, ITS or REJ, and MetaPath; Node2Vec is refused
  * (TRW_E_UNSUPPORTED): its acceptance test reads the previous vertex's row,
- * which may lie in another partition.  Until every query ends, the partition
- * holding the most waiting queries (the lowest index among equals) is loaded
- * (its edges read into h_pinned, copied to the device, its table built there)
- * and every query in it moves until it ends or steps into another partition.
+ * which may lie in another partition.  Until every query ends: the queries
+ * waiting in resident partitions move until they end or step into a
+ * partition that is not resident; when no resident partition holds a waiting
+ * query, the partition holding the most (the lowest index among equals) is
+ * loaded (its edges read through h_pinned, copied to the device, its table
+ * built there) into a free slot or the one whose partition ran longest ago.
  *   d_sources, d_paths, path_stride, d_lengths, d_status   as trw_walk
+ *   slots       partitions resident at once, as trw_disk_walk_bytes
  *   d_ws        device workspace, >= device_bytes, 256-byte aligned
  *   h_pinned    host memory from hipHostMalloc, >= host_bytes, 256-byte aligned
  *   stats       filled on return (NULL: not wanted)
@@ -514,8 +522,8 @@ trw_status trw_disk_walk_bytes(trw_disk_graph g, const trw_walk_params *p, uint6
  */
 trw_status trw_disk_walk(trw_disk_graph g, const trw_walk_params *p, const int32_t *d_sources, uint64_t nq,
                          uint64_t qid_base, int32_t *d_paths, uint64_t path_stride, uint32_t *d_lengths,
-                         uint8_t *d_status, void *d_ws, size_t ws_bytes, void *h_pinned, size_t h_bytes,
-                         trw_disk_walk_stats *stats, trw_stream_t stream);
+                         uint8_t *d_status, uint32_t slots, void *d_ws, size_t ws_bytes, void *h_pinned,
+                         size_t h_bytes, trw_disk_walk_stats *stats, trw_stream_t stream);
 
 /* ------------------------------------------------------------------------ */
 /* PPR estimate (Random Walk based Algorithms, PPR): the score of vertex v   */

@@ -503,27 +503,28 @@ class DiskGraph:
         check(_abi.trw_disk_graph_partition(self.handle, i, *[ctypes.byref(v) for v in vals]))
         return tuple(int(v.value) for v in vals)
 
-    def walk_bytes(self, p: trw_walk_params, nq: int):
+    def walk_bytes(self, p: trw_walk_params, nq: int, slots: int = 1):
         d, h = ctypes.c_size_t(0), ctypes.c_size_t(0)
-        check(_abi.trw_disk_walk_bytes(self.handle, ctypes.byref(p), nq, ctypes.byref(d), ctypes.byref(h)))
+        check(_abi.trw_disk_walk_bytes(self.handle, ctypes.byref(p), nq, slots, ctypes.byref(d), ctypes.byref(h)))
         return int(d.value), int(h.value)
 
     def walk(self, p: trw_walk_params, sources: torch.Tensor, qid_base: int = 0, stride: Optional[int] = None,
-             stream=None):
-        """Run len(sources) queries (device int32 sources); returns (paths int32[nq, stride],
-        lengths, status, stats dict), the outputs those of trw_walk on the whole graph."""
+             slots: int = 1, stream=None):
+        """Run len(sources) queries (device int32 sources) with up to `slots` partitions resident;
+        returns (paths int32[nq, stride], lengths, status, stats dict), the outputs those of
+        trw_walk on the whole graph."""
         nq = int(sources.numel())
         dev = sources.device
         stride = stride or int(p.max_len) + 1
         paths = torch.empty((nq, stride), dtype=torch.int32, device=dev)
         lengths = torch.empty(nq, dtype=torch.int32, device=dev)
         status = torch.empty(nq, dtype=torch.uint8, device=dev)
-        dbytes, hbytes = self.walk_bytes(p, nq) if nq else (0, 0)
+        dbytes, hbytes = self.walk_bytes(p, nq, slots) if nq else (0, 0)
         d_keep, d_ws = _aligned(max(dbytes, 256), device=dev)
         h_keep, h_buf = _aligned(max(hbytes, 256), pin=True)
         stats = _abi.trw_disk_walk_stats()
         check(_abi.trw_disk_walk(self.handle, ctypes.byref(p), _dptr(sources), nq, qid_base, _dptr(paths), stride,
-                                 _dptr(lengths), _dptr(status), _dptr(d_ws), d_ws.numel(),
+                                 _dptr(lengths), _dptr(status), slots, _dptr(d_ws), d_ws.numel(),
                                  ctypes.c_void_p(h_buf.data_ptr()), h_buf.numel(), ctypes.byref(stats),
                                  _stream_ptr(stream)))
         del d_keep, h_keep

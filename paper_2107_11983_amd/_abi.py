@@ -144,10 +144,10 @@ _SIGS = {
     "trw_disk_graph_partition": (_st, [_P, _u32, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i64),
                                        ctypes.POINTER(_i64)]),
     "trw_disk_graph_close": (_st, [_P]),
-    "trw_disk_walk_bytes": (_st, [_P, ctypes.POINTER(trw_walk_params), _u64, ctypes.POINTER(_sz),
+    "trw_disk_walk_bytes": (_st, [_P, ctypes.POINTER(trw_walk_params), _u64, _u32, ctypes.POINTER(_sz),
                                   ctypes.POINTER(_sz)]),
-    "trw_disk_walk": (_st, [_P, ctypes.POINTER(trw_walk_params), _P, _u64, _u64, _P, _u64, _P, _P, _P, _sz, _P, _sz,
-                            ctypes.POINTER(trw_disk_walk_stats), _P]),
+    "trw_disk_walk": (_st, [_P, ctypes.POINTER(trw_walk_params), _P, _u64, _u64, _P, _u64, _P, _P, _u32, _P, _sz, _P,
+                            _sz, ctypes.POINTER(trw_disk_walk_stats), _P]),
     "trw_server_arena_bytes": (_st, [ctypes.POINTER(trw_server_cfg), _sz, ctypes.POINTER(_sz)]),
     "trw_server_create": (_st, [_P, _P, _P, ctypes.POINTER(trw_server_cfg), _P, _sz, _PP]),
     "trw_server_request_bytes": (_st, [_P, ctypes.POINTER(trw_request), ctypes.POINTER(_sz)]),

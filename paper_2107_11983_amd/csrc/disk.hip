@@ -1,20 +1,23 @@
-// Walks over a CSR graph kept in a file: the graph is split into vertex
-// ranges, one range ("partition") is resident on the device at a time, and
-// the queries waiting in it walk until they end or step into another range.
-// The paper leaves graphs larger than memory to future work (Future
-// Extension: an external-memory system hosting the graph on disk) and
-// describes, among related systems, the scheme used here: load the partition
-// holding the most queries, run each of its queries until it completes or
-// leaves, swap, repeat (Related Work).  The moves are the batch walker's
-// (same random contract, same tables, built on the device for the resident
-// range at each load), so a query's path is the one trw_walk gives on the
-// whole graph.
+// Walks over a CSR graph kept in a file.  The graph is split into vertex
+// ranges ("partitions"); up to `slots` of them are resident on the device at
+// once, and the queries waiting in resident partitions walk until they end
+// or step into a partition that is not resident.  The paper leaves graphs
+// larger than memory to future work (Future Extension: an external-memory
+// system hosting the graph on disk) and describes, among related systems,
+// the scheme used here: load the partition holding the most queries, run
+// each of its queries until it completes or leaves, swap, repeat (Related
+// Work).  Here HBM holds many partitions at once, so a walk crosses freely
+// between resident ones and a partition is read again only after eviction.
+// The moves are the batch walker's (same random contract, same tables,
+// built on the device for each partition at its load), so a query's path is
+// the one trw_walk gives on the whole graph.
 //
-// Device view of a resident partition [v0, v1) with edges [e0, e1): a row
-// offset array over all n + 1 vertices holding offsets relative to e0 (0 below
-// v0 and e1 - e0 above v1, so rows outside the range are empty), the range's
+// A slot holds one partition [v0, v1) with edges [e0, e1): a row offset
+// array over all n + 1 vertices with offsets relative to e0 (0 below v0 and
+// e1 - e0 above v1, so rows outside the range are empty), the range's
 // destinations, weights and labels, and its table.  Destinations keep their
-// global ids; a walker whose vertex falls outside [v0, v1) leaves.
+// global ids; a per-vertex map gives the slot of each vertex's partition
+// (kNoSlot when it is not resident).
 #include <hip/hip_runtime.h>
 
 #include <errno.h>
@@ -23,9 +26,11 @@
 #include <unistd.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "walk_common.hpp"
@@ -47,6 +52,10 @@ namespace {
 constexpr char kMagic[8] = {'T', 'R', 'W', 'C', 'S', 'R', '1', '\0'};
 constexpr uint64_t kHeaderBytes = 32;
 constexpr uint64_t kMaxParts = 1u << 24;
+constexpr uint32_t kMaxSlots = 4096;
+constexpr uint16_t kNoSlot = 0xFFFF;
+constexpr size_t kReadChunk = size_t(64) << 20;   // file bytes per read (then copied while the next is read)
+constexpr size_t kReadPiece = size_t(8) << 20;    // bytes per reading thread
 
 trw_status dfail(trw_status st, const std::string &m) {
     set_error(m);
@@ -74,6 +83,26 @@ bool read_at(int fd, void *dst, size_t bytes, uint64_t off) {
     return true;
 }
 
+// pread of one range split over up to 8 threads (page-cache copies and device
+// queues both gain from several reads in flight).
+bool read_parallel(int fd, void *dst, size_t bytes, uint64_t off) {
+    const size_t pieces = std::min<size_t>(8, (bytes + kReadPiece - 1) / kReadPiece);
+    if (pieces <= 1) return read_at(fd, dst, bytes, off);
+    const size_t each = (bytes + pieces - 1) / pieces;
+    std::atomic<bool> ok{true};
+    std::vector<std::thread> th;
+    th.reserve(pieces);
+    for (size_t i = 0; i < pieces; ++i) {
+        const size_t a = i * each, b = std::min(bytes, a + each);
+        if (a >= b) break;
+        th.emplace_back([&, a, b] {
+            if (!read_at(fd, static_cast<char *>(dst) + a, b - a, off + a)) ok = false;
+        });
+    }
+    for (auto &t : th) t.join();
+    return ok;
+}
+
 bool write_all(int fd, const void *src, size_t bytes) {
     const char *p = static_cast<const char *>(src);
     while (bytes > 0) {
@@ -97,6 +126,38 @@ struct alignas(16) DRec {
     uint32_t part;
 };
 
+// Where the pieces of a slot sit: slot s starts at base + s * stride; the
+// table's parts are at fixed offsets sized for the largest partition.
+struct SlotsDev {
+    char *base;
+    uint64_t stride;
+    uint64_t o_rp, o_col, o_wgt, o_lab, o_tab;
+    uint64_t tab_o1, tab_o2;   // REJ: p* at o1; ITS: next-slot records at o1, W at o2
+    int32_t n;
+    uint32_t has_wgt, has_lab;
+};
+
+__device__ __forceinline__ void slot_views(const SlotsDev &S, uint32_t slot, GraphDev &g, TableDev &t,
+                                           uint32_t sampler) {
+    char *b = S.base + (uint64_t)slot * S.stride;
+    g.row_ptr = reinterpret_cast<const int32_t *>(b + S.o_rp);
+    g.col = reinterpret_cast<const int32_t *>(b + S.o_col);
+    g.weight = S.has_wgt ? reinterpret_cast<const uint32_t *>(b + S.o_wgt) : nullptr;
+    g.label = S.has_lab ? reinterpret_cast<const uint8_t *>(b + S.o_lab) : nullptr;
+    g.n = S.n;
+    g.m = 0;
+    g.symmetric = 0;
+    char *tb = b + S.o_tab;
+    if (sampler == SMP_ALIAS) {
+        t.alias = reinterpret_cast<const uint4 *>(tb);
+    } else if (sampler == SMP_REJ) {
+        t.rej = reinterpret_cast<const uint4 *>(tb);
+        t.pmax = reinterpret_cast<const uint32_t *>(tb + S.tab_o1);
+    } else if (sampler == SMP_ITS) {
+        t.prefix = reinterpret_cast<const uint64_t *>(tb);
+    }
+}
+
 // The partition holding v: the largest i with vstart[i] <= v.
 __device__ __forceinline__ uint32_t part_of(const int32_t *__restrict__ vstart, uint32_t parts, int32_t v) {
     uint32_t lo = 0, hi = parts;
@@ -107,12 +168,37 @@ __device__ __forceinline__ uint32_t part_of(const int32_t *__restrict__ vstart, 
     return lo;
 }
 
+// Lanes holding the same key share one atomic: the wave serves one key at a
+// time (the number of distinct keys among its lanes).  Returns this lane's
+// position among the additions to counters[key] (undefined when !active).
+__device__ __forceinline__ uint32_t wave_add_by_key(uint32_t *counters, uint32_t key, bool active) {
+    uint64_t todo = __ballot(active);
+    uint32_t pos = 0;
+    while (todo) {
+        const int leader = (int)__builtin_ctzll(todo);
+        const uint32_t k = __shfl(key, leader);
+        const uint64_t same = __ballot(active && key == k) & todo;
+        uint32_t base = 0;
+        if (lane_id() == (uint32_t)leader) base = atomicAdd(&counters[k], (uint32_t)__popcll(same));
+        base = __shfl(base, leader);
+        if ((same >> lane_id()) & 1) pos = base + rank_below(same);
+        todo &= ~same;
+    }
+    return pos;
+}
+
 __global__ void k_disk_fill(uint32_t *p, uint32_t n, uint32_t v) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
 }
 
-// Row offsets outside the resident range: 0 below v0, mp above v1.
+// Slot map entries of the vertices [lo, hi).
+__global__ void k_disk_set_slot(uint16_t *vslot, int64_t lo, int64_t hi, uint16_t v) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < hi; i += stride) vslot[i] = v;
+}
+
+// Row offsets outside the slot's range: 0 below v0, mp above v1.
 __global__ void k_disk_rows(int32_t *rp, int64_t n, int64_t v0, int64_t v1, int32_t mp) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v <= n; v += stride) {
@@ -145,30 +231,42 @@ __global__ void __launch_bounds__(256) k_disk_init(WalkDev a, int32_t n, const i
     }
 }
 
-__global__ void k_disk_hist(const DRec *__restrict__ in, const uint32_t *count, uint32_t *hist) {
+__global__ void __launch_bounds__(256) k_disk_hist(const DRec *__restrict__ in, const uint32_t *count,
+                                                   uint32_t *hist) {
     const uint32_t n = *count;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-        atomicAdd(&hist[in[i].part], 1u);
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t base = 0; base < n; base += stride) {
+        const uint32_t i = base + blockIdx.x * blockDim.x + threadIdx.x;
+        const bool act = i < n;
+        (void)wave_add_by_key(hist, act ? in[i].part : 0u, act);
+    }
 }
 
-// The waiting list grouped by partition: records of partitions other than
-// `skip` move, in order, to their partition's new start; the newly arrived
-// ones follow them (in any order: a walk does not depend on its position).
-__global__ void k_disk_move_old(const DRec *__restrict__ in, uint32_t n_in, uint32_t skip,
+// The waiting list grouped by partition: records of partitions not walked
+// (consumed[part] == 0) move, in order, to their partition's new start; the
+// newly arrived ones follow them (in any order: a walk does not depend on
+// its position).
+__global__ void k_disk_move_old(const DRec *__restrict__ in, uint32_t n_in, const uint8_t *__restrict__ consumed,
                                 const uint32_t *__restrict__ old_off, const uint32_t *__restrict__ new_off,
                                 DRec *__restrict__ out) {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_in; i += gridDim.x * blockDim.x) {
         const DRec r = in[i];
-        if (r.part != skip) out[new_off[r.part] + (i - old_off[r.part])] = r;
+        if (!consumed[r.part]) out[new_off[r.part] + (i - old_off[r.part])] = r;
     }
 }
 
-__global__ void k_disk_place_new(const DRec *__restrict__ in, const uint32_t *count, const uint32_t *__restrict__ base,
-                                 uint32_t *cursor, DRec *__restrict__ out) {
+__global__ void __launch_bounds__(256) k_disk_place_new(const DRec *__restrict__ in, const uint32_t *count,
+                                                        const uint32_t *__restrict__ base, uint32_t *cursor,
+                                                        DRec *__restrict__ out) {
     const uint32_t n = *count;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const DRec r = in[i];
-        out[base[r.part] + atomicAdd(&cursor[r.part], 1u)] = r;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t b = 0; b < n; b += stride) {
+        const uint32_t i = b + blockIdx.x * blockDim.x + threadIdx.x;
+        const bool act = i < n;
+        DRec r{0u, 0, 0u, 0u};
+        if (act) r = in[i];
+        const uint32_t pos = wave_add_by_key(cursor, r.part, act);
+        if (act) out[base[r.part] + pos] = r;
     }
 }
 
@@ -210,11 +308,12 @@ __device__ __forceinline__ int32_t disk_move(const GraphDev &g, const TableDev &
     return static_next<SMP>(g, t, off, d, r, a.its_gallop);
 }
 
-// Every waiting walker of the resident partition [v0, v1) moves until it
-// ends (its length and status written) or its vertex leaves the range (it
-// is appended to `out` with its new partition).
+// Every waiting walker of one resident partition moves until it ends (its
+// length and status written) or its vertex lies in a partition that is not
+// resident (it is appended to `out` with that partition).  Moves between
+// resident partitions continue in place.
 template <uint32_t ALGO, uint32_t SMP>
-__global__ void __launch_bounds__(256) k_disk_walk(GraphDev g, TableDev t, WalkDev a, int32_t v0, int32_t v1,
+__global__ void __launch_bounds__(256) k_disk_walk(SlotsDev S, WalkDev a, const uint16_t *__restrict__ vslot,
                                                    const DRec *__restrict__ in, uint32_t n_in,
                                                    const int32_t *__restrict__ vstart, uint32_t parts,
                                                    DRec *__restrict__ out, uint32_t *count_out) {
@@ -229,10 +328,14 @@ __global__ void __launch_bounds__(256) k_disk_walk(GraphDev g, TableDev t, WalkD
             int32_t *__restrict__ path = a.paths + (uint64_t)rc.qi * a.stride;
             uint8_t st = 0;
             for (;;) {
-                if (rc.cur < v0 || rc.cur >= v1) {
+                const uint16_t slot = vslot[rc.cur];
+                if (slot == kNoSlot) {
                     leave = true;
                     break;
                 }
+                GraphDev g;
+                TableDev t{};
+                slot_views(S, slot, g, t, SMP);
                 const int32_t off = g.row_ptr[rc.cur];
                 const uint32_t d = (uint32_t)(g.row_ptr[rc.cur + 1] - off);
                 Rand4 r = philox(rc.k, 0, qid, a.seed);
@@ -272,34 +375,58 @@ bool needs_weights(uint32_t sampler, uint32_t algo) {
     return algo != TRW_A_METAPATH && (sampler == TRW_S_ALIAS || sampler == TRW_S_ITS || sampler == TRW_S_REJ);
 }
 
-size_t table_bytes(uint32_t algo, uint32_t sampler, int64_t mp, int64_t n) {
+// Table parts for partitions of up to mp edges: total, and the offsets of
+// the second and third parts (REJ: p*; ITS: next-slot records, W).
+size_t table_bytes(uint32_t algo, uint32_t sampler, int64_t mp, int64_t n, size_t *o1, size_t *o2) {
+    *o1 = *o2 = 0;
     if (algo == TRW_A_METAPATH) return 0;
     switch (sampler) {
         case TRW_S_ALIAS: return kAliasEntryBytes * (size_t)mp;
-        case TRW_S_ITS: return its_prefix_bytes(mp) + its_next_bytes(mp) + sizeof(uint64_t) * (size_t)n;
-        case TRW_S_REJ: return rej_records_bytes(mp) + sizeof(uint32_t) * (size_t)n;
+        case TRW_S_ITS:
+            *o1 = its_prefix_bytes(mp);
+            *o2 = *o1 + its_next_bytes(mp);
+            return *o2 + sizeof(uint64_t) * (size_t)n;
+        case TRW_S_REJ:
+            *o1 = rej_records_bytes(mp);
+            return *o1 + sizeof(uint32_t) * (size_t)n;
         default: return 0;
     }
 }
 
+uint32_t clamp_slots(const trw_disk_graph_s &g, uint32_t slots) {
+    const uint32_t parts = (uint32_t)(g.vstart.size() - 1);
+    return std::max<uint32_t>(1, std::min<uint32_t>(std::min(slots, kMaxSlots), parts));
+}
+
 // Offsets of the pieces of the device workspace and of the pinned buffer.
 struct Layout {
-    size_t rp, col, wgt, lab, table, lists[3], vstart, hist, cursor, new_off, old_off, base, count, dev_total;
-    size_t h_rp, h_col, h_wgt, h_lab, h_hist, h_new_off, h_old_off, h_base, host_total;
+    SlotsDev S;
+    size_t slots_bytes, vslot, lists[3], vstart, hist, cursor, new_off, old_off, base, consumed, count, dev_total;
+    size_t h_rp, h_col, h_wgt, h_lab, h_hist, h_new_off, h_old_off, h_base, h_consumed, host_total;
 };
 
-Layout layout(const trw_disk_graph_s &g, const trw_walk_params &p, uint64_t nq) {
+Layout layout(const trw_disk_graph_s &g, const trw_walk_params &p, uint64_t nq, uint32_t slots) {
     const size_t parts = g.vstart.size() - 1;
     const size_t mp = (size_t)g.max_edges;
     const bool w = needs_weights(p.sampler, p.algo), l = p.algo == TRW_A_METAPATH;
     Layout L{};
     size_t o = 0;
     auto take = [&o](size_t bytes) { const size_t at = o; o += r256(bytes); return at; };
-    L.rp = take(4 * ((size_t)g.n + 1));
-    L.col = take(4 * mp);
-    L.wgt = take(w ? 4 * mp : 0);
-    L.lab = take(l ? mp : 0);
-    L.table = take(table_bytes(p.algo, p.sampler, (int64_t)mp, g.n));
+    size_t o1 = 0, o2 = 0;
+    L.S.o_rp = take(4 * ((size_t)g.n + 1));
+    L.S.o_col = take(4 * mp);
+    L.S.o_wgt = take(w ? 4 * mp : 0);
+    L.S.o_lab = take(l ? mp : 0);
+    L.S.o_tab = take(table_bytes(p.algo, p.sampler, (int64_t)mp, g.n, &o1, &o2));
+    L.S.stride = o;
+    L.S.tab_o1 = o1;
+    L.S.tab_o2 = o2;
+    L.S.n = (int32_t)g.n;
+    L.S.has_wgt = w;
+    L.S.has_lab = l;
+    L.slots_bytes = o * clamp_slots(g, slots);
+    o = L.slots_bytes;
+    L.vslot = take(2 * (size_t)g.n + 4);
     for (auto &x : L.lists) x = take(sizeof(DRec) * (size_t)nq);
     L.vstart = take(4 * (parts + 1));
     L.hist = take(4 * parts);
@@ -307,6 +434,7 @@ Layout layout(const trw_disk_graph_s &g, const trw_walk_params &p, uint64_t nq) 
     L.new_off = take(4 * parts);
     L.old_off = take(4 * parts);
     L.base = take(4 * parts);
+    L.consumed = take(parts);
     L.count = take(4);
     L.dev_total = o;
     o = 0;
@@ -318,6 +446,7 @@ Layout layout(const trw_disk_graph_s &g, const trw_walk_params &p, uint64_t nq) 
     L.h_new_off = take(4 * parts);
     L.h_old_off = take(4 * parts);
     L.h_base = take(4 * parts);
+    L.h_consumed = take(parts);
     L.host_total = o;
     return L;
 }
@@ -345,30 +474,36 @@ trw_status check_walk(const trw_disk_graph_s *g, const trw_walk_params *p) {
 }
 
 template <uint32_t ALGO, uint32_t SMP>
-void launch_disk_walk(const GraphDev &g, const TableDev &t, const WalkDev &w, int32_t v0, int32_t v1,
-                      const DRec *in, uint32_t n_in, const int32_t *vstart, uint32_t parts, DRec *out,
-                      uint32_t *count, uint32_t blocks, hipStream_t s) {
-    hipLaunchKernelGGL((k_disk_walk<ALGO, SMP>), dim3(blocks), dim3(256), 0, s, g, t, w, v0, v1, in, n_in, vstart,
-                       parts, out, count);
+void launch_disk_walk(const SlotsDev &S, const WalkDev &w, const uint16_t *vslot, const DRec *in, uint32_t n_in,
+                      const int32_t *vstart, uint32_t parts, DRec *out, uint32_t *count, uint32_t blocks,
+                      hipStream_t s) {
+    hipLaunchKernelGGL((k_disk_walk<ALGO, SMP>), dim3(blocks), dim3(256), 0, s, S, w, vslot, in, n_in, vstart, parts,
+                       out, count);
 }
 
-template <uint32_t ALGO>
-void dispatch_walk(uint32_t sampler, const GraphDev &g, const TableDev &t, const WalkDev &w, int32_t v0, int32_t v1,
-                   const DRec *in, uint32_t n_in, const int32_t *vstart, uint32_t parts, DRec *out,
-                   uint32_t *count, uint32_t blocks, hipStream_t s) {
+void dispatch_walk(uint32_t algo, uint32_t sampler, const SlotsDev &S, const WalkDev &w, const uint16_t *vslot,
+                   const DRec *in, uint32_t n_in, const int32_t *vstart, uint32_t parts, DRec *out, uint32_t *count,
+                   uint32_t blocks, hipStream_t s) {
+#define TRW_DISK_WALK(A, M) launch_disk_walk<A, M>(S, w, vslot, in, n_in, vstart, parts, out, count, blocks, s)
+    if (algo == TRW_A_METAPATH) {
+        TRW_DISK_WALK(ALG_METAPATH, SMP_ITS);
+        return;
+    }
+    const bool ppr = algo == TRW_A_PPR;
     switch (sampler) {
         case TRW_S_NAIVE:
-            launch_disk_walk<ALGO, SMP_NAIVE>(g, t, w, v0, v1, in, n_in, vstart, parts, out, count, blocks, s);
+            if (ppr) TRW_DISK_WALK(ALG_PPR, SMP_NAIVE); else TRW_DISK_WALK(ALG_DEEPWALK, SMP_NAIVE);
             break;
         case TRW_S_ALIAS:
-            launch_disk_walk<ALGO, SMP_ALIAS>(g, t, w, v0, v1, in, n_in, vstart, parts, out, count, blocks, s);
+            if (ppr) TRW_DISK_WALK(ALG_PPR, SMP_ALIAS); else TRW_DISK_WALK(ALG_DEEPWALK, SMP_ALIAS);
             break;
         case TRW_S_REJ:
-            launch_disk_walk<ALGO, SMP_REJ>(g, t, w, v0, v1, in, n_in, vstart, parts, out, count, blocks, s);
+            if (ppr) TRW_DISK_WALK(ALG_PPR, SMP_REJ); else TRW_DISK_WALK(ALG_DEEPWALK, SMP_REJ);
             break;
         default:
-            launch_disk_walk<ALGO, SMP_ITS>(g, t, w, v0, v1, in, n_in, vstart, parts, out, count, blocks, s);
+            if (ppr) TRW_DISK_WALK(ALG_PPR, SMP_ITS); else TRW_DISK_WALK(ALG_DEEPWALK, SMP_ITS);
     }
+#undef TRW_DISK_WALK
 }
 
 uint32_t grid_for(uint64_t items, const DeviceInfo &di) {
@@ -506,13 +641,14 @@ trw_status trw_disk_graph_close(trw_disk_graph g) {
     return TRW_OK;
 }
 
-trw_status trw_disk_walk_bytes(trw_disk_graph g, const trw_walk_params *p, uint64_t nq, size_t *device_bytes,
-                               size_t *host_bytes) {
+
+trw_status trw_disk_walk_bytes(trw_disk_graph g, const trw_walk_params *p, uint64_t nq, uint32_t slots,
+                               size_t *device_bytes, size_t *host_bytes) {
     trw_status st = check_walk(g, p);
     if (st != TRW_OK) return st;
     if (!device_bytes || !host_bytes) return dfail(TRW_E_INVALID, "device_bytes / host_bytes is NULL");
     if (nq >= (uint64_t(1) << 32)) return dfail(TRW_E_INVALID, "nq must be < 2^32");
-    const Layout L = layout(*g, *p, nq);
+    const Layout L = layout(*g, *p, nq, slots);
     *device_bytes = L.dev_total;
     *host_bytes = L.host_total;
     return TRW_OK;
@@ -520,8 +656,8 @@ trw_status trw_disk_walk_bytes(trw_disk_graph g, const trw_walk_params *p, uint6
 
 trw_status trw_disk_walk(trw_disk_graph g, const trw_walk_params *p, const int32_t *d_sources, uint64_t nq,
                          uint64_t qid_base, int32_t *d_paths, uint64_t path_stride, uint32_t *d_lengths,
-                         uint8_t *d_status, void *d_ws, size_t ws_bytes, void *h_pinned, size_t h_bytes,
-                         trw_disk_walk_stats *stats, trw_stream_t stream) {
+                         uint8_t *d_status, uint32_t slots, void *d_ws, size_t ws_bytes, void *h_pinned,
+                         size_t h_bytes, trw_disk_walk_stats *stats, trw_stream_t stream) {
     const uint64_t t_start = now_ns();
     trw_status st = check_walk(g, p);
     if (st != TRW_OK) return st;
@@ -534,7 +670,8 @@ trw_status trw_disk_walk(trw_disk_graph g, const trw_walk_params *p, const int32
     }
     if (!d_sources || !d_paths || !d_lengths || !d_status)
         return dfail(TRW_E_INVALID, "sources / paths / lengths / status is NULL");
-    const Layout L = layout(*g, *p, nq);
+    const uint32_t K = clamp_slots(*g, slots);
+    Layout L = layout(*g, *p, nq, K);
     if (!d_ws || ws_bytes < L.dev_total || (reinterpret_cast<uintptr_t>(d_ws) & 255))
         return dfail(TRW_E_INVALID, "workspace NULL, too small or not 256-byte aligned");
     if (!h_pinned || h_bytes < L.host_total || (reinterpret_cast<uintptr_t>(h_pinned) & 255))
@@ -546,12 +683,10 @@ trw_status trw_disk_walk(trw_disk_graph g, const trw_walk_params *p, const int32
     const uint32_t parts = (uint32_t)(g->vstart.size() - 1);
     const bool want_w = needs_weights(p->sampler, p->algo), want_l = p->algo == TRW_A_METAPATH;
     const DeviceInfo di = device_info();
+    L.S.base = D;
+    const SlotsDev &SD = L.S;
 
-    int32_t *d_rp = reinterpret_cast<int32_t *>(D + L.rp);
-    int32_t *d_col = reinterpret_cast<int32_t *>(D + L.col);
-    uint32_t *d_wgt = want_w ? reinterpret_cast<uint32_t *>(D + L.wgt) : nullptr;
-    uint8_t *d_lab = want_l ? reinterpret_cast<uint8_t *>(D + L.lab) : nullptr;
-    char *d_tab = D + L.table;
+    uint16_t *d_vslot = reinterpret_cast<uint16_t *>(D + L.vslot);
     DRec *lists[3] = {reinterpret_cast<DRec *>(D + L.lists[0]), reinterpret_cast<DRec *>(D + L.lists[1]),
                       reinterpret_cast<DRec *>(D + L.lists[2])};
     int32_t *d_vstart = reinterpret_cast<int32_t *>(D + L.vstart);
@@ -560,15 +695,17 @@ trw_status trw_disk_walk(trw_disk_graph g, const trw_walk_params *p, const int32
     uint32_t *d_new_off = reinterpret_cast<uint32_t *>(D + L.new_off);
     uint32_t *d_old_off = reinterpret_cast<uint32_t *>(D + L.old_off);
     uint32_t *d_base = reinterpret_cast<uint32_t *>(D + L.base);
+    uint8_t *d_consumed = reinterpret_cast<uint8_t *>(D + L.consumed);
     uint32_t *d_count = reinterpret_cast<uint32_t *>(D + L.count);
     int32_t *h_rp = reinterpret_cast<int32_t *>(H + L.h_rp);
-    int32_t *h_col = reinterpret_cast<int32_t *>(H + L.h_col);
-    uint32_t *h_wgt = reinterpret_cast<uint32_t *>(H + L.h_wgt);
-    uint8_t *h_lab = reinterpret_cast<uint8_t *>(H + L.h_lab);
+    char *h_col = H + L.h_col;
+    char *h_wgt = H + L.h_wgt;
+    char *h_lab = H + L.h_lab;
     uint32_t *h_hist = reinterpret_cast<uint32_t *>(H + L.h_hist);   // parts counts, then the arrival count
     uint32_t *h_new_off = reinterpret_cast<uint32_t *>(H + L.h_new_off);
     uint32_t *h_old_off = reinterpret_cast<uint32_t *>(H + L.h_old_off);
     uint32_t *h_base = reinterpret_cast<uint32_t *>(H + L.h_base);
+    uint8_t *h_consumed = reinterpret_cast<uint8_t *>(H + L.h_consumed);
 
     WalkDev w{};
     w.max_len = p->max_len;
@@ -600,6 +737,11 @@ trw_status trw_disk_walk(trw_disk_graph g, const trw_walk_params *p, const int32
     auto fill = [&](uint32_t *ptr, uint32_t count, uint32_t v) {
         if (count) hipLaunchKernelGGL(k_disk_fill, dim3((count + 255) / 256), dim3(256), 0, s, ptr, count, v);
     };
+    auto set_slot = [&](int64_t lo, int64_t hi, uint16_t v) {
+        if (hi > lo)
+            hipLaunchKernelGGL(k_disk_set_slot, dim3(grid_for((uint64_t)(hi - lo), di)), dim3(256), 0, s, d_vslot, lo,
+                               hi, v);
+    };
     // histogram of the arrivals in lists[2] (count in d_count) into h_hist; waits
     auto read_arrivals = [&]() {
         fill(d_hist, parts, 0u);
@@ -609,14 +751,45 @@ trw_status trw_disk_walk(trw_disk_graph g, const trw_walk_params *p, const int32
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         return e == hipSuccess;
     };
+    // file bytes [foff, foff + bytes) to device memory through the pinned
+    // staging area, in chunks: each chunk's copy runs while the next is read
+    auto stream_in = [&](char *hbuf, char *dbuf, size_t bytes, uint64_t foff, bool check_cols, int64_t e0) -> bool {
+        for (size_t o = 0; o < bytes; o += kReadChunk) {
+            const size_t b = std::min(kReadChunk, bytes - o);
+            const uint64_t t0 = now_ns();
+            const bool ok = read_parallel(g->fd, hbuf + o, b, foff + o);
+            S.read_ns += now_ns() - t0;
+            if (!ok) {
+                set_error("cannot read the file");
+                return false;
+            }
+            S.bytes_read += b;
+            if (check_cols) {
+                const int32_t *c = reinterpret_cast<const int32_t *>(hbuf + o);
+                for (size_t i = 0; i < b / 4; ++i)
+                    if ((uint32_t)c[i] >= (uint32_t)g->n) {
+                        set_error("edge " + std::to_string(e0 + (int64_t)(o / 4 + i)) +
+                                  " has a destination outside [0, n)");
+                        return false;
+                    }
+            }
+            e = hipMemcpyAsync(dbuf + o, hbuf + o, b, hipMemcpyHostToDevice, s);
+            if (e != hipSuccess) {
+                set_error(std::string("partition copy: ") + hipGetErrorString(e));
+                return false;
+            }
+        }
+        return true;
+    };
 
-    // partition starts on the device (int32: n < 2^31)
+    // partition starts on the device (int32: n < 2^31); no vertex resident
     {
         std::vector<int32_t> vs(g->vstart.begin(), g->vstart.end());
         e = hipMemcpyAsync(d_vstart, vs.data(), 4 * vs.size(), hipMemcpyHostToDevice, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) return device_error("partition starts upload");
     }
+    set_slot(0, g->n, kNoSlot);
     // the sources wait in their partitions
     fill(d_count, 1, 0u);
     hipLaunchKernelGGL(k_disk_init, dim3(grid_for(nq, di)), dim3(256), 0, s, w, (int32_t)g->n, d_vstart, parts,
@@ -626,33 +799,37 @@ trw_status trw_disk_walk(trw_disk_graph g, const trw_walk_params *p, const int32
 
     // host copies of the waiting list's layout: per partition its count and start
     std::vector<uint64_t> counts(parts, 0), next(parts, 0), off(parts, 0);
+    std::vector<uint8_t> consumed(parts, 0);
+    // resident partitions: slot -> partition, partition -> slot, last round used
+    std::vector<int64_t> slot_part(K, -1), slot_used(K, -1);
+    std::vector<int32_t> part_slot(parts, -1);
     DRec *cur = lists[0], *spare = lists[1];
-    int64_t resident = -1;
-    uint32_t skip = 0xFFFFFFFFu;   // the partition just walked (its old records are consumed)
-    uint64_t old_total = 0;
+    uint64_t old_total = 0, round = 0, moved_max = nq * (uint64_t)p->max_len;
     for (;;) {
-        // regroup into `spare`: each partition's old records (none for `skip`),
-        // then its arrivals.  The pinned offset arrays are written here only,
-        // after the previous iteration's wait, and read by this one's copies.
-        uint64_t acc = 0;
+        // regroup into `spare`: each partition's old records (none for those
+        // just walked), then its arrivals.  The pinned arrays are written here
+        // only, after the previous round's wait, and read by this round's copies.
+        uint64_t acc = 0, old_kept = 0;
         for (uint32_t q = 0; q < parts; ++q) {
-            const uint64_t kept = q == skip ? 0 : counts[q];
+            const uint64_t kept = consumed[q] ? 0 : counts[q];
+            old_kept += kept;
             next[q] = kept + h_hist[q];
             h_old_off[q] = (uint32_t)off[q];
             h_new_off[q] = (uint32_t)acc;
             h_base[q] = (uint32_t)(acc + kept);
+            h_consumed[q] = consumed[q];
             acc += next[q];
         }
         const uint64_t waiting = acc;
-        const uint64_t old_kept = old_total - (skip == 0xFFFFFFFFu ? 0 : counts[skip]);
         e = hipMemcpyAsync(d_new_off, h_new_off, 4 * (size_t)parts, hipMemcpyHostToDevice, s);
         if (e == hipSuccess) e = hipMemcpyAsync(d_base, h_base, 4 * (size_t)parts, hipMemcpyHostToDevice, s);
         if (e == hipSuccess && old_kept > 0)
             e = hipMemcpyAsync(d_old_off, h_old_off, 4 * (size_t)parts, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess && old_kept > 0) e = hipMemcpyAsync(d_consumed, h_consumed, parts, hipMemcpyHostToDevice, s);
         if (e != hipSuccess) return device_error("offsets upload");
         if (old_kept > 0)
             hipLaunchKernelGGL(k_disk_move_old, dim3(grid_for(old_total, di)), dim3(256), 0, s, cur,
-                               (uint32_t)old_total, skip, d_old_off, d_new_off, spare);
+                               (uint32_t)old_total, d_consumed, d_old_off, d_new_off, spare);
         fill(d_cursor, parts, 0u);
         hipLaunchKernelGGL(k_disk_place_new, dim3(grid_for(h_hist[parts], di)), dim3(256), 0, s, lists[2], d_count,
                            d_base, d_cursor, spare);
@@ -663,92 +840,87 @@ trw_status trw_disk_walk(trw_disk_graph g, const trw_walk_params *p, const int32
         for (uint32_t q = 0; q < parts; ++q) off[q] = h_new_off[q];
         old_total = waiting;
         if (waiting == 0) break;
+        // Each round moves every walker it runs at least once or ends it, so
+        // there are at most nq * max_len rounds.
+        if (++round > moved_max) return host_error("partition walks made no progress");
 
-        // the partition with the most waiting queries (the lowest index among equals)
-        uint32_t pbest = 0;
-        for (uint32_t q = 1; q < parts; ++q)
-            if (counts[q] > counts[pbest]) pbest = q;
-        const int64_t v0 = g->vstart[pbest], v1 = g->vstart[pbest + 1];
-        const int64_t e0 = g->row_ptr[v0], e1 = g->row_ptr[v1];
-        const int64_t mp = e1 - e0;
-        GraphDev view{d_rp, d_col, d_wgt, d_lab, (int32_t)g->n, (int32_t)mp, 0};
-        TableDev t{};
-        if (p->algo != TRW_A_METAPATH && p->sampler == TRW_S_ALIAS) {
-            t.alias = reinterpret_cast<const uint4 *>(d_tab);
-        } else if (p->algo != TRW_A_METAPATH && p->sampler == TRW_S_REJ) {
-            t.rej = reinterpret_cast<const uint4 *>(d_tab);
-            t.pmax = reinterpret_cast<const uint32_t *>(d_tab + rej_records_bytes(mp));
-        } else if (p->algo != TRW_A_METAPATH && p->sampler == TRW_S_ITS) {
-            t.prefix = reinterpret_cast<const uint64_t *>(d_tab);
-            t.its_next = reinterpret_cast<const uint4 *>(d_tab + its_prefix_bytes(mp));
-            t.its_w = reinterpret_cast<const uint64_t *>(d_tab + its_prefix_bytes(mp) + its_next_bytes(mp));
-        }
-        if (resident != (int64_t)pbest) {
-            // read the range's rows and edges, copy them, build its table
-            const uint64_t t0 = now_ns();
-            for (int64_t v = v0; v <= v1; ++v) h_rp[v - v0] = (int32_t)(g->row_ptr[v] - e0);
-            bool ok = mp == 0 || read_at(g->fd, h_col, 4 * (size_t)mp, g->off_col + 4 * (uint64_t)e0);
-            if (ok && want_w && mp > 0) ok = read_at(g->fd, h_wgt, 4 * (size_t)mp, g->off_weight + 4 * (uint64_t)e0);
-            if (ok && want_l && mp > 0) ok = read_at(g->fd, h_lab, (size_t)mp, g->off_label + (uint64_t)e0);
-            S.read_ns += now_ns() - t0;
-            if (!ok) return host_error("cannot read partition " + std::to_string(pbest) + " of the file");
-            S.bytes_read += (uint64_t)mp * (4 + (want_w ? 4 : 0) + (want_l ? 1 : 0));
-            if (!g->checked[pbest]) {
-                for (int64_t i = 0; i < mp; ++i)
-                    if ((uint32_t)h_col[i] >= (uint32_t)g->n)
-                        return host_error("edge " + std::to_string(e0 + i) + " has a destination outside [0, n)");
-                g->checked[pbest] = 1;
+        // run the resident partitions that hold waiting queries; if none does,
+        // load the partition holding the most (the lowest index among equals)
+        // into a free slot or the one used longest ago
+        std::vector<uint32_t> run;
+        for (uint32_t k = 0; k < K; ++k)
+            if (slot_part[k] >= 0 && counts[slot_part[k]] > 0) run.push_back((uint32_t)slot_part[k]);
+        if (run.empty()) {
+            uint32_t pbest = 0;
+            for (uint32_t q = 1; q < parts; ++q)
+                if (counts[q] > counts[pbest]) pbest = q;
+            uint32_t slot = 0;
+            for (uint32_t k = 1; k < K; ++k)
+                if (slot_used[k] < slot_used[slot]) slot = k;
+            const int64_t v0 = g->vstart[pbest], v1 = g->vstart[pbest + 1];
+            const int64_t e0 = g->row_ptr[v0], e1 = g->row_ptr[v1];
+            const int64_t mp = e1 - e0;
+            if (slot_part[slot] >= 0) {
+                const int64_t old = slot_part[slot];
+                set_slot(g->vstart[old], g->vstart[old + 1], kNoSlot);
+                part_slot[old] = -1;
+                slot_part[slot] = -1;
             }
-            resident = -1;
+            char *b = D + (uint64_t)slot * SD.stride;
+            int32_t *d_rp = reinterpret_cast<int32_t *>(b + SD.o_rp);
+            char *d_tab = b + SD.o_tab;
+            // rows of the range, then its edges
+            for (int64_t v = v0; v <= v1; ++v) h_rp[v - v0] = (int32_t)(g->row_ptr[v] - e0);
             hipLaunchKernelGGL(k_disk_rows, dim3(grid_for((uint64_t)g->n + 1, di)), dim3(256), 0, s, d_rp, g->n, v0,
                                v1, (int32_t)mp);
             e = hipMemcpyAsync(d_rp + v0, h_rp, 4 * (size_t)(v1 - v0 + 1), hipMemcpyHostToDevice, s);
-            if (e == hipSuccess && mp > 0) e = hipMemcpyAsync(d_col, h_col, 4 * (size_t)mp, hipMemcpyHostToDevice, s);
-            if (e == hipSuccess && want_w && mp > 0)
-                e = hipMemcpyAsync(d_wgt, h_wgt, 4 * (size_t)mp, hipMemcpyHostToDevice, s);
-            if (e == hipSuccess && want_l && mp > 0)
-                e = hipMemcpyAsync(d_lab, h_lab, (size_t)mp, hipMemcpyHostToDevice, s);
             if (e != hipSuccess) return device_error("partition copy");
+            const bool check = !g->checked[pbest];
+            bool ok = stream_in(h_col, b + SD.o_col, 4 * (size_t)mp, g->off_col + 4 * (uint64_t)e0, check, e0);
+            if (ok && want_w)
+                ok = stream_in(h_wgt, b + SD.o_wgt, 4 * (size_t)mp, g->off_weight + 4 * (uint64_t)e0, false, e0);
+            if (ok && want_l) ok = stream_in(h_lab, b + SD.o_lab, (size_t)mp, g->off_label + (uint64_t)e0, false, e0);
+            if (!ok) {
+                if (e != hipSuccess) return device_error("partition copy");
+                (void)hipStreamSynchronize(s);
+                return TRW_E_INVALID;   // the message is set
+            }
+            g->checked[pbest] = 1;
             if (mp > 0 && p->algo != TRW_A_METAPATH) {
+                GraphDev view{d_rp, reinterpret_cast<const int32_t *>(b + SD.o_col),
+                              want_w ? reinterpret_cast<const uint32_t *>(b + SD.o_wgt) : nullptr, nullptr,
+                              (int32_t)g->n, (int32_t)mp, 0};
                 if (p->sampler == TRW_S_ALIAS)
                     e = launch_alias_build(view, reinterpret_cast<uint4 *>(d_tab), s);
                 else if (p->sampler == TRW_S_ITS)
                     e = launch_its_build(view, reinterpret_cast<uint64_t *>(d_tab),
-                                         reinterpret_cast<uint4 *>(d_tab + its_prefix_bytes(mp)),
-                                         reinterpret_cast<uint64_t *>(d_tab + its_prefix_bytes(mp) + its_next_bytes(mp)),
-                                         s);
+                                         reinterpret_cast<uint4 *>(d_tab + SD.tab_o1),
+                                         reinterpret_cast<uint64_t *>(d_tab + SD.tab_o2), s);
                 else if (p->sampler == TRW_S_REJ)
                     e = launch_rej_build(view, reinterpret_cast<uint4 *>(d_tab),
-                                         reinterpret_cast<uint32_t *>(d_tab + rej_records_bytes(mp)), s);
+                                         reinterpret_cast<uint32_t *>(d_tab + SD.tab_o1), s);
                 if (e != hipSuccess) return device_error("table build launch");
             }
-            resident = pbest;
+            set_slot(v0, v1, (uint16_t)slot);
+            slot_part[slot] = pbest;
+            part_slot[pbest] = (int32_t)slot;
             ++S.loads;
+            run.push_back(pbest);
         }
-        // walk every query waiting there; those that leave arrive in lists[2].
-        // Each walker of a run moves at least once or ends, so there are at most
-        // nq * max_len runs with work.
-        if (++S.runs > nq * (uint64_t)p->max_len) return host_error("partition walks made no progress");
+        // walk every query waiting there; those that step into a partition
+        // that is not resident arrive in lists[2]
+        ++S.runs;
         fill(d_count, 1, 0u);
-        const uint32_t n_in = (uint32_t)counts[pbest];
-        const DRec *in = cur + off[pbest];
-        const uint32_t blocks = grid_for(n_in, di);
-        switch (p->algo) {
-            case TRW_A_DEEPWALK:
-                dispatch_walk<ALG_DEEPWALK>(p->sampler, view, t, w, (int32_t)v0, (int32_t)v1, in, n_in, d_vstart, parts,
-                                            lists[2], d_count, blocks, s);
-                break;
-            case TRW_A_PPR:
-                dispatch_walk<ALG_PPR>(p->sampler, view, t, w, (int32_t)v0, (int32_t)v1, in, n_in, d_vstart, parts,
-                                       lists[2], d_count, blocks, s);
-                break;
-            default:
-                launch_disk_walk<ALG_METAPATH, SMP_ITS>(view, t, w, (int32_t)v0, (int32_t)v1, in, n_in, d_vstart, parts,
-                                                        lists[2], d_count, blocks, s);
+        std::fill(consumed.begin(), consumed.end(), 0);
+        for (uint32_t q : run) {
+            const uint32_t n_in = (uint32_t)counts[q];
+            dispatch_walk(p->algo, p->sampler, SD, w, d_vslot, cur + off[q], n_in, d_vstart, parts, lists[2], d_count,
+                          grid_for(n_in, di), s);
+            consumed[q] = 1;
+            slot_used[part_slot[q]] = (int64_t)round;
         }
         e = hipGetLastError();
         if (e != hipSuccess || !read_arrivals()) return device_error("partition walk");
-        skip = pbest;
     }
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) return device_error("finish");

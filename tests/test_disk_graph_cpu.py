@@ -172,14 +172,22 @@ def test_walk_argument_checks(tmp_path):
     # the pinned buffer holds the largest partition: its row offsets, destinations and labels
     biggest = max(Gw.partition(i)[3] - Gw.partition(i)[2] for i in range(Gw.parts))
     assert h >= 5 * biggest
+    # device bytes grow by one slot's worth per resident partition, up to the partition count
+    one = Gw.walk_bytes(trw.make_params("deepwalk", "alias", 10, 1), 10, 1)[0]
+    two = Gw.walk_bytes(trw.make_params("deepwalk", "alias", 10, 1), 10, 2)[0]
+    slot = two - one
+    assert slot >= 4 * (g.n + 1) + (4 + 4 + 32) * biggest
+    assert Gw.walk_bytes(trw.make_params("deepwalk", "alias", 10, 1), 10, Gw.parts)[0] == one + (Gw.parts - 1) * slot
+    assert Gw.walk_bytes(trw.make_params("deepwalk", "alias", 10, 1), 10, 10 ** 6)[0] == one + (Gw.parts - 1) * slot
+    assert Gw.walk_bytes(trw.make_params("deepwalk", "alias", 10, 1), 10, 0)[0] == one
     # nq = 0 returns at once (no device work), with zero stats
     stats = _abi.trw_disk_walk_stats()
     p = trw.make_params("deepwalk", "naive", 10, 1)
-    assert _abi.trw_disk_walk(Gp.handle, ctypes.byref(p), None, 0, 0, None, 11, None, None, None, 0, None, 0,
+    assert _abi.trw_disk_walk(Gp.handle, ctypes.byref(p), None, 0, 0, None, 11, None, None, 1, None, 0, None, 0,
                               ctypes.byref(stats), None) == 0
     assert stats.as_dict() == {"runs": 0, "loads": 0, "bytes_read": 0, "read_ns": 0, "total_ns": 0}
     # path_stride below max_len + 1
-    assert _abi.trw_disk_walk(Gp.handle, ctypes.byref(p), None, 0, 0, None, 10, None, None, None, 0, None, 0,
+    assert _abi.trw_disk_walk(Gp.handle, ctypes.byref(p), None, 0, 0, None, 10, None, None, 1, None, 0, None, 0,
                               None, None) == _abi.TRW_E_INVALID
     Gw.close()
     Gp.close()

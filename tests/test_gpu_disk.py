@@ -1,7 +1,8 @@
-"""Walks over a graph kept in a file, one vertex-range partition on the device at
-a time (trw_disk_walk): every query's path, length and status equal the
-oracle's on the whole graph, for every supported (algorithm, sampler), with
-many partitions, hub rows alone in theirs, and one partition."""
+"""Walks over a graph kept in a file, vertex-range partitions loaded onto the
+device as the walks need them (trw_disk_walk): every query's path, length and
+status equal the oracle's on the whole graph, for every supported (algorithm,
+sampler), with many partitions, hub rows alone in theirs, one partition, and
+one, a few or all partitions resident at once."""
 import numpy as np
 import pytest
 import torch
@@ -71,26 +72,33 @@ def part_sizes(g):
     return {"sevenths": g.m // 7, "hubs_alone": int(deg.max()) // 2, "one": 0}
 
 
-@pytest.mark.parametrize("split", ["sevenths", "hubs_alone", "one"])
+@pytest.mark.parametrize("split,slots", [("sevenths", 1), ("sevenths", 3), ("sevenths", 99), ("hubs_alone", 1),
+                                         ("hubs_alone", 16), ("one", 1)])
 @pytest.mark.parametrize("algo,sampler,max_len", CASES)
-def test_disk_walk_equals_oracle(graph, algo, sampler, max_len, split):
+def test_disk_walk_equals_oracle(graph, algo, sampler, max_len, split, slots):
     g, path = graph
     pe = part_sizes(g)[split]
     G = trw.DiskGraph(path, pe)
     src = np.concatenate([synth.sources(3000, g.n, 41), np.array([-1, g.n], np.int32)]).astype(np.int32)
     p = params(algo, sampler, max_len, 1234)
-    log(f"  disk {algo}/{sampler} part_edges={pe} parts={G.parts} nq={len(src)}")
-    P, L, S, st = G.walk(p, torch.from_numpy(src).cuda(), qid_base=77)
+    log(f"  disk {algo}/{sampler} part_edges={pe} parts={G.parts} slots={slots} nq={len(src)}")
+    P, L, S, st = G.walk(p, torch.from_numpy(src).cuda(), qid_base=77, slots=slots)
     torch.cuda.synchronize()
     ref = oracle_walk(g, algo, sampler, max_len, 1234, src, 77, int(p.stop_q32))
     same_as(ref, P, L, S, max_len)
     assert 1 <= st["loads"] <= st["runs"]
     per_edge = 4 + (4 if sampler in ("alias", "its", "rej") and algo != "metapath" else 0) + \
         (1 if algo == "metapath" else 0)
+    sizes = [G.partition(i)[3] - G.partition(i)[2] for i in range(G.parts)]
+    if slots == 1:
+        assert st["loads"] == st["runs"]          # the partition just walked holds no waiting query
+    if slots >= G.parts:
+        # nothing is evicted: each partition is read at most once
+        assert st["loads"] <= G.parts and st["bytes_read"] <= g.m * per_edge
     if G.parts == 1:
         assert st["runs"] == 1 and st["loads"] == 1 and st["bytes_read"] == g.m * per_edge
     else:
-        assert st["bytes_read"] >= per_edge * min(G.partition(i)[3] - G.partition(i)[2] for i in range(G.parts))
+        assert st["bytes_read"] >= per_edge * min(sizes)
     G.close()
 
 
@@ -103,7 +111,7 @@ def test_disk_walk_equals_in_memory_walk(graph):
     src = synth.sources(20000, g.n, 5)
     p = params("deepwalk", "alias", 80, 99)
     qid_base = (1 << 40) + 5
-    P, L, S, st = G.walk(p, torch.from_numpy(src).cuda(), qid_base=qid_base)
+    P, L, S, st = G.walk(p, torch.from_numpy(src).cuda(), qid_base=qid_base, slots=2)
     P2, L2, S2 = trw.walk(Gm, alias, p, torch.from_numpy(src).cuda(), qid_base=qid_base)
     torch.cuda.synchronize()
     assert torch.equal(L, L2) and torch.equal(S, S2)
@@ -121,7 +129,7 @@ def test_disk_walk_edge_cases(graph, tmp_path):
     for src, max_len, stride in ((np.array([5], np.int32), 1, None), (np.array([-7, g.n, 1 << 30], np.int32), 5, None),
                                  (synth.sources(513, g.n, 8), 7, 19)):
         p = params("ppr", "naive", max_len, 3)
-        P, L, S, _ = G.walk(p, torch.from_numpy(src).cuda(), stride=stride)
+        P, L, S, _ = G.walk(p, torch.from_numpy(src).cuda(), stride=stride, slots=2)
         torch.cuda.synchronize()
         ref = oracle_walk(g, "ppr", "naive", max_len, 3, src, 0, int(p.stop_q32))
         same_as(ref, P, L, S, max_len)
