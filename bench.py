@@ -14,8 +14,10 @@ at 0.7x the saturated request rate.
 
 The four batch workloads (deepwalk-rmat12, ppr-rmat22, node2vec-rmat24,
 metapath-rmat24) run first and are reported as nested objects, each with its
-own roofline, schedules and oracle baseline.  ``--workload NAME`` runs one
-workload alone and prints its own line.
+own roofline, schedules and oracle baseline.  Then ppr-rmat22 is walked from
+a CSR file (the graph kept on disk, partitions loaded as the walks need
+them) and reported as ``disk_graph``.  ``--workload NAME`` runs one workload
+alone and prints its own line.
 
 Metric: walk steps (moves) per second of walk time, graph and tables
 resident in HBM (the paper's throughput: steps of all queries / execution
@@ -143,6 +145,7 @@ def main():
     ap.add_argument("--nq", type=int, default=0, help="override the number of queries (throughput-vs-batch sweeps)")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="headline only, without the nested batch workloads")
+    ap.add_argument("--no-disk", action="store_true", help="without the walk from a graph file")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-probe", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle CPU time (headline)")
@@ -195,11 +198,82 @@ def main():
             nested[name] = bench_batch(args, synth.WORKLOADS[name], ctx, nested=True)
             ctx.release()
             log(f"nested {name}: {time.time() - t0:.1f}s")
+    disk = None
+    if not args.no_batch and not args.no_disk and not args.profile_pass:
+        t0 = time.time()
+        disk = bench_disk(ctx)
+        ctx.release()
+        log(f"disk graph: {time.time() - t0:.1f}s")
     out = bench_served(args, synth.WORKLOADS[SERVED_WORKLOAD], ctx)
     if out is None:
         return
     out["batch_workloads"] = nested
+    if disk is not None:
+        out["disk_graph"] = disk
     print(json.dumps(out), flush=True)
+
+
+def bench_disk(ctx):
+    """ppr-rmat22's batch walked from a CSR file (trw_disk_walk): as one partition, and as
+    17 vertex-range partitions with 16 resident at once; every output compared with the
+    in-memory walk.  The file is written just before, so its reads come from the page
+    cache."""
+    import tempfile
+
+    np, torch, synth, trw = ctx.np, ctx.torch, ctx.synth, ctx.trw
+    wl = synth.WORKLOADS["ppr-rmat22"]
+    g = synth.make_graph(wl)
+    path = os.path.join(tempfile.gettempdir(), f"trw_bench_{os.getpid()}.csr")
+    try:
+        trw.write_disk_graph(path, g.row_ptr.astype(np.int64), g.col, g.weight)
+        file_bytes = os.path.getsize(path)
+        src = torch.from_numpy(synth.make_sources(wl, g)).to(ctx.dev)
+        nq = int(src.numel())
+        p = trw.make_params("ppr", "alias", wl.max_len, wl.walk_seed, stop_q32=trw.stop_threshold(wl.stop_prob))
+        G = trw.Graph(g.row_ptr, g.col, g.weight, device="cuda:0")
+        alias = G.table("alias")
+        bufs = trw.WalkBuffers(G, p, nq)
+        trw.walk(G, alias, p, src, bufs=bufs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        P2, L2, S2 = trw.walk(G, alias, p, src, bufs=bufs)
+        torch.cuda.synchronize()
+        mem_s = time.perf_counter() - t0
+        moves = int(L2.to(torch.int64).sum())
+        runs = []
+        for parts, slots in ((1, 1), (16, 16)):
+            D = trw.DiskGraph(path, 0 if parts == 1 else g.m // parts)
+            D.walk(p, src[:1000], slots=D.parts)     # every partition's destinations checked once, untimed
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            P, L, S, st = D.walk(p, src, slots=slots)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            same = bool(torch.equal(L, L2) and torch.equal(S, S2))
+            cols = torch.arange(wl.max_len + 1, device=P.device)[None, :]
+            for a in range(0, nq, 1 << 20):
+                if not same:
+                    break
+                b = min(nq, a + (1 << 20))
+                keep = cols <= L[a:b, None]
+                same = bool(torch.equal(torch.where(keep, P[a:b], 0), torch.where(keep, P2[a:b, :wl.max_len + 1], 0)))
+            runs.append({"partitions": D.parts, "slots": slots, "ms": round(dt * 1e3, 2), "steps_per_s": moves / dt,
+                         "vs_in_memory": (moves / dt) / (moves / mem_s), "same_as_in_memory": same,
+                         "rounds": st["runs"], "loads": st["loads"], "bytes_read": st["bytes_read"],
+                         "read_GBps": st["bytes_read"] / max(st["read_ns"], 1)})
+            log(f"disk graph: {D.parts} partitions, {slots} resident: {dt * 1e3:.1f} ms, {st['loads']} loads, "
+                f"{st['bytes_read'] / 1e9:.2f} GB read, same as in memory: {same}")
+            del P, L, S
+            D.close()
+        del P2, L2, S2, bufs
+        G.close()
+        return {"workload": "ppr-rmat22 from a CSR file", "algo": "ppr", "sampler": "alias", "nq": nq,
+                "moves": moves, "file_bytes": file_bytes, "in_memory_ms": round(mem_s * 1e3, 3),
+                "in_memory_steps_per_s": moves / mem_s, "runs": runs,
+                "note": "file in the page cache (written just before); partitions' ALIAS tables built at each load"}
+    finally:
+        if os.path.exists(path):
+            os.remove(path)
 
 
 def bench_batch(args, wl, ctx, nested=False):
