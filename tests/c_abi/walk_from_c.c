@@ -2,15 +2,16 @@
  * The C ABI driven from plain C (no Python, no torch): device buffers from
  * hipMalloc, a CSR graph, its ALIAS table, a PPR walk, the end-vertex counts
  * and their top 10; the same walk streamed to a file by the library's file
- * sink; and a server given six requests of three kinds (one with host
- * buffers).  Test input and output are raw little-endian files in one
+ * sink; a server given six requests of three kinds (one with host
+ * buffers); and the walk again from the graph written to a CSR file.  Test input and output are raw little-endian files in one
  * directory:
  *   in : meta.txt ("n m nq max_len seed stop_q32"), row_ptr, col, weight, sources
  *   out: lengths, status, paths (nq rows of max_len + 1 int32), counts, top_ids, top_vals,
  *        stream.bin (trw_chunk_to_fd records), srv<i>_{paths,lengths,status} for request i
  *        (sources [i nq / 6, (i + 1) nq / 6), qid_base its first index; kinds PPR ALIAS,
  *        DeepWalk ALIAS, Node2Vec O-REJ in turn; max_len, 40 and 40; path_stride
- *        max_len + 1; request 3 with host buffers)
+ *        max_len + 1; request 3 with host buffers), graph.csr (the graph as a CSR file) and
+ *        disk_{paths,lengths,status} (the PPR walk from that file, 2 of its partitions resident)
  * Exit status 0 on success; any failing call prints trw_last_error().
  */
 #define __HIP_PLATFORM_AMD__
@@ -263,8 +264,47 @@ int main(int argc, char **argv) {
         HIP(hipFree(d_eidx));
     }
 
+    /* The graph written to a CSR file and walked from it: partitions of m / 5
+     * edges, two resident at once. */
+    {
+        int64_t *rp64 = malloc(sizeof(int64_t) * (size_t)(n + 1));
+        for (long long v = 0; v <= n; ++v) rp64[v] = h_rp[v];
+        snprintf(path, sizeof(path), "%s/graph.csr", dir);
+        TRW(trw_disk_graph_write(path, n, m, rp64, h_col, h_w, NULL));
+        free(rp64);
+        trw_disk_graph dg;
+        TRW(trw_disk_graph_open(path, (uint64_t)(m / 5), &dg));
+        uint32_t parts = 0;
+        TRW(trw_disk_graph_info(dg, NULL, NULL, NULL, &parts));
+        size_t ddb = 0, dhb = 0;
+        TRW(trw_disk_walk_bytes(dg, &p, (uint64_t)nq, 2, &ddb, &dhb));
+        void *d_dws = dalloc(ddb);
+        void *h_dpin = NULL;
+        HIP(hipHostMalloc(&h_dpin, dhb, hipHostMallocDefault));
+        int32_t *d_dpaths = dalloc(sizeof(int32_t) * (size_t)nq * stride);
+        uint32_t *d_dlen = dalloc(sizeof(uint32_t) * (size_t)nq);
+        uint8_t *d_dst = dalloc((size_t)nq);
+        trw_disk_walk_stats ds;
+        TRW(trw_disk_walk(dg, &p, d_src, (uint64_t)nq, 0, d_dpaths, stride, d_dlen, d_dst, 2, d_dws, ddb, h_dpin, dhb,
+                          &ds, NULL));
+        HIP(hipMemcpy(h_paths, d_dpaths, sizeof(int32_t) * (size_t)nq * stride, hipMemcpyDeviceToHost));
+        HIP(hipMemcpy(h_len, d_dlen, sizeof(uint32_t) * (size_t)nq, hipMemcpyDeviceToHost));
+        HIP(hipMemcpy(h_st, d_dst, (size_t)nq, hipMemcpyDeviceToHost));
+        write_file("disk_paths", h_paths, sizeof(int32_t) * (size_t)nq * stride);
+        write_file("disk_lengths", h_len, sizeof(uint32_t) * (size_t)nq);
+        write_file("disk_status", h_st, (size_t)nq);
+        printf("disk walk: %u partitions, %llu rounds, %llu loads, %llu bytes read\n", parts,
+               (unsigned long long)ds.runs, (unsigned long long)ds.loads, (unsigned long long)ds.bytes_read);
+        TRW(trw_disk_graph_close(dg));
+        HIP(hipHostFree(h_dpin));
+        HIP(hipFree(d_dws));
+        HIP(hipFree(d_dpaths));
+        HIP(hipFree(d_dlen));
+        HIP(hipFree(d_dst));
+    }
+
     TRW(trw_table_destroy(alias));
     TRW(trw_graph_destroy(g));
-    printf("walked %lld queries from C (batch, streamed to disk, served)\n", nq);
+    printf("walked %lld queries from C (batch, streamed to disk, served, from a graph file)\n", nq);
     return 0;
 }

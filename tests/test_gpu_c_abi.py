@@ -1,7 +1,7 @@
 """The C ABI driven from a plain C program (tests/c_abi/walk_from_c.c: hipMalloc,
 graph, ALIAS table, PPR walk, end counts, top-k, the walk streamed to a file,
-a server with device and host requests; no Python in the process), its outputs
-compared with the oracle."""
+a server with device and host requests, the walk from the graph written to a
+CSR file; no Python in the process), its outputs compared with the oracle."""
 import os
 import subprocess
 import sys
@@ -33,6 +33,7 @@ def test_c_program_matches_oracle(tmp_path):
     r = subprocess.run([BIN, str(tmp_path)], capture_output=True, text=True, timeout=120)
     sys.stdout.write(r.stdout)
     assert r.returncode == 0, r.stderr
+    printed = r.stdout
     nq, stride = len(src), max_len + 1
     L = np.fromfile(tmp_path / "lengths", np.uint32)
     S = np.fromfile(tmp_path / "status", np.uint8)
@@ -87,3 +88,12 @@ def test_c_program_matches_oracle(tmp_path):
         m = (np.arange(ml + 1)[None, :] <= r.lengths[:, None]) & ok[:, None]
         assert np.array_equal(Ps[m], r.paths[m]), i
     assert (np.fromfile(tmp_path / "srv5_status", np.uint8)[-2:] == oracle.ST_BAD_SOURCE).all()
+
+    # the same PPR walk from the graph written to a CSR file, 2 partitions resident
+    Ld = np.fromfile(tmp_path / "disk_lengths", np.uint32)
+    Sd = np.fromfile(tmp_path / "disk_status", np.uint8)
+    Pd = np.fromfile(tmp_path / "disk_paths", np.int32).reshape(nq, stride)
+    assert np.array_equal(Ld, ref.lengths) and np.array_equal(Sd, ref.status)
+    assert np.array_equal(Pd[mask], ref.paths[mask])
+    parts = trw.DiskGraph(str(tmp_path / "graph.csr"), g.m // 5).parts
+    assert parts >= 5 and f"disk walk: {parts} partitions" in printed
