@@ -146,6 +146,7 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="headline only, without the nested batch workloads")
     ap.add_argument("--no-disk", action="store_true", help="without the walk from a graph file")
+    ap.add_argument("--disk-only", action="store_true", help="only the walk from a graph file, as its own line")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-probe", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle CPU time (headline)")
@@ -184,6 +185,9 @@ def main():
         ctx.gather = probe_gather(trw, torch, ctx.dev, props.multi_processor_count)
         ctx.release()
 
+    if args.disk_only:
+        print(json.dumps(bench_disk(ctx)), flush=True)
+        return
     if args.workload:
         wl = synth.WORKLOADS[args.workload]
         out = bench_served(args, wl, ctx) if wl.algo == "mixed" else bench_batch(args, wl, ctx)

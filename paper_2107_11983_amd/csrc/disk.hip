@@ -15,9 +15,12 @@
 // A slot holds one partition [v0, v1) with edges [e0, e1): a row offset
 // array over all n + 1 vertices with offsets relative to e0 (0 below v0 and
 // e1 - e0 above v1, so rows outside the range are empty), the range's
-// destinations, weights and labels, and its table.  Destinations keep their
-// global ids; a per-vertex map gives the slot of each vertex's partition
-// (kNoSlot when it is not resident).
+// destinations, weights and labels, and its table, built for the range's
+// rows only.  Destinations keep their global ids; a per-vertex map gives the
+// slot of each vertex's partition (kNoSlot when it is not resident).  A table
+// record's copy of its destination's row or bound is right only for a
+// destination in the same range, so a move here reads the current vertex's
+// row offsets and bound itself.
 #include <hip/hip_runtime.h>
 
 #include <errno.h>
@@ -33,6 +36,7 @@
 #include <thread>
 #include <vector>
 
+#include "table_range.hpp"
 #include "walk_common.hpp"
 
 struct trw_disk_graph_s {
@@ -56,6 +60,7 @@ constexpr uint32_t kMaxSlots = 4096;
 constexpr uint16_t kNoSlot = 0xFFFF;
 constexpr size_t kReadChunk = size_t(64) << 20;   // file bytes per read (then copied while the next is read)
 constexpr size_t kReadPiece = size_t(8) << 20;    // bytes per reading thread
+constexpr uint32_t kLdsParts = 4096;              // partitions the regroup kernels count in LDS
 
 trw_status dfail(trw_status st, const std::string &m) {
     set_error(m);
@@ -231,14 +236,34 @@ __global__ void __launch_bounds__(256) k_disk_init(WalkDev a, int32_t n, const i
     }
 }
 
+// Arrivals per partition.  Up to kLdsParts partitions a workgroup counts its
+// share in LDS and adds each nonzero count to memory once (a batch's walkers
+// spread over few partitions would otherwise queue on few counters); beyond
+// that, lanes with the same partition share one atomic per wave.
 __global__ void __launch_bounds__(256) k_disk_hist(const DRec *__restrict__ in, const uint32_t *count,
-                                                   uint32_t *hist) {
+                                                   uint32_t *hist, uint32_t parts) {
+    extern __shared__ uint32_t sh_cnt[];
     const uint32_t n = *count;
     const uint32_t stride = gridDim.x * blockDim.x;
+    const bool lds = parts <= kLdsParts;
+    if (lds) {
+        for (uint32_t q = threadIdx.x; q < parts; q += blockDim.x) sh_cnt[q] = 0;
+        __syncthreads();
+    }
     for (uint32_t base = 0; base < n; base += stride) {
         const uint32_t i = base + blockIdx.x * blockDim.x + threadIdx.x;
         const bool act = i < n;
-        (void)wave_add_by_key(hist, act ? in[i].part : 0u, act);
+        const uint32_t part = act ? in[i].part : 0u;
+        if (lds) {
+            if (act) atomicAdd(&sh_cnt[part], 1u);
+        } else {
+            (void)wave_add_by_key(hist, part, act);
+        }
+    }
+    if (lds) {
+        __syncthreads();
+        for (uint32_t q = threadIdx.x; q < parts; q += blockDim.x)
+            if (sh_cnt[q]) atomicAdd(&hist[q], sh_cnt[q]);
     }
 }
 
@@ -255,11 +280,34 @@ __global__ void k_disk_move_old(const DRec *__restrict__ in, uint32_t n_in, cons
     }
 }
 
+// Arrivals to their places after base[part].  Up to kLdsParts partitions a
+// workgroup counts its share in LDS, reserves one range per partition with
+// one atomic, and places its records by LDS ranks; beyond that, per wave as
+// in k_disk_hist.  Launched with the same grid as the count it follows.
 __global__ void __launch_bounds__(256) k_disk_place_new(const DRec *__restrict__ in, const uint32_t *count,
                                                         const uint32_t *__restrict__ base, uint32_t *cursor,
-                                                        DRec *__restrict__ out) {
+                                                        DRec *__restrict__ out, uint32_t parts) {
+    extern __shared__ uint32_t sh_place[];   // counts[parts], then starts[parts]
     const uint32_t n = *count;
     const uint32_t stride = gridDim.x * blockDim.x;
+    if (parts <= kLdsParts) {
+        uint32_t *cnt = sh_place, *start = sh_place + parts;
+        for (uint32_t q = threadIdx.x; q < parts; q += blockDim.x) cnt[q] = 0;
+        __syncthreads();
+        for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) atomicAdd(&cnt[in[i].part], 1u);
+        __syncthreads();
+        for (uint32_t q = threadIdx.x; q < parts; q += blockDim.x) {
+            const uint32_t c = cnt[q];
+            start[q] = c ? atomicAdd(&cursor[q], c) : 0u;
+            cnt[q] = 0;
+        }
+        __syncthreads();
+        for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+            const DRec r = in[i];
+            out[base[r.part] + start[r.part] + atomicAdd(&cnt[r.part], 1u)] = r;
+        }
+        return;
+    }
     for (uint32_t b = 0; b < n; b += stride) {
         const uint32_t i = b + blockIdx.x * blockDim.x + threadIdx.x;
         const bool act = i < n;
@@ -683,6 +731,7 @@ trw_status trw_disk_walk(trw_disk_graph g, const trw_walk_params *p, const int32
     const uint32_t parts = (uint32_t)(g->vstart.size() - 1);
     const bool want_w = needs_weights(p->sampler, p->algo), want_l = p->algo == TRW_A_METAPATH;
     const DeviceInfo di = device_info();
+    const size_t lds_hist = parts <= kLdsParts ? 4 * (size_t)parts : 0;   // the regroup kernels' LDS counts
     L.S.base = D;
     const SlotsDev &SD = L.S;
 
@@ -745,7 +794,8 @@ trw_status trw_disk_walk(trw_disk_graph g, const trw_walk_params *p, const int32
     // histogram of the arrivals in lists[2] (count in d_count) into h_hist; waits
     auto read_arrivals = [&]() {
         fill(d_hist, parts, 0u);
-        hipLaunchKernelGGL(k_disk_hist, dim3(grid_for(nq, di)), dim3(256), 0, s, lists[2], d_count, d_hist);
+        hipLaunchKernelGGL(k_disk_hist, dim3(grid_for(nq, di)), dim3(256), lds_hist, s, lists[2], d_count, d_hist,
+                           parts);
         e = hipMemcpyAsync(h_hist, d_hist, 4 * (size_t)parts, hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipMemcpyAsync(h_hist + parts, d_count, 4, hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -831,8 +881,8 @@ trw_status trw_disk_walk(trw_disk_graph g, const trw_walk_params *p, const int32
             hipLaunchKernelGGL(k_disk_move_old, dim3(grid_for(old_total, di)), dim3(256), 0, s, cur,
                                (uint32_t)old_total, d_consumed, d_old_off, d_new_off, spare);
         fill(d_cursor, parts, 0u);
-        hipLaunchKernelGGL(k_disk_place_new, dim3(grid_for(h_hist[parts], di)), dim3(256), 0, s, lists[2], d_count,
-                           d_base, d_cursor, spare);
+        hipLaunchKernelGGL(k_disk_place_new, dim3(grid_for(h_hist[parts], di)), dim3(256), 2 * lds_hist, s, lists[2],
+                           d_count, d_base, d_cursor, spare, parts);
         e = hipGetLastError();
         if (e != hipSuccess) return device_error("regroup launch");
         std::swap(cur, spare);
@@ -891,14 +941,14 @@ trw_status trw_disk_walk(trw_disk_graph g, const trw_walk_params *p, const int32
                               want_w ? reinterpret_cast<const uint32_t *>(b + SD.o_wgt) : nullptr, nullptr,
                               (int32_t)g->n, (int32_t)mp, 0};
                 if (p->sampler == TRW_S_ALIAS)
-                    e = launch_alias_build(view, reinterpret_cast<uint4 *>(d_tab), s);
+                    e = launch_alias_build_range(view, v0, v1, reinterpret_cast<uint4 *>(d_tab), s);
                 else if (p->sampler == TRW_S_ITS)
-                    e = launch_its_build(view, reinterpret_cast<uint64_t *>(d_tab),
-                                         reinterpret_cast<uint4 *>(d_tab + SD.tab_o1),
-                                         reinterpret_cast<uint64_t *>(d_tab + SD.tab_o2), s);
+                    e = launch_its_build_range(view, v0, v1, reinterpret_cast<uint64_t *>(d_tab),
+                                               reinterpret_cast<uint4 *>(d_tab + SD.tab_o1),
+                                               reinterpret_cast<uint64_t *>(d_tab + SD.tab_o2), s);
                 else if (p->sampler == TRW_S_REJ)
-                    e = launch_rej_build(view, reinterpret_cast<uint4 *>(d_tab),
-                                         reinterpret_cast<uint32_t *>(d_tab + SD.tab_o1), s);
+                    e = launch_rej_build_range(view, v0, v1, reinterpret_cast<uint4 *>(d_tab),
+                                               reinterpret_cast<uint32_t *>(d_tab + SD.tab_o1), s);
                 if (e != hipSuccess) return device_error("table build launch");
             }
             set_slot(v0, v1, (uint16_t)slot);

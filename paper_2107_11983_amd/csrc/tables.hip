@@ -27,6 +27,7 @@
 // destination's row and bound (k_rej_records).
 #include <algorithm>
 
+#include "table_range.hpp"
 #include "trw_device.hpp"
 #include "trw_internal.hpp"
 
@@ -122,9 +123,9 @@ __device__ void alias_row_sequential(const GraphDev &g, int64_t off, int64_t d, 
 constexpr int64_t kBigRow = 128;
 constexpr int kBuildBlock = 256;
 
-__global__ void k_alias_build(GraphDev g, uint4 *__restrict__ out) {
-    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= g.n) return;
+__global__ void k_alias_build(GraphDev g, VRange r, uint4 *__restrict__ out) {
+    const int64_t v = r.lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= r.hi) return;
     const int64_t off = g.row_ptr[v];
     const int64_t d = (int64_t)g.row_ptr[v + 1] - off;
     if (d <= 0 || d > kBigRow) return;
@@ -161,22 +162,26 @@ __device__ __forceinline__ T block_sum(T v, T *sh) {
     return total;
 }
 
-// Calls body(v, off, d) for every vertex whose row exceeds kBigRow slots,
-// workgroup-uniformly; the workgroup sweeps vertex chunks of kBuildBlock.
+// Calls body(v, off, d) for every vertex of [r.lo, r.hi) whose row exceeds
+// kBigRow slots, workgroup-uniformly.  Vertices are dealt to the workgroups
+// in turn (v - r.lo = j * G + b goes to workgroup b of G), so the hubs, which
+// R-MAT numbers first, are spread over the grid instead of falling to one
+// workgroup.
 template <typename Body>
-__device__ __forceinline__ void for_each_big_row(const GraphDev &g, Body body) {
+__device__ __forceinline__ void for_each_big_row(const GraphDev &g, VRange r, Body body) {
     __shared__ uint64_t flags[kBuildBlock / 64];
     const uint32_t tid = threadIdx.x;
-    for (int64_t base = (int64_t)blockIdx.x * kBuildBlock; base < g.n; base += (int64_t)gridDim.x * kBuildBlock) {
-        const int64_t v = base + tid;
-        const bool big = v < g.n && (int64_t)g.row_ptr[v + 1] - g.row_ptr[v] > kBigRow;
+    const int64_t G = gridDim.x;
+    for (int64_t base = r.lo; base < r.hi; base += G * kBuildBlock) {
+        const int64_t v = base + (int64_t)tid * G + blockIdx.x;
+        const bool big = v < r.hi && (int64_t)g.row_ptr[v + 1] - g.row_ptr[v] > kBigRow;
         const uint64_t m = __ballot(big);
         if ((tid & 63) == 0) flags[tid >> 6] = m;
         __syncthreads();
         for (uint32_t wv = 0; wv < kBuildBlock / 64; ++wv) {
             uint64_t bits = flags[wv];
             while (bits) {
-                const int64_t u = base + 64 * wv + __builtin_ctzll(bits);
+                const int64_t u = base + (int64_t)(64 * wv + __builtin_ctzll(bits)) * G + blockIdx.x;
                 bits &= bits - 1;
                 const int64_t off = g.row_ptr[u];
                 body(u, off, (int64_t)g.row_ptr[u + 1] - off);
@@ -185,6 +190,10 @@ __device__ __forceinline__ void for_each_big_row(const GraphDev &g, Body body) {
         }
         __syncthreads();
     }
+}
+template <typename Body>
+__device__ __forceinline__ void for_each_big_row(const GraphDev &g, Body body) {
+    for_each_big_row(g, VRange{0, g.n}, body);
 }
 
 // Virtual 32-bit word k of the scratch area kept in the second 16-byte half of
@@ -215,11 +224,11 @@ __device__ __forceinline__ uint64_t *scratch_u64(uint4 *row, uint64_t k) {   // 
 // in pop order, then (at an even word) the u64 array P with P[0] = 0,
 // P[1..n_s] = D, P[n_s+1 .. n_s+n_l] = S.  3d + 3 words fit in the 4d words
 // of the second halves for d > 3.
-__global__ void __launch_bounds__(kBuildBlock) k_alias_build_big(GraphDev g, uint4 *__restrict__ out) {
+__global__ void __launch_bounds__(kBuildBlock) k_alias_build_big(GraphDev g, VRange r, uint4 *__restrict__ out) {
     __shared__ uint64_t sh64[kBuildBlock / 64];
     __shared__ uint32_t sh32[kBuildBlock / 64];
     const uint32_t tid = threadIdx.x;
-    for_each_big_row(g, [&](int64_t v, int64_t off, int64_t d) {
+    for_each_big_row(g, r, [&](int64_t v, int64_t off, int64_t d) {
         const uint32_t *__restrict__ w = g.weight + off;
         const int32_t *__restrict__ col = g.col + off;
         uint4 *__restrict__ row = out + 2 * off;
@@ -302,9 +311,9 @@ __global__ void __launch_bounds__(kBuildBlock) k_alias_build_big(GraphDev g, uin
     });
 }
 
-__global__ void k_its_build(GraphDev g, uint64_t *__restrict__ out) {
-    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= g.n) return;
+__global__ void k_its_build(GraphDev g, VRange r, uint64_t *__restrict__ out) {
+    const int64_t v = r.lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= r.hi) return;
     const int64_t lo = g.row_ptr[v], hi = g.row_ptr[v + 1];
     if (hi - lo > kBigRow) return;
     uint64_t acc = 0;
@@ -314,9 +323,9 @@ __global__ void k_its_build(GraphDev g, uint64_t *__restrict__ out) {
     }
 }
 
-__global__ void __launch_bounds__(kBuildBlock) k_its_build_big(GraphDev g, uint64_t *__restrict__ out) {
+__global__ void __launch_bounds__(kBuildBlock) k_its_build_big(GraphDev g, VRange r, uint64_t *__restrict__ out) {
     __shared__ uint64_t sh64[kBuildBlock / 64];
-    for_each_big_row(g, [&](int64_t, int64_t off, int64_t d) {
+    for_each_big_row(g, r, [&](int64_t, int64_t off, int64_t d) {
         uint64_t carry = 0;
         for (int64_t r0 = 0; r0 < d; r0 += kBuildBlock) {
             const int64_t e = off + r0 + threadIdx.x;
@@ -448,9 +457,9 @@ __global__ void k_adjacency_build(GraphDev g, uint4 *__restrict__ out) {
 // the search over the prefix plus one 32-byte read, with no lookup of the
 // chosen slot's destination, its row or its total:
 //   [0] {dst, row_off(dst), deg(dst), 0}   [1] {W(dst) lo, W(dst) hi, 0, 0}
-__global__ void k_its_vw(GraphDev g, const uint64_t *__restrict__ prefix, uint64_t *__restrict__ vw) {
-    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= g.n) return;
+__global__ void k_its_vw(GraphDev g, VRange r, const uint64_t *__restrict__ prefix, uint64_t *__restrict__ vw) {
+    const int64_t v = r.lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= r.hi) return;
     const int64_t hi = g.row_ptr[v + 1];
     vw[v] = hi > g.row_ptr[v] ? prefix[hi - 1] : 0ull;
 }
@@ -470,9 +479,9 @@ __global__ void k_its_next(GraphDev g, const uint64_t *__restrict__ vw, uint4 *_
 // record then carries its weight and the destination's id, row range and
 // p*, so a dart is one 32-byte read and a hit needs no further lookup:
 //   [0] {w, dst, row_off(dst), deg(dst)}   [1] {p*(dst), 0, 0, 0}
-__global__ void k_rej_pmax(GraphDev g, uint32_t *__restrict__ pmax) {
-    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= g.n) return;
+__global__ void k_rej_pmax(GraphDev g, VRange r, uint32_t *__restrict__ pmax) {
+    const int64_t v = r.lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= r.hi) return;
     const int64_t lo = g.row_ptr[v], hi = g.row_ptr[v + 1];
     if (hi - lo > kBigRow) return;
     uint32_t mx = 0;
@@ -480,9 +489,9 @@ __global__ void k_rej_pmax(GraphDev g, uint32_t *__restrict__ pmax) {
     pmax[v] = mx;
 }
 
-__global__ void __launch_bounds__(kBuildBlock) k_rej_pmax_big(GraphDev g, uint32_t *__restrict__ pmax) {
+__global__ void __launch_bounds__(kBuildBlock) k_rej_pmax_big(GraphDev g, VRange r, uint32_t *__restrict__ pmax) {
     __shared__ uint32_t sh[kBuildBlock / 64];
-    for_each_big_row(g, [&](int64_t v, int64_t off, int64_t d) {
+    for_each_big_row(g, r, [&](int64_t v, int64_t off, int64_t d) {
         uint32_t mx = 0;
         for (int64_t e = off + threadIdx.x; e < off + d; e += kBuildBlock) mx = max(mx, g.weight[e]);
 #pragma unroll
@@ -561,32 +570,48 @@ __global__ void k_symmetry_check(GraphDev g, unsigned long long *__restrict__ ba
 
 constexpr int kBuildThreads = 256;
 
-// Workgroups for the big-row kernels (each sweeps its own vertex chunks).
-int big_row_blocks(const GraphDev &g) {
-    return (int)std::min<int64_t>(((int64_t)g.n + kBuildBlock - 1) / kBuildBlock, 2048);
+// Workgroups for the big-row kernels: one per vertex up to 2048 (each deals
+// itself every G-th vertex).
+int big_row_blocks(int64_t verts) {
+    return (int)std::max<int64_t>(1, std::min<int64_t>(verts, 2048));
+}
+int big_row_blocks(const GraphDev &g) { return big_row_blocks((int64_t)g.n); }
+
+// Thread-per-vertex workgroups for [lo, hi) (at least one).
+int vertex_blocks(VRange r) {
+    return (int)std::max<int64_t>(1, (r.hi - r.lo + kBuildThreads - 1) / kBuildThreads);
 }
 
 }  // namespace
 
-hipError_t launch_alias_build(const GraphDev &g, uint4 *out, hipStream_t s) {
-    const int blocks = (g.n + kBuildThreads - 1) / kBuildThreads;
-    hipLaunchKernelGGL(k_alias_build, dim3(blocks), dim3(kBuildThreads), 0, s, g, out);
-    hipLaunchKernelGGL(k_alias_build_big, dim3(big_row_blocks(g)), dim3(kBuildBlock), 0, s, g, out);
+hipError_t launch_alias_build_range(const GraphDev &g, int64_t lo, int64_t hi, uint4 *out, hipStream_t s) {
+    const VRange r{lo, hi};
+    hipLaunchKernelGGL(k_alias_build, dim3(vertex_blocks(r)), dim3(kBuildThreads), 0, s, g, r, out);
+    hipLaunchKernelGGL(k_alias_build_big, dim3(big_row_blocks(hi - lo)), dim3(kBuildBlock), 0, s, g, r, out);
     return hipGetLastError();
 }
 
-hipError_t launch_its_build(const GraphDev &g, uint64_t *prefix, uint4 *next, uint64_t *vw, hipStream_t s) {
-    const int blocks = (g.n + kBuildThreads - 1) / kBuildThreads;
+hipError_t launch_alias_build(const GraphDev &g, uint4 *out, hipStream_t s) {
+    return launch_alias_build_range(g, 0, g.n, out, s);
+}
+
+hipError_t launch_its_build_range(const GraphDev &g, int64_t lo, int64_t hi, uint64_t *prefix, uint4 *next,
+                                  uint64_t *vw, hipStream_t s) {
+    const VRange r{lo, hi};
     if (g.m > 0) {
-        hipLaunchKernelGGL(k_its_build, dim3(blocks), dim3(kBuildThreads), 0, s, g, prefix);
-        hipLaunchKernelGGL(k_its_build_big, dim3(big_row_blocks(g)), dim3(kBuildBlock), 0, s, g, prefix);
+        hipLaunchKernelGGL(k_its_build, dim3(vertex_blocks(r)), dim3(kBuildThreads), 0, s, g, r, prefix);
+        hipLaunchKernelGGL(k_its_build_big, dim3(big_row_blocks(hi - lo)), dim3(kBuildBlock), 0, s, g, r, prefix);
     }
-    hipLaunchKernelGGL(k_its_vw, dim3(blocks), dim3(kBuildThreads), 0, s, g, prefix, vw);
+    hipLaunchKernelGGL(k_its_vw, dim3(vertex_blocks(r)), dim3(kBuildThreads), 0, s, g, r, prefix, vw);
     if (g.m > 0) {
         const int64_t eblocks = ((int64_t)g.m + kBuildThreads - 1) / kBuildThreads;
         hipLaunchKernelGGL(k_its_next, dim3((uint32_t)eblocks), dim3(kBuildThreads), 0, s, g, vw, next);
     }
     return hipGetLastError();
+}
+
+hipError_t launch_its_build(const GraphDev &g, uint64_t *prefix, uint4 *next, uint64_t *vw, hipStream_t s) {
+    return launch_its_build_range(g, 0, g.n, prefix, next, vw, s);
 }
 
 hipError_t launch_label_fused_build(const GraphDev &g, uint32_t nlab, const int32_t *loff, const int32_t *lcol,
@@ -611,15 +636,20 @@ hipError_t launch_adjacency_build(const GraphDev &g, uint4 *out, hipStream_t s) 
     return hipGetLastError();
 }
 
-hipError_t launch_rej_build(const GraphDev &g, uint4 *records, uint32_t *pmax, hipStream_t s) {
-    const int blocks = (g.n + kBuildThreads - 1) / kBuildThreads;
-    hipLaunchKernelGGL(k_rej_pmax, dim3(blocks), dim3(kBuildThreads), 0, s, g, pmax);
-    hipLaunchKernelGGL(k_rej_pmax_big, dim3(big_row_blocks(g)), dim3(kBuildBlock), 0, s, g, pmax);
+hipError_t launch_rej_build_range(const GraphDev &g, int64_t lo, int64_t hi, uint4 *records, uint32_t *pmax,
+                                  hipStream_t s) {
+    const VRange r{lo, hi};
+    hipLaunchKernelGGL(k_rej_pmax, dim3(vertex_blocks(r)), dim3(kBuildThreads), 0, s, g, r, pmax);
+    hipLaunchKernelGGL(k_rej_pmax_big, dim3(big_row_blocks(hi - lo)), dim3(kBuildBlock), 0, s, g, r, pmax);
     if (g.m > 0) {
         const int64_t eblocks = ((int64_t)g.m + kBuildThreads - 1) / kBuildThreads;
         hipLaunchKernelGGL(k_rej_records, dim3((uint32_t)eblocks), dim3(kBuildThreads), 0, s, g, pmax, records);
     }
     return hipGetLastError();
+}
+
+hipError_t launch_rej_build(const GraphDev &g, uint4 *records, uint32_t *pmax, hipStream_t s) {
+    return launch_rej_build_range(g, 0, g.n, records, pmax, s);
 }
 
 hipError_t launch_edge_set_build(const GraphDev &g, unsigned long long *keys, unsigned long long slots, hipStream_t s) {
