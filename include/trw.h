@@ -492,7 +492,7 @@ typedef struct {
 
 /* Device workspace and pinned host bytes trw_disk_walk needs for nq queries
  * with `slots` partitions resident at once (1 .. the partition count; 0 counts
- * as 1, more than the partitions as all of them).  Per slot: 4(n + 1) bytes of
+ * as 1, more than the partitions as all of them; Node2Vec takes at least 2).  Per slot: 4(n + 1) bytes of
  * row offsets plus the largest partition's edges (4 B each, 4 more for
  * weights, 1 for labels) and table (ALIAS 32 B per edge; ITS 40 B per edge +
  * 8n; REJ 32 B per edge + 4n). */
@@ -502,14 +502,16 @@ trw_status trw_disk_walk_bytes(trw_disk_graph g, const trw_walk_params *p, uint6
 /*
  * Run nq queries over the file's graph: the same paths, lengths and status as
  * trw_walk over the whole graph (query i has id qid_base + i).  DeepWalk and
- * PPR with NAIVE, ALIAS, ITS or REJ, and MetaPath; Node2Vec is refused
- * (TRW_E_UNSUPPORTED): its acceptance test reads the previous vertex's row,
- * which may lie in another partition.  Until every query ends: the queries
- * waiting in resident partitions move until they end or step into a
- * partition that is not resident; when no resident partition holds a waiting
- * query, the partition holding the most (the lowest index among equals) is
- * loaded (its edges read through h_pinned, copied to the device, its table
- * built there) into a free slot or the one whose partition ran longest ago.
+ * PPR with NAIVE, ALIAS, ITS or REJ, MetaPath, and Node2Vec with O-REJ.  A
+ * query waits under its partition; a Node2Vec query, whose acceptance test
+ * searches the previous vertex's row, under the pair of its current and
+ * previous vertices' partitions (so at most 1024 partitions, and rows sorted
+ * as trw_graph_validate wants them).  Until every query ends: the queries
+ * waiting under resident partitions move until they end or need a partition
+ * that is not resident; when none waits there, the partitions of the key
+ * holding the most queries (the lowest index among equals) are loaded (edges
+ * read through h_pinned, copied to the device, table built there) into free
+ * slots or those whose partitions ran longest ago.
  *   d_sources, d_paths, path_stride, d_lengths, d_status   as trw_walk
  *   slots       partitions resident at once, as trw_disk_walk_bytes
  *   d_ws        device workspace, >= device_bytes, 256-byte aligned
@@ -518,7 +520,8 @@ trw_status trw_disk_walk_bytes(trw_disk_graph g, const trw_walk_params *p, uint6
  * Synchronous: returns when every query has ended; runs on `stream`.  Errors
  * as trw_walk (TRW_E_INVALID for a file whose weights or labels the walk needs
  * are absent), TRW_E_INVALID for a destination outside [0, n) in a loaded
- * partition or a failed read, TRW_E_DEVICE for a device error.
+ * partition, an unsorted row (Node2Vec) or a failed read, TRW_E_UNSUPPORTED for
+ * Node2Vec over more than 1024 partitions, TRW_E_DEVICE for a device error.
  */
 trw_status trw_disk_walk(trw_disk_graph g, const trw_walk_params *p, const int32_t *d_sources, uint64_t nq,
                          uint64_t qid_base, int32_t *d_paths, uint64_t path_stride, uint32_t *d_lengths,

@@ -46,6 +46,7 @@ struct trw_disk_graph_s {
     std::vector<int64_t> row_ptr;        // n + 1
     std::vector<int64_t> vstart;         // partitions + 1 vertex starts (vstart[parts] = n)
     std::vector<uint8_t> checked;        // destinations of partition i checked to lie in [0, n)
+    std::vector<uint8_t> sorted;         // rows of partition i: 0 not checked, 1 sorted, 2 not sorted
     int64_t max_edges, max_verts;        // largest partition
     uint64_t off_col, off_weight, off_label;
 };
@@ -60,7 +61,8 @@ constexpr uint32_t kMaxSlots = 4096;
 constexpr uint16_t kNoSlot = 0xFFFF;
 constexpr size_t kReadChunk = size_t(64) << 20;   // file bytes per read (then copied while the next is read)
 constexpr size_t kReadPiece = size_t(8) << 20;    // bytes per reading thread
-constexpr uint32_t kLdsParts = 4096;              // partitions the regroup kernels count in LDS
+constexpr uint32_t kLdsParts = 4096;              // keys the regroup kernels count in LDS
+constexpr uint64_t kMaxPairParts = 1024;          // Node2Vec: partitions (so at most 2^20 pair keys)
 
 trw_status dfail(trw_status st, const std::string &m) {
     set_error(m);
@@ -123,12 +125,17 @@ bool write_all(int fd, const void *src, size_t bytes) {
 // ---------------------------------------------------------------------------
 // Kernels
 // ---------------------------------------------------------------------------
-// A waiting walker: query index, current vertex, moves made, its partition.
+// A waiting walker: query index, current vertex, moves made, the key it
+// waits under (its partition; for Node2Vec the pair of its current and
+// previous vertices' partitions, current * parts + previous), and the
+// previous vertex (Node2Vec; -1 before the first move).
 struct alignas(16) DRec {
     uint32_t qi;
     int32_t cur;
     uint32_t k;
     uint32_t part;
+    int32_t prev;
+    uint32_t pad[3];
 };
 
 // Where the pieces of a slot sit: slot s starts at base + s * stride; the
@@ -213,9 +220,10 @@ __global__ void k_disk_rows(int32_t *rp, int64_t n, int64_t v0, int64_t v1, int3
 }
 
 // Sources: a bad one ends at once; the others start a path and wait in
-// their partition.
+// their partition (pairs: under the pair (partition, partition)).
 __global__ void __launch_bounds__(256) k_disk_init(WalkDev a, int32_t n, const int32_t *__restrict__ vstart,
-                                                   uint32_t parts, DRec *__restrict__ out, uint32_t *count) {
+                                                   uint32_t parts, uint32_t pairs, DRec *__restrict__ out,
+                                                   uint32_t *count) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t base = 0; base < a.nq; base += stride) {
         const uint64_t i = base + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -232,7 +240,10 @@ __global__ void __launch_bounds__(256) k_disk_init(WalkDev a, int32_t n, const i
             }
         }
         const uint32_t slot = wave_append(count, keep);
-        if (keep) out[slot] = DRec{(uint32_t)i, s, 0u, part_of(vstart, parts, s)};
+        if (keep) {
+            const uint32_t ps = part_of(vstart, parts, s);
+            out[slot] = DRec{(uint32_t)i, s, 0u, pairs ? ps * parts + ps : ps, -1, {0u, 0u, 0u}};
+        }
     }
 }
 
@@ -311,7 +322,7 @@ __global__ void __launch_bounds__(256) k_disk_place_new(const DRec *__restrict__
     for (uint32_t b = 0; b < n; b += stride) {
         const uint32_t i = b + blockIdx.x * blockDim.x + threadIdx.x;
         const bool act = i < n;
-        DRec r{0u, 0, 0u, 0u};
+        DRec r{0u, 0, 0u, 0u, -1, {0u, 0u, 0u}};
         if (act) r = in[i];
         const uint32_t pos = wave_add_by_key(cursor, r.part, act);
         if (act) out[base[r.part] + pos] = r;
@@ -369,7 +380,7 @@ __global__ void __launch_bounds__(256) k_disk_walk(SlotsDev S, WalkDev a, const 
     for (uint32_t base = 0; base < n_in; base += stride) {
         const uint32_t idx = base + blockIdx.x * blockDim.x + threadIdx.x;
         bool leave = false;
-        DRec rc{0u, 0, 0u, 0u};
+        DRec rc{0u, 0, 0u, 0u, -1, {0u, 0u, 0u}};
         if (idx < n_in) {
             rc = in[idx];
             const uint64_t qid = a.qid_base + rc.qi;
@@ -416,6 +427,101 @@ __global__ void __launch_bounds__(256) k_disk_walk(SlotsDev S, WalkDev a, const 
     }
 }
 
+// Node2Vec O-REJ move with cur's row in one slot and prev's row in another:
+// the darts over cur's row, and for a dart whose height lies between the two
+// thresholds it could be judged by, the adjacency test by binary search in
+// prev's sorted row.  The darts, thresholds and acceptance are those of the
+// in-memory walk without an index (the Node2Vec transition equation; the
+// first move takes its first dart).
+__device__ __forceinline__ int32_t disk_n2v_move(const int32_t *__restrict__ colc, int32_t off, uint32_t d,
+                                                 const int32_t *__restrict__ colp, int32_t poff, int32_t pd,
+                                                 const WalkDev &a, uint64_t qid, uint32_t k, int32_t prev,
+                                                 const Rand4 &r) {
+    Rand4 rr = r;
+    for (uint32_t dart = 0;; ++dart) {
+        if (dart > 0) rr = philox(k, dart, qid, a.seed);
+        const int32_t x = colc[(uint32_t)off + scale32(rr.r0, d)];
+        bool accept = (k == 0 || dart + 1 == kMaxDarts);
+        if (!accept) {
+            const uint32_t y = rr.r1 >> 16;
+            if (x == prev) accept = y < a.thr[0];
+            else if (y < min(a.thr[1], a.thr[2])) accept = true;
+            else if (y >= max(a.thr[1], a.thr[2])) accept = false;
+            else accept = y < (in_row(colp, poff, poff + pd, x) ? a.thr[1] : a.thr[2]);
+        }
+        if (accept) return x;
+    }
+}
+
+// Node2Vec walkers of one resident pair: each moves while its current and
+// previous vertices' partitions are both resident, then ends or waits under
+// its new pair.
+__global__ void __launch_bounds__(256) k_disk_walk_n2v(SlotsDev S, WalkDev a, const uint16_t *__restrict__ vslot,
+                                                       const DRec *__restrict__ in, uint32_t n_in,
+                                                       const int32_t *__restrict__ vstart, uint32_t parts,
+                                                       DRec *__restrict__ out, uint32_t *count_out) {
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t base = 0; base < n_in; base += stride) {
+        const uint32_t idx = base + blockIdx.x * blockDim.x + threadIdx.x;
+        bool leave = false;
+        DRec rc{0u, 0, 0u, 0u, -1, {0u, 0u, 0u}};
+        if (idx < n_in) {
+            rc = in[idx];
+            const uint64_t qid = a.qid_base + rc.qi;
+            int32_t *__restrict__ path = a.paths + (uint64_t)rc.qi * a.stride;
+            uint8_t st = 0;
+            for (;;) {
+                const uint16_t sc = vslot[rc.cur];
+                const uint16_t sp = rc.prev >= 0 ? vslot[rc.prev] : sc;
+                if (sc == kNoSlot || sp == kNoSlot) {
+                    leave = true;
+                    break;
+                }
+                const char *bc = S.base + (uint64_t)sc * S.stride;
+                const int32_t *rpc = reinterpret_cast<const int32_t *>(bc + S.o_rp);
+                const int32_t *colc = reinterpret_cast<const int32_t *>(bc + S.o_col);
+                const int32_t off = rpc[rc.cur];
+                const uint32_t d = (uint32_t)(rpc[rc.cur + 1] - off);
+                int32_t nxt = -1;
+                if (d != 0) {
+                    const Rand4 r = philox(rc.k, 0, qid, a.seed);
+                    const int32_t *colp = colc;
+                    int32_t poff = 0, pd = 0;
+                    if (rc.prev >= 0) {
+                        const char *bp = S.base + (uint64_t)sp * S.stride;
+                        const int32_t *rpp = reinterpret_cast<const int32_t *>(bp + S.o_rp);
+                        colp = reinterpret_cast<const int32_t *>(bp + S.o_col);
+                        poff = rpp[rc.prev];
+                        pd = rpp[rc.prev + 1] - poff;
+                    }
+                    nxt = disk_n2v_move(colc, off, d, colp, poff, pd, a, qid, rc.k, rc.prev, r);
+                }
+                if (nxt < 0) {
+                    st = ST_DEAD_END;
+                    break;
+                }
+                path[rc.k + 1] = nxt;
+                ++rc.k;
+                if (rc.k == a.max_len) {
+                    st = ST_LENGTH;
+                    break;
+                }
+                rc.prev = rc.cur;
+                rc.cur = nxt;
+            }
+            if (leave) {
+                const uint32_t pc = part_of(vstart, parts, rc.cur);
+                rc.part = pc * parts + (rc.prev >= 0 ? part_of(vstart, parts, rc.prev) : pc);
+            } else {
+                a.lengths[rc.qi] = rc.k;
+                a.status[rc.qi] = st;
+            }
+        }
+        const uint32_t slot = wave_append(count_out, leave);
+        if (leave) out[slot] = rc;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
@@ -441,9 +547,19 @@ size_t table_bytes(uint32_t algo, uint32_t sampler, int64_t mp, int64_t n, size_
     }
 }
 
-uint32_t clamp_slots(const trw_disk_graph_s &g, uint32_t slots) {
+// Resident partitions: slots within 1 .. parts; Node2Vec needs two (its
+// current and previous vertices' partitions) when there are two.
+uint32_t clamp_slots(const trw_disk_graph_s &g, const trw_walk_params &p, uint32_t slots) {
     const uint32_t parts = (uint32_t)(g.vstart.size() - 1);
-    return std::max<uint32_t>(1, std::min<uint32_t>(std::min(slots, kMaxSlots), parts));
+    const uint32_t least = p.algo == TRW_A_NODE2VEC ? 2u : 1u;
+    return std::min<uint32_t>(std::max<uint32_t>(least, std::min(slots, kMaxSlots)), parts);
+}
+
+// Keys the waiting walkers are grouped under: partitions, or for Node2Vec
+// pairs of partitions.
+uint64_t key_count(const trw_disk_graph_s &g, const trw_walk_params &p) {
+    const uint64_t parts = g.vstart.size() - 1;
+    return p.algo == TRW_A_NODE2VEC ? parts * parts : parts;
 }
 
 // Offsets of the pieces of the device workspace and of the pinned buffer.
@@ -454,7 +570,7 @@ struct Layout {
 };
 
 Layout layout(const trw_disk_graph_s &g, const trw_walk_params &p, uint64_t nq, uint32_t slots) {
-    const size_t parts = g.vstart.size() - 1;
+    const size_t parts = g.vstart.size() - 1, keys = key_count(g, p);
     const size_t mp = (size_t)g.max_edges;
     const bool w = needs_weights(p.sampler, p.algo), l = p.algo == TRW_A_METAPATH;
     Layout L{};
@@ -472,17 +588,17 @@ Layout layout(const trw_disk_graph_s &g, const trw_walk_params &p, uint64_t nq, 
     L.S.n = (int32_t)g.n;
     L.S.has_wgt = w;
     L.S.has_lab = l;
-    L.slots_bytes = o * clamp_slots(g, slots);
+    L.slots_bytes = o * clamp_slots(g, p, slots);
     o = L.slots_bytes;
     L.vslot = take(2 * (size_t)g.n + 4);
     for (auto &x : L.lists) x = take(sizeof(DRec) * (size_t)nq);
     L.vstart = take(4 * (parts + 1));
-    L.hist = take(4 * parts);
-    L.cursor = take(4 * parts);
-    L.new_off = take(4 * parts);
-    L.old_off = take(4 * parts);
-    L.base = take(4 * parts);
-    L.consumed = take(parts);
+    L.hist = take(4 * keys);
+    L.cursor = take(4 * keys);
+    L.new_off = take(4 * keys);
+    L.old_off = take(4 * keys);
+    L.base = take(4 * keys);
+    L.consumed = take(keys);
     L.count = take(4);
     L.dev_total = o;
     o = 0;
@@ -490,11 +606,11 @@ Layout layout(const trw_disk_graph_s &g, const trw_walk_params &p, uint64_t nq, 
     L.h_col = take(4 * mp);
     L.h_wgt = take(w ? 4 * mp : 0);
     L.h_lab = take(l ? mp : 0);
-    L.h_hist = take(4 * parts + 4);
-    L.h_new_off = take(4 * parts);
-    L.h_old_off = take(4 * parts);
-    L.h_base = take(4 * parts);
-    L.h_consumed = take(parts);
+    L.h_hist = take(4 * keys + 4);
+    L.h_new_off = take(4 * keys);
+    L.h_old_off = take(4 * keys);
+    L.h_base = take(4 * keys);
+    L.h_consumed = take(keys);
     L.host_total = o;
     return L;
 }
@@ -502,9 +618,15 @@ Layout layout(const trw_disk_graph_s &g, const trw_walk_params &p, uint64_t nq, 
 trw_status check_walk(const trw_disk_graph_s *g, const trw_walk_params *p) {
     if (!g) return dfail(TRW_E_INVALID, "disk graph is NULL");
     if (!p) return dfail(TRW_E_INVALID, "params is NULL");
-    if (p->algo == TRW_A_NODE2VEC)
-        return dfail(TRW_E_UNSUPPORTED, "Node2Vec reads the previous vertex's row, which may lie in another partition");
-    if (p->algo == TRW_A_DEEPWALK || p->algo == TRW_A_PPR) {
+    if (p->algo == TRW_A_NODE2VEC) {
+        if (p->sampler != TRW_S_OREJ) return dfail(TRW_E_UNSUPPORTED, "Node2Vec walks with O-REJ");
+        for (int i = 0; i < 3; ++i)
+            if (p->n2v_thr_q16[i] == 0 || p->n2v_thr_q16[i] > 65536)
+                return dfail(TRW_E_INVALID, "Node2Vec thresholds must be in 1..65536");
+        if (g->vstart.size() - 1 > kMaxPairParts)
+            return dfail(TRW_E_UNSUPPORTED, "Node2Vec from a file takes at most 1024 partitions (its walkers wait "
+                                            "under pairs of partitions)");
+    } else if (p->algo == TRW_A_DEEPWALK || p->algo == TRW_A_PPR) {
         if (p->sampler != TRW_S_NAIVE && p->sampler != TRW_S_ALIAS && p->sampler != TRW_S_ITS &&
             p->sampler != TRW_S_REJ)
             return dfail(TRW_E_UNSUPPORTED, "sampler not provided for this algorithm");
@@ -533,6 +655,11 @@ void dispatch_walk(uint32_t algo, uint32_t sampler, const SlotsDev &S, const Wal
                    const DRec *in, uint32_t n_in, const int32_t *vstart, uint32_t parts, DRec *out, uint32_t *count,
                    uint32_t blocks, hipStream_t s) {
 #define TRW_DISK_WALK(A, M) launch_disk_walk<A, M>(S, w, vslot, in, n_in, vstart, parts, out, count, blocks, s)
+    if (algo == TRW_A_NODE2VEC) {
+        hipLaunchKernelGGL(k_disk_walk_n2v, dim3(blocks), dim3(256), 0, s, S, w, vslot, in, n_in, vstart, parts, out,
+                           count);
+        return;
+    }
     if (algo == TRW_A_METAPATH) {
         TRW_DISK_WALK(ALG_METAPATH, SMP_ITS);
         return;
@@ -652,6 +779,7 @@ trw_status trw_disk_graph_open(const char *path, uint64_t part_edges, trw_disk_g
     g->m = (int64_t)m;
     g->flags = (uint32_t)flags;
     g->checked.assign(g->vstart.size() - 1, 0);
+    g->sorted.assign(g->vstart.size() - 1, 0);
     g->max_edges = max_e;
     g->max_verts = max_v;
     g->off_col = off_col;
@@ -718,7 +846,9 @@ trw_status trw_disk_walk(trw_disk_graph g, const trw_walk_params *p, const int32
     }
     if (!d_sources || !d_paths || !d_lengths || !d_status)
         return dfail(TRW_E_INVALID, "sources / paths / lengths / status is NULL");
-    const uint32_t K = clamp_slots(*g, slots);
+    const uint32_t K = clamp_slots(*g, *p, slots);
+    const bool pairs = p->algo == TRW_A_NODE2VEC;
+    const uint32_t keys = (uint32_t)key_count(*g, *p);
     Layout L = layout(*g, *p, nq, K);
     if (!d_ws || ws_bytes < L.dev_total || (reinterpret_cast<uintptr_t>(d_ws) & 255))
         return dfail(TRW_E_INVALID, "workspace NULL, too small or not 256-byte aligned");
@@ -731,7 +861,7 @@ trw_status trw_disk_walk(trw_disk_graph g, const trw_walk_params *p, const int32
     const uint32_t parts = (uint32_t)(g->vstart.size() - 1);
     const bool want_w = needs_weights(p->sampler, p->algo), want_l = p->algo == TRW_A_METAPATH;
     const DeviceInfo di = device_info();
-    const size_t lds_hist = parts <= kLdsParts ? 4 * (size_t)parts : 0;   // the regroup kernels' LDS counts
+    const size_t lds_hist = keys <= kLdsParts ? 4 * (size_t)keys : 0;   // the regroup kernels' LDS counts
     L.S.base = D;
     const SlotsDev &SD = L.S;
 
@@ -750,7 +880,7 @@ trw_status trw_disk_walk(trw_disk_graph g, const trw_walk_params *p, const int32
     char *h_col = H + L.h_col;
     char *h_wgt = H + L.h_wgt;
     char *h_lab = H + L.h_lab;
-    uint32_t *h_hist = reinterpret_cast<uint32_t *>(H + L.h_hist);   // parts counts, then the arrival count
+    uint32_t *h_hist = reinterpret_cast<uint32_t *>(H + L.h_hist);   // key counts, then the arrival count
     uint32_t *h_new_off = reinterpret_cast<uint32_t *>(H + L.h_new_off);
     uint32_t *h_old_off = reinterpret_cast<uint32_t *>(H + L.h_old_off);
     uint32_t *h_base = reinterpret_cast<uint32_t *>(H + L.h_base);
@@ -759,6 +889,7 @@ trw_status trw_disk_walk(trw_disk_graph g, const trw_walk_params *p, const int32
     WalkDev w{};
     w.max_len = p->max_len;
     w.stop_q32 = p->algo == TRW_A_PPR ? p->stop_q32 : 0;
+    for (int i = 0; i < 3; ++i) w.thr[i] = p->n2v_thr_q16[i];
     w.schema_len = p->algo == TRW_A_METAPATH ? p->schema_len : 1;
     for (int i = 0; i < 8; ++i) {
         w.schema_lo |= (uint64_t)p->schema[i] << (8 * i);
@@ -793,11 +924,11 @@ trw_status trw_disk_walk(trw_disk_graph g, const trw_walk_params *p, const int32
     };
     // histogram of the arrivals in lists[2] (count in d_count) into h_hist; waits
     auto read_arrivals = [&]() {
-        fill(d_hist, parts, 0u);
+        fill(d_hist, keys, 0u);
         hipLaunchKernelGGL(k_disk_hist, dim3(grid_for(nq, di)), dim3(256), lds_hist, s, lists[2], d_count, d_hist,
-                           parts);
-        e = hipMemcpyAsync(h_hist, d_hist, 4 * (size_t)parts, hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess) e = hipMemcpyAsync(h_hist + parts, d_count, 4, hipMemcpyDeviceToHost, s);
+                           keys);
+        e = hipMemcpyAsync(h_hist, d_hist, 4 * (size_t)keys, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(h_hist + keys, d_count, 4, hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         return e == hipSuccess;
     };
@@ -843,24 +974,99 @@ trw_status trw_disk_walk(trw_disk_graph g, const trw_walk_params *p, const int32
     // the sources wait in their partitions
     fill(d_count, 1, 0u);
     hipLaunchKernelGGL(k_disk_init, dim3(grid_for(nq, di)), dim3(256), 0, s, w, (int32_t)g->n, d_vstart, parts,
-                       lists[2], d_count);
+                       (uint32_t)pairs, lists[2], d_count);
     e = hipGetLastError();
     if (e != hipSuccess || !read_arrivals()) return device_error("start");
 
-    // host copies of the waiting list's layout: per partition its count and start
-    std::vector<uint64_t> counts(parts, 0), next(parts, 0), off(parts, 0);
-    std::vector<uint8_t> consumed(parts, 0);
+    // host copies of the waiting list's layout: per key its count and start
+    std::vector<uint64_t> counts(keys, 0), next(keys, 0), off(keys, 0);
+    std::vector<uint8_t> consumed(keys, 0);
     // resident partitions: slot -> partition, partition -> slot, last round used
     std::vector<int64_t> slot_part(K, -1), slot_used(K, -1);
     std::vector<int32_t> part_slot(parts, -1);
     DRec *cur = lists[0], *spare = lists[1];
     uint64_t old_total = 0, round = 0, moved_max = nq * (uint64_t)p->max_len;
+
+    // Load partition q into the slot used longest ago that does not hold
+    // `keep` (the other partition a Node2Vec pair needs): its rows, its edges
+    // (checked on the first load), its table.
+    auto load = [&](uint32_t q, uint32_t keep) -> trw_status {
+        // the pinned staging area is refilled below: the copies of a load just
+        // made (a Node2Vec pair loads two partitions in one round) must be done
+        e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return device_error("partition copy");
+        uint32_t slot = K;
+        for (uint32_t k = 0; k < K; ++k)
+            if (slot_part[k] != (int64_t)keep && (slot == K || slot_used[k] < slot_used[slot])) slot = k;
+        const int64_t v0 = g->vstart[q], v1 = g->vstart[q + 1];
+        const int64_t e0 = g->row_ptr[v0], e1 = g->row_ptr[v1];
+        const int64_t mp = e1 - e0;
+        if (slot_part[slot] >= 0) {
+            const int64_t old = slot_part[slot];
+            set_slot(g->vstart[old], g->vstart[old + 1], kNoSlot);
+            part_slot[old] = -1;
+            slot_part[slot] = -1;
+        }
+        char *b = D + (uint64_t)slot * SD.stride;
+        int32_t *d_rp = reinterpret_cast<int32_t *>(b + SD.o_rp);
+        char *d_tab = b + SD.o_tab;
+        for (int64_t v = v0; v <= v1; ++v) h_rp[v - v0] = (int32_t)(g->row_ptr[v] - e0);
+        hipLaunchKernelGGL(k_disk_rows, dim3(grid_for((uint64_t)g->n + 1, di)), dim3(256), 0, s, d_rp, g->n, v0, v1,
+                           (int32_t)mp);
+        e = hipMemcpyAsync(d_rp + v0, h_rp, 4 * (size_t)(v1 - v0 + 1), hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return device_error("partition copy");
+        bool ok = stream_in(h_col, b + SD.o_col, 4 * (size_t)mp, g->off_col + 4 * (uint64_t)e0, !g->checked[q], e0);
+        if (ok && want_w)
+            ok = stream_in(h_wgt, b + SD.o_wgt, 4 * (size_t)mp, g->off_weight + 4 * (uint64_t)e0, false, e0);
+        if (ok && want_l) ok = stream_in(h_lab, b + SD.o_lab, (size_t)mp, g->off_label + (uint64_t)e0, false, e0);
+        if (!ok) {
+            if (e != hipSuccess) return device_error("partition copy");
+            (void)hipStreamSynchronize(s);
+            return TRW_E_INVALID;   // the message is set
+        }
+        g->checked[q] = 1;
+        if (pairs && g->sorted[q] == 0) {
+            // the adjacency test searches rows: each must be sorted
+            const int32_t *c = reinterpret_cast<const int32_t *>(h_col);
+            g->sorted[q] = 1;
+            for (int64_t v = v0; v < v1 && g->sorted[q] == 1; ++v)
+                for (int64_t x = g->row_ptr[v] - e0 + 1; x < g->row_ptr[v + 1] - e0; ++x)
+                    if (c[x - 1] > c[x]) {
+                        g->sorted[q] = 2;
+                        break;
+                    }
+        }
+        if (pairs && g->sorted[q] == 2)
+            return host_error("Node2Vec searches rows: a row of partition " + std::to_string(q) + " is not sorted");
+        if (mp > 0 && p->algo != TRW_A_METAPATH && p->algo != TRW_A_NODE2VEC) {
+            GraphDev view{d_rp, reinterpret_cast<const int32_t *>(b + SD.o_col),
+                          want_w ? reinterpret_cast<const uint32_t *>(b + SD.o_wgt) : nullptr, nullptr,
+                          (int32_t)g->n, (int32_t)mp, 0};
+            if (p->sampler == TRW_S_ALIAS)
+                e = launch_alias_build_range(view, v0, v1, reinterpret_cast<uint4 *>(d_tab), s);
+            else if (p->sampler == TRW_S_ITS)
+                e = launch_its_build_range(view, v0, v1, reinterpret_cast<uint64_t *>(d_tab),
+                                           reinterpret_cast<uint4 *>(d_tab + SD.tab_o1),
+                                           reinterpret_cast<uint64_t *>(d_tab + SD.tab_o2), s);
+            else if (p->sampler == TRW_S_REJ)
+                e = launch_rej_build_range(view, v0, v1, reinterpret_cast<uint4 *>(d_tab),
+                                           reinterpret_cast<uint32_t *>(d_tab + SD.tab_o1), s);
+            if (e != hipSuccess) return device_error("table build launch");
+        }
+        set_slot(v0, v1, (uint16_t)slot);
+        slot_part[slot] = q;
+        part_slot[q] = (int32_t)slot;
+        slot_used[slot] = (int64_t)round;
+        ++S.loads;
+        return TRW_OK;
+    };
+
     for (;;) {
-        // regroup into `spare`: each partition's old records (none for those
-        // just walked), then its arrivals.  The pinned arrays are written here
+        // regroup into `spare`: each key's old records (none for those just
+        // walked), then its arrivals.  The pinned arrays are written here
         // only, after the previous round's wait, and read by this round's copies.
         uint64_t acc = 0, old_kept = 0;
-        for (uint32_t q = 0; q < parts; ++q) {
+        for (uint32_t q = 0; q < keys; ++q) {
             const uint64_t kept = consumed[q] ? 0 : counts[q];
             old_kept += kept;
             next[q] = kept + h_hist[q];
@@ -871,94 +1077,54 @@ trw_status trw_disk_walk(trw_disk_graph g, const trw_walk_params *p, const int32
             acc += next[q];
         }
         const uint64_t waiting = acc;
-        e = hipMemcpyAsync(d_new_off, h_new_off, 4 * (size_t)parts, hipMemcpyHostToDevice, s);
-        if (e == hipSuccess) e = hipMemcpyAsync(d_base, h_base, 4 * (size_t)parts, hipMemcpyHostToDevice, s);
+        e = hipMemcpyAsync(d_new_off, h_new_off, 4 * (size_t)keys, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(d_base, h_base, 4 * (size_t)keys, hipMemcpyHostToDevice, s);
         if (e == hipSuccess && old_kept > 0)
-            e = hipMemcpyAsync(d_old_off, h_old_off, 4 * (size_t)parts, hipMemcpyHostToDevice, s);
-        if (e == hipSuccess && old_kept > 0) e = hipMemcpyAsync(d_consumed, h_consumed, parts, hipMemcpyHostToDevice, s);
+            e = hipMemcpyAsync(d_old_off, h_old_off, 4 * (size_t)keys, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess && old_kept > 0) e = hipMemcpyAsync(d_consumed, h_consumed, keys, hipMemcpyHostToDevice, s);
         if (e != hipSuccess) return device_error("offsets upload");
         if (old_kept > 0)
             hipLaunchKernelGGL(k_disk_move_old, dim3(grid_for(old_total, di)), dim3(256), 0, s, cur,
                                (uint32_t)old_total, d_consumed, d_old_off, d_new_off, spare);
-        fill(d_cursor, parts, 0u);
-        hipLaunchKernelGGL(k_disk_place_new, dim3(grid_for(h_hist[parts], di)), dim3(256), 2 * lds_hist, s, lists[2],
-                           d_count, d_base, d_cursor, spare, parts);
+        fill(d_cursor, keys, 0u);
+        hipLaunchKernelGGL(k_disk_place_new, dim3(grid_for(h_hist[keys], di)), dim3(256), 2 * lds_hist, s, lists[2],
+                           d_count, d_base, d_cursor, spare, keys);
         e = hipGetLastError();
         if (e != hipSuccess) return device_error("regroup launch");
         std::swap(cur, spare);
         counts.swap(next);
-        for (uint32_t q = 0; q < parts; ++q) off[q] = h_new_off[q];
+        for (uint32_t q = 0; q < keys; ++q) off[q] = h_new_off[q];
         old_total = waiting;
         if (waiting == 0) break;
         // Each round moves every walker it runs at least once or ends it, so
         // there are at most nq * max_len rounds.
         if (++round > moved_max) return host_error("partition walks made no progress");
 
-        // run the resident partitions that hold waiting queries; if none does,
-        // load the partition holding the most (the lowest index among equals)
-        // into a free slot or the one used longest ago
-        std::vector<uint32_t> run;
+        // run the keys whose partitions are resident; if none holds a waiting
+        // query, load the partitions of the key holding the most (the lowest
+        // index among equals)
+        std::vector<uint32_t> resident, run;
         for (uint32_t k = 0; k < K; ++k)
-            if (slot_part[k] >= 0 && counts[slot_part[k]] > 0) run.push_back((uint32_t)slot_part[k]);
-        if (run.empty()) {
-            uint32_t pbest = 0;
-            for (uint32_t q = 1; q < parts; ++q)
-                if (counts[q] > counts[pbest]) pbest = q;
-            uint32_t slot = 0;
-            for (uint32_t k = 1; k < K; ++k)
-                if (slot_used[k] < slot_used[slot]) slot = k;
-            const int64_t v0 = g->vstart[pbest], v1 = g->vstart[pbest + 1];
-            const int64_t e0 = g->row_ptr[v0], e1 = g->row_ptr[v1];
-            const int64_t mp = e1 - e0;
-            if (slot_part[slot] >= 0) {
-                const int64_t old = slot_part[slot];
-                set_slot(g->vstart[old], g->vstart[old + 1], kNoSlot);
-                part_slot[old] = -1;
-                slot_part[slot] = -1;
+            if (slot_part[k] >= 0) resident.push_back((uint32_t)slot_part[k]);
+        for (uint32_t a : resident) {
+            if (!pairs) {
+                if (counts[a] > 0) run.push_back(a);
+                continue;
             }
-            char *b = D + (uint64_t)slot * SD.stride;
-            int32_t *d_rp = reinterpret_cast<int32_t *>(b + SD.o_rp);
-            char *d_tab = b + SD.o_tab;
-            // rows of the range, then its edges
-            for (int64_t v = v0; v <= v1; ++v) h_rp[v - v0] = (int32_t)(g->row_ptr[v] - e0);
-            hipLaunchKernelGGL(k_disk_rows, dim3(grid_for((uint64_t)g->n + 1, di)), dim3(256), 0, s, d_rp, g->n, v0,
-                               v1, (int32_t)mp);
-            e = hipMemcpyAsync(d_rp + v0, h_rp, 4 * (size_t)(v1 - v0 + 1), hipMemcpyHostToDevice, s);
-            if (e != hipSuccess) return device_error("partition copy");
-            const bool check = !g->checked[pbest];
-            bool ok = stream_in(h_col, b + SD.o_col, 4 * (size_t)mp, g->off_col + 4 * (uint64_t)e0, check, e0);
-            if (ok && want_w)
-                ok = stream_in(h_wgt, b + SD.o_wgt, 4 * (size_t)mp, g->off_weight + 4 * (uint64_t)e0, false, e0);
-            if (ok && want_l) ok = stream_in(h_lab, b + SD.o_lab, (size_t)mp, g->off_label + (uint64_t)e0, false, e0);
-            if (!ok) {
-                if (e != hipSuccess) return device_error("partition copy");
-                (void)hipStreamSynchronize(s);
-                return TRW_E_INVALID;   // the message is set
-            }
-            g->checked[pbest] = 1;
-            if (mp > 0 && p->algo != TRW_A_METAPATH) {
-                GraphDev view{d_rp, reinterpret_cast<const int32_t *>(b + SD.o_col),
-                              want_w ? reinterpret_cast<const uint32_t *>(b + SD.o_wgt) : nullptr, nullptr,
-                              (int32_t)g->n, (int32_t)mp, 0};
-                if (p->sampler == TRW_S_ALIAS)
-                    e = launch_alias_build_range(view, v0, v1, reinterpret_cast<uint4 *>(d_tab), s);
-                else if (p->sampler == TRW_S_ITS)
-                    e = launch_its_build_range(view, v0, v1, reinterpret_cast<uint64_t *>(d_tab),
-                                               reinterpret_cast<uint4 *>(d_tab + SD.tab_o1),
-                                               reinterpret_cast<uint64_t *>(d_tab + SD.tab_o2), s);
-                else if (p->sampler == TRW_S_REJ)
-                    e = launch_rej_build_range(view, v0, v1, reinterpret_cast<uint4 *>(d_tab),
-                                               reinterpret_cast<uint32_t *>(d_tab + SD.tab_o1), s);
-                if (e != hipSuccess) return device_error("table build launch");
-            }
-            set_slot(v0, v1, (uint16_t)slot);
-            slot_part[slot] = pbest;
-            part_slot[pbest] = (int32_t)slot;
-            ++S.loads;
-            run.push_back(pbest);
+            for (uint32_t b : resident)
+                if (counts[(uint64_t)a * parts + b] > 0) run.push_back(a * parts + b);
         }
-        // walk every query waiting there; those that step into a partition
-        // that is not resident arrive in lists[2]
+        if (run.empty()) {
+            uint32_t best = 0;
+            for (uint32_t q = 1; q < keys; ++q)
+                if (counts[q] > counts[best]) best = q;
+            const uint32_t a = pairs ? best / parts : best, b = pairs ? best % parts : best;
+            if (part_slot[a] < 0 && (st = load(a, b)) != TRW_OK) return st;
+            if (part_slot[b] < 0 && (st = load(b, a)) != TRW_OK) return st;
+            run.push_back(best);
+        }
+        // walk every query waiting under them; those that step out of the
+        // resident partitions arrive in lists[2]
         ++S.runs;
         fill(d_count, 1, 0u);
         std::fill(consumed.begin(), consumed.end(), 0);
@@ -967,7 +1133,8 @@ trw_status trw_disk_walk(trw_disk_graph g, const trw_walk_params *p, const int32
             dispatch_walk(p->algo, p->sampler, SD, w, d_vslot, cur + off[q], n_in, d_vstart, parts, lists[2], d_count,
                           grid_for(n_in, di), s);
             consumed[q] = 1;
-            slot_used[part_slot[q]] = (int64_t)round;
+            slot_used[part_slot[pairs ? q / parts : q]] = (int64_t)round;
+            slot_used[part_slot[pairs ? q % parts : q]] = (int64_t)round;
         }
         e = hipGetLastError();
         if (e != hipSuccess || !read_arrivals()) return device_error("partition walk");

@@ -157,10 +157,23 @@ def test_walk_argument_checks(tmp_path):
     trw.write_disk_graph(path_w, g.row_ptr, g.col, g.weight, g.label)
     trw.write_disk_graph(path_plain, g.row_ptr, g.col)
     Gw, Gp = trw.DiskGraph(path_w, 500), trw.DiskGraph(path_plain, 500)
-    n2v = trw.make_params("node2vec", "orej", 10, 1, n2v_thr_q16=(65536, 65536, 65536))
+    # Node2Vec waits under pairs of partitions: at most 1024 partitions, at least 2 resident
+    n2v = trw.make_params("node2vec", "orej", 10, 1, n2v_thr_q16=(16384, 32768, 65536))
+    assert Gw.walk_bytes(n2v, 10, 1) == Gw.walk_bytes(n2v, 10, 2)
+    with pytest.raises(trw.TrwError, match="thresholds"):
+        Gw.walk_bytes(trw.make_params("node2vec", "orej", 10, 1, n2v_thr_q16=(0, 1, 1)), 10)
+    with pytest.raises(trw.TrwError, match="O-REJ"):
+        Gw.walk_bytes(trw.make_params("node2vec", "alias", 10, 1), 10)
+    big = synth.rmat(12, 8, False, 79)
+    path_big = str(tmp_path / "big.csr")
+    trw.write_disk_graph(path_big, big.row_ptr, big.col)
+    many = trw.DiskGraph(path_big, 1)                   # about one partition per row: more than 1024
+    assert many.parts > 1024
     with pytest.raises(trw.TrwError) as ei:
-        Gw.walk_bytes(n2v, 10)
+        many.walk_bytes(n2v, 10)
     assert ei.value.status == _abi.TRW_E_UNSUPPORTED
+    many.walk_bytes(trw.make_params("deepwalk", "naive", 10, 1), 10)   # other walks take any count
+    many.close()
     for sampler in ("alias", "its", "rej"):
         with pytest.raises(trw.TrwError, match="weights"):
             Gp.walk_bytes(trw.make_params("deepwalk", sampler, 10, 1), 10)

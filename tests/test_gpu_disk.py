@@ -30,8 +30,9 @@ def graph(tmp_path_factory):
 
 CASES = [("deepwalk", "naive", 40), ("deepwalk", "alias", 40), ("deepwalk", "its", 40), ("deepwalk", "rej", 40),
          ("ppr", "naive", 64), ("ppr", "alias", 64), ("ppr", "its", 64), ("ppr", "rej", 64),
-         ("metapath", "its", 20)]
+         ("metapath", "its", 20), ("node2vec", "orej", 30)]
 SCHEMA = (0, 1, 2, 1)
+N2V_THR = (16384, 32768, 65536)     # p = 2, q = 0.5
 
 
 def params(algo, sampler, max_len, seed):
@@ -40,12 +41,15 @@ def params(algo, sampler, max_len, seed):
         kw["stop_q32"] = trw.stop_threshold(0.15)
     if algo == "metapath":
         kw["schema"] = SCHEMA
+    if algo == "node2vec":
+        kw["n2v_thr_q16"] = N2V_THR
     return trw.make_params(algo, sampler, max_len, seed, **kw)
 
 
 def oracle_walk(g, algo, sampler, max_len, seed, src, qid_base, stop):
     op = oracle.WalkParams(oracle.ALGOS[algo], oracle.SAMPLERS[sampler], max_len, seed, stop_q32=stop,
-                           schema=SCHEMA if algo == "metapath" else ())
+                           schema=SCHEMA if algo == "metapath" else (),
+                           n2v_thr_q16=N2V_THR if algo == "node2vec" else (65536, 65536, 65536))
     kw = {}
     if algo == "metapath":
         kw["label"] = g.label
@@ -86,11 +90,12 @@ def test_disk_walk_equals_oracle(graph, algo, sampler, max_len, split, slots):
     torch.cuda.synchronize()
     ref = oracle_walk(g, algo, sampler, max_len, 1234, src, 77, int(p.stop_q32))
     same_as(ref, P, L, S, max_len)
-    assert 1 <= st["loads"] <= st["runs"]
+    # a round loads at most one partition (Node2Vec: the two of a pair)
+    assert 1 <= st["loads"] <= (2 if algo == "node2vec" else 1) * st["runs"]
     per_edge = 4 + (4 if sampler in ("alias", "its", "rej") and algo != "metapath" else 0) + \
         (1 if algo == "metapath" else 0)
     sizes = [G.partition(i)[3] - G.partition(i)[2] for i in range(G.parts)]
-    if slots == 1:
+    if slots == 1 and algo != "node2vec":
         assert st["loads"] == st["runs"]          # the partition just walked holds no waiting query
     if slots >= G.parts:
         # nothing is evicted: each partition is read at most once
@@ -152,4 +157,43 @@ def test_destination_out_of_range_is_refused(graph, tmp_path):
     src = np.full(64, bad_v, np.int32)
     with pytest.raises(trw.TrwError, match="outside"):
         G.walk(params("deepwalk", "naive", 10, 1), torch.from_numpy(src).cuda())
+    G.close()
+
+
+@pytest.mark.parametrize("split,slots", [("sevenths", 2), ("sevenths", 99), ("hubs_alone", 4)])
+def test_disk_node2vec_symmetric(tmp_path, split, slots):
+    """Node2Vec on a symmetric graph (a move often returns to the previous vertex's
+    partition): every query equals the oracle's."""
+    g = synth.rmat(12, 16, True, 0x5E7)
+    path = str(tmp_path / "sym.csr")
+    trw.write_disk_graph(path, g.row_ptr.astype(np.int64), g.col)
+    G = trw.DiskGraph(path, part_sizes(g)[split])
+    src = synth.sources(4000, g.n, 17)
+    p = params("node2vec", "orej", 40, 555)
+    log(f"  disk node2vec symmetric parts={G.parts} slots={slots}")
+    P, L, S, st = G.walk(p, torch.from_numpy(src).cuda(), qid_base=9, slots=slots)
+    torch.cuda.synchronize()
+    ref = oracle_walk(g, "node2vec", "orej", 40, 555, src, 9, 0)
+    same_as(ref, P, L, S, 40)
+    log(f"  runs={st['runs']} loads={st['loads']}")
+    G.close()
+
+
+def test_disk_node2vec_needs_sorted_rows(graph, tmp_path):
+    """Node2Vec searches the previous vertex's row: a partition with an unsorted row is
+    refused when it is loaded (a host check; the other walks take such rows)."""
+    g, _ = graph
+    col = g.col.copy()
+    v = int(np.argmax(np.diff(g.row_ptr)))
+    a, b = int(g.row_ptr[v]), int(g.row_ptr[v + 1])
+    col[a:b] = col[a:b][::-1]
+    path = str(tmp_path / "unsorted.csr")
+    trw.write_disk_graph(path, g.row_ptr.astype(np.int64), col)
+    G = trw.DiskGraph(path, g.m // 4)
+    src = np.full(32, v, np.int32)
+    with pytest.raises(trw.TrwError, match="not sorted"):
+        G.walk(params("node2vec", "orej", 10, 1), torch.from_numpy(src).cuda(), slots=2)
+    P, L, S, _ = G.walk(params("deepwalk", "naive", 10, 1), torch.from_numpy(src).cuda(), slots=2)
+    torch.cuda.synchronize()
+    assert (S.cpu().numpy() != 0).all()
     G.close()
