@@ -522,6 +522,9 @@ trw_status trw_disk_walk_bytes(trw_disk_graph g, const trw_walk_params *p, uint6
  * are absent), TRW_E_INVALID for a destination outside [0, n) in a loaded
  * partition, an unsorted row (Node2Vec) or a failed read, TRW_E_UNSUPPORTED for
  * Node2Vec over more than 1024 partitions, TRW_E_DEVICE for a device error.
+ * Unlike other calls, an error found at a load (a bad destination, an unsorted
+ * row, a failed read) comes after some queries have run: their outputs are
+ * written, the others' are not; nothing of the call is in flight on return.
  */
 trw_status trw_disk_walk(trw_disk_graph g, const trw_walk_params *p, const int32_t *d_sources, uint64_t nq,
                          uint64_t qid_base, int32_t *d_paths, uint64_t path_stride, uint32_t *d_lengths,
