@@ -102,9 +102,14 @@ bool read_parallel(int fd, void *dst, size_t bytes, uint64_t off) {
     for (size_t i = 0; i < pieces; ++i) {
         const size_t a = i * each, b = std::min(bytes, a + each);
         if (a >= b) break;
-        th.emplace_back([&, a, b] {
+        auto piece = [&ok, fd, dst, off, a, b] {
             if (!read_at(fd, static_cast<char *>(dst) + a, b - a, off + a)) ok = false;
-        });
+        };
+        try {
+            th.emplace_back(piece);
+        } catch (...) {   // no thread to be had: read this piece here
+            piece();
+        }
     }
     for (auto &t : th) t.join();
     return ok;
@@ -712,7 +717,17 @@ trw_status trw_disk_graph_write(const char *path, int64_t n, int64_t m, const in
     return TRW_OK;
 }
 
+static trw_status disk_graph_open(const char *path, uint64_t part_edges, trw_disk_graph *out);
+
 trw_status trw_disk_graph_open(const char *path, uint64_t part_edges, trw_disk_graph *out) {
+    try {
+        return disk_graph_open(path, part_edges, out);
+    } catch (...) {
+        return dfail(TRW_E_INVALID, "out of host memory opening the file");
+    }
+}
+
+static trw_status disk_graph_open(const char *path, uint64_t part_edges, trw_disk_graph *out) {
     if (!path || !out) return dfail(TRW_E_INVALID, "path / out is NULL");
     if (part_edges >= (uint64_t(1) << 31)) return dfail(TRW_E_INVALID, "part_edges must be < 2^31");
     if (part_edges == 0) part_edges = (uint64_t(1) << 31) - 1;
@@ -830,10 +845,28 @@ trw_status trw_disk_walk_bytes(trw_disk_graph g, const trw_walk_params *p, uint6
     return TRW_OK;
 }
 
+static trw_status disk_walk(trw_disk_graph g, const trw_walk_params *p, const int32_t *d_sources, uint64_t nq,
+                            uint64_t qid_base, int32_t *d_paths, uint64_t path_stride, uint32_t *d_lengths,
+                            uint8_t *d_status, uint32_t slots, void *d_ws, size_t ws_bytes, void *h_pinned,
+                            size_t h_bytes, trw_disk_walk_stats *stats, trw_stream_t stream);
+
 trw_status trw_disk_walk(trw_disk_graph g, const trw_walk_params *p, const int32_t *d_sources, uint64_t nq,
                          uint64_t qid_base, int32_t *d_paths, uint64_t path_stride, uint32_t *d_lengths,
                          uint8_t *d_status, uint32_t slots, void *d_ws, size_t ws_bytes, void *h_pinned,
                          size_t h_bytes, trw_disk_walk_stats *stats, trw_stream_t stream) {
+    try {
+        return disk_walk(g, p, d_sources, nq, qid_base, d_paths, path_stride, d_lengths, d_status, slots, d_ws,
+                         ws_bytes, h_pinned, h_bytes, stats, stream);
+    } catch (...) {
+        (void)hipStreamSynchronize(static_cast<hipStream_t>(stream));
+        return dfail(TRW_E_INVALID, "out of host memory during the walk");
+    }
+}
+
+static trw_status disk_walk(trw_disk_graph g, const trw_walk_params *p, const int32_t *d_sources, uint64_t nq,
+                            uint64_t qid_base, int32_t *d_paths, uint64_t path_stride, uint32_t *d_lengths,
+                            uint8_t *d_status, uint32_t slots, void *d_ws, size_t ws_bytes, void *h_pinned,
+                            size_t h_bytes, trw_disk_walk_stats *stats, trw_stream_t stream) {
     const uint64_t t_start = now_ns();
     trw_status st = check_walk(g, p);
     if (st != TRW_OK) return st;
