@@ -122,6 +122,12 @@ __device__ void alias_row_sequential(const GraphDev &g, int64_t off, int64_t d, 
 // the rows and hold about 70% of the edges.
 constexpr int64_t kBigRow = 128;
 constexpr int kBuildBlock = 256;
+// Rows above kHugeRow slots (R-MAT's largest hubs, whose one workgroup sets a
+// build's time) are built by workgroups of kHugeBlock threads: half the
+// block-wide steps, and still no register spills (1024 threads would spill
+// the ALIAS build); the tables are the same.
+constexpr int64_t kHugeRow = 16384;
+constexpr uint32_t kHugeBlock = 512;
 
 __global__ void k_alias_build(GraphDev g, VRange r, uint4 *__restrict__ out) {
     const int64_t v = r.lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -132,9 +138,9 @@ __global__ void k_alias_build(GraphDev g, VRange r, uint4 *__restrict__ out) {
     alias_row_sequential(g, off, d, out);
 }
 
-// Inclusive scan over the kBuildBlock threads of a workgroup; `total` gets
-// the sum over the block.  Every thread must call it.
-template <typename T>
+// Inclusive scan over the NT threads of a workgroup; `total` gets the sum
+// over the block.  Every thread must call it.
+template <typename T, uint32_t NT = kBuildBlock>
 __device__ __forceinline__ T block_inclusive_scan(T v, T *sh, T &total) {
     const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
@@ -147,7 +153,7 @@ __device__ __forceinline__ T block_inclusive_scan(T v, T *sh, T &total) {
     T before = 0;
     total = 0;
 #pragma unroll
-    for (uint32_t k = 0; k < kBuildBlock / 64; ++k) {
+    for (uint32_t k = 0; k < NT / 64; ++k) {
         if (k < wv) before += sh[k];
         total += sh[k];
     }
@@ -155,10 +161,10 @@ __device__ __forceinline__ T block_inclusive_scan(T v, T *sh, T &total) {
     return v + before;
 }
 
-template <typename T>
+template <typename T, uint32_t NT = kBuildBlock>
 __device__ __forceinline__ T block_sum(T v, T *sh) {
     T total;
-    (void)block_inclusive_scan(v, sh, total);
+    (void)block_inclusive_scan<T, NT>(v, sh, total);
     return total;
 }
 
@@ -167,18 +173,20 @@ __device__ __forceinline__ T block_sum(T v, T *sh) {
 // in turn (v - r.lo = j * G + b goes to workgroup b of G), so the hubs, which
 // R-MAT numbers first, are spread over the grid instead of falling to one
 // workgroup.
-template <typename Body>
-__device__ __forceinline__ void for_each_big_row(const GraphDev &g, VRange r, Body body) {
-    __shared__ uint64_t flags[kBuildBlock / 64];
+// With NT threads per workgroup, the rows of (d_lo, d_hi] slots only.
+template <uint32_t NT = kBuildBlock, typename Body>
+__device__ __forceinline__ void for_each_big_row(const GraphDev &g, VRange r, int64_t d_lo, int64_t d_hi, Body body) {
+    __shared__ uint64_t flags[NT / 64];
     const uint32_t tid = threadIdx.x;
     const int64_t G = gridDim.x;
-    for (int64_t base = r.lo; base < r.hi; base += G * kBuildBlock) {
+    for (int64_t base = r.lo; base < r.hi; base += G * NT) {
         const int64_t v = base + (int64_t)tid * G + blockIdx.x;
-        const bool big = v < r.hi && (int64_t)g.row_ptr[v + 1] - g.row_ptr[v] > kBigRow;
+        const int64_t d = v < r.hi ? (int64_t)g.row_ptr[v + 1] - g.row_ptr[v] : 0;
+        const bool big = d > d_lo && d <= d_hi;
         const uint64_t m = __ballot(big);
         if ((tid & 63) == 0) flags[tid >> 6] = m;
         __syncthreads();
-        for (uint32_t wv = 0; wv < kBuildBlock / 64; ++wv) {
+        for (uint32_t wv = 0; wv < NT / 64; ++wv) {
             uint64_t bits = flags[wv];
             while (bits) {
                 const int64_t u = base + (int64_t)(64 * wv + __builtin_ctzll(bits)) * G + blockIdx.x;
@@ -190,6 +198,10 @@ __device__ __forceinline__ void for_each_big_row(const GraphDev &g, VRange r, Bo
         }
         __syncthreads();
     }
+}
+template <typename Body>
+__device__ __forceinline__ void for_each_big_row(const GraphDev &g, VRange r, Body body) {
+    for_each_big_row<kBuildBlock>(g, r, kBigRow, INT64_MAX, body);
 }
 template <typename Body>
 __device__ __forceinline__ void for_each_big_row(const GraphDev &g, Body body) {
@@ -224,11 +236,13 @@ __device__ __forceinline__ uint64_t *scratch_u64(uint4 *row, uint64_t k) {   // 
 // in pop order, then (at an even word) the u64 array P with P[0] = 0,
 // P[1..n_s] = D, P[n_s+1 .. n_s+n_l] = S.  3d + 3 words fit in the 4d words
 // of the second halves for d > 3.
-__global__ void __launch_bounds__(kBuildBlock) k_alias_build_big(GraphDev g, VRange r, uint4 *__restrict__ out) {
-    __shared__ uint64_t sh64[kBuildBlock / 64];
-    __shared__ uint32_t sh32[kBuildBlock / 64];
+template <uint32_t NT>
+__global__ void __launch_bounds__(NT) k_alias_build_big(GraphDev g, VRange r, int64_t d_lo, int64_t d_hi,
+                                                  uint4 *__restrict__ out) {
+    __shared__ uint64_t sh64[NT / 64];
+    __shared__ uint32_t sh32[NT / 64];
     const uint32_t tid = threadIdx.x;
-    for_each_big_row(g, r, [&](int64_t v, int64_t off, int64_t d) {
+    for_each_big_row<NT>(g, r, d_lo, d_hi, [&](int64_t v, int64_t off, int64_t d) {
         const uint32_t *__restrict__ w = g.weight + off;
         const int32_t *__restrict__ col = g.col + off;
         uint4 *__restrict__ row = out + 2 * off;
@@ -236,20 +250,20 @@ __global__ void __launch_bounds__(kBuildBlock) k_alias_build_big(GraphDev g, VRa
         (void)v;
 
         uint64_t part = 0;
-        for (int64_t i = tid; i < d; i += kBuildBlock) part += w[i];
-        const uint64_t W = block_sum(part, sh64);
+        for (int64_t i = tid; i < d; i += NT) part += w[i];
+        const uint64_t W = block_sum<uint64_t, NT>(part, sh64);
         if (W == 0 || W > ~0ull / ud) {                        // no transition, or d*W would overflow
             if (tid == 0) alias_row_sequential(g, off, d, out);
             return;
         }
         uint32_t cs = 0;
-        for (int64_t i = tid; i < d; i += kBuildBlock) cs += ((uint64_t)w[i] * ud < W);
-        const uint64_t n_s = block_sum(cs, sh32);
+        for (int64_t i = tid; i < d; i += NT) cs += ((uint64_t)w[i] * ud < W);
+        const uint64_t n_s = block_sum<uint32_t, NT>(cs, sh32);
         const uint64_t n_l = ud - n_s;
         const uint64_t pbase = ud + (ud & 1);
         if (tid == 0) *scratch_u64(row, pbase) = 0;
         uint64_t carry_s = 0, carry_l = 0, carry_D = 0, carry_S = 0;
-        for (int64_t r0 = 0; r0 < d; r0 += kBuildBlock) {
+        for (int64_t r0 = 0; r0 < d; r0 += NT) {
             const int64_t r = r0 + tid;                        // position in descending index order
             const bool in = r < d;
             const int64_t i = d - 1 - r;
@@ -258,10 +272,10 @@ __global__ void __launch_bounds__(kBuildBlock) k_alias_build_big(GraphDev g, VRa
             const bool large = in && !small;
             uint32_t ts, tl;
             uint64_t tD, tS;
-            const uint32_t is = block_inclusive_scan((uint32_t)small, sh32, ts);
-            const uint32_t il = block_inclusive_scan((uint32_t)large, sh32, tl);
-            const uint64_t iD = block_inclusive_scan<uint64_t>(small ? W - s_i : 0ull, sh64, tD);
-            const uint64_t iS = block_inclusive_scan<uint64_t>(large ? s_i - W : 0ull, sh64, tS);
+            const uint32_t is = block_inclusive_scan<uint32_t, NT>((uint32_t)small, sh32, ts);
+            const uint32_t il = block_inclusive_scan<uint32_t, NT>((uint32_t)large, sh32, tl);
+            const uint64_t iD = block_inclusive_scan<uint64_t, NT>(small ? W - s_i : 0ull, sh64, tD);
+            const uint64_t iS = block_inclusive_scan<uint64_t, NT>(large ? s_i - W : 0ull, sh64, tS);
             if (small) {
                 const uint64_t pos = carry_s + is - 1;
                 *scratch_word(row, pos) = (uint32_t)i;
@@ -275,7 +289,7 @@ __global__ void __launch_bounds__(kBuildBlock) k_alias_build_big(GraphDev g, VRa
         }
         __syncthreads();
         const uint64_t D_total = carry_D;
-        for (uint64_t pos = tid; pos < n_s; pos += kBuildBlock) {       // small columns
+        for (uint64_t pos = tid; pos < n_s; pos += NT) {       // small columns
             const uint32_t l = *scratch_word(row, pos);
             const uint64_t x = *scratch_u64(row, pbase + 2 * pos);   // D_(i-1)
             uint64_t lo = 0, hi = n_l - 1;
@@ -286,7 +300,7 @@ __global__ void __launch_bounds__(kBuildBlock) k_alias_build_big(GraphDev g, VRa
             const uint32_t gl = *scratch_word(row, n_s + lo);
             row[2 * l] = make_uint4(frac32((uint64_t)w[l] * ud, W), (uint32_t)col[l], (uint32_t)col[gl], 0u);
         }
-        for (uint64_t pos = tid; pos < n_l; pos += kBuildBlock) {       // large columns
+        for (uint64_t pos = tid; pos < n_l; pos += NT) {       // large columns
             const uint32_t gl = *scratch_word(row, n_s + pos);
             const uint64_t S = *scratch_u64(row, pbase + 2 * (n_s + 1 + pos));
             if (S >= D_total) {
@@ -303,7 +317,7 @@ __global__ void __launch_bounds__(kBuildBlock) k_alias_build_big(GraphDev g, VRa
             }
         }
         __syncthreads();
-        for (int64_t j = tid; j < d; j += kBuildBlock) {                // second halves, over the scratch
+        for (int64_t j = tid; j < d; j += NT) {                // second halves, over the scratch
             const uint4 e = row[2 * j];
             const uint2 ra = row_of(g, (int32_t)e.y), rb = row_of(g, (int32_t)e.z);
             row[2 * j + 1] = make_uint4(ra.x, ra.y, rb.x, rb.y);
@@ -323,15 +337,17 @@ __global__ void k_its_build(GraphDev g, VRange r, uint64_t *__restrict__ out) {
     }
 }
 
-__global__ void __launch_bounds__(kBuildBlock) k_its_build_big(GraphDev g, VRange r, uint64_t *__restrict__ out) {
-    __shared__ uint64_t sh64[kBuildBlock / 64];
-    for_each_big_row(g, r, [&](int64_t, int64_t off, int64_t d) {
+template <uint32_t NT>
+__global__ void __launch_bounds__(NT) k_its_build_big(GraphDev g, VRange r, int64_t d_lo, int64_t d_hi,
+                                                uint64_t *__restrict__ out) {
+    __shared__ uint64_t sh64[NT / 64];
+    for_each_big_row<NT>(g, r, d_lo, d_hi, [&](int64_t, int64_t off, int64_t d) {
         uint64_t carry = 0;
-        for (int64_t r0 = 0; r0 < d; r0 += kBuildBlock) {
+        for (int64_t r0 = 0; r0 < d; r0 += NT) {
             const int64_t e = off + r0 + threadIdx.x;
             const bool in = r0 + threadIdx.x < d;
             uint64_t tot;
-            const uint64_t inc = block_inclusive_scan<uint64_t>(in ? (uint64_t)g.weight[e] : 0ull, sh64, tot);
+            const uint64_t inc = block_inclusive_scan<uint64_t, NT>(in ? (uint64_t)g.weight[e] : 0ull, sh64, tot);
             if (in) out[e] = carry + inc;
             carry += tot;
         }
@@ -576,6 +592,10 @@ int big_row_blocks(int64_t verts) {
     return (int)std::max<int64_t>(1, std::min<int64_t>(verts, 2048));
 }
 int big_row_blocks(const GraphDev &g) { return big_row_blocks((int64_t)g.n); }
+// Workgroups for the huge-row kernels (few rows, each a long loop).
+int huge_row_blocks(int64_t verts) {
+    return (int)std::max<int64_t>(1, std::min<int64_t>(verts, 512));
+}
 
 // Thread-per-vertex workgroups for [lo, hi) (at least one).
 int vertex_blocks(VRange r) {
@@ -587,7 +607,10 @@ int vertex_blocks(VRange r) {
 hipError_t launch_alias_build_range(const GraphDev &g, int64_t lo, int64_t hi, uint4 *out, hipStream_t s) {
     const VRange r{lo, hi};
     hipLaunchKernelGGL(k_alias_build, dim3(vertex_blocks(r)), dim3(kBuildThreads), 0, s, g, r, out);
-    hipLaunchKernelGGL(k_alias_build_big, dim3(big_row_blocks(hi - lo)), dim3(kBuildBlock), 0, s, g, r, out);
+    hipLaunchKernelGGL(k_alias_build_big<kBuildBlock>, dim3(big_row_blocks(hi - lo)), dim3(kBuildBlock), 0, s, g, r,
+                       kBigRow, kHugeRow, out);
+    hipLaunchKernelGGL(k_alias_build_big<kHugeBlock>, dim3(huge_row_blocks(hi - lo)), dim3(kHugeBlock), 0, s, g, r,
+                       kHugeRow, INT64_MAX, out);
     return hipGetLastError();
 }
 
@@ -600,7 +623,10 @@ hipError_t launch_its_build_range(const GraphDev &g, int64_t lo, int64_t hi, uin
     const VRange r{lo, hi};
     if (g.m > 0) {
         hipLaunchKernelGGL(k_its_build, dim3(vertex_blocks(r)), dim3(kBuildThreads), 0, s, g, r, prefix);
-        hipLaunchKernelGGL(k_its_build_big, dim3(big_row_blocks(hi - lo)), dim3(kBuildBlock), 0, s, g, r, prefix);
+        hipLaunchKernelGGL(k_its_build_big<kBuildBlock>, dim3(big_row_blocks(hi - lo)), dim3(kBuildBlock), 0, s, g, r,
+                           kBigRow, kHugeRow, prefix);
+        hipLaunchKernelGGL(k_its_build_big<kHugeBlock>, dim3(huge_row_blocks(hi - lo)), dim3(kHugeBlock), 0, s, g,
+                           r, kHugeRow, INT64_MAX, prefix);
     }
     hipLaunchKernelGGL(k_its_vw, dim3(vertex_blocks(r)), dim3(kBuildThreads), 0, s, g, r, prefix, vw);
     if (g.m > 0) {
