@@ -222,9 +222,9 @@ def main():
 
 def bench_disk(ctx):
     """ppr-rmat22's batch walked from a CSR file (trw_disk_walk): as one partition, and as
-    17 vertex-range partitions with 16 resident at once; every output compared with the
-    in-memory walk.  The file is written just before, so its reads come from the page
-    cache."""
+    17 vertex-range partitions with 16 resident at once, first with the file in the page
+    cache (written just before), then with its pages dropped so the reads come from the
+    disk; every output compared with the in-memory walk."""
     import tempfile
 
     np, torch, synth, trw = ctx.np, ctx.torch, ctx.synth, ctx.trw
@@ -248,10 +248,17 @@ def bench_disk(ctx):
         mem_s = time.perf_counter() - t0
         moves = int(L2.to(torch.int64).sum())
         runs = []
-        for parts, slots in ((1, 1), (16, 16)):
+        fd = os.open(path, os.O_RDONLY)
+        os.fsync(fd)                                 # written back, so its pages can be dropped below
+        os.close(fd)
+        for parts, slots, cache in ((1, 1, "page"), (16, 16, "page"), (16, 16, "dropped")):
             D = trw.DiskGraph(path, 0 if parts == 1 else g.m // parts)
             D.walk(p, src[:1000], slots=D.parts)     # every partition's destinations checked once, untimed
             torch.cuda.synchronize()
+            if cache == "dropped":                   # the file's pages out of the page cache: reads from the disk
+                fd = os.open(path, os.O_RDONLY)
+                os.posix_fadvise(fd, 0, 0, os.POSIX_FADV_DONTNEED)
+                os.close(fd)
             t0 = time.perf_counter()
             P, L, S, st = D.walk(p, src, slots=slots)
             torch.cuda.synchronize()
@@ -264,11 +271,13 @@ def bench_disk(ctx):
                 b = min(nq, a + (1 << 20))
                 keep = cols <= L[a:b, None]
                 same = bool(torch.equal(torch.where(keep, P[a:b], 0), torch.where(keep, P2[a:b, :wl.max_len + 1], 0)))
-            runs.append({"partitions": D.parts, "slots": slots, "ms": round(dt * 1e3, 2), "steps_per_s": moves / dt,
+            runs.append({"partitions": D.parts, "slots": slots, "file_cache": cache, "ms": round(dt * 1e3, 2),
+                         "steps_per_s": moves / dt,
                          "vs_in_memory": (moves / dt) / (moves / mem_s), "same_as_in_memory": same,
                          "rounds": st["runs"], "loads": st["loads"], "bytes_read": st["bytes_read"],
                          "read_GBps": st["bytes_read"] / max(st["read_ns"], 1)})
-            log(f"disk graph: {D.parts} partitions, {slots} resident: {dt * 1e3:.1f} ms, {st['loads']} loads, "
+            log(f"disk graph: {D.parts} partitions, {slots} resident, file pages {cache}: {dt * 1e3:.1f} ms, "
+                f"{st['loads']} loads, "
                 f"{st['bytes_read'] / 1e9:.2f} GB read, same as in memory: {same}")
             del P, L, S
             D.close()
@@ -277,7 +286,9 @@ def bench_disk(ctx):
         return {"workload": "ppr-rmat22 from a CSR file", "algo": "ppr", "sampler": "alias", "nq": nq,
                 "moves": moves, "file_bytes": file_bytes, "in_memory_ms": round(mem_s * 1e3, 3),
                 "in_memory_steps_per_s": moves / mem_s, "runs": runs,
-                "note": "file in the page cache (written just before); partitions' ALIAS tables built at each load"}
+                "note": "file_cache page: the file was just written and its reads come from the page cache; "
+                        "dropped: its pages were dropped first (fsync, posix_fadvise DONTNEED), so they come from "
+                        "the disk; partitions' ALIAS tables built at each load"}
     finally:
         if os.path.exists(path):
             os.remove(path)
