@@ -208,7 +208,11 @@ def main():
     disk = None
     if not args.no_batch and not args.no_disk and not args.profile_pass:
         t0 = time.time()
-        disk = bench_disk(ctx)
+        try:
+            disk = bench_disk(ctx)
+        except OSError as e:         # no room or no temporary directory for the graph file: say so, go on
+            disk = {"error": f"{type(e).__name__}: {e}"}
+            log(f"disk graph: not measured ({disk['error']})")
         ctx.release()
         log(f"disk graph: {time.time() - t0:.1f}s")
     out = bench_served(args, synth.WORKLOADS[SERVED_WORKLOAD], ctx)
