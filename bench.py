@@ -210,7 +210,7 @@ def main():
         t0 = time.time()
         try:
             disk = bench_disk(ctx)
-        except OSError as e:         # no room or no temporary directory for the graph file: say so, go on
+        except (OSError, trw.TrwError) as e:   # e.g. no room for the graph file: in the line, and go on
             disk = {"error": f"{type(e).__name__}: {e}"}
             log(f"disk graph: not measured ({disk['error']})")
         ctx.release()
