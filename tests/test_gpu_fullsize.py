@@ -10,8 +10,9 @@ back in chunks of 2^20 queries.
   counting walk that writes no paths.  The same batch with REJ: every query.
 * Node2Vec on R-MAT 2^24 (one query per vertex) with the edge index: every
   query.
-* The same Node2Vec batch walked from a CSR file (8 partitions, 4 resident):
-  every query equals the in-memory walk.
+* The same Node2Vec batch walked from a CSR file (8 partitions, 4 resident),
+  and the PPR batch from a file with ITS and with REJ (17 partitions, 8
+  resident): every query equals the in-memory walk.
 * MetaPath on R-MAT 2^24 (one query per vertex): every query, once through
   the label index and once by row scans (no index).
 * The served mix on R-MAT 2^26 (about 1.06 G directed edges): the bench's
@@ -224,6 +225,38 @@ def test_node2vec_rmat24_every_query():
     _check_rules(wl, Lh, Sh)
     _check_hops(g, P[:300].cpu().numpy(), Lh[:300].view(np.uint32))
     _every_query("node2vec-rmat24", g, src, [(P, L, S)], _oracle_params(p), wl.max_len)
+    G.close()
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("sampler", ["its", "rej"])
+def test_ppr_rmat22_from_disk_every_query(tmp_path, sampler):
+    """The PPR batch with ITS and with REJ walked from a CSR file in 17 partitions, 8
+    resident (tables built per partition over its vertex range, partitions evicted and
+    reloaded): every query equals the in-memory walk, itself compared with the oracle on
+    every query above."""
+    wl = synth.WORKLOADS["ppr-rmat22"]
+    g = synth.make_graph(wl)
+    src = synth.make_sources(wl, g)
+    path = str(tmp_path / "ppr22.csr")
+    trw.write_disk_graph(path, g.row_ptr.astype(np.int64), g.col, g.weight)
+    G = trw.Graph(g.row_ptr, g.col, g.weight)
+    p = _params(wl, sampler)
+    P, L, S = _walk_full(G, G.table(sampler), p, src)
+    D = trw.DiskGraph(path, g.m // 16)
+    log(f"  ppr-rmat22 {sampler} from disk: {D.parts} partitions, 8 resident, nq={len(src)}")
+    t0 = time.time()
+    Pd, Ld, Sd, st = D.walk(p, torch.from_numpy(src).cuda(), slots=8)
+    torch.cuda.synchronize()
+    log(f"  {time.time() - t0:.2f} s, {st['runs']} rounds, {st['loads']} loads")
+    assert torch.equal(Ld, L) and torch.equal(Sd, S)
+    cols = torch.arange(wl.max_len + 1, device=P.device)[None, :]
+    for a in range(0, len(src), CHUNK):
+        b = min(len(src), a + CHUNK)
+        keep = cols <= L[a:b, None]
+        assert torch.equal(torch.where(keep, Pd[a:b], 0), torch.where(keep, P[a:b, :wl.max_len + 1], 0)), a
+    log("  every query identical to the in-memory walk")
+    D.close()
     G.close()
 
 
