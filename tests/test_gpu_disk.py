@@ -197,3 +197,24 @@ def test_disk_node2vec_needs_sorted_rows(graph, tmp_path):
     torch.cuda.synchronize()
     assert (S.cpu().numpy() != 0).all()
     G.close()
+
+
+def test_disk_walk_on_a_side_stream(graph):
+    """The walk launched on a stream of its own (default priority) gives the same
+    outputs as on the current stream."""
+    g, path = graph
+    G = trw.DiskGraph(path, g.m // 5)
+    src = torch.from_numpy(synth.sources(5000, g.n, 23)).cuda()
+    p = params("ppr", "its", 64, 31)
+    P0, L0, S0, _ = G.walk(p, src, qid_base=3, slots=2)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        P1, L1, S1, st = G.walk(p, src, qid_base=3, slots=2, stream=s)
+    s.synchronize()
+    assert torch.equal(L0, L1) and torch.equal(S0, S1)
+    mask = torch.arange(P0.shape[1], device=P0.device)[None, :] <= L0[:, None]
+    assert torch.equal(P0[mask], P1[mask])
+    assert st["runs"] >= 1
+    G.close()
