@@ -204,3 +204,17 @@ def test_walk_argument_checks(tmp_path):
                               None, None) == _abi.TRW_E_INVALID
     Gw.close()
     Gp.close()
+
+
+def test_use_after_close_is_an_error(tmp_path):
+    """A closed DiskGraph passes a NULL handle: every call reports TRW_E_INVALID, and a
+    second close does nothing."""
+    path = str(tmp_path / "c.csr")
+    _write_raw(path)
+    G = trw.DiskGraph(path, 0)
+    G.close()
+    G.close()
+    for call in (lambda: G.partition(0), lambda: G.walk_bytes(trw.make_params("deepwalk", "naive", 4, 1), 8)):
+        with pytest.raises(trw.TrwError, match="NULL") as ei:
+            call()
+        assert ei.value.status == _abi.TRW_E_INVALID
